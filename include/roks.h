@@ -1,0 +1,238 @@
+/*
+ * roks.h -- C ABI of the MI355X (gfx950) restricted open-shell Kohn-Sham
+ * (ROKS) plane-wave hot path.
+ *
+ * The method is the one of Sahre, Romanelli, Marsman, Gonzalez and Kresse,
+ * "Excited States from Restricted Open Shell Plane-Wave DFT" (equations are
+ * cited by their LaTeX labels, sections by number):
+ *
+ *   E = sum_L c_L E_L - sum_mn gamma_mn (<m|S|n> - delta_mn)    Sec. II A
+ *   with the mixed-spin (c = 2) and triplet (c = -1) configurations of the
+ *   Ziegler sum rule E_S = 2 E_M - E_T (Eq. ziegler_sum), minimised over one
+ *   set of real Gamma-point orbitals by preconditioned Fletcher-Reeves CG
+ *   (Eqs. orbital_update, cg_search, gradient, prec_grad_I, prec_k) with the
+ *   in-subspace rotation of Eqs. r_matrix_singlet and prec_grad_IIa-c, and
+ *   Hellmann-Feynman forces (Eq. force_hf).
+ *
+ * Units: Hartree atomic units (bohr, Ha).  Overlap operator S = 1 (the
+ * projectors carry no augmentation charge, q_kl = 0).
+ *
+ * Plane-wave storage ("half sphere"): the library owns the list of stored
+ * reciprocal vectors G = h b1 + k b2 + l b3 with |G|^2/2 <= ecut; of each
+ * pair {G, -G} one is stored, c(-G) = conj(c(G)) is implied, and G = 0 is
+ * entry 0.  roks_gvectors() returns the Miller triples in storage order.
+ * A band is npw complex numbers stored as [npw][2] doubles (re, im); band
+ * arrays are [nbands][npw][2].  psi(r) = Omega^-1/2 sum_G c(G) e^{iG.r} over
+ * the full sphere, so <a|b> = a(0) b(0) + 2 Re sum_{G != 0, stored} a* b.
+ *
+ * Ownership: the caller owns every array it passes; the library copies what
+ * it keeps during the call.  The context owns all device state (orbitals,
+ * potentials, projector tables, CG state).  All device work is ordered on
+ * the context's HIP stream; calls taking host pointers synchronise that
+ * stream before returning, calls whose name ends in _d take device pointers
+ * and only enqueue work.
+ *
+ * Errors: every call returns a roks_status; argument and shape checks come
+ * before any device work.  roks_last_error() gives a message for the last
+ * failing call on that context (or the last failing roks_create when ctx is
+ * NULL).  On ROKS_ERR_NOT_PD, ROKS_ERR_LINESEARCH or ROKS_ERR_NAN inside
+ * roks_pcg_step the orbitals and CG state are those of the last accepted
+ * iterate.
+ */
+#ifndef ROKS_H
+#define ROKS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct roks_ctx_s* roks_ctx;
+
+typedef enum {
+  ROKS_OK = 0,
+  ROKS_ERR_ARG = 1,        /* invalid argument value                     */
+  ROKS_ERR_SHAPE = 2,      /* inconsistent sizes (grid too small, ...)   */
+  ROKS_ERR_HIP = 3,        /* HIP runtime error or no usable GPU         */
+  ROKS_ERR_OOM = 4,        /* device allocation failed                   */
+  ROKS_ERR_NOT_PD = 5,     /* Gram matrix not positive definite          */
+  ROKS_ERR_LINESEARCH = 6, /* no energy decrease found along the search  */
+  ROKS_ERR_NAN = 7,        /* non-finite energy or gradient              */
+  ROKS_ERR_STATE = 8       /* call out of order (e.g. no orbitals set)   */
+} roks_status;
+
+/* Arithmetic tier of the FFT, pointwise and projector work.  Gram, Cholesky,
+ * rotation, energy sums and the line search are FP64 in every tier. */
+typedef enum { ROKS_FP64 = 0, ROKS_FP32 = 1 } roks_precision;
+
+enum {
+  ROKS_XC_PW92 = 0, /* spin LDA: Slater exchange + Perdew-Wang 1992 correlation */
+  ROKS_XC_X = 1     /* spin LDA exchange only                                   */
+};
+
+enum {
+  /* Sec. II A (collapse to a triplet-like state): set the F^a - F^b block of
+   * R (Eq. r_matrix_singlet) to zero, i.e. do not rotate open shell a into b. */
+  ROKS_FLAG_SUPPRESS_OPEN_COUPLING = 1u,
+  /* also rotate within occupied shells with the Jacobi angle that diagonalises
+   * the shell's own block of R (energy neutral) */
+  ROKS_FLAG_CANONICALIZE = 2u,
+  /* divide the Teter preconditioner of band n by its weight sum c_L f_n */
+  ROKS_FLAG_WEIGHT_PRECOND = 4u
+};
+
+/* Separable Gaussian projector of one radial channel (Sec. II A, projector
+ * functions beta): unit-normalised exp(-r^2/(2 rp^2)) times a real solid
+ * harmonic of degree l in {0, 1} (l = 1 expands to x, y, z). */
+typedef struct {
+  int32_t l;
+  double rp; /* bohr, > 0 */
+} roks_proj;
+
+/* Species: local Gaussian well v(r) = -A exp(-r^2/(2 sigma^2)) and nproj
+ * radial channels with the symmetric coupling D[nproj][nproj] (Ha) of
+ * V_NL = sum_ij |beta_i> D_ij <beta_j|; D_ij must vanish when l_i != l_j. */
+typedef struct {
+  double A;
+  double sigma;
+  int32_t nproj;
+  const roks_proj* proj;
+  const double* D;
+} roks_species;
+
+/* The problem statement (Sec. II A / III): cell, cutoff, atoms, projectors,
+ * bands and the occupations f_n^{sigma L} of each configuration L with
+ * weight c_L.  occ is [nconfig][2 spins (up, down)][nbands] with entries in
+ * {0, 1}; bands must be ordered closed shell, open shells, virtual (the
+ * shells are the groups of identical occupation patterns, Sec. II A). */
+typedef struct {
+  double cell[3][3];  /* rows a1, a2, a3 (bohr); must be orthogonal        */
+  double ecut;        /* Ha, sphere |G|^2/2 <= ecut                        */
+  int32_t grid[3];    /* FFT grid; every size of the form 2^a 3^b 5^c <= 128 */
+  int32_t natoms;
+  const int32_t* species; /* [natoms] index into spec                     */
+  const double* pos;      /* [natoms][3] Cartesian bohr                   */
+  int32_t nspecies;
+  const roks_species* spec;
+  int32_t nbands;
+  int32_t nconfig;        /* 1 (ground state, triplet) or 2 (singlet ROKS) */
+  const uint8_t* occ;
+  const double* cL;       /* [nconfig], e.g. {2, -1}                       */
+  int32_t xc;             /* ROKS_XC_*                                     */
+  int32_t precision;      /* roks_precision                                */
+  uint32_t flags;         /* ROKS_FLAG_*                                   */
+} roks_system;
+
+/* Energies of the current orbitals (Sec. II A, constrained functional). */
+typedef struct {
+  double E;             /* sum_L c_L E_L (E_S for the singlet)            */
+  double E_L[2];        /* configuration energies                         */
+  double kinetic[2];    /* sum_sigma,n f <n|T|n> per configuration        */
+  double nonlocal[2];   /* sum_sigma,n f <n|V_NL|n>                       */
+  double external[2];   /* int V_ext rho_L                                */
+  double hartree[2];    /* 1/2 int V_H[rho_L] rho_L                       */
+  double xc[2];         /* E_xc[rho_L^up, rho_L^down]                     */
+} roks_energies;
+
+/* Outcome of one CG iteration. */
+typedef struct {
+  double E0;       /* energy at the start of the step                     */
+  double E1;       /* energy after the step                               */
+  double delta;    /* accepted step length                                */
+  double beta;     /* Fletcher-Reeves ratio used (0 after a restart)      */
+  double dE0;      /* directional derivative dE/d delta at 0              */
+  double norm_gI;  /* || g_I ||, out-of-subspace gradient (Eq. gradient)  */
+  double max_Rab;  /* max |<a|F^a - F^b|b>| over the open shells (Eq. stat2) */
+  int32_t restarted;   /* CG direction reset to the preconditioned gradient */
+  int32_t stalled;     /* no decrease found at rounding level: no move      */
+  int32_t evaluations; /* trial-energy evaluations in the line search       */
+  int32_t iteration;
+} roks_step_info;
+
+/* Build a context: validate the system, build the plane-wave sphere and FFT
+ * maps, upload V_ext and the projector tables.  hip_stream may be NULL (the
+ * null stream) or a hipStream_t owned by the caller that outlives ctx. */
+roks_status roks_create(const roks_system* sys, void* hip_stream, roks_ctx* out);
+roks_status roks_destroy(roks_ctx ctx);
+const char* roks_last_error(roks_ctx ctx);
+const char* roks_version(void);
+
+/* Sizes: stored plane waves, FFT grid, projectors (l = 1 counts 3), bands. */
+roks_status roks_sizes(roks_ctx ctx, int32_t* npw, int32_t grid[3], int32_t* nproj,
+                       int32_t* nbands);
+/* Miller triples of the stored plane waves, [npw][3] int32, storage order. */
+roks_status roks_gvectors(roks_ctx ctx, int32_t* miller);
+
+/* Set the orbitals from c [nbands][npw][2]; orthonormalize != 0 applies the
+ * Cholesky orthonormalisation in band order (Gram-Schmidt).  Resets the CG
+ * state.  roks_get_coeffs copies the current orbitals out. */
+roks_status roks_set_coeffs(roks_ctx ctx, const double* c, int32_t orthonormalize);
+roks_status roks_get_coeffs(roks_ctx ctx, double* c);
+roks_status roks_set_coeffs_d(roks_ctx ctx, const void* c_dev, int32_t orthonormalize);
+roks_status roks_get_coeffs_d(roks_ctx ctx, void* c_dev);
+
+/* Move the atoms ([natoms][3] bohr): rebuilds V_ext and the projector tables
+ * and resets the CG state; orbitals are kept. */
+roks_status roks_set_positions(roks_ctx ctx, const double* pos);
+
+/* Apply the Kohn-Sham operators of the current orbitals' density to the
+ * vectors c_in [nbands][npw][2] (NULL: the current orbitals).
+ *   channel_mask == 0 ("shell mode"): h_out[n] = F^{X(n)} c_in[n] with F^X
+ *     the shell operator of band n (Eq. shell_operator; zero for virtual
+ *     bands); h_out is [nbands][npw][2].
+ *   channel_mask != 0: bit (2 L + s) selects H^{sigma L} (Eq. for H^{sigma L}:
+ *     T + V_NL + V_ext + V_H[rho_L] + v_xc^sigma[rho_L]); h_out is
+ *     [popcount(mask)][nbands][npw][2] in increasing bit order. */
+roks_status roks_apply_h(roks_ctx ctx, const double* c_in, uint32_t channel_mask,
+                         double* h_out);
+roks_status roks_apply_h_d(roks_ctx ctx, const void* c_in_dev, uint32_t channel_mask,
+                           void* h_out_dev);
+
+/* Energies of the current orbitals and, if grad != NULL, the out-of-subspace
+ * gradient g_I,n = (1 - sum_m |m><m|) F^n|n> (Eq. gradient), [nbands][npw][2];
+ * if theta != NULL the matrix theta_mn = <m|F^n|n> (Sec. II A, theta form of
+ * the gradient), [nbands][nbands] row-major (row m). */
+roks_status roks_energy_gradient(roks_ctx ctx, roks_energies* e, double* grad,
+                                 double* theta);
+
+/* Subspace matrices of the current orbitals, each [nbands][nbands]
+ * row-major: R_mn (Eq. r_matrix_singlet), the pair curvature kappa_mn and the
+ * rotation generator A_mn (Eqs. prec_grad_IIb/c).  Any pointer may be NULL. */
+roks_status roks_subspace(roks_ctx ctx, double* R, double* kappa, double* A);
+
+/* One preconditioned CG iteration with line search (Eqs. orbital_update,
+ * cg_search, prec_grad_I, prec_k and the conjugated rotation
+ * U = exp(Delta (A^i + gamma A^{i-1}))). */
+roks_status roks_pcg_step(roks_ctx ctx, roks_step_info* info);
+/* Forget the carried search directions (next step is steepest descent). */
+roks_status roks_reset_cg(roks_ctx ctx);
+/* Iterate roks_pcg_step until |E_{i+1} - E_i| < tol on two consecutive
+ * iterations or maxiter; *iterations receives the count, *last the final
+ * step's info (either may be NULL). */
+roks_status roks_solve(roks_ctx ctx, double tol, int32_t maxiter, roks_step_info* last,
+                       int32_t* iterations);
+
+/* Hellmann-Feynman forces F_I = -dE/dR_I (Eq. force_hf; the overlap term
+ * vanishes for S = 1) at the current orbitals, [natoms][3] Ha/bohr. */
+roks_status roks_forces(roks_ctx ctx, double* f);
+
+/* Wait for all work enqueued on the context's stream. */
+roks_status roks_synchronize(roks_ctx ctx);
+
+/* Diagnostics (no paper counterpart): GPU time of the library's kernels,
+ * measured with HIP events recorded on the context's stream around each
+ * launch.  roks_timing_enable(ctx, 1) clears the totals and starts
+ * recording, 0 stops.  roks_timing_read() synchronises the stream and
+ * returns the summed milliseconds and the launch count of one kernel family
+ * ("zpass_bwd", "plane_apply", "plane_density", "zpass_fwd", "fft3d",
+ * "gemm_wdot", "gemm_expand", "xc"); unknown names give zero. */
+roks_status roks_timing_enable(roks_ctx ctx, int32_t enable);
+roks_status roks_timing_read(roks_ctx ctx, const char* kernel, double* total_ms,
+                             int32_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ROKS_H */

@@ -91,13 +91,16 @@ class Model:
 
     # -- sphere -----------------------------------------------------------
     def _build_sphere(self):
-        gcut = np.sqrt(2.0 * self.ecut)
-        hmax = [int(np.floor(gcut * np.linalg.norm(self.cell[i]) / (2 * np.pi))) for i in range(3)]
+        # points on the cutoff within rounding (relative 1e-10) are included
+        ecut = self.ecut * (1.0 + 1e-10)
+        gcut = np.sqrt(2.0 * ecut)
+        hmax = [int(np.floor(gcut * np.linalg.norm(self.cell[i]) / (2 * np.pi))) + 1
+                for i in range(3)]
         rng = [np.arange(-h, h + 1) for h in hmax]
         m = np.stack(np.meshgrid(*rng, indexing="ij"), axis=-1).reshape(-1, 3)
         g = m @ self.recip
         g2 = (g * g).sum(axis=1)
-        keep = 0.5 * g2 <= self.ecut
+        keep = 0.5 * g2 <= ecut
         self.miller = m[keep]
         self.G = g[keep]
         self.g2 = g2[keep]
@@ -409,6 +412,14 @@ def gradient(model: Model, psi: np.ndarray, flags: Flags = Flags()) -> Gradient:
     R = np.zeros((nb, nb))
     kappa = np.zeros((nb, nb))
     A = np.zeros((nb, nb))
+    # diagonal blocks of Eq. (r_matrix_singlet): F^X for an occupied shell X,
+    # F^c for the virtual shell
+    for n in range(nb):
+        X = model.band_shell[n]
+        if not model.shell_virtual[X]:
+            R[n, n] = FXdiag[X, n]
+        elif closed:
+            R[n, n] = FXdiag[closed[0], n]
     for m in range(nb):
         for n in range(m + 1, nb):
             Xm, Xn = model.band_shell[m], model.band_shell[n]

@@ -1,0 +1,170 @@
+// Device memory layout and the upload of the static tables.
+#include <algorithm>
+#include <cmath>
+
+#include "roks_internal.h"
+
+namespace roks {
+
+void init_device(Ctx& c, void* stream) {
+  int ndev = 0;
+  ROKS_CHECK(hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0, ROKS_ERR_HIP, "no HIP device");
+  ROKS_HIP(hipGetDevice(&c.device));
+  c.stream = reinterpret_cast<hipStream_t>(stream);
+
+  const size_t nb = c.nb, npw = c.npw, ntot = c.ntot, np = c.nproj;
+  c.npairs = (c.nb + 1) / 2;
+  c.nchunk = std::max(1, std::min(c.npairs, cdiv(512, c.N[2])));
+
+  c.d_miller = dalloc<int32_t>(c, 3 * npw);
+  c.d_g2 = dalloc<double>(c, npw);
+  c.d_cols = dalloc<ColDesc>(c, c.cols.size());
+  c.d_colpos = dalloc<int32_t>(c, 2 * (size_t)c.ncol);
+  for (int d = 0; d < 3; ++d) c.d_tw[d] = dalloc<double2>(c, c.N[d]);
+  c.d_vext = dalloc<double>(c, ntot);
+  c.d_B = dalloc<double2>(c, np * npw);
+  c.d_proj_atom = dalloc<int32_t>(c, np);
+  c.d_Dblk = dalloc<double>(c, c.Dblk.size());
+  c.d_Dblk_off = dalloc<int32_t>(c, c.natoms);
+  c.d_atom_proj_off = dalloc<int32_t>(c, c.natoms);
+  c.d_atom_proj_cnt = dalloc<int32_t>(c, c.natoms);
+  c.d_band_shell = dalloc<int32_t>(c, nb);
+  c.d_atoms = dalloc<char>(c, atom_info_bytes() * std::max(1, c.natoms));
+  c.d_projinfo = dalloc<char>(c, proj_info_bytes() * std::max<size_t>(1, np));
+
+  const size_t band = nb * npw;
+  c.d_psi = dalloc<double2>(c, band);
+  c.d_in = dalloc<double2>(c, band);
+  c.d_Y = dalloc<double2>(c, band);
+  c.d_gI = dalloc<double2>(c, band);
+  c.d_p = dalloc<double2>(c, band);
+  c.d_S = dalloc<double2>(c, band);
+  c.d_Sold = dalloc<double2>(c, band);
+  c.d_Pt = dalloc<double2>(c, band);
+  c.d_trial = dalloc<double2>(c, 2 * band);
+  c.d_w1 = dalloc<double2>(c, band);
+  c.d_T = dalloc<double2>(c, (size_t)c.npairs * c.N[2] * c.ncol);
+  c.d_rho_part = dalloc<double>(c, (size_t)c.nchunk * c.nsocc * ntot);
+  c.d_rho = dalloc<double>(c, (size_t)c.nsocc * ntot);
+  c.d_vloc = dalloc<double>(c, (size_t)2 * c.nconf * ntot);
+  c.d_vsh = dalloc<double>(c, (size_t)c.nsocc * ntot);
+  c.d_vh = dalloc<double>(c, (size_t)c.nconf * ntot);
+  c.d_fft = dalloc<double2>(c, ntot);
+  c.d_P = dalloc<double>(c, np * nb);
+  c.d_DP = dalloc<double>(c, np * nb);
+  c.d_dP = dalloc<double>(c, np * nb);
+  c.part_capacity = std::max<size_t>(6 * 1024, (size_t)c.natoms * 32 * 3) + 64;
+  c.d_part = dalloc<double>(c, c.part_capacity);
+  c.d_scal = dalloc<double>(c, 16 + 2 * nb);
+  c.d_red = c.d_scal;
+  c.d_kin = c.d_scal + 16;
+  c.d_enl = c.d_scal + 16 + nb;
+  c.gemm_part_capacity = std::max<size_t>({4 * np * nb, 64 * nb * nb, (size_t)1 << 16});
+  c.d_gemm_part = dalloc<double>(c, c.gemm_part_capacity);
+  c.d_Qpart = dalloc<double>(c, (size_t)c.npairs * c.N[2] * 2 * c.nsocc);
+  c.d_Q = dalloc<double>(c, 2 * (size_t)c.npairs * c.nsocc);
+  c.d_bandv = dalloc<double>(c, 8 * nb);
+  const size_t nn = nb * nb;
+  double** mats[] = {&c.d_theta, &c.d_R, &c.d_kappa, &c.d_A, &c.d_D, &c.d_Dold, &c.d_gram,
+                     &c.d_Linv, &c.d_U, &c.d_M, &c.d_m1, &c.d_m2, &c.d_m3, &c.d_Mkeep,
+                     &c.d_Ukeep, &c.d_m4};
+  for (double** m : mats) *m = dalloc<double>(c, nn);
+  c.d_flag = dalloc<int32_t>(c, 16);
+  c.d_force = dalloc<double>(c, 3 * (size_t)std::max(1, c.natoms));
+  c.d_kinw_shell = dalloc<double>(c, nb);
+  c.d_ones = dalloc<double>(c, nb);
+  c.d_potidx = dalloc<int32_t>(c, (size_t)5 * nb);
+}
+
+void upload_static(Ctx& c) {
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (bytes) ROKS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c.stream));
+  };
+  up(c.d_miller, c.miller.data(), c.miller.size() * sizeof(int32_t));
+  up(c.d_g2, c.g2half.data(), c.g2half.size() * sizeof(double));
+  up(c.d_cols, c.cols.data(), c.cols.size() * sizeof(ColDesc));
+  std::vector<int32_t> colpos(2 * (size_t)c.ncol);
+  auto wrap = [](int v, int n) { return ((v % n) + n) % n; };
+  for (int j = 0; j <= c.nH; ++j) {
+    colpos[2 * j] = wrap(c.cols[j].h, c.N[0]);
+    colpos[2 * j + 1] = wrap(c.cols[j].k, c.N[1]);
+    if (j > 0) {
+      colpos[2 * (c.nH + j)] = wrap(-c.cols[j].h, c.N[0]);
+      colpos[2 * (c.nH + j) + 1] = wrap(-c.cols[j].k, c.N[1]);
+    }
+  }
+  up(c.d_colpos, colpos.data(), colpos.size() * sizeof(int32_t));
+  std::vector<double2> tw[3];  // host sources stay alive until the stream synchronises below
+  for (int d = 0; d < 3; ++d) {
+    tw[d].resize(c.N[d]);
+    for (int k = 0; k < c.N[d]; ++k) {
+      long double a = -2.0L * (long double)M_PI * (long double)k / (long double)c.N[d];
+      tw[d][k] = make_double2((double)std::cos(a), (double)std::sin(a));
+    }
+    up(c.d_tw[d], tw[d].data(), tw[d].size() * sizeof(double2));
+  }
+  up(c.d_proj_atom, c.proj_atom.data(), c.proj_atom.size() * sizeof(int32_t));
+  up(c.d_Dblk, c.Dblk.data(), c.Dblk.size() * sizeof(double));
+  up(c.d_Dblk_off, c.Dblk_off.data(), c.Dblk_off.size() * sizeof(int32_t));
+  up(c.d_atom_proj_off, c.atom_proj_off.data(), c.atom_proj_off.size() * sizeof(int32_t));
+  up(c.d_atom_proj_cnt, c.atom_proj_cnt.data(), c.atom_proj_cnt.size() * sizeof(int32_t));
+  up(c.d_band_shell, c.band_shell.data(), c.band_shell.size() * sizeof(int32_t));
+  // shell-mode kinetic weights and potential indices; channel-mode indices
+  std::vector<double> kw, ones;
+  std::vector<int32_t> pidx;
+  kw.assign(c.nb, 0.0);
+  ones.assign(c.nb, 1.0);
+  pidx.assign((size_t)5 * c.nb, -1);
+  for (int n = 0; n < c.nb; ++n) {
+    const int X = c.band_shell[n];
+    kw[n] = c.shell_virtual[X] ? 0.0 : c.shell_w[X];
+    pidx[n] = c.shell_virtual[X] ? -1 : X;
+    for (int ch = 0; ch < 4; ++ch) pidx[(size_t)(1 + ch) * c.nb + n] = ch;
+  }
+  up(c.d_kinw_shell, kw.data(), kw.size() * sizeof(double));
+  up(c.d_ones, ones.data(), ones.size() * sizeof(double));
+  up(c.d_potidx, pidx.data(), pidx.size() * sizeof(int32_t));
+  ROKS_HIP(hipStreamSynchronize(c.stream));
+  upload_positions(c);
+  ROKS_HIP(hipStreamSynchronize(c.stream));
+}
+
+KernelTimer::KernelTimer(Ctx& ctx, const char* name) : c(ctx) {
+  if (!c.timing) return;
+  Ctx::Timed t;
+  t.name = name;
+  if (hipEventCreate(&t.a) != hipSuccess) return;
+  if (hipEventCreate(&t.b) != hipSuccess) {
+    (void)hipEventDestroy(t.a);
+    return;
+  }
+  if (hipEventRecord(t.a, c.stream) != hipSuccess) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+    return;
+  }
+  c.timed.push_back(t);
+  idx = (int)c.timed.size() - 1;
+}
+
+KernelTimer::~KernelTimer() {
+  if (idx >= 0) (void)hipEventRecord(c.timed[idx].b, c.stream);
+}
+
+void clear_timing(Ctx& c) {
+  if (!c.timed.empty()) (void)hipStreamSynchronize(c.stream);
+  for (auto& t : c.timed) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  c.timed.clear();
+}
+
+void free_device(Ctx& c) {
+  clear_timing(c);
+  if (c.stream || !c.allocations.empty()) (void)hipStreamSynchronize(c.stream);
+  for (DevBuf& b : c.allocations) (void)hipFree(b.p);
+  c.allocations.clear();
+}
+
+}  // namespace roks

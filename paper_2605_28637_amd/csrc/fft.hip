@@ -1,0 +1,669 @@
+// Batched 3D FFTs of Gamma-point bands for gfx950, staged in LDS.
+//
+// One band pair (u1 + i u2, both real in r-space) is one complex transform.
+// The G -> r direction runs in two kernels:
+//   zpass_bwd  : gather the stored sphere into the full sphere's z-columns
+//                (column and mirror column from the same half column) and
+//                transform along z; writes T[pair][z][col].
+//   plane pass : per z-plane, scatter the columns into an N1 x N2 plane in
+//                LDS, transform along y (only the rows |h| <= hmax that hold
+//                data) and along x, then either multiply by the band's local
+//                potential and transform back (apply), or accumulate the
+//                squared real / imaginary parts into per-shell densities.
+// r -> G is zpass_fwd: transform along z, unpack the two bands with
+// c(-G) = conj(c(G)), scale by 1/N^3 and add the kinetic term.
+//
+// All 1D transforms are in-place mixed-radix Stockham passes (radices 8, 4,
+// 2, 3, 5): every thread stages the inputs of its butterflies in registers,
+// the block synchronises, and the outputs are written back to the same LDS.
+#include <cstdio>
+
+#include "roks_internal.h"
+
+namespace roks {
+
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// multiply by s*i (s = +-1)
+__device__ __forceinline__ double2 cmuli(double2 a, int s) {
+  return s > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+__device__ __forceinline__ double2 cscale(double2 a, double f) { return make_double2(a.x * f, a.y * f); }
+
+// DFT of length R with kernel exp(s 2 pi i r q / R), in place.
+template <int R>
+__device__ __forceinline__ void dft(double2* v, int s);
+
+template <>
+__device__ __forceinline__ void dft<2>(double2* v, int) {
+  double2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <>
+__device__ __forceinline__ void dft<4>(double2* v, int s) {
+  double2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+  double2 c = cadd(v[1], v[3]), d = cmuli(csub(v[1], v[3]), s);
+  v[0] = cadd(a, c);
+  v[2] = csub(a, c);
+  v[1] = cadd(b, d);
+  v[3] = csub(b, d);
+}
+
+template <>
+__device__ __forceinline__ void dft<8>(double2* v, int s) {
+  const double h = 0.70710678118654752440;
+  double2 e[4] = {v[0], v[2], v[4], v[6]};
+  double2 o[4] = {v[1], v[3], v[5], v[7]};
+  dft<4>(e, s);
+  dft<4>(o, s);
+  // w8^q = exp(s 2 pi i q / 8)
+  double2 o1 = make_double2(h * (o[1].x - s * o[1].y), h * (o[1].y + s * o[1].x));
+  double2 o2 = cmuli(o[2], s);
+  double2 o3 = make_double2(h * (-o[3].x - s * o[3].y), h * (-o[3].y + s * o[3].x));
+  v[0] = cadd(e[0], o[0]);
+  v[4] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], o1);
+  v[5] = csub(e[1], o1);
+  v[2] = cadd(e[2], o2);
+  v[6] = csub(e[2], o2);
+  v[3] = cadd(e[3], o3);
+  v[7] = csub(e[3], o3);
+}
+
+template <>
+__device__ __forceinline__ void dft<3>(double2* v, int s) {
+  const double r3 = 0.86602540378443864676;  // sqrt(3)/2
+  double2 t = cadd(v[1], v[2]);
+  double2 m = make_double2(v[0].x - 0.5 * t.x, v[0].y - 0.5 * t.y);
+  double2 d = cmuli(cscale(csub(v[1], v[2]), r3), s);
+  v[0] = cadd(v[0], t);
+  v[1] = cadd(m, d);
+  v[2] = csub(m, d);
+}
+
+template <>
+__device__ __forceinline__ void dft<5>(double2* v, int s) {
+  const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
+  const double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
+  double2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+  double2 d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
+  double2 a1 = make_double2(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
+  double2 a2 = make_double2(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
+  double2 b1 = cmuli(make_double2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y), s);
+  double2 b2 = cmuli(make_double2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y), s);
+  v[0] = cadd(v[0], cadd(t1, t2));
+  v[1] = cadd(a1, b1);
+  v[4] = csub(a1, b1);
+  v[2] = cadd(a2, b2);
+  v[3] = csub(a2, b2);
+}
+
+struct Strided {
+  int stride;
+  __device__ int operator()(int l) const { return l * stride; }
+};
+
+// Row r of the pruned set maps to h = r - hmax (mod N1).
+struct Rows {
+  int hmax, n1, rowstride;
+  __device__ int operator()(int r) const {
+    int h = r - hmax;
+    if (h < 0) h += n1;
+    return h * rowstride;
+  }
+};
+
+// One Stockham pass of radix R over `nlines` lines of length N.
+template <int RADIX, int MAXBF, typename LineMap>
+__device__ __forceinline__ void fft_stage(double2* buf, int N, int Ns, int nlines, LineMap lm,
+                                          int estride, const double2* tw, int sign) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int NR = N / RADIX;
+  const int nbf = nlines * NR;
+  const int twstep = N / (Ns * RADIX);
+  double2 v[MAXBF][RADIX];
+#pragma unroll
+  for (int i = 0; i < MAXBF; ++i) {
+    const int b = tid + i * nthr;
+    if (b < nbf) {
+      const int line = b / NR, t = b - line * NR;
+      const double2* src = buf + lm(line);
+#pragma unroll
+      for (int r = 0; r < RADIX; ++r) v[i][r] = src[(t + r * NR) * estride];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MAXBF; ++i) {
+    const int b = tid + i * nthr;
+    if (b < nbf) {
+      const int line = b / NR, t = b - line * NR;
+      const int k = t % Ns;
+      if (k != 0) {
+#pragma unroll
+        for (int r = 1; r < RADIX; ++r) {
+          double2 w = tw[k * r * twstep];  // exp(-2 pi i k r / (Ns R))
+          if (sign > 0) w.y = -w.y;
+          v[i][r] = cmul(v[i][r], w);
+        }
+      }
+      dft<RADIX>(v[i], sign);
+      const int j = (t / Ns) * Ns * RADIX + k;
+      double2* dst = buf + lm(line);
+#pragma unroll
+      for (int r = 0; r < RADIX; ++r) dst[(j + r * Ns) * estride] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Transform `nlines` lines in place; MAXP bounds ceil(nlines N / blockDim).
+template <int MAXP, typename LineMap>
+__device__ void fft_lines(double2* buf, const FftPlan1D& plan, int nlines, LineMap lm, int estride,
+                          const double2* tw, int sign) {
+  int Ns = 1;
+  for (int s = 0; s < plan.nstages; ++s) {
+    const int R = plan.radix[s];
+    switch (R) {
+      case 8: fft_stage<8, (MAXP + 7) / 8>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
+      case 4: fft_stage<4, (MAXP + 3) / 4>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
+      case 2: fft_stage<2, (MAXP + 1) / 2>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
+      case 3: fft_stage<3, (MAXP + 2) / 3>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
+      default: fft_stage<5, (MAXP + 4) / 5>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
+    }
+    Ns *= R;
+  }
+}
+
+__device__ __forceinline__ int wrap(int l, int n) {
+  int r = l % n;
+  return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// z pass, G -> r
+// ---------------------------------------------------------------------------
+template <int MAXP>
+__global__ void __launch_bounds__(256) k_zpass_bwd(const double2* __restrict__ vecs, int nvec,
+                                                    int npw, const ColDesc* __restrict__ cols,
+                                                    int ndesc, int nH, FftPlan1D plan,
+                                                    const double2* __restrict__ twg,
+                                                    double2* __restrict__ T, int ncol, int CH) {
+  extern __shared__ double2 smem[];
+  const int N3 = plan.n;
+  double2* tw = smem;
+  double2* buf = smem + N3;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int pair = blockIdx.y;
+  const int j0 = blockIdx.x * CH;
+  const int n1 = 2 * pair, n2 = 2 * pair + 1;
+  const double2* c1 = vecs + (size_t)n1 * npw;
+  const double2* c2 = vecs + (size_t)n2 * npw;
+  const bool has2 = n2 < nvec;
+  for (int i = tid; i < N3; i += nthr) tw[i] = twg[i];
+  for (int i = tid; i < 2 * CH * N3; i += nthr) buf[i] = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int idx = tid; idx < CH * N3; idx += nthr) {
+    const int c = idx / N3, e = idx - c * N3;
+    const int j = j0 + c;
+    if (j >= ndesc) continue;
+    const ColDesc d = cols[j];
+    if (e > d.lmax - d.lmin) continue;
+    const int l = d.lmin + e;
+    const int g = d.base + e;
+    const double2 a = c1[g];
+    const double2 b = has2 ? c2[g] : make_double2(0.0, 0.0);
+    const double2 v = make_double2(a.x - b.y, a.y + b.x);    // c1 + i c2
+    const double2 vm = make_double2(a.x + b.y, b.x - a.y);   // conj(c1) + i conj(c2)
+    buf[(2 * c) * N3 + wrap(l, N3)] = v;
+    if (j > 0)
+      buf[(2 * c + 1) * N3 + wrap(-l, N3)] = vm;
+    else if (l > 0)
+      buf[(2 * c) * N3 + wrap(-l, N3)] = vm;
+  }
+  __syncthreads();
+  fft_lines<MAXP>(buf, plan, 2 * CH, Strided{N3}, 1, tw, +1);
+  for (int idx = tid; idx < CH * N3; idx += nthr) {
+    const int z = idx / CH, c = idx - z * CH;
+    const int j = j0 + c;
+    if (j >= ndesc) continue;
+    const size_t row = ((size_t)pair * N3 + z) * ncol;
+    T[row + j] = buf[(2 * c) * N3 + z];
+    if (j > 0) T[row + nH + j] = buf[(2 * c + 1) * N3 + z];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// z pass, r -> G, with unpacking, scaling and the kinetic term
+// ---------------------------------------------------------------------------
+template <int MAXP>
+__global__ void __launch_bounds__(256) k_zpass_fwd(
+    const double2* __restrict__ T, int ncol, const ColDesc* __restrict__ cols, int ndesc, int nH,
+    FftPlan1D plan, const double2* __restrict__ twg, const double2* __restrict__ vecs, int nvec,
+    int npw, const double* __restrict__ kinw, const double* __restrict__ g2, double scale,
+    double2* __restrict__ Y, int CH) {
+  extern __shared__ double2 smem[];
+  const int N3 = plan.n;
+  double2* tw = smem;
+  double2* buf = smem + N3;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int pair = blockIdx.y;
+  const int j0 = blockIdx.x * CH;
+  const int n1 = 2 * pair, n2 = 2 * pair + 1;
+  const bool has2 = n2 < nvec;
+  for (int i = tid; i < N3; i += nthr) tw[i] = twg[i];
+  for (int idx = tid; idx < CH * N3; idx += nthr) {
+    const int z = idx / CH, c = idx - z * CH;
+    const int j = j0 + c;
+    const size_t row = ((size_t)pair * N3 + z) * ncol;
+    double2 s = make_double2(0.0, 0.0), m = make_double2(0.0, 0.0);
+    if (j < ndesc) {
+      s = T[row + j];
+      if (j > 0) m = T[row + nH + j];
+    }
+    buf[(2 * c) * N3 + z] = s;
+    buf[(2 * c + 1) * N3 + z] = m;
+  }
+  __syncthreads();
+  fft_lines<MAXP>(buf, plan, 2 * CH, Strided{N3}, 1, tw, -1);
+  const double w1 = kinw[n1];
+  const double w2 = has2 ? kinw[n2] : 0.0;
+  for (int idx = tid; idx < CH * N3; idx += nthr) {
+    const int c = idx / N3, e = idx - c * N3;
+    const int j = j0 + c;
+    if (j >= ndesc) continue;
+    const ColDesc d = cols[j];
+    if (e > d.lmax - d.lmin) continue;
+    const int l = d.lmin + e;
+    const int g = d.base + e;
+    const double2 F = buf[(2 * c) * N3 + wrap(l, N3)];
+    const double2 Fm = (j == 0) ? buf[(2 * c) * N3 + wrap(-l, N3)] : buf[(2 * c + 1) * N3 + wrap(-l, N3)];
+    const double2 y1 = make_double2(0.5 * (F.x + Fm.x), 0.5 * (F.y - Fm.y));
+    const double2 dd = make_double2(0.5 * (F.x - Fm.x), 0.5 * (F.y + Fm.y));
+    const double2 y2 = make_double2(dd.y, -dd.x);
+    const double k = g2[g];
+    const double2 a = vecs[(size_t)n1 * npw + g];
+    Y[(size_t)n1 * npw + g] = make_double2(scale * y1.x + w1 * k * a.x, scale * y1.y + w1 * k * a.y);
+    if (has2) {
+      const double2 b = vecs[(size_t)n2 * npw + g];
+      Y[(size_t)n2 * npw + g] = make_double2(scale * y2.x + w2 * k * b.x, scale * y2.y + w2 * k * b.y);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// plane pass: scatter, y/x backward, potential multiply, x/y forward, gather
+// ---------------------------------------------------------------------------
+struct PlaneGeom {
+  int N1, N2, N3, PS, hmax, ncol;
+  FftPlan1D p1, p2;
+};
+
+template <int MAXP>
+__global__ void __launch_bounds__(512) k_plane_apply(
+    double2* __restrict__ T, const int32_t* __restrict__ colpos, PlaneGeom g,
+    const double2* __restrict__ tw1g, const double2* __restrict__ tw2g,
+    const double* __restrict__ pot, size_t ntot, const int32_t* __restrict__ potidx, int nvec,
+    const double* __restrict__ vq, int nQ, double* __restrict__ Qpart) {
+  extern __shared__ double2 smem[];
+  double2* tw1 = smem;
+  double2* tw2 = smem + g.N1;
+  double2* plane = smem + g.N1 + g.N2;
+  double* red = reinterpret_cast<double*>(plane + g.N1 * g.PS);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int z = blockIdx.x, pair = blockIdx.y;
+  const int n1 = 2 * pair, n2 = 2 * pair + 1;
+  const int np2 = g.N1 * g.N2;
+  for (int i = tid; i < g.N1; i += nthr) tw1[i] = tw1g[i];
+  for (int i = tid; i < g.N2; i += nthr) tw2[i] = tw2g[i];
+  for (int i = tid; i < g.N1 * g.PS; i += nthr) plane[i] = make_double2(0.0, 0.0);
+  __syncthreads();
+  double2* Tz = T + ((size_t)pair * g.N3 + z) * g.ncol;
+  for (int col = tid; col < g.ncol; col += nthr)
+    plane[colpos[2 * col] * g.PS + colpos[2 * col + 1]] = Tz[col];
+  __syncthreads();
+  const int nh = 2 * g.hmax + 1;
+  fft_lines<MAXP>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, +1);
+  fft_lines<MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, +1);
+  const int i1 = potidx[n1];
+  const int i2 = n2 < nvec ? potidx[n2] : -1;
+  const double* V1 = i1 >= 0 ? pot + (size_t)i1 * ntot : nullptr;
+  const double* V2 = i2 >= 0 ? pot + (size_t)i2 * ntot : nullptr;
+  const size_t zoff = (size_t)z * np2;
+  double q1[kMaxShell] = {0, 0, 0, 0}, q2[kMaxShell] = {0, 0, 0, 0};
+  for (int pt = tid; pt < np2; pt += nthr) {
+    const int x = pt / g.N2, y = pt - x * g.N2;
+    double2& w = plane[x * g.PS + y];
+    const double u1 = w.x, u2 = w.y;
+#pragma unroll
+    for (int X = 0; X < kMaxShell; ++X) {
+      if (X < nQ) {
+        const double vx = vq[(size_t)X * ntot + zoff + pt];
+        q1[X] += vx * u1 * u1;
+        q2[X] += vx * u2 * u2;
+      }
+    }
+    const double a = V1 ? V1[zoff + pt] : 0.0;
+    const double b = V2 ? V2[zoff + pt] : 0.0;
+    w = make_double2(a * u1, b * u2);
+  }
+  __syncthreads();
+  fft_lines<MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, -1);
+  fft_lines<MAXP>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, -1);
+  for (int col = tid; col < g.ncol; col += nthr)
+    Tz[col] = plane[colpos[2 * col] * g.PS + colpos[2 * col + 1]];
+  if (nQ > 0) {
+    const int wid = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+    for (int X = 0; X < nQ; ++X) {
+      const double s1 = wave_sum(q1[X]);
+      const double s2 = wave_sum(q2[X]);
+      if (lane == 0) {
+        red[(2 * X) * nw + wid] = s1;
+        red[(2 * X + 1) * nw + wid] = s2;
+      }
+    }
+    __syncthreads();
+    if (tid < 2 * nQ) {
+      double s = 0;
+      for (int w = 0; w < nw; ++w) s += red[tid * nw + w];
+      const int X = tid >> 1, b = tid & 1;
+      // Qpart[pair][z][band b][X]
+      Qpart[(((size_t)pair * g.N3 + z) * 2 + b) * nQ + X] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// plane pass for densities: G -> r only, accumulate per-shell |u|^2
+// ---------------------------------------------------------------------------
+template <int MAXP>
+__global__ void __launch_bounds__(512) k_plane_density(
+    const double2* __restrict__ T, const int32_t* __restrict__ colpos, PlaneGeom g,
+    const double2* __restrict__ tw1g, const double2* __restrict__ tw2g,
+    const int32_t* __restrict__ band_shell, int nvec, int nsocc, int npairs, int per_chunk,
+    double* __restrict__ rho_part, size_t ntot) {
+  extern __shared__ double2 smem[];
+  double2* tw1 = smem;
+  double2* tw2 = smem + g.N1;
+  double2* plane = smem + g.N1 + g.N2;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int z = blockIdx.x, chunk = blockIdx.y;
+  const int np2 = g.N1 * g.N2;
+  const int nh = 2 * g.hmax + 1;
+  for (int i = tid; i < g.N1; i += nthr) tw1[i] = tw1g[i];
+  for (int i = tid; i < g.N2; i += nthr) tw2[i] = tw2g[i];
+  double acc[3][MAXP];
+#pragma unroll
+  for (int X = 0; X < 3; ++X)
+#pragma unroll
+    for (int i = 0; i < MAXP; ++i) acc[X][i] = 0.0;
+  const int p0 = chunk * per_chunk;
+  const int p1 = min(npairs, p0 + per_chunk);
+  for (int pair = p0; pair < p1; ++pair) {
+    for (int i = tid; i < g.N1 * g.PS; i += nthr) plane[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+    const double2* Tz = T + ((size_t)pair * g.N3 + z) * g.ncol;
+    for (int col = tid; col < g.ncol; col += nthr)
+      plane[colpos[2 * col] * g.PS + colpos[2 * col + 1]] = Tz[col];
+    __syncthreads();
+    fft_lines<MAXP>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, +1);
+    fft_lines<MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, +1);
+    const int s1 = band_shell[2 * pair];
+    const int s2 = (2 * pair + 1 < nvec) ? band_shell[2 * pair + 1] : 99;
+#pragma unroll
+    for (int i = 0; i < MAXP; ++i) {
+      const int pt = tid + i * nthr;
+      if (pt < np2) {
+        const int x = pt / g.N2, y = pt - x * g.N2;
+        const double2 w = plane[x * g.PS + y];
+#pragma unroll
+        for (int X = 0; X < 3; ++X)
+          acc[X][i] += (s1 == X ? w.x * w.x : 0.0) + (s2 == X ? w.y * w.y : 0.0);
+      }
+    }
+    __syncthreads();
+  }
+  const size_t zoff = (size_t)z * np2;
+#pragma unroll
+  for (int X = 0; X < 3; ++X) {
+    if (X < nsocc) {
+      double* out = rho_part + ((size_t)chunk * nsocc + X) * ntot + zoff;
+#pragma unroll
+      for (int i = 0; i < MAXP; ++i) {
+        const int pt = tid + i * nthr;
+        if (pt < np2) out[pt] = acc[X][i];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// full-grid complex 3D FFT on [z][x][y] data (Hartree, V_ext)
+// ---------------------------------------------------------------------------
+template <int MAXP>
+__global__ void __launch_bounds__(512) k_fft_planes(double2* __restrict__ data, PlaneGeom g,
+                                                    const double2* __restrict__ tw1g,
+                                                    const double2* __restrict__ tw2g, int sign) {
+  extern __shared__ double2 smem[];
+  double2* tw1 = smem;
+  double2* tw2 = smem + g.N1;
+  double2* plane = smem + g.N1 + g.N2;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int z = blockIdx.x;
+  const int np2 = g.N1 * g.N2;
+  for (int i = tid; i < g.N1; i += nthr) tw1[i] = tw1g[i];
+  for (int i = tid; i < g.N2; i += nthr) tw2[i] = tw2g[i];
+  double2* d = data + (size_t)z * np2;
+  for (int pt = tid; pt < np2; pt += nthr) {
+    const int x = pt / g.N2, y = pt - x * g.N2;
+    plane[x * g.PS + y] = d[pt];
+  }
+  __syncthreads();
+  fft_lines<MAXP>(plane, g.p2, g.N1, Strided{g.PS}, 1, tw2, sign);
+  fft_lines<MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, sign);
+  for (int pt = tid; pt < np2; pt += nthr) {
+    const int x = pt / g.N2, y = pt - x * g.N2;
+    d[pt] = plane[x * g.PS + y];
+  }
+}
+
+template <int MAXP>
+__global__ void __launch_bounds__(256) k_fft_zlines(double2* __restrict__ data, int np2,
+                                                    FftPlan1D plan, const double2* __restrict__ twg,
+                                                    int CH, int sign) {
+  extern __shared__ double2 smem[];
+  const int N3 = plan.n;
+  double2* tw = smem;
+  double2* buf = smem + N3;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int p0 = blockIdx.x * CH;
+  for (int i = tid; i < N3; i += nthr) tw[i] = twg[i];
+  for (int idx = tid; idx < CH * N3; idx += nthr) {
+    const int z = idx / CH, c = idx - z * CH;
+    buf[c * N3 + z] = (p0 + c < np2) ? data[(size_t)z * np2 + p0 + c] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  fft_lines<MAXP>(buf, plan, CH, Strided{N3}, 1, tw, sign);
+  for (int idx = tid; idx < CH * N3; idx += nthr) {
+    const int z = idx / CH, c = idx - z * CH;
+    if (p0 + c < np2) data[(size_t)z * np2 + p0 + c] = buf[c * N3 + z];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+int plane_threads(const Ctx& c) { return c.N[0] * c.N[1] > 4096 ? 512 : 256; }
+
+int needed_points(int points, int nthr) { return (points + nthr - 1) / nthr; }
+
+int pick_maxp(int need) {
+  ROKS_CHECK(need <= 32, ROKS_ERR_SHAPE, "FFT plane too large for the LDS kernels");
+  if (need <= 8) return 8;
+  if (need <= 16) return 16;
+  if (need <= 24) return 24;
+  return 32;
+}
+
+PlaneGeom geom(const Ctx& c) {
+  PlaneGeom g;
+  g.N1 = c.N[0];
+  g.N2 = c.N[1];
+  g.N3 = c.N[2];
+  g.PS = c.N[1] + 1;
+  g.hmax = c.hmax;
+  g.ncol = c.ncol;
+  g.p1 = c.plan[0];
+  g.p2 = c.plan[1];
+  return g;
+}
+
+size_t plane_lds(const Ctx& c, int nthr, int nQ) {
+  size_t b = (size_t)(c.N[0] + c.N[1] + c.N[0] * (c.N[1] + 1)) * sizeof(double2);
+  b += (size_t)2 * kMaxShell * (nthr / 64) * sizeof(double);
+  return b;
+}
+
+int zchunk(const Ctx& c) {
+  const int N3 = c.N[2];
+  int CH = 32;
+  while (CH > 1 && 2 * CH * N3 > 256 * 16) CH /= 2;
+  return CH;
+}
+
+template <typename K>
+void allow_lds(K kernel, size_t bytes) {
+  if (bytes > 65536)
+    ROKS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+}  // namespace
+
+#define ROKS_DISPATCH_MAXP(mp, KER, ...)                      \
+  switch (mp) {                                               \
+    case 8: KER<8>(__VA_ARGS__); break;                       \
+    case 16: KER<16>(__VA_ARGS__); break;                     \
+    case 24: KER<24>(__VA_ARGS__); break;                     \
+    default: KER<32>(__VA_ARGS__); break;                     \
+  }
+
+template <int MP>
+static void run_zpass_bwd(Ctx& c, const double2* vecs, int nvec, double2* T, int npairs, int CH) {
+  const int nthr = 256;
+  const size_t lds = (size_t)(c.N[2] + 2 * CH * c.N[2]) * sizeof(double2);
+  allow_lds(k_zpass_bwd<MP>, lds);
+  dim3 grid(cdiv(c.nH + 1, CH), npairs);
+  hipLaunchKernelGGL(k_zpass_bwd<MP>, grid, dim3(nthr), lds, c.stream, vecs, nvec, c.npw, c.d_cols,
+                     c.nH + 1, c.nH, c.plan[2], c.d_tw[2], T, c.ncol, CH);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_zpass_bwd(Ctx& c, const double2* vecs, int nvec, double2* T, int npairs) {
+  KernelTimer kt(c, "zpass_bwd");
+  const int CH = zchunk(c);
+  const int mp = pick_maxp(needed_points(2 * CH * c.N[2], 256));
+  ROKS_DISPATCH_MAXP(mp, run_zpass_bwd, c, vecs, nvec, T, npairs, CH);
+}
+
+template <int MP>
+static void run_zpass_fwd(Ctx& c, const double2* T, int npairs, const double2* vecs, int nvec,
+                          const double* kinw, double2* Y, int CH) {
+  const size_t lds = (size_t)(c.N[2] + 2 * CH * c.N[2]) * sizeof(double2);
+  allow_lds(k_zpass_fwd<MP>, lds);
+  dim3 grid(cdiv(c.nH + 1, CH), npairs);
+  hipLaunchKernelGGL(k_zpass_fwd<MP>, grid, dim3(256), lds, c.stream, T, c.ncol, c.d_cols, c.nH + 1,
+                     c.nH, c.plan[2], c.d_tw[2], vecs, nvec, c.npw, kinw, c.d_g2,
+                     1.0 / (double)c.ntot, Y, CH);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_zpass_fwd(Ctx& c, const double2* T, int npairs, const double2* vecs, int nvec,
+                      const double* kinw, double2* Y) {
+  KernelTimer kt(c, "zpass_fwd");
+  const int CH = zchunk(c);
+  const int mp = pick_maxp(needed_points(2 * CH * c.N[2], 256));
+  ROKS_DISPATCH_MAXP(mp, run_zpass_fwd, c, T, npairs, vecs, nvec, kinw, Y, CH);
+}
+
+template <int MP>
+static void run_plane_apply(Ctx& c, double2* T, int npairs, const double* pot,
+                            const int32_t* potidx, int nvec, double* Qpart, int nQ) {
+  const int nthr = plane_threads(c);
+  const size_t lds = plane_lds(c, nthr, nQ);
+  allow_lds(k_plane_apply<MP>, lds);
+  dim3 grid(c.N[2], npairs);
+  hipLaunchKernelGGL(k_plane_apply<MP>, grid, dim3(nthr), lds, c.stream, T, c.d_colpos, geom(c),
+                     c.d_tw[0], c.d_tw[1], pot, (size_t)c.ntot, potidx, nvec, c.d_vsh, nQ, Qpart);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_plane_apply(Ctx& c, double2* T, int npairs, const double* pot, const int32_t* potidx,
+                        int nvec, double* Qpart, int nQ) {
+  KernelTimer kt(c, "plane_apply");
+  const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], plane_threads(c)));
+  ROKS_DISPATCH_MAXP(mp, run_plane_apply, c, T, npairs, pot, potidx, nvec, Qpart, nQ);
+}
+
+template <int MP>
+static void run_plane_density(Ctx& c, const double2* T, int npairs, double* rho_part, int nchunk) {
+  const int nthr = plane_threads(c);
+  const size_t lds = plane_lds(c, nthr, 0);
+  allow_lds(k_plane_density<MP>, lds);
+  const int per = cdiv(npairs, nchunk);
+  dim3 grid(c.N[2], nchunk);
+  hipLaunchKernelGGL(k_plane_density<MP>, grid, dim3(nthr), lds, c.stream, T, c.d_colpos, geom(c),
+                     c.d_tw[0], c.d_tw[1], c.d_band_shell, c.nb, c.nsocc, npairs, per, rho_part,
+                     (size_t)c.ntot);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_plane_density(Ctx& c, const double2* T, int npairs, double* rho_part, int nchunk) {
+  KernelTimer kt(c, "plane_density");
+  const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], plane_threads(c)));
+  ROKS_DISPATCH_MAXP(mp, run_plane_density, c, T, npairs, rho_part, nchunk);
+}
+
+template <int MP>
+static void run_fft_planes(Ctx& c, double2* data, int sign) {
+  const int nthr = plane_threads(c);
+  const size_t lds = plane_lds(c, nthr, 0);
+  allow_lds(k_fft_planes<MP>, lds);
+  hipLaunchKernelGGL(k_fft_planes<MP>, dim3(c.N[2]), dim3(nthr), lds, c.stream, data, geom(c),
+                     c.d_tw[0], c.d_tw[1], sign);
+  ROKS_HIP(hipGetLastError());
+}
+
+template <int MP>
+static void run_fft_zlines(Ctx& c, double2* data, int sign, int CH) {
+  const size_t lds = (size_t)(c.N[2] + CH * c.N[2]) * sizeof(double2);
+  allow_lds(k_fft_zlines<MP>, lds);
+  const int np2 = c.N[0] * c.N[1];
+  hipLaunchKernelGGL(k_fft_zlines<MP>, dim3(cdiv(np2, CH)), dim3(256), lds, c.stream, data, np2,
+                     c.plan[2], c.d_tw[2], CH, sign);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_fft3d(Ctx& c, double2* data, int sign) {
+  KernelTimer kt(c, "fft3d");
+  const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], plane_threads(c)));
+  ROKS_DISPATCH_MAXP(mp, run_fft_planes, c, data, sign);
+  const int CH = 2 * zchunk(c);
+  const int mz = pick_maxp(needed_points(CH * c.N[2], 256));
+  ROKS_DISPATCH_MAXP(mz, run_fft_zlines, c, data, sign, CH);
+}
+
+}  // namespace roks

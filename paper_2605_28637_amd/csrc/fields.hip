@@ -1,0 +1,590 @@
+// Pointwise and reduction kernels: external potential, projector tables,
+// shell densities, Hartree and spin-LDA exchange-correlation potentials,
+// energy terms and forces.  All reductions use a fixed block count and a
+// fixed order (partials, then an ordered sum), so results are reproducible.
+#include <cmath>
+
+#include "roks_internal.h"
+
+namespace roks {
+
+namespace {
+
+constexpr int kRedBlocks = 1024;
+
+struct Lattice {
+  double b[3][3];  // reciprocal vectors (rows)
+  int N[3];
+  double omega;
+};
+
+Lattice lattice(const Ctx& c) {
+  Lattice L;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) L.b[i][j] = c.recip[i][j];
+  for (int d = 0; d < 3; ++d) L.N[d] = c.N[d];
+  L.omega = c.omega;
+  return L;
+}
+
+// grid index [z][x][y] -> signed frequencies (h, k, l); returns true on a
+// Nyquist plane of an even grid
+__device__ __forceinline__ bool grid_freq(const Lattice& L, size_t i, int* m) {
+  const int np2 = L.N[0] * L.N[1];
+  const int z = (int)(i / np2);
+  const int r = (int)(i - (size_t)z * np2);
+  const int x = r / L.N[1], y = r - x * L.N[1];
+  const int idx[3] = {x, y, z};
+  bool nyq = false;
+  for (int d = 0; d < 3; ++d) {
+    int v = idx[d];
+    if (2 * v >= L.N[d]) v -= L.N[d];
+    if ((L.N[d] & 1) == 0 && 2 * v == -L.N[d]) nyq = true;
+    m[d] = v;
+  }
+  return nyq;
+}
+
+__device__ __forceinline__ void gvec(const Lattice& L, const int* m, double* G) {
+  for (int a = 0; a < 3; ++a) G[a] = m[0] * L.b[0][a] + m[1] * L.b[1][a] + m[2] * L.b[2][a];
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// block sum of k values per thread (k <= 8); result valid in thread 0
+template <int K>
+__device__ void block_sum(double (&v)[K], double* red) {
+  const int tid = threadIdx.x, nw = blockDim.x >> 6, wid = tid >> 6, lane = tid & 63;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    double s = wave_sum(v[j]);
+    if (lane == 0) red[j * 16 + wid] = s;
+  }
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      double s = 0;
+      for (int w = 0; w < nw; ++w) s += red[j * 16 + w];
+      v[j] = s;
+    }
+  }
+  __syncthreads();
+}
+
+struct AtomP {
+  double x, y, z, A, sigma;
+};
+
+// ---------------------------------------------------------------------------
+// V_ext(G) on the grid: Omega^-1 sum_I v_s(G) e^{-iG.R_I}; Nyquist planes zero
+// ---------------------------------------------------------------------------
+__global__ void k_vext_G(Lattice L, const AtomP* __restrict__ atoms, int natoms,
+                         double2* __restrict__ out, size_t ntot) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
+       i += (size_t)gridDim.x * blockDim.x) {
+    int m[3];
+    const bool nyq = grid_freq(L, i, m);
+    double G[3];
+    gvec(L, m, G);
+    const double g2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+    double re = 0, im = 0;
+    if (!nyq) {
+      for (int a = 0; a < natoms; ++a) {
+        const AtomP p = atoms[a];
+        const double s2 = p.sigma * p.sigma;
+        const double vs = -p.A * pow(2.0 * M_PI * s2, 1.5) * exp(-0.5 * g2 * s2);
+        const double th = G[0] * p.x + G[1] * p.y + G[2] * p.z;
+        double sn, cs;
+        sincos(th, &sn, &cs);
+        re += vs * cs;
+        im -= vs * sn;
+      }
+    }
+    out[i] = make_double2(re / L.omega, im / L.omega);
+  }
+}
+
+__global__ void k_take_real(const double2* __restrict__ in, double* __restrict__ out, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    out[i] = in[i].x;
+}
+
+// ---------------------------------------------------------------------------
+// projector table beta_i(G) = Omega^-1/2 f_i(G) e^{-iG.R} (optionally times -iG_a)
+// ---------------------------------------------------------------------------
+struct ProjP {
+  int atom, l, m;
+  double rp;
+};
+
+__global__ void k_projectors(Lattice L, const int32_t* __restrict__ miller, int npw,
+                             const ProjP* __restrict__ proj, int nproj,
+                             const AtomP* __restrict__ atoms, int axis, double2* __restrict__ B) {
+  const size_t total = (size_t)nproj * npw;
+  const double inv_sqrt_omega = 1.0 / sqrt(L.omega);
+  const double c0 = 4.0 * M_PI;
+  const double c1 = 4.0 * pow(M_PI, 0.75);
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
+       t += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t / npw), g = (int)(t - (size_t)i * npw);
+    const int m[3] = {miller[3 * g], miller[3 * g + 1], miller[3 * g + 2]};
+    double G[3];
+    gvec(L, m, G);
+    const double g2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+    const ProjP p = proj[i];
+    const AtomP a = atoms[p.atom];
+    const double e = exp(-0.5 * g2 * p.rp * p.rp) * inv_sqrt_omega;
+    const double th = G[0] * a.x + G[1] * a.y + G[2] * a.z;
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    double2 v;
+    if (p.l == 0) {
+      const double f = pow(c0 * p.rp * p.rp, 0.75) * e;
+      v = make_double2(f * cs, -f * sn);
+    } else {
+      const double f = c1 * pow(p.rp, 2.5) * e * G[p.m];
+      // -i f (cos - i sin) = f (-sin, -cos)
+      v = make_double2(-f * sn, -f * cs);
+    }
+    if (axis >= 0) {
+      const double ga = G[axis];
+      v = make_double2(ga * v.y, -ga * v.x);  // times -i G_a
+    }
+    B[t] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// densities
+// ---------------------------------------------------------------------------
+__global__ void k_density_reduce(const double* __restrict__ part, int nchunk, int nsocc,
+                                 size_t ntot, double inv_omega, double* __restrict__ rho) {
+  const size_t total = (size_t)nsocc * ntot;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
+       t += (size_t)gridDim.x * blockDim.x) {
+    double s = 0;
+    for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * total + t];
+    rho[t] = s * inv_omega;
+  }
+}
+
+struct ShellArgs {
+  int nconf, nsocc, xc;
+  double f[3][kMaxConf][2];
+  double cL[kMaxConf];
+};
+
+// configuration densities rho_L = sum_X (f_X^up + f_X^dn) rho_X packed as rho_0 + i rho_1
+__global__ void k_pack_rho(ShellArgs a, const double* __restrict__ rho, size_t ntot,
+                           double2* __restrict__ out, int weighted) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double r[kMaxConf] = {0, 0};
+    for (int X = 0; X < a.nsocc; ++X) {
+      const double v = rho[(size_t)X * ntot + i];
+      for (int L = 0; L < a.nconf; ++L) r[L] += (a.f[X][L][0] + a.f[X][L][1]) * v;
+    }
+    if (weighted) {
+      double s = 0;
+      for (int L = 0; L < a.nconf; ++L) s += a.cL[L] * r[L];
+      out[i] = make_double2(s, 0.0);
+    } else {
+      out[i] = make_double2(r[0], a.nconf > 1 ? r[1] : 0.0);
+    }
+  }
+}
+
+// V_H(G) = 4 pi rho(G) / G^2, rho(G) = FFT(rho)/N^3; G = 0 -> 0
+__global__ void k_hartree_mul(Lattice L, double2* __restrict__ f, size_t ntot) {
+  const double inv = 1.0 / (double)ntot;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
+       i += (size_t)gridDim.x * blockDim.x) {
+    int m[3];
+    grid_freq(L, i, m);
+    double G[3];
+    gvec(L, m, G);
+    const double g2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+    const double s = g2 > 0.0 ? 4.0 * M_PI * inv / g2 : 0.0;
+    f[i] = make_double2(f[i].x * s, f[i].y * s);
+  }
+}
+
+__global__ void k_unpack_vh(const double2* __restrict__ f, size_t ntot, int nconf,
+                            double* __restrict__ vh) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
+       i += (size_t)gridDim.x * blockDim.x) {
+    vh[i] = f[i].x;
+    if (nconf > 1) vh[ntot + i] = f[i].y;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// spin LDA: Slater exchange + Perdew-Wang 1992 correlation
+// ---------------------------------------------------------------------------
+__device__ void pw92_G(double rs, double A, double a1, double b1, double b2, double b3, double b4,
+                       double* G, double* dG) {
+  const double srs = sqrt(rs);
+  const double Q = 2.0 * A * (b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs);
+  const double dQ = 2.0 * A * (0.5 * b1 / srs + b2 + 1.5 * b3 * srs + 2.0 * b4 * rs);
+  const double lg = log1p(1.0 / Q);
+  *G = -2.0 * A * (1.0 + a1 * rs) * lg;
+  *dG = -2.0 * A * a1 * lg + 2.0 * A * (1.0 + a1 * rs) * dQ / (Q * Q + Q);
+}
+
+__device__ void lda_point(double ru, double rd, int kind, double* e, double* vu, double* vd) {
+  ru = fmax(ru, 0.0);
+  rd = fmax(rd, 0.0);
+  const double rho = ru + rd;
+  if (rho < 1e-12) {
+    *e = 0.0;
+    *vu = 0.0;
+    *vd = 0.0;
+    return;
+  }
+  const double third = 1.0 / 3.0;
+  const double cx = cbrt(6.0 / M_PI);
+  const double cu = cbrt(ru), cd = cbrt(rd);
+  double ex = -0.75 * cx * (ru * cu + rd * cd);
+  double vxu = -cx * cu, vxd = -cx * cd;
+  if (kind == ROKS_XC_X) {
+    *e = ex;
+    *vu = vxu;
+    *vd = vxd;
+    return;
+  }
+  double z = (ru - rd) / rho;
+  z = fmin(1.0, fmax(-1.0, z));
+  const double rs = cbrt(3.0 / (4.0 * M_PI * rho));
+  double ec0, dec0, ec1, dec1, mac, dmac;
+  pw92_G(rs, 0.031091, 0.21370, 7.5957, 3.5876, 1.6382, 0.49294, &ec0, &dec0);
+  pw92_G(rs, 0.015545, 0.20548, 14.1189, 6.1977, 3.3662, 0.62517, &ec1, &dec1);
+  pw92_G(rs, 0.016887, 0.11125, 10.357, 3.6231, 0.88026, 0.49671, &mac, &dmac);
+  const double ac = -mac, dac = -dmac;
+  const double fz20 = 1.709921;
+  const double den = exp2(4.0 * third) - 2.0;
+  const double opz = 1.0 + z, omz = 1.0 - z;
+  const double copz = cbrt(opz), comz = cbrt(omz);
+  const double f = (opz * copz + omz * comz - 2.0) / den;
+  const double fp = (4.0 * third) * (copz - comz) / den;
+  const double z3 = z * z * z, z4 = z3 * z;
+  const double eps = ec0 + ac * f / fz20 * (1.0 - z4) + (ec1 - ec0) * f * z4;
+  const double deps_rs = dec0 + dac * f / fz20 * (1.0 - z4) + (dec1 - dec0) * f * z4;
+  const double deps_z =
+      4.0 * z3 * f * (ec1 - ec0 - ac / fz20) + fp * (z4 * (ec1 - ec0) + (1.0 - z4) * ac / fz20);
+  const double common = eps - rs * third * deps_rs;
+  *e = ex + rho * eps;
+  *vu = vxu + common + (1.0 - z) * deps_z;
+  *vd = vxd + common - (1.0 + z) * deps_z;
+}
+
+// per point: configuration spin densities, LDA, V_loc^{sigma L}, shell potentials
+// V^X = sum c_L f_X V_loc^{sigma L}; partial sums of e_xc, V_ext rho, V_H rho per L
+__global__ void __launch_bounds__(256) k_xc(ShellArgs a, const double* __restrict__ rho,
+                                            const double* __restrict__ vext,
+                                            const double* __restrict__ vh, size_t ntot,
+                                            double* __restrict__ vloc, double* __restrict__ vsh,
+                                            double* __restrict__ part) {
+  __shared__ double red[8 * 16];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double rX[3] = {0, 0, 0};
+    for (int X = 0; X < a.nsocc; ++X) rX[X] = rho[(size_t)X * ntot + i];
+    const double ve = vext[i];
+    double vl[kMaxConf][2];
+    for (int L = 0; L < a.nconf; ++L) {
+      double ru = 0, rd = 0;
+      for (int X = 0; X < a.nsocc; ++X) {
+        ru += a.f[X][L][0] * rX[X];
+        rd += a.f[X][L][1] * rX[X];
+      }
+      double e, vu, vd;
+      lda_point(ru, rd, a.xc, &e, &vu, &vd);
+      const double h = vh[(size_t)L * ntot + i];
+      vl[L][0] = ve + h + vu;
+      vl[L][1] = ve + h + vd;
+      vloc[(size_t)(2 * L) * ntot + i] = vl[L][0];
+      vloc[(size_t)(2 * L + 1) * ntot + i] = vl[L][1];
+      acc[3 * L + 0] += e;
+      acc[3 * L + 1] += ve * (ru + rd);
+      acc[3 * L + 2] += h * (ru + rd);
+    }
+    for (int X = 0; X < a.nsocc; ++X) {
+      double s = 0;
+      for (int L = 0; L < a.nconf; ++L)
+        s += a.cL[L] * (a.f[X][L][0] * vl[L][0] + a.f[X][L][1] * vl[L][1]);
+      vsh[(size_t)X * ntot + i] = s;
+    }
+  }
+  block_sum<6>(acc, red);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < 6; ++j) part[(size_t)blockIdx.x * 6 + j] = acc[j];
+}
+
+// out[j] = sum_r part[r][j] in row order
+__global__ void k_reduce_columns(const double* __restrict__ part, int nrows, int ncols,
+                                 double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ncols) return;
+  double s = 0;
+  for (int r = 0; r < nrows; ++r) s += part[(size_t)r * ncols + j];
+  out[j] = s;
+}
+
+// ---------------------------------------------------------------------------
+// nonlocal energies and D application (per-atom dense blocks)
+// ---------------------------------------------------------------------------
+__global__ void k_nl_energy(const double* __restrict__ P, int nb, int natoms,
+                            const int32_t* __restrict__ off, const int32_t* __restrict__ cnt,
+                            const int32_t* __restrict__ doff, const double* __restrict__ D,
+                            double* __restrict__ out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nb) return;
+  double s = 0;
+  for (int a = 0; a < natoms; ++a) {
+    const int o = off[a], k = cnt[a];
+    const double* Da = D + doff[a];
+    for (int i = 0; i < k; ++i) {
+      const double pi = P[(size_t)(o + i) * nb + n];
+      double t = 0;
+      for (int j = 0; j < k; ++j) t += Da[i * k + j] * P[(size_t)(o + j) * nb + n];
+      s += pi * t;
+    }
+  }
+  out[n] = s;
+}
+
+__global__ void k_apply_D(const double* __restrict__ P, int nb, int nproj,
+                          const int32_t* __restrict__ patom, const int32_t* __restrict__ off,
+                          const int32_t* __restrict__ cnt, const int32_t* __restrict__ doff,
+                          const double* __restrict__ D, const double* __restrict__ w,
+                          double* __restrict__ DP) {
+  const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (t >= (size_t)nproj * nb) return;
+  const int i = (int)(t / nb), n = (int)(t - (size_t)i * nb);
+  const int a = patom[i];
+  const int o = off[a], k = cnt[a];
+  const double* Da = D + doff[a] + (i - o) * k;
+  double s = 0;
+  for (int j = 0; j < k; ++j) s += Da[j] * P[(size_t)(o + j) * nb + n];
+  DP[t] = (w ? w[n] : 1.0) * s;
+}
+
+// ---------------------------------------------------------------------------
+// forces
+// ---------------------------------------------------------------------------
+// partial sums over G of v_s(G) G_a Im(e^{-iG.R_I} conj(rho(G))), rho(G) already / N^3
+__global__ void __launch_bounds__(256) k_local_force(Lattice L, const AtomP* __restrict__ atoms,
+                                                     const double2* __restrict__ rg, size_t ntot,
+                                                     double scale, double* __restrict__ part) {
+  __shared__ double red[8 * 16];
+  const int I = blockIdx.y;
+  const AtomP p = atoms[I];
+  const double s2 = p.sigma * p.sigma;
+  const double pre = -p.A * pow(2.0 * M_PI * s2, 1.5);
+  double acc[3] = {0, 0, 0};
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
+       i += (size_t)gridDim.x * blockDim.x) {
+    int m[3];
+    if (grid_freq(L, i, m)) continue;
+    double G[3];
+    gvec(L, m, G);
+    const double g2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+    const double vs = pre * exp(-0.5 * g2 * s2);
+    double sn, cs;
+    sincos(G[0] * p.x + G[1] * p.y + G[2] * p.z, &sn, &cs);
+    const double2 r = make_double2(rg[i].x * scale, rg[i].y * scale);
+    // e^{-i th} conj(r) = (cs - i sn)(r.x - i r.y): imaginary part
+    const double im = -cs * r.y - sn * r.x;
+    for (int a = 0; a < 3; ++a) acc[a] += vs * G[a] * im;
+  }
+  block_sum<3>(acc, red);
+  if (threadIdx.x == 0)
+    for (int a = 0; a < 3; ++a) part[((size_t)I * gridDim.x + blockIdx.x) * 3 + a] = acc[a];
+}
+
+// dE/dR_I,axis (nonlocal) = sum_{i in I} sum_n 2 w_n dP_in (D P)_in
+__global__ void k_nl_force(const double* __restrict__ dP, const double* __restrict__ DP, int nb,
+                           int natoms, const int32_t* __restrict__ off,
+                           const int32_t* __restrict__ cnt, const double* __restrict__ w,
+                           int axis, double* __restrict__ out) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= natoms) return;
+  double s = 0;
+  for (int i = off[I]; i < off[I] + cnt[I]; ++i)
+    for (int n = 0; n < nb; ++n) s += 2.0 * w[n] * dP[(size_t)i * nb + n] * DP[(size_t)i * nb + n];
+  out[I * 3 + axis] += s;
+}
+
+// out[o][j] = scale * sum_i part[o][i][j]
+__global__ void k_reduce_strided(const double* __restrict__ part, int nouter, int ninner, int ncols,
+                                 double scale, double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nouter * ncols) return;
+  const int o = t / ncols, j = t - o * ncols;
+  double s = 0;
+  for (int i = 0; i < ninner; ++i) s += part[((size_t)o * ninner + i) * ncols + j];
+  out[t] = scale * s;
+}
+
+int grid_blocks(size_t n, int nthr = 256) {
+  size_t b = (n + nthr - 1) / nthr;
+  return (int)(b > 8192 ? 8192 : (b == 0 ? 1 : b));
+}
+
+ShellArgs shell_args(const Ctx& c) {
+  ShellArgs a{};
+  a.nconf = c.nconf;
+  a.nsocc = c.nsocc;
+  a.xc = c.xc;
+  for (int X = 0; X < 3; ++X)
+    for (int L = 0; L < kMaxConf; ++L)
+      for (int s = 0; s < 2; ++s) a.f[X][L][s] = X < c.nsocc && L < c.nconf ? c.shell_f[X][L][s] : 0.0;
+  for (int L = 0; L < kMaxConf; ++L) a.cL[L] = c.cL[L];
+  return a;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static AtomP* atoms_dev(Ctx& c) {
+  static_assert(sizeof(AtomP) == 5 * sizeof(double), "AtomP layout");
+  return reinterpret_cast<AtomP*>(c.d_atoms);
+}
+
+size_t atom_info_bytes() { return sizeof(AtomP); }
+size_t proj_info_bytes() { return sizeof(ProjP); }
+
+void upload_positions(Ctx& c) {
+  std::vector<AtomP> h(c.natoms);
+  for (int a = 0; a < c.natoms; ++a) {
+    const Ctx::Species& sp = c.species[c.spec_of[a]];
+    h[a] = AtomP{c.pos[3 * a], c.pos[3 * a + 1], c.pos[3 * a + 2], sp.A, sp.sigma};
+  }
+  if (c.natoms > 0)
+    ROKS_HIP(hipMemcpyAsync(atoms_dev(c), h.data(), h.size() * sizeof(AtomP), hipMemcpyHostToDevice,
+                            c.stream));
+  // projector descriptors live right after the atoms
+  std::vector<ProjP> pp(c.nproj);
+  for (int i = 0; i < c.nproj; ++i) pp[i] = ProjP{c.proj_atom[i], c.proj_l[i], c.proj_m[i], c.proj_rp[i]};
+  if (c.nproj > 0)
+    ROKS_HIP(hipMemcpyAsync(c.d_projinfo, pp.data(),
+                            pp.size() * sizeof(ProjP), hipMemcpyHostToDevice, c.stream));
+  ROKS_HIP(hipStreamSynchronize(c.stream));  // the host vectors go out of scope
+  launch_vext(c);
+  if (c.nproj > 0) launch_projectors(c, c.d_B, -1);
+  c.potentials_valid = false;
+}
+
+void launch_vext(Ctx& c) {
+  const size_t n = c.ntot;
+  hipLaunchKernelGGL(k_vext_G, dim3(grid_blocks(n)), dim3(256), 0, c.stream, lattice(c), atoms_dev(c),
+                     c.natoms, c.d_fft, n);
+  ROKS_HIP(hipGetLastError());
+  launch_fft3d(c, c.d_fft, +1);
+  hipLaunchKernelGGL(k_take_real, dim3(grid_blocks(n)), dim3(256), 0, c.stream, c.d_fft, c.d_vext, n);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_projectors(Ctx& c, double2* B, int axis) {
+  const size_t n = (size_t)c.nproj * c.npw;
+  if (n == 0) return;
+  const ProjP* pp = reinterpret_cast<const ProjP*>(c.d_projinfo);
+  hipLaunchKernelGGL(k_projectors, dim3(grid_blocks(n)), dim3(256), 0, c.stream, lattice(c), c.d_miller,
+                     c.npw, pp, c.nproj, atoms_dev(c), axis, B);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_density_reduce(Ctx& c, const double* rho_part, int nchunk, double* rho) {
+  const size_t n = (size_t)c.nsocc * c.ntot;
+  hipLaunchKernelGGL(k_density_reduce, dim3(grid_blocks(n)), dim3(256), 0, c.stream, rho_part, nchunk,
+                     c.nsocc, (size_t)c.ntot, 1.0 / c.omega, rho);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_hartree(Ctx& c) {
+  const size_t n = c.ntot;
+  hipLaunchKernelGGL(k_pack_rho, dim3(grid_blocks(n)), dim3(256), 0, c.stream, shell_args(c), c.d_rho, n,
+                     c.d_fft, 0);
+  ROKS_HIP(hipGetLastError());
+  launch_fft3d(c, c.d_fft, -1);
+  hipLaunchKernelGGL(k_hartree_mul, dim3(grid_blocks(n)), dim3(256), 0, c.stream, lattice(c), c.d_fft, n);
+  ROKS_HIP(hipGetLastError());
+  launch_fft3d(c, c.d_fft, +1);
+  hipLaunchKernelGGL(k_unpack_vh, dim3(grid_blocks(n)), dim3(256), 0, c.stream, c.d_fft, n, c.nconf,
+                     c.d_vh);
+  ROKS_HIP(hipGetLastError());
+}
+
+int xc_blocks(const Ctx& c) {
+  int b = grid_blocks(c.ntot);
+  return b < kRedBlocks ? b : kRedBlocks;
+}
+
+void launch_xc_potentials(Ctx& c, double* part, int nblocks) {
+  KernelTimer kt(c, "xc");
+  hipLaunchKernelGGL(k_xc, dim3(nblocks), dim3(256), 0, c.stream, shell_args(c), c.d_rho, c.d_vext,
+                     c.d_vh, (size_t)c.ntot, c.d_vloc, c.d_vsh, part);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_reduce_columns(Ctx& c, const double* part, int nrows, int ncols, double* out) {
+  hipLaunchKernelGGL(k_reduce_columns, dim3(cdiv(ncols, 64)), dim3(64), 0, c.stream, part, nrows, ncols,
+                     out);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_reduce_strided(Ctx& c, const double* part, int nouter, int ninner, int ncols,
+                           double scale, double* out) {
+  const int n = nouter * ncols;
+  hipLaunchKernelGGL(k_reduce_strided, dim3(cdiv(n, 128)), dim3(128), 0, c.stream, part, nouter, ninner,
+                     ncols, scale, out);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_nl_energy(Ctx& c, const double* P, double* out) {
+  hipLaunchKernelGGL(k_nl_energy, dim3(cdiv(c.nb, 64)), dim3(64), 0, c.stream, P, c.nb, c.natoms,
+                     c.d_atom_proj_off, c.d_atom_proj_cnt, c.d_Dblk_off, c.d_Dblk, out);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_apply_D(Ctx& c, const double* P, const double* w, double* DP) {
+  const size_t n = (size_t)c.nproj * c.nb;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_apply_D, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, P, c.nb,
+                     c.nproj, c.d_proj_atom, c.d_atom_proj_off, c.d_atom_proj_cnt, c.d_Dblk_off,
+                     c.d_Dblk, w, DP);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_pack_rho_weighted(Ctx& c) {
+  const size_t n = c.ntot;
+  hipLaunchKernelGGL(k_pack_rho, dim3(grid_blocks(n)), dim3(256), 0, c.stream, shell_args(c), c.d_rho, n,
+                     c.d_fft, 1);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_local_force(Ctx& c, const double2* rhoG, double* out_part, int nblk) {
+  if (c.natoms == 0) return;
+  hipLaunchKernelGGL(k_local_force, dim3(nblk, c.natoms), dim3(256), 0, c.stream, lattice(c),
+                     atoms_dev(c), rhoG, (size_t)c.ntot, 1.0 / (double)c.ntot, out_part);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_nl_force(Ctx& c, const double* dP, const double* DP, const double* w, int axis,
+                     double* out) {
+  if (c.natoms == 0) return;
+  hipLaunchKernelGGL(k_nl_force, dim3(cdiv(c.natoms, 64)), dim3(64), 0, c.stream, dP, DP, c.nb,
+                     c.natoms, c.d_atom_proj_off, c.d_atom_proj_cnt, w, axis, out);
+  ROKS_HIP(hipGetLastError());
+}
+
+}  // namespace roks

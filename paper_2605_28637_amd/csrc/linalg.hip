@@ -1,0 +1,527 @@
+// Dense linear algebra for the band and projector spaces (FP64):
+//   gemm_wdot   C = alpha * A W B^T + beta * C, long K (split-K, ordered sum);
+//               W is the Gamma half-sphere weight (1 for G = 0, 2 otherwise),
+//               so this is the real inner product <a|b> of stored bands.
+//   gemm_expand Y = alpha * M^T X + beta * Y with a short inner dimension.
+//   gemm_small  nb x nb products (rotation, exponential, Cholesky factors).
+// plus per-band weighted dots, the Cholesky inverse, the subspace matrices
+// R / kappa / A and the Teter preconditioner.
+#include <cmath>
+
+#include "roks_internal.h"
+
+namespace roks {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// --------------------------------------------------------------------------
+// C[m][n] (+)= sum_k w_k A[m][k] B[n][k]: 64 x 64 tile, 16-deep k slices,
+// 4 x 4 outputs per thread; blockIdx.z splits K.
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_gemm_wdot(int M, int N, int K, const double* __restrict__ A,
+                                                   int lda, const double* __restrict__ B, int ldb,
+                                                   double* __restrict__ out, int ldo, int kchunk,
+                                                   int hw, double alpha, double beta, int direct) {
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const int tid = threadIdx.x;
+  const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+  const int kb = blockIdx.z * kchunk;
+  const int ke = min(K, kb + kchunk);
+  const int tm = tid >> 4, tn = tid & 15;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + q * 256;
+      const int row = idx >> 4, kk = idx & 15;
+      const int k = k0 + kk;
+      double a = 0.0, b = 0.0;
+      if (k < ke) {
+        const double w = (hw && k >= 2) ? 2.0 : 1.0;
+        if (m0 + row < M) a = w * A[(size_t)(m0 + row) * lda + k];
+        if (n0 + row < N) b = B[(size_t)(n0 + row) * ldb + k];
+      }
+      As[kk][row] = a;
+      Bs[kk][row] = b;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][tm * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tn * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = m0 + tm * 4 + i;
+    if (m >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + tn * 4 + j;
+      if (n >= N) continue;
+      if (direct) {
+        double v = alpha * acc[i][j];
+        if (beta != 0.0) v += beta * out[(size_t)m * ldo + n];
+        out[(size_t)m * ldo + n] = v;
+      } else {
+        out[((size_t)blockIdx.z * M + m) * N + n] = acc[i][j];
+      }
+    }
+  }
+}
+
+__global__ void k_splitk_reduce(const double* __restrict__ part, int ks, int M, int N,
+                                double* __restrict__ C, int ldc, double alpha, double beta) {
+  const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (t >= (size_t)M * N) return;
+  const int m = (int)(t / N), n = (int)(t - (size_t)m * N);
+  double s = 0;
+  for (int z = 0; z < ks; ++z) s += part[(size_t)z * M * N + t];
+  double v = alpha * s;
+  if (beta != 0.0) v += beta * C[(size_t)m * ldc + n];
+  C[(size_t)m * ldc + n] = v;
+}
+
+// --------------------------------------------------------------------------
+// Y[n][k] = alpha sum_m M(m, n) X[m][k] + beta Y[n][k]; tile 32 n x 128 k.
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_gemm_expand(int N, int K, int Md, const double* __restrict__ Mt,
+                                                     int ldm, int transM, const double* __restrict__ X,
+                                                     int ldx, double* __restrict__ Y, int ldy,
+                                                     double alpha, double beta) {
+  __shared__ double Xs[16][128];
+  __shared__ double Ms[16][33];
+  const int tid = threadIdx.x;
+  const int k0 = blockIdx.x * 128, n0 = blockIdx.y * 32;
+  const int tn = tid >> 5, tk = tid & 31;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int mb = 0; mb < Md; mb += 16) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + q * 256;
+      const int mm = idx >> 7, kk = idx & 127;
+      const int m = mb + mm, k = k0 + kk;
+      Xs[mm][kk] = (m < Md && k < K) ? X[(size_t)m * ldx + k] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = tid + q * 256;
+      const int mm = idx >> 5, nn = idx & 31;
+      const int m = mb + mm, n = n0 + nn;
+      double v = 0.0;
+      if (m < Md && n < N) v = transM ? Mt[(size_t)n * ldm + m] : Mt[(size_t)m * ldm + n];
+      Ms[mm][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = Ms[mm][tn * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Xs[mm][tk * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int n = n0 + tn * 4 + i;
+    if (n >= N) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = k0 + tk * 4 + j;
+      if (k >= K) continue;
+      double v = alpha * acc[i][j];
+      if (beta != 0.0) v += beta * Y[(size_t)n * ldy + k];
+      Y[(size_t)n * ldy + k] = v;
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// small products: C = alpha op(A) op(B) + beta C, 16 x 16 tiles
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_gemm_small(int M, int N, int K, const double* __restrict__ A,
+                                                    int lda, int tA, const double* __restrict__ B,
+                                                    int ldb, int tB, double* __restrict__ C, int ldc,
+                                                    double alpha, double beta) {
+  __shared__ double As[16][17];
+  __shared__ double Bs[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int m = blockIdx.y * 16 + ty, n = blockIdx.x * 16 + tx;
+  double acc = 0.0;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const int ka = k0 + tx, kb = k0 + ty;
+    // A(m, k) for this thread's row, B(k, n) for this thread's column
+    double a = 0.0, b = 0.0;
+    if (m < M && ka < K) a = tA ? A[(size_t)ka * lda + m] : A[(size_t)m * lda + ka];
+    if (n < N && kb < K) b = tB ? B[(size_t)n * ldb + kb] : B[(size_t)kb * ldb + n];
+    As[ty][tx] = a;
+    Bs[ty][tx] = b;
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) acc = fma(As[ty][kk], Bs[kk][tx], acc);
+    __syncthreads();
+  }
+  if (m < M && n < N) {
+    double v = alpha * acc;
+    if (beta != 0.0) v += beta * C[(size_t)m * ldc + n];
+    C[(size_t)m * ldc + n] = v;
+  }
+}
+
+// --------------------------------------------------------------------------
+// per-band weighted dots: mode 0: sum w x.y; mode 1: sum w |G|^2/2 x.y
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_band_dots(const double2* __restrict__ X,
+                                                   const double2* __restrict__ Yv, int npw,
+                                                   const double* __restrict__ g2, int mode,
+                                                   double* __restrict__ out) {
+  __shared__ double red[16];
+  const int n = blockIdx.x;
+  const double2* x = X + (size_t)n * npw;
+  const double2* y = Yv + (size_t)n * npw;
+  double s = 0.0;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) {
+    double v = x[g].x * y[g].x + x[g].y * y[g].y;
+    if (mode == 1) v *= g2[g];
+    s += (g == 0) ? v : 2.0 * v;
+  }
+  s = wave_sum(s);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) red[wid] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    out[n] = t;
+  }
+}
+
+__global__ void k_axpby(size_t n, double a, const double* __restrict__ x, double b,
+                        const double* __restrict__ y, double* __restrict__ out) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double v = a * x[i];
+    if (y) v += b * y[i];
+    out[i] = v;
+  }
+}
+
+__global__ void k_set_identity(double* A, int n, double d) {
+  const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (t >= (size_t)n * n) return;
+  const int i = (int)(t / n), j = (int)(t - (size_t)i * n);
+  A[t] = (i == j) ? d : 0.0;
+}
+
+__global__ void k_norm1(const double* A, int n, double* out) {
+  __shared__ double red[16];
+  double mx = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += fabs(A[(size_t)i * n + j]);
+    mx = fmax(mx, s);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+    *out = m;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Cholesky G = L L^T and L^-1 (lower), one workgroup, global memory.
+// flag[0] = 1 if G is not numerically positive definite.
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_cholesky_inverse(const double* __restrict__ G, int n,
+                                                          double* __restrict__ Lw,
+                                                          double* __restrict__ Linv,
+                                                          int32_t* __restrict__ flag) {
+  __shared__ double diag;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  if (tid == 0) flag[0] = 0;
+  for (size_t t = tid; t < (size_t)n * n; t += nthr) Lw[t] = 0.0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (tid == 0) {
+      double s = G[(size_t)j * n + j];
+      for (int k = 0; k < j; ++k) s -= Lw[(size_t)j * n + k] * Lw[(size_t)j * n + k];
+      if (!(s > 0.0) || !isfinite(s)) {
+        flag[0] = 1;
+        s = 1.0;
+      }
+      diag = sqrt(s);
+      Lw[(size_t)j * n + j] = diag;
+    }
+    __syncthreads();
+    const double d = diag;
+    for (int i = j + 1 + tid; i < n; i += nthr) {
+      double s = G[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) s -= Lw[(size_t)i * n + k] * Lw[(size_t)j * n + k];
+      Lw[(size_t)i * n + j] = s / d;
+    }
+    __syncthreads();
+  }
+  // columns of L^-1 by forward substitution, one column per thread
+  for (int col = tid; col < n; col += nthr) {
+    for (int i = 0; i < col; ++i) Linv[(size_t)i * n + col] = 0.0;
+    Linv[(size_t)col * n + col] = 1.0 / Lw[(size_t)col * n + col];
+    for (int i = col + 1; i < n; ++i) {
+      double s = 0.0;
+      for (int k = col; k < i; ++k) s += Lw[(size_t)i * n + k] * Linv[(size_t)k * n + col];
+      Linv[(size_t)i * n + col] = -s / Lw[(size_t)i * n + i];
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// subspace matrices from theta_mn = <m|F^{X(n)}|n>, the band scalars
+// t_n = <n|T + V_NL|n> and Q[n][X] = <n|V^X|n> (local part of F^X):
+//   cross-shell pairs (m in an earlier shell than n):
+//     R_mn = theta_nm - theta_mn = <m|F^X(m) - F^X(n)|n>  (F^virtual = 0)
+//     kappa_mn = F^Xm_nn - F^Xm_mm + F^Xn_mm - F^Xn_nn
+//     A_mn = atan2(2 R_mn, |kappa_mn|) / 2,  A_nm = -A_mn
+//   same occupied shell: R_mn = theta_mn; rotated only when canonicalising,
+//     with kappa = R_nn - R_mm (Jacobi angle).
+// --------------------------------------------------------------------------
+struct SubArgs {
+  int nb, nsocc, flags, open_a, open_b;
+  double w[kMaxShell];
+  int virt[kMaxShell];
+};
+
+__global__ void k_subspace(SubArgs a, const double* __restrict__ theta,
+                           const int32_t* __restrict__ shell, const double* __restrict__ tkin,
+                           const double* __restrict__ tnl, const double* __restrict__ Q,
+                           double* __restrict__ R, double* __restrict__ kappa,
+                           double* __restrict__ A) {
+  const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const int nb = a.nb;
+  if (t >= (size_t)nb * nb) return;
+  const int m = (int)(t / nb), n = (int)(t - (size_t)m * nb);
+  const int Xm = shell[m], Xn = shell[n];
+  auto FX = [&](int X, int b) -> double {
+    if (a.virt[X]) return 0.0;
+    return a.w[X] * (tkin[b] + tnl[b]) + Q[(size_t)b * a.nsocc + X];
+  };
+  double r = 0.0, k = 0.0, ang = 0.0;
+  if (m == n) {
+    r = a.virt[Xm] ? 0.0 : theta[(size_t)m * nb + m];
+  } else {
+    const int lo = m < n ? m : n, hi = m < n ? n : m;
+    const int Xl = shell[lo], Xh = shell[hi];
+    double rl, kl, al = 0.0;
+    if (Xl == Xh) {
+      rl = a.virt[Xl] ? 0.0 : theta[(size_t)lo * nb + hi];
+      kl = 0.0;
+      if ((a.flags & ROKS_FLAG_CANONICALIZE) && !a.virt[Xl]) {
+        kl = theta[(size_t)hi * nb + hi] - theta[(size_t)lo * nb + lo];
+        al = kl != 0.0 ? 0.5 * atan(2.0 * rl / kl) : (rl > 0 ? M_PI / 4 : (rl < 0 ? -M_PI / 4 : 0.0));
+      }
+    } else {
+      rl = theta[(size_t)hi * nb + lo] - theta[(size_t)lo * nb + hi];
+      if ((a.flags & ROKS_FLAG_SUPPRESS_OPEN_COUPLING) && a.open_a >= 0 &&
+          ((Xl == a.open_a && Xh == a.open_b) || (Xl == a.open_b && Xh == a.open_a)))
+        rl = 0.0;
+      kl = FX(Xl, hi) - FX(Xl, lo) + FX(Xh, lo) - FX(Xh, hi);
+      al = 0.5 * atan2(2.0 * rl, fabs(kl));
+    }
+    r = rl;
+    k = kl;
+    ang = m < n ? al : -al;
+  }
+  R[t] = r;
+  kappa[t] = k;
+  A[t] = ang;
+}
+
+// sum_mn A_mn (theta_mn - theta_nm), one workgroup
+__global__ void k_asym_dot(const double* __restrict__ A, const double* __restrict__ th, int nb,
+                           double* __restrict__ out) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (size_t t = threadIdx.x; t < (size_t)nb * nb; t += blockDim.x) {
+    const int m = (int)(t / nb), n = (int)(t - (size_t)m * nb);
+    s += A[t] * (th[t] - th[(size_t)n * nb + m]);
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w];
+    *out = v;
+  }
+}
+
+// Teter-Payne-Allan: K(x) = -(2/E_ref) P(x)/(P(x) + 16 x^4), P = 27 + 18x + 12x^2 + 8x^3,
+// x = (|G|^2/2) / E_ref with E_ref = 1.5 <g|T|g>/<g|g> per band
+__global__ void k_teter(const double2* __restrict__ g, int npw, int nb, const double* __restrict__ gTg,
+                        const double* __restrict__ gg, const double* __restrict__ g2,
+                        const double* __restrict__ bandw, double2* __restrict__ out) {
+  const size_t total = (size_t)nb * npw;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
+       t += (size_t)gridDim.x * blockDim.x) {
+    const int n = (int)(t / npw), q = (int)(t - (size_t)n * npw);
+    double2 v = make_double2(0.0, 0.0);
+    if (gg[n] > 0.0) {
+      const double eref = 1.5 * gTg[n] / gg[n];
+      if (eref > 0.0) {
+        const double x = g2[q] / eref;
+        const double x2 = x * x;
+        const double p = 27.0 + 18.0 * x + 12.0 * x2 + 8.0 * x2 * x;
+        double K = -(2.0 / eref) * p / (p + 16.0 * x2 * x2);
+        if (bandw) K /= bandw[n];
+        v = make_double2(K * g[t].x, K * g[t].y);
+      }
+    }
+    out[t] = v;
+  }
+}
+
+int blocks_for(size_t n) {
+  size_t b = (n + 255) / 256;
+  return (int)(b > 8192 ? 8192 : (b == 0 ? 1 : b));
+}
+
+}  // namespace
+
+void gemm_wdot(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
+               double* C, int ldc, double alpha, double beta, bool half_weights) {
+  if (M == 0 || N == 0) return;
+  KernelTimer kt(c, "gemm_wdot");
+  const int tiles = cdiv(M, 64) * cdiv(N, 64);
+  int ks = 512 / tiles;
+  ks = std::max(1, std::min(ks, K / 512));
+  while ((size_t)ks * M * N > c.gemm_part_capacity && ks > 1) --ks;
+  int kchunk = cdiv(cdiv(K, ks), 16) * 16;
+  ks = cdiv(K, kchunk);
+  dim3 grid(cdiv(M, 64), cdiv(N, 64), ks);
+  if (ks == 1) {
+    hipLaunchKernelGGL(k_gemm_wdot, grid, dim3(256), 0, c.stream, M, N, K, A, lda, B, ldb, C, ldc,
+                       kchunk, half_weights ? 1 : 0, alpha, beta, 1);
+    ROKS_HIP(hipGetLastError());
+    return;
+  }
+  hipLaunchKernelGGL(k_gemm_wdot, grid, dim3(256), 0, c.stream, M, N, K, A, lda, B, ldb, c.d_gemm_part,
+                     N, kchunk, half_weights ? 1 : 0, 1.0, 0.0, 0);
+  ROKS_HIP(hipGetLastError());
+  const size_t mn = (size_t)M * N;
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, c.stream,
+                     c.d_gemm_part, ks, M, N, C, ldc, alpha, beta);
+  ROKS_HIP(hipGetLastError());
+}
+
+void gemm_expand(Ctx& c, int N, int K, int Md, const double* M, int ldm, bool transM,
+                 const double* X, int ldx, double* Y, int ldy, double alpha, double beta) {
+  if (N == 0 || K == 0) return;
+  KernelTimer kt(c, "gemm_expand");
+  dim3 grid(cdiv(K, 128), cdiv(N, 32));
+  hipLaunchKernelGGL(k_gemm_expand, grid, dim3(256), 0, c.stream, N, K, Md, M, ldm, transM ? 1 : 0, X,
+                     ldx, Y, ldy, alpha, beta);
+  ROKS_HIP(hipGetLastError());
+}
+
+void gemm_small(Ctx& c, int M, int N, int K, const double* A, int lda, bool tA, const double* B,
+                int ldb, bool tB, double* C, int ldc, double alpha, double beta) {
+  dim3 grid(cdiv(N, 16), cdiv(M, 16));
+  hipLaunchKernelGGL(k_gemm_small, grid, dim3(256), 0, c.stream, M, N, K, A, lda, tA ? 1 : 0, B, ldb,
+                     tB ? 1 : 0, C, ldc, alpha, beta);
+  ROKS_HIP(hipGetLastError());
+}
+
+void band_dots(Ctx& c, const double2* X, const double2* Y, int nvec, int mode, double* out) {
+  hipLaunchKernelGGL(k_band_dots, dim3(nvec), dim3(256), 0, c.stream, X, Y, c.npw, c.d_g2, mode, out);
+  ROKS_HIP(hipGetLastError());
+}
+
+void axpby(Ctx& c, size_t n, double a, const double* x, double b, const double* y, double* out) {
+  hipLaunchKernelGGL(k_axpby, dim3(blocks_for(n)), dim3(256), 0, c.stream, n, a, x, b, y, out);
+  ROKS_HIP(hipGetLastError());
+}
+
+void set_identity(Ctx& c, double* A, int n, double diag) {
+  const size_t nn = (size_t)n * n;
+  hipLaunchKernelGGL(k_set_identity, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, c.stream, A, n,
+                     diag);
+  ROKS_HIP(hipGetLastError());
+}
+
+void matrix_norm1(Ctx& c, const double* A, int n, double* out) {
+  hipLaunchKernelGGL(k_norm1, dim3(1), dim3(256), 0, c.stream, A, n, out);
+  ROKS_HIP(hipGetLastError());
+}
+
+void cholesky_inverse(Ctx& c, const double* G, int n, double* Linv, int32_t* flag) {
+  hipLaunchKernelGGL(k_cholesky_inverse, dim3(1), dim3(256), 0, c.stream, G, n, c.d_m3, Linv, flag);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_subspace(Ctx& c) {
+  SubArgs a{};
+  a.nb = c.nb;
+  a.nsocc = c.nsocc;
+  a.flags = (int)c.flags;
+  a.open_a = a.open_b = -1;
+  int opens[kMaxShell], no = 0;
+  for (int X = 0; X < c.nshell; ++X) {
+    a.w[X] = c.shell_w[X];
+    a.virt[X] = c.shell_virtual[X];
+    if (!c.shell_closed[X] && !c.shell_virtual[X]) opens[no++] = X;
+  }
+  if (no == 2) {
+    a.open_a = opens[0];
+    a.open_b = opens[1];
+  }
+  const size_t nn = (size_t)c.nb * c.nb;
+  hipLaunchKernelGGL(k_subspace, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, c.stream, a, c.d_theta,
+                     c.d_band_shell, c.d_kin, c.d_enl, c.d_Q, c.d_R, c.d_kappa, c.d_A);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_asym_dot(Ctx& c, const double* A, const double* theta, double* out) {
+  hipLaunchKernelGGL(k_asym_dot, dim3(1), dim3(256), 0, c.stream, A, theta, c.nb, out);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_teter(Ctx& c, const double* gTg, const double* gg, const double2* g, const double* bandw,
+                  double2* out) {
+  const size_t n = (size_t)c.nb * c.npw;
+  hipLaunchKernelGGL(k_teter, dim3(blocks_for(n)), dim3(256), 0, c.stream, g, c.npw, c.nb, gTg, gg,
+                     c.d_g2, bandw, out);
+  ROKS_HIP(hipGetLastError());
+}
+
+}  // namespace roks

@@ -1,0 +1,304 @@
+// Internal declarations of the gfx950 ROKS library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/roks.h"
+
+namespace roks {
+
+// ---------------------------------------------------------------------------
+// error handling
+// ---------------------------------------------------------------------------
+struct Error {
+  roks_status code;
+  std::string msg;
+};
+
+#define ROKS_HIP(call)                                                                    \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw ::roks::Error{ROKS_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define ROKS_CHECK(cond, code, text)                             \
+  do {                                                           \
+    if (!(cond)) throw ::roks::Error{(code), std::string(text)}; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// plane-wave layout
+// ---------------------------------------------------------------------------
+// A "half column" is a line of stored plane waves with fixed (h, k): index 0
+// is (0, 0) holding l >= 0; indices 1..nH are the columns with k > 0 or
+// (k == 0, h > 0), each holding its whole l range [lmin, lmax].  Stored
+// coefficients are ordered column by column, l ascending.  In the column
+// buffers of the FFT the full sphere has ncol = 2 nH + 1 columns: column j
+// (j <= nH) is half column j, column nH + j (j >= 1) its mirror (-h, -k).
+struct ColDesc {
+  int32_t h, k;       // Miller indices of the column (signed)
+  int32_t base;       // storage index of (h, k, lmin)
+  int32_t lmin, lmax; // stored l range
+};
+
+constexpr int kMaxShell = 4;  // closed, two open, virtual
+constexpr int kMaxConf = 2;
+constexpr int kMaxStages = 8;
+
+struct FftPlan1D {
+  int n = 0;
+  int nstages = 0;
+  int radix[kMaxStages] = {0};
+};
+
+FftPlan1D make_plan(int n);  // radices 8, 4, 2, 3, 5 (throws if n has other factors)
+
+// ---------------------------------------------------------------------------
+// the context
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Ctx {
+  // ---- problem description (host) ----
+  double cell[3][3];
+  double recip[3][3];
+  double omega = 0;
+  double ecut = 0;
+  int N[3] = {0, 0, 0};
+  int ntot = 0;
+  int natoms = 0;
+  std::vector<int32_t> spec_of;
+  std::vector<double> pos;  // [natoms][3]
+  struct Species {
+    double A, sigma;
+    std::vector<int32_t> l;
+    std::vector<double> rp;
+    std::vector<double> D;  // [nproj][nproj]
+  };
+  std::vector<Species> species;
+  int nb = 0;
+  int nconf = 0;
+  std::vector<uint8_t> occ;  // [nconf][2][nb]
+  double cL[kMaxConf] = {0, 0};
+  int xc = 0;
+  int prec = 0;
+  uint32_t flags = 0;
+
+  // shells (groups of identical occupation patterns; order closed, open, virtual)
+  int nshell = 0;
+  int nsocc = 0;                                  // occupied shells (all but virtual)
+  double shell_f[kMaxShell][kMaxConf][2] = {};    // f_X^{sigma L}
+  double shell_w[kMaxShell] = {};                 // sum c_L f
+  int shell_closed[kMaxShell] = {};
+  int shell_virtual[kMaxShell] = {};
+  std::vector<int32_t> band_shell;                // [nb]
+
+  // plane waves
+  int npw = 0;
+  std::vector<int32_t> miller;  // [npw][3]
+  std::vector<double> g2half;   // |G|^2 / 2
+  int nH = 0, ncol = 0;
+  std::vector<ColDesc> cols;    // nH + 1 half columns
+  int hmax = 0;                 // max |h| over the sphere
+  FftPlan1D plan[3];
+
+  // projectors (atom-major, channel order of the species, l = 1 as x, y, z)
+  int nproj = 0;
+  std::vector<int32_t> proj_atom, proj_l, proj_m;
+  std::vector<double> proj_rp;
+  std::vector<int32_t> atom_proj_off, atom_proj_cnt;  // [natoms]
+  std::vector<double> Dblk;       // per atom dense block, concatenated
+  std::vector<int32_t> Dblk_off;  // [natoms]
+
+  // ---- device ----
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::vector<DevBuf> allocations;
+  bool have_orbitals = false;
+  bool potentials_valid = false;
+
+  // device arrays (FP64 tier; FP32 copies live in the *_f32 members)
+  int32_t* d_miller = nullptr;
+  double* d_g2 = nullptr;        // |G|^2/2
+  ColDesc* d_cols = nullptr;
+  int32_t* d_colpos = nullptr;   // [ncol][2] (h mod N1, k mod N2)
+  double2* d_tw[3] = {nullptr, nullptr, nullptr};  // exp(-2 pi i k / N_d)
+  double* d_vext = nullptr;      // [N3][N1][N2]
+  double2* d_B = nullptr;        // [nproj][npw]
+  int32_t* d_proj_atom = nullptr;
+  double* d_Dblk = nullptr;
+  int32_t* d_Dblk_off = nullptr;
+  int32_t* d_atom_proj_off = nullptr;
+  int32_t* d_atom_proj_cnt = nullptr;
+  int32_t* d_band_shell = nullptr;
+
+  double2* d_psi = nullptr;      // [nb][npw] current orbitals
+  double2* d_in = nullptr;       // [nb][npw] staging for caller vectors
+  double2* d_Y = nullptr;        // [nb][npw]
+  double2* d_gI = nullptr;
+  double2* d_p = nullptr;
+  double2* d_S = nullptr;
+  double2* d_Sold = nullptr;
+  double2* d_Pt = nullptr;       // trial vectors
+  double2* d_trial = nullptr;    // trial orbitals
+  double2* d_w1 = nullptr;       // scratch band array
+  double2* d_T = nullptr;        // [npairs][N3][ncol] column buffer
+  double* d_rho_part = nullptr;  // [nchunk][nsocc][ntot]
+  double* d_rho = nullptr;       // [nsocc][ntot]
+  double* d_vloc = nullptr;      // [nconf][2][ntot]
+  double* d_vsh = nullptr;       // [nsocc][ntot]
+  double* d_vh = nullptr;        // [nconf][ntot]
+  double2* d_fft = nullptr;      // [ntot]
+  double* d_P = nullptr;         // [nproj][nb]
+  double* d_DP = nullptr;        // [nproj][nb]
+  double* d_part = nullptr;      // reduction partials
+  double* d_red = nullptr;       // reduced scalars
+  double* d_gemm_part = nullptr; // split-K partials
+  double* d_Qpart = nullptr;     // [npairs][N3][2][nsocc]
+  double* d_Q = nullptr;         // [nb][nsocc]
+  double* d_kin = nullptr;       // [nb]
+  double* d_enl = nullptr;       // [nb]
+  double* d_bandv = nullptr;     // [4][nb] per-band scratch scalars
+  // nb x nb matrices
+  double *d_theta = nullptr, *d_R = nullptr, *d_kappa = nullptr, *d_A = nullptr, *d_D = nullptr,
+         *d_Dold = nullptr, *d_gram = nullptr, *d_Linv = nullptr, *d_U = nullptr,
+         *d_M = nullptr, *d_m1 = nullptr, *d_m2 = nullptr, *d_m3 = nullptr, *d_Mkeep = nullptr,
+         *d_Ukeep = nullptr;
+  int32_t* d_flag = nullptr;     // device status flags
+  double* d_force = nullptr;     // [natoms][3]
+  double2* d_dB = nullptr;       // [nproj][npw] derivative projector scratch
+  void* d_atoms = nullptr;       // per-atom position and local-well parameters
+  void* d_projinfo = nullptr;    // per-projector atom, l, m, radius
+  double* d_dP = nullptr;        // [nproj][nb] derivative projections
+  double2* d_hch = nullptr;      // [4][nb][npw] multi-channel apply output (lazy)
+  double* d_scal = nullptr;      // [16 + 2 nb]: reduced energy sums, then kin, enl
+  double* d_m4 = nullptr;
+  double* d_kinw_shell = nullptr;  // [nb] shell weight of each band (0 for virtual)
+  double* d_ones = nullptr;        // [nb] ones
+  int32_t* d_potidx = nullptr;     // [5][nb]: shell potential per band, channel 0..3
+
+  int npairs = 0;
+  int nchunk = 0;
+  size_t part_capacity = 0;      // doubles in d_part
+  size_t gemm_part_capacity = 0;
+
+  // ---- CG state (host mirrors of scalars) ----
+  bool have_old = false;
+  double pg_old = 0;
+  double dt = 0.5;
+  int iteration = 0;
+
+  // ---- cached results of the last energy evaluation ----
+  roks_energies last_e{};
+  std::string last_error;
+
+  // ---- diagnostics: per-kernel event pairs on `stream` ----
+  bool timing = false;
+  struct Timed {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  std::vector<Timed> timed;
+};
+
+// Records HIP events around the launches in its scope when timing is on.
+struct KernelTimer {
+  Ctx& c;
+  int idx = -1;
+  KernelTimer(Ctx& ctx, const char* name);
+  ~KernelTimer();
+};
+
+// host setup (setup.cpp)
+void build_problem(Ctx& c, const roks_system* sys);
+void build_sphere(Ctx& c);
+void build_projectors(Ctx& c);
+
+// device setup and memory (device.cpp)
+void init_device(Ctx& c, void* stream);
+void free_device(Ctx& c);
+void clear_timing(Ctx& c);
+void upload_static(Ctx& c);   // sphere tables, twiddles, V_ext, projectors
+void upload_positions(Ctx& c);
+
+// kernels launchers -----------------------------------------------------------
+// fft.hip
+void launch_zpass_bwd(Ctx& c, const double2* vecs, int nvec, double2* T, int npairs);
+void launch_plane_apply(Ctx& c, double2* T, int npairs, const double* pot, const int32_t* potidx,
+                        int npot_stride, double* Qpart, int nQ);
+void launch_plane_density(Ctx& c, const double2* T, int npairs, double* rho_part, int nchunk);
+void launch_zpass_fwd(Ctx& c, const double2* T, int npairs, const double2* vecs, int nvec,
+                      const double* kinw, double2* Y);
+void launch_fft3d(Ctx& c, double2* data, int sign);
+
+// fields.hip
+void launch_vext(Ctx& c);
+void launch_projectors(Ctx& c, double2* B, int deriv_axis);
+void launch_density_reduce(Ctx& c, const double* rho_part, int nchunk, double* rho);
+void launch_hartree(Ctx& c);
+void launch_xc_potentials(Ctx& c, double* part, int nblocks);
+int xc_blocks(const Ctx& c);
+void launch_band_kinetic(Ctx& c, const double2* vecs, int nvec, double* out);
+void launch_nl_energy(Ctx& c, const double* P, double* out);
+void launch_apply_D(Ctx& c, const double* P, const double* w, double* DP);
+void launch_reduce_columns(Ctx& c, const double* part, int nrows, int ncols, double* out);
+void launch_reduce_strided(Ctx& c, const double* part, int nouter, int ninner, int ncols,
+                           double scale, double* out);
+void launch_local_force(Ctx& c, const double2* rhoG, double* out_part, int nblk);
+void launch_pack_rho_weighted(Ctx& c);
+size_t atom_info_bytes();
+size_t proj_info_bytes();
+void launch_nl_force(Ctx& c, const double* dP, const double* P, const double* w, int axis,
+                     double* out);
+
+// linalg.hip
+void gemm_wdot(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
+               double* C, int ldc, double alpha, double beta, bool half_weights);
+void gemm_expand(Ctx& c, int N, int K, int Mdim, const double* M, int ldm, bool transM,
+                 const double* X, int ldx, double* Y, int ldy, double alpha, double beta);
+void gemm_small(Ctx& c, int M, int N, int K, const double* A, int lda, bool tA, const double* B,
+                int ldb, bool tB, double* C, int ldc, double alpha, double beta);
+void band_dots(Ctx& c, const double2* X, const double2* Y, int nvec, int mode, double* out);
+void axpby(Ctx& c, size_t n, double a, const double* x, double b, const double* y, double* out);
+void cholesky_inverse(Ctx& c, const double* G, int n, double* Linv, int32_t* flag);
+void set_identity(Ctx& c, double* A, int n, double diag);
+void matrix_norm1(Ctx& c, const double* A, int n, double* out);
+void launch_subspace(Ctx& c);
+void launch_asym_dot(Ctx& c, const double* A, const double* theta, double* out);
+void launch_teter(Ctx& c, const double* gTg, const double* gg, const double2* g, const double* bandw,
+                  double2* out);
+
+// solver (solver.cpp)
+void compute_potentials(Ctx& c, const double2* orbitals, roks_energies* e);
+void ensure_potentials(Ctx& c);
+void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bool want_Q);
+void energy_gradient(Ctx& c, roks_energies* e);
+void pcg_step(Ctx& c, roks_step_info* info);
+void orthonormalize(Ctx& c, double2* vecs);
+void forces(Ctx& c, double* f_host);
+void reset_cg(Ctx& c);
+
+// helpers
+template <typename T>
+T* dalloc(Ctx& c, size_t count) {
+  void* p = nullptr;
+  size_t bytes = count * sizeof(T);
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) throw Error{ROKS_ERR_OOM, "hipMalloc failed"};
+  ROKS_HIP(hipMemsetAsync(p, 0, bytes, c.stream));
+  c.allocations.push_back({p, bytes});
+  return static_cast<T*>(p);
+}
+
+inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+}  // namespace roks

@@ -1,0 +1,416 @@
+// The ROKS hot path on the device, orchestrated from the host:
+// densities -> potentials -> energies, shell-operator application, subspace
+// matrices, the projected Teter preconditioner, Fletcher-Reeves directions,
+// the line search over Cholesky-orthonormalised and rotated trial orbitals,
+// and the Hellmann-Feynman forces.  Scalars that steer control flow (energies,
+// directional derivatives) are copied to the host; everything else stays on
+// the GPU.
+#include <algorithm>
+#include <cmath>
+
+#include "roks_internal.h"
+
+namespace roks {
+
+namespace {
+
+constexpr double kDtMin = 0.1, kDtMax = 2.0, kDtInit = 0.5;
+constexpr int kHalvings = 4;
+
+void to_host(Ctx& c, void* dst, const void* src, size_t bytes) {
+  ROKS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c.stream));
+  ROKS_HIP(hipStreamSynchronize(c.stream));
+}
+
+void copy_dev(Ctx& c, void* dst, const void* src, size_t bytes) {
+  ROKS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c.stream));
+}
+
+double host_sum(const std::vector<double>& v) {
+  double s = 0.0;
+  for (double x : v) s += x;
+  return s;
+}
+
+double* dbl(double2* p) { return reinterpret_cast<double*>(p); }
+const double* dbl(const double2* p) { return reinterpret_cast<const double*>(p); }
+
+// sum over bands of the weighted inner products <x_n|y_n>
+double total_dot(Ctx& c, const double2* x, const double2* y) {
+  band_dots(c, x, y, c.nb, 0, c.d_bandv);
+  std::vector<double> h(c.nb);
+  to_host(c, h.data(), c.d_bandv, c.nb * sizeof(double));
+  return host_sum(h);
+}
+
+// U = exp(X) for X = delta * D (antisymmetric): scaling and squaring with a
+// degree-16 Taylor polynomial in Horner form
+void expm(Ctx& c, double delta, const double* D, double* U) {
+  const int n = c.nb;
+  const size_t nn = (size_t)n * n;
+  axpby(c, nn, delta, D, 0.0, nullptr, c.d_m1);
+  matrix_norm1(c, c.d_m1, n, c.d_bandv);
+  double nrm = 0.0;
+  to_host(c, &nrm, c.d_bandv, sizeof(double));
+  ROKS_CHECK(std::isfinite(nrm), ROKS_ERR_NAN, "non-finite rotation generator");
+  int s = 0;
+  while (nrm > 0.5) {
+    nrm *= 0.5;
+    ++s;
+  }
+  if (s > 0) axpby(c, nn, std::ldexp(1.0, -s), c.d_m1, 0.0, nullptr, c.d_m1);
+  set_identity(c, c.d_m2, n, 1.0);
+  axpby(c, nn, 1.0 / 16.0, c.d_m1, 1.0, c.d_m2, c.d_m2);
+  for (int q = 15; q >= 1; --q) {
+    gemm_small(c, n, n, n, c.d_m1, n, false, c.d_m2, n, false, c.d_m4, n, 1.0, 0.0);
+    set_identity(c, c.d_m2, n, 1.0);
+    axpby(c, nn, 1.0 / q, c.d_m4, 1.0, c.d_m2, c.d_m2);
+  }
+  for (int i = 0; i < s; ++i) {
+    gemm_small(c, n, n, n, c.d_m2, n, false, c.d_m2, n, false, c.d_m4, n, 1.0, 0.0);
+    copy_dev(c, c.d_m2, c.d_m4, nn * sizeof(double));
+  }
+  copy_dev(c, U, c.d_m2, nn * sizeof(double));
+}
+
+struct Trial {
+  double2* psi;
+  double* M;
+  double* U;
+  double E;
+  roks_energies e;
+  bool ok;
+};
+
+// Psi(delta) = U^T L^-1 (Psi + delta S), U = exp(delta D); its energy
+void evaluate_trial(Ctx& c, double delta, Trial& t) {
+  const int nb = c.nb, K = 2 * c.npw;
+  const size_t band = (size_t)nb * c.npw;
+  axpby(c, 2 * band, 1.0, dbl(c.d_psi), delta, dbl(c.d_S), dbl(c.d_Pt));
+  gemm_wdot(c, nb, nb, K, dbl(c.d_Pt), K, dbl(c.d_Pt), K, c.d_gram, nb, 1.0, 0.0, true);
+  cholesky_inverse(c, c.d_gram, nb, c.d_Linv, c.d_flag);
+  int32_t flag = 0;
+  to_host(c, &flag, c.d_flag, sizeof(int32_t));
+  t.ok = flag == 0;
+  t.E = INFINITY;
+  if (!t.ok) return;
+  expm(c, delta, c.d_D, t.U);
+  gemm_small(c, nb, nb, nb, t.U, nb, true, c.d_Linv, nb, false, t.M, nb, 1.0, 0.0);
+  gemm_expand(c, nb, K, nb, t.M, nb, true, dbl(c.d_Pt), K, dbl(t.psi), K, 1.0, 0.0);
+  compute_potentials(c, t.psi, &t.e);
+  t.E = t.e.E;
+  if (!std::isfinite(t.E)) {
+    t.ok = false;
+    t.E = INFINITY;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// densities, potentials and energies of `orb` (Sec. II A, H^{sigma L})
+// ---------------------------------------------------------------------------
+void compute_potentials(Ctx& c, const double2* orb, roks_energies* e) {
+  const int nb = c.nb, K = 2 * c.npw;
+  launch_zpass_bwd(c, orb, nb, c.d_T, c.npairs);
+  launch_plane_density(c, c.d_T, c.npairs, c.d_rho_part, c.nchunk);
+  launch_density_reduce(c, c.d_rho_part, c.nchunk, c.d_rho);
+  launch_hartree(c);
+  const int nblk = xc_blocks(c);
+  launch_xc_potentials(c, c.d_part, nblk);
+  launch_reduce_columns(c, c.d_part, nblk, 6, c.d_red);
+  band_dots(c, orb, orb, nb, 1, c.d_kin);
+  if (c.nproj > 0) {
+    gemm_wdot(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(orb), K, c.d_P, nb, 1.0, 0.0, true);
+    launch_nl_energy(c, c.d_P, c.d_enl);
+  } else {
+    ROKS_HIP(hipMemsetAsync(c.d_enl, 0, nb * sizeof(double), c.stream));
+  }
+  std::vector<double> h(16 + 2 * (size_t)nb);
+  to_host(c, h.data(), c.d_scal, h.size() * sizeof(double));
+  const double* kin = h.data() + 16;
+  const double* enl = h.data() + 16 + nb;
+  roks_energies out{};
+  const double dv = c.omega / (double)c.ntot;
+  double E = 0.0;
+  for (int L = 0; L < c.nconf; ++L) {
+    double k = 0.0, nl = 0.0;
+    for (int n = 0; n < nb; ++n) {
+      const double f = (double)c.occ[(L * 2 + 0) * nb + n] + (double)c.occ[(L * 2 + 1) * nb + n];
+      k += f * kin[n];
+      nl += f * enl[n];
+    }
+    out.kinetic[L] = k;
+    out.nonlocal[L] = nl;
+    out.xc[L] = dv * h[3 * L + 0];
+    out.external[L] = dv * h[3 * L + 1];
+    out.hartree[L] = 0.5 * dv * h[3 * L + 2];
+    out.E_L[L] = k + nl + out.external[L] + out.hartree[L] + out.xc[L];
+    E += c.cL[L] * out.E_L[L];
+  }
+  out.E = E;
+  if (e) *e = out;
+  c.potentials_valid = (orb == c.d_psi);
+}
+
+void ensure_potentials(Ctx& c) {
+  ROKS_CHECK(c.have_orbitals, ROKS_ERR_STATE, "no orbitals set");
+  if (!c.potentials_valid) compute_potentials(c, c.d_psi, &c.last_e);
+}
+
+// ---------------------------------------------------------------------------
+// operator application: shell mode (F^{X(n)}, Eq. shell_operator) or channels
+// ---------------------------------------------------------------------------
+void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bool want_Q) {
+  const int nb = c.nb, K = 2 * c.npw;
+  const size_t band = (size_t)nb * c.npw;
+  if (c.nproj > 0)
+    gemm_wdot(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(vecs), K, c.d_dP, nb, 1.0, 0.0, true);
+  if (mask == 0) {
+    launch_zpass_bwd(c, vecs, nb, c.d_T, c.npairs);
+    launch_plane_apply(c, c.d_T, c.npairs, c.d_vsh, c.d_potidx, nb, c.d_Qpart,
+                       want_Q ? c.nsocc : 0);
+    launch_zpass_fwd(c, c.d_T, c.npairs, vecs, nb, c.d_kinw_shell, out);
+    if (c.nproj > 0) {
+      launch_apply_D(c, c.d_dP, c.d_kinw_shell, c.d_DP);
+      gemm_expand(c, nb, K, c.nproj, c.d_DP, nb, false, dbl(c.d_B), K, dbl(out), K, 1.0, 1.0);
+    }
+    if (want_Q) {
+      // Q[n][X] = N^-3 sum_z Qpart[pair][z][b][X], n = 2 pair + b; d_Q holds
+      // 2 npairs rows so an odd band count needs no special case
+      launch_reduce_strided(c, c.d_Qpart, c.npairs, c.N[2], 2 * c.nsocc, 1.0 / (double)c.ntot,
+                            c.d_Q);
+    }
+    return;
+  }
+  int idx = 0;
+  for (int b = 0; b < 2 * c.nconf; ++b) {
+    if (!(mask & (1u << b))) continue;
+    double2* o = out + (size_t)idx * band;
+    launch_zpass_bwd(c, vecs, nb, c.d_T, c.npairs);
+    launch_plane_apply(c, c.d_T, c.npairs, c.d_vloc, c.d_potidx + (size_t)(1 + b) * nb, nb, c.d_Qpart, 0);
+    launch_zpass_fwd(c, c.d_T, c.npairs, vecs, nb, c.d_ones, o);
+    if (c.nproj > 0) {
+      launch_apply_D(c, c.d_dP, nullptr, c.d_DP);
+      gemm_expand(c, nb, K, c.nproj, c.d_DP, nb, false, dbl(c.d_B), K, dbl(o), K, 1.0, 1.0);
+    }
+    ++idx;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// energy, Y = F^n|n>, theta, g_I = (1 - P) Y, and R / kappa / A
+// ---------------------------------------------------------------------------
+void energy_gradient(Ctx& c, roks_energies* e) {
+  ROKS_CHECK(c.have_orbitals, ROKS_ERR_STATE, "no orbitals set");
+  const int nb = c.nb, K = 2 * c.npw;
+  const size_t band = (size_t)nb * c.npw;
+  compute_potentials(c, c.d_psi, &c.last_e);
+  ROKS_CHECK(std::isfinite(c.last_e.E), ROKS_ERR_NAN, "non-finite energy");
+  if (e) *e = c.last_e;
+  apply_operator(c, c.d_psi, 0, c.d_Y, true);
+  gemm_wdot(c, nb, nb, K, dbl(c.d_psi), K, dbl(c.d_Y), K, c.d_theta, nb, 1.0, 0.0, true);
+  copy_dev(c, c.d_gI, c.d_Y, band * sizeof(double2));
+  gemm_expand(c, nb, K, nb, c.d_theta, nb, false, dbl(c.d_psi), K, dbl(c.d_gI), K, -1.0, 1.0);
+  launch_subspace(c);
+}
+
+void reset_cg(Ctx& c) {
+  c.have_old = false;
+  c.pg_old = 0.0;
+  c.dt = kDtInit;
+}
+
+// ---------------------------------------------------------------------------
+// one CG iteration (Eqs. orbital_update, cg_search, prec_grad_I, prec_k and the
+// conjugated rotation; readings R1-R7, R9 of the oracle)
+// ---------------------------------------------------------------------------
+void pcg_step(Ctx& c, roks_step_info* info) {
+  const int nb = c.nb, K = 2 * c.npw;
+  const size_t band = (size_t)nb * c.npw, nn = (size_t)nb * nb;
+  roks_energies e0;
+  energy_gradient(c, &e0);
+  const double E0 = e0.E;
+
+  // preconditioned out-of-subspace gradient p = (1 - P) K g_I
+  band_dots(c, c.d_gI, c.d_gI, nb, 1, c.d_bandv);
+  band_dots(c, c.d_gI, c.d_gI, nb, 0, c.d_bandv + nb);
+  launch_teter(c, c.d_bandv, c.d_bandv + nb, c.d_gI,
+               (c.flags & ROKS_FLAG_WEIGHT_PRECOND) ? c.d_kinw_shell : nullptr, c.d_w1);
+  gemm_wdot(c, nb, nb, K, dbl(c.d_psi), K, dbl(c.d_w1), K, c.d_m1, nb, 1.0, 0.0, true);
+  copy_dev(c, c.d_p, c.d_w1, band * sizeof(double2));
+  gemm_expand(c, nb, K, nb, c.d_m1, nb, false, dbl(c.d_psi), K, dbl(c.d_p), K, -1.0, 1.0);
+
+  // <p|g> = sum <p_I|g_I> + 1/2 sum A (theta - theta^T)
+  launch_asym_dot(c, c.d_A, c.d_theta, c.d_bandv + 2 * nb);
+  double asymA = 0.0;
+  const double pgI = total_dot(c, c.d_p, c.d_gI);
+  to_host(c, &asymA, c.d_bandv + 2 * nb, sizeof(double));
+  const double pg = pgI + 0.5 * asymA;
+  double beta = (c.have_old && c.pg_old != 0.0) ? pg / c.pg_old : 0.0;
+  bool restarted = false;
+
+  // Sold projected out of the current span (kept in d_w1)
+  if (c.have_old) {
+    gemm_wdot(c, nb, nb, K, dbl(c.d_psi), K, dbl(c.d_Sold), K, c.d_m1, nb, 1.0, 0.0, true);
+    copy_dev(c, c.d_w1, c.d_Sold, band * sizeof(double2));
+    gemm_expand(c, nb, K, nb, c.d_m1, nb, false, dbl(c.d_psi), K, dbl(c.d_w1), K, -1.0, 1.0);
+  }
+  auto directions = [&](double b) {
+    if (b != 0.0) {
+      axpby(c, 2 * band, 1.0, dbl(c.d_p), b, dbl(c.d_w1), dbl(c.d_S));
+      axpby(c, nn, 1.0, c.d_A, b, c.d_Dold, c.d_D);
+    } else {
+      copy_dev(c, c.d_S, c.d_p, band * sizeof(double2));
+      copy_dev(c, c.d_D, c.d_A, nn * sizeof(double));
+    }
+    launch_asym_dot(c, c.d_D, c.d_theta, c.d_bandv + 3 * nb);
+    const double sg = total_dot(c, c.d_S, c.d_gI);
+    double asymD = 0.0;
+    to_host(c, &asymD, c.d_bandv + 3 * nb, sizeof(double));
+    return 2.0 * sg + asymD;
+  };
+  double dE0 = directions(beta);
+  if (beta != 0.0 && dE0 >= 0.0) {
+    beta = 0.0;
+    restarted = true;
+    dE0 = directions(0.0);
+  }
+
+  // norms for the report
+  const double gnorm = std::sqrt(std::max(0.0, total_dot(c, c.d_gI, c.d_gI)));
+  double max_rab = 0.0;
+  {
+    int opens[kMaxShell], no = 0;
+    for (int X = 0; X < c.nshell; ++X)
+      if (!c.shell_closed[X] && !c.shell_virtual[X]) opens[no++] = X;
+    if (no == 2) {
+      std::vector<double> th(nn);
+      to_host(c, th.data(), c.d_theta, nn * sizeof(double));
+      for (int m = 0; m < nb; ++m)
+        for (int n = 0; n < nb; ++n)
+          if (c.band_shell[m] == opens[0] && c.band_shell[n] == opens[1])
+            max_rab = std::max(max_rab, std::fabs(th[(size_t)n * nb + m] - th[(size_t)m * nb + n]));
+    }
+  }
+
+  Trial tr[2] = {{c.d_trial, c.d_M, c.d_U, 0, {}, false},
+                 {c.d_trial + band, c.d_Mkeep, c.d_Ukeep, 0, {}, false}};
+  double tdelta[2] = {0.0, 0.0};
+  // reading R7: trial step, parabola through E(0), E'(0), E(dt), keep the
+  // lower of the two if it is below E(0), else halve the trial step
+  auto line_search = [&](double dt, int* evals) -> int {
+    for (int attempt = 0; attempt <= kHalvings; ++attempt) {
+      const double t = dt / std::ldexp(1.0, attempt);
+      evaluate_trial(c, t, tr[0]);
+      ++*evals;
+      double ts;
+      if (tr[0].ok) {
+        const double curv = (tr[0].E - E0 - dE0 * t) / (t * t);
+        ts = curv > 0.0 ? std::min(-dE0 / (2.0 * curv), 4.0 * t) : 2.0 * t;
+      } else {
+        ts = 0.5 * t;
+      }
+      evaluate_trial(c, ts, tr[1]);
+      ++*evals;
+      tdelta[0] = t;
+      tdelta[1] = ts;
+      const int best = (tr[1].E <= tr[0].E) ? 1 : 0;
+      if (tr[best].E < E0) return best;
+    }
+    return -1;
+  };
+
+  int evals = 0, best = -1;
+  if (dE0 < 0.0) {
+    best = line_search(c.dt, &evals);
+    if (best < 0 && beta != 0.0) {
+      beta = 0.0;
+      restarted = true;
+      dE0 = directions(0.0);
+      if (dE0 < 0.0) best = line_search(c.dt, &evals);
+    }
+  }
+  roks_step_info r{};
+  r.E0 = E0;
+  r.beta = beta;
+  r.dE0 = dE0;
+  r.norm_gI = gnorm;
+  r.max_Rab = max_rab;
+  r.restarted = restarted ? 1 : 0;
+  r.evaluations = evals;
+  if (best < 0) {
+    r.E1 = E0;
+    r.delta = 0.0;
+    r.stalled = 1;
+    c.iteration++;
+    r.iteration = c.iteration;
+    c.potentials_valid = false;
+    if (info) *info = r;
+    return;
+  }
+  Trial& t = tr[best];
+  const double delta = tdelta[best];
+  r.E1 = t.E;
+  r.delta = delta;
+  // commit: psi <- trial, S_old <- M S, D_old <- U^T D U
+  copy_dev(c, c.d_psi, t.psi, band * sizeof(double2));
+  gemm_expand(c, nb, K, nb, t.M, nb, true, dbl(c.d_S), K, dbl(c.d_Sold), K, 1.0, 0.0);
+  gemm_small(c, nb, nb, nb, c.d_D, nb, false, t.U, nb, false, c.d_m4, nb, 1.0, 0.0);
+  gemm_small(c, nb, nb, nb, t.U, nb, true, c.d_m4, nb, false, c.d_Dold, nb, 1.0, 0.0);
+  c.have_old = true;
+  c.pg_old = pg;
+  c.dt = std::min(kDtMax, std::max(kDtMin, delta));
+  c.iteration++;
+  r.iteration = c.iteration;
+  c.potentials_valid = false;
+  ROKS_HIP(hipStreamSynchronize(c.stream));
+  if (info) *info = r;
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky orthonormalisation in band order
+// ---------------------------------------------------------------------------
+void orthonormalize(Ctx& c, double2* vecs) {
+  const int nb = c.nb, K = 2 * c.npw;
+  const size_t band = (size_t)nb * c.npw;
+  gemm_wdot(c, nb, nb, K, dbl(vecs), K, dbl(vecs), K, c.d_gram, nb, 1.0, 0.0, true);
+  cholesky_inverse(c, c.d_gram, nb, c.d_Linv, c.d_flag);
+  int32_t flag = 0;
+  to_host(c, &flag, c.d_flag, sizeof(int32_t));
+  ROKS_CHECK(flag == 0, ROKS_ERR_NOT_PD, "orbitals are linearly dependent (Gram not positive definite)");
+  copy_dev(c, c.d_w1, vecs, band * sizeof(double2));
+  gemm_expand(c, nb, K, nb, c.d_Linv, nb, true, dbl(c.d_w1), K, dbl(vecs), K, 1.0, 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// forces (Eq. force_hf, S = 1)
+// ---------------------------------------------------------------------------
+void forces(Ctx& c, double* f_host) {
+  ensure_potentials(c);
+  const int nb = c.nb, K = 2 * c.npw;
+  const int nat = c.natoms;
+  if (nat == 0) return;
+  // local part: dE/dR_I from rho_w = sum_L c_L rho_L, into d_force
+  launch_pack_rho_weighted(c);
+  launch_fft3d(c, c.d_fft, -1);
+  const int nblk = 32;
+  launch_local_force(c, c.d_fft, c.d_part, nblk);
+  launch_reduce_strided(c, c.d_part, nat, nblk, 3, 1.0, c.d_force);
+  // nonlocal part: += 2 sum_n w_n <d beta_i|n> (D P)_in
+  if (c.nproj > 0) {
+    if (!c.d_dB) c.d_dB = dalloc<double2>(c, (size_t)c.nproj * c.npw);
+    gemm_wdot(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(c.d_psi), K, c.d_P, nb, 1.0, 0.0, true);
+    launch_apply_D(c, c.d_P, nullptr, c.d_DP);
+    for (int a = 0; a < 3; ++a) {
+      launch_projectors(c, c.d_dB, a);
+      gemm_wdot(c, c.nproj, nb, K, dbl(c.d_dB), K, dbl(c.d_psi), K, c.d_dP, nb, 1.0, 0.0, true);
+      launch_nl_force(c, c.d_dP, c.d_DP, c.d_kinw_shell, a, c.d_force);
+    }
+  }
+  // F = -dE/dR
+  axpby(c, 3 * (size_t)nat, -1.0, c.d_force, 0.0, nullptr, c.d_force);
+  to_host(c, f_host, c.d_force, 3 * (size_t)nat * sizeof(double));
+}
+
+}  // namespace roks

@@ -1,0 +1,302 @@
+"""ctypes binding of libroks.so (include/roks.h): argument marshalling only.
+
+Every numerical step runs in the gfx950 library; this module converts the
+seeded problem descriptions of ``inputs`` to the C structs, copies NumPy
+arrays in and out, and raises on error statuses.  If the shared library is
+missing the import of ``lib()`` raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libroks.so")
+
+FP64, FP32 = 0, 1
+XC = {"pw92": 0, "x": 1}
+FLAG_SUPPRESS_OPEN_COUPLING = 1
+FLAG_CANONICALIZE = 2
+FLAG_WEIGHT_PRECOND = 4
+
+STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_SHAPE", 3: "ERR_HIP", 4: "ERR_OOM", 5: "ERR_NOT_PD",
+          6: "ERR_LINESEARCH", 7: "ERR_NAN", 8: "ERR_STATE"}
+
+
+class RoksError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), message))
+        self.status = status
+
+
+class Proj(C.Structure):
+    _fields_ = [("l", C.c_int32), ("rp", C.c_double)]
+
+
+class Species(C.Structure):
+    _fields_ = [("A", C.c_double), ("sigma", C.c_double), ("nproj", C.c_int32),
+                ("proj", C.POINTER(Proj)), ("D", C.POINTER(C.c_double))]
+
+
+class System(C.Structure):
+    _fields_ = [("cell", C.c_double * 9), ("ecut", C.c_double), ("grid", C.c_int32 * 3),
+                ("natoms", C.c_int32), ("species", C.POINTER(C.c_int32)),
+                ("pos", C.POINTER(C.c_double)), ("nspecies", C.c_int32),
+                ("spec", C.POINTER(Species)), ("nbands", C.c_int32), ("nconfig", C.c_int32),
+                ("occ", C.POINTER(C.c_uint8)), ("cL", C.POINTER(C.c_double)), ("xc", C.c_int32),
+                ("precision", C.c_int32), ("flags", C.c_uint32)]
+
+
+class Energies(C.Structure):
+    _fields_ = [("E", C.c_double), ("E_L", C.c_double * 2), ("kinetic", C.c_double * 2),
+                ("nonlocal", C.c_double * 2), ("external", C.c_double * 2),
+                ("hartree", C.c_double * 2), ("xc", C.c_double * 2)]
+
+    def as_dict(self, nconf: int) -> Dict:
+        d = {"E": self.E}
+        for k in ("E_L", "kinetic", "nonlocal", "external", "hartree", "xc"):
+            d[k] = np.array(list(getattr(self, k))[:nconf])
+        return d
+
+
+class StepInfo(C.Structure):
+    _fields_ = [("E0", C.c_double), ("E1", C.c_double), ("delta", C.c_double),
+                ("beta", C.c_double), ("dE0", C.c_double), ("norm_gI", C.c_double),
+                ("max_Rab", C.c_double), ("restarted", C.c_int32), ("stalled", C.c_int32),
+                ("evaluations", C.c_int32), ("iteration", C.c_int32)]
+
+    def as_dict(self) -> Dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_LIB = None
+
+# name -> (restype, argtypes)
+_P = C.c_void_p
+_SIGS = {
+    "roks_create": (C.c_int, [C.POINTER(System), _P, C.POINTER(_P)]),
+    "roks_destroy": (C.c_int, [_P]),
+    "roks_last_error": (C.c_char_p, [_P]),
+    "roks_version": (C.c_char_p, []),
+    "roks_sizes": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                             C.POINTER(C.c_int32)]),
+    "roks_gvectors": (C.c_int, [_P, C.POINTER(C.c_int32)]),
+    "roks_set_coeffs": (C.c_int, [_P, C.POINTER(C.c_double), C.c_int32]),
+    "roks_get_coeffs": (C.c_int, [_P, C.POINTER(C.c_double)]),
+    "roks_set_coeffs_d": (C.c_int, [_P, _P, C.c_int32]),
+    "roks_get_coeffs_d": (C.c_int, [_P, _P]),
+    "roks_set_positions": (C.c_int, [_P, C.POINTER(C.c_double)]),
+    "roks_apply_h": (C.c_int, [_P, C.POINTER(C.c_double), C.c_uint32, C.POINTER(C.c_double)]),
+    "roks_apply_h_d": (C.c_int, [_P, _P, C.c_uint32, _P]),
+    "roks_energy_gradient": (C.c_int, [_P, C.POINTER(Energies), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double)]),
+    "roks_subspace": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                C.POINTER(C.c_double)]),
+    "roks_pcg_step": (C.c_int, [_P, C.POINTER(StepInfo)]),
+    "roks_reset_cg": (C.c_int, [_P]),
+    "roks_solve": (C.c_int, [_P, C.c_double, C.c_int32, C.POINTER(StepInfo), C.POINTER(C.c_int32)]),
+    "roks_forces": (C.c_int, [_P, C.POINTER(C.c_double)]),
+    "roks_synchronize": (C.c_int, [_P]),
+    "roks_timing_enable": (C.c_int, [_P, C.c_int32]),
+    "roks_timing_read": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+}
+
+
+def lib() -> C.CDLL:
+    """Load libroks.so (built in-tree); raises if it is missing."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError("libroks.so is not built: run python -m paper_2605_28637_amd.build")
+        L = C.CDLL(LIBPATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _packed(c: np.ndarray) -> np.ndarray:
+    """complex [..., npw] -> contiguous float64 [..., npw, 2]"""
+    c = np.asarray(c)
+    out = np.empty(c.shape + (2,), dtype=np.float64)
+    out[..., 0] = c.real
+    out[..., 1] = c.imag
+    return out
+
+
+def _unpacked(a: np.ndarray) -> np.ndarray:
+    return a[..., 0] + 1j * a[..., 1]
+
+
+class _SystemBuffers:
+    """Keeps the arrays a System struct points to alive."""
+
+    def __init__(self, system: Dict, precision: int, flags: int):
+        s = system
+        self.cell = np.ascontiguousarray(s["cell"], dtype=np.float64).reshape(9)
+        self.pos = np.ascontiguousarray(s["pos"], dtype=np.float64).reshape(-1)
+        self.spa = np.ascontiguousarray(s["species_of_atom"], dtype=np.int32)
+        self.occ = np.ascontiguousarray(s["occ"], dtype=np.uint8)
+        self.cL = np.ascontiguousarray(s["cL"], dtype=np.float64)
+        nspec = len(s["species"])
+        self.specs = (Species * max(1, nspec))()
+        self.keep = []
+        for i, sp in enumerate(s["species"]):
+            npj = len(sp["proj"])
+            pj = (Proj * max(1, npj))()
+            for j, (l, rp) in enumerate(sp["proj"]):
+                pj[j].l, pj[j].rp = int(l), float(rp)
+            D = np.ascontiguousarray(np.asarray(sp["D"], dtype=np.float64).reshape(-1))
+            if D.size == 0:
+                D = np.zeros(1)
+            self.keep += [pj, D]
+            self.specs[i].A = float(sp["A"])
+            self.specs[i].sigma = float(sp["sigma"])
+            self.specs[i].nproj = npj
+            self.specs[i].proj = C.cast(pj, C.POINTER(Proj))
+            self.specs[i].D = _dptr(D)
+        st = System()
+        for i in range(9):
+            st.cell[i] = self.cell[i]
+        st.ecut = float(s["ecut"])
+        for d in range(3):
+            st.grid[d] = int(s["grid"][d])
+        st.natoms = len(self.spa)
+        st.species = self.spa.ctypes.data_as(C.POINTER(C.c_int32))
+        st.pos = _dptr(self.pos)
+        st.nspecies = nspec
+        st.spec = C.cast(self.specs, C.POINTER(Species))
+        st.nbands = int(s["nbands"])
+        st.nconfig = int(self.occ.shape[0])
+        st.occ = self.occ.ctypes.data_as(C.POINTER(C.c_uint8))
+        st.cL = _dptr(self.cL)
+        st.xc = XC[s.get("xc", "pw92")]
+        st.precision = precision
+        st.flags = flags
+        self.struct = st
+
+
+class Roks:
+    """One ROKS problem on the GPU (a roks_ctx)."""
+
+    def __init__(self, system: Dict, precision: int = FP64, flags: int = 0, stream: Optional[int] = None):
+        self._L = lib()
+        self.system = system
+        self._buf = _SystemBuffers(system, precision, flags)
+        h = _P()
+        st = self._L.roks_create(C.byref(self._buf.struct), _P(stream or 0), C.byref(h))
+        if st != 0:
+            raise RoksError(st, self._L.roks_last_error(None).decode())
+        self._h = h
+        npw, nproj, nb = C.c_int32(), C.c_int32(), C.c_int32()
+        grid = (C.c_int32 * 3)()
+        self._check(self._L.roks_sizes(self._h, C.byref(npw), grid, C.byref(nproj), C.byref(nb)))
+        self.npw, self.nproj, self.nb = npw.value, nproj.value, nb.value
+        self.grid = tuple(grid)
+        self.nconf = int(np.asarray(system["occ"]).shape[0])
+        self.natoms = len(system["species_of_atom"])
+
+    # -- plumbing -----------------------------------------------------------
+    def _check(self, status: int):
+        if status != 0:
+            raise RoksError(status, self._L.roks_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.roks_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- ABI ------------------------------------------------------------------
+    def miller(self) -> np.ndarray:
+        m = np.empty((self.npw, 3), dtype=np.int32)
+        self._check(self._L.roks_gvectors(self._h, m.ctypes.data_as(C.POINTER(C.c_int32))))
+        return m
+
+    def set_coeffs(self, c: np.ndarray, orthonormalize: bool = True):
+        a = _packed(np.asarray(c).reshape(self.nb, self.npw))
+        self._check(self._L.roks_set_coeffs(self._h, _dptr(a), 1 if orthonormalize else 0))
+
+    def get_coeffs(self) -> np.ndarray:
+        a = np.empty((self.nb, self.npw, 2))
+        self._check(self._L.roks_get_coeffs(self._h, _dptr(a)))
+        return _unpacked(a)
+
+    def set_positions(self, pos: np.ndarray):
+        p = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1)
+        self._check(self._L.roks_set_positions(self._h, _dptr(p)))
+
+    def apply_h(self, c: Optional[np.ndarray] = None, mask: int = 0) -> np.ndarray:
+        nch = bin(mask).count("1") if mask else 1
+        out = np.empty((nch, self.nb, self.npw, 2))
+        cin = None
+        if c is not None:
+            cin = _packed(np.asarray(c).reshape(self.nb, self.npw))
+        self._check(self._L.roks_apply_h(self._h, _dptr(cin) if cin is not None else None, mask,
+                                         _dptr(out)))
+        r = _unpacked(out)
+        return r[0] if mask == 0 else r
+
+    def energy_gradient(self):
+        e = Energies()
+        g = np.empty((self.nb, self.npw, 2))
+        th = np.empty((self.nb, self.nb))
+        self._check(self._L.roks_energy_gradient(self._h, C.byref(e), _dptr(g), _dptr(th)))
+        return e.as_dict(self.nconf), _unpacked(g), th
+
+    def subspace(self):
+        R, k, A = (np.empty((self.nb, self.nb)) for _ in range(3))
+        self._check(self._L.roks_subspace(self._h, _dptr(R), _dptr(k), _dptr(A)))
+        return R, k, A
+
+    def pcg_step(self) -> Dict:
+        info = StepInfo()
+        self._check(self._L.roks_pcg_step(self._h, C.byref(info)))
+        return info.as_dict()
+
+    def reset_cg(self):
+        self._check(self._L.roks_reset_cg(self._h))
+
+    def solve(self, tol: float = 1e-6, maxiter: int = 500):
+        info = StepInfo()
+        it = C.c_int32()
+        self._check(self._L.roks_solve(self._h, tol, maxiter, C.byref(info), C.byref(it)))
+        return info.as_dict(), it.value
+
+    def forces(self) -> np.ndarray:
+        f = np.empty((max(1, self.natoms), 3))
+        self._check(self._L.roks_forces(self._h, _dptr(f)))
+        return f[: self.natoms]
+
+    def synchronize(self):
+        self._check(self._L.roks_synchronize(self._h))
+
+    def timing_enable(self, on: bool = True):
+        self._check(self._L.roks_timing_enable(self._h, 1 if on else 0))
+
+    def timing_read(self, kernel: str):
+        ms, n = C.c_double(), C.c_int32()
+        self._check(self._L.roks_timing_read(self._h, kernel.encode(), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    # device-pointer variants (torch tensors or raw ints)
+    def apply_h_d(self, c_in_ptr: Optional[int], mask: int, out_ptr: int):
+        self._check(self._L.roks_apply_h_d(self._h, _P(c_in_ptr or 0), mask, _P(out_ptr)))

@@ -1,0 +1,62 @@
+"""Shared test utilities: build-on-demand, Miller-index matching between the
+GPU's half-sphere storage and the oracle's full sphere, seeded systems."""
+import os
+
+import numpy as np
+
+from paper_2605_28637_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def ensure_built():
+    from paper_2605_28637_amd import build, roks as rb
+    if not os.path.exists(rb.LIBPATH):
+        build.build()
+    return rb
+
+
+class SphereMap:
+    """Maps GPU half-sphere vectors <-> oracle full-sphere vectors by Miller index."""
+
+    def __init__(self, gpu_miller: np.ndarray, oracle_miller: np.ndarray):
+        look = {tuple(t): i for i, t in enumerate(np.asarray(oracle_miller))}
+        gm = np.asarray(gpu_miller)
+        self.plus = np.array([look[tuple(t)] for t in gm])
+        self.minus = np.array([look[tuple(-t)] for t in gm])
+        self.nfull = len(oracle_miller)
+
+    def to_full(self, c_half: np.ndarray) -> np.ndarray:
+        c_half = np.atleast_2d(c_half)
+        out = np.zeros((c_half.shape[0], self.nfull), dtype=complex)
+        out[:, self.minus] = np.conj(c_half)
+        out[:, self.plus] = c_half
+        return out
+
+    def to_half(self, c_full: np.ndarray) -> np.ndarray:
+        return np.atleast_2d(c_full)[:, self.plus]
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def small_molecule(seed=2001, natoms=6, nb=11, N=24, L=12.0, configuration="roks"):
+    """Small molecule-in-box with an odd band count (ragged last band pair)."""
+    return inputs.molecule_box(seed=seed, natoms=natoms, nb=nb, N=N, L=L,
+                               configuration=configuration)
+
+
+def orthorhombic_cell(seed=2500):
+    """Non-cubic cell and grid (20 x 24 x 30), cutoff below every grid rule."""
+    s = inputs.molecule_box(seed=seed, natoms=4, nb=8, N=24, L=12.0)
+    s = dict(s)
+    s["cell"] = np.diag([10.0, 12.0, 15.0])
+    s["grid"] = (20, 24, 30)
+    s["ecut"] = min(inputs.grid_rule_ecut(10.0, 20), inputs.grid_rule_ecut(12.0, 24),
+                    inputs.grid_rule_ecut(15.0, 30))
+    rng = np.random.default_rng(seed)
+    s["pos"] = np.array([[2.5, 3.0, 4.0], [6.0, 7.5, 9.0], [4.0, 9.0, 12.0], [7.5, 4.0, 6.5]])
+    s["pos"] = s["pos"] + rng.normal(0, 0.05, size=s["pos"].shape)
+    return s
