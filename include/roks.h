@@ -224,12 +224,15 @@ roks_status roks_synchronize(roks_ctx ctx);
  * measured with HIP events recorded on the context's stream around each
  * launch.  roks_timing_enable(ctx, 1) clears the totals and starts
  * recording, 0 stops.  roks_timing_read() synchronises the stream and
- * returns the summed milliseconds and the launch count of one kernel family
- * ("zpass_bwd", "plane_apply", "plane_density", "zpass_fwd", "fft3d",
- * "gemm_wdot", "gemm_expand", "xc"); unknown names give zero. */
+ * returns, for one kernel family ("zpass_bwd", "plane_apply",
+ * "plane_density", "zpass_fwd", "fft3d", "gemm_wdot", "gemm_expand", "xc"),
+ * the summed milliseconds, the launch count and the summed algorithmic HBM
+ * bytes and flops of those launches (the minimum traffic and arithmetic the
+ * launches' inputs and outputs imply); unknown names give zero.  Any output
+ * pointer may be NULL. */
 roks_status roks_timing_enable(roks_ctx ctx, int32_t enable);
 roks_status roks_timing_read(roks_ctx ctx, const char* kernel, double* total_ms,
-                             int32_t* launches);
+                             int32_t* launches, double* bytes, double* flops);
 
 #ifdef __cplusplus
 }

@@ -270,21 +270,26 @@ roks_status roks_timing_enable(roks_ctx ctx, int32_t enable) {
   });
 }
 
-roks_status roks_timing_read(roks_ctx ctx, const char* kernel, double* total_ms, int32_t* launches) {
+roks_status roks_timing_read(roks_ctx ctx, const char* kernel, double* total_ms, int32_t* launches,
+                             double* bytes, double* flops) {
   return guard(ctx, [&](roks::Ctx& c) {
     ROKS_CHECK(kernel, ROKS_ERR_ARG, "kernel name is NULL");
     ROKS_HIP(hipStreamSynchronize(c.stream));
-    double ms = 0.0;
+    double ms = 0.0, by = 0.0, fl = 0.0;
     int32_t n = 0;
     for (auto& t : c.timed) {
       if (t.name != kernel) continue;
       float e = 0.f;
       ROKS_HIP(hipEventElapsedTime(&e, t.a, t.b));
       ms += e;
+      by += t.bytes;
+      fl += t.flops;
       ++n;
     }
     if (total_ms) *total_ms = ms;
     if (launches) *launches = n;
+    if (bytes) *bytes = by;
+    if (flops) *flops = fl;
   });
 }
 

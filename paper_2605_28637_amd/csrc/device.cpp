@@ -59,7 +59,7 @@ void init_device(Ctx& c, void* stream) {
   c.d_red = c.d_scal;
   c.d_kin = c.d_scal + 16;
   c.d_enl = c.d_scal + 16 + nb;
-  c.gemm_part_capacity = std::max<size_t>({4 * np * nb, 64 * nb * nb, (size_t)1 << 16});
+  c.gemm_part_capacity = std::max<size_t>({4 * np * nb, 64 * nb * nb, (size_t)1 << 21});
   c.d_gemm_part = dalloc<double>(c, c.gemm_part_capacity);
   c.d_Qpart = dalloc<double>(c, (size_t)c.npairs * c.N[2] * 2 * c.nsocc);
   c.d_Q = dalloc<double>(c, 2 * (size_t)c.npairs * c.nsocc);
@@ -129,10 +129,12 @@ void upload_static(Ctx& c) {
   ROKS_HIP(hipStreamSynchronize(c.stream));
 }
 
-KernelTimer::KernelTimer(Ctx& ctx, const char* name) : c(ctx) {
+KernelTimer::KernelTimer(Ctx& ctx, const char* name, double bytes, double flops) : c(ctx) {
   if (!c.timing) return;
   Ctx::Timed t;
   t.name = name;
+  t.bytes = bytes;
+  t.flops = flops;
   if (hipEventCreate(&t.a) != hipSuccess) return;
   if (hipEventCreate(&t.b) != hipSuccess) {
     (void)hipEventDestroy(t.a);

@@ -197,7 +197,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // z pass, G -> r
 // ---------------------------------------------------------------------------
 template <int MAXP>
-__global__ void __launch_bounds__(256) k_zpass_bwd(const double2* __restrict__ vecs, int nvec,
+__global__ void __launch_bounds__(512) k_zpass_bwd(const double2* __restrict__ vecs, int nvec,
                                                     int npw, const ColDesc* __restrict__ cols,
                                                     int ndesc, int nH, FftPlan1D plan,
                                                     const double2* __restrict__ twg,
@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(256) k_zpass_bwd(const double2* __restrict__ v
 // z pass, r -> G, with unpacking, scaling and the kinetic term
 // ---------------------------------------------------------------------------
 template <int MAXP>
-__global__ void __launch_bounds__(256) k_zpass_fwd(
+__global__ void __launch_bounds__(512) k_zpass_fwd(
     const double2* __restrict__ T, int ncol, const ColDesc* __restrict__ cols, int ndesc, int nH,
     FftPlan1D plan, const double2* __restrict__ twg, const double2* __restrict__ vecs, int nvec,
     int npw, const double* __restrict__ kinw, const double* __restrict__ g2, double scale,
@@ -481,7 +481,7 @@ __global__ void __launch_bounds__(512) k_fft_planes(double2* __restrict__ data, 
 }
 
 template <int MAXP>
-__global__ void __launch_bounds__(256) k_fft_zlines(double2* __restrict__ data, int np2,
+__global__ void __launch_bounds__(512) k_fft_zlines(double2* __restrict__ data, int np2,
                                                     FftPlan1D plan, const double2* __restrict__ twg,
                                                     int CH, int sign) {
   extern __shared__ double2 smem[];
@@ -506,7 +506,10 @@ __global__ void __launch_bounds__(256) k_fft_zlines(double2* __restrict__ data, 
 // ---------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------
-int plane_threads(const Ctx& c) { return c.N[0] * c.N[1] > 4096 ? 512 : 256; }
+// 512 threads keep every thread at <= 8 (N <= 64) or <= 18 (N <= 96) points
+// per FFT pass, so the butterfly registers fit without spilling
+constexpr int kZThreads = 512;
+int plane_threads(const Ctx& c) { return c.N[0] * c.N[1] > 1024 ? 512 : 256; }
 
 int needed_points(int points, int nthr) { return (points + nthr - 1) / nthr; }
 
@@ -540,7 +543,7 @@ size_t plane_lds(const Ctx& c, int nthr, int nQ) {
 int zchunk(const Ctx& c) {
   const int N3 = c.N[2];
   int CH = 32;
-  while (CH > 1 && 2 * CH * N3 > 256 * 16) CH /= 2;
+  while (CH > 1 && 2 * CH * N3 > kZThreads * 8) CH /= 2;
   return CH;
 }
 
@@ -563,7 +566,7 @@ void allow_lds(K kernel, size_t bytes) {
 
 template <int MP>
 static void run_zpass_bwd(Ctx& c, const double2* vecs, int nvec, double2* T, int npairs, int CH) {
-  const int nthr = 256;
+  const int nthr = kZThreads;
   const size_t lds = (size_t)(c.N[2] + 2 * CH * c.N[2]) * sizeof(double2);
   allow_lds(k_zpass_bwd<MP>, lds);
   dim3 grid(cdiv(c.nH + 1, CH), npairs);
@@ -572,10 +575,18 @@ static void run_zpass_bwd(Ctx& c, const double2* vecs, int nvec, double2* T, int
   ROKS_HIP(hipGetLastError());
 }
 
+// algorithmic HBM bytes: the column buffer of all pairs, the band arrays and
+// real grids each move once per launch
+static double colbuf_bytes(const Ctx& c, int npairs) {
+  return (double)npairs * c.N[2] * c.ncol * sizeof(double2);
+}
+static double band_bytes(const Ctx& c, int nvec) { return (double)nvec * c.npw * sizeof(double2); }
+static double grid_bytes(const Ctx& c) { return (double)c.ntot * sizeof(double); }
+
 void launch_zpass_bwd(Ctx& c, const double2* vecs, int nvec, double2* T, int npairs) {
-  KernelTimer kt(c, "zpass_bwd");
+  KernelTimer kt(c, "zpass_bwd", band_bytes(c, nvec) + colbuf_bytes(c, npairs));
   const int CH = zchunk(c);
-  const int mp = pick_maxp(needed_points(2 * CH * c.N[2], 256));
+  const int mp = pick_maxp(needed_points(2 * CH * c.N[2], kZThreads));
   ROKS_DISPATCH_MAXP(mp, run_zpass_bwd, c, vecs, nvec, T, npairs, CH);
 }
 
@@ -585,7 +596,7 @@ static void run_zpass_fwd(Ctx& c, const double2* T, int npairs, const double2* v
   const size_t lds = (size_t)(c.N[2] + 2 * CH * c.N[2]) * sizeof(double2);
   allow_lds(k_zpass_fwd<MP>, lds);
   dim3 grid(cdiv(c.nH + 1, CH), npairs);
-  hipLaunchKernelGGL(k_zpass_fwd<MP>, grid, dim3(256), lds, c.stream, T, c.ncol, c.d_cols, c.nH + 1,
+  hipLaunchKernelGGL(k_zpass_fwd<MP>, grid, dim3(kZThreads), lds, c.stream, T, c.ncol, c.d_cols, c.nH + 1,
                      c.nH, c.plan[2], c.d_tw[2], vecs, nvec, c.npw, kinw, c.d_g2,
                      1.0 / (double)c.ntot, Y, CH);
   ROKS_HIP(hipGetLastError());
@@ -593,9 +604,9 @@ static void run_zpass_fwd(Ctx& c, const double2* T, int npairs, const double2* v
 
 void launch_zpass_fwd(Ctx& c, const double2* T, int npairs, const double2* vecs, int nvec,
                       const double* kinw, double2* Y) {
-  KernelTimer kt(c, "zpass_fwd");
+  KernelTimer kt(c, "zpass_fwd", colbuf_bytes(c, npairs) + 2.0 * band_bytes(c, nvec));
   const int CH = zchunk(c);
-  const int mp = pick_maxp(needed_points(2 * CH * c.N[2], 256));
+  const int mp = pick_maxp(needed_points(2 * CH * c.N[2], kZThreads));
   ROKS_DISPATCH_MAXP(mp, run_zpass_fwd, c, T, npairs, vecs, nvec, kinw, Y, CH);
 }
 
@@ -613,7 +624,8 @@ static void run_plane_apply(Ctx& c, double2* T, int npairs, const double* pot,
 
 void launch_plane_apply(Ctx& c, double2* T, int npairs, const double* pot, const int32_t* potidx,
                         int nvec, double* Qpart, int nQ) {
-  KernelTimer kt(c, "plane_apply");
+  KernelTimer kt(c, "plane_apply",
+                 2.0 * colbuf_bytes(c, npairs) + (nQ > 0 ? nQ : 1) * grid_bytes(c));
   const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], plane_threads(c)));
   ROKS_DISPATCH_MAXP(mp, run_plane_apply, c, T, npairs, pot, potidx, nvec, Qpart, nQ);
 }
@@ -632,7 +644,8 @@ static void run_plane_density(Ctx& c, const double2* T, int npairs, double* rho_
 }
 
 void launch_plane_density(Ctx& c, const double2* T, int npairs, double* rho_part, int nchunk) {
-  KernelTimer kt(c, "plane_density");
+  KernelTimer kt(c, "plane_density",
+                 colbuf_bytes(c, npairs) + (double)nchunk * c.nsocc * grid_bytes(c));
   const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], plane_threads(c)));
   ROKS_DISPATCH_MAXP(mp, run_plane_density, c, T, npairs, rho_part, nchunk);
 }
@@ -652,17 +665,17 @@ static void run_fft_zlines(Ctx& c, double2* data, int sign, int CH) {
   const size_t lds = (size_t)(c.N[2] + CH * c.N[2]) * sizeof(double2);
   allow_lds(k_fft_zlines<MP>, lds);
   const int np2 = c.N[0] * c.N[1];
-  hipLaunchKernelGGL(k_fft_zlines<MP>, dim3(cdiv(np2, CH)), dim3(256), lds, c.stream, data, np2,
+  hipLaunchKernelGGL(k_fft_zlines<MP>, dim3(cdiv(np2, CH)), dim3(kZThreads), lds, c.stream, data, np2,
                      c.plan[2], c.d_tw[2], CH, sign);
   ROKS_HIP(hipGetLastError());
 }
 
 void launch_fft3d(Ctx& c, double2* data, int sign) {
-  KernelTimer kt(c, "fft3d");
+  KernelTimer kt(c, "fft3d", 4.0 * c.ntot * sizeof(double2));
   const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], plane_threads(c)));
   ROKS_DISPATCH_MAXP(mp, run_fft_planes, c, data, sign);
   const int CH = 2 * zchunk(c);
-  const int mz = pick_maxp(needed_points(CH * c.N[2], 256));
+  const int mz = pick_maxp(needed_points(CH * c.N[2], kZThreads));
   ROKS_DISPATCH_MAXP(mz, run_fft_zlines, c, data, sign, CH);
 }
 

@@ -327,27 +327,30 @@ __global__ void __launch_bounds__(256) k_xc(ShellArgs a, const double* __restric
     for (int j = 0; j < 6; ++j) part[(size_t)blockIdx.x * 6 + j] = acc[j];
 }
 
-// out[j] = sum_r part[r][j] in row order
-__global__ void k_reduce_columns(const double* __restrict__ part, int nrows, int ncols,
-                                 double* __restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= ncols) return;
-  double s = 0;
-  for (int r = 0; r < nrows; ++r) s += part[(size_t)r * ncols + j];
-  out[j] = s;
+// out[j] = sum_r part[r][j]; one workgroup per column, fixed summation tree
+__global__ void __launch_bounds__(256) k_reduce_columns(const double* __restrict__ part, int nrows,
+                                                        int ncols, double* __restrict__ out) {
+  __shared__ double red[8 * 16];
+  const int j = blockIdx.x;
+  double v[1] = {0.0};
+  for (int r = threadIdx.x; r < nrows; r += blockDim.x) v[0] += part[(size_t)r * ncols + j];
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) out[j] = v[0];
 }
 
 // ---------------------------------------------------------------------------
 // nonlocal energies and D application (per-atom dense blocks)
 // ---------------------------------------------------------------------------
-__global__ void k_nl_energy(const double* __restrict__ P, int nb, int natoms,
-                            const int32_t* __restrict__ off, const int32_t* __restrict__ cnt,
-                            const int32_t* __restrict__ doff, const double* __restrict__ D,
-                            double* __restrict__ out) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= nb) return;
+// e_n = sum_atoms sum_ij P_in D_ij P_jn: one wave per band, atoms split over lanes
+__global__ void __launch_bounds__(64) k_nl_energy(const double* __restrict__ P, int nb, int natoms,
+                                                  const int32_t* __restrict__ off,
+                                                  const int32_t* __restrict__ cnt,
+                                                  const int32_t* __restrict__ doff,
+                                                  const double* __restrict__ D,
+                                                  double* __restrict__ out) {
+  const int n = blockIdx.x;
   double s = 0;
-  for (int a = 0; a < natoms; ++a) {
+  for (int a = threadIdx.x; a < natoms; a += blockDim.x) {
     const int o = off[a], k = cnt[a];
     const double* Da = D + doff[a];
     for (int i = 0; i < k; ++i) {
@@ -357,7 +360,8 @@ __global__ void k_nl_energy(const double* __restrict__ P, int nb, int natoms,
       s += pi * t;
     }
   }
-  out[n] = s;
+  s = wave_sum(s);
+  if (threadIdx.x == 0) out[n] = s;
 }
 
 __global__ void k_apply_D(const double* __restrict__ P, int nb, int nproj,
@@ -530,15 +534,15 @@ int xc_blocks(const Ctx& c) {
 }
 
 void launch_xc_potentials(Ctx& c, double* part, int nblocks) {
-  KernelTimer kt(c, "xc");
+  // reads shell densities, V_ext, V_H; writes V_loc and the shell potentials
+  KernelTimer kt(c, "xc", (double)(2 * c.nsocc + 1 + 3 * c.nconf) * c.ntot * sizeof(double));
   hipLaunchKernelGGL(k_xc, dim3(nblocks), dim3(256), 0, c.stream, shell_args(c), c.d_rho, c.d_vext,
                      c.d_vh, (size_t)c.ntot, c.d_vloc, c.d_vsh, part);
   ROKS_HIP(hipGetLastError());
 }
 
 void launch_reduce_columns(Ctx& c, const double* part, int nrows, int ncols, double* out) {
-  hipLaunchKernelGGL(k_reduce_columns, dim3(cdiv(ncols, 64)), dim3(64), 0, c.stream, part, nrows, ncols,
-                     out);
+  hipLaunchKernelGGL(k_reduce_columns, dim3(ncols), dim3(256), 0, c.stream, part, nrows, ncols, out);
   ROKS_HIP(hipGetLastError());
 }
 
@@ -551,7 +555,7 @@ void launch_reduce_strided(Ctx& c, const double* part, int nouter, int ninner, i
 }
 
 void launch_nl_energy(Ctx& c, const double* P, double* out) {
-  hipLaunchKernelGGL(k_nl_energy, dim3(cdiv(c.nb, 64)), dim3(64), 0, c.stream, P, c.nb, c.natoms,
+  hipLaunchKernelGGL(k_nl_energy, dim3(c.nb), dim3(64), 0, c.stream, P, c.nb, c.natoms,
                      c.d_atom_proj_off, c.d_atom_proj_cnt, c.d_Dblk_off, c.d_Dblk, out);
   ROKS_HIP(hipGetLastError());
 }

@@ -89,6 +89,7 @@ __global__ void __launch_bounds__(256) k_gemm_wdot(int M, int N, int K, const do
   }
 }
 
+// few splits: one thread per output sums them in order
 __global__ void k_splitk_reduce(const double* __restrict__ part, int ks, int M, int N,
                                 double* __restrict__ C, int ldc, double alpha, double beta) {
   const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -99,6 +100,22 @@ __global__ void k_splitk_reduce(const double* __restrict__ part, int ks, int M, 
   double v = alpha * s;
   if (beta != 0.0) v += beta * C[(size_t)m * ldc + n];
   C[(size_t)m * ldc + n] = v;
+}
+
+// many splits: one wave per output, lanes stride over the splits, fixed tree
+__global__ void __launch_bounds__(64) k_splitk_reduce_wave(const double* __restrict__ part, int ks,
+                                                           int M, int N, double* __restrict__ C,
+                                                           int ldc, double alpha, double beta) {
+  const size_t t = blockIdx.x;
+  const int m = (int)(t / N), n = (int)(t - (size_t)m * N);
+  double s = 0;
+  for (int z = threadIdx.x; z < ks; z += 64) s += part[(size_t)z * M * N + t];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) {
+    double v = alpha * s;
+    if (beta != 0.0) v += beta * C[(size_t)m * ldc + n];
+    C[(size_t)m * ldc + n] = v;
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -171,7 +188,7 @@ __global__ void __launch_bounds__(256) k_gemm_expand(int N, int K, int Md, const
 __global__ void __launch_bounds__(256) k_gemm_small(int M, int N, int K, const double* __restrict__ A,
                                                     int lda, int tA, const double* __restrict__ B,
                                                     int ldb, int tB, double* __restrict__ C, int ldc,
-                                                    double alpha, double beta) {
+                                                    double alpha, double beta, double diag) {
   __shared__ double As[16][17];
   __shared__ double Bs[16][17];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -193,6 +210,7 @@ __global__ void __launch_bounds__(256) k_gemm_small(int M, int N, int K, const d
   if (m < M && n < N) {
     double v = alpha * acc;
     if (beta != 0.0) v += beta * C[(size_t)m * ldc + n];
+    if (m == n) v += diag;
     C[(size_t)m * ldc + n] = v;
   }
 }
@@ -200,7 +218,7 @@ __global__ void __launch_bounds__(256) k_gemm_small(int M, int N, int K, const d
 // --------------------------------------------------------------------------
 // per-band weighted dots: mode 0: sum w x.y; mode 1: sum w |G|^2/2 x.y
 // --------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_band_dots(const double2* __restrict__ X,
+__global__ void __launch_bounds__(1024) k_band_dots(const double2* __restrict__ X,
                                                    const double2* __restrict__ Yv, int npw,
                                                    const double* __restrict__ g2, int mode,
                                                    double* __restrict__ out) {
@@ -276,9 +294,11 @@ __global__ void __launch_bounds__(256) k_cholesky_inverse(const double* __restri
   __syncthreads();
   for (int j = 0; j < n; ++j) {
     if (tid == 0) {
-      double s = G[(size_t)j * n + j];
+      const double gjj = G[(size_t)j * n + j];
+      double s = gjj;
       for (int k = 0; k < j; ++k) s -= Lw[(size_t)j * n + k] * Lw[(size_t)j * n + k];
-      if (!(s > 0.0) || !isfinite(s)) {
+      // numerically dependent: less than 1e-12 of the vector's own norm^2 is left
+      if (!(s > 1e-12 * gjj) || !isfinite(s)) {
         flag[0] = 1;
         s = 1.0;
       }
@@ -304,6 +324,52 @@ __global__ void __launch_bounds__(256) k_cholesky_inverse(const double* __restri
       Linv[(size_t)i * n + col] = -s / Lw[(size_t)i * n + i];
     }
   }
+}
+
+// Same factorisation for n <= 128 with the matrix resident in LDS:
+// right-looking Cholesky (column scale, then rank-1 update of the trailing
+// block), then L^-1 by forward substitution, one column per thread.
+__global__ void __launch_bounds__(256) k_cholesky_inverse_lds(const double* __restrict__ G, int n,
+                                                              double* __restrict__ Linv,
+                                                              int32_t* __restrict__ flag) {
+  extern __shared__ double A[];
+  __shared__ int bad;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  if (tid == 0) bad = 0;
+  for (int t = tid; t < n * n; t += nthr) A[t] = G[t];
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (tid == 0) {
+      double d = A[j * n + j];
+      if (!(d > 1e-12 * G[(size_t)j * n + j]) || !isfinite(d)) {
+        bad = 1;
+        d = 1.0;
+      }
+      A[j * n + j] = sqrt(d);
+    }
+    __syncthreads();
+    const double dj = A[j * n + j];
+    for (int i = j + 1 + tid; i < n; i += nthr) A[i * n + j] /= dj;
+    __syncthreads();
+    const int r = n - j - 1;
+    for (int idx = tid; idx < r * r; idx += nthr) {
+      const int i = j + 1 + idx / r, k = j + 1 + idx % r;
+      if (k <= i) A[i * n + k] -= A[i * n + j] * A[k * n + j];
+    }
+    __syncthreads();
+  }
+  for (int col = tid; col < n; col += nthr) {
+    for (int i = 0; i < col; ++i) Linv[(size_t)i * n + col] = 0.0;
+    double xc[1];
+    xc[0] = 1.0 / A[col * n + col];
+    Linv[(size_t)col * n + col] = xc[0];
+    for (int i = col + 1; i < n; ++i) {
+      double s = 0.0;
+      for (int k = col; k < i; ++k) s += A[i * n + k] * Linv[(size_t)k * n + col];
+      Linv[(size_t)i * n + col] = -s / A[i * n + i];
+    }
+  }
+  if (tid == 0) flag[0] = bad;
 }
 
 // --------------------------------------------------------------------------
@@ -421,10 +487,12 @@ int blocks_for(size_t n) {
 void gemm_wdot(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
                double* C, int ldc, double alpha, double beta, bool half_weights) {
   if (M == 0 || N == 0) return;
-  KernelTimer kt(c, "gemm_wdot");
+  KernelTimer kt(c, "gemm_wdot", ((double)M + N) * K * sizeof(double) + (double)M * N * sizeof(double),
+                 2.0 * M * N * (double)K);
+  // enough workgroups to fill 256 CUs, each still streaming >= 128 k values
   const int tiles = cdiv(M, 64) * cdiv(N, 64);
-  int ks = 512 / tiles;
-  ks = std::max(1, std::min(ks, K / 512));
+  int ks = 1024 / tiles;
+  ks = std::max(1, std::min(ks, K / 128));
   while ((size_t)ks * M * N > c.gemm_part_capacity && ks > 1) --ks;
   int kchunk = cdiv(cdiv(K, ks), 16) * 16;
   ks = cdiv(K, kchunk);
@@ -439,15 +507,21 @@ void gemm_wdot(Ctx& c, int M, int N, int K, const double* A, int lda, const doub
                      N, kchunk, half_weights ? 1 : 0, 1.0, 0.0, 0);
   ROKS_HIP(hipGetLastError());
   const size_t mn = (size_t)M * N;
-  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, c.stream,
-                     c.d_gemm_part, ks, M, N, C, ldc, alpha, beta);
+  if (ks > 16 && mn <= 65536)
+    hipLaunchKernelGGL(k_splitk_reduce_wave, dim3((unsigned)mn), dim3(64), 0, c.stream,
+                       c.d_gemm_part, ks, M, N, C, ldc, alpha, beta);
+  else
+    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, c.stream,
+                       c.d_gemm_part, ks, M, N, C, ldc, alpha, beta);
   ROKS_HIP(hipGetLastError());
 }
 
 void gemm_expand(Ctx& c, int N, int K, int Md, const double* M, int ldm, bool transM,
                  const double* X, int ldx, double* Y, int ldy, double alpha, double beta) {
   if (N == 0 || K == 0) return;
-  KernelTimer kt(c, "gemm_expand");
+  KernelTimer kt(c, "gemm_expand",
+                 ((double)Md * K + (beta != 0.0 ? 2.0 : 1.0) * N * K) * sizeof(double),
+                 2.0 * N * (double)K * Md);
   dim3 grid(cdiv(K, 128), cdiv(N, 32));
   hipLaunchKernelGGL(k_gemm_expand, grid, dim3(256), 0, c.stream, N, K, Md, M, ldm, transM ? 1 : 0, X,
                      ldx, Y, ldy, alpha, beta);
@@ -455,15 +529,15 @@ void gemm_expand(Ctx& c, int N, int K, int Md, const double* M, int ldm, bool tr
 }
 
 void gemm_small(Ctx& c, int M, int N, int K, const double* A, int lda, bool tA, const double* B,
-                int ldb, bool tB, double* C, int ldc, double alpha, double beta) {
+                int ldb, bool tB, double* C, int ldc, double alpha, double beta, double diag) {
   dim3 grid(cdiv(N, 16), cdiv(M, 16));
   hipLaunchKernelGGL(k_gemm_small, grid, dim3(256), 0, c.stream, M, N, K, A, lda, tA ? 1 : 0, B, ldb,
-                     tB ? 1 : 0, C, ldc, alpha, beta);
+                     tB ? 1 : 0, C, ldc, alpha, beta, diag);
   ROKS_HIP(hipGetLastError());
 }
 
 void band_dots(Ctx& c, const double2* X, const double2* Y, int nvec, int mode, double* out) {
-  hipLaunchKernelGGL(k_band_dots, dim3(nvec), dim3(256), 0, c.stream, X, Y, c.npw, c.d_g2, mode, out);
+  hipLaunchKernelGGL(k_band_dots, dim3(nvec), dim3(1024), 0, c.stream, X, Y, c.npw, c.d_g2, mode, out);
   ROKS_HIP(hipGetLastError());
 }
 
@@ -485,7 +559,15 @@ void matrix_norm1(Ctx& c, const double* A, int n, double* out) {
 }
 
 void cholesky_inverse(Ctx& c, const double* G, int n, double* Linv, int32_t* flag) {
-  hipLaunchKernelGGL(k_cholesky_inverse, dim3(1), dim3(256), 0, c.stream, G, n, c.d_m3, Linv, flag);
+  if (n <= 128) {
+    const size_t lds = (size_t)n * n * sizeof(double);
+    if (lds > 65536)
+      ROKS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholesky_inverse_lds),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_cholesky_inverse_lds, dim3(1), dim3(256), lds, c.stream, G, n, Linv, flag);
+  } else {
+    hipLaunchKernelGGL(k_cholesky_inverse, dim3(1), dim3(256), 0, c.stream, G, n, c.d_m3, Linv, flag);
+  }
   ROKS_HIP(hipGetLastError());
 }
 

@@ -205,15 +205,17 @@ struct Ctx {
   struct Timed {
     std::string name;
     hipEvent_t a, b;
+    double bytes, flops;  // algorithmic HBM bytes and flops of the launch
   };
   std::vector<Timed> timed;
 };
 
-// Records HIP events around the launches in its scope when timing is on.
+// Records HIP events around the launches in its scope when timing is on,
+// with the launch's algorithmic byte and flop counts.
 struct KernelTimer {
   Ctx& c;
   int idx = -1;
-  KernelTimer(Ctx& ctx, const char* name);
+  KernelTimer(Ctx& ctx, const char* name, double bytes = 0.0, double flops = 0.0);
   ~KernelTimer();
 };
 
@@ -264,8 +266,9 @@ void gemm_wdot(Ctx& c, int M, int N, int K, const double* A, int lda, const doub
                double* C, int ldc, double alpha, double beta, bool half_weights);
 void gemm_expand(Ctx& c, int N, int K, int Mdim, const double* M, int ldm, bool transM,
                  const double* X, int ldx, double* Y, int ldy, double alpha, double beta);
+// C = alpha op(A) op(B) + beta C + diag I
 void gemm_small(Ctx& c, int M, int N, int K, const double* A, int lda, bool tA, const double* B,
-                int ldb, bool tB, double* C, int ldc, double alpha, double beta);
+                int ldb, bool tB, double* C, int ldc, double alpha, double beta, double diag = 0.0);
 void band_dots(Ctx& c, const double2* X, const double2* Y, int nvec, int mode, double* out);
 void axpby(Ctx& c, size_t n, double a, const double* x, double b, const double* y, double* out);
 void cholesky_inverse(Ctx& c, const double* G, int n, double* Linv, int32_t* flag);

@@ -59,18 +59,20 @@ void expm(Ctx& c, double delta, const double* D, double* U) {
     ++s;
   }
   if (s > 0) axpby(c, nn, std::ldexp(1.0, -s), c.d_m1, 0.0, nullptr, c.d_m1);
+  // P_16 = I + X/16, P_q = I + X P_{q+1} / q, ..., P_1 = exp(X) to degree 16
   set_identity(c, c.d_m2, n, 1.0);
   axpby(c, nn, 1.0 / 16.0, c.d_m1, 1.0, c.d_m2, c.d_m2);
+  double* cur = c.d_m2;
+  double* nxt = c.d_m4;
   for (int q = 15; q >= 1; --q) {
-    gemm_small(c, n, n, n, c.d_m1, n, false, c.d_m2, n, false, c.d_m4, n, 1.0, 0.0);
-    set_identity(c, c.d_m2, n, 1.0);
-    axpby(c, nn, 1.0 / q, c.d_m4, 1.0, c.d_m2, c.d_m2);
+    gemm_small(c, n, n, n, c.d_m1, n, false, cur, n, false, nxt, n, 1.0 / q, 0.0, 1.0);
+    std::swap(cur, nxt);
   }
   for (int i = 0; i < s; ++i) {
-    gemm_small(c, n, n, n, c.d_m2, n, false, c.d_m2, n, false, c.d_m4, n, 1.0, 0.0);
-    copy_dev(c, c.d_m2, c.d_m4, nn * sizeof(double));
+    gemm_small(c, n, n, n, cur, n, false, cur, n, false, nxt, n, 1.0, 0.0);
+    std::swap(cur, nxt);
   }
-  copy_dev(c, U, c.d_m2, nn * sizeof(double));
+  copy_dev(c, U, cur, nn * sizeof(double));
 }
 
 struct Trial {

@@ -101,7 +101,8 @@ _SIGS = {
     "roks_forces": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "roks_synchronize": (C.c_int, [_P]),
     "roks_timing_enable": (C.c_int, [_P, C.c_int32]),
-    "roks_timing_read": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "roks_timing_read": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
 }
 
 
@@ -292,10 +293,11 @@ class Roks:
     def timing_enable(self, on: bool = True):
         self._check(self._L.roks_timing_enable(self._h, 1 if on else 0))
 
-    def timing_read(self, kernel: str):
-        ms, n = C.c_double(), C.c_int32()
-        self._check(self._L.roks_timing_read(self._h, kernel.encode(), C.byref(ms), C.byref(n)))
-        return ms.value, n.value
+    def timing_read(self, kernel: str) -> Dict:
+        ms, n, by, fl = C.c_double(), C.c_int32(), C.c_double(), C.c_double()
+        self._check(self._L.roks_timing_read(self._h, kernel.encode(), C.byref(ms), C.byref(n),
+                                             C.byref(by), C.byref(fl)))
+        return {"ms_total": ms.value, "launches": n.value, "bytes": by.value, "flops": fl.value}
 
     # device-pointer variants (torch tensors or raw ints)
     def apply_h_d(self, c_in_ptr: Optional[int], mask: int, out_ptr: int):
