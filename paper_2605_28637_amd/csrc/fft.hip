@@ -16,6 +16,7 @@
 // All 1D transforms are in-place mixed-radix Stockham passes (radices 8, 4,
 // 2, 3, 5): every thread stages the inputs of its butterflies in registers,
 // the block synchronises, and the outputs are written back to the same LDS.
+#include <algorithm>
 #include <cstdio>
 
 #include "roks_internal.h"
@@ -316,73 +317,94 @@ template <int MAXP>
 __global__ void __launch_bounds__(512) k_plane_apply(
     double2* __restrict__ T, const int32_t* __restrict__ colpos, PlaneGeom g,
     const double2* __restrict__ tw1g, const double2* __restrict__ tw2g,
-    const double* __restrict__ pot, size_t ntot, const int32_t* __restrict__ potidx, int nvec,
-    const double* __restrict__ vq, int nQ, double* __restrict__ Qpart) {
+    const double* __restrict__ pot, int npot, size_t ntot, const int32_t* __restrict__ potidx,
+    int nvec, int nQ, double* __restrict__ Qpart, int npairs, int per_chunk) {
+  // The workgroup owns one z-plane and a chunk of band pairs.  The npot (<= 3)
+  // potentials of its plane points stay in registers across the pairs; nQ > 0
+  // also accumulates <n|V^X|n> for X < nQ from the same registers.
   extern __shared__ double2 smem[];
   double2* tw1 = smem;
   double2* tw2 = smem + g.N1;
   double2* plane = smem + g.N1 + g.N2;
   double* red = reinterpret_cast<double*>(plane + g.N1 * g.PS);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int z = blockIdx.x, pair = blockIdx.y;
-  const int n1 = 2 * pair, n2 = 2 * pair + 1;
+  const int z = blockIdx.x, chunk = blockIdx.y;
   const int np2 = g.N1 * g.N2;
+  const int nh = 2 * g.hmax + 1;
+  const size_t zoff = (size_t)z * np2;
   for (int i = tid; i < g.N1; i += nthr) tw1[i] = tw1g[i];
   for (int i = tid; i < g.N2; i += nthr) tw2[i] = tw2g[i];
-  for (int i = tid; i < g.N1 * g.PS; i += nthr) plane[i] = make_double2(0.0, 0.0);
-  __syncthreads();
-  double2* Tz = T + ((size_t)pair * g.N3 + z) * g.ncol;
-  for (int col = tid; col < g.ncol; col += nthr)
-    plane[colpos[2 * col] * g.PS + colpos[2 * col + 1]] = Tz[col];
-  __syncthreads();
-  const int nh = 2 * g.hmax + 1;
-  fft_lines<MAXP>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, +1);
-  fft_lines<MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, +1);
-  const int i1 = potidx[n1];
-  const int i2 = n2 < nvec ? potidx[n2] : -1;
-  const double* V1 = i1 >= 0 ? pot + (size_t)i1 * ntot : nullptr;
-  const double* V2 = i2 >= 0 ? pot + (size_t)i2 * ntot : nullptr;
-  const size_t zoff = (size_t)z * np2;
-  double q1[kMaxShell] = {0, 0, 0, 0}, q2[kMaxShell] = {0, 0, 0, 0};
-  for (int pt = tid; pt < np2; pt += nthr) {
-    const int x = pt / g.N2, y = pt - x * g.N2;
-    double2& w = plane[x * g.PS + y];
-    const double u1 = w.x, u2 = w.y;
+  double vr[3][MAXP];
 #pragma unroll
-    for (int X = 0; X < kMaxShell; ++X) {
-      if (X < nQ) {
-        const double vx = vq[(size_t)X * ntot + zoff + pt];
-        q1[X] += vx * u1 * u1;
-        q2[X] += vx * u2 * u2;
-      }
+  for (int X = 0; X < 3; ++X)
+#pragma unroll
+    for (int i = 0; i < MAXP; ++i) {
+      const int pt = tid + i * nthr;
+      vr[X][i] = (X < npot && pt < np2) ? pot[(size_t)X * ntot + zoff + pt] : 0.0;
     }
-    const double a = V1 ? V1[zoff + pt] : 0.0;
-    const double b = V2 ? V2[zoff + pt] : 0.0;
-    w = make_double2(a * u1, b * u2);
-  }
-  __syncthreads();
-  fft_lines<MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, -1);
-  fft_lines<MAXP>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, -1);
-  for (int col = tid; col < g.ncol; col += nthr)
-    Tz[col] = plane[colpos[2 * col] * g.PS + colpos[2 * col + 1]];
-  if (nQ > 0) {
-    const int wid = tid >> 6, lane = tid & 63, nw = nthr >> 6;
-    for (int X = 0; X < nQ; ++X) {
-      const double s1 = wave_sum(q1[X]);
-      const double s2 = wave_sum(q2[X]);
-      if (lane == 0) {
-        red[(2 * X) * nw + wid] = s1;
-        red[(2 * X + 1) * nw + wid] = s2;
+  const int p0 = chunk * per_chunk;
+  const int p1 = min(npairs, p0 + per_chunk);
+  for (int pair = p0; pair < p1; ++pair) {
+    const int n1 = 2 * pair, n2 = 2 * pair + 1;
+    for (int i = tid; i < g.N1 * g.PS; i += nthr) plane[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+    double2* Tz = T + ((size_t)pair * g.N3 + z) * g.ncol;
+    for (int col = tid; col < g.ncol; col += nthr)
+      plane[colpos[2 * col] * g.PS + colpos[2 * col + 1]] = Tz[col];
+    __syncthreads();
+    fft_lines<MAXP>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, +1);
+    fft_lines<MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, +1);
+    const int s1 = potidx[n1];
+    const int s2 = n2 < nvec ? potidx[n2] : -1;
+    double q1[3] = {0, 0, 0}, q2[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < MAXP; ++i) {
+      const int pt = tid + i * nthr;
+      if (pt < np2) {
+        const int x = pt / g.N2, y = pt - x * g.N2;
+        double2& w = plane[x * g.PS + y];
+        const double u1 = w.x, u2 = w.y;
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int X = 0; X < 3; ++X) {
+          if (X < nQ) {
+            q1[X] += vr[X][i] * u1 * u1;
+            q2[X] += vr[X][i] * u2 * u2;
+          }
+          if (s1 == X) a = vr[X][i];
+          if (s2 == X) b = vr[X][i];
+        }
+        w = make_double2(a * u1, b * u2);
       }
     }
     __syncthreads();
-    if (tid < 2 * nQ) {
-      double s = 0;
-      for (int w = 0; w < nw; ++w) s += red[tid * nw + w];
-      const int X = tid >> 1, b = tid & 1;
-      // Qpart[pair][z][band b][X]
-      Qpart[(((size_t)pair * g.N3 + z) * 2 + b) * nQ + X] = s;
+    fft_lines<MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, -1);
+    fft_lines<MAXP>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, -1);
+    for (int col = tid; col < g.ncol; col += nthr)
+      Tz[col] = plane[colpos[2 * col] * g.PS + colpos[2 * col + 1]];
+    if (nQ > 0) {
+      const int wid = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+#pragma unroll
+      for (int X = 0; X < 3; ++X) {
+        if (X < nQ) {
+          const double t1 = wave_sum(q1[X]);
+          const double t2 = wave_sum(q2[X]);
+          if (lane == 0) {
+            red[(2 * X) * nw + wid] = t1;
+            red[(2 * X + 1) * nw + wid] = t2;
+          }
+        }
+      }
+      __syncthreads();
+      if (tid < 2 * nQ) {
+        double s = 0;
+        for (int w = 0; w < nw; ++w) s += red[tid * nw + w];
+        const int X = tid >> 1, b = tid & 1;
+        // Qpart[pair][z][band b][X]
+        Qpart[(((size_t)pair * g.N3 + z) * 2 + b) * nQ + X] = s;
+      }
     }
+    __syncthreads();
   }
 }
 
@@ -611,23 +633,26 @@ void launch_zpass_fwd(Ctx& c, const double2* T, int npairs, const double2* vecs,
 }
 
 template <int MP>
-static void run_plane_apply(Ctx& c, double2* T, int npairs, const double* pot,
+static void run_plane_apply(Ctx& c, double2* T, int npairs, const double* pot, int npot,
                             const int32_t* potidx, int nvec, double* Qpart, int nQ) {
   const int nthr = plane_threads(c);
   const size_t lds = plane_lds(c, nthr, nQ);
   allow_lds(k_plane_apply<MP>, lds);
-  dim3 grid(c.N[2], npairs);
+  const int nchunk = std::max(1, std::min(npairs, c.nchunk));
+  const int per = cdiv(npairs, nchunk);
+  dim3 grid(c.N[2], nchunk);
   hipLaunchKernelGGL(k_plane_apply<MP>, grid, dim3(nthr), lds, c.stream, T, c.d_colpos, geom(c),
-                     c.d_tw[0], c.d_tw[1], pot, (size_t)c.ntot, potidx, nvec, c.d_vsh, nQ, Qpart);
+                     c.d_tw[0], c.d_tw[1], pot, npot, (size_t)c.ntot, potidx, nvec, nQ, Qpart,
+                     npairs, per);
   ROKS_HIP(hipGetLastError());
 }
 
-void launch_plane_apply(Ctx& c, double2* T, int npairs, const double* pot, const int32_t* potidx,
-                        int nvec, double* Qpart, int nQ) {
-  KernelTimer kt(c, "plane_apply",
-                 2.0 * colbuf_bytes(c, npairs) + (nQ > 0 ? nQ : 1) * grid_bytes(c));
+void launch_plane_apply(Ctx& c, double2* T, int npairs, const double* pot, int npot,
+                        const int32_t* potidx, int nvec, double* Qpart, int nQ) {
+  ROKS_CHECK(npot >= 1 && npot <= 3 && nQ <= npot, ROKS_ERR_ARG, "plane pass takes 1..3 potentials");
+  KernelTimer kt(c, "plane_apply", 2.0 * colbuf_bytes(c, npairs) + npot * grid_bytes(c));
   const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], plane_threads(c)));
-  ROKS_DISPATCH_MAXP(mp, run_plane_apply, c, T, npairs, pot, potidx, nvec, Qpart, nQ);
+  ROKS_DISPATCH_MAXP(mp, run_plane_apply, c, T, npairs, pot, npot, potidx, nvec, Qpart, nQ);
 }
 
 template <int MP>

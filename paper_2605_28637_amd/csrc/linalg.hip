@@ -40,22 +40,34 @@ __global__ void __launch_bounds__(256) k_gemm_wdot(int M, int N, int K, const do
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int k0 = kb; k0 < ke; k0 += 16) {
+  // the next k slice is loaded into registers while the current one is used
+  double pa[4], pb[4];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int idx = tid + q * 256;
       const int row = idx >> 4, kk = idx & 15;
       const int k = k0 + kk;
-      double a = 0.0, b = 0.0;
+      pa[q] = 0.0;
+      pb[q] = 0.0;
       if (k < ke) {
         const double w = (hw && k >= 2) ? 2.0 : 1.0;
-        if (m0 + row < M) a = w * A[(size_t)(m0 + row) * lda + k];
-        if (n0 + row < N) b = B[(size_t)(n0 + row) * ldb + k];
+        if (m0 + row < M) pa[q] = w * A[(size_t)(m0 + row) * lda + k];
+        if (n0 + row < N) pb[q] = B[(size_t)(n0 + row) * ldb + k];
       }
-      As[kk][row] = a;
-      Bs[kk][row] = b;
+    }
+  };
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + q * 256;
+      const int row = idx >> 4, kk = idx & 15;
+      As[kk][row] = pa[q];
+      Bs[kk][row] = pb[q];
     }
     __syncthreads();
+    if (k0 + 16 < ke) load(k0 + 16);
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
       double a[4], b[4];
@@ -326,17 +338,24 @@ __global__ void __launch_bounds__(256) k_cholesky_inverse(const double* __restri
   }
 }
 
-// Same factorisation for n <= 128 with the matrix resident in LDS:
-// right-looking Cholesky (column scale, then rank-1 update of the trailing
-// block), then L^-1 by forward substitution, one column per thread.
-__global__ void __launch_bounds__(256) k_cholesky_inverse_lds(const double* __restrict__ G, int n,
-                                                              double* __restrict__ Linv,
-                                                              int32_t* __restrict__ flag) {
+// Same factorisation for n <= 128 with the matrix resident in LDS,
+// right-looking: at column j scale column j of L, and (n <= 96) also run the
+// forward elimination of L X = I on an LDS copy of the identity, so that row
+// j of X = L^-1 is final after step j; then rank-1 updates of the trailing
+// block of A and of the rows below j of X.  All work per step is parallel.
+__global__ void __launch_bounds__(1024) k_cholesky_inverse_lds(const double* __restrict__ G, int n,
+                                                               double* __restrict__ Linv,
+                                                               int32_t* __restrict__ flag,
+                                                               int inv_in_lds) {
   extern __shared__ double A[];
   __shared__ int bad;
   const int tid = threadIdx.x, nthr = blockDim.x;
+  double* X = A + n * n;
   if (tid == 0) bad = 0;
-  for (int t = tid; t < n * n; t += nthr) A[t] = G[t];
+  for (int t = tid; t < n * n; t += nthr) {
+    A[t] = G[t];
+    if (inv_in_lds) X[t] = (t / n == t % n) ? 1.0 : 0.0;
+  }
   __syncthreads();
   for (int j = 0; j < n; ++j) {
     if (tid == 0) {
@@ -350,26 +369,110 @@ __global__ void __launch_bounds__(256) k_cholesky_inverse_lds(const double* __re
     __syncthreads();
     const double dj = A[j * n + j];
     for (int i = j + 1 + tid; i < n; i += nthr) A[i * n + j] /= dj;
+    if (inv_in_lds)
+      for (int cc = tid; cc <= j; cc += nthr) X[j * n + cc] /= dj;
     __syncthreads();
     const int r = n - j - 1;
     for (int idx = tid; idx < r * r; idx += nthr) {
       const int i = j + 1 + idx / r, k = j + 1 + idx % r;
       if (k <= i) A[i * n + k] -= A[i * n + j] * A[k * n + j];
     }
+    if (inv_in_lds) {
+      const int w = j + 1;
+      for (int idx = tid; idx < r * w; idx += nthr) {
+        const int i = j + 1 + idx / w, cc = idx % w;
+        X[i * n + cc] -= A[i * n + j] * X[j * n + cc];
+      }
+    }
     __syncthreads();
   }
-  for (int col = tid; col < n; col += nthr) {
-    for (int i = 0; i < col; ++i) Linv[(size_t)i * n + col] = 0.0;
-    double xc[1];
-    xc[0] = 1.0 / A[col * n + col];
-    Linv[(size_t)col * n + col] = xc[0];
-    for (int i = col + 1; i < n; ++i) {
-      double s = 0.0;
-      for (int k = col; k < i; ++k) s += A[i * n + k] * Linv[(size_t)k * n + col];
-      Linv[(size_t)i * n + col] = -s / A[i * n + i];
+  if (inv_in_lds) {
+    for (int t = tid; t < n * n; t += nthr) Linv[t] = (t % n <= t / n) ? X[t] : 0.0;
+  } else {
+    for (int col = tid; col < n; col += nthr) {
+      for (int i = 0; i < col; ++i) Linv[(size_t)i * n + col] = 0.0;
+      Linv[(size_t)col * n + col] = 1.0 / A[col * n + col];
+      for (int i = col + 1; i < n; ++i) {
+        double s = 0.0;
+        for (int k = col; k < i; ++k) s += A[i * n + k] * Linv[(size_t)k * n + col];
+        Linv[(size_t)i * n + col] = -s / A[i * n + i];
+      }
     }
   }
   if (tid == 0) flag[0] = bad;
+}
+
+// exp(delta D) for n <= 78 in one workgroup: 1-norm, scaling by 2^-s with
+// ||X|| <= 1/2, degree-16 Taylor in Horner form, s squarings; X, P, Q in LDS
+__global__ void __launch_bounds__(1024) k_expm_lds(const double* __restrict__ D, int n, double delta,
+                                                  double* __restrict__ U) {
+  extern __shared__ double S[];
+  __shared__ double nrm;
+  double* X = S;
+  double* P = S + n * n;
+  double* Q = P + n * n;
+  const int tid = threadIdx.x, nthr = blockDim.x, nn = n * n;
+  for (int t = tid; t < nn; t += nthr) X[t] = delta * D[t];
+  __syncthreads();
+  if (tid < 64) {
+    double mx = 0.0;
+    for (int j = tid; j < n; j += 64) {
+      double s = 0.0;
+      for (int i = 0; i < n; ++i) s += fabs(X[i * n + j]);
+      mx = fmax(mx, s);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if (tid == 0) nrm = mx;
+  }
+  __syncthreads();
+  double v = nrm;
+  int sq = 0;
+  while (v > 0.5) {
+    v *= 0.5;
+    ++sq;
+  }
+  const double scale = ldexp(1.0, -sq);
+  for (int t = tid; t < nn; t += nthr) {
+    X[t] *= scale;
+    P[t] = X[t] / 16.0 + ((t / n) == (t % n) ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  // products with four independent partial sums per output (the k loop is a
+  // latency chain otherwise)
+  auto prod = [&](const double* L, const double* R, int i, int j) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = 0;
+    for (; k + 3 < n; k += 4) {
+      s0 = fma(L[i * n + k], R[k * n + j], s0);
+      s1 = fma(L[i * n + k + 1], R[(k + 1) * n + j], s1);
+      s2 = fma(L[i * n + k + 2], R[(k + 2) * n + j], s2);
+      s3 = fma(L[i * n + k + 3], R[(k + 3) * n + j], s3);
+    }
+    for (; k < n; ++k) s0 = fma(L[i * n + k], R[k * n + j], s0);
+    return (s0 + s1) + (s2 + s3);
+  };
+  for (int q = 15; q >= 1; --q) {
+    for (int t = tid; t < nn; t += nthr) {
+      const int i = t / n, j = t - i * n;
+      Q[t] = prod(X, P, i, j) / q + (i == j ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    double* tmp = P;
+    P = Q;
+    Q = tmp;
+  }
+  for (int r = 0; r < sq; ++r) {
+    for (int t = tid; t < nn; t += nthr) {
+      const int i = t / n, j = t - i * n;
+      Q[t] = prod(P, P, i, j);
+    }
+    __syncthreads();
+    double* tmp = P;
+    P = Q;
+    Q = tmp;
+  }
+  for (int t = tid; t < nn; t += nthr) U[t] = P[t];
 }
 
 // --------------------------------------------------------------------------
@@ -489,10 +592,12 @@ void gemm_wdot(Ctx& c, int M, int N, int K, const double* A, int lda, const doub
   if (M == 0 || N == 0) return;
   KernelTimer kt(c, "gemm_wdot", ((double)M + N) * K * sizeof(double) + (double)M * N * sizeof(double),
                  2.0 * M * N * (double)K);
-  // enough workgroups to fill 256 CUs, each still streaming >= 128 k values
+  // Every k slice costs one global-load latency that one slice of compute
+  // cannot hide, so small outputs get many workgroups of ~2 slices each
+  // (several per CU); the split-K partials are summed in a fixed order.
   const int tiles = cdiv(M, 64) * cdiv(N, 64);
-  int ks = 1024 / tiles;
-  ks = std::max(1, std::min(ks, K / 128));
+  int ks = 2048 / tiles;
+  ks = std::max(1, std::min(ks, K / 32));
   while ((size_t)ks * M * N > c.gemm_part_capacity && ks > 1) --ks;
   int kchunk = cdiv(cdiv(K, ks), 16) * 16;
   ks = cdiv(K, kchunk);
@@ -560,14 +665,28 @@ void matrix_norm1(Ctx& c, const double* A, int n, double* out) {
 
 void cholesky_inverse(Ctx& c, const double* G, int n, double* Linv, int32_t* flag) {
   if (n <= 128) {
-    const size_t lds = (size_t)n * n * sizeof(double);
+    const int inv = n <= 96 ? 1 : 0;
+    const size_t lds = (size_t)(inv ? 2 : 1) * n * n * sizeof(double);
     if (lds > 65536)
       ROKS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholesky_inverse_lds),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_cholesky_inverse_lds, dim3(1), dim3(256), lds, c.stream, G, n, Linv, flag);
+    hipLaunchKernelGGL(k_cholesky_inverse_lds, dim3(1), dim3(1024), lds, c.stream, G, n, Linv, flag,
+                       inv);
   } else {
     hipLaunchKernelGGL(k_cholesky_inverse, dim3(1), dim3(256), 0, c.stream, G, n, c.d_m3, Linv, flag);
   }
+  ROKS_HIP(hipGetLastError());
+}
+
+bool expm_in_lds(const Ctx& c) { return c.nb <= 78; }
+
+void launch_expm_lds(Ctx& c, const double* D, double delta, double* U) {
+  const int n = c.nb;
+  const size_t lds = (size_t)3 * n * n * sizeof(double);
+  if (lds > 65536)
+    ROKS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_expm_lds),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_expm_lds, dim3(1), dim3(1024), lds, c.stream, D, n, delta, U);
   ROKS_HIP(hipGetLastError());
 }
 

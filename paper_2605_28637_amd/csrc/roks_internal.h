@@ -234,8 +234,10 @@ void upload_positions(Ctx& c);
 // kernels launchers -----------------------------------------------------------
 // fft.hip
 void launch_zpass_bwd(Ctx& c, const double2* vecs, int nvec, double2* T, int npairs);
-void launch_plane_apply(Ctx& c, double2* T, int npairs, const double* pot, const int32_t* potidx,
-                        int npot_stride, double* Qpart, int nQ);
+// pot holds npot (1..3) grids; potidx[n] selects band n's grid (-1: zero);
+// nQ > 0 also accumulates <n|V^X|n> for the first nQ grids into Qpart
+void launch_plane_apply(Ctx& c, double2* T, int npairs, const double* pot, int npot,
+                        const int32_t* potidx, int nvec, double* Qpart, int nQ);
 void launch_plane_density(Ctx& c, const double2* T, int npairs, double* rho_part, int nchunk);
 void launch_zpass_fwd(Ctx& c, const double2* T, int npairs, const double2* vecs, int nvec,
                       const double* kinw, double2* Y);
@@ -275,6 +277,8 @@ void cholesky_inverse(Ctx& c, const double* G, int n, double* Linv, int32_t* fla
 void set_identity(Ctx& c, double* A, int n, double diag);
 void matrix_norm1(Ctx& c, const double* A, int n, double* out);
 void launch_subspace(Ctx& c);
+bool expm_in_lds(const Ctx& c);
+void launch_expm_lds(Ctx& c, const double* D, double delta, double* U);
 void launch_asym_dot(Ctx& c, const double* A, const double* theta, double* out);
 void launch_teter(Ctx& c, const double* gTg, const double* gg, const double2* g, const double* bandw,
                   double2* out);

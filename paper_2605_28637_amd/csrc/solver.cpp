@@ -46,6 +46,10 @@ double total_dot(Ctx& c, const double2* x, const double2* y) {
 // U = exp(X) for X = delta * D (antisymmetric): scaling and squaring with a
 // degree-16 Taylor polynomial in Horner form
 void expm(Ctx& c, double delta, const double* D, double* U) {
+  if (expm_in_lds(c)) {
+    launch_expm_lds(c, D, delta, U);
+    return;
+  }
   const int n = c.nb;
   const size_t nn = (size_t)n * n;
   axpby(c, nn, delta, D, 0.0, nullptr, c.d_m1);
@@ -170,7 +174,7 @@ void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bo
     gemm_wdot(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(vecs), K, c.d_dP, nb, 1.0, 0.0, true);
   if (mask == 0) {
     launch_zpass_bwd(c, vecs, nb, c.d_T, c.npairs);
-    launch_plane_apply(c, c.d_T, c.npairs, c.d_vsh, c.d_potidx, nb, c.d_Qpart,
+    launch_plane_apply(c, c.d_T, c.npairs, c.d_vsh, c.nsocc, c.d_potidx, nb, c.d_Qpart,
                        want_Q ? c.nsocc : 0);
     launch_zpass_fwd(c, c.d_T, c.npairs, vecs, nb, c.d_kinw_shell, out);
     if (c.nproj > 0) {
@@ -190,7 +194,9 @@ void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bo
     if (!(mask & (1u << b))) continue;
     double2* o = out + (size_t)idx * band;
     launch_zpass_bwd(c, vecs, nb, c.d_T, c.npairs);
-    launch_plane_apply(c, c.d_T, c.npairs, c.d_vloc, c.d_potidx + (size_t)(1 + b) * nb, nb, c.d_Qpart, 0);
+    // one potential grid (channel b); row 1 of d_potidx is all zeros
+    launch_plane_apply(c, c.d_T, c.npairs, c.d_vloc + (size_t)b * c.ntot, 1, c.d_potidx + nb, nb,
+                       c.d_Qpart, 0);
     launch_zpass_fwd(c, c.d_T, c.npairs, vecs, nb, c.d_ones, o);
     if (c.nproj > 0) {
       launch_apply_D(c, c.d_dP, nullptr, c.d_DP);
