@@ -207,6 +207,10 @@ roks_status roks_subspace(roks_ctx ctx, double* R, double* kappa, double* A);
 roks_status roks_pcg_step(roks_ctx ctx, roks_step_info* info);
 /* Forget the carried search directions (next step is steepest descent). */
 roks_status roks_reset_cg(roks_ctx ctx);
+/* Switch the arithmetic tier of the FFT / pointwise work (roks_precision)
+ * for the following calls, keeping the orbitals and the CG state: a
+ * precision ladder runs FP32 iterations first and polishes in FP64. */
+roks_status roks_set_precision(roks_ctx ctx, int32_t precision);
 /* Iterate roks_pcg_step until |E_{i+1} - E_i| < tol on two consecutive
  * iterations or maxiter; *iterations receives the count, *last the final
  * step's info (either may be NULL). */

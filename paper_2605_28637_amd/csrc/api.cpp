@@ -231,6 +231,18 @@ roks_status roks_reset_cg(roks_ctx ctx) {
   return guard(ctx, [&](roks::Ctx& c) { roks::reset_cg(c); });
 }
 
+roks_status roks_set_precision(roks_ctx ctx, int32_t precision) {
+  return guard(ctx, [&](roks::Ctx& c) {
+    ROKS_CHECK(precision == ROKS_FP64 || precision == ROKS_FP32, ROKS_ERR_ARG, "unknown precision");
+    if (precision == ROKS_FP32 && !c.d_vsh32) {
+      c.d_vsh32 = roks::dalloc<float>(c, (size_t)c.nsocc * c.ntot);
+      c.d_vloc32 = roks::dalloc<float>(c, (size_t)2 * c.nconf * c.ntot);
+    }
+    if (precision != c.prec) c.potentials_valid = false;
+    c.prec = precision;
+  });
+}
+
 roks_status roks_solve(roks_ctx ctx, double tol, int32_t maxiter, roks_step_info* last,
                        int32_t* iterations) {
   return guard(ctx, [&](roks::Ctx& c) {

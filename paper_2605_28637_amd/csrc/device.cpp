@@ -20,7 +20,14 @@ void init_device(Ctx& c, void* stream) {
   c.d_g2 = dalloc<double>(c, npw);
   c.d_cols = dalloc<ColDesc>(c, c.cols.size());
   c.d_colpos = dalloc<int32_t>(c, 2 * (size_t)c.ncol);
-  for (int d = 0; d < 3; ++d) c.d_tw[d] = dalloc<double2>(c, c.N[d]);
+  for (int d = 0; d < 3; ++d) {
+    c.d_tw[d] = dalloc<double2>(c, c.N[d]);
+    c.d_tw32[d] = dalloc<float2>(c, c.N[d]);
+  }
+  if (c.prec == ROKS_FP32) {
+    c.d_vsh32 = dalloc<float>(c, (size_t)c.nsocc * c.ntot);
+    c.d_vloc32 = dalloc<float>(c, (size_t)2 * c.nconf * c.ntot);
+  }
   c.d_vext = dalloc<double>(c, ntot);
   c.d_B = dalloc<double2>(c, np * npw);
   c.d_proj_atom = dalloc<int32_t>(c, np);
@@ -95,13 +102,17 @@ void upload_static(Ctx& c) {
   }
   up(c.d_colpos, colpos.data(), colpos.size() * sizeof(int32_t));
   std::vector<double2> tw[3];  // host sources stay alive until the stream synchronises below
+  std::vector<float2> tw32[3];
   for (int d = 0; d < 3; ++d) {
     tw[d].resize(c.N[d]);
+    tw32[d].resize(c.N[d]);
     for (int k = 0; k < c.N[d]; ++k) {
       long double a = -2.0L * (long double)M_PI * (long double)k / (long double)c.N[d];
       tw[d][k] = make_double2((double)std::cos(a), (double)std::sin(a));
+      tw32[d][k] = make_float2((float)std::cos(a), (float)std::sin(a));
     }
     up(c.d_tw[d], tw[d].data(), tw[d].size() * sizeof(double2));
+    up(c.d_tw32[d], tw32[d].data(), tw32[d].size() * sizeof(float2));
   }
   up(c.d_proj_atom, c.proj_atom.data(), c.proj_atom.size() * sizeof(int32_t));
   up(c.d_Dblk, c.Dblk.data(), c.Dblk.size() * sizeof(double));

@@ -1,4 +1,5 @@
-// Batched 3D FFTs of Gamma-point bands for gfx950, staged in LDS.
+// Batched 3D FFTs of Gamma-point bands for gfx950, staged in LDS, in FP64 or
+// FP32 (the arithmetic tier of the context).
 //
 // One band pair (u1 + i u2, both real in r-space) is one complex transform.
 // The G -> r direction runs in two kernels:
@@ -16,6 +17,8 @@
 // All 1D transforms are in-place mixed-radix Stockham passes (radices 8, 4,
 // 2, 3, 5): every thread stages the inputs of its butterflies in registers,
 // the block synchronises, and the outputs are written back to the same LDS.
+// Band coefficients in and out are FP64 in both tiers; the column buffer,
+// the plane arithmetic and the potentials are in the tier's precision R.
 #include <algorithm>
 #include <cstdio>
 
@@ -25,86 +28,121 @@ namespace roks {
 
 namespace {
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+template <typename R>
+struct CT;
+template <>
+struct CT<double> {
+  using V = double2;
+};
+template <>
+struct CT<float> {
+  using V = float2;
+};
+template <typename R>
+using C2 = typename CT<R>::V;
+
+template <typename R>
+__device__ __forceinline__ C2<R> mk(R x, R y) {
+  C2<R> v;
+  v.x = x;
+  v.y = y;
+  return v;
 }
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+template <typename R>
+__device__ __forceinline__ C2<R> cmul(C2<R> a, C2<R> b) {
+  return mk<R>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename R>
+__device__ __forceinline__ C2<R> cadd(C2<R> a, C2<R> b) { return mk<R>(a.x + b.x, a.y + b.y); }
+template <typename R>
+__device__ __forceinline__ C2<R> csub(C2<R> a, C2<R> b) { return mk<R>(a.x - b.x, a.y - b.y); }
 // multiply by s*i (s = +-1)
-__device__ __forceinline__ double2 cmuli(double2 a, int s) {
-  return s > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+template <typename R>
+__device__ __forceinline__ C2<R> cmuli(C2<R> a, int s) {
+  return s > 0 ? mk<R>(-a.y, a.x) : mk<R>(a.y, -a.x);
 }
-__device__ __forceinline__ double2 cscale(double2 a, double f) { return make_double2(a.x * f, a.y * f); }
+template <typename R>
+__device__ __forceinline__ C2<R> cscale(C2<R> a, R f) { return mk<R>(a.x * f, a.y * f); }
 
-// DFT of length R with kernel exp(s 2 pi i r q / R), in place.
-template <int R>
-__device__ __forceinline__ void dft(double2* v, int s);
+// DFT of length N with kernel exp(s 2 pi i r q / N), in place.
+template <typename R, int N>
+struct Dft;
 
-template <>
-__device__ __forceinline__ void dft<2>(double2* v, int) {
-  double2 a = v[0], b = v[1];
-  v[0] = cadd(a, b);
-  v[1] = csub(a, b);
-}
+template <typename R>
+struct Dft<R, 2> {
+  static __device__ __forceinline__ void run(C2<R>* v, int) {
+    C2<R> a = v[0], b = v[1];
+    v[0] = cadd<R>(a, b);
+    v[1] = csub<R>(a, b);
+  }
+};
 
-template <>
-__device__ __forceinline__ void dft<4>(double2* v, int s) {
-  double2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
-  double2 c = cadd(v[1], v[3]), d = cmuli(csub(v[1], v[3]), s);
-  v[0] = cadd(a, c);
-  v[2] = csub(a, c);
-  v[1] = cadd(b, d);
-  v[3] = csub(b, d);
-}
+template <typename R>
+struct Dft<R, 4> {
+  static __device__ __forceinline__ void run(C2<R>* v, int s) {
+    C2<R> a = cadd<R>(v[0], v[2]), b = csub<R>(v[0], v[2]);
+    C2<R> c = cadd<R>(v[1], v[3]), d = cmuli<R>(csub<R>(v[1], v[3]), s);
+    v[0] = cadd<R>(a, c);
+    v[2] = csub<R>(a, c);
+    v[1] = cadd<R>(b, d);
+    v[3] = csub<R>(b, d);
+  }
+};
 
-template <>
-__device__ __forceinline__ void dft<8>(double2* v, int s) {
-  const double h = 0.70710678118654752440;
-  double2 e[4] = {v[0], v[2], v[4], v[6]};
-  double2 o[4] = {v[1], v[3], v[5], v[7]};
-  dft<4>(e, s);
-  dft<4>(o, s);
-  // w8^q = exp(s 2 pi i q / 8)
-  double2 o1 = make_double2(h * (o[1].x - s * o[1].y), h * (o[1].y + s * o[1].x));
-  double2 o2 = cmuli(o[2], s);
-  double2 o3 = make_double2(h * (-o[3].x - s * o[3].y), h * (-o[3].y + s * o[3].x));
-  v[0] = cadd(e[0], o[0]);
-  v[4] = csub(e[0], o[0]);
-  v[1] = cadd(e[1], o1);
-  v[5] = csub(e[1], o1);
-  v[2] = cadd(e[2], o2);
-  v[6] = csub(e[2], o2);
-  v[3] = cadd(e[3], o3);
-  v[7] = csub(e[3], o3);
-}
+template <typename R>
+struct Dft<R, 8> {
+  static __device__ __forceinline__ void run(C2<R>* v, int s) {
+    const R h = (R)0.70710678118654752440;
+    C2<R> e[4] = {v[0], v[2], v[4], v[6]};
+    C2<R> o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<R, 4>::run(e, s);
+    Dft<R, 4>::run(o, s);
+    // w8^q = exp(s 2 pi i q / 8)
+    C2<R> o1 = mk<R>(h * (o[1].x - s * o[1].y), h * (o[1].y + s * o[1].x));
+    C2<R> o2 = cmuli<R>(o[2], s);
+    C2<R> o3 = mk<R>(h * (-o[3].x - s * o[3].y), h * (-o[3].y + s * o[3].x));
+    v[0] = cadd<R>(e[0], o[0]);
+    v[4] = csub<R>(e[0], o[0]);
+    v[1] = cadd<R>(e[1], o1);
+    v[5] = csub<R>(e[1], o1);
+    v[2] = cadd<R>(e[2], o2);
+    v[6] = csub<R>(e[2], o2);
+    v[3] = cadd<R>(e[3], o3);
+    v[7] = csub<R>(e[3], o3);
+  }
+};
 
-template <>
-__device__ __forceinline__ void dft<3>(double2* v, int s) {
-  const double r3 = 0.86602540378443864676;  // sqrt(3)/2
-  double2 t = cadd(v[1], v[2]);
-  double2 m = make_double2(v[0].x - 0.5 * t.x, v[0].y - 0.5 * t.y);
-  double2 d = cmuli(cscale(csub(v[1], v[2]), r3), s);
-  v[0] = cadd(v[0], t);
-  v[1] = cadd(m, d);
-  v[2] = csub(m, d);
-}
+template <typename R>
+struct Dft<R, 3> {
+  static __device__ __forceinline__ void run(C2<R>* v, int s) {
+    const R r3 = (R)0.86602540378443864676;  // sqrt(3)/2
+    C2<R> t = cadd<R>(v[1], v[2]);
+    C2<R> m = mk<R>(v[0].x - (R)0.5 * t.x, v[0].y - (R)0.5 * t.y);
+    C2<R> d = cmuli<R>(cscale<R>(csub<R>(v[1], v[2]), r3), s);
+    v[0] = cadd<R>(v[0], t);
+    v[1] = cadd<R>(m, d);
+    v[2] = csub<R>(m, d);
+  }
+};
 
-template <>
-__device__ __forceinline__ void dft<5>(double2* v, int s) {
-  const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
-  const double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
-  double2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
-  double2 d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
-  double2 a1 = make_double2(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
-  double2 a2 = make_double2(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
-  double2 b1 = cmuli(make_double2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y), s);
-  double2 b2 = cmuli(make_double2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y), s);
-  v[0] = cadd(v[0], cadd(t1, t2));
-  v[1] = cadd(a1, b1);
-  v[4] = csub(a1, b1);
-  v[2] = cadd(a2, b2);
-  v[3] = csub(a2, b2);
-}
+template <typename R>
+struct Dft<R, 5> {
+  static __device__ __forceinline__ void run(C2<R>* v, int s) {
+    const R c1 = (R)0.30901699437494742410, c2 = (R)-0.80901699437494742410;
+    const R s1 = (R)0.95105651629515357212, s2 = (R)0.58778525229247312917;
+    C2<R> t1 = cadd<R>(v[1], v[4]), t2 = cadd<R>(v[2], v[3]);
+    C2<R> d1 = csub<R>(v[1], v[4]), d2 = csub<R>(v[2], v[3]);
+    C2<R> a1 = mk<R>(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
+    C2<R> a2 = mk<R>(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
+    C2<R> b1 = cmuli<R>(mk<R>(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y), s);
+    C2<R> b2 = cmuli<R>(mk<R>(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y), s);
+    v[0] = cadd<R>(v[0], cadd<R>(t1, t2));
+    v[1] = cadd<R>(a1, b1);
+    v[4] = csub<R>(a1, b1);
+    v[2] = cadd<R>(a2, b2);
+    v[3] = csub<R>(a2, b2);
+  }
+};
 
 struct Strided {
   int stride;
@@ -121,23 +159,23 @@ struct Rows {
   }
 };
 
-// One Stockham pass of radix R over `nlines` lines of length N.
-template <int RADIX, int MAXBF, typename LineMap>
-__device__ __forceinline__ void fft_stage(double2* buf, int N, int Ns, int nlines, LineMap lm,
-                                          int estride, const double2* tw, int sign) {
+// One Stockham pass of radix RX over `nlines` lines of length N.
+template <typename R, int RX, int MAXBF, typename LineMap>
+__device__ __forceinline__ void fft_stage(C2<R>* buf, int N, int Ns, int nlines, LineMap lm,
+                                          int estride, const C2<R>* tw, int sign) {
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int NR = N / RADIX;
+  const int NR = N / RX;
   const int nbf = nlines * NR;
-  const int twstep = N / (Ns * RADIX);
-  double2 v[MAXBF][RADIX];
+  const int twstep = N / (Ns * RX);
+  C2<R> v[MAXBF][RX];
 #pragma unroll
   for (int i = 0; i < MAXBF; ++i) {
     const int b = tid + i * nthr;
     if (b < nbf) {
       const int line = b / NR, t = b - line * NR;
-      const double2* src = buf + lm(line);
+      const C2<R>* src = buf + lm(line);
 #pragma unroll
-      for (int r = 0; r < RADIX; ++r) v[i][r] = src[(t + r * NR) * estride];
+      for (int r = 0; r < RX; ++r) v[i][r] = src[(t + r * NR) * estride];
     }
   }
   __syncthreads();
@@ -149,37 +187,37 @@ __device__ __forceinline__ void fft_stage(double2* buf, int N, int Ns, int nline
       const int k = t % Ns;
       if (k != 0) {
 #pragma unroll
-        for (int r = 1; r < RADIX; ++r) {
-          double2 w = tw[k * r * twstep];  // exp(-2 pi i k r / (Ns R))
+        for (int r = 1; r < RX; ++r) {
+          C2<R> w = tw[k * r * twstep];  // exp(-2 pi i k r / (Ns RX))
           if (sign > 0) w.y = -w.y;
-          v[i][r] = cmul(v[i][r], w);
+          v[i][r] = cmul<R>(v[i][r], w);
         }
       }
-      dft<RADIX>(v[i], sign);
-      const int j = (t / Ns) * Ns * RADIX + k;
-      double2* dst = buf + lm(line);
+      Dft<R, RX>::run(v[i], sign);
+      const int j = (t / Ns) * Ns * RX + k;
+      C2<R>* dst = buf + lm(line);
 #pragma unroll
-      for (int r = 0; r < RADIX; ++r) dst[(j + r * Ns) * estride] = v[i][r];
+      for (int r = 0; r < RX; ++r) dst[(j + r * Ns) * estride] = v[i][r];
     }
   }
   __syncthreads();
 }
 
 // Transform `nlines` lines in place; MAXP bounds ceil(nlines N / blockDim).
-template <int MAXP, typename LineMap>
-__device__ void fft_lines(double2* buf, const FftPlan1D& plan, int nlines, LineMap lm, int estride,
-                          const double2* tw, int sign) {
+template <typename R, int MAXP, typename LineMap>
+__device__ void fft_lines(C2<R>* buf, const FftPlan1D& plan, int nlines, LineMap lm, int estride,
+                          const C2<R>* tw, int sign) {
   int Ns = 1;
   for (int s = 0; s < plan.nstages; ++s) {
-    const int R = plan.radix[s];
-    switch (R) {
-      case 8: fft_stage<8, (MAXP + 7) / 8>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
-      case 4: fft_stage<4, (MAXP + 3) / 4>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
-      case 2: fft_stage<2, (MAXP + 1) / 2>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
-      case 3: fft_stage<3, (MAXP + 2) / 3>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
-      default: fft_stage<5, (MAXP + 4) / 5>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
+    const int RX = plan.radix[s];
+    switch (RX) {
+      case 8: fft_stage<R, 8, (MAXP + 7) / 8>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
+      case 4: fft_stage<R, 4, (MAXP + 3) / 4>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
+      case 2: fft_stage<R, 2, (MAXP + 1) / 2>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
+      case 3: fft_stage<R, 3, (MAXP + 2) / 3>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
+      default: fft_stage<R, 5, (MAXP + 4) / 5>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
     }
-    Ns *= R;
+    Ns *= RX;
   }
 }
 
@@ -197,16 +235,17 @@ __device__ __forceinline__ double wave_sum(double v) {
 // ---------------------------------------------------------------------------
 // z pass, G -> r
 // ---------------------------------------------------------------------------
-template <int MAXP>
+template <typename R, int MAXP>
 __global__ void __launch_bounds__(512) k_zpass_bwd(const double2* __restrict__ vecs, int nvec,
                                                     int npw, const ColDesc* __restrict__ cols,
                                                     int ndesc, int nH, FftPlan1D plan,
-                                                    const double2* __restrict__ twg,
-                                                    double2* __restrict__ T, int ncol, int CH) {
-  extern __shared__ double2 smem[];
+                                                    const C2<R>* __restrict__ twg,
+                                                    C2<R>* __restrict__ T, int ncol, int CH) {
+  extern __shared__ char smem_raw[];
+  C2<R>* smem = reinterpret_cast<C2<R>*>(smem_raw);
   const int N3 = plan.n;
-  double2* tw = smem;
-  double2* buf = smem + N3;
+  C2<R>* tw = smem;
+  C2<R>* buf = smem + N3;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int pair = blockIdx.y;
   const int j0 = blockIdx.x * CH;
@@ -215,7 +254,7 @@ __global__ void __launch_bounds__(512) k_zpass_bwd(const double2* __restrict__ v
   const double2* c2 = vecs + (size_t)n2 * npw;
   const bool has2 = n2 < nvec;
   for (int i = tid; i < N3; i += nthr) tw[i] = twg[i];
-  for (int i = tid; i < 2 * CH * N3; i += nthr) buf[i] = make_double2(0.0, 0.0);
+  for (int i = tid; i < 2 * CH * N3; i += nthr) buf[i] = mk<R>(0, 0);
   __syncthreads();
   for (int idx = tid; idx < CH * N3; idx += nthr) {
     const int c = idx / N3, e = idx - c * N3;
@@ -227,8 +266,8 @@ __global__ void __launch_bounds__(512) k_zpass_bwd(const double2* __restrict__ v
     const int g = d.base + e;
     const double2 a = c1[g];
     const double2 b = has2 ? c2[g] : make_double2(0.0, 0.0);
-    const double2 v = make_double2(a.x - b.y, a.y + b.x);    // c1 + i c2
-    const double2 vm = make_double2(a.x + b.y, b.x - a.y);   // conj(c1) + i conj(c2)
+    const C2<R> v = mk<R>((R)(a.x - b.y), (R)(a.y + b.x));    // c1 + i c2
+    const C2<R> vm = mk<R>((R)(a.x + b.y), (R)(b.x - a.y));   // conj(c1) + i conj(c2)
     buf[(2 * c) * N3 + wrap(l, N3)] = v;
     if (j > 0)
       buf[(2 * c + 1) * N3 + wrap(-l, N3)] = vm;
@@ -236,7 +275,7 @@ __global__ void __launch_bounds__(512) k_zpass_bwd(const double2* __restrict__ v
       buf[(2 * c) * N3 + wrap(-l, N3)] = vm;
   }
   __syncthreads();
-  fft_lines<MAXP>(buf, plan, 2 * CH, Strided{N3}, 1, tw, +1);
+  fft_lines<R, MAXP>(buf, plan, 2 * CH, Strided{N3}, 1, tw, +1);
   for (int idx = tid; idx < CH * N3; idx += nthr) {
     const int z = idx / CH, c = idx - z * CH;
     const int j = j0 + c;
@@ -248,18 +287,19 @@ __global__ void __launch_bounds__(512) k_zpass_bwd(const double2* __restrict__ v
 }
 
 // ---------------------------------------------------------------------------
-// z pass, r -> G, with unpacking, scaling and the kinetic term
+// z pass, r -> G, with unpacking, scaling and the (FP64) kinetic term
 // ---------------------------------------------------------------------------
-template <int MAXP>
+template <typename R, int MAXP>
 __global__ void __launch_bounds__(512) k_zpass_fwd(
-    const double2* __restrict__ T, int ncol, const ColDesc* __restrict__ cols, int ndesc, int nH,
-    FftPlan1D plan, const double2* __restrict__ twg, const double2* __restrict__ vecs, int nvec,
+    const C2<R>* __restrict__ T, int ncol, const ColDesc* __restrict__ cols, int ndesc, int nH,
+    FftPlan1D plan, const C2<R>* __restrict__ twg, const double2* __restrict__ vecs, int nvec,
     int npw, const double* __restrict__ kinw, const double* __restrict__ g2, double scale,
     double2* __restrict__ Y, int CH) {
-  extern __shared__ double2 smem[];
+  extern __shared__ char smem_raw[];
+  C2<R>* smem = reinterpret_cast<C2<R>*>(smem_raw);
   const int N3 = plan.n;
-  double2* tw = smem;
-  double2* buf = smem + N3;
+  C2<R>* tw = smem;
+  C2<R>* buf = smem + N3;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int pair = blockIdx.y;
   const int j0 = blockIdx.x * CH;
@@ -270,7 +310,7 @@ __global__ void __launch_bounds__(512) k_zpass_fwd(
     const int z = idx / CH, c = idx - z * CH;
     const int j = j0 + c;
     const size_t row = ((size_t)pair * N3 + z) * ncol;
-    double2 s = make_double2(0.0, 0.0), m = make_double2(0.0, 0.0);
+    C2<R> s = mk<R>(0, 0), m = mk<R>(0, 0);
     if (j < ndesc) {
       s = T[row + j];
       if (j > 0) m = T[row + nH + j];
@@ -279,7 +319,7 @@ __global__ void __launch_bounds__(512) k_zpass_fwd(
     buf[(2 * c + 1) * N3 + z] = m;
   }
   __syncthreads();
-  fft_lines<MAXP>(buf, plan, 2 * CH, Strided{N3}, 1, tw, -1);
+  fft_lines<R, MAXP>(buf, plan, 2 * CH, Strided{N3}, 1, tw, -1);
   const double w1 = kinw[n1];
   const double w2 = has2 ? kinw[n2] : 0.0;
   for (int idx = tid; idx < CH * N3; idx += nthr) {
@@ -290,17 +330,17 @@ __global__ void __launch_bounds__(512) k_zpass_fwd(
     if (e > d.lmax - d.lmin) continue;
     const int l = d.lmin + e;
     const int g = d.base + e;
-    const double2 F = buf[(2 * c) * N3 + wrap(l, N3)];
-    const double2 Fm = (j == 0) ? buf[(2 * c) * N3 + wrap(-l, N3)] : buf[(2 * c + 1) * N3 + wrap(-l, N3)];
-    const double2 y1 = make_double2(0.5 * (F.x + Fm.x), 0.5 * (F.y - Fm.y));
-    const double2 dd = make_double2(0.5 * (F.x - Fm.x), 0.5 * (F.y + Fm.y));
-    const double2 y2 = make_double2(dd.y, -dd.x);
+    const C2<R> F = buf[(2 * c) * N3 + wrap(l, N3)];
+    const C2<R> Fm = (j == 0) ? buf[(2 * c) * N3 + wrap(-l, N3)] : buf[(2 * c + 1) * N3 + wrap(-l, N3)];
+    const double y1x = 0.5 * ((double)F.x + (double)Fm.x), y1y = 0.5 * ((double)F.y - (double)Fm.y);
+    const double ddx = 0.5 * ((double)F.x - (double)Fm.x), ddy = 0.5 * ((double)F.y + (double)Fm.y);
     const double k = g2[g];
     const double2 a = vecs[(size_t)n1 * npw + g];
-    Y[(size_t)n1 * npw + g] = make_double2(scale * y1.x + w1 * k * a.x, scale * y1.y + w1 * k * a.y);
+    Y[(size_t)n1 * npw + g] = make_double2(scale * y1x + w1 * k * a.x, scale * y1y + w1 * k * a.y);
     if (has2) {
       const double2 b = vecs[(size_t)n2 * npw + g];
-      Y[(size_t)n2 * npw + g] = make_double2(scale * y2.x + w2 * k * b.x, scale * y2.y + w2 * k * b.y);
+      // (F - conj Fm) / (2i)
+      Y[(size_t)n2 * npw + g] = make_double2(scale * ddy + w2 * k * b.x, -scale * ddx + w2 * k * b.y);
     }
   }
 }
@@ -313,20 +353,21 @@ struct PlaneGeom {
   FftPlan1D p1, p2;
 };
 
-template <int MAXP>
+template <typename R, int MAXP>
 __global__ void __launch_bounds__(512) k_plane_apply(
-    double2* __restrict__ T, const int32_t* __restrict__ colpos, PlaneGeom g,
-    const double2* __restrict__ tw1g, const double2* __restrict__ tw2g,
-    const double* __restrict__ pot, int npot, size_t ntot, const int32_t* __restrict__ potidx,
+    C2<R>* __restrict__ T, const int32_t* __restrict__ colpos, PlaneGeom g,
+    const C2<R>* __restrict__ tw1g, const C2<R>* __restrict__ tw2g,
+    const R* __restrict__ pot, int npot, size_t ntot, const int32_t* __restrict__ potidx,
     int nvec, int nQ, double* __restrict__ Qpart, int npairs, int per_chunk) {
   // The workgroup owns one z-plane and a chunk of band pairs.  The npot (<= 3)
   // potentials of its plane points stay in registers across the pairs; nQ > 0
   // also accumulates <n|V^X|n> for X < nQ from the same registers.
-  extern __shared__ double2 smem[];
-  double2* tw1 = smem;
-  double2* tw2 = smem + g.N1;
-  double2* plane = smem + g.N1 + g.N2;
-  double* red = reinterpret_cast<double*>(plane + g.N1 * g.PS);
+  extern __shared__ char smem_raw[];
+  C2<R>* smem = reinterpret_cast<C2<R>*>(smem_raw);
+  C2<R>* tw1 = smem;
+  C2<R>* tw2 = smem + g.N1;
+  C2<R>* plane = smem + g.N1 + g.N2;
+  double* red = reinterpret_cast<double*>(plane + g.N1 * g.PS + 1);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int z = blockIdx.x, chunk = blockIdx.y;
   const int np2 = g.N1 * g.N2;
@@ -334,37 +375,37 @@ __global__ void __launch_bounds__(512) k_plane_apply(
   const size_t zoff = (size_t)z * np2;
   for (int i = tid; i < g.N1; i += nthr) tw1[i] = tw1g[i];
   for (int i = tid; i < g.N2; i += nthr) tw2[i] = tw2g[i];
-  double vr[3][MAXP];
+  R vr[3][MAXP];
 #pragma unroll
   for (int X = 0; X < 3; ++X)
 #pragma unroll
     for (int i = 0; i < MAXP; ++i) {
       const int pt = tid + i * nthr;
-      vr[X][i] = (X < npot && pt < np2) ? pot[(size_t)X * ntot + zoff + pt] : 0.0;
+      vr[X][i] = (X < npot && pt < np2) ? pot[(size_t)X * ntot + zoff + pt] : (R)0;
     }
   const int p0 = chunk * per_chunk;
   const int p1 = min(npairs, p0 + per_chunk);
   for (int pair = p0; pair < p1; ++pair) {
     const int n1 = 2 * pair, n2 = 2 * pair + 1;
-    for (int i = tid; i < g.N1 * g.PS; i += nthr) plane[i] = make_double2(0.0, 0.0);
+    for (int i = tid; i < g.N1 * g.PS; i += nthr) plane[i] = mk<R>(0, 0);
     __syncthreads();
-    double2* Tz = T + ((size_t)pair * g.N3 + z) * g.ncol;
+    C2<R>* Tz = T + ((size_t)pair * g.N3 + z) * g.ncol;
     for (int col = tid; col < g.ncol; col += nthr)
       plane[colpos[2 * col] * g.PS + colpos[2 * col + 1]] = Tz[col];
     __syncthreads();
-    fft_lines<MAXP>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, +1);
-    fft_lines<MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, +1);
+    fft_lines<R, MAXP>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, +1);
+    fft_lines<R, MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, +1);
     const int s1 = potidx[n1];
     const int s2 = n2 < nvec ? potidx[n2] : -1;
-    double q1[3] = {0, 0, 0}, q2[3] = {0, 0, 0};
+    R q1[3] = {0, 0, 0}, q2[3] = {0, 0, 0};
 #pragma unroll
     for (int i = 0; i < MAXP; ++i) {
       const int pt = tid + i * nthr;
       if (pt < np2) {
         const int x = pt / g.N2, y = pt - x * g.N2;
-        double2& w = plane[x * g.PS + y];
-        const double u1 = w.x, u2 = w.y;
-        double a = 0.0, b = 0.0;
+        C2<R>& w = plane[x * g.PS + y];
+        const R u1 = w.x, u2 = w.y;
+        R a = 0, b = 0;
 #pragma unroll
         for (int X = 0; X < 3; ++X) {
           if (X < nQ) {
@@ -374,12 +415,12 @@ __global__ void __launch_bounds__(512) k_plane_apply(
           if (s1 == X) a = vr[X][i];
           if (s2 == X) b = vr[X][i];
         }
-        w = make_double2(a * u1, b * u2);
+        w = mk<R>(a * u1, b * u2);
       }
     }
     __syncthreads();
-    fft_lines<MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, -1);
-    fft_lines<MAXP>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, -1);
+    fft_lines<R, MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, -1);
+    fft_lines<R, MAXP>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, -1);
     for (int col = tid; col < g.ncol; col += nthr)
       Tz[col] = plane[colpos[2 * col] * g.PS + colpos[2 * col + 1]];
     if (nQ > 0) {
@@ -387,8 +428,8 @@ __global__ void __launch_bounds__(512) k_plane_apply(
 #pragma unroll
       for (int X = 0; X < 3; ++X) {
         if (X < nQ) {
-          const double t1 = wave_sum(q1[X]);
-          const double t2 = wave_sum(q2[X]);
+          const double t1 = wave_sum((double)q1[X]);
+          const double t2 = wave_sum((double)q2[X]);
           if (lane == 0) {
             red[(2 * X) * nw + wid] = t1;
             red[(2 * X + 1) * nw + wid] = t2;
@@ -411,38 +452,39 @@ __global__ void __launch_bounds__(512) k_plane_apply(
 // ---------------------------------------------------------------------------
 // plane pass for densities: G -> r only, accumulate per-shell |u|^2
 // ---------------------------------------------------------------------------
-template <int MAXP>
+template <typename R, int MAXP>
 __global__ void __launch_bounds__(512) k_plane_density(
-    const double2* __restrict__ T, const int32_t* __restrict__ colpos, PlaneGeom g,
-    const double2* __restrict__ tw1g, const double2* __restrict__ tw2g,
+    const C2<R>* __restrict__ T, const int32_t* __restrict__ colpos, PlaneGeom g,
+    const C2<R>* __restrict__ tw1g, const C2<R>* __restrict__ tw2g,
     const int32_t* __restrict__ band_shell, int nvec, int nsocc, int npairs, int per_chunk,
     double* __restrict__ rho_part, size_t ntot) {
-  extern __shared__ double2 smem[];
-  double2* tw1 = smem;
-  double2* tw2 = smem + g.N1;
-  double2* plane = smem + g.N1 + g.N2;
+  extern __shared__ char smem_raw[];
+  C2<R>* smem = reinterpret_cast<C2<R>*>(smem_raw);
+  C2<R>* tw1 = smem;
+  C2<R>* tw2 = smem + g.N1;
+  C2<R>* plane = smem + g.N1 + g.N2;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int z = blockIdx.x, chunk = blockIdx.y;
   const int np2 = g.N1 * g.N2;
   const int nh = 2 * g.hmax + 1;
   for (int i = tid; i < g.N1; i += nthr) tw1[i] = tw1g[i];
   for (int i = tid; i < g.N2; i += nthr) tw2[i] = tw2g[i];
-  double acc[3][MAXP];
+  R acc[3][MAXP];
 #pragma unroll
   for (int X = 0; X < 3; ++X)
 #pragma unroll
-    for (int i = 0; i < MAXP; ++i) acc[X][i] = 0.0;
+    for (int i = 0; i < MAXP; ++i) acc[X][i] = 0;
   const int p0 = chunk * per_chunk;
   const int p1 = min(npairs, p0 + per_chunk);
   for (int pair = p0; pair < p1; ++pair) {
-    for (int i = tid; i < g.N1 * g.PS; i += nthr) plane[i] = make_double2(0.0, 0.0);
+    for (int i = tid; i < g.N1 * g.PS; i += nthr) plane[i] = mk<R>(0, 0);
     __syncthreads();
-    const double2* Tz = T + ((size_t)pair * g.N3 + z) * g.ncol;
+    const C2<R>* Tz = T + ((size_t)pair * g.N3 + z) * g.ncol;
     for (int col = tid; col < g.ncol; col += nthr)
       plane[colpos[2 * col] * g.PS + colpos[2 * col + 1]] = Tz[col];
     __syncthreads();
-    fft_lines<MAXP>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, +1);
-    fft_lines<MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, +1);
+    fft_lines<R, MAXP>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, +1);
+    fft_lines<R, MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, +1);
     const int s1 = band_shell[2 * pair];
     const int s2 = (2 * pair + 1 < nvec) ? band_shell[2 * pair + 1] : 99;
 #pragma unroll
@@ -450,10 +492,10 @@ __global__ void __launch_bounds__(512) k_plane_density(
       const int pt = tid + i * nthr;
       if (pt < np2) {
         const int x = pt / g.N2, y = pt - x * g.N2;
-        const double2 w = plane[x * g.PS + y];
+        const C2<R> w = plane[x * g.PS + y];
 #pragma unroll
         for (int X = 0; X < 3; ++X)
-          acc[X][i] += (s1 == X ? w.x * w.x : 0.0) + (s2 == X ? w.y * w.y : 0.0);
+          acc[X][i] += (s1 == X ? w.x * w.x : (R)0) + (s2 == X ? w.y * w.y : (R)0);
       }
     }
     __syncthreads();
@@ -466,20 +508,21 @@ __global__ void __launch_bounds__(512) k_plane_density(
 #pragma unroll
       for (int i = 0; i < MAXP; ++i) {
         const int pt = tid + i * nthr;
-        if (pt < np2) out[pt] = acc[X][i];
+        if (pt < np2) out[pt] = (double)acc[X][i];
       }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// full-grid complex 3D FFT on [z][x][y] data (Hartree, V_ext)
+// full-grid complex 3D FFT on [z][x][y] data (Hartree, V_ext, forces), FP64
 // ---------------------------------------------------------------------------
 template <int MAXP>
 __global__ void __launch_bounds__(512) k_fft_planes(double2* __restrict__ data, PlaneGeom g,
                                                     const double2* __restrict__ tw1g,
                                                     const double2* __restrict__ tw2g, int sign) {
-  extern __shared__ double2 smem[];
+  extern __shared__ char smem_raw[];
+  double2* smem = reinterpret_cast<double2*>(smem_raw);
   double2* tw1 = smem;
   double2* tw2 = smem + g.N1;
   double2* plane = smem + g.N1 + g.N2;
@@ -494,8 +537,8 @@ __global__ void __launch_bounds__(512) k_fft_planes(double2* __restrict__ data, 
     plane[x * g.PS + y] = d[pt];
   }
   __syncthreads();
-  fft_lines<MAXP>(plane, g.p2, g.N1, Strided{g.PS}, 1, tw2, sign);
-  fft_lines<MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, sign);
+  fft_lines<double, MAXP>(plane, g.p2, g.N1, Strided{g.PS}, 1, tw2, sign);
+  fft_lines<double, MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, sign);
   for (int pt = tid; pt < np2; pt += nthr) {
     const int x = pt / g.N2, y = pt - x * g.N2;
     d[pt] = plane[x * g.PS + y];
@@ -506,7 +549,8 @@ template <int MAXP>
 __global__ void __launch_bounds__(512) k_fft_zlines(double2* __restrict__ data, int np2,
                                                     FftPlan1D plan, const double2* __restrict__ twg,
                                                     int CH, int sign) {
-  extern __shared__ double2 smem[];
+  extern __shared__ char smem_raw[];
+  double2* smem = reinterpret_cast<double2*>(smem_raw);
   const int N3 = plan.n;
   double2* tw = smem;
   double2* buf = smem + N3;
@@ -518,7 +562,7 @@ __global__ void __launch_bounds__(512) k_fft_zlines(double2* __restrict__ data, 
     buf[c * N3 + z] = (p0 + c < np2) ? data[(size_t)z * np2 + p0 + c] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  fft_lines<MAXP>(buf, plan, CH, Strided{N3}, 1, tw, sign);
+  fft_lines<double, MAXP>(buf, plan, CH, Strided{N3}, 1, tw, sign);
   for (int idx = tid; idx < CH * N3; idx += nthr) {
     const int z = idx / CH, c = idx - z * CH;
     if (p0 + c < np2) data[(size_t)z * np2 + p0 + c] = buf[c * N3 + z];
@@ -556,8 +600,8 @@ PlaneGeom geom(const Ctx& c) {
   return g;
 }
 
-size_t plane_lds(const Ctx& c, int nthr, int nQ) {
-  size_t b = (size_t)(c.N[0] + c.N[1] + c.N[0] * (c.N[1] + 1)) * sizeof(double2);
+size_t plane_lds(const Ctx& c, int nthr, size_t elem) {
+  size_t b = (size_t)(c.N[0] + c.N[1] + c.N[0] * (c.N[1] + 1) + 1) * elem;
   b += (size_t)2 * kMaxShell * (nthr / 64) * sizeof(double);
   return b;
 }
@@ -576,132 +620,159 @@ void allow_lds(K kernel, size_t bytes) {
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
 }
 
-}  // namespace
-
-#define ROKS_DISPATCH_MAXP(mp, KER, ...)                      \
-  switch (mp) {                                               \
-    case 8: KER<8>(__VA_ARGS__); break;                       \
-    case 16: KER<16>(__VA_ARGS__); break;                     \
-    case 24: KER<24>(__VA_ARGS__); break;                     \
-    default: KER<32>(__VA_ARGS__); break;                     \
-  }
-
-template <int MP>
-static void run_zpass_bwd(Ctx& c, const double2* vecs, int nvec, double2* T, int npairs, int CH) {
-  const int nthr = kZThreads;
-  const size_t lds = (size_t)(c.N[2] + 2 * CH * c.N[2]) * sizeof(double2);
-  allow_lds(k_zpass_bwd<MP>, lds);
-  dim3 grid(cdiv(c.nH + 1, CH), npairs);
-  hipLaunchKernelGGL(k_zpass_bwd<MP>, grid, dim3(nthr), lds, c.stream, vecs, nvec, c.npw, c.d_cols,
-                     c.nH + 1, c.nH, c.plan[2], c.d_tw[2], T, c.ncol, CH);
-  ROKS_HIP(hipGetLastError());
-}
+template <typename R>
+const C2<R>* twiddles(const Ctx& c, int d);
+template <>
+const double2* twiddles<double>(const Ctx& c, int d) { return c.d_tw[d]; }
+template <>
+const float2* twiddles<float>(const Ctx& c, int d) { return c.d_tw32[d]; }
 
 // algorithmic HBM bytes: the column buffer of all pairs, the band arrays and
 // real grids each move once per launch
-static double colbuf_bytes(const Ctx& c, int npairs) {
-  return (double)npairs * c.N[2] * c.ncol * sizeof(double2);
+double colbuf_bytes(const Ctx& c, int npairs) {
+  return (double)npairs * c.N[2] * c.ncol * (c.prec == ROKS_FP32 ? sizeof(float2) : sizeof(double2));
 }
-static double band_bytes(const Ctx& c, int nvec) { return (double)nvec * c.npw * sizeof(double2); }
-static double grid_bytes(const Ctx& c) { return (double)c.ntot * sizeof(double); }
-
-void launch_zpass_bwd(Ctx& c, const double2* vecs, int nvec, double2* T, int npairs) {
-  KernelTimer kt(c, "zpass_bwd", band_bytes(c, nvec) + colbuf_bytes(c, npairs));
-  const int CH = zchunk(c);
-  const int mp = pick_maxp(needed_points(2 * CH * c.N[2], kZThreads));
-  ROKS_DISPATCH_MAXP(mp, run_zpass_bwd, c, vecs, nvec, T, npairs, CH);
+double band_bytes(const Ctx& c, int nvec) { return (double)nvec * c.npw * sizeof(double2); }
+double grid_bytes(const Ctx& c) {
+  return (double)c.ntot * (c.prec == ROKS_FP32 ? sizeof(float) : sizeof(double));
 }
 
-template <int MP>
-static void run_zpass_fwd(Ctx& c, const double2* T, int npairs, const double2* vecs, int nvec,
-                          const double* kinw, double2* Y, int CH) {
-  const size_t lds = (size_t)(c.N[2] + 2 * CH * c.N[2]) * sizeof(double2);
-  allow_lds(k_zpass_fwd<MP>, lds);
+}  // namespace
+
+#define ROKS_DISPATCH_MAXP(R, mp, KER, ...)               \
+  switch (mp) {                                           \
+    case 8: KER<R, 8>(__VA_ARGS__); break;                \
+    case 16: KER<R, 16>(__VA_ARGS__); break;              \
+    case 24: KER<R, 24>(__VA_ARGS__); break;              \
+    default: KER<R, 32>(__VA_ARGS__); break;              \
+  }
+
+template <typename R, int MP>
+static void run_zpass_bwd(Ctx& c, const double2* vecs, int nvec, void* T, int npairs, int CH) {
+  const size_t lds = (size_t)(c.N[2] + 2 * CH * c.N[2]) * sizeof(C2<R>);
+  allow_lds(k_zpass_bwd<R, MP>, lds);
   dim3 grid(cdiv(c.nH + 1, CH), npairs);
-  hipLaunchKernelGGL(k_zpass_fwd<MP>, grid, dim3(kZThreads), lds, c.stream, T, c.ncol, c.d_cols, c.nH + 1,
-                     c.nH, c.plan[2], c.d_tw[2], vecs, nvec, c.npw, kinw, c.d_g2,
-                     1.0 / (double)c.ntot, Y, CH);
+  hipLaunchKernelGGL((k_zpass_bwd<R, MP>), grid, dim3(kZThreads), lds, c.stream, vecs, nvec, c.npw,
+                     c.d_cols, c.nH + 1, c.nH, c.plan[2], twiddles<R>(c, 2),
+                     reinterpret_cast<C2<R>*>(T), c.ncol, CH);
   ROKS_HIP(hipGetLastError());
 }
 
-void launch_zpass_fwd(Ctx& c, const double2* T, int npairs, const double2* vecs, int nvec,
+void launch_zpass_bwd(Ctx& c, const double2* vecs, int nvec, void* T, int npairs) {
+  KernelTimer kt(c, "zpass_bwd", band_bytes(c, nvec) + colbuf_bytes(c, npairs));
+  const int CH = zchunk(c);
+  const int mp = pick_maxp(needed_points(2 * CH * c.N[2], kZThreads));
+  if (c.prec == ROKS_FP32) {
+    ROKS_DISPATCH_MAXP(float, mp, run_zpass_bwd, c, vecs, nvec, T, npairs, CH);
+  } else {
+    ROKS_DISPATCH_MAXP(double, mp, run_zpass_bwd, c, vecs, nvec, T, npairs, CH);
+  }
+}
+
+template <typename R, int MP>
+static void run_zpass_fwd(Ctx& c, const void* T, int npairs, const double2* vecs, int nvec,
+                          const double* kinw, double2* Y, int CH) {
+  const size_t lds = (size_t)(c.N[2] + 2 * CH * c.N[2]) * sizeof(C2<R>);
+  allow_lds(k_zpass_fwd<R, MP>, lds);
+  dim3 grid(cdiv(c.nH + 1, CH), npairs);
+  hipLaunchKernelGGL((k_zpass_fwd<R, MP>), grid, dim3(kZThreads), lds, c.stream,
+                     reinterpret_cast<const C2<R>*>(T), c.ncol, c.d_cols, c.nH + 1, c.nH, c.plan[2],
+                     twiddles<R>(c, 2), vecs, nvec, c.npw, kinw, c.d_g2, 1.0 / (double)c.ntot, Y, CH);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_zpass_fwd(Ctx& c, const void* T, int npairs, const double2* vecs, int nvec,
                       const double* kinw, double2* Y) {
   KernelTimer kt(c, "zpass_fwd", colbuf_bytes(c, npairs) + 2.0 * band_bytes(c, nvec));
   const int CH = zchunk(c);
   const int mp = pick_maxp(needed_points(2 * CH * c.N[2], kZThreads));
-  ROKS_DISPATCH_MAXP(mp, run_zpass_fwd, c, T, npairs, vecs, nvec, kinw, Y, CH);
+  if (c.prec == ROKS_FP32) {
+    ROKS_DISPATCH_MAXP(float, mp, run_zpass_fwd, c, T, npairs, vecs, nvec, kinw, Y, CH);
+  } else {
+    ROKS_DISPATCH_MAXP(double, mp, run_zpass_fwd, c, T, npairs, vecs, nvec, kinw, Y, CH);
+  }
 }
 
-template <int MP>
-static void run_plane_apply(Ctx& c, double2* T, int npairs, const double* pot, int npot,
+template <typename R, int MP>
+static void run_plane_apply(Ctx& c, void* T, int npairs, const void* pot, int npot,
                             const int32_t* potidx, int nvec, double* Qpart, int nQ) {
   const int nthr = plane_threads(c);
-  const size_t lds = plane_lds(c, nthr, nQ);
-  allow_lds(k_plane_apply<MP>, lds);
+  const size_t lds = plane_lds(c, nthr, sizeof(C2<R>));
+  allow_lds(k_plane_apply<R, MP>, lds);
   const int nchunk = std::max(1, std::min(npairs, c.nchunk));
   const int per = cdiv(npairs, nchunk);
   dim3 grid(c.N[2], nchunk);
-  hipLaunchKernelGGL(k_plane_apply<MP>, grid, dim3(nthr), lds, c.stream, T, c.d_colpos, geom(c),
-                     c.d_tw[0], c.d_tw[1], pot, npot, (size_t)c.ntot, potidx, nvec, nQ, Qpart,
-                     npairs, per);
+  hipLaunchKernelGGL((k_plane_apply<R, MP>), grid, dim3(nthr), lds, c.stream,
+                     reinterpret_cast<C2<R>*>(T), c.d_colpos, geom(c), twiddles<R>(c, 0),
+                     twiddles<R>(c, 1), reinterpret_cast<const R*>(pot), npot, (size_t)c.ntot,
+                     potidx, nvec, nQ, Qpart, npairs, per);
   ROKS_HIP(hipGetLastError());
 }
 
-void launch_plane_apply(Ctx& c, double2* T, int npairs, const double* pot, int npot,
+void launch_plane_apply(Ctx& c, void* T, int npairs, const void* pot, int npot,
                         const int32_t* potidx, int nvec, double* Qpart, int nQ) {
   ROKS_CHECK(npot >= 1 && npot <= 3 && nQ <= npot, ROKS_ERR_ARG, "plane pass takes 1..3 potentials");
   KernelTimer kt(c, "plane_apply", 2.0 * colbuf_bytes(c, npairs) + npot * grid_bytes(c));
   const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], plane_threads(c)));
-  ROKS_DISPATCH_MAXP(mp, run_plane_apply, c, T, npairs, pot, npot, potidx, nvec, Qpart, nQ);
+  if (c.prec == ROKS_FP32) {
+    ROKS_DISPATCH_MAXP(float, mp, run_plane_apply, c, T, npairs, pot, npot, potidx, nvec, Qpart, nQ);
+  } else {
+    ROKS_DISPATCH_MAXP(double, mp, run_plane_apply, c, T, npairs, pot, npot, potidx, nvec, Qpart, nQ);
+  }
 }
 
-template <int MP>
-static void run_plane_density(Ctx& c, const double2* T, int npairs, double* rho_part, int nchunk) {
+template <typename R, int MP>
+static void run_plane_density(Ctx& c, const void* T, int npairs, double* rho_part, int nchunk) {
   const int nthr = plane_threads(c);
-  const size_t lds = plane_lds(c, nthr, 0);
-  allow_lds(k_plane_density<MP>, lds);
+  const size_t lds = plane_lds(c, nthr, sizeof(C2<R>));
+  allow_lds(k_plane_density<R, MP>, lds);
   const int per = cdiv(npairs, nchunk);
   dim3 grid(c.N[2], nchunk);
-  hipLaunchKernelGGL(k_plane_density<MP>, grid, dim3(nthr), lds, c.stream, T, c.d_colpos, geom(c),
-                     c.d_tw[0], c.d_tw[1], c.d_band_shell, c.nb, c.nsocc, npairs, per, rho_part,
+  hipLaunchKernelGGL((k_plane_density<R, MP>), grid, dim3(nthr), lds, c.stream,
+                     reinterpret_cast<const C2<R>*>(T), c.d_colpos, geom(c), twiddles<R>(c, 0),
+                     twiddles<R>(c, 1), c.d_band_shell, c.nb, c.nsocc, npairs, per, rho_part,
                      (size_t)c.ntot);
   ROKS_HIP(hipGetLastError());
 }
 
-void launch_plane_density(Ctx& c, const double2* T, int npairs, double* rho_part, int nchunk) {
+void launch_plane_density(Ctx& c, const void* T, int npairs, double* rho_part, int nchunk) {
   KernelTimer kt(c, "plane_density",
-                 colbuf_bytes(c, npairs) + (double)nchunk * c.nsocc * grid_bytes(c));
+                 colbuf_bytes(c, npairs) + (double)nchunk * c.nsocc * c.ntot * sizeof(double));
   const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], plane_threads(c)));
-  ROKS_DISPATCH_MAXP(mp, run_plane_density, c, T, npairs, rho_part, nchunk);
+  if (c.prec == ROKS_FP32) {
+    ROKS_DISPATCH_MAXP(float, mp, run_plane_density, c, T, npairs, rho_part, nchunk);
+  } else {
+    ROKS_DISPATCH_MAXP(double, mp, run_plane_density, c, T, npairs, rho_part, nchunk);
+  }
 }
 
-template <int MP>
+template <typename R, int MP>
 static void run_fft_planes(Ctx& c, double2* data, int sign) {
   const int nthr = plane_threads(c);
-  const size_t lds = plane_lds(c, nthr, 0);
+  const size_t lds = plane_lds(c, nthr, sizeof(double2));
   allow_lds(k_fft_planes<MP>, lds);
   hipLaunchKernelGGL(k_fft_planes<MP>, dim3(c.N[2]), dim3(nthr), lds, c.stream, data, geom(c),
                      c.d_tw[0], c.d_tw[1], sign);
   ROKS_HIP(hipGetLastError());
 }
 
-template <int MP>
+template <typename R, int MP>
 static void run_fft_zlines(Ctx& c, double2* data, int sign, int CH) {
   const size_t lds = (size_t)(c.N[2] + CH * c.N[2]) * sizeof(double2);
   allow_lds(k_fft_zlines<MP>, lds);
   const int np2 = c.N[0] * c.N[1];
-  hipLaunchKernelGGL(k_fft_zlines<MP>, dim3(cdiv(np2, CH)), dim3(kZThreads), lds, c.stream, data, np2,
-                     c.plan[2], c.d_tw[2], CH, sign);
+  hipLaunchKernelGGL(k_fft_zlines<MP>, dim3(cdiv(np2, CH)), dim3(kZThreads), lds, c.stream, data,
+                     np2, c.plan[2], c.d_tw[2], CH, sign);
   ROKS_HIP(hipGetLastError());
 }
 
 void launch_fft3d(Ctx& c, double2* data, int sign) {
   KernelTimer kt(c, "fft3d", 4.0 * c.ntot * sizeof(double2));
   const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], plane_threads(c)));
-  ROKS_DISPATCH_MAXP(mp, run_fft_planes, c, data, sign);
+  ROKS_DISPATCH_MAXP(double, mp, run_fft_planes, c, data, sign);
   const int CH = 2 * zchunk(c);
   const int mz = pick_maxp(needed_points(CH * c.N[2], kZThreads));
-  ROKS_DISPATCH_MAXP(mz, run_fft_zlines, c, data, sign, CH);
+  ROKS_DISPATCH_MAXP(double, mz, run_fft_zlines, c, data, sign, CH);
 }
 
 }  // namespace roks

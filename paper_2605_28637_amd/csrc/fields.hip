@@ -109,6 +109,12 @@ __global__ void k_vext_G(Lattice L, const AtomP* __restrict__ atoms, int natoms,
   }
 }
 
+__global__ void k_to_float(const double* __restrict__ in, float* __restrict__ out, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    out[i] = (float)in[i];
+}
+
 __global__ void k_take_real(const double2* __restrict__ in, double* __restrict__ out, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)
@@ -543,6 +549,11 @@ void launch_xc_potentials(Ctx& c, double* part, int nblocks) {
 
 void launch_reduce_columns(Ctx& c, const double* part, int nrows, int ncols, double* out) {
   hipLaunchKernelGGL(k_reduce_columns, dim3(ncols), dim3(256), 0, c.stream, part, nrows, ncols, out);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_to_float(Ctx& c, const double* in, float* out, size_t n) {
+  hipLaunchKernelGGL(k_to_float, dim3(grid_blocks(n)), dim3(256), 0, c.stream, in, out, n);
   ROKS_HIP(hipGetLastError());
 }
 

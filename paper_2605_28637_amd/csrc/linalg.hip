@@ -295,47 +295,50 @@ __global__ void k_norm1(const double* A, int n, double* out) {
 // Cholesky G = L L^T and L^-1 (lower), one workgroup, global memory.
 // flag[0] = 1 if G is not numerically positive definite.
 // --------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_cholesky_inverse(const double* __restrict__ G, int n,
-                                                          double* __restrict__ Lw,
-                                                          double* __restrict__ Linv,
-                                                          int32_t* __restrict__ flag) {
-  __shared__ double diag;
+__global__ void __launch_bounds__(1024) k_cholesky_inverse(const double* __restrict__ G, int n,
+                                                           double* __restrict__ A,
+                                                           double* __restrict__ X,
+                                                           int32_t* __restrict__ flag) {
+  // right-looking factorisation in global memory (A := L) with the forward
+  // elimination of L X = I fused in, as in the LDS variant; every step's work
+  // is spread over the workgroup
+  __shared__ int bad;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  if (tid == 0) flag[0] = 0;
-  for (size_t t = tid; t < (size_t)n * n; t += nthr) Lw[t] = 0.0;
+  if (tid == 0) bad = 0;
+  for (size_t t = tid; t < (size_t)n * n; t += nthr) {
+    A[t] = G[t];
+    X[t] = (t / n == t % n) ? 1.0 : 0.0;
+  }
   __syncthreads();
   for (int j = 0; j < n; ++j) {
     if (tid == 0) {
-      const double gjj = G[(size_t)j * n + j];
-      double s = gjj;
-      for (int k = 0; k < j; ++k) s -= Lw[(size_t)j * n + k] * Lw[(size_t)j * n + k];
+      double d = A[(size_t)j * n + j];
       // numerically dependent: less than 1e-12 of the vector's own norm^2 is left
-      if (!(s > 1e-12 * gjj) || !isfinite(s)) {
-        flag[0] = 1;
-        s = 1.0;
+      if (!(d > 1e-12 * G[(size_t)j * n + j]) || !isfinite(d)) {
+        bad = 1;
+        d = 1.0;
       }
-      diag = sqrt(s);
-      Lw[(size_t)j * n + j] = diag;
+      A[(size_t)j * n + j] = sqrt(d);
     }
     __syncthreads();
-    const double d = diag;
-    for (int i = j + 1 + tid; i < n; i += nthr) {
-      double s = G[(size_t)i * n + j];
-      for (int k = 0; k < j; ++k) s -= Lw[(size_t)i * n + k] * Lw[(size_t)j * n + k];
-      Lw[(size_t)i * n + j] = s / d;
+    const double dj = A[(size_t)j * n + j];
+    for (int i = j + 1 + tid; i < n; i += nthr) A[(size_t)i * n + j] /= dj;
+    for (int cc = tid; cc <= j; cc += nthr) X[(size_t)j * n + cc] /= dj;
+    __syncthreads();
+    const int r = n - j - 1, w = j + 1;
+    for (int idx = tid; idx < r * r; idx += nthr) {
+      const int i = j + 1 + idx / r, k = j + 1 + idx % r;
+      if (k <= i) A[(size_t)i * n + k] -= A[(size_t)i * n + j] * A[(size_t)k * n + j];
+    }
+    for (int idx = tid; idx < r * w; idx += nthr) {
+      const int i = j + 1 + idx / w, cc = idx % w;
+      X[(size_t)i * n + cc] -= A[(size_t)i * n + j] * X[(size_t)j * n + cc];
     }
     __syncthreads();
   }
-  // columns of L^-1 by forward substitution, one column per thread
-  for (int col = tid; col < n; col += nthr) {
-    for (int i = 0; i < col; ++i) Linv[(size_t)i * n + col] = 0.0;
-    Linv[(size_t)col * n + col] = 1.0 / Lw[(size_t)col * n + col];
-    for (int i = col + 1; i < n; ++i) {
-      double s = 0.0;
-      for (int k = col; k < i; ++k) s += Lw[(size_t)i * n + k] * Linv[(size_t)k * n + col];
-      Linv[(size_t)i * n + col] = -s / Lw[(size_t)i * n + i];
-    }
-  }
+  for (size_t t = tid; t < (size_t)n * n; t += nthr)
+    if (t % n > t / n) X[t] = 0.0;
+  if (tid == 0) flag[0] = bad;
 }
 
 // Same factorisation for n <= 128 with the matrix resident in LDS,
@@ -673,7 +676,7 @@ void cholesky_inverse(Ctx& c, const double* G, int n, double* Linv, int32_t* fla
     hipLaunchKernelGGL(k_cholesky_inverse_lds, dim3(1), dim3(1024), lds, c.stream, G, n, Linv, flag,
                        inv);
   } else {
-    hipLaunchKernelGGL(k_cholesky_inverse, dim3(1), dim3(256), 0, c.stream, G, n, c.d_m3, Linv, flag);
+    hipLaunchKernelGGL(k_cholesky_inverse, dim3(1), dim3(1024), 0, c.stream, G, n, c.d_m3, Linv, flag);
   }
   ROKS_HIP(hipGetLastError());
 }

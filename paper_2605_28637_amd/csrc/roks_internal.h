@@ -131,6 +131,9 @@ struct Ctx {
   ColDesc* d_cols = nullptr;
   int32_t* d_colpos = nullptr;   // [ncol][2] (h mod N1, k mod N2)
   double2* d_tw[3] = {nullptr, nullptr, nullptr};  // exp(-2 pi i k / N_d)
+  float2* d_tw32[3] = {nullptr, nullptr, nullptr};
+  float* d_vsh32 = nullptr;      // FP32 tier copies of the shell and channel potentials
+  float* d_vloc32 = nullptr;
   double* d_vext = nullptr;      // [N3][N1][N2]
   double2* d_B = nullptr;        // [nproj][npw]
   int32_t* d_proj_atom = nullptr;
@@ -233,15 +236,17 @@ void upload_positions(Ctx& c);
 
 // kernels launchers -----------------------------------------------------------
 // fft.hip
-void launch_zpass_bwd(Ctx& c, const double2* vecs, int nvec, double2* T, int npairs);
+// The column buffer T and the potential grids are in the context's tier
+// (double for ROKS_FP64, float for ROKS_FP32); band vectors are FP64.
+void launch_zpass_bwd(Ctx& c, const double2* vecs, int nvec, void* T, int npairs);
 // pot holds npot (1..3) grids; potidx[n] selects band n's grid (-1: zero);
 // nQ > 0 also accumulates <n|V^X|n> for the first nQ grids into Qpart
-void launch_plane_apply(Ctx& c, double2* T, int npairs, const double* pot, int npot,
+void launch_plane_apply(Ctx& c, void* T, int npairs, const void* pot, int npot,
                         const int32_t* potidx, int nvec, double* Qpart, int nQ);
-void launch_plane_density(Ctx& c, const double2* T, int npairs, double* rho_part, int nchunk);
-void launch_zpass_fwd(Ctx& c, const double2* T, int npairs, const double2* vecs, int nvec,
+void launch_plane_density(Ctx& c, const void* T, int npairs, double* rho_part, int nchunk);
+void launch_zpass_fwd(Ctx& c, const void* T, int npairs, const double2* vecs, int nvec,
                       const double* kinw, double2* Y);
-void launch_fft3d(Ctx& c, double2* data, int sign);
+void launch_fft3d(Ctx& c, double2* data, int sign);  // FP64 full-grid transform
 
 // fields.hip
 void launch_vext(Ctx& c);
@@ -254,6 +259,7 @@ void launch_band_kinetic(Ctx& c, const double2* vecs, int nvec, double* out);
 void launch_nl_energy(Ctx& c, const double* P, double* out);
 void launch_apply_D(Ctx& c, const double* P, const double* w, double* DP);
 void launch_reduce_columns(Ctx& c, const double* part, int nrows, int ncols, double* out);
+void launch_to_float(Ctx& c, const double* in, float* out, size_t n);
 void launch_reduce_strided(Ctx& c, const double* part, int nouter, int ninner, int ncols,
                            double scale, double* out);
 void launch_local_force(Ctx& c, const double2* rhoG, double* out_part, int nblk);

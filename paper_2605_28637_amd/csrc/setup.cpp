@@ -113,7 +113,8 @@ void build_problem(Ctx& c, const roks_system* s) {
   }
   ROKS_CHECK(s->xc == ROKS_XC_PW92 || s->xc == ROKS_XC_X, ROKS_ERR_ARG, "unknown xc");
   c.xc = s->xc;
-  ROKS_CHECK(s->precision == ROKS_FP64, ROKS_ERR_ARG, "precision tier not available");
+  ROKS_CHECK(s->precision == ROKS_FP64 || s->precision == ROKS_FP32, ROKS_ERR_ARG,
+             "precision tier not available");
   c.prec = s->precision;
   c.flags = s->flags;
 

@@ -125,6 +125,11 @@ void compute_potentials(Ctx& c, const double2* orb, roks_energies* e) {
   const int nblk = xc_blocks(c);
   launch_xc_potentials(c, c.d_part, nblk);
   launch_reduce_columns(c, c.d_part, nblk, 6, c.d_red);
+  if (c.prec == ROKS_FP32) {
+    // the plane passes of the FP32 tier read FP32 copies of the potentials
+    launch_to_float(c, c.d_vsh, c.d_vsh32, (size_t)c.nsocc * c.ntot);
+    launch_to_float(c, c.d_vloc, c.d_vloc32, (size_t)2 * c.nconf * c.ntot);
+  }
   band_dots(c, orb, orb, nb, 1, c.d_kin);
   if (c.nproj > 0) {
     gemm_wdot(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(orb), K, c.d_P, nb, 1.0, 0.0, true);
@@ -174,7 +179,8 @@ void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bo
     gemm_wdot(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(vecs), K, c.d_dP, nb, 1.0, 0.0, true);
   if (mask == 0) {
     launch_zpass_bwd(c, vecs, nb, c.d_T, c.npairs);
-    launch_plane_apply(c, c.d_T, c.npairs, c.d_vsh, c.nsocc, c.d_potidx, nb, c.d_Qpart,
+    const void* vsh = c.prec == ROKS_FP32 ? (const void*)c.d_vsh32 : (const void*)c.d_vsh;
+    launch_plane_apply(c, c.d_T, c.npairs, vsh, c.nsocc, c.d_potidx, nb, c.d_Qpart,
                        want_Q ? c.nsocc : 0);
     launch_zpass_fwd(c, c.d_T, c.npairs, vecs, nb, c.d_kinw_shell, out);
     if (c.nproj > 0) {
@@ -195,8 +201,9 @@ void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bo
     double2* o = out + (size_t)idx * band;
     launch_zpass_bwd(c, vecs, nb, c.d_T, c.npairs);
     // one potential grid (channel b); row 1 of d_potidx is all zeros
-    launch_plane_apply(c, c.d_T, c.npairs, c.d_vloc + (size_t)b * c.ntot, 1, c.d_potidx + nb, nb,
-                       c.d_Qpart, 0);
+    const void* vl = c.prec == ROKS_FP32 ? (const void*)(c.d_vloc32 + (size_t)b * c.ntot)
+                                         : (const void*)(c.d_vloc + (size_t)b * c.ntot);
+    launch_plane_apply(c, c.d_T, c.npairs, vl, 1, c.d_potidx + nb, nb, c.d_Qpart, 0);
     launch_zpass_fwd(c, c.d_T, c.npairs, vecs, nb, c.d_ones, o);
     if (c.nproj > 0) {
       launch_apply_D(c, c.d_dP, nullptr, c.d_DP);

@@ -1,0 +1,57 @@
+"""The rocksalt oxide-vacancy supercell at full size (a = 8 bohr, 3x3x3
+conventional cells, 215 atoms, 96^3 grid, 28 889 stored plane waves, 1 720
+projectors, 432 bands): energies of both configurations over all bands, and
+F^n|n> on sampled bands (every band class: closed, both open, virtual, and
+the last closed band of an odd/even pair), which the oracle computes one by
+one.  FP64 at 1e-10, the FP32 tier at 2e-6 (relative)."""
+import numpy as np
+import pytest
+
+from helpers import SphereMap, ensure_built, rel
+from oracle import roks as orc
+from paper_2605_28637_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SAMPLE = [0, 1, 213, 427, 428, 429, 430, 431]
+
+
+@pytest.fixture(scope="module")
+def oxide():
+    s = inputs.oxide_vacancy()
+    print("building oracle model", flush=True)
+    m = orc.Model(s)
+    psi = orc.orthonormalize(inputs.random_coefficients(m.miller, m.cell, m.nb, s["seed"]))
+    print("oracle potentials", flush=True)
+    pot = orc.potentials(m, psi)
+    pot.u = None  # release the real-space orbitals
+    ref = {}
+    for n in SAMPLE:
+        X = m.band_shell[n]
+        ref[n] = (np.zeros(m.npw, complex) if m.shell_virtual[X]
+                  else orc.apply_shell_operator(m, pot, X, psi[n:n + 1])[0])
+    print("oracle reference ready", flush=True)
+    return s, m, pot, ref
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 2e-6)])
+def test_oxide_energies_and_sampled_apply(oxide, precision, tol):
+    rb = ensure_built()
+    s, m, pot, ref = oxide
+    print("gpu precision", precision, flush=True)
+    g = rb.Roks(s, precision=precision)
+    assert (g.npw, g.nproj, g.nb) == ((m.npw + 1) // 2, 1720, 432)
+    mp = SphereMap(g.miller(), m.miller)
+    g.set_coeffs(inputs.random_coefficients(g.miller(), s["cell"], g.nb, s["seed"]), True)
+    e, _, _ = g.energy_gradient()
+    scale = max(abs(v) for t in pot.terms.values() for v in t)
+    assert abs(e["E"] - pot.E) < tol * scale
+    np.testing.assert_allclose(e["E_L"], pot.E_L, rtol=0, atol=tol * scale)
+    Y = g.apply_h()
+    for n in SAMPLE:
+        got = mp.to_full(Y[n])[0]
+        if np.linalg.norm(ref[n]) == 0:
+            assert np.abs(got).max() == 0
+        else:
+            assert rel(got, ref[n]) < tol, n
+    g.close()
