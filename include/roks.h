@@ -107,7 +107,7 @@ typedef struct {
  * {0, 1}; bands must be ordered closed shell, open shells, virtual (the
  * shells are the groups of identical occupation patterns, Sec. II A). */
 typedef struct {
-  double cell[3][3];  /* rows a1, a2, a3 (bohr); must be orthogonal        */
+  double cell[3][3];  /* rows a1, a2, a3 (bohr); non-singular               */
   double ecut;        /* Ha, sphere |G|^2/2 <= ecut                        */
   int32_t grid[3];    /* FFT grid; every size of the form 2^a 3^b 5^c <= 128 */
   int32_t natoms;
@@ -148,6 +148,9 @@ typedef struct {
   int32_t stalled;     /* no decrease found at rounding level: no move      */
   int32_t evaluations; /* trial-energy evaluations in the line search       */
   int32_t iteration;
+  int32_t learned;     /* the step used the attached network's rescaling    */
+  int32_t fallback;    /* the learned direction failed; the step was redone
+                          with the plain Teter preconditioner, beta = 0     */
 } roks_step_info;
 
 /* Build a context: validate the system, build the plane-wave sphere and FFT
@@ -237,6 +240,82 @@ roks_status roks_synchronize(roks_ctx ctx);
 roks_status roks_timing_enable(roks_ctx ctx, int32_t enable);
 roks_status roks_timing_read(roks_ctx ctx, const char* kernel, double* total_ms,
                              int32_t* launches, double* bytes, double* flops);
+
+/* ------------------------------------------------------------------------
+ * Learned rescaling of the Teter preconditioner.  Not part of the paper: it
+ * modifies K of Eq. prec_k to s K, p_I = (1 - P)(s K g_I), with
+ * s = exp(2 tanh(o)) in [e^-2, e^2] (K stays negative definite) and o the
+ * output of a 3-64-64-1 network with GELU activations (erf form).  The
+ * network sees, for band n and one distinct |G|^2 ("G shell"), the features
+ *   x = (log(1 + (|G|^2/2)/E_ref,n), log <n|T|n>, log ||g_I,n||),
+ * E_ref,n = 1.5 <g_n|T|g_n>/<g_n|g_n>, and its factor is shared by every G
+ * of the shell.  Parameters (ROKS_MLP_PARAMS floats, flat, row-major):
+ *   W1[64][3], b1[64], W2[64][64], b2[64], w3[64], b3.
+ * The library keeps FP32 master parameters and evaluates with their BF16
+ * rounding (nearest, ties to even); activations and sums are FP32.
+ *
+ * Training pairs: roks_record() makes the following roks_pcg_step calls keep
+ * the iterate psi_i, the plain Teter K g_I and the features.  Once converged,
+ * roks_mlp_collect() takes the context's orbitals as psi_inf, aligns them to
+ * each recorded psi_i within every occupation shell by the orthogonal polar
+ * factor Q of O_mn = <psi_inf_m|psi_i,n> (psi_inf'_n = sum_m Q_mn psi_inf_m),
+ * forms the correction delta_n = (1 - P_i) psi_inf'_n and stores, for each
+ * occupied band with a usable gradient and each G shell k, the features and
+ * the moments alpha = <Kg|delta>_k, beta = <Kg|Kg>_k, gamma = <delta|delta>_k
+ * (full-sphere sums restricted to the shell).  The loss of a band is
+ * 1 - A^2/(B C), A = sum_k s_k alpha_k, B = sum_k s_k^2 beta_k,
+ * C = sum_k gamma_k: one minus the squared cosine between s K g_I and the
+ * correction (scale free: the line search sets the length), averaged over
+ * the bands with B, C > 0.  Training minimises it with Adam (beta1 = 0.9,
+ * beta2 = 0.999, eps = 1e-8, bias-corrected).
+ *
+ * A network's calls are ordered on its stream and synchronise it before
+ * returning; a network attached to contexts must not be trained while their
+ * steps run.  Errors as for contexts; roks_mlp_last_error gives the message.
+ * ------------------------------------------------------------------------ */
+#define ROKS_MLP_PARAMS 4481
+typedef struct roks_mlp_s* roks_mlp;
+
+/* theta: initial parameters [ROKS_MLP_PARAMS] (copied), or NULL for the
+ * library's seeded initialisation (uniform +-1/sqrt(fan_in), the output
+ * layer scaled by 1e-2, b3 = 0; splitmix64 stream from seed).  hip_stream
+ * NULL: the network creates its own. */
+roks_status roks_mlp_create(const float* theta, uint64_t seed, void* hip_stream, roks_mlp* out);
+roks_status roks_mlp_destroy(roks_mlp mlp);
+const char* roks_mlp_last_error(roks_mlp mlp);
+/* Replace the parameters (and reset the Adam moments); read the FP32 master copy. */
+roks_status roks_mlp_set_params(roks_mlp mlp, const float* theta);
+roks_status roks_mlp_get_params(roks_mlp mlp, float* theta);
+/* o for nsamples feature rows x [nsamples][3] (host arrays). */
+roks_status roks_mlp_forward(roks_mlp mlp, const float* x, int64_t nsamples, float* o);
+/* Size of the training set: samples and band segments. */
+roks_status roks_mlp_num_samples(roks_mlp mlp, int64_t* nsamples, int32_t* nbands);
+/* Copy the training set out: x [nsamples][3], moments [3][nsamples] (alpha,
+ * beta, gamma), band_offsets [nbands + 1] (segment of band j is samples
+ * band_offsets[j] .. band_offsets[j+1]-1).  Any pointer may be NULL. */
+roks_status roks_mlp_get_samples(roks_mlp mlp, float* x, double* moments, int32_t* band_offsets);
+roks_status roks_mlp_clear_samples(roks_mlp mlp);
+/* Loss over the training set at the current parameters and, if grad is not
+ * NULL, its gradient [ROKS_MLP_PARAMS].  ROKS_ERR_STATE without samples. */
+roks_status roks_mlp_loss_grad(roks_mlp mlp, double* loss, float* grad);
+/* steps Adam iterations with learning rate lr > 0; loss_history [steps]
+ * (nullable) receives the loss before each update. */
+roks_status roks_mlp_train(roks_mlp mlp, int32_t steps, double lr, double* loss_history);
+
+/* Record every stride-th iterate (iteration count modulo stride == 0) of the
+ * following roks_pcg_step calls, at most max_records (device memory:
+ * max_records x (2 nbands npw_half 16 B + nbands n_shells 12 B)); 0 stops
+ * recording and drops what is kept. */
+roks_status roks_record(roks_ctx ctx, int32_t max_records, int32_t stride);
+/* Turn the context's records into training samples of mlp with the current
+ * orbitals as psi_inf, then drop the records.  *used counts the records
+ * taken, *skipped those whose polar iteration did not converge (an exactly
+ * singular overlap block). */
+roks_status roks_mlp_collect(roks_mlp mlp, roks_ctx ctx, int32_t* used, int32_t* skipped);
+/* Attach a network to the context (NULL: plain Teter).  Its steps then use
+ * s K and fall back to the plain preconditioner when the learned direction
+ * finds no decrease. */
+roks_status roks_set_mlp(roks_ctx ctx, roks_mlp mlp);
 
 #ifdef __cplusplus
 }

@@ -11,6 +11,10 @@ struct roks_ctx_s {
   roks::Ctx c;
 };
 
+struct roks_mlp_s {
+  roks::Mlp m;
+};
+
 namespace {
 
 thread_local std::string g_create_error;
@@ -28,6 +32,45 @@ roks_status guard(roks_ctx ctx, F&& f) {
     ctx->c.last_error = e.what();
     return ROKS_ERR_HIP;
   }
+}
+
+template <typename F>
+roks_status guard_mlp(roks_mlp mlp, F&& f) {
+  if (!mlp) return ROKS_ERR_ARG;
+  try {
+    f(mlp->m);
+    return ROKS_OK;
+  } catch (const roks::Error& e) {
+    mlp->m.last_error = e.msg;
+    return e.code;
+  } catch (const std::exception& e) {
+    mlp->m.last_error = e.what();
+    return ROKS_ERR_HIP;
+  }
+}
+
+// release one allocation of the context (stream-synchronised)
+void dfree(roks::Ctx& c, void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < c.allocations.size(); ++i)
+    if (c.allocations[i].p == p) {
+      ROKS_HIP(hipStreamSynchronize(c.stream));
+      ROKS_HIP(hipFree(p));
+      c.allocations.erase(c.allocations.begin() + (long)i);
+      return;
+    }
+}
+
+void drop_records(roks::Ctx& c) {
+  dfree(c, c.d_rec_psi);
+  dfree(c, c.d_rec_kg);
+  dfree(c, c.d_rec_feat);
+  dfree(c, c.d_rec_valid);
+  c.d_rec_psi = c.d_rec_kg = nullptr;
+  c.d_rec_feat = nullptr;
+  c.d_rec_valid = nullptr;
+  c.rec_max = 0;
+  c.rec_count = 0;
 }
 
 void upload_bands(roks::Ctx& c, double2* dst, const double* src) {
@@ -302,6 +345,208 @@ roks_status roks_timing_read(roks_ctx ctx, const char* kernel, double* total_ms,
     if (launches) *launches = n;
     if (bytes) *bytes = by;
     if (flops) *flops = fl;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// learned rescaling of the preconditioner
+// ---------------------------------------------------------------------------
+roks_status roks_mlp_create(const float* theta, uint64_t seed, void* hip_stream, roks_mlp* out) {
+  if (!out) return ROKS_ERR_ARG;
+  *out = nullptr;
+  roks_mlp mlp = new (std::nothrow) roks_mlp_s;
+  if (!mlp) return ROKS_ERR_OOM;
+  try {
+    if (hip_stream) {
+      mlp->m.stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+      ROKS_HIP(hipStreamCreate(&mlp->m.stream));
+      mlp->m.own_stream = true;
+    }
+    roks::mlp_init(mlp->m, theta, seed);
+  } catch (const roks::Error& e) {
+    g_create_error = e.msg;
+    roks::mlp_free(mlp->m);
+    delete mlp;
+    return e.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    roks::mlp_free(mlp->m);
+    delete mlp;
+    return ROKS_ERR_HIP;
+  }
+  *out = mlp;
+  return ROKS_OK;
+}
+
+roks_status roks_mlp_destroy(roks_mlp mlp) {
+  if (!mlp) return ROKS_ERR_ARG;
+  roks::mlp_free(mlp->m);
+  delete mlp;
+  return ROKS_OK;
+}
+
+const char* roks_mlp_last_error(roks_mlp mlp) {
+  if (!mlp) return g_create_error.c_str();
+  return mlp->m.last_error.c_str();
+}
+
+roks_status roks_mlp_set_params(roks_mlp mlp, const float* theta) {
+  return guard_mlp(mlp, [&](roks::Mlp& m) {
+    ROKS_CHECK(theta != nullptr, ROKS_ERR_ARG, "theta is NULL");
+    roks::mlp_set_params(m, theta);
+  });
+}
+
+roks_status roks_mlp_get_params(roks_mlp mlp, float* theta) {
+  return guard_mlp(mlp, [&](roks::Mlp& m) {
+    ROKS_CHECK(theta != nullptr, ROKS_ERR_ARG, "theta is NULL");
+    ROKS_HIP(hipMemcpyAsync(theta, m.d_p, ROKS_MLP_PARAMS * sizeof(float), hipMemcpyDeviceToHost,
+                            m.stream));
+    ROKS_HIP(hipStreamSynchronize(m.stream));
+  });
+}
+
+roks_status roks_mlp_forward(roks_mlp mlp, const float* x, int64_t nsamples, float* o) {
+  return guard_mlp(mlp, [&](roks::Mlp& m) {
+    ROKS_CHECK(x && o, ROKS_ERR_ARG, "x and o must not be NULL");
+    ROKS_CHECK(nsamples > 0 && nsamples <= (int64_t)1 << 30, ROKS_ERR_SHAPE,
+               "nsamples must be in 1 .. 2^30");
+    for (int64_t i = 0; i < 3 * nsamples; ++i)
+      ROKS_CHECK(std::isfinite(x[i]), ROKS_ERR_NAN, "non-finite feature");
+    float* dx = nullptr;
+    float* dout = nullptr;
+    ROKS_HIP(hipMalloc(&dx, (size_t)nsamples * 3 * sizeof(float)));
+    if (hipMalloc(&dout, (size_t)nsamples * sizeof(float)) != hipSuccess) {
+      (void)hipFree(dx);
+      throw roks::Error{ROKS_ERR_OOM, "hipMalloc failed"};
+    }
+    hipError_t e = hipMemcpyAsync(dx, x, (size_t)nsamples * 3 * sizeof(float),
+                                  hipMemcpyHostToDevice, m.stream);
+    if (e == hipSuccess) {
+      try {
+        roks::mlp_forward(m, dx, (int)nsamples, dout, nullptr, m.stream);
+      } catch (...) {
+        e = hipErrorLaunchFailure;
+      }
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(o, dout, (size_t)nsamples * sizeof(float), hipMemcpyDeviceToHost, m.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m.stream);
+    (void)hipFree(dx);
+    (void)hipFree(dout);
+    ROKS_HIP(e);
+  });
+}
+
+roks_status roks_mlp_num_samples(roks_mlp mlp, int64_t* nsamples, int32_t* nbands) {
+  return guard_mlp(mlp, [&](roks::Mlp& m) {
+    if (nsamples) *nsamples = m.S;
+    if (nbands) *nbands = m.nseg;
+  });
+}
+
+roks_status roks_mlp_get_samples(roks_mlp mlp, float* x, double* moments, int32_t* band_offsets) {
+  return guard_mlp(mlp, [&](roks::Mlp& m) {
+    if (m.S > 0) {
+      if (x)
+        ROKS_HIP(hipMemcpyAsync(x, m.d_X, (size_t)m.S * 3 * sizeof(float), hipMemcpyDeviceToHost,
+                                m.stream));
+      if (moments)
+        for (int r = 0; r < 3; ++r)
+          ROKS_HIP(hipMemcpyAsync(moments + (size_t)r * m.S, m.d_abg + (size_t)r * m.Scap,
+                                  (size_t)m.S * sizeof(double), hipMemcpyDeviceToHost, m.stream));
+      ROKS_HIP(hipStreamSynchronize(m.stream));
+    }
+    if (band_offsets)
+      std::memcpy(band_offsets, m.band_off.data(), m.band_off.size() * sizeof(int32_t));
+  });
+}
+
+roks_status roks_mlp_clear_samples(roks_mlp mlp) {
+  return guard_mlp(mlp, [&](roks::Mlp& m) { roks::mlp_clear_samples(m); });
+}
+
+roks_status roks_mlp_loss_grad(roks_mlp mlp, double* loss, float* grad) {
+  return guard_mlp(mlp, [&](roks::Mlp& m) {
+    roks::mlp_loss_grad(m, m.d_loss);
+    double h[2] = {0.0, 0.0};
+    ROKS_HIP(hipMemcpyAsync(h, m.d_loss, sizeof(h), hipMemcpyDeviceToHost, m.stream));
+    if (grad)
+      ROKS_HIP(hipMemcpyAsync(grad, m.d_g, ROKS_MLP_PARAMS * sizeof(float), hipMemcpyDeviceToHost,
+                              m.stream));
+    ROKS_HIP(hipStreamSynchronize(m.stream));
+    if (loss) *loss = h[0];
+  });
+}
+
+roks_status roks_mlp_train(roks_mlp mlp, int32_t steps, double lr, double* loss_history) {
+  return guard_mlp(mlp, [&](roks::Mlp& m) {
+    ROKS_CHECK(steps >= 0, ROKS_ERR_ARG, "steps must be >= 0");
+    ROKS_CHECK(lr > 0 && std::isfinite(lr), ROKS_ERR_ARG, "lr must be > 0");
+    ROKS_CHECK(m.S > 0 && m.nseg > 0, ROKS_ERR_STATE, "the network has no training samples");
+    if (steps == 0) return;
+    double* hist = nullptr;
+    ROKS_HIP(hipMalloc(&hist, (size_t)steps * 2 * sizeof(double)));
+    hipError_t e = hipSuccess;
+    try {
+      for (int k = 0; k < steps; ++k) {
+        roks::mlp_loss_grad(m, hist + 2 * k);
+        roks::mlp_adam(m, lr);
+      }
+    } catch (...) {
+      e = hipErrorLaunchFailure;
+    }
+    std::vector<double> h((size_t)steps * 2);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h.data(), hist, h.size() * sizeof(double), hipMemcpyDeviceToHost, m.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m.stream);
+    (void)hipFree(hist);
+    ROKS_HIP(e);
+    if (loss_history)
+      for (int k = 0; k < steps; ++k) loss_history[k] = h[2 * (size_t)k];
+  });
+}
+
+roks_status roks_record(roks_ctx ctx, int32_t max_records, int32_t stride) {
+  return guard(ctx, [&](roks::Ctx& c) {
+    ROKS_CHECK(max_records >= 0 && stride >= 1, ROKS_ERR_ARG,
+               "max_records must be >= 0 and stride >= 1");
+    drop_records(c);
+    if (max_records == 0) return;
+    roks::build_gshells(c);
+    const size_t band = (size_t)c.nb * c.npw;
+    c.d_rec_psi = roks::dalloc<double2>(c, band * max_records);
+    c.d_rec_kg = roks::dalloc<double2>(c, band * max_records);
+    c.d_rec_feat = roks::dalloc<float>(c, 3 * (size_t)c.nb * c.nsh * max_records);
+    c.d_rec_valid = roks::dalloc<int32_t>(c, (size_t)c.nb * max_records);
+    if (!c.d_rec_sel) c.d_rec_sel = roks::dalloc<int32_t>(c, c.nb);
+    c.rec_max = max_records;
+    c.rec_stride = stride;
+    c.rec_count = 0;
+    ROKS_HIP(hipStreamSynchronize(c.stream));
+  });
+}
+
+roks_status roks_mlp_collect(roks_mlp mlp, roks_ctx ctx, int32_t* used, int32_t* skipped) {
+  if (!mlp) return ROKS_ERR_ARG;
+  return guard(ctx, [&](roks::Ctx& c) {
+    int u = 0, k = 0;
+    roks::collect_records(c, mlp->m, &u, &k);
+    if (used) *used = u;
+    if (skipped) *skipped = k;
+  });
+}
+
+roks_status roks_set_mlp(roks_ctx ctx, roks_mlp mlp) {
+  return guard(ctx, [&](roks::Ctx& c) {
+    if (mlp) {
+      roks::build_gshells(c);
+      ROKS_HIP(hipStreamSynchronize(mlp->m.stream));
+      c.mlp = &mlp->m;
+    } else {
+      c.mlp = nullptr;
+    }
   });
 }
 

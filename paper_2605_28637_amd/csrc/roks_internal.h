@@ -66,6 +66,8 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+struct Mlp;
+
 struct Ctx {
   // ---- problem description (host) ----
   double cell[3][3];
@@ -203,6 +205,28 @@ struct Ctx {
   roks_energies last_e{};
   std::string last_error;
 
+  // ---- learned preconditioner ----
+  Mlp* mlp = nullptr;               // attached network (not owned)
+  int nsh = 0;                      // distinct |G|^2 values ("G shells")
+  std::vector<double> g2sh;         // their |G|^2/2
+  std::vector<int32_t> gshell;      // shell of every stored G
+  std::vector<int32_t> sh_perm, sh_off;  // G sorted by shell, shell offsets
+  int32_t* d_gshell = nullptr;
+  int32_t* d_sh_perm = nullptr;
+  int32_t* d_sh_off = nullptr;
+  double* d_g2sh = nullptr;
+  float* d_feat = nullptr;          // [nb][nsh][3]
+  float* d_scale = nullptr;         // [nb][nsh]
+  int32_t* d_valid = nullptr;       // [nb]: band has a nonzero g_I
+  // recording of (psi_i, plain Teter K g_I, features) for training
+  int rec_max = 0, rec_stride = 1, rec_count = 0;
+  double2* d_rec_psi = nullptr;     // [rec_max][nb][npw]
+  double2* d_rec_kg = nullptr;
+  float* d_rec_feat = nullptr;      // [rec_max][nb][nsh][3]
+  int32_t* d_rec_valid = nullptr;   // [rec_max][nb]
+  int32_t* d_rec_sel = nullptr;     // [nb] selected bands during collection
+  double* d_mom = nullptr;          // [3][nb][nsh] moments scratch
+
   // ---- diagnostics: per-kernel event pairs on `stream` ----
   bool timing = false;
   struct Timed {
@@ -211,6 +235,42 @@ struct Ctx {
     double bytes, flops;  // algorithmic HBM bytes and flops of the launch
   };
   std::vector<Timed> timed;
+};
+
+// ---------------------------------------------------------------------------
+// learned rescaling of the Teter preconditioner (mlp.hip)
+// ---------------------------------------------------------------------------
+constexpr int kMlpWidth = 64;
+constexpr int kMlpFeat = 3;
+constexpr int kMlpParams = kMlpWidth * kMlpFeat + kMlpWidth + kMlpWidth * kMlpWidth + kMlpWidth +
+                           kMlpWidth + 1;  // 4481
+
+struct Mlp {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<DevBuf> allocations;
+  float* d_p = nullptr;      // FP32 master parameters
+  uint16_t* d_pb = nullptr;  // BF16 copy read by every evaluation
+  float *d_m = nullptr, *d_v = nullptr, *d_g = nullptr;  // Adam moments, gradient
+  int adam_t = 0;
+  double* d_loss = nullptr;  // [2]: mean loss, counted bands
+  // training set: samples grouped by band (segments), one per (band, G shell)
+  int S = 0, Scap = 0, nseg = 0;
+  size_t seg_cap = 0;
+  std::vector<int32_t> band_off{0};  // host copy, nseg + 1
+  float* d_X = nullptr;              // [Scap][3]
+  double* d_abg = nullptr;           // [3][Scap]: alpha, beta, gamma
+  int32_t* d_band_of = nullptr;      // [Scap] segment of every sample
+  int32_t* d_band_off = nullptr;     // [nseg + 1]
+  // scratch sized with the training set
+  float *d_o = nullptr, *d_do = nullptr;
+  float *d_H1 = nullptr, *d_DZ2 = nullptr, *d_DZ1 = nullptr, *d_HD3 = nullptr;  // [64][Scap]
+  double* d_ABC = nullptr;  // [nseg][3]
+  double* d_Lseg = nullptr;
+  int32_t* d_ok = nullptr;
+  float* d_part = nullptr;  // gradient partials [chunks][params]
+  size_t part_cap = 0;
+  std::string last_error;
 };
 
 // Records HIP events around the launches in its scope when timing is on,
@@ -288,6 +348,22 @@ void launch_expm_lds(Ctx& c, const double* D, double delta, double* U);
 void launch_asym_dot(Ctx& c, const double* A, const double* theta, double* out);
 void launch_teter(Ctx& c, const double* gTg, const double* gg, const double2* g, const double* bandw,
                   double2* out);
+
+// mlp.hip
+void mlp_init(Mlp& m, const float* theta, uint64_t seed);  // theta NULL: seeded init
+void mlp_free(Mlp& m);
+void mlp_set_params(Mlp& m, const float* host);
+void mlp_forward(Mlp& m, const float* dX, int S, float* d_o, float* d_s, hipStream_t stream);
+void mlp_loss_grad(Mlp& m, double* d_out);  // loss (and count) into d_out, gradient into d_g
+void mlp_adam(Mlp& m, double lr);
+void mlp_clear_samples(Mlp& m);
+void build_gshells(Ctx& c);
+void launch_features(Ctx& c, const double* gTg, const double* gg, const double* ekin);
+void launch_teter_scaled(Ctx& c, const double* gTg, const double* gg, const double2* g,
+                         const double* bandw, double2* out);
+void record_iterate(Ctx& c, const double* gTg, const double* gg);
+void polar_factor(Ctx& c, double* X, int n, double* T, double* Xn, bool* converged);
+void collect_records(Ctx& c, Mlp& m, int* used, int* skipped);
 
 // solver (solver.cpp)
 void compute_potentials(Ctx& c, const double2* orbitals, roks_energies* e);

@@ -247,21 +247,35 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   energy_gradient(c, &e0);
   const double E0 = e0.E;
 
-  // preconditioned out-of-subspace gradient p = (1 - P) K g_I
+  // preconditioned out-of-subspace gradient p = (1 - P) K g_I; with a
+  // network attached K carries the learned factor of (band, |G|^2 shell)
   band_dots(c, c.d_gI, c.d_gI, nb, 1, c.d_bandv);
   band_dots(c, c.d_gI, c.d_gI, nb, 0, c.d_bandv + nb);
-  launch_teter(c, c.d_bandv, c.d_bandv + nb, c.d_gI,
-               (c.flags & ROKS_FLAG_WEIGHT_PRECOND) ? c.d_kinw_shell : nullptr, c.d_w1);
-  gemm_wdot(c, nb, nb, K, dbl(c.d_psi), K, dbl(c.d_w1), K, c.d_m1, nb, 1.0, 0.0, true);
-  copy_dev(c, c.d_p, c.d_w1, band * sizeof(double2));
-  gemm_expand(c, nb, K, nb, c.d_m1, nb, false, dbl(c.d_psi), K, dbl(c.d_p), K, -1.0, 1.0);
-
-  // <p|g> = sum <p_I|g_I> + 1/2 sum A (theta - theta^T)
-  launch_asym_dot(c, c.d_A, c.d_theta, c.d_bandv + 2 * nb);
-  double asymA = 0.0;
-  const double pgI = total_dot(c, c.d_p, c.d_gI);
-  to_host(c, &asymA, c.d_bandv + 2 * nb, sizeof(double));
-  const double pg = pgI + 0.5 * asymA;
+  const bool recording = c.rec_max > 0 && c.rec_count < c.rec_max &&
+                         (c.iteration % std::max(1, c.rec_stride)) == 0;
+  if (c.mlp || recording) {
+    band_dots(c, c.d_psi, c.d_psi, nb, 1, c.d_bandv + 4 * nb);
+    launch_features(c, c.d_bandv, c.d_bandv + nb, c.d_bandv + 4 * nb);
+  }
+  if (recording) record_iterate(c, c.d_bandv, c.d_bandv + nb);
+  const double* bandw = (c.flags & ROKS_FLAG_WEIGHT_PRECOND) ? c.d_kinw_shell : nullptr;
+  auto precondition = [&](bool learned) {
+    if (learned)
+      launch_teter_scaled(c, c.d_bandv, c.d_bandv + nb, c.d_gI, bandw, c.d_w1);
+    else
+      launch_teter(c, c.d_bandv, c.d_bandv + nb, c.d_gI, bandw, c.d_w1);
+    gemm_wdot(c, nb, nb, K, dbl(c.d_psi), K, dbl(c.d_w1), K, c.d_m1, nb, 1.0, 0.0, true);
+    copy_dev(c, c.d_p, c.d_w1, band * sizeof(double2));
+    gemm_expand(c, nb, K, nb, c.d_m1, nb, false, dbl(c.d_psi), K, dbl(c.d_p), K, -1.0, 1.0);
+    // <p|g> = sum <p_I|g_I> + 1/2 sum A (theta - theta^T)
+    launch_asym_dot(c, c.d_A, c.d_theta, c.d_bandv + 2 * nb);
+    double asymA = 0.0;
+    const double pgI = total_dot(c, c.d_p, c.d_gI);
+    to_host(c, &asymA, c.d_bandv + 2 * nb, sizeof(double));
+    return pgI + 0.5 * asymA;
+  };
+  const bool learned = c.mlp != nullptr;
+  double pg = precondition(learned);
   double beta = (c.have_old && c.pg_old != 0.0) ? pg / c.pg_old : 0.0;
   bool restarted = false;
 
@@ -337,6 +351,7 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   };
 
   int evals = 0, best = -1;
+  bool fallback = false;
   if (dE0 < 0.0) {
     best = line_search(c.dt, &evals);
     if (best < 0 && beta != 0.0) {
@@ -346,6 +361,16 @@ void pcg_step(Ctx& c, roks_step_info* info) {
       if (dE0 < 0.0) best = line_search(c.dt, &evals);
     }
   }
+  if (best < 0 && learned) {
+    // the learned direction found no decrease: redo the step with the plain
+    // Teter preconditioner from the steepest-descent direction
+    fallback = true;
+    pg = precondition(false);
+    beta = 0.0;
+    restarted = true;
+    dE0 = directions(0.0);
+    if (dE0 < 0.0) best = line_search(c.dt, &evals);
+  }
   roks_step_info r{};
   r.E0 = E0;
   r.beta = beta;
@@ -354,6 +379,8 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   r.max_Rab = max_rab;
   r.restarted = restarted ? 1 : 0;
   r.evaluations = evals;
+  r.learned = learned ? 1 : 0;
+  r.fallback = fallback ? 1 : 0;
   if (best < 0) {
     r.E1 = E0;
     r.delta = 0.0;

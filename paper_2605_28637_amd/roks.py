@@ -66,7 +66,8 @@ class StepInfo(C.Structure):
     _fields_ = [("E0", C.c_double), ("E1", C.c_double), ("delta", C.c_double),
                 ("beta", C.c_double), ("dE0", C.c_double), ("norm_gI", C.c_double),
                 ("max_Rab", C.c_double), ("restarted", C.c_int32), ("stalled", C.c_int32),
-                ("evaluations", C.c_int32), ("iteration", C.c_int32)]
+                ("evaluations", C.c_int32), ("iteration", C.c_int32), ("learned", C.c_int32),
+                ("fallback", C.c_int32)]
 
     def as_dict(self) -> Dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -104,7 +105,24 @@ _SIGS = {
     "roks_timing_enable": (C.c_int, [_P, C.c_int32]),
     "roks_timing_read": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "roks_mlp_create": (C.c_int, [C.POINTER(C.c_float), C.c_uint64, _P, C.POINTER(_P)]),
+    "roks_mlp_destroy": (C.c_int, [_P]),
+    "roks_mlp_last_error": (C.c_char_p, [_P]),
+    "roks_mlp_set_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "roks_mlp_get_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "roks_mlp_forward": (C.c_int, [_P, C.POINTER(C.c_float), C.c_int64, C.POINTER(C.c_float)]),
+    "roks_mlp_num_samples": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    "roks_mlp_get_samples": (C.c_int, [_P, C.POINTER(C.c_float), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_int32)]),
+    "roks_mlp_clear_samples": (C.c_int, [_P]),
+    "roks_mlp_loss_grad": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_float)]),
+    "roks_mlp_train": (C.c_int, [_P, C.c_int32, C.c_double, C.POINTER(C.c_double)]),
+    "roks_record": (C.c_int, [_P, C.c_int32, C.c_int32]),
+    "roks_mlp_collect": (C.c_int, [_P, _P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "roks_set_mlp": (C.c_int, [_P, _P]),
 }
+
+MLP_PARAMS = 4481
 
 
 def lib() -> C.CDLL:
@@ -124,6 +142,10 @@ def lib() -> C.CDLL:
 
 def _dptr(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
 
 
 def _packed(c: np.ndarray) -> np.ndarray:
@@ -294,6 +316,13 @@ class Roks:
     def synchronize(self):
         self._check(self._L.roks_synchronize(self._h))
 
+    def record(self, max_records: int, stride: int = 1):
+        self._check(self._L.roks_record(self._h, max_records, stride))
+
+    def set_mlp(self, mlp: Optional["Mlp"]):
+        self._mlp = mlp  # keep the network alive while attached
+        self._check(self._L.roks_set_mlp(self._h, mlp.handle if mlp is not None else None))
+
     def timing_enable(self, on: bool = True):
         self._check(self._L.roks_timing_enable(self._h, 1 if on else 0))
 
@@ -306,3 +335,89 @@ class Roks:
     # device-pointer variants (torch tensors or raw ints)
     def apply_h_d(self, c_in_ptr: Optional[int], mask: int, out_ptr: int):
         self._check(self._L.roks_apply_h_d(self._h, _P(c_in_ptr or 0), mask, _P(out_ptr)))
+
+
+class Mlp:
+    """The learned rescaling network (a roks_mlp)."""
+
+    def __init__(self, theta: Optional[np.ndarray] = None, seed: int = 0, stream: Optional[int] = None):
+        self._L = lib()
+        h = _P()
+        t = None
+        if theta is not None:
+            t = np.ascontiguousarray(theta, dtype=np.float32)
+            assert t.size == MLP_PARAMS
+        st = self._L.roks_mlp_create(_fptr(t) if t is not None else None, seed, _P(stream or 0),
+                                     C.byref(h))
+        if st != 0:
+            raise RoksError(st, self._L.roks_mlp_last_error(None).decode())
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _check(self, status: int):
+        if status != 0:
+            raise RoksError(status, self._L.roks_mlp_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.roks_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta: np.ndarray):
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        assert t.size == MLP_PARAMS
+        self._check(self._L.roks_mlp_set_params(self._h, _fptr(t)))
+
+    def get_params(self) -> np.ndarray:
+        t = np.empty(MLP_PARAMS, dtype=np.float32)
+        self._check(self._L.roks_mlp_get_params(self._h, _fptr(t)))
+        return t
+
+    def forward(self, x: np.ndarray) -> np.ndarray:
+        xx = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 3)
+        o = np.empty(len(xx), dtype=np.float32)
+        self._check(self._L.roks_mlp_forward(self._h, _fptr(xx), len(xx), _fptr(o)))
+        return o
+
+    def num_samples(self):
+        S, nb = C.c_int64(), C.c_int32()
+        self._check(self._L.roks_mlp_num_samples(self._h, C.byref(S), C.byref(nb)))
+        return S.value, nb.value
+
+    def get_samples(self):
+        """(x [S][3] float32, moments [3][S] (alpha, beta, gamma), band offsets)"""
+        S, nb = self.num_samples()
+        x = np.empty((max(S, 1), 3), dtype=np.float32)
+        mom = np.empty((3, max(S, 1)))
+        off = np.empty(nb + 1, dtype=np.int32)
+        self._check(self._L.roks_mlp_get_samples(self._h, _fptr(x), _dptr(mom),
+                                                 off.ctypes.data_as(C.POINTER(C.c_int32))))
+        return x[:S], mom[:, :S], off
+
+    def clear_samples(self):
+        self._check(self._L.roks_mlp_clear_samples(self._h))
+
+    def loss_grad(self):
+        loss = C.c_double()
+        g = np.empty(MLP_PARAMS, dtype=np.float32)
+        self._check(self._L.roks_mlp_loss_grad(self._h, C.byref(loss), _fptr(g)))
+        return loss.value, g
+
+    def train(self, steps: int, lr: float) -> np.ndarray:
+        hist = np.empty(max(steps, 1))
+        self._check(self._L.roks_mlp_train(self._h, steps, lr, _dptr(hist)))
+        return hist[:steps]
+
+    def collect(self, roks: Roks):
+        used, skipped = C.c_int32(), C.c_int32()
+        self._check(self._L.roks_mlp_collect(self._h, roks.handle, C.byref(used), C.byref(skipped)))
+        return used.value, skipped.value
