@@ -210,6 +210,11 @@ roks_status roks_subspace(roks_ctx ctx, double* R, double* kappa, double* A);
 roks_status roks_pcg_step(roks_ctx ctx, roks_step_info* info);
 /* Forget the carried search directions (next step is steepest descent). */
 roks_status roks_reset_cg(roks_ctx ctx);
+/* Restart the CG recursion every `period` steps (0, the default: never, the
+ * plain Fletcher-Reeves recursion).  A restart drops the carried directions
+ * and resets the trial step length; the step reports restarted = 1.  The
+ * count starts at roks_set_coeffs / roks_reset_cg. */
+roks_status roks_set_restart(roks_ctx ctx, int32_t period);
 /* Switch the arithmetic tier of the FFT / pointwise work (roks_precision)
  * for the following calls, keeping the orbitals and the CG state: a
  * precision ladder runs FP32 iterations first and polishes in FP64. */
@@ -260,14 +265,23 @@ roks_status roks_timing_read(roks_ctx ctx, const char* kernel, double* total_ms,
  * each recorded psi_i within every occupation shell by the orthogonal polar
  * factor Q of O_mn = <psi_inf_m|psi_i,n> (psi_inf'_n = sum_m Q_mn psi_inf_m),
  * forms the correction delta_n = (1 - P_i) psi_inf'_n and stores, for each
- * occupied band with a usable gradient and each G shell k, the features and
- * the moments alpha = <Kg|delta>_k, beta = <Kg|Kg>_k, gamma = <delta|delta>_k
- * (full-sphere sums restricted to the shell).  The loss of a band is
- * 1 - A^2/(B C), A = sum_k s_k alpha_k, B = sum_k s_k^2 beta_k,
- * C = sum_k gamma_k: one minus the squared cosine between s K g_I and the
- * correction (scale free: the line search sets the length), averaged over
- * the bands with B, C > 0.  Training minimises it with Adam (beta1 = 0.9,
- * beta2 = 0.999, eps = 1e-8, bias-corrected).
+ * occupied band n with a usable gradient and each G shell k, the features
+ * and the moments alpha = <Kg_n|delta_n>_k, beta = <Kg_n|Kg_n>_k,
+ * gamma = <delta_n|delta_n>_k (full-sphere sums restricted to the shell).
+ * The samples of one recorded iterate form a segment; its loss is
+ * 1 - A^2/(B C) with A = sum s alpha, B = sum s^2 beta, C = sum gamma over
+ * the segment: one minus the squared cosine between the rescaled
+ * preconditioned gradient of all bands and the correction of all bands.  It
+ * fixes the shape and the relative weights of the bands, not the overall
+ * length (the line search sets it).  The training loss is the mean over
+ * segments with B, C > 0, minimised with Adam (beta1 = 0.9, beta2 = 0.999,
+ * eps = 1e-8, bias-corrected).
+ *
+ * Inside a CG step the factor is renormalised by one constant for all bands
+ * so that sum_n <s K g_n|g_n> equals the plain sum_n <K g_n|g_n>: the
+ * first-order energy change along the out-of-subspace direction, and its
+ * balance with the rotation that shares the line search, stay those of the
+ * plain preconditioner.
  *
  * A network's calls are ordered on its stream and synchronise it before
  * returning; a network attached to contexts must not be trained while their
@@ -288,12 +302,14 @@ roks_status roks_mlp_set_params(roks_mlp mlp, const float* theta);
 roks_status roks_mlp_get_params(roks_mlp mlp, float* theta);
 /* o for nsamples feature rows x [nsamples][3] (host arrays). */
 roks_status roks_mlp_forward(roks_mlp mlp, const float* x, int64_t nsamples, float* o);
-/* Size of the training set: samples and band segments. */
-roks_status roks_mlp_num_samples(roks_mlp mlp, int64_t* nsamples, int32_t* nbands);
+/* Size of the training set: samples and segments (recorded iterates). */
+roks_status roks_mlp_num_samples(roks_mlp mlp, int64_t* nsamples, int32_t* nsegments);
 /* Copy the training set out: x [nsamples][3], moments [3][nsamples] (alpha,
- * beta, gamma), band_offsets [nbands + 1] (segment of band j is samples
- * band_offsets[j] .. band_offsets[j+1]-1).  Any pointer may be NULL. */
-roks_status roks_mlp_get_samples(roks_mlp mlp, float* x, double* moments, int32_t* band_offsets);
+ * beta, gamma), segment_offsets [nsegments + 1] (segment j is samples
+ * segment_offsets[j] .. segment_offsets[j+1]-1, band-major, shells in
+ * ascending |G|^2).  Any pointer may be NULL. */
+roks_status roks_mlp_get_samples(roks_mlp mlp, float* x, double* moments,
+                                 int32_t* segment_offsets);
 roks_status roks_mlp_clear_samples(roks_mlp mlp);
 /* Loss over the training set at the current parameters and, if grad is not
  * NULL, its gradient [ROKS_MLP_PARAMS].  ROKS_ERR_STATE without samples. */

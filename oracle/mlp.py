@@ -19,12 +19,21 @@ library implements the same ones independently):
   within each occupation shell by the orthogonal polar factor of
   O_mn = <psi_inf_m|psi_i_n> (orthogonal Procrustes), give the correction
   delta_n = (1 - P_i) psi_inf'_n.
-* loss of band n (scale free; the line search fixes the step length):
-  L_n = 1 - <a_n|delta_n>^2 / (<a_n|a_n> <delta_n|delta_n>), a_n = s K g_I,n;
-  the training loss is the mean over bands with delta_n != 0.  With
-  moments per G shell k:  alpha = sum_k <Kg|delta>, beta = sum_k <Kg|Kg>,
-  gamma = sum_k <delta|delta>,  A = sum_k s_k alpha_k, B = sum_k s_k^2 beta_k,
-  C = sum_k gamma_k and L = 1 - A^2/(B C).
+* loss of one recorded iterate (a segment; scale free as a whole, the line
+  search fixes the step length): L = 1 - <a|delta>^2 / (<a|a> <delta|delta>)
+  with a_n = s K g_I,n and the inner products summed over all occupied bands
+  with a gradient, so the shape within a band and the relative weights of
+  the bands are both trained.  The inner products are taken in an energy
+  norm, <x|y>_h = sum_G h_n(G) x*(G) y(G) with the diagonal Hessian model
+  h_n(G) = |G|^2/2 + <n|T|n>: a stiff component that the correction does
+  not need then costs what it costs the line search.  With moments per
+  (band n, G shell k): alpha = <Kg_n|delta_n>_h,k, beta = <Kg_n|Kg_n>_h,k,
+  gamma = <delta_n|delta_n>_h,k,
+  A = sum s alpha, B = sum s^2 beta, C = sum gamma over the segment and
+  L = 1 - A^2/(B C); the training loss is the mean over segments with
+  B, C > 0.  band_loss takes one segment per row.
+* inference: one constant for all bands makes sum_n <s K g_n|g_n> equal to
+  the plain preconditioner's; the loss leaves this overall length free.
 * optimiser: Adam (Kingma & Ba 2015) with bias correction.
 """
 from __future__ import annotations
@@ -160,6 +169,34 @@ def plain_teter_Kg(model, gI: np.ndarray) -> np.ndarray:
     return out
 
 
+def normalized_scale(model, gI: np.ndarray, s_shell: np.ndarray, shell_of_G: np.ndarray):
+    """Full-sphere factor [nb][npw] applied to K: the network's s of (band,
+    G shell), times one constant for all bands chosen so that
+    sum_n <s K g_n|g_n> equals the plain sum_n <K g_n|g_n> (the first-order
+    energy change along the out-of-subspace direction is kept).  Rows of
+    s_shell that hold NaN (bands without features) give s = 1 and take part
+    in neither sum."""
+    from . import roks
+    out = np.ones((model.nb, model.npw))
+    a = b = 0.0
+    rows = []
+    for n in range(model.nb):
+        if np.isnan(s_shell[n]).any():
+            continue
+        Er = roks.teter_reference_energy(model, gI[n])
+        if Er <= 0:
+            continue
+        w = (2.0 / Er) * roks.teter_polynomial_ratio(0.5 * model.g2 / Er) * np.abs(gI[n]) ** 2
+        s = s_shell[n][shell_of_G]
+        a += float(w.sum())
+        b += float((s * w).sum())
+        rows.append((n, s))
+    r = a / b if a > 0 and b > 0 else 1.0
+    for n, s in rows:
+        out[n] = s * r
+    return out
+
+
 def aligned_correction(model, psi_i: np.ndarray, psi_inf: np.ndarray) -> np.ndarray:
     """delta_n = (1 - P_i) psi_inf'_n with psi_inf aligned to psi_i per shell."""
     from . import roks
@@ -172,23 +209,25 @@ def aligned_correction(model, psi_i: np.ndarray, psi_inf: np.ndarray) -> np.ndar
     return aligned - roks.overlap(psi_i, aligned).T @ psi_i
 
 
-def moments(model, Kg: np.ndarray, delta: np.ndarray, shell_of_G: np.ndarray, nsh: int):
-    """alpha, beta, gamma [n][k]: <Kg|delta>, <Kg|Kg>, <delta|delta> restricted
-    to G shell k (full-sphere sums)."""
+def moments(model, Kg: np.ndarray, delta: np.ndarray, shell_of_G: np.ndarray, nsh: int,
+            ekin: np.ndarray):
+    """alpha, beta, gamma [n][k]: <Kg|delta>_h, <Kg|Kg>_h, <delta|delta>_h
+    restricted to G shell k (full-sphere sums), in the energy norm of band n:
+    every G weighted by h_n(G) = |G|^2/2 + ekin[n]."""
     nb = len(Kg)
-    # the oracle stores the full sphere: map each G to the shell of |G|^2
     a = np.zeros((nb, nsh))
     b = np.zeros((nb, nsh))
     c = np.zeros((nb, nsh))
     for n in range(nb):
-        np.add.at(a[n], shell_of_G, np.real(np.conj(Kg[n]) * delta[n]))
-        np.add.at(b[n], shell_of_G, np.abs(Kg[n]) ** 2)
-        np.add.at(c[n], shell_of_G, np.abs(delta[n]) ** 2)
+        h = 0.5 * model.g2 + ekin[n]
+        np.add.at(a[n], shell_of_G, h * np.real(np.conj(Kg[n]) * delta[n]))
+        np.add.at(b[n], shell_of_G, h * np.abs(Kg[n]) ** 2)
+        np.add.at(c[n], shell_of_G, h * np.abs(delta[n]) ** 2)
     return a, b, c
 
 
 def band_loss(s: np.ndarray, alpha: np.ndarray, beta: np.ndarray, gamma: np.ndarray):
-    """Mean over bands (rows with sum gamma > 0) of 1 - A^2/(B C); also dL/ds."""
+    """Mean over segments (rows, with B, C > 0) of 1 - A^2/(B C); also dL/ds."""
     A = (s * alpha).sum(axis=1)
     B = (s * s * beta).sum(axis=1)
     Cc = gamma.sum(axis=1)
@@ -202,7 +241,7 @@ def band_loss(s: np.ndarray, alpha: np.ndarray, beta: np.ndarray, gamma: np.ndar
 
 
 def loss_and_grad(theta: np.ndarray, X: np.ndarray, alpha, beta, gamma):
-    """Loss over a set of bands; X [nb][nsh][3] and moments [nb][nsh]."""
+    """Loss over segments: X [nseg][len][3] and moments [nseg][len]."""
     nb, nsh, _ = X.shape
     o, cache = forward(theta, X.reshape(-1, NFEAT))
     t = np.tanh(o)

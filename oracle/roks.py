@@ -530,6 +530,8 @@ class CGState:
     pg_old: Optional[float] = None
     dt: float = 0.5
     iteration: int = 0
+    restart_period: int = 0   # reading R23: restart every this many steps (0: never)
+    since_restart: int = 0
 
 
 @dataclasses.dataclass
@@ -578,13 +580,20 @@ def _line_search(model: Model, psi, S, D, E0, dE0, dt):
 def pcg_step(model: Model, state: CGState, flags: Flags = Flags(),
              scale: Optional[np.ndarray] = None) -> StepInfo:
     """One ROKS conjugate-gradient iteration on ``state`` (modified in place)."""
+    periodic = state.restart_period > 0 and state.since_restart >= state.restart_period
+    if periodic:
+        # reading R23: forget the carried directions, the step length estimate too
+        state.S_old = state.D_old = state.pg_old = None
+        state.dt = DT_INIT
+        state.since_restart = 0
+    state.since_restart += 1
     psi = state.psi
     gr = gradient(model, psi, flags)
     E0 = gr.pot.E
     p = precondition(model, psi, gr.gI, flags, scale)
     asym = gr.theta - gr.theta.T
     pg = float(np.sum(np.real(np.conj(p) * gr.gI)) + 0.5 * np.sum(gr.A * asym))
-    restarted = False
+    restarted = periodic
     beta = 0.0
     if state.pg_old is not None and state.pg_old != 0.0:
         beta = pg / state.pg_old
@@ -642,10 +651,11 @@ def _max_open_coupling(model: Model, gr: Gradient) -> float:
 
 
 def solve(model: Model, psi0: np.ndarray, tol: float = 1e-10, maxiter: int = 500,
-          flags: Flags = Flags(), orthonormalize_start: bool = True, log=None):
+          flags: Flags = Flags(), orthonormalize_start: bool = True, log=None,
+          restart_period: int = 0):
     """Iterate pcg_step until |E_{i+1} - E_i| < tol on two consecutive steps."""
     psi = orthonormalize(psi0) if orthonormalize_start else psi0.copy()
-    state = CGState(psi=psi, dt=DT_INIT)
+    state = CGState(psi=psi, dt=DT_INIT, restart_period=restart_period)
     hits = 0
     history: List[StepInfo] = []
     for _ in range(maxiter):

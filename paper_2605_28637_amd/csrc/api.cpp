@@ -66,6 +66,8 @@ void drop_records(roks::Ctx& c) {
   dfree(c, c.d_rec_kg);
   dfree(c, c.d_rec_feat);
   dfree(c, c.d_rec_valid);
+  dfree(c, c.d_rec_ekin);
+  c.d_rec_ekin = nullptr;
   c.d_rec_psi = c.d_rec_kg = nullptr;
   c.d_rec_feat = nullptr;
   c.d_rec_valid = nullptr;
@@ -274,6 +276,13 @@ roks_status roks_reset_cg(roks_ctx ctx) {
   return guard(ctx, [&](roks::Ctx& c) { roks::reset_cg(c); });
 }
 
+roks_status roks_set_restart(roks_ctx ctx, int32_t period) {
+  return guard(ctx, [&](roks::Ctx& c) {
+    ROKS_CHECK(period >= 0, ROKS_ERR_ARG, "period must be >= 0");
+    c.restart_period = period;
+  });
+}
+
 roks_status roks_set_precision(roks_ctx ctx, int32_t precision) {
   return guard(ctx, [&](roks::Ctx& c) {
     ROKS_CHECK(precision == ROKS_FP64 || precision == ROKS_FP32, ROKS_ERR_ARG, "unknown precision");
@@ -439,14 +448,15 @@ roks_status roks_mlp_forward(roks_mlp mlp, const float* x, int64_t nsamples, flo
   });
 }
 
-roks_status roks_mlp_num_samples(roks_mlp mlp, int64_t* nsamples, int32_t* nbands) {
+roks_status roks_mlp_num_samples(roks_mlp mlp, int64_t* nsamples, int32_t* nsegments) {
   return guard_mlp(mlp, [&](roks::Mlp& m) {
     if (nsamples) *nsamples = m.S;
-    if (nbands) *nbands = m.nseg;
+    if (nsegments) *nsegments = m.nseg;
   });
 }
 
-roks_status roks_mlp_get_samples(roks_mlp mlp, float* x, double* moments, int32_t* band_offsets) {
+roks_status roks_mlp_get_samples(roks_mlp mlp, float* x, double* moments,
+                                 int32_t* segment_offsets) {
   return guard_mlp(mlp, [&](roks::Mlp& m) {
     if (m.S > 0) {
       if (x)
@@ -458,8 +468,8 @@ roks_status roks_mlp_get_samples(roks_mlp mlp, float* x, double* moments, int32_
                                   (size_t)m.S * sizeof(double), hipMemcpyDeviceToHost, m.stream));
       ROKS_HIP(hipStreamSynchronize(m.stream));
     }
-    if (band_offsets)
-      std::memcpy(band_offsets, m.band_off.data(), m.band_off.size() * sizeof(int32_t));
+    if (segment_offsets)
+      std::memcpy(segment_offsets, m.band_off.data(), m.band_off.size() * sizeof(int32_t));
   });
 }
 
@@ -520,6 +530,7 @@ roks_status roks_record(roks_ctx ctx, int32_t max_records, int32_t stride) {
     c.d_rec_kg = roks::dalloc<double2>(c, band * max_records);
     c.d_rec_feat = roks::dalloc<float>(c, 3 * (size_t)c.nb * c.nsh * max_records);
     c.d_rec_valid = roks::dalloc<int32_t>(c, (size_t)c.nb * max_records);
+    c.d_rec_ekin = roks::dalloc<double>(c, (size_t)c.nb * max_records);
     if (!c.d_rec_sel) c.d_rec_sel = roks::dalloc<int32_t>(c, c.nb);
     c.rec_max = max_records;
     c.rec_stride = stride;

@@ -361,8 +361,8 @@ __global__ void k_teter_scaled(const double2* __restrict__ g, int npw, int nb,
                                const double* __restrict__ gTg, const double* __restrict__ gg,
                                const double* __restrict__ g2, const int32_t* __restrict__ gshell,
                                int nsh, const float* __restrict__ scale,
-                               const int32_t* __restrict__ valid, const double* __restrict__ bandw,
-                               double2* __restrict__ out) {
+                               const int32_t* __restrict__ valid, const double* __restrict__ ratio,
+                               const double* __restrict__ bandw, double2* __restrict__ out) {
   const size_t total = (size_t)nb * npw;
   for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
        t += (size_t)gridDim.x * blockDim.x) {
@@ -376,7 +376,7 @@ __global__ void k_teter_scaled(const double2* __restrict__ g, int npw, int nb,
         const double p = 27.0 + 18.0 * x + 12.0 * x2 + 8.0 * x2 * x;
         double K = -(2.0 / eref) * p / (p + 16.0 * x2 * x2);
         if (bandw) K /= bandw[n];
-        if (valid[n]) K *= (double)scale[(size_t)n * nsh + gshell[q]];
+        if (valid[n]) K *= (double)scale[(size_t)n * nsh + gshell[q]] * ratio[0];
         v = make_double2(K * g[t].x, K * g[t].y);
       }
     }
@@ -384,21 +384,96 @@ __global__ void k_teter_scaled(const double2* __restrict__ g, int npw, int nb,
   }
 }
 
-// moments of band n restricted to G shell k (full-sphere sums: weight 2 for
-// the stored G != 0, 1 for G = 0), G vectors of a shell in ascending order
+// per band, <K g|g> and <s K g|g> (without the common -2/E_ref factor's
+// sign; both are positive sums)
+__global__ void __launch_bounds__(1024) k_teter_norm(const double2* __restrict__ g, int npw,
+                                                     const double* __restrict__ gTg,
+                                                     const double* __restrict__ gg,
+                                                     const double* __restrict__ g2,
+                                                     const int32_t* __restrict__ gshell, int nsh,
+                                                     const float* __restrict__ scale,
+                                                     const int32_t* __restrict__ valid,
+                                                     double* __restrict__ ab) {
+  __shared__ double ra[16], rb[16];
+  const int n = blockIdx.x;
+  double a = 0.0, b = 0.0;
+  if (valid[n]) {
+    const double eref = 1.5 * gTg[n] / gg[n];
+    const double2* x = g + (size_t)n * npw;
+    const float* sc = scale + (size_t)n * nsh;
+    for (int q = threadIdx.x; q < npw; q += blockDim.x) {
+      const double t = g2[q] / eref;
+      const double t2 = t * t;
+      const double p = 27.0 + 18.0 * t + 12.0 * t2 + 8.0 * t2 * t;
+      const double k = (q == 0 ? 1.0 : 2.0) * (2.0 / eref) * p / (p + 16.0 * t2 * t2) *
+                       (x[q].x * x[q].x + x[q].y * x[q].y);
+      a += k;
+      b += (double)sc[gshell[q]] * k;
+    }
+  }
+  a = wave_sum_d(a);
+  b = wave_sum_d(b);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    ra[wid] = a;
+    rb[wid] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      sa += ra[w];
+      sb += rb[w];
+    }
+    ab[2 * n] = sa;
+    ab[2 * n + 1] = sb;
+  }
+}
+
+// one factor for all bands: sum <K g|g> / sum <s K g|g>, so the learned
+// direction keeps the plain preconditioner's first-order energy change and
+// its balance with the rotation step; the network sets the shape and the
+// relative weights of the bands
+__global__ void __launch_bounds__(256) k_norm_reduce(const double* __restrict__ ab, int nb,
+                                                     double* __restrict__ ratio) {
+  __shared__ double sa[256], sb[256];
+  double a = 0.0, b = 0.0;
+  for (int n = threadIdx.x; n < nb; n += 256) {
+    a += ab[2 * n];
+    b += ab[2 * n + 1];
+  }
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sa[threadIdx.x] += sa[threadIdx.x + w];
+      sb[threadIdx.x] += sb[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *ratio = (sa[0] > 0.0 && sb[0] > 0.0) ? sa[0] / sb[0] : 1.0;
+}
+
+// energy-norm moments of band n restricted to G shell k: every G weighted
+// by h = |G|^2/2 + <n|T|n> (a diagonal model of the band's Hessian) and by
+// the half-sphere factor (2 for the stored G != 0, 1 for G = 0); the G
+// vectors of a shell in ascending order
 __global__ void k_moments(const double2* __restrict__ Kg, const double2* __restrict__ dl, int npw,
                           int nb, int nsh, const int32_t* __restrict__ perm,
-                          const int32_t* __restrict__ shoff, double* __restrict__ a,
+                          const int32_t* __restrict__ shoff, const double* __restrict__ g2,
+                          const double* __restrict__ ekin, double* __restrict__ a,
                           double* __restrict__ b, double* __restrict__ c) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nb * nsh) return;
   const int n = idx / nsh, k = idx - n * nsh;
   const double2* x = Kg + (size_t)n * npw;
   const double2* y = dl + (size_t)n * npw;
+  const double en = ekin[n];
   double sa = 0.0, sb = 0.0, sc = 0.0;
   for (int i = shoff[k]; i < shoff[k + 1]; ++i) {
     const int q = perm[i];
-    const double w = q == 0 ? 1.0 : 2.0;
+    const double w = (q == 0 ? 1.0 : 2.0) * (g2[q] + en);
     const double2 u = x[q], v = y[q];
     sa += w * (u.x * v.x + u.y * v.y);
     sb += w * (u.x * u.x + u.y * u.y);
@@ -434,7 +509,8 @@ __global__ void __launch_bounds__(256) k_identity_dev(const double* __restrict__
   if (threadIdx.x == 0) *out = red[0];
 }
 
-// append the selected bands' (features, moments) to the training set
+// append the selected bands' (features, moments) to the training set as one
+// segment (the iterate)
 __global__ void k_gather_segments(const float* __restrict__ feat, const double* __restrict__ a,
                                   const double* __restrict__ b, const double* __restrict__ c,
                                   const int32_t* __restrict__ sel, int nsel, int nsh,
@@ -451,7 +527,7 @@ __global__ void k_gather_segments(const float* __restrict__ feat, const double* 
   ad[idx] = a[src];
   bd[idx] = b[src];
   cd[idx] = c[src];
-  seg_of[idx] = seg_base + j;
+  seg_of[idx] = seg_base;
 }
 
 int grid_for(size_t n, int block) { return (int)std::max<size_t>(1, (n + block - 1) / block); }
@@ -700,14 +776,19 @@ void launch_teter_scaled(Ctx& c, const double* gTg, const double* gg, const doub
                    2.0 * (W * kMlpFeat + W * W + W) * (double)c.nb * c.nsh);
     mlp_forward(*c.mlp, c.d_feat, c.nb * c.nsh, nullptr, c.d_scale, c.stream);
   }
+  double* ab = c.d_bandv + 4 * c.nb;  // [nb][2], after the features are taken
+  double* ratio = c.d_bandv + 7 * c.nb;
+  hipLaunchKernelGGL(k_teter_norm, dim3(c.nb), dim3(1024), 0, c.stream, g, c.npw, gTg, gg, c.d_g2,
+                     c.d_gshell, c.nsh, c.d_scale, c.d_valid, ab);
+  hipLaunchKernelGGL(k_norm_reduce, dim3(1), dim3(256), 0, c.stream, ab, c.nb, ratio);
   const size_t n = (size_t)c.nb * c.npw;
   const int blocks = (int)std::min<size_t>(8192, std::max<size_t>(1, (n + 255) / 256));
   hipLaunchKernelGGL(k_teter_scaled, dim3(blocks), dim3(256), 0, c.stream, g, c.npw, c.nb, gTg, gg,
-                     c.d_g2, c.d_gshell, c.nsh, c.d_scale, c.d_valid, bandw, out);
+                     c.d_g2, c.d_gshell, c.nsh, c.d_scale, c.d_valid, ratio, bandw, out);
   ROKS_HIP(hipGetLastError());
 }
 
-void record_iterate(Ctx& c, const double* gTg, const double* gg) {
+void record_iterate(Ctx& c, const double* gTg, const double* gg, const double* ekin) {
   const int r = c.rec_count;
   const size_t band = (size_t)c.nb * c.npw;
   const size_t fs = 3 * (size_t)c.nb * c.nsh;
@@ -717,6 +798,8 @@ void record_iterate(Ctx& c, const double* gTg, const double* gg) {
   ROKS_HIP(hipMemcpyAsync(c.d_rec_feat + r * fs, c.d_feat, fs * sizeof(float),
                           hipMemcpyDeviceToDevice, c.stream));
   ROKS_HIP(hipMemcpyAsync(c.d_rec_valid + (size_t)r * c.nb, c.d_valid, c.nb * sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, c.stream));
+  ROKS_HIP(hipMemcpyAsync(c.d_rec_ekin + (size_t)r * c.nb, ekin, c.nb * sizeof(double),
                           hipMemcpyDeviceToDevice, c.stream));
   c.rec_count++;
 }
@@ -788,8 +871,8 @@ void collect_records(Ctx& c, Mlp& m, int* used, int* skipped) {
     double* db = c.d_mom + (size_t)nb * nsh;
     double* dc = c.d_mom + 2 * (size_t)nb * nsh;
     hipLaunchKernelGGL(k_moments, dim3(grid_for((size_t)nb * nsh, 128)), dim3(128), 0, c.stream,
-                       c.d_rec_kg + r * band, c.d_w1, c.npw, nb, nsh, c.d_sh_perm, c.d_sh_off, da,
-                       db, dc);
+                       c.d_rec_kg + r * band, c.d_w1, c.npw, nb, nsh, c.d_sh_perm, c.d_sh_off, c.d_g2,
+                       c.d_rec_ekin + (size_t)r * nb, da, db, dc);
     ROKS_HIP(hipGetLastError());
     // bands with a usable gradient become segments of the training set
     ROKS_HIP(hipMemcpyAsync(valid.data(), c.d_rec_valid + (size_t)r * nb, nb * sizeof(int32_t),
@@ -804,7 +887,7 @@ void collect_records(Ctx& c, Mlp& m, int* used, int* skipped) {
     }
     const int nsel = (int)sel.size();
     ROKS_HIP(hipStreamSynchronize(m.stream));
-    reserve_samples(m, m.S + nsel * nsh, m.nseg + nsel);
+    reserve_samples(m, m.S + nsel * nsh, m.nseg + 1);
     ROKS_HIP(hipStreamSynchronize(m.stream));
     ROKS_HIP(hipMemcpyAsync(d_sel, sel.data(), nsel * sizeof(int32_t), hipMemcpyHostToDevice,
                             c.stream));
@@ -814,9 +897,9 @@ void collect_records(Ctx& c, Mlp& m, int* used, int* skipped) {
                        m.d_X + 3 * (size_t)m.S, m.d_abg + m.S, m.d_abg + ld + m.S,
                        m.d_abg + 2 * ld + m.S, m.d_band_of + m.S, m.nseg);
     ROKS_HIP(hipGetLastError());
-    for (int j = 0; j < nsel; ++j) m.band_off.push_back(m.band_off.back() + nsh);
+    m.band_off.push_back(m.band_off.back() + nsel * nsh);
     m.S += nsel * nsh;
-    m.nseg += nsel;
+    m.nseg += 1;
     ROKS_HIP(hipMemcpyAsync(m.d_band_off, m.band_off.data(), (m.nseg + 1) * sizeof(int32_t),
                             hipMemcpyHostToDevice, c.stream));
     ROKS_HIP(hipStreamSynchronize(c.stream));

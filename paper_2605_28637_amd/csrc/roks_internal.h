@@ -205,6 +205,10 @@ struct Ctx {
   roks_energies last_e{};
   std::string last_error;
 
+  // periodic CG restart (0: never) and the steps since the last one
+  int restart_period = 0;
+  int since_restart = 0;
+
   // ---- learned preconditioner ----
   Mlp* mlp = nullptr;               // attached network (not owned)
   int nsh = 0;                      // distinct |G|^2 values ("G shells")
@@ -224,6 +228,7 @@ struct Ctx {
   double2* d_rec_kg = nullptr;
   float* d_rec_feat = nullptr;      // [rec_max][nb][nsh][3]
   int32_t* d_rec_valid = nullptr;   // [rec_max][nb]
+  double* d_rec_ekin = nullptr;     // [rec_max][nb] <n|T|n> of the iterate
   int32_t* d_rec_sel = nullptr;     // [nb] selected bands during collection
   double* d_mom = nullptr;          // [3][nb][nsh] moments scratch
 
@@ -254,10 +259,11 @@ struct Mlp {
   float *d_m = nullptr, *d_v = nullptr, *d_g = nullptr;  // Adam moments, gradient
   int adam_t = 0;
   double* d_loss = nullptr;  // [2]: mean loss, counted bands
-  // training set: samples grouped by band (segments), one per (band, G shell)
+  // training set: one sample per (band, G shell), grouped by recorded
+  // iterate (segments)
   int S = 0, Scap = 0, nseg = 0;
   size_t seg_cap = 0;
-  std::vector<int32_t> band_off{0};  // host copy, nseg + 1
+  std::vector<int32_t> band_off{0};  // segment offsets (host copy), nseg + 1
   float* d_X = nullptr;              // [Scap][3]
   double* d_abg = nullptr;           // [3][Scap]: alpha, beta, gamma
   int32_t* d_band_of = nullptr;      // [Scap] segment of every sample
@@ -361,7 +367,7 @@ void build_gshells(Ctx& c);
 void launch_features(Ctx& c, const double* gTg, const double* gg, const double* ekin);
 void launch_teter_scaled(Ctx& c, const double* gTg, const double* gg, const double2* g,
                          const double* bandw, double2* out);
-void record_iterate(Ctx& c, const double* gTg, const double* gg);
+void record_iterate(Ctx& c, const double* gTg, const double* gg, const double* ekin);
 void polar_factor(Ctx& c, double* X, int n, double* T, double* Xn, bool* converged);
 void collect_records(Ctx& c, Mlp& m, int* used, int* skipped);
 

@@ -234,6 +234,7 @@ void reset_cg(Ctx& c) {
   c.have_old = false;
   c.pg_old = 0.0;
   c.dt = kDtInit;
+  c.since_restart = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -243,6 +244,11 @@ void reset_cg(Ctx& c) {
 void pcg_step(Ctx& c, roks_step_info* info) {
   const int nb = c.nb, K = 2 * c.npw;
   const size_t band = (size_t)nb * c.npw, nn = (size_t)nb * nb;
+  // periodic restart: every restart_period steps the carried directions and
+  // the step length estimate are dropped (a fresh preconditioned gradient)
+  const bool periodic = c.restart_period > 0 && c.since_restart >= c.restart_period;
+  if (periodic) reset_cg(c);
+  c.since_restart++;
   roks_energies e0;
   energy_gradient(c, &e0);
   const double E0 = e0.E;
@@ -257,7 +263,7 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     band_dots(c, c.d_psi, c.d_psi, nb, 1, c.d_bandv + 4 * nb);
     launch_features(c, c.d_bandv, c.d_bandv + nb, c.d_bandv + 4 * nb);
   }
-  if (recording) record_iterate(c, c.d_bandv, c.d_bandv + nb);
+  if (recording) record_iterate(c, c.d_bandv, c.d_bandv + nb, c.d_bandv + 4 * nb);
   const double* bandw = (c.flags & ROKS_FLAG_WEIGHT_PRECOND) ? c.d_kinw_shell : nullptr;
   auto precondition = [&](bool learned) {
     if (learned)
@@ -277,7 +283,7 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   const bool learned = c.mlp != nullptr;
   double pg = precondition(learned);
   double beta = (c.have_old && c.pg_old != 0.0) ? pg / c.pg_old : 0.0;
-  bool restarted = false;
+  bool restarted = periodic;
 
   // Sold projected out of the current span (kept in d_w1)
   if (c.have_old) {

@@ -98,6 +98,7 @@ _SIGS = {
                                 C.POINTER(C.c_double)]),
     "roks_pcg_step": (C.c_int, [_P, C.POINTER(StepInfo)]),
     "roks_reset_cg": (C.c_int, [_P]),
+    "roks_set_restart": (C.c_int, [_P, C.c_int32]),
     "roks_set_precision": (C.c_int, [_P, C.c_int32]),
     "roks_solve": (C.c_int, [_P, C.c_double, C.c_int32, C.POINTER(StepInfo), C.POINTER(C.c_int32)]),
     "roks_forces": (C.c_int, [_P, C.POINTER(C.c_double)]),
@@ -298,6 +299,9 @@ class Roks:
 
     def reset_cg(self):
         self._check(self._L.roks_reset_cg(self._h))
+
+    def set_restart(self, period: int):
+        self._check(self._L.roks_set_restart(self._h, period))
 
     def set_precision(self, precision: int):
         self._check(self._L.roks_set_precision(self._h, precision))

@@ -7,7 +7,7 @@ Tolerances follow from the arithmetic:
   u = 2^-24, per dot product; activation values carry 8 u (|z| + 1) for erf
   and the product), propagated through |GELU'| <= 1.13;
 * training pairs: features are FP64 values rounded to FP32 (2 u relative);
-  moments are FP64 sums over iterates that agree to 1e-12, with the polar
+  moments (energy-norm products per (band, |G|^2 shell)) are FP64 sums over iterates that agree to 1e-12, with the polar
   factor by Newton-Schulz on the GPU and by SVD in the oracle: 1e-9 relative;
 * loss: s in FP32 (a few u relative) enters A^2/(BC) to second order: 1e-5;
 * gradient: per parameter, a sum over samples of FP32 products, chunks of
@@ -89,23 +89,30 @@ def test_seeded_initialisation_is_near_plain_teter():
 # training pairs from recorded iterates
 # ---------------------------------------------------------------------------
 def _oracle_pairs(m, psi_list, psi_inf):
-    """Oracle features and moments of the occupied bands with a gradient,
-    per recorded iterate, in the library's order (sorted |G|^2 shells)."""
+    """Oracle features [nseg][len][3] and moments [nseg][3][len] of the
+    occupied bands with a gradient, one segment per recorded iterate, in the
+    library's order (band-major, shells in ascending |G|^2); shorter segments
+    are padded with zero moments, which add nothing to a segment's sums."""
     g2sh, shell_of = om.g_shells(0.5 * m.g2)
-    X, mom, bands = [], [], []
+    segs = []
     for psi in psi_list:
         gr = orc.gradient(m, psi)
         F = om.band_features(m, psi, gr.gI, g2sh)
         Kg = om.plain_teter_Kg(m, gr.gI)
         d = om.aligned_correction(m, psi, psi_inf)
-        a, b, c = om.moments(m, Kg, d, shell_of, len(g2sh))
-        for n in range(m.nb):
-            if m.shell_virtual[m.band_shell[n]] or np.isnan(F[n, 0, 0]):
-                continue
-            X.append(F[n])
-            mom.append(np.stack([a[n], b[n], c[n]]))
-            bands.append(n)
-    return np.array(X), np.array(mom), bands
+        a, b, c = om.moments(m, Kg, d, shell_of, len(g2sh), orc.band_kinetic(m, psi))
+        sel = [n for n in range(m.nb)
+               if not m.shell_virtual[m.band_shell[n]] and not np.isnan(F[n, 0, 0])]
+        segs.append((F[sel].reshape(-1, 3), np.stack([a[sel].ravel(), b[sel].ravel(), c[sel].ravel()])))
+    L = max(len(x) for x, _ in segs)
+    X = np.zeros((len(segs), L, 3))
+    M = np.zeros((len(segs), 3, L))
+    lens = []
+    for j, (x, mo) in enumerate(segs):
+        X[j, :len(x)] = x
+        M[j, :, :len(x)] = mo
+        lens.append(len(x))
+    return X, M, lens
 
 
 @pytest.fixture(scope="module")
@@ -136,27 +143,28 @@ def pairs():
     full0 = inputs.random_coefficients(m.miller, m.cell, m.nb, s["seed"])
     full1 = inputs.random_coefficients(m.miller, m.cell, m.nb, s["seed"] + 77)
     psi_inf = orc.orthonormalize(full0 + 0.3 * full1)
-    Xo, Mo, bands = _oracle_pairs(m, [psi0, psi1], psi_inf)
-    yield rb, g, net, m, Xo, Mo, bands
+    Xo, Mo, lens = _oracle_pairs(m, [psi0, psi1], psi_inf)
+    yield rb, g, net, m, Xo, Mo, lens
     g.close()
     net.close()
 
 
 def test_collected_pairs_match_oracle(pairs):
-    rb, g, net, m, Xo, Mo, bands = pairs
+    rb, g, net, m, Xo, Mo, lens = pairs
     S, nseg = net.num_samples()
-    nsh = Xo.shape[1]
-    assert nseg == len(bands) and S == nseg * nsh
+    assert nseg == 2 and S == sum(lens)
     x, mom, off = net.get_samples()
-    np.testing.assert_array_equal(off, np.arange(nseg + 1) * nsh)
-    xg = x.reshape(nseg, nsh, 3).astype(np.float64)
-    assert np.all(np.abs(xg - Xo) <= 4 * U * np.abs(Xo) + 1e-7)
-    mg = mom.reshape(3, nseg, nsh).transpose(1, 0, 2)
+    np.testing.assert_array_equal(off, np.r_[0, np.cumsum(lens)])
     for j in range(nseg):
-        B, C = Mo[j, 1].sum(), Mo[j, 2].sum()
-        assert np.abs(mg[j, 0] - Mo[j, 0]).max() <= 1e-9 * math.sqrt(B * C), j
-        assert np.abs(mg[j, 1] - Mo[j, 1]).max() <= 1e-9 * B, j
-        assert np.abs(mg[j, 2] - Mo[j, 2]).max() <= 1e-9 * C, j
+        xg = x[off[j]:off[j + 1]].astype(np.float64)
+        xo = Xo[j, :lens[j]]
+        assert np.all(np.abs(xg - xo) <= 4 * U * np.abs(xo) + 1e-7), j
+        mg = mom[:, off[j]:off[j + 1]]
+        mo = Mo[j, :, :lens[j]]
+        B, C = mo[1].sum(), mo[2].sum()
+        assert np.abs(mg[0] - mo[0]).max() <= 1e-9 * math.sqrt(B * C), j
+        assert np.abs(mg[1] - mo[1]).max() <= 1e-9 * B, j
+        assert np.abs(mg[2] - mo[2]).max() <= 1e-9 * C, j
 
 
 def _abs_grad_magnitude(theta, X, do):
@@ -172,7 +180,7 @@ def _abs_grad_magnitude(theta, X, do):
 
 
 def test_loss_and_gradient_match_oracle(pairs):
-    rb, g, net, m, Xo, Mo, bands = pairs
+    rb, g, net, m, Xo, Mo, lens = pairs
     th = net.get_params().astype(np.float64)
     L, grad = net.loss_grad()
     thb = om.bf16_round(th)
@@ -192,7 +200,7 @@ def test_loss_and_gradient_match_oracle(pairs):
 
 
 def test_adam_step_matches_oracle(pairs):
-    rb, g, net, m, Xo, Mo, bands = pairs
+    rb, g, net, m, Xo, Mo, lens = pairs
     th = _theta(5, 300.0)
     net.set_params(th)
     lr = 1e-3
@@ -210,7 +218,7 @@ def test_adam_step_matches_oracle(pairs):
 
 
 def test_training_lowers_the_loss(pairs):
-    rb, g, net, m, Xo, Mo, bands = pairs
+    rb, g, net, m, Xo, Mo, lens = pairs
     net.set_params(_theta(5, 300.0))
     hist = net.train(200, 3e-3)
     L_end, _ = net.loss_grad()
@@ -236,6 +244,8 @@ def test_learned_pcg_steps_match_oracle():
     mp = SphereMap(g.miller(), m.miller)
     g.set_coeffs(inputs.random_coefficients(g.miller(), s["cell"], g.nb, s["seed"]), True)
     th = _theta(9, 300.0)
+    om.unpack(th)["W1"][:, 0] *= 4.0  # a strong dependence on |G|^2
+    th = th.astype(np.float32).astype(np.float64)
     net = rb.Mlp(th)
     g.set_mlp(net)
     thb = om.bf16_round(th)
@@ -246,11 +256,12 @@ def test_learned_pcg_steps_match_oracle():
     for i in range(3):
         gr = orc.gradient(m, st.psi)
         F = om.band_features(m, st.psi, gr.gI, g2sh)
-        sc = np.ones((m.nb, m.npw))
+        s_shell = np.full(F.shape[:2], np.nan)
         for n in range(m.nb):
             if not np.isnan(F[n, 0, 0]):
-                sc[n] = om.scale_of(om.forward(thb, F[n])[0])[shell_of]
-        spread.append(sc.max() / sc.min())
+                s_shell[n] = om.scale_of(om.forward(thb, F[n])[0])
+        sc = om.normalized_scale(m, gr.gI, s_shell, shell_of)
+        spread.append(max(sc[n].max() / sc[n].min() for n in range(m.nb)))
         oi = orc.pcg_step(m, st, scale=sc)
         gi = g.pcg_step()
         assert gi["learned"] == 1 and gi["fallback"] == 0
@@ -258,7 +269,7 @@ def test_learned_pcg_steps_match_oracle():
         print("step", i, "E1 gpu %.12f oracle %.12f, s spread %.3f" % (gi["E1"], oi.E1, spread[-1]))
         assert abs(gi["E0"] - oi.E0) < 1e-5 * dE + 1e-10 * abs(oi.E0), i
         assert abs(gi["E1"] - oi.E1) < 1e-5 * dE + 1e-10 * abs(oi.E0), i
-    assert min(spread) > 1.2  # the rescaling is not a no-op
+    assert min(spread) > 1.2  # within a band the rescaling is not a no-op
     assert rel(mp.to_full(g.get_coeffs()), st.psi) < 1e-5
     g.set_mlp(None)
     assert g.pcg_step()["learned"] == 0

@@ -130,6 +130,29 @@ def test_three_cg_steps_and_forces(pair):
     assert np.abs(F - Fo).max() < 1e-8 * max(1.0, np.abs(Fo).max())
 
 
+def test_periodic_restart_matches_oracle():
+    """Reading R23 on both sides: 12 steps with a restart every 5."""
+    rb = ensure_built()
+    s = inputs.tiny_cell()
+    print("restart case tiny", flush=True)
+    m = orc.Model(s)
+    g = rb.Roks(s)
+    g.set_coeffs(inputs.random_coefficients(g.miller(), s["cell"], g.nb, s["seed"]), True)
+    g.set_restart(5)
+    st = orc.CGState(psi=orc.orthonormalize(inputs.random_coefficients(m.miller, m.cell, m.nb, s["seed"])),
+                     dt=orc.DT_INIT, restart_period=5)
+    flags = []
+    for i in range(12):
+        gi = g.pcg_step()
+        oi = orc.pcg_step(m, st)
+        flags.append(gi["restarted"])
+        assert bool(gi["restarted"]) == bool(oi.restarted), i
+        assert (gi["beta"] == 0.0) == (oi.beta == 0.0), i
+        assert abs(gi["E1"] - oi.E1) < 1e-9 * max(1.0, abs(oi.E0)), i
+    assert flags[5] == 1 and flags[10] == 1
+    g.close()
+
+
 def test_state_errors():
     rb = ensure_built()
     r = rb.Roks(inputs.tiny_cell())

@@ -106,3 +106,49 @@ def test_untrained_network_is_near_plain_teter():
     X = np.random.default_rng(3).normal(size=(100, 3))
     s = mlp.scale_of(mlp.forward(th, X)[0])
     assert np.abs(s - 1).max() < 0.1
+
+
+def test_normalized_scale_keeps_the_plain_first_order_decrease():
+    m = roks.Model(inputs.molecule_box(natoms=2, nb=8, N=16, L=8.0))
+    psi = roks.orthonormalize(inputs.random_coefficients(m.miller, m.cell, m.nb, 4))
+    gr = roks.gradient(m, psi)
+    g2sh, shell_of = mlp.g_shells(0.5 * m.g2)
+    rng = np.random.default_rng(5)
+    s_shell = np.exp(rng.uniform(-2, 2, size=(m.nb, len(g2sh))))
+    s_shell[0] = np.nan  # a band without features keeps s = 1
+    sc = mlp.normalized_scale(m, gr.gI, s_shell, shell_of)
+    p1 = roks.precondition(m, psi, gr.gI, scale=sc)
+    p0 = roks.precondition(m, psi, gr.gI)
+    d1 = sum(roks.dot(p1[n], gr.gI[n]) for n in range(1, m.nb))
+    d0 = sum(roks.dot(p0[n], gr.gI[n]) for n in range(1, m.nb))
+    assert abs(d1 - d0) <= 1e-12 * abs(d0)
+    assert abs(roks.dot(p1[0], gr.gI[0]) - roks.dot(p0[0], gr.gI[0])) <= 1e-12 * abs(d0)
+    np.testing.assert_allclose(sc[0], 1.0)
+    occupied = [n for n in range(1, m.nb) if roks.dot(gr.gI[n], gr.gI[n]) > 0]
+    assert len(occupied) >= 3
+    # per band the first-order change is redistributed, not kept
+    per = [roks.dot(p1[n], gr.gI[n]) / roks.dot(p0[n], gr.gI[n]) for n in occupied]
+    assert max(per) / min(per) > 1.1
+    # a factor constant over all bands and shells is removed entirely
+    sc2 = mlp.normalized_scale(m, gr.gI, np.full((m.nb, len(g2sh)), 3.7), shell_of)
+    np.testing.assert_allclose(sc2, 1.0, rtol=1e-13)
+
+
+def test_moments_are_energy_norm_products_split_by_shell():
+    m = roks.Model(inputs.molecule_box(natoms=2, nb=6, N=16, L=8.0))
+    x = inputs.random_coefficients(m.miller, m.cell, m.nb, 21)
+    y = inputs.random_coefficients(m.miller, m.cell, m.nb, 22)
+    ekin = np.linspace(0.5, 2.0, m.nb)
+    g2sh, shell_of = mlp.g_shells(0.5 * m.g2)
+    a, b, c = mlp.moments(m, x, y, shell_of, len(g2sh), ekin)
+    # summed over shells: <x|T|y> + ekin <x|y> from the model's own kinetic operator
+    xTy = np.real(np.sum(np.conj(x) * (0.5 * m.g2) * y, axis=1))
+    np.testing.assert_allclose(a.sum(1), xTy + ekin * np.array([roks.dot(x[n], y[n]) for n in range(m.nb)]),
+                               rtol=1e-12)
+    np.testing.assert_allclose(b.sum(1), roks.band_kinetic(m, x) + ekin * np.sum(np.abs(x) ** 2, 1), rtol=1e-12)
+    np.testing.assert_allclose(c.sum(1), roks.band_kinetic(m, y) + ekin * np.sum(np.abs(y) ** 2, 1), rtol=1e-12)
+    # each shell holds only its own |G|^2: moving one G's weight to another
+    # shell changes exactly those two entries
+    k = shell_of[5]
+    assert np.all(np.isclose(g2sh[shell_of], 0.5 * m.g2, rtol=0, atol=1e-9))
+    assert b[0, k] > 0

@@ -444,3 +444,18 @@ def test_p22_electron_count(tiny, tiny_psi):
     for L in range(tiny.nconf):
         ne = tiny.integrate(pot.rho[L].sum(axis=0))
         assert abs(ne - tiny.occ[L].sum()) < 1e-12
+
+
+def test_periodic_restart_is_a_fresh_state(tiny, tiny_psi):
+    """Reading R23: with restart period 2 the third step equals a step from a
+    fresh CG state at the same orbitals (directions and step length dropped)."""
+    st = roks.CGState(psi=tiny_psi.copy(), dt=roks.DT_INIT, restart_period=2)
+    i1 = roks.pcg_step(tiny, st)
+    i2 = roks.pcg_step(tiny, st)
+    assert not i1.restarted and i2.beta != 0.0
+    fresh = roks.CGState(psi=st.psi.copy(), dt=roks.DT_INIT)
+    i3 = roks.pcg_step(tiny, st)
+    f3 = roks.pcg_step(tiny, fresh)
+    assert i3.restarted and i3.beta == 0.0
+    assert (i3.E1, i3.delta) == (f3.E1, f3.delta)
+    np.testing.assert_array_equal(st.psi, fresh.psi)
