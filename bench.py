@@ -246,6 +246,21 @@ def converge_report(system, tol=1e-6):
     return out
 
 
+def calibrate_copy(mib=512, reps=3):
+    """A plain copy kernel of known size (y = 1.0 * x, FP32, contiguous) for
+    scaling the FETCH_SIZE / WRITE_SIZE counters: it reads and writes
+    exactly `mib` MiB per launch."""
+    import torch
+    n = mib * 1024 * 1024 // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_kernel": "elementwise y = 1.0 * x (torch.mul, FP32)", "launches": reps,
+                      "read_bytes_per_launch": 4 * n, "write_bytes_per_launch": 4 * n}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,7 +268,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run the copy kernel that scales the HBM byte counters")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)

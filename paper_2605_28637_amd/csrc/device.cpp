@@ -77,6 +77,13 @@ void init_device(Ctx& c, void* stream) {
                      &c.d_Ukeep, &c.d_m4};
   for (double** m : mats) *m = dalloc<double>(c, nn);
   c.d_flag = dalloc<int32_t>(c, 16);
+  c.d_stage = dalloc<double>(c, kStage + 4 * (size_t)nb);
+  ROKS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_scal), (16 + 2 * (size_t)nb) * sizeof(double),
+                         hipHostMallocDefault));
+  ROKS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_stage),
+                         (kStage + 4 * (size_t)nb) * sizeof(double), hipHostMallocDefault));
+  ROKS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_flag), 16 * sizeof(int32_t),
+                         hipHostMallocDefault));
   c.d_force = dalloc<double>(c, 3 * (size_t)std::max(1, c.natoms));
   c.d_kinw_shell = dalloc<double>(c, nb);
   c.d_ones = dalloc<double>(c, nb);
@@ -178,6 +185,10 @@ void free_device(Ctx& c) {
   if (c.stream || !c.allocations.empty()) (void)hipStreamSynchronize(c.stream);
   for (DevBuf& b : c.allocations) (void)hipFree(b.p);
   c.allocations.clear();
+  for (void* h : {(void*)c.h_scal, (void*)c.h_stage, (void*)c.h_flag})
+    if (h) (void)hipHostFree(h);
+  c.h_scal = c.h_stage = nullptr;
+  c.h_flag = nullptr;
 }
 
 }  // namespace roks

@@ -583,6 +583,26 @@ __global__ void k_teter(const double2* __restrict__ g, int npw, int nb, const do
   }
 }
 
+// max |theta_nm - theta_mn| over bands m of shell sa and n of shell sb
+__global__ void __launch_bounds__(256) k_open_coupling(const double* __restrict__ theta, int nb,
+                                                       const int32_t* __restrict__ shell, int sa,
+                                                       int sb, double* __restrict__ out) {
+  __shared__ double red[256];
+  double mx = 0.0;
+  for (int t = threadIdx.x; t < nb * nb; t += 256) {
+    const int m = t / nb, n = t - m * nb;
+    if (shell[m] == sa && shell[n] == sb)
+      mx = fmax(mx, fabs(theta[(size_t)n * nb + m] - theta[(size_t)m * nb + n]));
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
 int blocks_for(size_t n) {
   size_t b = (n + 255) / 256;
   return (int)(b > 8192 ? 8192 : (b == 0 ? 1 : b));
@@ -717,6 +737,12 @@ void launch_subspace(Ctx& c) {
 
 void launch_asym_dot(Ctx& c, const double* A, const double* theta, double* out) {
   hipLaunchKernelGGL(k_asym_dot, dim3(1), dim3(256), 0, c.stream, A, theta, c.nb, out);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_open_coupling(Ctx& c, int sa, int sb, double* out) {
+  hipLaunchKernelGGL(k_open_coupling, dim3(1), dim3(256), 0, c.stream, c.d_theta, c.nb,
+                     c.d_band_shell, sa, sb, out);
   ROKS_HIP(hipGetLastError());
 }
 

@@ -185,6 +185,11 @@ struct Ctx {
   double* d_dP = nullptr;        // [nproj][nb] derivative projections
   double2* d_hch = nullptr;      // [4][nb][npw] multi-channel apply output (lazy)
   double* d_scal = nullptr;      // [16 + 2 nb]: reduced energy sums, then kin, enl
+  double* d_stage = nullptr;     // [kStage + 4 nb] step scalars fetched together
+  // pinned host mirrors (one stream-ordered copy, one synchronisation)
+  double* h_scal = nullptr;      // [16 + 2 nb]
+  double* h_stage = nullptr;     // [kStage + 4 nb]
+  int32_t* h_flag = nullptr;     // [16]
   double* d_m4 = nullptr;
   double* d_kinw_shell = nullptr;  // [nb] shell weight of each band (0 for virtual)
   double* d_ones = nullptr;        // [nb] ones
@@ -352,6 +357,8 @@ void launch_subspace(Ctx& c);
 bool expm_in_lds(const Ctx& c);
 void launch_expm_lds(Ctx& c, const double* D, double delta, double* U);
 void launch_asym_dot(Ctx& c, const double* A, const double* theta, double* out);
+// max |theta_nm - theta_mn| over m of shell sa, n of shell sb (one value)
+void launch_open_coupling(Ctx& c, int sa, int sb, double* out);
 void launch_teter(Ctx& c, const double* gTg, const double* gg, const double2* g, const double* bandw,
                   double2* out);
 
@@ -395,5 +402,7 @@ T* dalloc(Ctx& c, size_t count) {
 }
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+constexpr int kStage = 16;  // scalar slots ahead of the per-band ones in d_stage
 
 }  // namespace roks

@@ -22,26 +22,20 @@ void to_host(Ctx& c, void* dst, const void* src, size_t bytes) {
   ROKS_HIP(hipStreamSynchronize(c.stream));
 }
 
-void copy_dev(Ctx& c, void* dst, const void* src, size_t bytes) {
-  ROKS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c.stream));
+// stream-ordered copy into pinned host memory; read it after sync()
+void fetch(Ctx& c, void* dst, const void* src, size_t bytes) {
+  ROKS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c.stream));
 }
 
-double host_sum(const std::vector<double>& v) {
-  double s = 0.0;
-  for (double x : v) s += x;
-  return s;
+void sync(Ctx& c) { ROKS_HIP(hipStreamSynchronize(c.stream)); }
+
+void copy_dev(Ctx& c, void* dst, const void* src, size_t bytes) {
+  ROKS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c.stream));
 }
 
 double* dbl(double2* p) { return reinterpret_cast<double*>(p); }
 const double* dbl(const double2* p) { return reinterpret_cast<const double*>(p); }
 
-// sum over bands of the weighted inner products <x_n|y_n>
-double total_dot(Ctx& c, const double2* x, const double2* y) {
-  band_dots(c, x, y, c.nb, 0, c.d_bandv);
-  std::vector<double> h(c.nb);
-  to_host(c, h.data(), c.d_bandv, c.nb * sizeof(double));
-  return host_sum(h);
-}
 
 // U = exp(X) for X = delta * D (antisymmetric): scaling and squaring with a
 // degree-16 Taylor polynomial in Horner form
@@ -79,6 +73,13 @@ void expm(Ctx& c, double delta, const double* D, double* U) {
   copy_dev(c, U, cur, nn * sizeof(double));
 }
 
+}  // namespace
+
+void compute_potentials_async(Ctx& c, const double2* orb);
+roks_energies assemble_energies(const Ctx& c);
+
+namespace {
+
 struct Trial {
   double2* psi;
   double* M;
@@ -88,22 +89,25 @@ struct Trial {
   bool ok;
 };
 
-// Psi(delta) = U^T L^-1 (Psi + delta S), U = exp(delta D); its energy
+// Psi(delta) = U^T L^-1 (Psi + delta S), U = exp(delta D); its energy.  One
+// synchronisation: the Cholesky status and the energy sums come back together
+// (a failed factorisation only makes the rest of the evaluation meaningless).
 void evaluate_trial(Ctx& c, double delta, Trial& t) {
   const int nb = c.nb, K = 2 * c.npw;
   const size_t band = (size_t)nb * c.npw;
   axpby(c, 2 * band, 1.0, dbl(c.d_psi), delta, dbl(c.d_S), dbl(c.d_Pt));
   gemm_wdot(c, nb, nb, K, dbl(c.d_Pt), K, dbl(c.d_Pt), K, c.d_gram, nb, 1.0, 0.0, true);
   cholesky_inverse(c, c.d_gram, nb, c.d_Linv, c.d_flag);
-  int32_t flag = 0;
-  to_host(c, &flag, c.d_flag, sizeof(int32_t));
-  t.ok = flag == 0;
-  t.E = INFINITY;
-  if (!t.ok) return;
+  fetch(c, c.h_flag, c.d_flag, sizeof(int32_t));
   expm(c, delta, c.d_D, t.U);
   gemm_small(c, nb, nb, nb, t.U, nb, true, c.d_Linv, nb, false, t.M, nb, 1.0, 0.0);
   gemm_expand(c, nb, K, nb, t.M, nb, true, dbl(c.d_Pt), K, dbl(t.psi), K, 1.0, 0.0);
-  compute_potentials(c, t.psi, &t.e);
+  compute_potentials_async(c, t.psi);
+  sync(c);
+  t.ok = c.h_flag[0] == 0;
+  t.E = INFINITY;
+  if (!t.ok) return;
+  t.e = assemble_energies(c);
   t.E = t.e.E;
   if (!std::isfinite(t.E)) {
     t.ok = false;
@@ -116,7 +120,9 @@ void evaluate_trial(Ctx& c, double delta, Trial& t) {
 // ---------------------------------------------------------------------------
 // densities, potentials and energies of `orb` (Sec. II A, H^{sigma L})
 // ---------------------------------------------------------------------------
-void compute_potentials(Ctx& c, const double2* orb, roks_energies* e) {
+// every launch of the energy evaluation; the reduced sums are copied to the
+// pinned mirror h_scal, read by assemble_energies after a synchronisation
+void compute_potentials_async(Ctx& c, const double2* orb) {
   const int nb = c.nb, K = 2 * c.npw;
   launch_zpass_bwd(c, orb, nb, c.d_T, c.npairs);
   launch_plane_density(c, c.d_T, c.npairs, c.d_rho_part, c.nchunk);
@@ -137,10 +143,14 @@ void compute_potentials(Ctx& c, const double2* orb, roks_energies* e) {
   } else {
     ROKS_HIP(hipMemsetAsync(c.d_enl, 0, nb * sizeof(double), c.stream));
   }
-  std::vector<double> h(16 + 2 * (size_t)nb);
-  to_host(c, h.data(), c.d_scal, h.size() * sizeof(double));
-  const double* kin = h.data() + 16;
-  const double* enl = h.data() + 16 + nb;
+  fetch(c, c.h_scal, c.d_scal, (16 + 2 * (size_t)nb) * sizeof(double));
+}
+
+roks_energies assemble_energies(const Ctx& c) {
+  const int nb = c.nb;
+  const double* h = c.h_scal;
+  const double* kin = h + 16;
+  const double* enl = h + 16 + nb;
   roks_energies out{};
   const double dv = c.omega / (double)c.ntot;
   double E = 0.0;
@@ -160,6 +170,13 @@ void compute_potentials(Ctx& c, const double2* orb, roks_energies* e) {
     E += c.cL[L] * out.E_L[L];
   }
   out.E = E;
+  return out;
+}
+
+void compute_potentials(Ctx& c, const double2* orb, roks_energies* e) {
+  compute_potentials_async(c, orb);
+  sync(c);
+  const roks_energies out = assemble_energies(c);
   if (e) *e = out;
   c.potentials_valid = (orb == c.d_psi);
 }
@@ -220,7 +237,7 @@ void energy_gradient(Ctx& c, roks_energies* e) {
   ROKS_CHECK(c.have_orbitals, ROKS_ERR_STATE, "no orbitals set");
   const int nb = c.nb, K = 2 * c.npw;
   const size_t band = (size_t)nb * c.npw;
-  compute_potentials(c, c.d_psi, &c.last_e);
+  if (!c.potentials_valid) compute_potentials(c, c.d_psi, &c.last_e);
   ROKS_CHECK(std::isfinite(c.last_e.E), ROKS_ERR_NAN, "non-finite energy");
   if (e) *e = c.last_e;
   apply_operator(c, c.d_psi, 0, c.d_Y, true);
@@ -265,6 +282,20 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   }
   if (recording) record_iterate(c, c.d_bandv, c.d_bandv + nb, c.d_bandv + 4 * nb);
   const double* bandw = (c.flags & ROKS_FLAG_WEIGHT_PRECOND) ? c.d_kinw_shell : nullptr;
+  // step scalars in d_stage: [0] sum A (theta - theta^T), [1] the same for D,
+  // [2] max open-shell coupling, [kStage + n] <p_n|g_n>, [kStage + nb + n]
+  // <g_n|g_n>, [kStage + 2 nb + n] <S_n|g_n>; sums over bands in band order
+  double* st = c.d_stage;
+  const double* hs = c.h_stage;
+  auto band_sum = [&](int off) {
+    double v = 0.0;
+    for (int n = 0; n < nb; ++n) v += hs[kStage + off + n];
+    return v;
+  };
+  int opens[kMaxShell], no = 0;
+  for (int X = 0; X < c.nshell; ++X)
+    if (!c.shell_closed[X] && !c.shell_virtual[X]) opens[no++] = X;
+  bool first_fetch = true;
   auto precondition = [&](bool learned) {
     if (learned)
       launch_teter_scaled(c, c.d_bandv, c.d_bandv + nb, c.d_gI, bandw, c.d_w1);
@@ -274,14 +305,24 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     copy_dev(c, c.d_p, c.d_w1, band * sizeof(double2));
     gemm_expand(c, nb, K, nb, c.d_m1, nb, false, dbl(c.d_psi), K, dbl(c.d_p), K, -1.0, 1.0);
     // <p|g> = sum <p_I|g_I> + 1/2 sum A (theta - theta^T)
-    launch_asym_dot(c, c.d_A, c.d_theta, c.d_bandv + 2 * nb);
-    double asymA = 0.0;
-    const double pgI = total_dot(c, c.d_p, c.d_gI);
-    to_host(c, &asymA, c.d_bandv + 2 * nb, sizeof(double));
-    return pgI + 0.5 * asymA;
+    launch_asym_dot(c, c.d_A, c.d_theta, st);
+    band_dots(c, c.d_p, c.d_gI, nb, 0, st + kStage);
+    if (first_fetch) {
+      // with the report's |g_I| and open-shell coupling
+      copy_dev(c, st + kStage + nb, c.d_bandv + nb, nb * sizeof(double));
+      if (no == 2) launch_open_coupling(c, opens[0], opens[1], st + 2);
+      fetch(c, c.h_stage, st, (kStage + 2 * (size_t)nb) * sizeof(double));
+    } else {
+      fetch(c, c.h_stage, st, (kStage + (size_t)nb) * sizeof(double));
+    }
+    sync(c);
+    first_fetch = false;
+    return band_sum(0) + 0.5 * hs[0];
   };
   const bool learned = c.mlp != nullptr;
   double pg = precondition(learned);
+  const double gnorm = std::sqrt(std::max(0.0, band_sum(nb)));
+  const double max_rab = no == 2 ? hs[2] : 0.0;
   double beta = (c.have_old && c.pg_old != 0.0) ? pg / c.pg_old : 0.0;
   bool restarted = periodic;
 
@@ -299,34 +340,18 @@ void pcg_step(Ctx& c, roks_step_info* info) {
       copy_dev(c, c.d_S, c.d_p, band * sizeof(double2));
       copy_dev(c, c.d_D, c.d_A, nn * sizeof(double));
     }
-    launch_asym_dot(c, c.d_D, c.d_theta, c.d_bandv + 3 * nb);
-    const double sg = total_dot(c, c.d_S, c.d_gI);
-    double asymD = 0.0;
-    to_host(c, &asymD, c.d_bandv + 3 * nb, sizeof(double));
-    return 2.0 * sg + asymD;
+    launch_asym_dot(c, c.d_D, c.d_theta, st + 1);
+    band_dots(c, c.d_S, c.d_gI, nb, 0, st + kStage + 2 * nb);
+    fetch(c, c.h_stage + 1, st + 1, sizeof(double));
+    fetch(c, c.h_stage + kStage + 2 * nb, st + kStage + 2 * nb, nb * sizeof(double));
+    sync(c);
+    return 2.0 * band_sum(2 * nb) + hs[1];
   };
   double dE0 = directions(beta);
   if (beta != 0.0 && dE0 >= 0.0) {
     beta = 0.0;
     restarted = true;
     dE0 = directions(0.0);
-  }
-
-  // norms for the report
-  const double gnorm = std::sqrt(std::max(0.0, total_dot(c, c.d_gI, c.d_gI)));
-  double max_rab = 0.0;
-  {
-    int opens[kMaxShell], no = 0;
-    for (int X = 0; X < c.nshell; ++X)
-      if (!c.shell_closed[X] && !c.shell_virtual[X]) opens[no++] = X;
-    if (no == 2) {
-      std::vector<double> th(nn);
-      to_host(c, th.data(), c.d_theta, nn * sizeof(double));
-      for (int m = 0; m < nb; ++m)
-        for (int n = 0; n < nb; ++n)
-          if (c.band_shell[m] == opens[0] && c.band_shell[n] == opens[1])
-            max_rab = std::max(max_rab, std::fabs(th[(size_t)n * nb + m] - th[(size_t)m * nb + n]));
-    }
   }
 
   Trial tr[2] = {{c.d_trial, c.d_M, c.d_U, 0, {}, false},
@@ -411,8 +436,12 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   c.dt = std::min(kDtMax, std::max(kDtMin, delta));
   c.iteration++;
   r.iteration = c.iteration;
-  c.potentials_valid = false;
-  ROKS_HIP(hipStreamSynchronize(c.stream));
+  // the last trial evaluated is tr[1]: when it is the one taken, its
+  // densities, potentials, projections and energies are those of the new
+  // orbitals (the same kernels on the same values), so they are kept
+  c.potentials_valid = (best == 1);
+  if (best == 1) c.last_e = t.e;
+  sync(c);
   if (info) *info = r;
 }
 
