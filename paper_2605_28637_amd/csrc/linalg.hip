@@ -405,16 +405,21 @@ __global__ void __launch_bounds__(1024) k_cholesky_inverse_lds(const double* __r
   if (tid == 0) flag[0] = bad;
 }
 
-// exp(delta D) for n <= 78 in one workgroup: 1-norm, scaling by 2^-s with
-// ||X|| <= 1/2, degree-16 Taylor in Horner form, s squarings; X, P, Q in LDS
+// U = exp(delta D) in one workgroup, the three n x n matrices in LDS:
+// scaling and squaring around a Taylor polynomial in Horner form.  The
+// degree m and the squarings s minimise the products m + s subject to
+// theta^(m+1)/(m+1)! <= 1e-17 with theta = ||delta D||_1 / 2^s <= 1 (the
+// Taylor tail; exp of an antisymmetric matrix is orthogonal, so the bound is
+// relative).  Products run as 2 x 2 register blocks.
 __global__ void __launch_bounds__(1024) k_expm_lds(const double* __restrict__ D, int n, double delta,
                                                   double* __restrict__ U) {
   extern __shared__ double S[];
   __shared__ double nrm;
-  double* X = S;
-  double* P = S + n * n;
-  double* Q = P + n * n;
+  __shared__ int plan[2];
   const int tid = threadIdx.x, nthr = blockDim.x, nn = n * n;
+  double* X = S;
+  double* P = S + nn;
+  double* Q = P + nn;
   for (int t = tid; t < nn; t += nthr) X[t] = delta * D[t];
   __syncthreads();
   if (tid < 64) {
@@ -426,51 +431,73 @@ __global__ void __launch_bounds__(1024) k_expm_lds(const double* __restrict__ D,
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-    if (tid == 0) nrm = mx;
+    if (tid == 0) {
+      nrm = mx;
+      int best_s = 0, best_m = isfinite(mx) ? 30 : 1, best = isfinite(mx) ? 1 << 30 : 0;
+      for (int sq = 0; sq <= 60; ++sq) {
+        const double th = ldexp(mx, -sq);
+        if (th > 1.0) continue;
+        double term = th;  // th^(m+1)/(m+1)!
+        int m = 0;
+        while (term > 1e-17 && m < 30) {
+          ++m;
+          term *= th / (m + 1);
+        }
+        if (m + sq < best) {
+          best = m + sq;
+          best_s = sq;
+          best_m = m;
+        }
+        if (m <= 1) break;
+      }
+      plan[0] = best_s;
+      plan[1] = best_m;
+    }
   }
   __syncthreads();
-  double v = nrm;
-  int sq = 0;
-  while (v > 0.5) {
-    v *= 0.5;
-    ++sq;
-  }
+  const int sq = plan[0], m = plan[1];
   const double scale = ldexp(1.0, -sq);
   for (int t = tid; t < nn; t += nthr) {
     X[t] *= scale;
-    P[t] = X[t] / 16.0 + ((t / n) == (t % n) ? 1.0 : 0.0);
+    const double id = (t / n) == (t % n) ? 1.0 : 0.0;
+    P[t] = m >= 1 ? X[t] / (double)m + id : id;
   }
   __syncthreads();
-  // products with four independent partial sums per output (the k loop is a
-  // latency chain otherwise)
-  auto prod = [&](const double* L, const double* R, int i, int j) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int k = 0;
-    for (; k + 3 < n; k += 4) {
-      s0 = fma(L[i * n + k], R[k * n + j], s0);
-      s1 = fma(L[i * n + k + 1], R[(k + 1) * n + j], s1);
-      s2 = fma(L[i * n + k + 2], R[(k + 2) * n + j], s2);
-      s3 = fma(L[i * n + k + 3], R[(k + 3) * n + j], s3);
-    }
-    for (; k < n; ++k) s0 = fma(L[i * n + k], R[k * n + j], s0);
-    return (s0 + s1) + (s2 + s3);
-  };
-  for (int q = 15; q >= 1; --q) {
-    for (int t = tid; t < nn; t += nthr) {
-      const int i = t / n, j = t - i * n;
-      Q[t] = prod(X, P, i, j) / q + (i == j ? 1.0 : 0.0);
+  const int nh = (n + 1) / 2;
+  // O = L R * f (+ I when add_id)
+  auto product = [&](const double* L, const double* R, double* O, double f, bool add_id) {
+    for (int b = tid; b < nh * nh; b += nthr) {
+      const int bi = b / nh, bj = b - bi * nh;
+      const int i0 = 2 * bi, j0 = 2 * bj;
+      const bool i1 = i0 + 1 < n, j1 = j0 + 1 < n;
+      double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
+      for (int k = 0; k < n; ++k) {
+        const double a0 = L[i0 * n + k];
+        const double a1 = i1 ? L[(i0 + 1) * n + k] : 0.0;
+        const double b0 = R[k * n + j0];
+        const double b1 = j1 ? R[k * n + j0 + 1] : 0.0;
+        c00 = fma(a0, b0, c00);
+        c01 = fma(a0, b1, c01);
+        c10 = fma(a1, b0, c10);
+        c11 = fma(a1, b1, c11);
+      }
+      const double d = add_id ? 1.0 : 0.0;
+      O[i0 * n + j0] = c00 * f + (i0 == j0 ? d : 0.0);
+      if (j1) O[i0 * n + j0 + 1] = c01 * f + (i0 == j0 + 1 ? d : 0.0);
+      if (i1) O[(i0 + 1) * n + j0] = c10 * f + (i0 + 1 == j0 ? d : 0.0);
+      if (i1 && j1) O[(i0 + 1) * n + j0 + 1] = c11 * f + (i0 == j0 ? d : 0.0);
     }
     __syncthreads();
+  };
+  // P_m = I + X/m, P_q = I + X P_{q+1} / q, ..., P_1 = the degree-m polynomial
+  for (int q = m - 1; q >= 1; --q) {
+    product(X, P, Q, 1.0 / (double)q, true);
     double* tmp = P;
     P = Q;
     Q = tmp;
   }
   for (int r = 0; r < sq; ++r) {
-    for (int t = tid; t < nn; t += nthr) {
-      const int i = t / n, j = t - i * n;
-      Q[t] = prod(P, P, i, j);
-    }
-    __syncthreads();
+    product(P, P, Q, 1.0, false);
     double* tmp = P;
     P = Q;
     Q = tmp;

@@ -37,8 +37,10 @@ double* dbl(double2* p) { return reinterpret_cast<double*>(p); }
 const double* dbl(const double2* p) { return reinterpret_cast<const double*>(p); }
 
 
-// U = exp(X) for X = delta * D (antisymmetric): scaling and squaring with a
-// degree-16 Taylor polynomial in Horner form
+// U = exp(X) for X = delta * D (antisymmetric): scaling and squaring around a
+// Taylor polynomial in Horner form, the degree m and squarings s chosen as in
+// the single-workgroup kernel (fewest products with theta^(m+1)/(m+1)! <= 1e-17,
+// theta = ||X||_1 / 2^s <= 1)
 void expm(Ctx& c, double delta, const double* D, double* U) {
   if (expm_in_lds(c)) {
     launch_expm_lds(c, D, delta, U);
@@ -51,18 +53,30 @@ void expm(Ctx& c, double delta, const double* D, double* U) {
   double nrm = 0.0;
   to_host(c, &nrm, c.d_bandv, sizeof(double));
   ROKS_CHECK(std::isfinite(nrm), ROKS_ERR_NAN, "non-finite rotation generator");
-  int s = 0;
-  while (nrm > 0.5) {
-    nrm *= 0.5;
-    ++s;
+  int s = 0, m = 30, best = 1 << 30;
+  for (int sq = 0; sq <= 60; ++sq) {
+    const double th = std::ldexp(nrm, -sq);
+    if (th > 1.0) continue;
+    double term = th;
+    int mm = 0;
+    while (term > 1e-17 && mm < 30) {
+      ++mm;
+      term *= th / (mm + 1);
+    }
+    if (mm + sq < best) {
+      best = mm + sq;
+      s = sq;
+      m = mm;
+    }
+    if (mm <= 1) break;
   }
   if (s > 0) axpby(c, nn, std::ldexp(1.0, -s), c.d_m1, 0.0, nullptr, c.d_m1);
-  // P_16 = I + X/16, P_q = I + X P_{q+1} / q, ..., P_1 = exp(X) to degree 16
+  // P_m = I + X/m, P_q = I + X P_{q+1} / q, ..., P_1
   set_identity(c, c.d_m2, n, 1.0);
-  axpby(c, nn, 1.0 / 16.0, c.d_m1, 1.0, c.d_m2, c.d_m2);
+  if (m >= 1) axpby(c, nn, 1.0 / m, c.d_m1, 1.0, c.d_m2, c.d_m2);
   double* cur = c.d_m2;
   double* nxt = c.d_m4;
-  for (int q = 15; q >= 1; --q) {
+  for (int q = m - 1; q >= 1; --q) {
     gemm_small(c, n, n, n, c.d_m1, n, false, cur, n, false, nxt, n, 1.0 / q, 0.0, 1.0);
     std::swap(cur, nxt);
   }

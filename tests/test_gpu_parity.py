@@ -130,6 +130,31 @@ def test_three_cg_steps_and_forces(pair):
     assert np.abs(F - Fo).max() < 1e-8 * max(1.0, np.abs(Fo).max())
 
 
+@pytest.mark.parametrize("nb", [90, 140])
+def test_cg_steps_with_many_bands(nb):
+    """Band counts past the single-workgroup rotation (nb > 78) and, at 140,
+    past the LDS Cholesky (nb > 128): the multi-kernel exponential and the
+    global-memory factorisation in the line search."""
+    rb = ensure_built()
+    s = small_molecule(nb=nb)
+    print("many-band case", nb, flush=True)
+    m = orc.Model(s)
+    g = rb.Roks(s)
+    g.set_coeffs(inputs.random_coefficients(g.miller(), s["cell"], g.nb, s["seed"]), True)
+    st = orc.CGState(psi=orc.orthonormalize(inputs.random_coefficients(m.miller, m.cell, m.nb, s["seed"])),
+                     dt=orc.DT_INIT)
+    for i in range(2):
+        gi = g.pcg_step()
+        oi = orc.pcg_step(m, st)
+        scale = max(1.0, abs(oi.E0))
+        assert abs(gi["E0"] - oi.E0) < TOL * scale, i
+        assert abs(gi["E1"] - oi.E1) < TOL * scale, i
+        assert abs(gi["delta"] - oi.delta) < 1e-8 * max(1.0, oi.delta), i
+    mp = SphereMap(g.miller(), m.miller)
+    assert rel(mp.to_full(g.get_coeffs()), st.psi) < 1e-8
+    g.close()
+
+
 def test_periodic_restart_matches_oracle():
     """Reading R23 on both sides: 12 steps with a restart every 5."""
     rb = ensure_built()
