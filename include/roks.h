@@ -169,7 +169,9 @@ roks_status roks_gvectors(roks_ctx ctx, int32_t* miller);
 
 /* Set the orbitals from c [nbands][npw][2]; orthonormalize != 0 applies the
  * Cholesky orthonormalisation in band order (Gram-Schmidt).  Resets the CG
- * state.  roks_get_coeffs copies the current orbitals out. */
+ * state.  roks_pcg_step / roks_solve take the orbitals to be orthonormal
+ * (every step keeps them so): pass orthonormalize = 0 only for orthonormal
+ * input.  roks_get_coeffs copies the current orbitals out. */
 roks_status roks_set_coeffs(roks_ctx ctx, const double* c, int32_t orthonormalize);
 roks_status roks_get_coeffs(roks_ctx ctx, double* c);
 roks_status roks_set_coeffs_d(roks_ctx ctx, const void* c_dev, int32_t orthonormalize);

@@ -60,6 +60,9 @@ void init_device(Ctx& c, void* stream) {
   c.d_P = dalloc<double>(c, np * nb);
   c.d_DP = dalloc<double>(c, np * nb);
   c.d_dP = dalloc<double>(c, np * nb);
+  c.d_P0 = dalloc<double>(c, np * nb);
+  c.d_PS = dalloc<double>(c, np * nb);
+  c.d_Pq = dalloc<double>(c, np * nb);
   c.part_capacity = std::max<size_t>(6 * 1024, (size_t)c.natoms * 32 * 3) + 64;
   c.d_part = dalloc<double>(c, c.part_capacity);
   c.d_scal = dalloc<double>(c, 16 + 2 * nb);
@@ -74,7 +77,7 @@ void init_device(Ctx& c, void* stream) {
   const size_t nn = nb * nb;
   double** mats[] = {&c.d_theta, &c.d_R, &c.d_kappa, &c.d_A, &c.d_D, &c.d_Dold, &c.d_gram,
                      &c.d_Linv, &c.d_U, &c.d_M, &c.d_m1, &c.d_m2, &c.d_m3, &c.d_Mkeep,
-                     &c.d_Ukeep, &c.d_m4};
+                     &c.d_Ukeep, &c.d_m4, &c.d_SS};
   for (double** m : mats) *m = dalloc<double>(c, nn);
   c.d_flag = dalloc<int32_t>(c, 16);
   c.d_stage = dalloc<double>(c, kStage + 4 * (size_t)nb);

@@ -129,16 +129,23 @@ struct ProjP {
   double rp;
 };
 
+// naxes = 1: the table of `axis` (-1: the projectors themselves); naxes = 3:
+// the three derivative tables, axis-major [3][nproj][npw]
 __global__ void k_projectors(Lattice L, const int32_t* __restrict__ miller, int npw,
                              const ProjP* __restrict__ proj, int nproj,
-                             const AtomP* __restrict__ atoms, int axis, double2* __restrict__ B) {
-  const size_t total = (size_t)nproj * npw;
+                             const AtomP* __restrict__ atoms, int axis0, int naxes,
+                             double2* __restrict__ B) {
+  const size_t per = (size_t)nproj * npw;
+  const size_t total = per * naxes;
   const double inv_sqrt_omega = 1.0 / sqrt(L.omega);
   const double c0 = 4.0 * M_PI;
   const double c1 = 4.0 * pow(M_PI, 0.75);
   for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
        t += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(t / npw), g = (int)(t - (size_t)i * npw);
+    const int ax = (int)(t / per);
+    const size_t r = t - (size_t)ax * per;
+    const int axis = naxes == 3 ? ax : axis0;
+    const int i = (int)(r / npw), g = (int)(r - (size_t)i * npw);
     const int m[3] = {miller[3 * g], miller[3 * g + 1], miller[3 * g + 2]};
     double G[3];
     gvec(L, m, G);
@@ -420,16 +427,28 @@ __global__ void __launch_bounds__(256) k_local_force(Lattice L, const AtomP* __r
 }
 
 // dE/dR_I,axis (nonlocal) = sum_{i in I} sum_n 2 w_n dP_in (D P)_in
-__global__ void k_nl_force(const double* __restrict__ dP, const double* __restrict__ DP, int nb,
-                           int natoms, const int32_t* __restrict__ off,
-                           const int32_t* __restrict__ cnt, const double* __restrict__ w,
-                           int axis, double* __restrict__ out) {
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= natoms) return;
-  double s = 0;
-  for (int i = off[I]; i < off[I] + cnt[I]; ++i)
-    for (int n = 0; n < nb; ++n) s += 2.0 * w[n] * dP[(size_t)i * nb + n] * DP[(size_t)i * nb + n];
-  out[I * 3 + axis] += s;
+// out[I][a] += 2 sum_{i of atom I} sum_n w_n dP[a][i][n] DP[i][n]: one wave
+// per (atom, axis), lanes over (projector, band), fixed butterfly
+__global__ void __launch_bounds__(256) k_nl_force(const double* __restrict__ dP,
+                                                  const double* __restrict__ DP, int nb, int nproj,
+                                                  int natoms, const int32_t* __restrict__ off,
+                                                  const int32_t* __restrict__ cnt,
+                                                  const double* __restrict__ w,
+                                                  double* __restrict__ out) {
+  const int wave = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (wave >= 3 * natoms) return;
+  const int I = wave / 3, a = wave - 3 * I;
+  const int i0 = off[I], len = cnt[I] * nb;
+  const double* d = dP + (size_t)a * nproj * nb;
+  double s = 0.0;
+  for (int j = lane; j < len; j += 64) {
+    const int i = i0 + j / nb, n = j - (j / nb) * nb;
+    s += 2.0 * w[n] * d[(size_t)i * nb + n] * DP[(size_t)i * nb + n];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) out[I * 3 + a] += s;
 }
 
 // out[o][j] = scale * sum_i part[o][i][j]
@@ -509,7 +528,16 @@ void launch_projectors(Ctx& c, double2* B, int axis) {
   if (n == 0) return;
   const ProjP* pp = reinterpret_cast<const ProjP*>(c.d_projinfo);
   hipLaunchKernelGGL(k_projectors, dim3(grid_blocks(n)), dim3(256), 0, c.stream, lattice(c), c.d_miller,
-                     c.npw, pp, c.nproj, atoms_dev(c), axis, B);
+                     c.npw, pp, c.nproj, atoms_dev(c), axis, 1, B);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_projector_gradients(Ctx& c, double2* dB) {
+  const size_t n = 3 * (size_t)c.nproj * c.npw;
+  if (n == 0) return;
+  const ProjP* pp = reinterpret_cast<const ProjP*>(c.d_projinfo);
+  hipLaunchKernelGGL(k_projectors, dim3(grid_blocks(n)), dim3(256), 0, c.stream, lattice(c), c.d_miller,
+                     c.npw, pp, c.nproj, atoms_dev(c), -1, 3, dB);
   ROKS_HIP(hipGetLastError());
 }
 
@@ -594,11 +622,10 @@ void launch_local_force(Ctx& c, const double2* rhoG, double* out_part, int nblk)
   ROKS_HIP(hipGetLastError());
 }
 
-void launch_nl_force(Ctx& c, const double* dP, const double* DP, const double* w, int axis,
-                     double* out) {
+void launch_nl_force(Ctx& c, const double* dP3, const double* DP, const double* w, double* out) {
   if (c.natoms == 0) return;
-  hipLaunchKernelGGL(k_nl_force, dim3(cdiv(c.natoms, 64)), dim3(64), 0, c.stream, dP, DP, c.nb,
-                     c.natoms, c.d_atom_proj_off, c.d_atom_proj_cnt, w, axis, out);
+  hipLaunchKernelGGL(k_nl_force, dim3(cdiv(3 * c.natoms, 4)), dim3(256), 0, c.stream, dP3, DP, c.nb,
+                     c.nproj, c.natoms, c.d_atom_proj_off, c.d_atom_proj_cnt, w, out);
   ROKS_HIP(hipGetLastError());
 }
 

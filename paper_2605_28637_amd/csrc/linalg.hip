@@ -272,6 +272,14 @@ __global__ void k_set_identity(double* A, int n, double d) {
   A[t] = (i == j) ? d : 0.0;
 }
 
+__global__ void k_scale_shift(const double* __restrict__ in, int n, double a, double d,
+                              double* __restrict__ out) {
+  const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (t >= (size_t)n * n) return;
+  const int i = (int)(t / n), j = (int)(t - (size_t)i * n);
+  out[t] = a * in[t] + ((i == j) ? d : 0.0);
+}
+
 __global__ void k_norm1(const double* A, int n, double* out) {
   __shared__ double red[16];
   double mx = 0.0;
@@ -705,6 +713,13 @@ void set_identity(Ctx& c, double* A, int n, double diag) {
   const size_t nn = (size_t)n * n;
   hipLaunchKernelGGL(k_set_identity, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, c.stream, A, n,
                      diag);
+  ROKS_HIP(hipGetLastError());
+}
+
+void scale_shift(Ctx& c, const double* in, int n, double a, double d, double* out) {
+  const size_t nn = (size_t)n * n;
+  hipLaunchKernelGGL(k_scale_shift, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, c.stream, in, n,
+                     a, d, out);
   ROKS_HIP(hipGetLastError());
 }
 

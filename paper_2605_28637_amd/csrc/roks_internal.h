@@ -177,9 +177,14 @@ struct Ctx {
          *d_Dold = nullptr, *d_gram = nullptr, *d_Linv = nullptr, *d_U = nullptr,
          *d_M = nullptr, *d_m1 = nullptr, *d_m2 = nullptr, *d_m3 = nullptr, *d_Mkeep = nullptr,
          *d_Ukeep = nullptr;
+  double* d_SS = nullptr;        // <S_m|S_n> of the current search direction
+  double* d_P0 = nullptr;        // [nproj][nb] <beta|psi> at the start of the line search
+  double* d_PS = nullptr;        // [nproj][nb] <beta|S>
+  double* d_Pq = nullptr;        // [nproj][nb] scratch
   int32_t* d_flag = nullptr;     // device status flags
   double* d_force = nullptr;     // [natoms][3]
-  double2* d_dB = nullptr;       // [nproj][npw] derivative projector scratch
+  double2* d_dB = nullptr;       // [3][nproj][npw] derivative projector tables (forces)
+  double* d_dP3 = nullptr;       // [3][nproj][nb] derivative projections (forces)
   void* d_atoms = nullptr;       // per-atom position and local-well parameters
   void* d_projinfo = nullptr;    // per-projector atom, l, m, radius
   double* d_dP = nullptr;        // [nproj][nb] derivative projections
@@ -337,8 +342,10 @@ void launch_local_force(Ctx& c, const double2* rhoG, double* out_part, int nblk)
 void launch_pack_rho_weighted(Ctx& c);
 size_t atom_info_bytes();
 size_t proj_info_bytes();
-void launch_nl_force(Ctx& c, const double* dP, const double* P, const double* w, int axis,
-                     double* out);
+// forces from the three derivative projections dP3 [3][nproj][nb]
+void launch_nl_force(Ctx& c, const double* dP3, const double* DP, const double* w, double* out);
+// the three derivative tables -i G_a beta, [3][nproj][npw]
+void launch_projector_gradients(Ctx& c, double2* dB);
 
 // linalg.hip
 void gemm_wdot(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
@@ -352,6 +359,8 @@ void band_dots(Ctx& c, const double2* X, const double2* Y, int nvec, int mode, d
 void axpby(Ctx& c, size_t n, double a, const double* x, double b, const double* y, double* out);
 void cholesky_inverse(Ctx& c, const double* G, int n, double* Linv, int32_t* flag);
 void set_identity(Ctx& c, double* A, int n, double diag);
+// out = a in + d I (n x n)
+void scale_shift(Ctx& c, const double* in, int n, double a, double d, double* out);
 void matrix_norm1(Ctx& c, const double* A, int n, double* out);
 void launch_subspace(Ctx& c);
 bool expm_in_lds(const Ctx& c);

@@ -89,7 +89,7 @@ void expm(Ctx& c, double delta, const double* D, double* U) {
 
 }  // namespace
 
-void compute_potentials_async(Ctx& c, const double2* orb);
+void compute_potentials_async(Ctx& c, const double2* orb, bool have_P);
 roks_energies assemble_energies(const Ctx& c);
 
 namespace {
@@ -103,20 +103,39 @@ struct Trial {
   bool ok;
 };
 
-// Psi(delta) = U^T L^-1 (Psi + delta S), U = exp(delta D); its energy.  One
+// Once per line search (the search direction is fixed): <S|S> and <beta|S>;
+// on the step's first search also <beta|psi> of the current orbitals (left
+// in d_P by their energy evaluation; trials overwrite d_P afterwards).
+void prepare_line_search(Ctx& c, bool first) {
+  const int nb = c.nb, K = 2 * c.npw;
+  gemm_wdot(c, nb, nb, K, dbl(c.d_S), K, dbl(c.d_S), K, c.d_SS, nb, 1.0, 0.0, true);
+  if (c.nproj > 0) {
+    if (first) copy_dev(c, c.d_P0, c.d_P, (size_t)c.nproj * nb * sizeof(double));
+    gemm_wdot(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(c.d_S), K, c.d_PS, nb, 1.0, 0.0, true);
+  }
+}
+
+// Psi(delta) = U^T L^-1 (Psi + delta S), U = exp(delta D); its energy.
+// The orbitals are orthonormal and S is orthogonal to them, so the Gram
+// matrix of Psi + delta S is I + delta^2 <S|S>, and the trial's projections
+// are <beta|Psi + delta S> = P0 + delta PS rotated by M.  One
 // synchronisation: the Cholesky status and the energy sums come back together
 // (a failed factorisation only makes the rest of the evaluation meaningless).
 void evaluate_trial(Ctx& c, double delta, Trial& t) {
   const int nb = c.nb, K = 2 * c.npw;
   const size_t band = (size_t)nb * c.npw;
   axpby(c, 2 * band, 1.0, dbl(c.d_psi), delta, dbl(c.d_S), dbl(c.d_Pt));
-  gemm_wdot(c, nb, nb, K, dbl(c.d_Pt), K, dbl(c.d_Pt), K, c.d_gram, nb, 1.0, 0.0, true);
+  scale_shift(c, c.d_SS, nb, delta * delta, 1.0, c.d_gram);
   cholesky_inverse(c, c.d_gram, nb, c.d_Linv, c.d_flag);
   fetch(c, c.h_flag, c.d_flag, sizeof(int32_t));
   expm(c, delta, c.d_D, t.U);
   gemm_small(c, nb, nb, nb, t.U, nb, true, c.d_Linv, nb, false, t.M, nb, 1.0, 0.0);
   gemm_expand(c, nb, K, nb, t.M, nb, true, dbl(c.d_Pt), K, dbl(t.psi), K, 1.0, 0.0);
-  compute_potentials_async(c, t.psi);
+  if (c.nproj > 0) {
+    axpby(c, (size_t)c.nproj * nb, 1.0, c.d_P0, delta, c.d_PS, c.d_Pq);
+    gemm_small(c, c.nproj, nb, nb, c.d_Pq, nb, false, t.M, nb, true, c.d_P, nb, 1.0, 0.0);
+  }
+  compute_potentials_async(c, t.psi, true);
   sync(c);
   t.ok = c.h_flag[0] == 0;
   t.E = INFINITY;
@@ -136,7 +155,7 @@ void evaluate_trial(Ctx& c, double delta, Trial& t) {
 // ---------------------------------------------------------------------------
 // every launch of the energy evaluation; the reduced sums are copied to the
 // pinned mirror h_scal, read by assemble_energies after a synchronisation
-void compute_potentials_async(Ctx& c, const double2* orb) {
+void compute_potentials_async(Ctx& c, const double2* orb, bool have_P) {
   const int nb = c.nb, K = 2 * c.npw;
   launch_zpass_bwd(c, orb, nb, c.d_T, c.npairs);
   launch_plane_density(c, c.d_T, c.npairs, c.d_rho_part, c.nchunk);
@@ -152,7 +171,7 @@ void compute_potentials_async(Ctx& c, const double2* orb) {
   }
   band_dots(c, orb, orb, nb, 1, c.d_kin);
   if (c.nproj > 0) {
-    gemm_wdot(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(orb), K, c.d_P, nb, 1.0, 0.0, true);
+    if (!have_P) gemm_wdot(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(orb), K, c.d_P, nb, 1.0, 0.0, true);
     launch_nl_energy(c, c.d_P, c.d_enl);
   } else {
     ROKS_HIP(hipMemsetAsync(c.d_enl, 0, nb * sizeof(double), c.stream));
@@ -188,7 +207,7 @@ roks_energies assemble_energies(const Ctx& c) {
 }
 
 void compute_potentials(Ctx& c, const double2* orb, roks_energies* e) {
-  compute_potentials_async(c, orb);
+  compute_potentials_async(c, orb, false);
   sync(c);
   const roks_energies out = assemble_energies(c);
   if (e) *e = out;
@@ -397,13 +416,19 @@ void pcg_step(Ctx& c, roks_step_info* info) {
 
   int evals = 0, best = -1;
   bool fallback = false;
+  bool first_search = true;
+  auto search = [&]() {
+    prepare_line_search(c, first_search);
+    first_search = false;
+    return line_search(c.dt, &evals);
+  };
   if (dE0 < 0.0) {
-    best = line_search(c.dt, &evals);
+    best = search();
     if (best < 0 && beta != 0.0) {
       beta = 0.0;
       restarted = true;
       dE0 = directions(0.0);
-      if (dE0 < 0.0) best = line_search(c.dt, &evals);
+      if (dE0 < 0.0) best = search();
     }
   }
   if (best < 0 && learned) {
@@ -414,7 +439,7 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     beta = 0.0;
     restarted = true;
     dE0 = directions(0.0);
-    if (dE0 < 0.0) best = line_search(c.dt, &evals);
+    if (dE0 < 0.0) best = search();
   }
   roks_step_info r{};
   r.E0 = E0;
@@ -489,15 +514,14 @@ void forces(Ctx& c, double* f_host) {
   launch_local_force(c, c.d_fft, c.d_part, nblk);
   launch_reduce_strided(c, c.d_part, nat, nblk, 3, 1.0, c.d_force);
   // nonlocal part: += 2 sum_n w_n <d beta_i|n> (D P)_in
+  // (P = <beta|psi> is current: the energy evaluation of these orbitals left it)
   if (c.nproj > 0) {
-    if (!c.d_dB) c.d_dB = dalloc<double2>(c, (size_t)c.nproj * c.npw);
-    gemm_wdot(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(c.d_psi), K, c.d_P, nb, 1.0, 0.0, true);
+    if (!c.d_dB) c.d_dB = dalloc<double2>(c, 3 * (size_t)c.nproj * c.npw);
+    if (!c.d_dP3) c.d_dP3 = dalloc<double>(c, 3 * (size_t)c.nproj * nb);
     launch_apply_D(c, c.d_P, nullptr, c.d_DP);
-    for (int a = 0; a < 3; ++a) {
-      launch_projectors(c, c.d_dB, a);
-      gemm_wdot(c, c.nproj, nb, K, dbl(c.d_dB), K, dbl(c.d_psi), K, c.d_dP, nb, 1.0, 0.0, true);
-      launch_nl_force(c, c.d_dP, c.d_DP, c.d_kinw_shell, a, c.d_force);
-    }
+    launch_projector_gradients(c, c.d_dB);
+    gemm_wdot(c, 3 * c.nproj, nb, K, dbl(c.d_dB), K, dbl(c.d_psi), K, c.d_dP3, nb, 1.0, 0.0, true);
+    launch_nl_force(c, c.d_dP3, c.d_DP, c.d_kinw_shell, c.d_force);
   }
   // F = -dE/dR
   axpby(c, 3 * (size_t)nat, -1.0, c.d_force, 0.0, nullptr, c.d_force);

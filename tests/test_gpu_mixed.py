@@ -51,9 +51,14 @@ def test_fp32_energies_apply_gradient(case):
 
 def test_fp32_ladder_reaches_fp64_minimum_tiny():
     """FP32 iterations to 1e-6 Ha, then FP64 polish to 1e-10 Ha: the same
-    E_S as the FP64 oracle from the same start."""
+    energy as the FP64 oracle from the same start, for the ground state (one
+    minimum).  From a random start the tiny singlet has several stationary
+    points (E = -0.14627, -0.14762, -0.16252 Ha): FP64 runs pass the first
+    and leave it along a direction whose energy change is below the FP32
+    tier's rounding, so which one a ladder reaches is not a property of the
+    arithmetic; the singlet is tested from the ground-state orbitals below."""
     rb = ensure_built()
-    s = inputs.tiny_cell()
+    s = inputs.with_configuration(inputs.tiny_cell(), "gs")
     g, m, mp, psi = _pair(s, rb.FP32)
     i32, n32 = g.solve(tol=1e-6, maxiter=400)
     g.set_precision(rb.FP64)
