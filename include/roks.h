@@ -79,7 +79,12 @@ enum {
    * the shell's own block of R (energy neutral) */
   ROKS_FLAG_CANONICALIZE = 2u,
   /* divide the Teter preconditioner of band n by its weight sum c_L f_n */
-  ROKS_FLAG_WEIGHT_PRECOND = 4u
+  ROKS_FLAG_WEIGHT_PRECOND = 4u,
+  /* choose the split count of the band-space GEMMs by timing candidates on
+   * the first use of each (M, N, K) shape; the choice is shared by all the
+   * process's contexts.  It changes the order of the FP64 sums, so results
+   * agree to rounding, not bit for bit, between processes. */
+  ROKS_FLAG_AUTOTUNE = 8u
 };
 
 /* Separable Gaussian projector of one radial channel (Sec. II A, projector
@@ -245,6 +250,10 @@ roks_status roks_synchronize(roks_ctx ctx);
  * launches' inputs and outputs imply); unknown names give zero.  Any output
  * pointer may be NULL. */
 roks_status roks_timing_enable(roks_ctx ctx, int32_t enable);
+/* Record only the launches of one kernel family (NULL or "": all).  Every
+ * recorded launch adds two events to the stream; restricting the recording
+ * to the family being measured keeps the others' timing undisturbed. */
+roks_status roks_timing_only(roks_ctx ctx, const char* kernel);
 roks_status roks_timing_read(roks_ctx ctx, const char* kernel, double* total_ms,
                              int32_t* launches, double* bytes, double* flops);
 
@@ -334,6 +343,28 @@ roks_status roks_mlp_collect(roks_mlp mlp, roks_ctx ctx, int32_t* used, int32_t*
  * s K and fall back to the plain preconditioner when the learned direction
  * finds no decrease. */
 roks_status roks_set_mlp(roks_ctx ctx, roks_mlp mlp);
+
+/* ------------------------------------------------------------------------
+ * Batches of independent systems (many structures and both configurations
+ * of uneven sizes).  A batch holds existing contexts (not owned; each must
+ * have its own stream, which roks_create gives a context created with
+ * hip_stream NULL).  Up to `workers` host threads take the contexts from a
+ * queue ordered by decreasing estimated cost (nb N^3 log N + nproj nb npw:
+ * longest first), so the kernels of different systems overlap on the GPU.
+ * Per-context outcomes are returned in arrays indexed like `ctxs`; the call
+ * returns ROKS_OK when the batch ran (check the per-context statuses).
+ * ------------------------------------------------------------------------ */
+typedef struct roks_batch_s* roks_batch;
+roks_status roks_batch_create(const roks_ctx* ctxs, int32_t n, int32_t workers, roks_batch* out);
+roks_status roks_batch_destroy(roks_batch batch);
+/* roks_solve(tol, maxiter) on every context; with switch_tol > 0 a context in
+ * the FP32 tier first solves to switch_tol, then switches to FP64 (the
+ * precision ladder).  status [n] (nullable), iterations [n] (nullable, the
+ * total over both tiers), last [n] (nullable, the final step's info). */
+roks_status roks_batch_solve(roks_batch batch, double tol, int32_t maxiter, double switch_tol,
+                             roks_status* status, int32_t* iterations, roks_step_info* last);
+/* `steps` CG steps on every context (a fixed amount of work). */
+roks_status roks_batch_steps(roks_batch batch, int32_t steps, roks_status* status);
 
 #ifdef __cplusplus
 }

@@ -7,10 +7,6 @@
 
 #include "roks_internal.h"
 
-struct roks_ctx_s {
-  roks::Ctx c;
-};
-
 struct roks_mlp_s {
   roks::Mlp m;
 };
@@ -332,6 +328,10 @@ roks_status roks_timing_enable(roks_ctx ctx, int32_t enable) {
     roks::clear_timing(c);
     c.timing = enable != 0;
   });
+}
+
+roks_status roks_timing_only(roks_ctx ctx, const char* kernel) {
+  return guard(ctx, [&](roks::Ctx& c) { c.timing_only = kernel ? kernel : ""; });
 }
 
 roks_status roks_timing_read(roks_ctx ctx, const char* kernel, double* total_ms, int32_t* launches,

@@ -11,6 +11,11 @@ void init_device(Ctx& c, void* stream) {
   ROKS_CHECK(hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0, ROKS_ERR_HIP, "no HIP device");
   ROKS_HIP(hipGetDevice(&c.device));
   c.stream = reinterpret_cast<hipStream_t>(stream);
+  if (!c.stream) {
+    // a stream of its own (default priority), so contexts run side by side
+    ROKS_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+    c.own_stream = true;
+  }
 
   const size_t nb = c.nb, npw = c.npw, ntot = c.ntot, np = c.nproj;
   c.npairs = (c.nb + 1) / 2;
@@ -152,6 +157,7 @@ void upload_static(Ctx& c) {
 
 KernelTimer::KernelTimer(Ctx& ctx, const char* name, double bytes, double flops) : c(ctx) {
   if (!c.timing) return;
+  if (!c.timing_only.empty() && c.timing_only != name) return;
   Ctx::Timed t;
   t.name = name;
   t.bytes = bytes;
@@ -192,6 +198,9 @@ void free_device(Ctx& c) {
     if (h) (void)hipHostFree(h);
   c.h_scal = c.h_stage = nullptr;
   c.h_flag = nullptr;
+  if (c.own_stream && c.stream) (void)hipStreamDestroy(c.stream);
+  c.stream = nullptr;
+  c.own_stream = false;
 }
 
 }  // namespace roks

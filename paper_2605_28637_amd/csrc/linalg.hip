@@ -6,7 +6,11 @@
 //   gemm_small  nb x nb products (rotation, exponential, Cholesky factors).
 // plus per-band weighted dots, the Cholesky inverse, the subspace matrices
 // R / kappa / A and the Teter preconditioner.
+#include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "roks_internal.h"
 
@@ -125,6 +129,30 @@ __global__ void __launch_bounds__(64) k_splitk_reduce_wave(const double* __restr
   s = wave_sum(s);
   if (threadIdx.x == 0) {
     double v = alpha * s;
+    if (beta != 0.0) v += beta * C[(size_t)m * ldc + n];
+    C[(size_t)m * ldc + n] = v;
+  }
+}
+
+// many splits, many outputs: 64 outputs per workgroup, 16 groups of 64 lanes
+// stride over the splits (coalesced rows), groups summed in order in LDS
+__global__ void __launch_bounds__(1024) k_splitk_reduce_cols(const double* __restrict__ part, int ks,
+                                                             int M, int N, double* __restrict__ C,
+                                                             int ldc, double alpha, double beta) {
+  __shared__ double red[16][64];
+  const size_t mn = (size_t)M * N;
+  const size_t o = blockIdx.x * (size_t)64 + (threadIdx.x & 63);
+  const int g = threadIdx.x >> 6;
+  double s = 0.0;
+  if (o < mn)
+    for (int z = g; z < ks; z += 16) s += part[(size_t)z * mn + o];
+  red[g][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (g == 0 && o < mn) {
+    double t = 0.0;
+    for (int q = 0; q < 16; ++q) t += red[q][threadIdx.x];
+    const int m = (int)(o / N), n = (int)(o - (size_t)m * N);
+    double v = alpha * t;
     if (beta != 0.0) v += beta * C[(size_t)m * ldc + n];
     C[(size_t)m * ldc + n] = v;
   }
@@ -645,20 +673,14 @@ int blocks_for(size_t n) {
 
 }  // namespace
 
-void gemm_wdot(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
-               double* C, int ldc, double alpha, double beta, bool half_weights) {
-  if (M == 0 || N == 0) return;
-  KernelTimer kt(c, "gemm_wdot", ((double)M + N) * K * sizeof(double) + (double)M * N * sizeof(double),
-                 2.0 * M * N * (double)K);
-  // Every k slice costs one global-load latency that one slice of compute
-  // cannot hide, so small outputs get many workgroups of ~2 slices each
-  // (several per CU); the split-K partials are summed in a fixed order.
-  const int tiles = cdiv(M, 64) * cdiv(N, 64);
-  int ks = 2048 / tiles;
-  ks = std::max(1, std::min(ks, K / 32));
-  while ((size_t)ks * M * N > c.gemm_part_capacity && ks > 1) --ks;
-  int kchunk = cdiv(cdiv(K, ks), 16) * 16;
-  ks = cdiv(K, kchunk);
+namespace {
+
+// the launches of one split count: partials then the ordered sum, or one pass
+void gemm_wdot_launch(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B,
+                      int ldb, double* C, int ldc, double alpha, double beta, bool half_weights,
+                      int ks_req) {
+  int kchunk = cdiv(cdiv(K, ks_req), 16) * 16;
+  const int ks = cdiv(K, kchunk);
   dim3 grid(cdiv(M, 64), cdiv(N, 64), ks);
   if (ks == 1) {
     hipLaunchKernelGGL(k_gemm_wdot, grid, dim3(256), 0, c.stream, M, N, K, A, lda, B, ldb, C, ldc,
@@ -670,13 +692,86 @@ void gemm_wdot(Ctx& c, int M, int N, int K, const double* A, int lda, const doub
                      N, kchunk, half_weights ? 1 : 0, 1.0, 0.0, 0);
   ROKS_HIP(hipGetLastError());
   const size_t mn = (size_t)M * N;
-  if (ks > 16 && mn <= 65536)
+  if (ks > 16 && mn <= 4096)
     hipLaunchKernelGGL(k_splitk_reduce_wave, dim3((unsigned)mn), dim3(64), 0, c.stream,
                        c.d_gemm_part, ks, M, N, C, ldc, alpha, beta);
+  else if (ks > 16)
+    hipLaunchKernelGGL(k_splitk_reduce_cols, dim3((unsigned)((mn + 63) / 64)), dim3(1024), 0,
+                       c.stream, c.d_gemm_part, ks, M, N, C, ldc, alpha, beta);
   else
     hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, c.stream,
                        c.d_gemm_part, ks, M, N, C, ldc, alpha, beta);
   ROKS_HIP(hipGetLastError());
+}
+
+int max_splits(const Ctx& c, int M, int N, int K) {
+  int ks = std::max(1, K / 16);
+  while ((size_t)ks * M * N > c.gemm_part_capacity && ks > 1) --ks;
+  return ks;
+}
+
+// Every k slice costs one global-load latency that one slice of compute
+// cannot hide, so small outputs get many workgroups of ~2 slices each
+// (several per CU); the split-K partials are summed in a fixed order.
+int heuristic_splits(const Ctx& c, int M, int N, int K) {
+  const int tiles = cdiv(M, 64) * cdiv(N, 64);
+  int ks = std::max(1, std::min(2048 / tiles, K / 32));
+  return std::min(ks, max_splits(c, M, N, K));
+}
+
+// autotuner: the split count of each (M, N, K) timed once per process
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, int> g_tuned;
+
+int tuned_splits(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
+                 bool half_weights) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  const auto key = std::make_tuple(M, N, K);
+  auto it = g_tuned.find(key);
+  if (it != g_tuned.end()) return it->second;
+  const int h = heuristic_splits(c, M, N, K), hi = max_splits(c, M, N, K);
+  std::vector<int> cand;
+  for (int v : {h / 4, h / 2, h, 2 * h, 4 * h, 1, 64, 128, 256, 512})
+    if (v >= 1 && v <= hi && std::find(cand.begin(), cand.end(), v) == cand.end()) cand.push_back(v);
+  double* scratch = dalloc<double>(c, (size_t)M * N);
+  hipEvent_t e0, e1;
+  ROKS_HIP(hipEventCreate(&e0));
+  ROKS_HIP(hipEventCreate(&e1));
+  int best = h;
+  float best_ms = 1e30f;
+  for (int v : cand) {
+    float tmin = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      ROKS_HIP(hipEventRecord(e0, c.stream));
+      gemm_wdot_launch(c, M, N, K, A, lda, B, ldb, scratch, N, 1.0, 0.0, half_weights, v);
+      ROKS_HIP(hipEventRecord(e1, c.stream));
+      ROKS_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      ROKS_HIP(hipEventElapsedTime(&ms, e0, e1));
+      tmin = std::min(tmin, ms);
+    }
+    if (tmin < best_ms) {
+      best_ms = tmin;
+      best = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  g_tuned[key] = best;
+  return best;
+}
+
+}  // namespace
+
+void gemm_wdot(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
+               double* C, int ldc, double alpha, double beta, bool half_weights) {
+  if (M == 0 || N == 0) return;
+  const int ks = (c.flags & ROKS_FLAG_AUTOTUNE)
+                     ? tuned_splits(c, M, N, K, A, lda, B, ldb, half_weights)
+                     : heuristic_splits(c, M, N, K);
+  KernelTimer kt(c, "gemm_wdot", ((double)M + N) * K * sizeof(double) + (double)M * N * sizeof(double),
+                 2.0 * M * N * (double)K);
+  gemm_wdot_launch(c, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, half_weights, ks);
 }
 
 void gemm_expand(Ctx& c, int N, int K, int Md, const double* M, int ldm, bool transM,

@@ -122,6 +122,7 @@ struct Ctx {
 
   // ---- device ----
   hipStream_t stream = nullptr;
+  bool own_stream = false;
   int device = 0;
   std::vector<DevBuf> allocations;
   bool have_orbitals = false;
@@ -244,6 +245,7 @@ struct Ctx {
 
   // ---- diagnostics: per-kernel event pairs on `stream` ----
   bool timing = false;
+  std::string timing_only;  // record only this kernel family (empty: all)
   struct Timed {
     std::string name;
     hipEvent_t a, b;
@@ -415,3 +417,8 @@ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 constexpr int kStage = 16;  // scalar slots ahead of the per-band ones in d_stage
 
 }  // namespace roks
+
+// the opaque handle of the C ABI
+struct roks_ctx_s {
+  roks::Ctx c;
+};

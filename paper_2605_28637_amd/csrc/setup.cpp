@@ -116,6 +116,7 @@ void build_problem(Ctx& c, const roks_system* s) {
   ROKS_CHECK(s->precision == ROKS_FP64 || s->precision == ROKS_FP32, ROKS_ERR_ARG,
              "precision tier not available");
   c.prec = s->precision;
+  ROKS_CHECK((s->flags & ~15u) == 0, ROKS_ERR_ARG, "unknown flag bits");
   c.flags = s->flags;
 
   // shells: closed (all ones), open patterns by first appearance, virtual (all zeros)

@@ -21,6 +21,7 @@ XC = {"pw92": 0, "x": 1}
 FLAG_SUPPRESS_OPEN_COUPLING = 1
 FLAG_CANONICALIZE = 2
 FLAG_WEIGHT_PRECOND = 4
+FLAG_AUTOTUNE = 8
 
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_SHAPE", 3: "ERR_HIP", 4: "ERR_OOM", 5: "ERR_NOT_PD",
           6: "ERR_LINESEARCH", 7: "ERR_NAN", 8: "ERR_STATE"}
@@ -104,6 +105,7 @@ _SIGS = {
     "roks_forces": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "roks_synchronize": (C.c_int, [_P]),
     "roks_timing_enable": (C.c_int, [_P, C.c_int32]),
+    "roks_timing_only": (C.c_int, [_P, C.c_char_p]),
     "roks_timing_read": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "roks_mlp_create": (C.c_int, [C.POINTER(C.c_float), C.c_uint64, _P, C.POINTER(_P)]),
@@ -121,6 +123,11 @@ _SIGS = {
     "roks_record": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "roks_mlp_collect": (C.c_int, [_P, _P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "roks_set_mlp": (C.c_int, [_P, _P]),
+    "roks_batch_create": (C.c_int, [C.POINTER(_P), C.c_int32, C.c_int32, C.POINTER(_P)]),
+    "roks_batch_destroy": (C.c_int, [_P]),
+    "roks_batch_solve": (C.c_int, [_P, C.c_double, C.c_int32, C.c_double, C.POINTER(C.c_int),
+                                   C.POINTER(C.c_int32), C.POINTER(StepInfo)]),
+    "roks_batch_steps": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int)]),
 }
 
 MLP_PARAMS = 4481
@@ -330,6 +337,9 @@ class Roks:
     def timing_enable(self, on: bool = True):
         self._check(self._L.roks_timing_enable(self._h, 1 if on else 0))
 
+    def timing_only(self, kernel: Optional[str]):
+        self._check(self._L.roks_timing_only(self._h, kernel.encode() if kernel else None))
+
     def timing_read(self, kernel: str) -> Dict:
         ms, n, by, fl = C.c_double(), C.c_int32(), C.c_double(), C.c_double()
         self._check(self._L.roks_timing_read(self._h, kernel.encode(), C.byref(ms), C.byref(n),
@@ -425,3 +435,49 @@ class Mlp:
         used, skipped = C.c_int32(), C.c_int32()
         self._check(self._L.roks_mlp_collect(self._h, roks.handle, C.byref(used), C.byref(skipped)))
         return used.value, skipped.value
+
+
+class Batch:
+    """Independent contexts solved side by side (a roks_batch): a work queue,
+    longest system first, drained by `workers` host threads."""
+
+    def __init__(self, systems, workers: int = 8):
+        self._L = lib()
+        self.systems = list(systems)
+        n = len(self.systems)
+        arr = (_P * n)(*[r.handle for r in self.systems])
+        h = _P()
+        st = self._L.roks_batch_create(arr, n, workers, C.byref(h))
+        if st != 0:
+            raise RoksError(st, "roks_batch_create failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.roks_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, tol: float = 1e-6, maxiter: int = 500, switch_tol: float = 0.0):
+        """Per system: (status, iterations, final step info)."""
+        n = len(self.systems)
+        st = (C.c_int * n)()
+        its = (C.c_int32 * n)()
+        info = (StepInfo * n)()
+        rc = self._L.roks_batch_solve(self._h, tol, maxiter, switch_tol, st, its, info)
+        if rc != 0:
+            raise RoksError(rc, "roks_batch_solve failed")
+        return [(st[i], its[i], info[i].as_dict()) for i in range(n)]
+
+    def steps(self, k: int):
+        n = len(self.systems)
+        st = (C.c_int * n)()
+        rc = self._L.roks_batch_steps(self._h, k, st)
+        if rc != 0:
+            raise RoksError(rc, "roks_batch_steps failed")
+        return list(st)
