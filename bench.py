@@ -22,6 +22,7 @@ entry), so the other launches run undisturbed.
 Prints ONE JSON line.  Inputs are resident on the GPU when timing starts.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -38,6 +39,11 @@ from paper_2605_28637_amd import roks as rb  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 RESTART = 20
+
+# HBM traffic per launch of a kernel family, from the rocprofv3 FETCH_SIZE /
+# WRITE_SIZE passes summarised in profiles/ (scaled by the copy-kernel
+# calibration); reported only while the family's source is the one measured.
+TRAFFIC = {}
 KERNELS = ("zpass_bwd", "plane_apply", "plane_density", "zpass_fwd", "fft3d", "gemm_wdot",
            "gemm_expand", "xc")
 
@@ -291,6 +297,39 @@ def batch_report(steps=8, workers=8):
             "batched_equals_sequential": bool(same)}
 
 
+def oxide_report(reps=3):
+    """The rocksalt oxide-vacancy supercell at full size (96^3, 28 889 stored
+    plane waves, 432 bands, 1 720 projectors): the all-band shell-operator
+    application F^n|n> (device in, device out) and one CG iteration, FP64 and
+    FP32 tier."""
+    import torch
+    s = inputs.oxide_vacancy()
+    out = {}
+    for name, prec in (("fp64", rb.FP64), ("fp32", rb.FP32)):
+        r = rb.Roks(s, precision=prec)
+        r.set_coeffs(inputs.random_coefficients(r.miller(), s["cell"], r.nb, s["seed"]), True)
+        y = torch.empty((r.nb, r.npw, 2), dtype=torch.float64, device="cuda")
+        r.apply_h_d(None, 0, y.data_ptr())  # energies and potentials, then one apply
+        r.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r.apply_h_d(None, 0, y.data_ptr())
+        r.synchronize()
+        t_apply = (time.perf_counter() - t0) / reps
+        r.pcg_step()
+        t0 = time.perf_counter()
+        info = r.pcg_step()
+        t_step = time.perf_counter() - t0
+        out[name] = {"ms_per_all_band_apply": 1e3 * t_apply,
+                     "band_applies_per_s": r.nb / t_apply,
+                     "ms_per_cg_iteration": 1e3 * t_step, "trial_energies": info["evaluations"]}
+        del y
+        r.close()
+    out["workload"] = ("rocksalt 3x3x3 supercell, a = 8 bohr, one anion removed (215 atoms), "
+                       "96^3 grid, 432 bands, 8 projectors per atom")
+    return out
+
+
 def calibrate_copy(mib=512, reps=3):
     """A plain copy kernel of known size (y = 1.0 * x, FP32, contiguous) for
     scaling the FETCH_SIZE / WRITE_SIZE counters: it reads and writes
@@ -314,6 +353,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-oxide", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the copy kernel that scales the HBM byte counters")
     args = ap.parse_args()
@@ -325,6 +365,12 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if not args.no_oxide:
+        # PyTorch (device buffers of the oxide leg) carries its own HIP
+        # runtime: its GPU context first
+        import torch
+        torch.zeros(1, device="cuda")
+        torch.cuda.synchronize()
     system = inputs.molecule_box()
     r = rb.Roks(system)
     r.set_coeffs(inputs.random_coefficients(r.miller(), system["cell"], r.nb, system["seed"]), True)
@@ -359,6 +405,13 @@ def main():
     nb, npw = r.nb, r.npw
     r.close()
     roof_live = roofline(dom, dom_live)
+    if roof_live and dom in TRAFFIC:
+        t = TRAFFIC[dom]
+        src = os.path.join(ROOT, t["source"])
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if digest == t["sha256"]:
+            roof_live["traffic"] = t["bytes_per_launch"]
+            roof_live["traffic_source"] = t["profile"]
 
     # the band H-apply pipeline (z pass G->r, plane multiply, z pass r->G);
     # the G->r z pass also serves every density evaluation, so its time and
@@ -402,6 +455,8 @@ def main():
         out["time_to_converge"] = converge_report(system)
     if not args.no_batch:
         out["batch"] = batch_report()
+    if not args.no_oxide:
+        out["oxide"] = oxide_report()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(system)
     print(json.dumps(out))

@@ -30,7 +30,11 @@
  * potentials, projector tables, CG state).  All device work is ordered on
  * the context's HIP stream; calls taking host pointers synchronise that
  * stream before returning, calls whose name ends in _d take device pointers
- * and only enqueue work.
+ * and only enqueue work: the caller's work producing their inputs must be
+ * complete (or ordered on the context's stream, by passing that stream to
+ * roks_create).  A host process that also uses a framework carrying its own
+ * HIP runtime (PyTorch's wheels do) must initialise that framework's GPU
+ * context before the first roks_create.
  *
  * Errors: every call returns a roks_status; argument and shape checks come
  * before any device work.  roks_last_error() gives a message for the last

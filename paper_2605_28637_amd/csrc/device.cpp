@@ -2,6 +2,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <rocblas/rocblas.h>
+
 #include "roks_internal.h"
 
 namespace roks {
@@ -15,6 +17,17 @@ void init_device(Ctx& c, void* stream) {
     // a stream of its own (default priority), so contexts run side by side
     ROKS_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
     c.own_stream = true;
+  }
+  {
+    rocblas_handle h = nullptr;
+    ROKS_CHECK(rocblas_create_handle(&h) == rocblas_status_success, ROKS_ERR_HIP,
+               "rocblas_create_handle failed");
+    c.blas = h;
+    ROKS_CHECK(rocblas_set_stream(h, c.stream) == rocblas_status_success, ROKS_ERR_HIP,
+               "rocblas_set_stream failed");
+    // deterministic sums: no atomics
+    ROKS_CHECK(rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed) == rocblas_status_success,
+               ROKS_ERR_HIP, "rocblas_set_atomics_mode failed");
   }
 
   const size_t nb = c.nb, npw = c.npw, ntot = c.ntot, np = c.nproj;
@@ -198,6 +211,8 @@ void free_device(Ctx& c) {
     if (h) (void)hipHostFree(h);
   c.h_scal = c.h_stage = nullptr;
   c.h_flag = nullptr;
+  if (c.blas) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(c.blas));
+  c.blas = nullptr;
   if (c.own_stream && c.stream) (void)hipStreamDestroy(c.stream);
   c.stream = nullptr;
   c.own_stream = false;

@@ -469,11 +469,17 @@ __global__ void __launch_bounds__(512) k_plane_density(
   const int nh = 2 * g.hmax + 1;
   for (int i = tid; i < g.N1; i += nthr) tw1[i] = tw1g[i];
   for (int i = tid; i < g.N2; i += nthr) tw2[i] = tw2g[i];
-  R acc[3][MAXP];
+  // shell 0 (the closed shell, nearly every band) accumulates in registers;
+  // the open shells (a band or two each) add into this chunk's slice of
+  // rho_part in pair order
+  const size_t zoff = (size_t)z * np2;
+  R acc[MAXP];
 #pragma unroll
-  for (int X = 0; X < 3; ++X)
-#pragma unroll
-    for (int i = 0; i < MAXP; ++i) acc[X][i] = 0;
+  for (int i = 0; i < MAXP; ++i) acc[i] = 0;
+  for (int X = 1; X < nsocc; ++X) {
+    double* out = rho_part + ((size_t)chunk * nsocc + X) * ntot + zoff;
+    for (int pt = tid; pt < np2; pt += nthr) out[pt] = 0.0;
+  }
   const int p0 = chunk * per_chunk;
   const int p1 = min(npairs, p0 + per_chunk);
   for (int pair = p0; pair < p1; ++pair) {
@@ -487,29 +493,26 @@ __global__ void __launch_bounds__(512) k_plane_density(
     fft_lines<R, MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, +1);
     const int s1 = band_shell[2 * pair];
     const int s2 = (2 * pair + 1 < nvec) ? band_shell[2 * pair + 1] : 99;
+    const bool open1 = s1 >= 1 && s1 < nsocc, open2 = s2 >= 1 && s2 < nsocc;
 #pragma unroll
     for (int i = 0; i < MAXP; ++i) {
       const int pt = tid + i * nthr;
       if (pt < np2) {
         const int x = pt / g.N2, y = pt - x * g.N2;
         const C2<R> w = plane[x * g.PS + y];
-#pragma unroll
-        for (int X = 0; X < 3; ++X)
-          acc[X][i] += (s1 == X ? w.x * w.x : (R)0) + (s2 == X ? w.y * w.y : (R)0);
+        acc[i] += (s1 == 0 ? w.x * w.x : (R)0) + (s2 == 0 ? w.y * w.y : (R)0);
+        if (open1) rho_part[((size_t)chunk * nsocc + s1) * ntot + zoff + pt] += (double)(w.x * w.x);
+        if (open2) rho_part[((size_t)chunk * nsocc + s2) * ntot + zoff + pt] += (double)(w.y * w.y);
       }
     }
     __syncthreads();
   }
-  const size_t zoff = (size_t)z * np2;
+  if (nsocc > 0) {
+    double* out = rho_part + ((size_t)chunk * nsocc) * ntot + zoff;
 #pragma unroll
-  for (int X = 0; X < 3; ++X) {
-    if (X < nsocc) {
-      double* out = rho_part + ((size_t)chunk * nsocc + X) * ntot + zoff;
-#pragma unroll
-      for (int i = 0; i < MAXP; ++i) {
-        const int pt = tid + i * nthr;
-        if (pt < np2) out[pt] = (double)acc[X][i];
-      }
+    for (int i = 0; i < MAXP; ++i) {
+      const int pt = tid + i * nthr;
+      if (pt < np2) out[pt] = (double)acc[i];
     }
   }
 }

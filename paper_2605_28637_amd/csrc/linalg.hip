@@ -1,16 +1,13 @@
 // Dense linear algebra for the band and projector spaces (FP64):
-//   gemm_wdot   C = alpha * A W B^T + beta * C, long K (split-K, ordered sum);
-//               W is the Gamma half-sphere weight (1 for G = 0, 2 otherwise),
-//               so this is the real inner product <a|b> of stored bands.
-//   gemm_expand Y = alpha * M^T X + beta * Y with a short inner dimension.
+//   gemm_expand Y = alpha * M^T X + beta * Y (short inner dimension; from 128
+//               rows of M on, the rocBLAS DGEMM).
 //   gemm_small  nb x nb products (rotation, exponential, Cholesky factors).
 // plus per-band weighted dots, the Cholesky inverse, the subspace matrices
 // R / kappa / A and the Teter preconditioner.
 #include <algorithm>
 #include <cmath>
-#include <map>
-#include <mutex>
-#include <tuple>
+
+#include <rocblas/rocblas.h>
 
 #include "roks_internal.h"
 
@@ -22,140 +19,6 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
-}
-
-// --------------------------------------------------------------------------
-// C[m][n] (+)= sum_k w_k A[m][k] B[n][k]: 64 x 64 tile, 16-deep k slices,
-// 4 x 4 outputs per thread; blockIdx.z splits K.
-// --------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_gemm_wdot(int M, int N, int K, const double* __restrict__ A,
-                                                   int lda, const double* __restrict__ B, int ldb,
-                                                   double* __restrict__ out, int ldo, int kchunk,
-                                                   int hw, double alpha, double beta, int direct) {
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][65];
-  const int tid = threadIdx.x;
-  const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
-  const int kb = blockIdx.z * kchunk;
-  const int ke = min(K, kb + kchunk);
-  const int tm = tid >> 4, tn = tid & 15;
-  double acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  // the next k slice is loaded into registers while the current one is used
-  double pa[4], pb[4];
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + q * 256;
-      const int row = idx >> 4, kk = idx & 15;
-      const int k = k0 + kk;
-      pa[q] = 0.0;
-      pb[q] = 0.0;
-      if (k < ke) {
-        const double w = (hw && k >= 2) ? 2.0 : 1.0;
-        if (m0 + row < M) pa[q] = w * A[(size_t)(m0 + row) * lda + k];
-        if (n0 + row < N) pb[q] = B[(size_t)(n0 + row) * ldb + k];
-      }
-    }
-  };
-  if (kb < ke) load(kb);
-  for (int k0 = kb; k0 < ke; k0 += 16) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + q * 256;
-      const int row = idx >> 4, kk = idx & 15;
-      As[kk][row] = pa[q];
-      Bs[kk][row] = pb[q];
-    }
-    __syncthreads();
-    if (k0 + 16 < ke) load(k0 + 16);
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tm * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tn * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int m = m0 + tm * 4 + i;
-    if (m >= M) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n = n0 + tn * 4 + j;
-      if (n >= N) continue;
-      if (direct) {
-        double v = alpha * acc[i][j];
-        if (beta != 0.0) v += beta * out[(size_t)m * ldo + n];
-        out[(size_t)m * ldo + n] = v;
-      } else {
-        out[((size_t)blockIdx.z * M + m) * N + n] = acc[i][j];
-      }
-    }
-  }
-}
-
-// few splits: one thread per output sums them in order
-__global__ void k_splitk_reduce(const double* __restrict__ part, int ks, int M, int N,
-                                double* __restrict__ C, int ldc, double alpha, double beta) {
-  const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  if (t >= (size_t)M * N) return;
-  const int m = (int)(t / N), n = (int)(t - (size_t)m * N);
-  double s = 0;
-  for (int z = 0; z < ks; ++z) s += part[(size_t)z * M * N + t];
-  double v = alpha * s;
-  if (beta != 0.0) v += beta * C[(size_t)m * ldc + n];
-  C[(size_t)m * ldc + n] = v;
-}
-
-// many splits: one wave per output, lanes stride over the splits, fixed tree
-__global__ void __launch_bounds__(64) k_splitk_reduce_wave(const double* __restrict__ part, int ks,
-                                                           int M, int N, double* __restrict__ C,
-                                                           int ldc, double alpha, double beta) {
-  const size_t t = blockIdx.x;
-  const int m = (int)(t / N), n = (int)(t - (size_t)m * N);
-  double s = 0;
-  for (int z = threadIdx.x; z < ks; z += 64) s += part[(size_t)z * M * N + t];
-  s = wave_sum(s);
-  if (threadIdx.x == 0) {
-    double v = alpha * s;
-    if (beta != 0.0) v += beta * C[(size_t)m * ldc + n];
-    C[(size_t)m * ldc + n] = v;
-  }
-}
-
-// many splits, many outputs: 64 outputs per workgroup, 16 groups of 64 lanes
-// stride over the splits (coalesced rows), groups summed in order in LDS
-__global__ void __launch_bounds__(1024) k_splitk_reduce_cols(const double* __restrict__ part, int ks,
-                                                             int M, int N, double* __restrict__ C,
-                                                             int ldc, double alpha, double beta) {
-  __shared__ double red[16][64];
-  const size_t mn = (size_t)M * N;
-  const size_t o = blockIdx.x * (size_t)64 + (threadIdx.x & 63);
-  const int g = threadIdx.x >> 6;
-  double s = 0.0;
-  if (o < mn)
-    for (int z = g; z < ks; z += 16) s += part[(size_t)z * mn + o];
-  red[g][threadIdx.x & 63] = s;
-  __syncthreads();
-  if (g == 0 && o < mn) {
-    double t = 0.0;
-    for (int q = 0; q < 16; ++q) t += red[q][threadIdx.x];
-    const int m = (int)(o / N), n = (int)(o - (size_t)m * N);
-    double v = alpha * t;
-    if (beta != 0.0) v += beta * C[(size_t)m * ldc + n];
-    C[(size_t)m * ldc + n] = v;
-  }
 }
 
 // --------------------------------------------------------------------------
@@ -673,113 +536,21 @@ int blocks_for(size_t n) {
 
 }  // namespace
 
-namespace {
-
-// the launches of one split count: partials then the ordered sum, or one pass
-void gemm_wdot_launch(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B,
-                      int ldb, double* C, int ldc, double alpha, double beta, bool half_weights,
-                      int ks_req) {
-  int kchunk = cdiv(cdiv(K, ks_req), 16) * 16;
-  const int ks = cdiv(K, kchunk);
-  dim3 grid(cdiv(M, 64), cdiv(N, 64), ks);
-  if (ks == 1) {
-    hipLaunchKernelGGL(k_gemm_wdot, grid, dim3(256), 0, c.stream, M, N, K, A, lda, B, ldb, C, ldc,
-                       kchunk, half_weights ? 1 : 0, alpha, beta, 1);
-    ROKS_HIP(hipGetLastError());
-    return;
-  }
-  hipLaunchKernelGGL(k_gemm_wdot, grid, dim3(256), 0, c.stream, M, N, K, A, lda, B, ldb, c.d_gemm_part,
-                     N, kchunk, half_weights ? 1 : 0, 1.0, 0.0, 0);
-  ROKS_HIP(hipGetLastError());
-  const size_t mn = (size_t)M * N;
-  if (ks > 16 && mn <= 4096)
-    hipLaunchKernelGGL(k_splitk_reduce_wave, dim3((unsigned)mn), dim3(64), 0, c.stream,
-                       c.d_gemm_part, ks, M, N, C, ldc, alpha, beta);
-  else if (ks > 16)
-    hipLaunchKernelGGL(k_splitk_reduce_cols, dim3((unsigned)((mn + 63) / 64)), dim3(1024), 0,
-                       c.stream, c.d_gemm_part, ks, M, N, C, ldc, alpha, beta);
-  else
-    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, c.stream,
-                       c.d_gemm_part, ks, M, N, C, ldc, alpha, beta);
-  ROKS_HIP(hipGetLastError());
-}
-
-int max_splits(const Ctx& c, int M, int N, int K) {
-  int ks = std::max(1, K / 16);
-  while ((size_t)ks * M * N > c.gemm_part_capacity && ks > 1) --ks;
-  return ks;
-}
-
-// Every k slice costs one global-load latency that one slice of compute
-// cannot hide, so small outputs get many workgroups of ~2 slices each
-// (several per CU); the split-K partials are summed in a fixed order.
-int heuristic_splits(const Ctx& c, int M, int N, int K) {
-  const int tiles = cdiv(M, 64) * cdiv(N, 64);
-  int ks = std::max(1, std::min(2048 / tiles, K / 32));
-  return std::min(ks, max_splits(c, M, N, K));
-}
-
-// autotuner: the split count of each (M, N, K) timed once per process
-std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, int> g_tuned;
-
-int tuned_splits(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
-                 bool half_weights) {
-  std::lock_guard<std::mutex> lock(g_tune_mu);
-  const auto key = std::make_tuple(M, N, K);
-  auto it = g_tuned.find(key);
-  if (it != g_tuned.end()) return it->second;
-  const int h = heuristic_splits(c, M, N, K), hi = max_splits(c, M, N, K);
-  std::vector<int> cand;
-  for (int v : {h / 4, h / 2, h, 2 * h, 4 * h, 1, 64, 128, 256, 512})
-    if (v >= 1 && v <= hi && std::find(cand.begin(), cand.end(), v) == cand.end()) cand.push_back(v);
-  double* scratch = dalloc<double>(c, (size_t)M * N);
-  hipEvent_t e0, e1;
-  ROKS_HIP(hipEventCreate(&e0));
-  ROKS_HIP(hipEventCreate(&e1));
-  int best = h;
-  float best_ms = 1e30f;
-  for (int v : cand) {
-    float tmin = 1e30f;
-    for (int rep = 0; rep < 3; ++rep) {
-      ROKS_HIP(hipEventRecord(e0, c.stream));
-      gemm_wdot_launch(c, M, N, K, A, lda, B, ldb, scratch, N, 1.0, 0.0, half_weights, v);
-      ROKS_HIP(hipEventRecord(e1, c.stream));
-      ROKS_HIP(hipEventSynchronize(e1));
-      float ms = 0.f;
-      ROKS_HIP(hipEventElapsedTime(&ms, e0, e1));
-      tmin = std::min(tmin, ms);
-    }
-    if (tmin < best_ms) {
-      best_ms = tmin;
-      best = v;
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  g_tuned[key] = best;
-  return best;
-}
-
-}  // namespace
-
-void gemm_wdot(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
-               double* C, int ldc, double alpha, double beta, bool half_weights) {
-  if (M == 0 || N == 0) return;
-  const int ks = (c.flags & ROKS_FLAG_AUTOTUNE)
-                     ? tuned_splits(c, M, N, K, A, lda, B, ldb, half_weights)
-                     : heuristic_splits(c, M, N, K);
-  KernelTimer kt(c, "gemm_wdot", ((double)M + N) * K * sizeof(double) + (double)M * N * sizeof(double),
-                 2.0 * M * N * (double)K);
-  gemm_wdot_launch(c, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, half_weights, ks);
-}
-
 void gemm_expand(Ctx& c, int N, int K, int Md, const double* M, int ldm, bool transM,
                  const double* X, int ldx, double* Y, int ldy, double alpha, double beta) {
   if (N == 0 || K == 0) return;
   KernelTimer kt(c, "gemm_expand",
                  ((double)Md * K + (beta != 0.0 ? 2.0 : 1.0) * N * K) * sizeof(double),
                  2.0 * N * (double)K * Md);
+  if (Md >= 128 && N >= 64) {
+    // a compute-bound size: one library DGEMM on the column-major views,
+    // Y^T (K x N) = X^T (K x Md) M (Md x N)
+    ROKS_CHECK(rocblas_dgemm(static_cast<rocblas_handle>(c.blas), rocblas_operation_none,
+                             transM ? rocblas_operation_none : rocblas_operation_transpose, K, N, Md,
+                             &alpha, X, ldx, M, ldm, &beta, Y, ldy) == rocblas_status_success,
+               ROKS_ERR_HIP, "rocblas_dgemm failed");
+    return;
+  }
   dim3 grid(cdiv(K, 128), cdiv(N, 32));
   hipLaunchKernelGGL(k_gemm_expand, grid, dim3(256), 0, c.stream, N, K, Md, M, ldm, transM ? 1 : 0, X,
                      ldx, Y, ldy, alpha, beta);

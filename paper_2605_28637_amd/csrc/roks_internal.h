@@ -123,6 +123,7 @@ struct Ctx {
   // ---- device ----
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  void* blas = nullptr;  // rocblas_handle on `stream` (large plain DGEMMs)
   int device = 0;
   std::vector<DevBuf> allocations;
   bool have_orbitals = false;
@@ -265,6 +266,7 @@ constexpr int kMlpParams = kMlpWidth * kMlpFeat + kMlpWidth + kMlpWidth * kMlpWi
 struct Mlp {
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  void* blas = nullptr;  // rocblas_handle on `stream` (large plain DGEMMs)
   std::vector<DevBuf> allocations;
   float* d_p = nullptr;      // FP32 master parameters
   uint16_t* d_pb = nullptr;  // BF16 copy read by every evaluation

@@ -272,6 +272,13 @@ class Roks:
         self._check(self._L.roks_get_coeffs(self._h, _dptr(a)))
         return _unpacked(a)
 
+    def set_coeffs_d(self, ptr: int, orthonormalize: bool = True):
+        """Orbitals from device memory [nb][npw][2] FP64 (e.g. a torch data_ptr)."""
+        self._check(self._L.roks_set_coeffs_d(self._h, _P(ptr), 1 if orthonormalize else 0))
+
+    def get_coeffs_d(self, ptr: int):
+        self._check(self._L.roks_get_coeffs_d(self._h, _P(ptr)))
+
     def set_positions(self, pos: np.ndarray):
         p = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1)
         self._check(self._L.roks_set_positions(self._h, _dptr(p)))
