@@ -43,7 +43,12 @@ RESTART = 20
 # HBM traffic per launch of a kernel family, from the rocprofv3 FETCH_SIZE /
 # WRITE_SIZE passes summarised in profiles/ (scaled by the copy-kernel
 # calibration); reported only while the family's source is the one measured.
-TRAFFIC = {}
+TRAFFIC = {
+    "gemm_wdot": {"source": "paper_2605_28637_amd/csrc/gemm.hip",
+                  "sha256": "3296e6e962e91496a674a4ad455970a2dc795e0fd17e391d6cd076b93da448a4",
+                  "bytes_per_launch": 3.984317e+07,
+                  "profile": "profiles/gemm_wdot_molecule64_fp64_traffic.md"},
+}
 KERNELS = ("zpass_bwd", "plane_apply", "plane_density", "zpass_fwd", "fft3d", "gemm_wdot",
            "gemm_expand", "xc")
 
