@@ -18,6 +18,9 @@ void init_device(Ctx& c, void* stream) {
     ROKS_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
     c.own_stream = true;
   }
+  ROKS_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
+  ROKS_HIP(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
+  ROKS_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
   {
     rocblas_handle h = nullptr;
     ROKS_CHECK(rocblas_create_handle(&h) == rocblas_status_success, ROKS_ERR_HIP,
@@ -81,7 +84,7 @@ void init_device(Ctx& c, void* stream) {
   c.d_P0 = dalloc<double>(c, np * nb);
   c.d_PS = dalloc<double>(c, np * nb);
   c.d_Pq = dalloc<double>(c, np * nb);
-  c.part_capacity = std::max<size_t>(6 * 1024, (size_t)c.natoms * 32 * 3) + 64;
+  c.part_capacity = std::max<size_t>(8 * 1024, (size_t)c.natoms * 32 * 3) + 64;
   c.d_part = dalloc<double>(c, c.part_capacity);
   c.d_scal = dalloc<double>(c, 16 + 2 * nb);
   c.d_red = c.d_scal;
@@ -211,6 +214,12 @@ void free_device(Ctx& c) {
     if (h) (void)hipHostFree(h);
   c.h_scal = c.h_stage = nullptr;
   c.h_flag = nullptr;
+  if (c.side) (void)hipStreamSynchronize(c.side);
+  if (c.ev_fork) (void)hipEventDestroy(c.ev_fork);
+  if (c.ev_join) (void)hipEventDestroy(c.ev_join);
+  if (c.side) (void)hipStreamDestroy(c.side);
+  c.side = nullptr;
+  c.ev_fork = c.ev_join = nullptr;
   if (c.blas) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(c.blas));
   c.blas = nullptr;
   if (c.own_stream && c.stream) (void)hipStreamDestroy(c.stream);

@@ -228,6 +228,47 @@ __global__ void k_hartree_mul(Lattice L, double2* __restrict__ f, size_t ntot) {
   }
 }
 
+// Hartree integrals sum_r V_H,L(r) rho_L(r) = sum_{G != 0} 4 pi |F_L(G)|^2 / (G^2 N^3)
+// straight from the packed transform F = FFT(rho_0 + i rho_1) (no inverse
+// transform): F_0 = (F(G) + F(-G)*)/2, F_1 = (F(G) - F(-G)*)/(2i); per-block
+// partials [block][2], fixed order
+__global__ void __launch_bounds__(256) k_hartree_energy(Lattice L, const double2* __restrict__ f,
+                                                        size_t ntot, int nconf,
+                                                        double* __restrict__ part) {
+  __shared__ double red[8 * 16];
+  double acc[2] = {0.0, 0.0};
+  const double inv = 1.0 / (double)ntot;
+  const int np2 = L.N[0] * L.N[1];
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
+       i += (size_t)gridDim.x * blockDim.x) {
+    int m[3];
+    grid_freq(L, i, m);
+    double G[3];
+    gvec(L, m, G);
+    const double g2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+    if (g2 > 0.0) {
+      const int z = (int)(i / np2);
+      const int r = (int)(i - (size_t)z * np2);
+      const int x = r / L.N[1], y = r - x * L.N[1];
+      const int xm = x ? L.N[0] - x : 0, ym = y ? L.N[1] - y : 0, zm = z ? L.N[2] - z : 0;
+      const double2 a = f[i];
+      const double2 b = f[(size_t)zm * np2 + (size_t)xm * L.N[1] + ym];
+      const double w = 4.0 * M_PI * inv / g2;
+      const double mx = 0.5 * (a.x + b.x), my = 0.5 * (a.y - b.y);
+      acc[0] += w * (mx * mx + my * my);
+      if (nconf > 1) {
+        const double tx = 0.5 * (a.y + b.y), ty = -0.5 * (a.x - b.x);
+        acc[1] += w * (tx * tx + ty * ty);
+      }
+    }
+  }
+  block_sum<2>(acc, red);
+  if (threadIdx.x == 0) {
+    part[(size_t)blockIdx.x * 2] = acc[0];
+    part[(size_t)blockIdx.x * 2 + 1] = acc[1];
+  }
+}
+
 __global__ void k_unpack_vh(const double2* __restrict__ f, size_t ntot, int nconf,
                             double* __restrict__ vh) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
@@ -298,11 +339,12 @@ __device__ void lda_point(double ru, double rd, int kind, double* e, double* vu,
 
 // per point: configuration spin densities, LDA, V_loc^{sigma L}, shell potentials
 // V^X = sum c_L f_X V_loc^{sigma L}; partial sums of e_xc, V_ext rho, V_H rho per L
+// write = 0: energy sums only (xc and external; no V_H read, no potentials)
 __global__ void __launch_bounds__(256) k_xc(ShellArgs a, const double* __restrict__ rho,
                                             const double* __restrict__ vext,
                                             const double* __restrict__ vh, size_t ntot,
                                             double* __restrict__ vloc, double* __restrict__ vsh,
-                                            double* __restrict__ part) {
+                                            double* __restrict__ part, int write) {
   __shared__ double red[8 * 16];
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
@@ -319,15 +361,17 @@ __global__ void __launch_bounds__(256) k_xc(ShellArgs a, const double* __restric
       }
       double e, vu, vd;
       lda_point(ru, rd, a.xc, &e, &vu, &vd);
+      acc[3 * L + 0] += e;
+      acc[3 * L + 1] += ve * (ru + rd);
+      if (!write) continue;
       const double h = vh[(size_t)L * ntot + i];
       vl[L][0] = ve + h + vu;
       vl[L][1] = ve + h + vd;
       vloc[(size_t)(2 * L) * ntot + i] = vl[L][0];
       vloc[(size_t)(2 * L + 1) * ntot + i] = vl[L][1];
-      acc[3 * L + 0] += e;
-      acc[3 * L + 1] += ve * (ru + rd);
       acc[3 * L + 2] += h * (ru + rd);
     }
+    if (!write) continue;
     for (int X = 0; X < a.nsocc; ++X) {
       double s = 0;
       for (int L = 0; L < a.nconf; ++L)
@@ -571,7 +615,24 @@ void launch_xc_potentials(Ctx& c, double* part, int nblocks) {
   // reads shell densities, V_ext, V_H; writes V_loc and the shell potentials
   KernelTimer kt(c, "xc", (double)(2 * c.nsocc + 1 + 3 * c.nconf) * c.ntot * sizeof(double));
   hipLaunchKernelGGL(k_xc, dim3(nblocks), dim3(256), 0, c.stream, shell_args(c), c.d_rho, c.d_vext,
-                     c.d_vh, (size_t)c.ntot, c.d_vloc, c.d_vsh, part);
+                     c.d_vh, (size_t)c.ntot, c.d_vloc, c.d_vsh, part, 1);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_xc_energy(Ctx& c, double* part, int nblocks) {
+  hipLaunchKernelGGL(k_xc, dim3(nblocks), dim3(256), 0, c.stream, shell_args(c), c.d_rho, c.d_vext,
+                     c.d_vh, (size_t)c.ntot, c.d_vloc, c.d_vsh, part, 0);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_hartree_energy(Ctx& c, double* part, int nblocks) {
+  const size_t n = c.ntot;
+  hipLaunchKernelGGL(k_pack_rho, dim3(grid_blocks(n)), dim3(256), 0, c.stream, shell_args(c), c.d_rho, n,
+                     c.d_fft, 0);
+  ROKS_HIP(hipGetLastError());
+  launch_fft3d(c, c.d_fft, -1);
+  hipLaunchKernelGGL(k_hartree_energy, dim3(nblocks), dim3(256), 0, c.stream, lattice(c), c.d_fft, n,
+                     c.nconf, part);
   ROKS_HIP(hipGetLastError());
 }
 

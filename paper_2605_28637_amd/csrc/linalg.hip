@@ -611,13 +611,13 @@ void cholesky_inverse(Ctx& c, const double* G, int n, double* Linv, int32_t* fla
 
 bool expm_in_lds(const Ctx& c) { return c.nb <= 78; }
 
-void launch_expm_lds(Ctx& c, const double* D, double delta, double* U) {
+void launch_expm_lds(Ctx& c, const double* D, double delta, double* U, hipStream_t stream) {
   const int n = c.nb;
   const size_t lds = (size_t)3 * n * n * sizeof(double);
   if (lds > 65536)
     ROKS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_expm_lds),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_expm_lds, dim3(1), dim3(1024), lds, c.stream, D, n, delta, U);
+  hipLaunchKernelGGL(k_expm_lds, dim3(1), dim3(1024), lds, stream, D, n, delta, U);
   ROKS_HIP(hipGetLastError());
 }
 

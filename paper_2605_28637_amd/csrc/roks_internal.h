@@ -124,6 +124,10 @@ struct Ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   void* blas = nullptr;  // rocblas_handle on `stream` (large plain DGEMMs)
+  // a second stream for independent single-workgroup work (the rotation's
+  // exponential beside the Cholesky factorisation), joined through events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int device = 0;
   std::vector<DevBuf> allocations;
   bool have_orbitals = false;
@@ -267,6 +271,10 @@ struct Mlp {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   void* blas = nullptr;  // rocblas_handle on `stream` (large plain DGEMMs)
+  // a second stream for independent single-workgroup work (the rotation's
+  // exponential beside the Cholesky factorisation), joined through events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<DevBuf> allocations;
   float* d_p = nullptr;      // FP32 master parameters
   uint16_t* d_pb = nullptr;  // BF16 copy read by every evaluation
@@ -338,6 +346,10 @@ int xc_blocks(const Ctx& c);
 void launch_band_kinetic(Ctx& c, const double2* vecs, int nvec, double* out);
 void launch_nl_energy(Ctx& c, const double* P, double* out);
 void launch_apply_D(Ctx& c, const double* P, const double* w, double* DP);
+// energy-only evaluation: xc and external sums without potentials, and the
+// Hartree integrals from the forward transform (partials [block][2])
+void launch_xc_energy(Ctx& c, double* part, int nblocks);
+void launch_hartree_energy(Ctx& c, double* part, int nblocks);
 void launch_reduce_columns(Ctx& c, const double* part, int nrows, int ncols, double* out);
 void launch_to_float(Ctx& c, const double* in, float* out, size_t n);
 void launch_reduce_strided(Ctx& c, const double* part, int nouter, int ninner, int ncols,
@@ -368,7 +380,7 @@ void scale_shift(Ctx& c, const double* in, int n, double a, double d, double* ou
 void matrix_norm1(Ctx& c, const double* A, int n, double* out);
 void launch_subspace(Ctx& c);
 bool expm_in_lds(const Ctx& c);
-void launch_expm_lds(Ctx& c, const double* D, double delta, double* U);
+void launch_expm_lds(Ctx& c, const double* D, double delta, double* U, hipStream_t stream);
 void launch_asym_dot(Ctx& c, const double* A, const double* theta, double* out);
 // max |theta_nm - theta_mn| over m of shell sa, n of shell sb (one value)
 void launch_open_coupling(Ctx& c, int sa, int sb, double* out);

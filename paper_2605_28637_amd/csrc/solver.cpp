@@ -43,7 +43,7 @@ const double* dbl(const double2* p) { return reinterpret_cast<const double*>(p);
 // theta = ||X||_1 / 2^s <= 1)
 void expm(Ctx& c, double delta, const double* D, double* U) {
   if (expm_in_lds(c)) {
-    launch_expm_lds(c, D, delta, U);
+    launch_expm_lds(c, D, delta, U, c.stream);
     return;
   }
   const int n = c.nb;
@@ -89,8 +89,8 @@ void expm(Ctx& c, double delta, const double* D, double* U) {
 
 }  // namespace
 
-void compute_potentials_async(Ctx& c, const double2* orb, bool have_P);
-roks_energies assemble_energies(const Ctx& c);
+void compute_potentials_async(Ctx& c, const double2* orb, bool have_P, bool energy_only);
+roks_energies assemble_energies(const Ctx& c, bool energy_only);
 
 namespace {
 
@@ -121,26 +121,38 @@ void prepare_line_search(Ctx& c, bool first) {
 // are <beta|Psi + delta S> = P0 + delta PS rotated by M.  One
 // synchronisation: the Cholesky status and the energy sums come back together
 // (a failed factorisation only makes the rest of the evaluation meaningless).
-void evaluate_trial(Ctx& c, double delta, Trial& t) {
+void evaluate_trial(Ctx& c, double delta, Trial& t, bool energy_only) {
   const int nb = c.nb, K = 2 * c.npw;
   const size_t band = (size_t)nb * c.npw;
   axpby(c, 2 * band, 1.0, dbl(c.d_psi), delta, dbl(c.d_S), dbl(c.d_Pt));
   scale_shift(c, c.d_SS, nb, delta * delta, 1.0, c.d_gram);
+  const bool fork = expm_in_lds(c);
+  if (fork) {
+    // the exponential (one workgroup) runs beside the factorisation (one
+    // workgroup) on the side stream; both finish before M = U^T L^-1
+    ROKS_HIP(hipEventRecord(c.ev_fork, c.stream));
+    ROKS_HIP(hipStreamWaitEvent(c.side, c.ev_fork, 0));
+    launch_expm_lds(c, c.d_D, delta, t.U, c.side);
+    ROKS_HIP(hipEventRecord(c.ev_join, c.side));
+  }
   cholesky_inverse(c, c.d_gram, nb, c.d_Linv, c.d_flag);
   fetch(c, c.h_flag, c.d_flag, sizeof(int32_t));
-  expm(c, delta, c.d_D, t.U);
+  if (fork)
+    ROKS_HIP(hipStreamWaitEvent(c.stream, c.ev_join, 0));
+  else
+    expm(c, delta, c.d_D, t.U);
   gemm_small(c, nb, nb, nb, t.U, nb, true, c.d_Linv, nb, false, t.M, nb, 1.0, 0.0);
   gemm_expand(c, nb, K, nb, t.M, nb, true, dbl(c.d_Pt), K, dbl(t.psi), K, 1.0, 0.0);
   if (c.nproj > 0) {
     axpby(c, (size_t)c.nproj * nb, 1.0, c.d_P0, delta, c.d_PS, c.d_Pq);
     gemm_small(c, c.nproj, nb, nb, c.d_Pq, nb, false, t.M, nb, true, c.d_P, nb, 1.0, 0.0);
   }
-  compute_potentials_async(c, t.psi, true);
+  compute_potentials_async(c, t.psi, true, energy_only);
   sync(c);
   t.ok = c.h_flag[0] == 0;
   t.E = INFINITY;
   if (!t.ok) return;
-  t.e = assemble_energies(c);
+  t.e = assemble_energies(c, energy_only);
   t.E = t.e.E;
   if (!std::isfinite(t.E)) {
     t.ok = false;
@@ -155,16 +167,25 @@ void evaluate_trial(Ctx& c, double delta, Trial& t) {
 // ---------------------------------------------------------------------------
 // every launch of the energy evaluation; the reduced sums are copied to the
 // pinned mirror h_scal, read by assemble_energies after a synchronisation
-void compute_potentials_async(Ctx& c, const double2* orb, bool have_P) {
+void compute_potentials_async(Ctx& c, const double2* orb, bool have_P, bool energy_only) {
   const int nb = c.nb, K = 2 * c.npw;
   launch_zpass_bwd(c, orb, nb, c.d_T, c.npairs);
   launch_plane_density(c, c.d_T, c.npairs, c.d_rho_part, c.nchunk);
   launch_density_reduce(c, c.d_rho_part, c.nchunk, c.d_rho);
-  launch_hartree(c);
   const int nblk = xc_blocks(c);
-  launch_xc_potentials(c, c.d_part, nblk);
-  launch_reduce_columns(c, c.d_part, nblk, 6, c.d_red);
-  if (c.prec == ROKS_FP32) {
+  if (energy_only) {
+    // energies only: the Hartree integrals from the forward transform, the
+    // xc and external sums without writing any potential
+    launch_hartree_energy(c, c.d_part + 6 * (size_t)nblk, nblk);
+    launch_xc_energy(c, c.d_part, nblk);
+    launch_reduce_columns(c, c.d_part, nblk, 6, c.d_red);
+    launch_reduce_columns(c, c.d_part + 6 * (size_t)nblk, nblk, 2, c.d_red + 6);
+  } else {
+    launch_hartree(c);
+    launch_xc_potentials(c, c.d_part, nblk);
+    launch_reduce_columns(c, c.d_part, nblk, 6, c.d_red);
+  }
+  if (c.prec == ROKS_FP32 && !energy_only) {
     // the plane passes of the FP32 tier read FP32 copies of the potentials
     launch_to_float(c, c.d_vsh, c.d_vsh32, (size_t)c.nsocc * c.ntot);
     launch_to_float(c, c.d_vloc, c.d_vloc32, (size_t)2 * c.nconf * c.ntot);
@@ -179,7 +200,7 @@ void compute_potentials_async(Ctx& c, const double2* orb, bool have_P) {
   fetch(c, c.h_scal, c.d_scal, (16 + 2 * (size_t)nb) * sizeof(double));
 }
 
-roks_energies assemble_energies(const Ctx& c) {
+roks_energies assemble_energies(const Ctx& c, bool energy_only) {
   const int nb = c.nb;
   const double* h = c.h_scal;
   const double* kin = h + 16;
@@ -198,7 +219,7 @@ roks_energies assemble_energies(const Ctx& c) {
     out.nonlocal[L] = nl;
     out.xc[L] = dv * h[3 * L + 0];
     out.external[L] = dv * h[3 * L + 1];
-    out.hartree[L] = 0.5 * dv * h[3 * L + 2];
+    out.hartree[L] = 0.5 * dv * (energy_only ? h[6 + L] : h[3 * L + 2]);
     out.E_L[L] = k + nl + out.external[L] + out.hartree[L] + out.xc[L];
     E += c.cL[L] * out.E_L[L];
   }
@@ -207,9 +228,9 @@ roks_energies assemble_energies(const Ctx& c) {
 }
 
 void compute_potentials(Ctx& c, const double2* orb, roks_energies* e) {
-  compute_potentials_async(c, orb, false);
+  compute_potentials_async(c, orb, false, false);
   sync(c);
-  const roks_energies out = assemble_energies(c);
+  const roks_energies out = assemble_energies(c, false);
   if (e) *e = out;
   c.potentials_valid = (orb == c.d_psi);
 }
@@ -395,7 +416,9 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   auto line_search = [&](double dt, int* evals) -> int {
     for (int attempt = 0; attempt <= kHalvings; ++attempt) {
       const double t = dt / std::ldexp(1.0, attempt);
-      evaluate_trial(c, t, tr[0]);
+      // the first trial's potentials are never kept (tr[1] is evaluated
+      // after it): energies only
+      evaluate_trial(c, t, tr[0], true);
       ++*evals;
       double ts;
       if (tr[0].ok) {
@@ -404,7 +427,7 @@ void pcg_step(Ctx& c, roks_step_info* info) {
       } else {
         ts = 0.5 * t;
       }
-      evaluate_trial(c, ts, tr[1]);
+      evaluate_trial(c, ts, tr[1], false);
       ++*evals;
       tdelta[0] = t;
       tdelta[1] = ts;
