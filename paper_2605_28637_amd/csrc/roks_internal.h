@@ -189,6 +189,7 @@ struct Ctx {
   double* d_Pq = nullptr;        // [nproj][nb] scratch
   int32_t* d_flag = nullptr;     // device status flags
   double* d_force = nullptr;     // [natoms][3]
+  double* d_force_loc = nullptr; // [natoms][3] local part (side stream)
   double2* d_dB = nullptr;       // [3][nproj][npw] derivative projector tables (forces)
   double* d_dP3 = nullptr;       // [3][nproj][nb] derivative projections (forces)
   void* d_atoms = nullptr;       // per-atom position and local-well parameters

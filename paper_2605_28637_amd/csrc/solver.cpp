@@ -246,7 +246,10 @@ void ensure_potentials(Ctx& c) {
 void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bool want_Q) {
   const int nb = c.nb, K = 2 * c.npw;
   const size_t band = (size_t)nb * c.npw;
-  if (c.nproj > 0)
+  // <beta|vecs>; for the current orbitals their energy evaluation left it in d_P
+  const bool have_P = vecs == c.d_psi && c.potentials_valid;
+  const double* P = have_P ? c.d_P : c.d_dP;
+  if (c.nproj > 0 && !have_P)
     gemm_wdot(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(vecs), K, c.d_dP, nb, 1.0, 0.0, true);
   if (mask == 0) {
     launch_zpass_bwd(c, vecs, nb, c.d_T, c.npairs);
@@ -255,7 +258,7 @@ void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bo
                        want_Q ? c.nsocc : 0);
     launch_zpass_fwd(c, c.d_T, c.npairs, vecs, nb, c.d_kinw_shell, out);
     if (c.nproj > 0) {
-      launch_apply_D(c, c.d_dP, c.d_kinw_shell, c.d_DP);
+      launch_apply_D(c, P, c.d_kinw_shell, c.d_DP);
       gemm_expand(c, nb, K, c.nproj, c.d_DP, nb, false, dbl(c.d_B), K, dbl(out), K, 1.0, 1.0);
     }
     if (want_Q) {
@@ -277,7 +280,7 @@ void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bo
     launch_plane_apply(c, c.d_T, c.npairs, vl, 1, c.d_potidx + nb, nb, c.d_Qpart, 0);
     launch_zpass_fwd(c, c.d_T, c.npairs, vecs, nb, c.d_ones, o);
     if (c.nproj > 0) {
-      launch_apply_D(c, c.d_dP, nullptr, c.d_DP);
+      launch_apply_D(c, P, nullptr, c.d_DP);
       gemm_expand(c, nb, K, c.nproj, c.d_DP, nb, false, dbl(c.d_B), K, dbl(o), K, 1.0, 1.0);
     }
     ++idx;
@@ -530,14 +533,25 @@ void forces(Ctx& c, double* f_host) {
   const int nb = c.nb, K = 2 * c.npw;
   const int nat = c.natoms;
   if (nat == 0) return;
-  // local part: dE/dR_I from rho_w = sum_L c_L rho_L, into d_force
-  launch_pack_rho_weighted(c);
-  launch_fft3d(c, c.d_fft, -1);
-  const int nblk = 32;
-  launch_local_force(c, c.d_fft, c.d_part, nblk);
-  launch_reduce_strided(c, c.d_part, nat, nblk, 3, 1.0, c.d_force);
-  // nonlocal part: += 2 sum_n w_n <d beta_i|n> (D P)_in
+  if (!c.d_force_loc) c.d_force_loc = dalloc<double>(c, 3 * (size_t)nat);
+  // local part, dE/dR_I from rho_w = sum_L c_L rho_L, on the side stream
+  // (no GEMMs there, so the library handle's stream is not involved)
+  ROKS_HIP(hipEventRecord(c.ev_fork, c.stream));
+  ROKS_HIP(hipStreamWaitEvent(c.side, c.ev_fork, 0));
+  {
+    const hipStream_t main = c.stream;
+    c.stream = c.side;
+    launch_pack_rho_weighted(c);
+    launch_fft3d(c, c.d_fft, -1);
+    const int nblk = 32;
+    launch_local_force(c, c.d_fft, c.d_part, nblk);
+    launch_reduce_strided(c, c.d_part, nat, nblk, 3, 1.0, c.d_force_loc);
+    c.stream = main;
+  }
+  ROKS_HIP(hipEventRecord(c.ev_join, c.side));
+  // nonlocal part on the main stream: 2 sum_n w_n <d beta_i|n> (D P)_in
   // (P = <beta|psi> is current: the energy evaluation of these orbitals left it)
+  ROKS_HIP(hipMemsetAsync(c.d_force, 0, 3 * (size_t)nat * sizeof(double), c.stream));
   if (c.nproj > 0) {
     if (!c.d_dB) c.d_dB = dalloc<double2>(c, 3 * (size_t)c.nproj * c.npw);
     if (!c.d_dP3) c.d_dP3 = dalloc<double>(c, 3 * (size_t)c.nproj * nb);
@@ -547,7 +561,8 @@ void forces(Ctx& c, double* f_host) {
     launch_nl_force(c, c.d_dP3, c.d_DP, c.d_kinw_shell, c.d_force);
   }
   // F = -dE/dR
-  axpby(c, 3 * (size_t)nat, -1.0, c.d_force, 0.0, nullptr, c.d_force);
+  ROKS_HIP(hipStreamWaitEvent(c.stream, c.ev_join, 0));
+  axpby(c, 3 * (size_t)nat, -1.0, c.d_force_loc, -1.0, c.d_force, c.d_force);
   to_host(c, f_host, c.d_force, 3 * (size_t)nat * sizeof(double));
 }
 
