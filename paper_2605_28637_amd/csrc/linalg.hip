@@ -245,11 +245,8 @@ __global__ void __launch_bounds__(1024) k_cholesky_inverse(const double* __restr
 // forward elimination of L X = I on an LDS copy of the identity, so that row
 // j of X = L^-1 is final after step j; then rank-1 updates of the trailing
 // block of A and of the rows below j of X.  All work per step is parallel.
-__global__ void __launch_bounds__(1024) k_cholesky_inverse_lds(const double* __restrict__ G, int n,
-                                                               double* __restrict__ Linv,
-                                                               int32_t* __restrict__ flag,
-                                                               int inv_in_lds) {
-  extern __shared__ double A[];
+__device__ void cholesky_lds_body(const double* __restrict__ G, int n, double* __restrict__ Linv,
+                                  int32_t* __restrict__ flag, int inv_in_lds, double* A) {
   __shared__ int bad;
   const int tid = threadIdx.x, nthr = blockDim.x;
   double* X = A + n * n;
@@ -304,15 +301,22 @@ __global__ void __launch_bounds__(1024) k_cholesky_inverse_lds(const double* __r
   if (tid == 0) flag[0] = bad;
 }
 
+__global__ void __launch_bounds__(1024) k_cholesky_inverse_lds(const double* __restrict__ G, int n,
+                                                               double* __restrict__ Linv,
+                                                               int32_t* __restrict__ flag,
+                                                               int inv_in_lds) {
+  extern __shared__ double A[];
+  cholesky_lds_body(G, n, Linv, flag, inv_in_lds, A);
+}
+
 // U = exp(delta D) in one workgroup, the three n x n matrices in LDS:
 // scaling and squaring around a Taylor polynomial in Horner form.  The
 // degree m and the squarings s minimise the products m + s subject to
 // theta^(m+1)/(m+1)! <= 1e-17 with theta = ||delta D||_1 / 2^s <= 1 (the
 // Taylor tail; exp of an antisymmetric matrix is orthogonal, so the bound is
 // relative).  Products run as 2 x 2 register blocks.
-__global__ void __launch_bounds__(1024) k_expm_lds(const double* __restrict__ D, int n, double delta,
-                                                  double* __restrict__ U) {
-  extern __shared__ double S[];
+__device__ void expm_lds_body(const double* __restrict__ D, int n, double delta,
+                              double* __restrict__ U, double* S) {
   __shared__ double nrm;
   __shared__ int plan[2];
   const int tid = threadIdx.x, nthr = blockDim.x, nn = n * n;
@@ -402,6 +406,26 @@ __global__ void __launch_bounds__(1024) k_expm_lds(const double* __restrict__ D,
     Q = tmp;
   }
   for (int t = tid; t < nn; t += nthr) U[t] = P[t];
+}
+
+__global__ void __launch_bounds__(1024) k_expm_lds(const double* __restrict__ D, int n, double delta,
+                                                  double* __restrict__ U) {
+  extern __shared__ double S[];
+  expm_lds_body(D, n, delta, U, S);
+}
+
+// the two independent single-workgroup steps of a trial in one launch:
+// workgroup 0 factorises the Gram matrix, workgroup 1 exponentiates delta D
+__global__ void __launch_bounds__(1024) k_chol_expm_lds(const double* __restrict__ G, int n,
+                                                       double* __restrict__ Linv,
+                                                       int32_t* __restrict__ flag, int inv_in_lds,
+                                                       const double* __restrict__ D, double delta,
+                                                       double* __restrict__ U) {
+  extern __shared__ double S[];
+  if (blockIdx.x == 0)
+    cholesky_lds_body(G, n, Linv, flag, inv_in_lds, S);
+  else
+    expm_lds_body(D, n, delta, U, S);
 }
 
 // --------------------------------------------------------------------------
@@ -610,6 +634,19 @@ void cholesky_inverse(Ctx& c, const double* G, int n, double* Linv, int32_t* fla
 }
 
 bool expm_in_lds(const Ctx& c) { return c.nb <= 78; }
+
+void launch_chol_expm_lds(Ctx& c, const double* G, double* Linv, int32_t* flag, const double* D,
+                          double delta, double* U) {
+  const int n = c.nb;
+  const int inv = n <= 96 ? 1 : 0;
+  const size_t lds = (size_t)std::max(inv ? 2 : 1, 3) * n * n * sizeof(double);
+  if (lds > 65536)
+    ROKS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_chol_expm_lds),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_chol_expm_lds, dim3(2), dim3(1024), lds, c.stream, G, n, Linv, flag, inv, D,
+                     delta, U);
+  ROKS_HIP(hipGetLastError());
+}
 
 void launch_expm_lds(Ctx& c, const double* D, double delta, double* U, hipStream_t stream) {
   const int n = c.nb;

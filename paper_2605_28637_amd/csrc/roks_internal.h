@@ -381,6 +381,10 @@ void scale_shift(Ctx& c, const double* in, int n, double a, double d, double* ou
 void matrix_norm1(Ctx& c, const double* A, int n, double* out);
 void launch_subspace(Ctx& c);
 bool expm_in_lds(const Ctx& c);
+// Cholesky inverse of G and U = exp(delta D) in one launch of two workgroups
+// (nb within the single-workgroup limits of both)
+void launch_chol_expm_lds(Ctx& c, const double* G, double* Linv, int32_t* flag, const double* D,
+                          double delta, double* U);
 void launch_expm_lds(Ctx& c, const double* D, double delta, double* U, hipStream_t stream);
 void launch_asym_dot(Ctx& c, const double* A, const double* theta, double* out);
 // max |theta_nm - theta_mn| over m of shell sa, n of shell sb (one value)

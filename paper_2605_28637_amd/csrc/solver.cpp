@@ -126,21 +126,15 @@ void evaluate_trial(Ctx& c, double delta, Trial& t, bool energy_only) {
   const size_t band = (size_t)nb * c.npw;
   axpby(c, 2 * band, 1.0, dbl(c.d_psi), delta, dbl(c.d_S), dbl(c.d_Pt));
   scale_shift(c, c.d_SS, nb, delta * delta, 1.0, c.d_gram);
-  const bool fork = expm_in_lds(c);
-  if (fork) {
-    // the exponential (one workgroup) runs beside the factorisation (one
-    // workgroup) on the side stream; both finish before M = U^T L^-1
-    ROKS_HIP(hipEventRecord(c.ev_fork, c.stream));
-    ROKS_HIP(hipStreamWaitEvent(c.side, c.ev_fork, 0));
-    launch_expm_lds(c, c.d_D, delta, t.U, c.side);
-    ROKS_HIP(hipEventRecord(c.ev_join, c.side));
-  }
-  cholesky_inverse(c, c.d_gram, nb, c.d_Linv, c.d_flag);
-  fetch(c, c.h_flag, c.d_flag, sizeof(int32_t));
-  if (fork)
-    ROKS_HIP(hipStreamWaitEvent(c.stream, c.ev_join, 0));
-  else
+  if (expm_in_lds(c)) {
+    // factorisation and exponential side by side: one launch, two workgroups
+    launch_chol_expm_lds(c, c.d_gram, c.d_Linv, c.d_flag, c.d_D, delta, t.U);
+    fetch(c, c.h_flag, c.d_flag, sizeof(int32_t));
+  } else {
+    cholesky_inverse(c, c.d_gram, nb, c.d_Linv, c.d_flag);
+    fetch(c, c.h_flag, c.d_flag, sizeof(int32_t));
     expm(c, delta, c.d_D, t.U);
+  }
   gemm_small(c, nb, nb, nb, t.U, nb, true, c.d_Linv, nb, false, t.M, nb, 1.0, 0.0);
   gemm_expand(c, nb, K, nb, t.M, nb, true, dbl(c.d_Pt), K, dbl(t.psi), K, 1.0, 0.0);
   if (c.nproj > 0) {
