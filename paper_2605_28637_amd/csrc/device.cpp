@@ -8,6 +8,27 @@
 
 namespace roks {
 
+// Band pairs per plane-pass workgroup. Each workgroup transforms one z-plane
+// for a run of pairs and pays, once per run, a fixed cost about one pair's
+// transform (reloading the plane's potentials, or writing its density
+// partial). With one such workgroup resident per CU, a pass takes
+// ceil(n3 * chunks / cus) rounds of (pairs per chunk + 1); the smallest chunk
+// count that minimises that is taken. Fixed per shape and device, so the
+// density's chunk sum keeps one order.
+static int plane_chunks(int n3, int npairs, int cus) {
+  int best = 1;
+  long best_cost = -1;
+  for (int n = 1; n <= npairs; ++n) {
+    const long rounds = cdiv(n3 * n, cus);
+    const long cost = rounds * (cdiv(npairs, n) + 1);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = n;
+    }
+  }
+  return best;
+}
+
 void init_device(Ctx& c, void* stream) {
   int ndev = 0;
   ROKS_CHECK(hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0, ROKS_ERR_HIP, "no HIP device");
@@ -35,7 +56,9 @@ void init_device(Ctx& c, void* stream) {
 
   const size_t nb = c.nb, npw = c.npw, ntot = c.ntot, np = c.nproj;
   c.npairs = (c.nb + 1) / 2;
-  c.nchunk = std::max(1, std::min(c.npairs, cdiv(512, c.N[2])));
+  int cus = 0;
+  ROKS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device));
+  c.nchunk = plane_chunks(c.N[2], c.npairs, std::max(1, cus));
 
   c.d_miller = dalloc<int32_t>(c, 3 * npw);
   c.d_g2 = dalloc<double>(c, npw);
