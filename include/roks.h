@@ -350,13 +350,18 @@ roks_status roks_set_mlp(roks_ctx ctx, roks_mlp mlp);
 
 /* ------------------------------------------------------------------------
  * Batches of independent systems (many structures and both configurations
- * of uneven sizes).  A batch holds existing contexts (not owned; each must
- * have its own stream, which roks_create gives a context created with
- * hip_stream NULL).  Up to `workers` host threads take the contexts from a
+ * of uneven sizes).  A batch holds existing contexts (not owned; no context
+ * may appear twice).  Up to `workers` host threads take the contexts from a
  * queue ordered by decreasing estimated cost (nb N^3 log N + nproj nb npw:
  * longest first), so the kernels of different systems overlap on the GPU.
- * Per-context outcomes are returned in arrays indexed like `ctxs`; the call
- * returns ROKS_OK when the batch ran (check the per-context statuses).
+ * roks_batch_create makes one stream per worker on the device of ctxs[0]
+ * (ROKS_ERR_HIP if it cannot); while a worker runs a context of that device,
+ * the context's launches go to the worker's stream, with the context's own
+ * stream synchronized before and the worker's after, so results do not
+ * depend on the stream; contexts of other devices run on their own streams.
+ * No other call may use a context of a running batch.  Per-context outcomes
+ * are returned in arrays indexed like `ctxs`; the call returns ROKS_OK when
+ * the batch ran (check the per-context statuses).
  * ------------------------------------------------------------------------ */
 typedef struct roks_batch_s* roks_batch;
 roks_status roks_batch_create(const roks_ctx* ctxs, int32_t n, int32_t workers, roks_batch* out);

@@ -29,6 +29,33 @@ static int plane_chunks(int n3, int npairs, int cus) {
   return best;
 }
 
+void* blas_handle(Ctx& c) {
+  if (!c.blas) {
+    rocblas_handle h = nullptr;
+    ROKS_CHECK(rocblas_create_handle(&h) == rocblas_status_success, ROKS_ERR_HIP,
+               "rocblas_create_handle failed");
+    c.blas = h;
+    c.blas_stream = nullptr;
+    // deterministic sums: no atomics
+    ROKS_CHECK(rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed) == rocblas_status_success,
+               ROKS_ERR_HIP, "rocblas_set_atomics_mode failed");
+  }
+  if (c.blas_stream != c.stream) {
+    ROKS_CHECK(rocblas_set_stream(static_cast<rocblas_handle>(c.blas), c.stream) ==
+                   rocblas_status_success,
+               ROKS_ERR_HIP, "rocblas_set_stream failed");
+    c.blas_stream = c.stream;
+  }
+  return c.blas;
+}
+
+void ensure_side_stream(Ctx& c) {
+  if (c.side) return;
+  ROKS_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
+  ROKS_HIP(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
+  ROKS_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
+}
+
 void init_device(Ctx& c, void* stream) {
   int ndev = 0;
   ROKS_CHECK(hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0, ROKS_ERR_HIP, "no HIP device");
@@ -39,21 +66,6 @@ void init_device(Ctx& c, void* stream) {
     ROKS_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
     c.own_stream = true;
   }
-  ROKS_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
-  ROKS_HIP(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
-  ROKS_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
-  {
-    rocblas_handle h = nullptr;
-    ROKS_CHECK(rocblas_create_handle(&h) == rocblas_status_success, ROKS_ERR_HIP,
-               "rocblas_create_handle failed");
-    c.blas = h;
-    ROKS_CHECK(rocblas_set_stream(h, c.stream) == rocblas_status_success, ROKS_ERR_HIP,
-               "rocblas_set_stream failed");
-    // deterministic sums: no atomics
-    ROKS_CHECK(rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed) == rocblas_status_success,
-               ROKS_ERR_HIP, "rocblas_set_atomics_mode failed");
-  }
-
   const size_t nb = c.nb, npw = c.npw, ntot = c.ntot, np = c.nproj;
   c.npairs = (c.nb + 1) / 2;
   int cus = 0;

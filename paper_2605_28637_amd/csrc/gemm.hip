@@ -162,7 +162,7 @@ namespace {
 void gemm_wdot_blas(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B,
                     int ldb, double* C, int ldc, double alpha, double beta, bool half_weights,
                     int nchunk) {
-  const rocblas_handle h = static_cast<rocblas_handle>(c.blas);
+  const rocblas_handle h = static_cast<rocblas_handle>(blas_handle(c));
   const double one = 1.0, zero = 0.0;
   const size_t mn = (size_t)M * N;
   nchunk = std::max(1, std::min<int>(nchunk, (int)(c.gemm_part_capacity / mn) - 1));

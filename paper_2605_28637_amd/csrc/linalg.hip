@@ -569,7 +569,7 @@ void gemm_expand(Ctx& c, int N, int K, int Md, const double* M, int ldm, bool tr
   if (Md >= 128 && N >= 64) {
     // a compute-bound size: one library DGEMM on the column-major views,
     // Y^T (K x N) = X^T (K x Md) M (Md x N)
-    ROKS_CHECK(rocblas_dgemm(static_cast<rocblas_handle>(c.blas), rocblas_operation_none,
+    ROKS_CHECK(rocblas_dgemm(static_cast<rocblas_handle>(blas_handle(c)), rocblas_operation_none,
                              transM ? rocblas_operation_none : rocblas_operation_transpose, K, N, Md,
                              &alpha, X, ldx, M, ldm, &beta, Y, ldy) == rocblas_status_success,
                ROKS_ERR_HIP, "rocblas_dgemm failed");

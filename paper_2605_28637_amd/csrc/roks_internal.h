@@ -123,9 +123,12 @@ struct Ctx {
   // ---- device ----
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  void* blas = nullptr;  // rocblas_handle on `stream` (large plain DGEMMs)
-  // a second stream for independent single-workgroup work (the rotation's
-  // exponential beside the Cholesky factorisation), joined through events
+  // created on first use (blas_handle, side_stream): every stream a context
+  // holds takes a share of the device's few hardware queues, idle or not
+  void* blas = nullptr;                 // rocblas_handle (large plain DGEMMs)
+  hipStream_t blas_stream = nullptr;    // the stream the handle was last set to
+  // a second stream for the local force part beside the nonlocal part,
+  // joined through events
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int device = 0;
@@ -271,11 +274,6 @@ constexpr int kMlpParams = kMlpWidth * kMlpFeat + kMlpWidth + kMlpWidth * kMlpWi
 struct Mlp {
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  void* blas = nullptr;  // rocblas_handle on `stream` (large plain DGEMMs)
-  // a second stream for independent single-workgroup work (the rotation's
-  // exponential beside the Cholesky factorisation), joined through events
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<DevBuf> allocations;
   float* d_p = nullptr;      // FP32 master parameters
   uint16_t* d_pb = nullptr;  // BF16 copy read by every evaluation
@@ -319,6 +317,10 @@ void build_projectors(Ctx& c);
 // device setup and memory (device.cpp)
 void init_device(Ctx& c, void* stream);
 void free_device(Ctx& c);
+// the library handle, created on first use and pointed at c.stream
+void* blas_handle(Ctx& c);
+// the side stream and its fork/join events, created on first use
+void ensure_side_stream(Ctx& c);
 void clear_timing(Ctx& c);
 void upload_static(Ctx& c);   // sphere tables, twiddles, V_ext, projectors
 void upload_positions(Ctx& c);

@@ -530,6 +530,7 @@ void forces(Ctx& c, double* f_host) {
   if (!c.d_force_loc) c.d_force_loc = dalloc<double>(c, 3 * (size_t)nat);
   // local part, dE/dR_I from rho_w = sum_L c_L rho_L, on the side stream
   // (no GEMMs there, so the library handle's stream is not involved)
+  ensure_side_stream(c);
   ROKS_HIP(hipEventRecord(c.ev_fork, c.stream));
   ROKS_HIP(hipStreamWaitEvent(c.side, c.ev_fork, 0));
   {
