@@ -1,12 +1,15 @@
 // The band-space inner products C = alpha * A W B^T + beta * C (FP64) with
 // a long K: W is the Gamma half-sphere weight (1 for G = 0, 2 otherwise), so
-// C_mn is the real inner product <a_m|b_n> of stored bands.  K is split over
-// workgroups and the partials are summed in a fixed order (bitwise
-// reproducible); the split count comes from a heuristic or, with
-// ROKS_FLAG_AUTOTUNE, from timing candidates once per shape.  Products with
-// M, N >= 128 are compute-bound and go to the rocBLAS DGEMM instead.
+// C_mn is the real inner product <a_m|b_n> of stored bands.  Small outputs
+// (the usual nb x nb or nproj x nb) run on the FP64 matrix cores with the
+// operands read straight from HBM; K is split over workgroups and the
+// partials are summed in a fixed order (bitwise reproducible); the split
+// count comes from a heuristic or, with ROKS_FLAG_AUTOTUNE, from timing
+// candidates once per shape.  Products with M, N >= 128 are compute-bound and
+// go to the rocBLAS DGEMM instead.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -20,84 +23,123 @@ namespace roks {
 namespace {
 
 // --------------------------------------------------------------------------
-// C[m][n] (+)= sum_k w_k A[m][k] B[n][k]: 64 x 64 tile, 16-deep k slices,
-// 4 x 4 outputs per thread; blockIdx.z splits K.
+// FP64 MFMA 16x16x4, one double per lane per operand: lane l gives the A
+// operand's row l%16 and the B operand's column l%16, both at depth slot
+// l/16; its 4 accumulator values are rows l/16 + 4r of column l%16.  A and B
+// only have to agree on which k each depth slot holds, so each lane reads 4
+// consecutive k of its own band: no LDS staging, 16-byte loads.
 // --------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_gemm_wdot(int M, int N, int K, const double* __restrict__ A,
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWdotGroup = 16;                  // k columns per wave and MFMA round
+constexpr int kWdotStep = 2 * 4 * kWdotGroup;   // per workgroup iteration: 2 rounds x 4 waves
+
+// 4 consecutive k of one band row (zeros beyond the row count or the chunk)
+__device__ inline void load4(const double* __restrict__ p, bool row_ok, int k, int ke, bool vec,
+                             double* v) {
+  if (vec && row_ok && k + 3 < ke) {
+    const double2 v0 = *reinterpret_cast<const double2*>(p);
+    const double2 v1 = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = v0.x;
+    v[1] = v0.y;
+    v[2] = v1.x;
+    v[3] = v1.y;
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = (row_ok && k + t < ke) ? p[t] : 0.0;
+  }
+}
+
+// C[m][n] (+)= sum_k w_k A[m][k] B[n][k] over one K chunk (blockIdx.z) for
+// an output tile of RB x CB blocks of 16 x 16.  The chunk is cut into groups
+// of 16 columns dealt to the 4 waves in turn, two groups per wave and
+// iteration with every load issued before the MFMAs; the waves' sums are
+// added in LDS in wave order, so the result does not depend on timing.
+// direct: C = alpha sum + beta C; else the sum goes to out[z][M][N].
+template <int RB, int CB>
+__global__ void __launch_bounds__(256) k_wdot_mfma(int M, int N, int K, const double* __restrict__ A,
                                                    int lda, const double* __restrict__ B, int ldb,
                                                    double* __restrict__ out, int ldo, int kchunk,
-                                                   int hw, double alpha, double beta, int direct) {
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][65];
-  const int tid = threadIdx.x;
-  const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
-  const int kb = blockIdx.z * kchunk;
-  const int ke = min(K, kb + kchunk);
-  const int tm = tid >> 4, tn = tid & 15;
-  double acc[4][4];
+                                                   int hw, int vec, double alpha, double beta,
+                                                   int direct) {
+  __shared__ double red[RB * CB * 4 * 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m0 = blockIdx.x * 16 * RB, n0 = blockIdx.y * 16 * CB;
+  const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  const int r16 = lane & 15, s = lane >> 4;
+  d4 acc[RB][CB];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < RB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  // the next k slice is loaded into registers while the current one is used
-  double pa[4], pb[4];
-  auto load = [&](int k0) {
+    for (int j = 0; j < CB; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int g0 = kb; g0 < ke; g0 += kWdotStep) {
+    double a[2][RB][4], b[2][CB][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + q * 256;
-      const int row = idx >> 4, kk = idx & 15;
-      const int k = k0 + kk;
-      pa[q] = 0.0;
-      pb[q] = 0.0;
-      if (k < ke) {
-        const double w = (hw && k >= 2) ? 2.0 : 1.0;
-        if (m0 + row < M) pa[q] = w * A[(size_t)(m0 + row) * lda + k];
-        if (n0 + row < N) pb[q] = B[(size_t)(n0 + row) * ldb + k];
+    for (int q = 0; q < 2; ++q) {
+      const int k = g0 + (4 * q + wave) * kWdotGroup + 4 * s;
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        const int row = m0 + 16 * i + r16;
+        load4(A + (size_t)row * lda + k, row < M, k, ke, vec != 0, a[q][i]);
+        if (hw) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (k + t >= 2) a[q][i][t] *= 2.0;  // stored-half weight; the G = 0 doubles weigh 1
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        const int row = n0 + 16 * j + r16;
+        load4(B + (size_t)row * ldb + k, row < N, k, ke, vec != 0, b[q][j]);
       }
     }
-  };
-  if (kb < ke) load(kb);
-  for (int k0 = kb; k0 < ke; k0 += 16) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + q * 256;
-      const int row = idx >> 4, kk = idx & 15;
-      As[kk][row] = pa[q];
-      Bs[kk][row] = pb[q];
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+          for (int j = 0; j < CB; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q][i][t], b[q][j][t], acc[i][j], 0, 0, 0);
+  }
+  for (int w = 1; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) red[((i * CB + j) * 4 + r) * 64 + lane] = acc[i][j][r];
     }
     __syncthreads();
-    if (k0 + 16 < ke) load(k0 + 16);
+    if (wave == 0) {
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
+      for (int i = 0; i < RB; ++i)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tm * 4 + i];
+        for (int j = 0; j < CB; ++j)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tn * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+          for (int r = 0; r < 4; ++r) acc[i][j][r] += red[((i * CB + j) * 4 + r) * 64 + lane];
     }
     __syncthreads();
   }
+  if (wave != 0) return;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int m = m0 + tm * 4 + i;
-    if (m >= M) continue;
+  for (int i = 0; i < RB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n = n0 + tn * 4 + j;
-      if (n >= N) continue;
-      if (direct) {
-        double v = alpha * acc[i][j];
-        if (beta != 0.0) v += beta * out[(size_t)m * ldo + n];
-        out[(size_t)m * ldo + n] = v;
-      } else {
-        out[((size_t)blockIdx.z * M + m) * N + n] = acc[i][j];
+    for (int j = 0; j < CB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + 16 * i + s + 4 * r, n = n0 + 16 * j + r16;
+        if (m >= M || n >= N) continue;
+        if (direct) {
+          double v = alpha * acc[i][j][r];
+          if (beta != 0.0) v += beta * out[(size_t)m * ldo + n];
+          out[(size_t)m * ldo + n] = v;
+        } else {
+          out[((size_t)blockIdx.z * M + m) * N + n] = acc[i][j][r];
+        }
       }
-    }
-  }
 }
 
 // few splits: one thread per output sums them in order
@@ -113,23 +155,27 @@ __global__ void k_splitk_reduce(const double* __restrict__ part, int ks, int M, 
   C[(size_t)m * ldc + n] = v;
 }
 
-// many splits: 64 outputs per workgroup, 16 groups of 64 lanes stride over
-// the splits (each split's row read coalesced), groups summed in order in LDS
-__global__ void __launch_bounds__(1024) k_splitk_reduce_cols(const double* __restrict__ part, int ks,
-                                                             int M, int N, double* __restrict__ C,
-                                                             int ldc, double alpha, double beta) {
-  __shared__ double red[16][64];
+// many splits: 16 outputs per workgroup (a 128-byte row piece of every
+// split), 64 groups of 16 lanes striding over the splits, the groups' sums
+// added in group order
+__global__ void __launch_bounds__(1024) k_splitk_reduce16(const double* __restrict__ part, int ks,
+                                                          int M, int N, double* __restrict__ C,
+                                                          int ldc, double alpha, double beta) {
+  __shared__ double red[64][17];
   const size_t mn = (size_t)M * N;
-  const size_t o = blockIdx.x * (size_t)64 + (threadIdx.x & 63);
-  const int g = threadIdx.x >> 6;
+  const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const size_t o = blockIdx.x * (size_t)16 + c;
   double s = 0.0;
-  if (o < mn)
-    for (int z = g; z < ks; z += 16) s += part[(size_t)z * mn + o];
-  red[g][threadIdx.x & 63] = s;
+  if (o < mn) {
+#pragma unroll 2
+    for (int z = g; z < ks; z += 64) s += part[(size_t)z * mn + o];
+  }
+  red[g][c] = s;
   __syncthreads();
   if (g == 0 && o < mn) {
     double t = 0.0;
-    for (int q = 0; q < 16; ++q) t += red[q][threadIdx.x];
+#pragma unroll 8
+    for (int q = 0; q < 64; ++q) t += red[q][c];
     const int m = (int)(o / N), n = (int)(o - (size_t)m * N);
     double v = alpha * t;
     if (beta != 0.0) v += beta * C[(size_t)m * ldc + n];
@@ -192,6 +238,26 @@ void gemm_wdot_blas(Ctx& c, int M, int N, int K, const double* A, int lda, const
   }
 }
 
+// blocks of 16 per tile side: the count in 1..cap with the least padding,
+// the larger on ties
+int tile_blocks(int n16, int cap) {
+  int best = 1;
+  for (int b = 1; b <= cap; ++b)
+    if (cdiv(n16, b) * b <= cdiv(n16, best) * best) best = b;
+  return best;
+}
+
+template <int RB, int CB>
+void launch_wdot_mfma(Ctx& c, dim3 grid, int M, int N, int K, const double* A, int lda, const double* B,
+                      int ldb, double* out, int ldo, int kchunk, int hw, int vec, double alpha,
+                      double beta, int direct) {
+  hipLaunchKernelGGL((k_wdot_mfma<RB, CB>), grid, dim3(256), 0, c.stream, M, N, K, A, lda, B, ldb, out,
+                     ldo, kchunk, hw, vec, alpha, beta, direct);
+}
+
+using WdotLaunch = void (*)(Ctx&, dim3, int, int, int, const double*, int, const double*, int, double*,
+                            int, int, int, int, double, double, int);
+
 // the launches of one split count (ks_req < 0: the library DGEMM in -ks_req
 // chunks of K): partials then the ordered sum, or one pass
 void gemm_wdot_launch(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B,
@@ -201,42 +267,55 @@ void gemm_wdot_launch(Ctx& c, int M, int N, int K, const double* A, int lda, con
     gemm_wdot_blas(c, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, half_weights, -ks_req);
     return;
   }
-  int kchunk = cdiv(cdiv(K, ks_req), 16) * 16;
+  static const WdotLaunch table[5][3] = {
+      {launch_wdot_mfma<1, 1>, launch_wdot_mfma<1, 2>, launch_wdot_mfma<1, 3>},
+      {launch_wdot_mfma<2, 1>, launch_wdot_mfma<2, 2>, launch_wdot_mfma<2, 3>},
+      {launch_wdot_mfma<3, 1>, launch_wdot_mfma<3, 2>, launch_wdot_mfma<3, 3>},
+      {launch_wdot_mfma<4, 1>, launch_wdot_mfma<4, 2>, launch_wdot_mfma<4, 3>},
+      {launch_wdot_mfma<5, 1>, launch_wdot_mfma<5, 2>, launch_wdot_mfma<5, 3>}};
+  const int RB = tile_blocks(cdiv(M, 16), 5), CB = tile_blocks(cdiv(N, 16), 3);
+  const WdotLaunch launch = table[RB - 1][CB - 1];
+  // 16-byte loads need 16-byte aligned rows
+  const int vec = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) % 16 == 0 &&
+                   lda % 2 == 0 && ldb % 2 == 0)
+                      ? 1
+                      : 0;
+  const int hw = half_weights ? 1 : 0;
+  const int kchunk = cdiv(cdiv(K, std::max(1, ks_req)), kWdotStep) * kWdotStep;
   const int ks = cdiv(K, kchunk);
-  dim3 grid(cdiv(M, 64), cdiv(N, 64), ks);
+  dim3 grid(cdiv(M, 16 * RB), cdiv(N, 16 * CB), ks);
   if (ks == 1) {
-    hipLaunchKernelGGL(k_gemm_wdot, grid, dim3(256), 0, c.stream, M, N, K, A, lda, B, ldb, C, ldc,
-                       kchunk, half_weights ? 1 : 0, alpha, beta, 1);
+    launch(c, grid, M, N, K, A, lda, B, ldb, C, ldc, kchunk, hw, vec, alpha, beta, 1);
     ROKS_HIP(hipGetLastError());
     return;
   }
-  hipLaunchKernelGGL(k_gemm_wdot, grid, dim3(256), 0, c.stream, M, N, K, A, lda, B, ldb, c.d_gemm_part,
-                     N, kchunk, half_weights ? 1 : 0, 1.0, 0.0, 0);
+  launch(c, grid, M, N, K, A, lda, B, ldb, c.d_gemm_part, N, kchunk, hw, vec, 1.0, 0.0, 0);
   ROKS_HIP(hipGetLastError());
   const size_t mn = (size_t)M * N;
   if (ks > 16)
-    hipLaunchKernelGGL(k_splitk_reduce_cols, dim3((unsigned)((mn + 63) / 64)), dim3(1024), 0,
-                       c.stream, c.d_gemm_part, ks, M, N, C, ldc, alpha, beta);
+    hipLaunchKernelGGL(k_splitk_reduce16, dim3((unsigned)((mn + 15) / 16)), dim3(1024), 0, c.stream,
+                       c.d_gemm_part, ks, M, N, C, ldc, alpha, beta);
   else
     hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, c.stream,
                        c.d_gemm_part, ks, M, N, C, ldc, alpha, beta);
   ROKS_HIP(hipGetLastError());
 }
 
+// split counts the partial buffer holds, at most one per workgroup step of K
 int max_splits(const Ctx& c, int M, int N, int K) {
-  int ks = std::max(1, K / 16);
+  int ks = std::max(1, cdiv(K, kWdotStep));
   while ((size_t)ks * M * N > c.gemm_part_capacity && ks > 1) --ks;
   return ks;
 }
 
-// Every k slice costs one global-load latency that one slice of compute
-// cannot hide, so small outputs get many workgroups of ~2 slices each
-// (several per CU); the split-K partials are summed in a fixed order.
+// A workgroup reads its K chunk once per tile; the smallest chunk (one step,
+// 128 columns) is used until the tiles times chunks reach ~1 000 workgroups.
 int heuristic_splits(const Ctx& c, int M, int N, int K) {
-  const int tiles = cdiv(M, 64) * cdiv(N, 64);
   // compute-bound sizes: the library DGEMM, K cut so ~1 000 tiles fill the GPU
-  if (M >= 128 && N >= 128) return -std::max(1, std::min(32, cdiv(1024, tiles)));
-  int ks = std::max(1, std::min(2048 / tiles, K / 32));
+  if (M >= 128 && N >= 128)
+    return -std::max(1, std::min(32, cdiv(1024, cdiv(M, 64) * cdiv(N, 64))));
+  const int tiles = cdiv(M, 16 * tile_blocks(cdiv(M, 16), 5)) * cdiv(N, 16 * tile_blocks(cdiv(N, 16), 3));
+  const int ks = std::max(1, std::min(cdiv(K, kWdotStep), cdiv(1024, tiles)));
   return std::min(ks, max_splits(c, M, N, K));
 }
 
@@ -256,7 +335,7 @@ int tuned_splits(Ctx& c, int M, int N, int K, const double* A, int lda, const do
     for (int v : {-1, -4, -8, -16, -32})  // the library DGEMM in |v| chunks of K
       if ((size_t)(-v + 1) * M * N <= c.gemm_part_capacity) cand.push_back(v);
   const int hh = std::max(1, std::abs(h));
-  for (int v : {hh / 4, hh / 2, hh, 2 * hh, 4 * hh, 1, 64, 128, 256, 512})
+  for (int v : {hh / 4, hh / 2, hh, 2 * hh, 4 * hh, 1, 32, 64})
     if (v >= 1 && v <= hi && std::find(cand.begin(), cand.end(), v) == cand.end()) cand.push_back(v);
   double* scratch = dalloc<double>(c, (size_t)M * N);
   hipEvent_t e0, e1;

@@ -1,6 +1,6 @@
 // Dense linear algebra for the band and projector spaces (FP64):
-//   gemm_expand Y = alpha * M^T X + beta * Y (short inner dimension; from 128
-//               rows of M on, the rocBLAS DGEMM).
+//   gemm_expand Y = alpha * M^T X + beta * Y (short inner dimension, on the
+//               FP64 matrix cores; from 128 rows of M on, the rocBLAS DGEMM).
 //   gemm_small  nb x nb products (rotation, exponential, Cholesky factors).
 // plus per-band weighted dots, the Cholesky inverse, the subspace matrices
 // R / kappa / A and the Teter preconditioner.
@@ -22,67 +22,85 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // --------------------------------------------------------------------------
-// Y[n][k] = alpha sum_m M(m, n) X[m][k] + beta Y[n][k]; tile 32 n x 128 k.
+// Y[n][k] = alpha sum_m M(m, n) X[m][k] + beta Y[n][k] on the FP64 matrix
+// cores (MFMA 16x16x4: lane l gives the A operand's row l%16 and the B
+// operand's column l%16 at depth slot l/16; its 4 results are rows
+// l/16 + 4r of column l%16).  Each wave owns 16 columns of K and 16 NB rows
+// of Y: A = M^T (rows n), B = X (columns k), so every X load is a 128-byte
+// row piece.  The workgroup stages M in LDS 64 rows at a time, and each wave
+// issues all of a chunk's X loads before its MFMAs.
 // --------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_gemm_expand(int N, int K, int Md, const double* __restrict__ Mt,
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kExpandRows = 64;  // rows of X (depth) per chunk
+
+template <int NB>
+__global__ void __launch_bounds__(256) k_expand_mfma(int N, int K, int Md, const double* __restrict__ Mt,
                                                      int ldm, int transM, const double* __restrict__ X,
                                                      int ldx, double* __restrict__ Y, int ldy,
                                                      double alpha, double beta) {
-  __shared__ double Xs[16][128];
-  __shared__ double Ms[16][33];
-  const int tid = threadIdx.x;
-  const int k0 = blockIdx.x * 128, n0 = blockIdx.y * 32;
-  const int tn = tid >> 5, tk = tid & 31;
-  double acc[4][4];
+  constexpr int MC = kExpandRows, W = 16 * NB, NL = MC * W / 256;
+  __shared__ double Ms[MC][W + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int k0 = (blockIdx.x * 4 + wave) * 16;
+  const bool active = k0 < K;
+  const int n0 = blockIdx.y * W;
+  const int c16 = lane & 15, s = lane >> 4;
+  const int k = k0 + c16;
+  double yv[NB][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int mb = 0; mb < Md; mb += 16) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int idx = tid + q * 256;
-      const int mm = idx >> 7, kk = idx & 127;
-      const int m = mb + mm, k = k0 + kk;
-      Xs[mm][kk] = (m < Md && k < K) ? X[(size_t)m * ldx + k] : 0.0;
+    for (int r = 0; r < 4; ++r) {
+      const int n = n0 + 16 * i + s + 4 * r;
+      yv[i][r] = (beta != 0.0 && active && n < N && k < K) ? Y[(size_t)n * ldy + k] : 0.0;
     }
+  d4 acc[NB];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int idx = tid + q * 256;
-      const int mm = idx >> 5, nn = idx & 31;
-      const int m = mb + mm, n = n0 + nn;
+  for (int i = 0; i < NB; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int mc = 0; mc < Md; mc += MC) {
+    double xb[MC / 4];
+#pragma unroll
+    for (int t = 0; t < MC / 4; ++t) {
+      const int m = mc + 4 * t + s;
+      xb[t] = (active && m < Md && k < K) ? X[(size_t)m * ldx + k] : 0.0;
+    }
+    double tv[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int idx = tid + 256 * q;
+      const int mm = idx / W, nn = idx - mm * W;
+      const int m = mc + mm, n = n0 + nn;
       double v = 0.0;
       if (m < Md && n < N) v = transM ? Mt[(size_t)n * ldm + m] : Mt[(size_t)m * ldm + n];
-      Ms[mm][nn] = v;
+      tv[q] = v;
+    }
+    __syncthreads();  // the previous chunk's reads of Ms are done
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int idx = tid + 256 * q;
+      const int mm = idx / W;
+      Ms[mm][idx - mm * W] = tv[q];
     }
     __syncthreads();
+    const int depth = min(MC, Md - mc);
 #pragma unroll
-    for (int mm = 0; mm < 16; ++mm) {
-      double a[4], b[4];
+    for (int t = 0; t < MC / 4; ++t) {
+      if (4 * t < depth) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = Ms[mm][tn * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Xs[mm][tk * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int n = n0 + tn * 4 + i;
-    if (n >= N) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = k0 + tk * 4 + j;
-      if (k >= K) continue;
-      double v = alpha * acc[i][j];
-      if (beta != 0.0) v += beta * Y[(size_t)n * ldy + k];
-      Y[(size_t)n * ldy + k] = v;
+        for (int i = 0; i < NB; ++i)
+          acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ms[4 * t + s][16 * i + c16], xb[t], acc[i], 0, 0, 0);
+      }
     }
   }
+  if (!active) return;
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int n = n0 + 16 * i + s + 4 * r;
+      if (n < N && k < K) Y[(size_t)n * ldy + k] = alpha * acc[i][r] + beta * yv[i][r];
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -575,9 +593,22 @@ void gemm_expand(Ctx& c, int N, int K, int Md, const double* M, int ldm, bool tr
                ROKS_ERR_HIP, "rocblas_dgemm failed");
     return;
   }
-  dim3 grid(cdiv(K, 128), cdiv(N, 32));
-  hipLaunchKernelGGL(k_gemm_expand, grid, dim3(256), 0, c.stream, N, K, Md, M, ldm, transM ? 1 : 0, X,
-                     ldx, Y, ldy, alpha, beta);
+  // 16-row blocks of Y per wave: 1..3, the least padding, the larger on ties
+  const int n16 = cdiv(N, 16);
+  int nb = 1;
+  for (int b = 2; b <= 3; ++b)
+    if (cdiv(n16, b) * b <= cdiv(n16, nb) * nb) nb = b;
+  dim3 grid(cdiv(K, 64), cdiv(N, 16 * nb));
+  const int tm = transM ? 1 : 0;
+  if (nb == 1)
+    hipLaunchKernelGGL(k_expand_mfma<1>, grid, dim3(256), 0, c.stream, N, K, Md, M, ldm, tm, X, ldx, Y,
+                       ldy, alpha, beta);
+  else if (nb == 2)
+    hipLaunchKernelGGL(k_expand_mfma<2>, grid, dim3(256), 0, c.stream, N, K, Md, M, ldm, tm, X, ldx, Y,
+                       ldy, alpha, beta);
+  else
+    hipLaunchKernelGGL(k_expand_mfma<3>, grid, dim3(256), 0, c.stream, N, K, Md, M, ldm, tm, X, ldx, Y,
+                       ldy, alpha, beta);
   ROKS_HIP(hipGetLastError());
 }
 
