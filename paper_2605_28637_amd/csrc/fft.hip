@@ -518,57 +518,50 @@ __global__ void __launch_bounds__(512) k_plane_density(
 }
 
 // ---------------------------------------------------------------------------
-// full-grid complex 3D FFT on [z][x][y] data (Hartree, V_ext, forces), FP64
+// full-grid complex 3D FFT on [z][x][y] data (Hartree, V_ext, forces), FP64:
+// one pass per axis.  Line c (of ncols) of batch b = blockIdx.y has element
+// j at data[b bstride + j estr + c cstr]; a workgroup moves CH consecutive
+// lines into LDS (line stride n + 1, so strided loads do not pile onto one
+// bank), transforms them and writes them back.  Loads run along the
+// contiguous direction: j when estr == 1, else c.
 // ---------------------------------------------------------------------------
 template <int MAXP>
-__global__ void __launch_bounds__(512) k_fft_planes(double2* __restrict__ data, PlaneGeom g,
-                                                    const double2* __restrict__ tw1g,
-                                                    const double2* __restrict__ tw2g, int sign) {
+__global__ void __launch_bounds__(256) k_fft_axis(double2* __restrict__ data, FftPlan1D plan,
+                                                  const double2* __restrict__ twg, int ncols, int CH,
+                                                  long estr, long cstr, long bstride, int sign) {
   extern __shared__ char smem_raw[];
   double2* smem = reinterpret_cast<double2*>(smem_raw);
-  double2* tw1 = smem;
-  double2* tw2 = smem + g.N1;
-  double2* plane = smem + g.N1 + g.N2;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int z = blockIdx.x;
-  const int np2 = g.N1 * g.N2;
-  for (int i = tid; i < g.N1; i += nthr) tw1[i] = tw1g[i];
-  for (int i = tid; i < g.N2; i += nthr) tw2[i] = tw2g[i];
-  double2* d = data + (size_t)z * np2;
-  for (int pt = tid; pt < np2; pt += nthr) {
-    const int x = pt / g.N2, y = pt - x * g.N2;
-    plane[x * g.PS + y] = d[pt];
-  }
-  __syncthreads();
-  fft_lines<double, MAXP>(plane, g.p2, g.N1, Strided{g.PS}, 1, tw2, sign);
-  fft_lines<double, MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, sign);
-  for (int pt = tid; pt < np2; pt += nthr) {
-    const int x = pt / g.N2, y = pt - x * g.N2;
-    d[pt] = plane[x * g.PS + y];
-  }
-}
-
-template <int MAXP>
-__global__ void __launch_bounds__(512) k_fft_zlines(double2* __restrict__ data, int np2,
-                                                    FftPlan1D plan, const double2* __restrict__ twg,
-                                                    int CH, int sign) {
-  extern __shared__ char smem_raw[];
-  double2* smem = reinterpret_cast<double2*>(smem_raw);
-  const int N3 = plan.n;
+  const int L = plan.n, LS = L + 1;
   double2* tw = smem;
-  double2* buf = smem + N3;
+  double2* buf = smem + L;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int p0 = blockIdx.x * CH;
-  for (int i = tid; i < N3; i += nthr) tw[i] = twg[i];
-  for (int idx = tid; idx < CH * N3; idx += nthr) {
-    const int z = idx / CH, c = idx - z * CH;
-    buf[c * N3 + z] = (p0 + c < np2) ? data[(size_t)z * np2 + p0 + c] : make_double2(0.0, 0.0);
+  const int c0 = blockIdx.x * CH;
+  double2* base = data + (size_t)blockIdx.y * bstride;
+  const bool contig = estr == 1;
+  for (int i = tid; i < L; i += nthr) tw[i] = twg[i];
+  for (int idx = tid; idx < CH * L; idx += nthr) {
+    int c, j;
+    if (contig) {
+      c = idx / L;
+      j = idx - c * L;
+    } else {
+      j = idx / CH;
+      c = idx - j * CH;
+    }
+    buf[c * LS + j] = (c0 + c < ncols) ? base[j * estr + (long)(c0 + c) * cstr] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  fft_lines<double, MAXP>(buf, plan, CH, Strided{N3}, 1, tw, sign);
-  for (int idx = tid; idx < CH * N3; idx += nthr) {
-    const int z = idx / CH, c = idx - z * CH;
-    if (p0 + c < np2) data[(size_t)z * np2 + p0 + c] = buf[c * N3 + z];
+  fft_lines<double, MAXP>(buf, plan, CH, Strided{LS}, 1, tw, sign);
+  for (int idx = tid; idx < CH * L; idx += nthr) {
+    int c, j;
+    if (contig) {
+      c = idx / L;
+      j = idx - c * L;
+    } else {
+      j = idx / CH;
+      c = idx - j * CH;
+    }
+    if (c0 + c < ncols) base[j * estr + (long)(c0 + c) * cstr] = buf[c * LS + j];
   }
 }
 
@@ -749,33 +742,50 @@ void launch_plane_density(Ctx& c, const void* T, int npairs, double* rho_part, i
   }
 }
 
-template <typename R, int MP>
-static void run_fft_planes(Ctx& c, double2* data, int sign) {
-  const int nthr = plane_threads(c);
-  const size_t lds = plane_lds(c, nthr, sizeof(double2));
-  allow_lds(k_fft_planes<MP>, lds);
-  hipLaunchKernelGGL(k_fft_planes<MP>, dim3(c.N[2]), dim3(nthr), lds, c.stream, data, geom(c),
-                     c.d_tw[0], c.d_tw[1], sign);
-  ROKS_HIP(hipGetLastError());
-}
+constexpr int kAxisThreads = 256;
+constexpr int kAxisPoints = 2048;  // points per workgroup at most (8 per thread)
 
 template <typename R, int MP>
-static void run_fft_zlines(Ctx& c, double2* data, int sign, int CH) {
-  const size_t lds = (size_t)(c.N[2] + CH * c.N[2]) * sizeof(double2);
-  allow_lds(k_fft_zlines<MP>, lds);
+static void run_fft_axis(Ctx& c, double2* data, int sign, int axis) {
+  const int n = c.N[axis];
   const int np2 = c.N[0] * c.N[1];
-  hipLaunchKernelGGL(k_fft_zlines<MP>, dim3(cdiv(np2, CH)), dim3(kZThreads), lds, c.stream, data,
-                     np2, c.plan[2], c.d_tw[2], CH, sign);
+  // lines of this axis, their strides, and the batch (x lines: one z-plane each)
+  int ncols, nbatch = 1;
+  long estr, cstr, bstride = 0;
+  if (axis == 1) {  // y: contiguous lines, one per (z, x)
+    ncols = c.N[2] * c.N[0];
+    estr = 1;
+    cstr = c.N[1];
+  } else if (axis == 0) {  // x: stride N2 within each z-plane
+    ncols = c.N[1];
+    estr = c.N[1];
+    cstr = 1;
+    nbatch = c.N[2];
+    bstride = np2;
+  } else {  // z: stride N1 N2
+    ncols = np2;
+    estr = np2;
+    cstr = 1;
+  }
+  // ~1 000 workgroups per pass (several per CU, so their loads overlap), at
+  // most kAxisPoints points each
+  const int lines = ncols * nbatch;
+  const int CH = std::max(1, std::min(kAxisPoints / n, cdiv(lines, 1024)));
+  const size_t lds = (size_t)(n + CH * (n + 1)) * sizeof(double2);
+  allow_lds(k_fft_axis<MP>, lds);
+  hipLaunchKernelGGL(k_fft_axis<MP>, dim3(cdiv(ncols, CH), nbatch), dim3(kAxisThreads), lds, c.stream,
+                     data, c.plan[axis], c.d_tw[axis], ncols, CH, estr, cstr, bstride, sign);
   ROKS_HIP(hipGetLastError());
 }
 
 void launch_fft3d(Ctx& c, double2* data, int sign) {
-  KernelTimer kt(c, "fft3d", 4.0 * c.ntot * sizeof(double2));
-  const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], plane_threads(c)));
-  ROKS_DISPATCH_MAXP(double, mp, run_fft_planes, c, data, sign);
-  const int CH = 2 * zchunk(c);
-  const int mz = pick_maxp(needed_points(CH * c.N[2], kZThreads));
-  ROKS_DISPATCH_MAXP(double, mz, run_fft_zlines, c, data, sign, CH);
+  KernelTimer kt(c, "fft3d", 6.0 * c.ntot * sizeof(double2));
+  for (int axis : {1, 0, 2}) {
+    const int n = c.N[axis];
+    const int pts = (kAxisPoints / n) * n;  // CH n at most
+    const int mp = pick_maxp(needed_points(std::max(n, pts), kAxisThreads));
+    ROKS_DISPATCH_MAXP(double, mp, run_fft_axis, c, data, sign, axis);
+  }
 }
 
 }  // namespace roks

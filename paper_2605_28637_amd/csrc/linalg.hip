@@ -258,54 +258,78 @@ __global__ void __launch_bounds__(1024) k_cholesky_inverse(const double* __restr
   if (tid == 0) flag[0] = bad;
 }
 
-// Same factorisation for n <= 128 with the matrix resident in LDS,
-// right-looking: at column j scale column j of L, and (n <= 96) also run the
-// forward elimination of L X = I on an LDS copy of the identity, so that row
-// j of X = L^-1 is final after step j; then rank-1 updates of the trailing
-// block of A and of the rows below j of X.  All work per step is parallel.
+// Cholesky factorisation G = L L^T and (inv_in_lds, n <= 96) the inverse
+// L^-1 in one workgroup, right-looking, one barrier per column.  Threads sit
+// on a fixed 32 x 32 grid (rows i = j + 1 + ty + 32 a, columns k = ... + tx).
+// At column j: A_ik -= A_ij A_kj / A_jj on the trailing block and
+// X_ic -= A_ij X_jc / A_jj on the rows below j of X (the forward elimination
+// of L X = I), both from the unscaled column j and row j, which nobody writes
+// in that step; row j of X becomes row j of L^-1 = X_j / sqrt(A_jj) one step
+// later.  Thread 0, which updates the next diagonal element, also takes the
+// next pivot's 1/d and 1/sqrt(d) (a pivot not above 1e-12 of its Gram
+// diagonal, or not finite, sets the flag and is replaced by 1).
+// Without inv_in_lds (97 <= n <= 128) the factor is scaled in place and
+// L^-1 is formed column by column from it.
 __device__ void cholesky_lds_body(const double* __restrict__ G, int n, double* __restrict__ Linv,
                                   int32_t* __restrict__ flag, int inv_in_lds, double* A) {
   __shared__ int bad;
+  __shared__ double gdiag[128];   // the Gram diagonal, the reference of the pivot test
+  __shared__ double piv[2][2];    // [step parity]: 1/d, 1/sqrt(d)
+  __shared__ double rsv[128];     // 1/L_jj
   const int tid = threadIdx.x, nthr = blockDim.x;
+  const int tx = tid & 31, ty = tid >> 5, ny = nthr >> 5;
   double* X = A + n * n;
-  if (tid == 0) bad = 0;
   for (int t = tid; t < n * n; t += nthr) {
-    A[t] = G[t];
-    if (inv_in_lds) X[t] = (t / n == t % n) ? 1.0 : 0.0;
+    const double g = G[t];
+    A[t] = g;
+    const bool dg = t / n == t % n;
+    if (dg) gdiag[t / n] = g;
+    if (inv_in_lds) X[t] = dg ? 1.0 : 0.0;
+  }
+  auto pivot = [&](int j, double d) {
+    if (!(d > 1e-12 * gdiag[j]) || !isfinite(d)) {
+      bad = 1;
+      d = 1.0;
+    }
+    const double rs = 1.0 / sqrt(d);
+    piv[j & 1][0] = 1.0 / d;
+    piv[j & 1][1] = rs;
+    rsv[j] = rs;
+  };
+  if (tid == 0) {
+    bad = 0;
+    pivot(0, G[0]);
   }
   __syncthreads();
   for (int j = 0; j < n; ++j) {
-    if (tid == 0) {
-      double d = A[j * n + j];
-      if (!(d > 1e-12 * G[(size_t)j * n + j]) || !isfinite(d)) {
-        bad = 1;
-        d = 1.0;
+    const double rd = piv[j & 1][0];
+    // the previous row of the inverse is final: scale it
+    if (inv_in_lds && j > 0)
+      for (int cc = tid; cc < j; cc += nthr) X[(j - 1) * n + cc] *= rsv[j - 1];
+    for (int i = j + 1 + ty; i < n; i += ny) {
+      const double f = A[i * n + j] * rd;
+      for (int k = j + 1 + tx; k <= i; k += 32) {
+        const double v = A[i * n + k] - f * A[k * n + j];
+        A[i * n + k] = v;
+        if (i == j + 1 && k == j + 1) pivot(j + 1, v);  // thread 0
       }
-      A[j * n + j] = sqrt(d);
-    }
-    __syncthreads();
-    const double dj = A[j * n + j];
-    for (int i = j + 1 + tid; i < n; i += nthr) A[i * n + j] /= dj;
-    if (inv_in_lds)
-      for (int cc = tid; cc <= j; cc += nthr) X[j * n + cc] /= dj;
-    __syncthreads();
-    const int r = n - j - 1;
-    for (int idx = tid; idx < r * r; idx += nthr) {
-      const int i = j + 1 + idx / r, k = j + 1 + idx % r;
-      if (k <= i) A[i * n + k] -= A[i * n + j] * A[k * n + j];
-    }
-    if (inv_in_lds) {
-      const int w = j + 1;
-      for (int idx = tid; idx < r * w; idx += nthr) {
-        const int i = j + 1 + idx / w, cc = idx % w;
-        X[i * n + cc] -= A[i * n + j] * X[j * n + cc];
-      }
+      if (inv_in_lds)
+        for (int cc = tx; cc <= j; cc += 32) X[i * n + cc] -= f * X[j * n + cc];
     }
     __syncthreads();
   }
   if (inv_in_lds) {
+    for (int cc = tid; cc < n; cc += nthr) X[(n - 1) * n + cc] *= rsv[n - 1];
+    __syncthreads();
     for (int t = tid; t < n * n; t += nthr) Linv[t] = (t % n <= t / n) ? X[t] : 0.0;
   } else {
+    // L = column j of A scaled by 1/sqrt(d_j), diagonal sqrt(d_j)
+    for (int t = tid; t < n * n; t += nthr) {
+      const int i = t / n, k = t % n;
+      if (k < i) A[t] *= rsv[k];
+      else if (k == i) A[t] = 1.0 / rsv[k];
+    }
+    __syncthreads();
     for (int col = tid; col < n; col += nthr) {
       for (int i = 0; i < col; ++i) Linv[(size_t)i * n + col] = 0.0;
       Linv[(size_t)col * n + col] = 1.0 / A[col * n + col];
@@ -332,7 +356,7 @@ __global__ void __launch_bounds__(1024) k_cholesky_inverse_lds(const double* __r
 // degree m and the squarings s minimise the products m + s subject to
 // theta^(m+1)/(m+1)! <= 1e-17 with theta = ||delta D||_1 / 2^s <= 1 (the
 // Taylor tail; exp of an antisymmetric matrix is orthogonal, so the bound is
-// relative).  Products run as 2 x 2 register blocks.
+// relative).  Products run on the FP64 matrix cores.
 __device__ void expm_lds_body(const double* __restrict__ D, int n, double delta,
                               double* __restrict__ U, double* S) {
   __shared__ double nrm;
@@ -352,27 +376,41 @@ __device__ void expm_lds_body(const double* __restrict__ D, int n, double delta,
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    // lane sq (0..60) prices s = sq squarings: the least degree m whose Taylor
+    // tail th^(m+1)/(m+1)! is below 1e-17 (th = ||X||_1 / 2^sq <= 1, m <= 30);
+    // the cheapest m + s wins, the fewest squarings on ties.  A norm that is
+    // not finite gets m = 1, s = 0 (the rotation is then rejected downstream);
+    // one above 2^60 gets m = 30, s = 0.
+    constexpr int kNone = 1 << 20;  // no admissible degree at this s
+    const int sq = tid;
+    int cost = kNone, m = 30;
+    const double th = ldexp(mx, -sq);
+    if (sq <= 60 && isfinite(mx) && th <= 1.0) {
+      double term = th;  // th^(m+1)/(m+1)!
+      m = 0;
+      while (term > 1e-17 && m < 30) {
+        ++m;
+        term *= th / (m + 1);
+      }
+      cost = m + sq;
+    }
+    int key = cost * 64 + sq;  // the least cost, then the least sq
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) key = min(key, __shfl_xor(key, off, 64));
+    const int win = key & 63;
+    const int mwin = __shfl(m, win, 64);
     if (tid == 0) {
       nrm = mx;
-      int best_s = 0, best_m = isfinite(mx) ? 30 : 1, best = isfinite(mx) ? 1 << 30 : 0;
-      for (int sq = 0; sq <= 60; ++sq) {
-        const double th = ldexp(mx, -sq);
-        if (th > 1.0) continue;
-        double term = th;  // th^(m+1)/(m+1)!
-        int m = 0;
-        while (term > 1e-17 && m < 30) {
-          ++m;
-          term *= th / (m + 1);
-        }
-        if (m + sq < best) {
-          best = m + sq;
-          best_s = sq;
-          best_m = m;
-        }
-        if (m <= 1) break;
+      if (!isfinite(mx)) {
+        plan[0] = 0;
+        plan[1] = 1;
+      } else if ((key >> 6) >= kNone) {
+        plan[0] = 0;
+        plan[1] = 30;
+      } else {
+        plan[0] = win;
+        plan[1] = mwin;
       }
-      plan[0] = best_s;
-      plan[1] = best_m;
     }
   }
   __syncthreads();
@@ -384,29 +422,28 @@ __device__ void expm_lds_body(const double* __restrict__ D, int n, double delta,
     P[t] = m >= 1 ? X[t] / (double)m + id : id;
   }
   __syncthreads();
-  const int nh = (n + 1) / 2;
-  // O = L R * f (+ I when add_id)
+  // O = L R * f (+ I when add_id) on the FP64 matrix cores: wave w computes
+  // the 16 x 16 output blocks w, w + 16, ...  (MFMA 16x16x4 operands from
+  // LDS: lane l reads row l%16 of L and column l%16 of R at depth slot l/16;
+  // its results are rows l/16 + 4r of column l%16)
+  const int lane = tid & 63, wave = tid >> 6, nw = nthr >> 6;
+  const int nbk = (n + 15) / 16, r16 = lane & 15, s4 = lane >> 4;
   auto product = [&](const double* L, const double* R, double* O, double f, bool add_id) {
-    for (int b = tid; b < nh * nh; b += nthr) {
-      const int bi = b / nh, bj = b - bi * nh;
-      const int i0 = 2 * bi, j0 = 2 * bj;
-      const bool i1 = i0 + 1 < n, j1 = j0 + 1 < n;
-      double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
-      for (int k = 0; k < n; ++k) {
-        const double a0 = L[i0 * n + k];
-        const double a1 = i1 ? L[(i0 + 1) * n + k] : 0.0;
-        const double b0 = R[k * n + j0];
-        const double b1 = j1 ? R[k * n + j0 + 1] : 0.0;
-        c00 = fma(a0, b0, c00);
-        c01 = fma(a0, b1, c01);
-        c10 = fma(a1, b0, c10);
-        c11 = fma(a1, b1, c11);
+    for (int blk = wave; blk < nbk * nbk; blk += nw) {
+      const int bi = blk / nbk, bj = blk - bi * nbk;
+      const int row = 16 * bi + r16, col = 16 * bj + r16;
+      d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+      for (int k4 = 0; k4 < n; k4 += 4) {
+        const int k = k4 + s4;
+        const double a = (row < n && k < n) ? L[row * n + k] : 0.0;
+        const double b = (k < n && col < n) ? R[k * n + col] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
       }
-      const double d = add_id ? 1.0 : 0.0;
-      O[i0 * n + j0] = c00 * f + (i0 == j0 ? d : 0.0);
-      if (j1) O[i0 * n + j0 + 1] = c01 * f + (i0 == j0 + 1 ? d : 0.0);
-      if (i1) O[(i0 + 1) * n + j0] = c10 * f + (i0 + 1 == j0 ? d : 0.0);
-      if (i1 && j1) O[(i0 + 1) * n + j0 + 1] = c11 * f + (i0 == j0 ? d : 0.0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * bi + s4 + 4 * r, j = 16 * bj + r16;
+        if (i < n && j < n) O[i * n + j] = acc[r] * f + ((add_id && i == j) ? 1.0 : 0.0);
+      }
     }
     __syncthreads();
   };
