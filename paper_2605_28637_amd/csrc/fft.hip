@@ -203,19 +203,29 @@ __device__ __forceinline__ void fft_stage(C2<R>* buf, int N, int Ns, int nlines,
   __syncthreads();
 }
 
+// Radix sets a kernel is built for: plans of radix-8 stages only (a length
+// that is a power of 8), or any of 8, 4, 2, 3, 5.  The stages a kernel can
+// meet are all inlined into its transform loop, and the general set needs
+// about twice the registers of the radix-8 one.
+constexpr int kRadix8 = 1, kRadixAny = 0;
+
 // Transform `nlines` lines in place; MAXP bounds ceil(nlines N / blockDim).
-template <typename R, int MAXP, typename LineMap>
+template <typename R, int MAXP, int RS, typename LineMap>
 __device__ void fft_lines(C2<R>* buf, const FftPlan1D& plan, int nlines, LineMap lm, int estride,
                           const C2<R>* tw, int sign) {
   int Ns = 1;
   for (int s = 0; s < plan.nstages; ++s) {
     const int RX = plan.radix[s];
-    switch (RX) {
-      case 8: fft_stage<R, 8, (MAXP + 7) / 8>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
-      case 4: fft_stage<R, 4, (MAXP + 3) / 4>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
-      case 2: fft_stage<R, 2, (MAXP + 1) / 2>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
-      case 3: fft_stage<R, 3, (MAXP + 2) / 3>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
-      default: fft_stage<R, 5, (MAXP + 4) / 5>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
+    if constexpr (RS == kRadix8) {
+      fft_stage<R, 8, (MAXP + 7) / 8>(buf, plan.n, Ns, nlines, lm, estride, tw, sign);
+    } else {
+      switch (RX) {
+        case 8: fft_stage<R, 8, (MAXP + 7) / 8>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
+        case 4: fft_stage<R, 4, (MAXP + 3) / 4>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
+        case 2: fft_stage<R, 2, (MAXP + 1) / 2>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
+        case 3: fft_stage<R, 3, (MAXP + 2) / 3>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
+        default: fft_stage<R, 5, (MAXP + 4) / 5>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
+      }
     }
     Ns *= RX;
   }
@@ -235,7 +245,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // ---------------------------------------------------------------------------
 // z pass, G -> r
 // ---------------------------------------------------------------------------
-template <typename R, int MAXP>
+template <typename R, int MAXP, int RS>
 __global__ void __launch_bounds__(512) k_zpass_bwd(const double2* __restrict__ vecs, int nvec,
                                                     int npw, const ColDesc* __restrict__ cols,
                                                     int ndesc, int nH, FftPlan1D plan,
@@ -275,7 +285,7 @@ __global__ void __launch_bounds__(512) k_zpass_bwd(const double2* __restrict__ v
       buf[(2 * c) * N3 + wrap(-l, N3)] = vm;
   }
   __syncthreads();
-  fft_lines<R, MAXP>(buf, plan, 2 * CH, Strided{N3}, 1, tw, +1);
+  fft_lines<R, MAXP, RS>(buf, plan, 2 * CH, Strided{N3}, 1, tw, +1);
   for (int idx = tid; idx < CH * N3; idx += nthr) {
     const int z = idx / CH, c = idx - z * CH;
     const int j = j0 + c;
@@ -289,7 +299,7 @@ __global__ void __launch_bounds__(512) k_zpass_bwd(const double2* __restrict__ v
 // ---------------------------------------------------------------------------
 // z pass, r -> G, with unpacking, scaling and the (FP64) kinetic term
 // ---------------------------------------------------------------------------
-template <typename R, int MAXP>
+template <typename R, int MAXP, int RS>
 __global__ void __launch_bounds__(512) k_zpass_fwd(
     const C2<R>* __restrict__ T, int ncol, const ColDesc* __restrict__ cols, int ndesc, int nH,
     FftPlan1D plan, const C2<R>* __restrict__ twg, const double2* __restrict__ vecs, int nvec,
@@ -319,7 +329,7 @@ __global__ void __launch_bounds__(512) k_zpass_fwd(
     buf[(2 * c + 1) * N3 + z] = m;
   }
   __syncthreads();
-  fft_lines<R, MAXP>(buf, plan, 2 * CH, Strided{N3}, 1, tw, -1);
+  fft_lines<R, MAXP, RS>(buf, plan, 2 * CH, Strided{N3}, 1, tw, -1);
   const double w1 = kinw[n1];
   const double w2 = has2 ? kinw[n2] : 0.0;
   for (int idx = tid; idx < CH * N3; idx += nthr) {
@@ -353,7 +363,7 @@ struct PlaneGeom {
   FftPlan1D p1, p2;
 };
 
-template <typename R, int MAXP>
+template <typename R, int MAXP, int RS>
 __global__ void __launch_bounds__(512) k_plane_apply(
     C2<R>* __restrict__ T, const int32_t* __restrict__ colpos, PlaneGeom g,
     const C2<R>* __restrict__ tw1g, const C2<R>* __restrict__ tw2g,
@@ -393,8 +403,8 @@ __global__ void __launch_bounds__(512) k_plane_apply(
     for (int col = tid; col < g.ncol; col += nthr)
       plane[colpos[2 * col] * g.PS + colpos[2 * col + 1]] = Tz[col];
     __syncthreads();
-    fft_lines<R, MAXP>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, +1);
-    fft_lines<R, MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, +1);
+    fft_lines<R, MAXP, RS>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, +1);
+    fft_lines<R, MAXP, RS>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, +1);
     const int s1 = potidx[n1];
     const int s2 = n2 < nvec ? potidx[n2] : -1;
     R q1[3] = {0, 0, 0}, q2[3] = {0, 0, 0};
@@ -419,8 +429,8 @@ __global__ void __launch_bounds__(512) k_plane_apply(
       }
     }
     __syncthreads();
-    fft_lines<R, MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, -1);
-    fft_lines<R, MAXP>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, -1);
+    fft_lines<R, MAXP, RS>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, -1);
+    fft_lines<R, MAXP, RS>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, -1);
     for (int col = tid; col < g.ncol; col += nthr)
       Tz[col] = plane[colpos[2 * col] * g.PS + colpos[2 * col + 1]];
     if (nQ > 0) {
@@ -452,7 +462,7 @@ __global__ void __launch_bounds__(512) k_plane_apply(
 // ---------------------------------------------------------------------------
 // plane pass for densities: G -> r only, accumulate per-shell |u|^2
 // ---------------------------------------------------------------------------
-template <typename R, int MAXP>
+template <typename R, int MAXP, int RS>
 __global__ void __launch_bounds__(512) k_plane_density(
     const C2<R>* __restrict__ T, const int32_t* __restrict__ colpos, PlaneGeom g,
     const C2<R>* __restrict__ tw1g, const C2<R>* __restrict__ tw2g,
@@ -489,8 +499,8 @@ __global__ void __launch_bounds__(512) k_plane_density(
     for (int col = tid; col < g.ncol; col += nthr)
       plane[colpos[2 * col] * g.PS + colpos[2 * col + 1]] = Tz[col];
     __syncthreads();
-    fft_lines<R, MAXP>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, +1);
-    fft_lines<R, MAXP>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, +1);
+    fft_lines<R, MAXP, RS>(plane, g.p2, nh, Rows{g.hmax, g.N1, g.PS}, 1, tw2, +1);
+    fft_lines<R, MAXP, RS>(plane, g.p1, g.N2, Strided{1}, g.PS, tw1, +1);
     const int s1 = band_shell[2 * pair];
     const int s2 = (2 * pair + 1 < nvec) ? band_shell[2 * pair + 1] : 99;
     const bool open1 = s1 >= 1 && s1 < nsocc, open2 = s2 >= 1 && s2 < nsocc;
@@ -525,7 +535,7 @@ __global__ void __launch_bounds__(512) k_plane_density(
 // bank), transforms them and writes them back.  Loads run along the
 // contiguous direction: j when estr == 1, else c.
 // ---------------------------------------------------------------------------
-template <int MAXP>
+template <int MAXP, int RS>
 __global__ void __launch_bounds__(256) k_fft_axis(double2* __restrict__ data, FftPlan1D plan,
                                                   const double2* __restrict__ twg, int ncols, int CH,
                                                   long estr, long cstr, long bstride, int sign) {
@@ -551,7 +561,7 @@ __global__ void __launch_bounds__(256) k_fft_axis(double2* __restrict__ data, Ff
     buf[c * LS + j] = (c0 + c < ncols) ? base[j * estr + (long)(c0 + c) * cstr] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  fft_lines<double, MAXP>(buf, plan, CH, Strided{LS}, 1, tw, sign);
+  fft_lines<double, MAXP, RS>(buf, plan, CH, Strided{LS}, 1, tw, sign);
   for (int idx = tid; idx < CH * L; idx += nthr) {
     int c, j;
     if (contig) {
@@ -635,20 +645,36 @@ double grid_bytes(const Ctx& c) {
 
 }  // namespace
 
-#define ROKS_DISPATCH_MAXP(R, mp, KER, ...)               \
+#define ROKS_DISPATCH_MAXP_RS(R, mp, RS, KER, ...)        \
   switch (mp) {                                           \
-    case 8: KER<R, 8>(__VA_ARGS__); break;                \
-    case 16: KER<R, 16>(__VA_ARGS__); break;              \
-    case 24: KER<R, 24>(__VA_ARGS__); break;              \
-    default: KER<R, 32>(__VA_ARGS__); break;              \
+    case 8: KER<R, 8, RS>(__VA_ARGS__); break;            \
+    case 16: KER<R, 16, RS>(__VA_ARGS__); break;          \
+    case 24: KER<R, 24, RS>(__VA_ARGS__); break;          \
+    default: KER<R, 32, RS>(__VA_ARGS__); break;          \
+  }
+#define ROKS_DISPATCH_MAXP(R, mp, rs, KER, ...)                              \
+  if (rs == kRadix8) {                                                      \
+    ROKS_DISPATCH_MAXP_RS(R, mp, kRadix8, KER, __VA_ARGS__)                 \
+  } else {                                                                  \
+    ROKS_DISPATCH_MAXP_RS(R, mp, kRadixAny, KER, __VA_ARGS__)               \
   }
 
-template <typename R, int MP>
+// the radix set of one or two plans
+int radix_set(const FftPlan1D& a) {
+  for (int s = 0; s < a.nstages; ++s)
+    if (a.radix[s] != 8) return kRadixAny;
+  return kRadix8;
+}
+int radix_set(const FftPlan1D& a, const FftPlan1D& b) {
+  return (radix_set(a) == kRadix8 && radix_set(b) == kRadix8) ? kRadix8 : kRadixAny;
+}
+
+template <typename R, int MP, int RS>
 static void run_zpass_bwd(Ctx& c, const double2* vecs, int nvec, void* T, int npairs, int CH) {
   const size_t lds = (size_t)(c.N[2] + 2 * CH * c.N[2]) * sizeof(C2<R>);
-  allow_lds(k_zpass_bwd<R, MP>, lds);
+  allow_lds(k_zpass_bwd<R, MP, RS>, lds);
   dim3 grid(cdiv(c.nH + 1, CH), npairs);
-  hipLaunchKernelGGL((k_zpass_bwd<R, MP>), grid, dim3(kZThreads), lds, c.stream, vecs, nvec, c.npw,
+  hipLaunchKernelGGL((k_zpass_bwd<R, MP, RS>), grid, dim3(kZThreads), lds, c.stream, vecs, nvec, c.npw,
                      c.d_cols, c.nH + 1, c.nH, c.plan[2], twiddles<R>(c, 2),
                      reinterpret_cast<C2<R>*>(T), c.ncol, CH);
   ROKS_HIP(hipGetLastError());
@@ -659,19 +685,19 @@ void launch_zpass_bwd(Ctx& c, const double2* vecs, int nvec, void* T, int npairs
   const int CH = zchunk(c);
   const int mp = pick_maxp(needed_points(2 * CH * c.N[2], kZThreads));
   if (c.prec == ROKS_FP32) {
-    ROKS_DISPATCH_MAXP(float, mp, run_zpass_bwd, c, vecs, nvec, T, npairs, CH);
+    ROKS_DISPATCH_MAXP(float, mp, radix_set(c.plan[2]), run_zpass_bwd, c, vecs, nvec, T, npairs, CH);
   } else {
-    ROKS_DISPATCH_MAXP(double, mp, run_zpass_bwd, c, vecs, nvec, T, npairs, CH);
+    ROKS_DISPATCH_MAXP(double, mp, radix_set(c.plan[2]), run_zpass_bwd, c, vecs, nvec, T, npairs, CH);
   }
 }
 
-template <typename R, int MP>
+template <typename R, int MP, int RS>
 static void run_zpass_fwd(Ctx& c, const void* T, int npairs, const double2* vecs, int nvec,
                           const double* kinw, double2* Y, int CH) {
   const size_t lds = (size_t)(c.N[2] + 2 * CH * c.N[2]) * sizeof(C2<R>);
-  allow_lds(k_zpass_fwd<R, MP>, lds);
+  allow_lds(k_zpass_fwd<R, MP, RS>, lds);
   dim3 grid(cdiv(c.nH + 1, CH), npairs);
-  hipLaunchKernelGGL((k_zpass_fwd<R, MP>), grid, dim3(kZThreads), lds, c.stream,
+  hipLaunchKernelGGL((k_zpass_fwd<R, MP, RS>), grid, dim3(kZThreads), lds, c.stream,
                      reinterpret_cast<const C2<R>*>(T), c.ncol, c.d_cols, c.nH + 1, c.nH, c.plan[2],
                      twiddles<R>(c, 2), vecs, nvec, c.npw, kinw, c.d_g2, 1.0 / (double)c.ntot, Y, CH);
   ROKS_HIP(hipGetLastError());
@@ -683,22 +709,22 @@ void launch_zpass_fwd(Ctx& c, const void* T, int npairs, const double2* vecs, in
   const int CH = zchunk(c);
   const int mp = pick_maxp(needed_points(2 * CH * c.N[2], kZThreads));
   if (c.prec == ROKS_FP32) {
-    ROKS_DISPATCH_MAXP(float, mp, run_zpass_fwd, c, T, npairs, vecs, nvec, kinw, Y, CH);
+    ROKS_DISPATCH_MAXP(float, mp, radix_set(c.plan[2]), run_zpass_fwd, c, T, npairs, vecs, nvec, kinw, Y, CH);
   } else {
-    ROKS_DISPATCH_MAXP(double, mp, run_zpass_fwd, c, T, npairs, vecs, nvec, kinw, Y, CH);
+    ROKS_DISPATCH_MAXP(double, mp, radix_set(c.plan[2]), run_zpass_fwd, c, T, npairs, vecs, nvec, kinw, Y, CH);
   }
 }
 
-template <typename R, int MP>
+template <typename R, int MP, int RS>
 static void run_plane_apply(Ctx& c, void* T, int npairs, const void* pot, int npot,
                             const int32_t* potidx, int nvec, double* Qpart, int nQ) {
   const int nthr = plane_threads(c);
   const size_t lds = plane_lds(c, nthr, sizeof(C2<R>));
-  allow_lds(k_plane_apply<R, MP>, lds);
+  allow_lds(k_plane_apply<R, MP, RS>, lds);
   const int nchunk = std::max(1, std::min(npairs, c.nchunk));
   const int per = cdiv(npairs, nchunk);
   dim3 grid(c.N[2], nchunk);
-  hipLaunchKernelGGL((k_plane_apply<R, MP>), grid, dim3(nthr), lds, c.stream,
+  hipLaunchKernelGGL((k_plane_apply<R, MP, RS>), grid, dim3(nthr), lds, c.stream,
                      reinterpret_cast<C2<R>*>(T), c.d_colpos, geom(c), twiddles<R>(c, 0),
                      twiddles<R>(c, 1), reinterpret_cast<const R*>(pot), npot, (size_t)c.ntot,
                      potidx, nvec, nQ, Qpart, npairs, per);
@@ -711,20 +737,20 @@ void launch_plane_apply(Ctx& c, void* T, int npairs, const void* pot, int npot,
   KernelTimer kt(c, "plane_apply", 2.0 * colbuf_bytes(c, npairs) + npot * grid_bytes(c));
   const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], plane_threads(c)));
   if (c.prec == ROKS_FP32) {
-    ROKS_DISPATCH_MAXP(float, mp, run_plane_apply, c, T, npairs, pot, npot, potidx, nvec, Qpart, nQ);
+    ROKS_DISPATCH_MAXP(float, mp, radix_set(c.plan[0], c.plan[1]), run_plane_apply, c, T, npairs, pot, npot, potidx, nvec, Qpart, nQ);
   } else {
-    ROKS_DISPATCH_MAXP(double, mp, run_plane_apply, c, T, npairs, pot, npot, potidx, nvec, Qpart, nQ);
+    ROKS_DISPATCH_MAXP(double, mp, radix_set(c.plan[0], c.plan[1]), run_plane_apply, c, T, npairs, pot, npot, potidx, nvec, Qpart, nQ);
   }
 }
 
-template <typename R, int MP>
+template <typename R, int MP, int RS>
 static void run_plane_density(Ctx& c, const void* T, int npairs, double* rho_part, int nchunk) {
   const int nthr = plane_threads(c);
   const size_t lds = plane_lds(c, nthr, sizeof(C2<R>));
-  allow_lds(k_plane_density<R, MP>, lds);
+  allow_lds(k_plane_density<R, MP, RS>, lds);
   const int per = cdiv(npairs, nchunk);
   dim3 grid(c.N[2], nchunk);
-  hipLaunchKernelGGL((k_plane_density<R, MP>), grid, dim3(nthr), lds, c.stream,
+  hipLaunchKernelGGL((k_plane_density<R, MP, RS>), grid, dim3(nthr), lds, c.stream,
                      reinterpret_cast<const C2<R>*>(T), c.d_colpos, geom(c), twiddles<R>(c, 0),
                      twiddles<R>(c, 1), c.d_band_shell, c.nb, c.nsocc, npairs, per, rho_part,
                      (size_t)c.ntot);
@@ -736,16 +762,16 @@ void launch_plane_density(Ctx& c, const void* T, int npairs, double* rho_part, i
                  colbuf_bytes(c, npairs) + (double)nchunk * c.nsocc * c.ntot * sizeof(double));
   const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], plane_threads(c)));
   if (c.prec == ROKS_FP32) {
-    ROKS_DISPATCH_MAXP(float, mp, run_plane_density, c, T, npairs, rho_part, nchunk);
+    ROKS_DISPATCH_MAXP(float, mp, radix_set(c.plan[0], c.plan[1]), run_plane_density, c, T, npairs, rho_part, nchunk);
   } else {
-    ROKS_DISPATCH_MAXP(double, mp, run_plane_density, c, T, npairs, rho_part, nchunk);
+    ROKS_DISPATCH_MAXP(double, mp, radix_set(c.plan[0], c.plan[1]), run_plane_density, c, T, npairs, rho_part, nchunk);
   }
 }
 
 constexpr int kAxisThreads = 256;
 constexpr int kAxisPoints = 2048;  // points per workgroup at most (8 per thread)
 
-template <typename R, int MP>
+template <typename R, int MP, int RS>
 static void run_fft_axis(Ctx& c, double2* data, int sign, int axis) {
   const int n = c.N[axis];
   const int np2 = c.N[0] * c.N[1];
@@ -772,8 +798,8 @@ static void run_fft_axis(Ctx& c, double2* data, int sign, int axis) {
   const int lines = ncols * nbatch;
   const int CH = std::max(1, std::min(kAxisPoints / n, cdiv(lines, 1024)));
   const size_t lds = (size_t)(n + CH * (n + 1)) * sizeof(double2);
-  allow_lds(k_fft_axis<MP>, lds);
-  hipLaunchKernelGGL(k_fft_axis<MP>, dim3(cdiv(ncols, CH), nbatch), dim3(kAxisThreads), lds, c.stream,
+  allow_lds(k_fft_axis<MP, RS>, lds);
+  hipLaunchKernelGGL((k_fft_axis<MP, RS>), dim3(cdiv(ncols, CH), nbatch), dim3(kAxisThreads), lds, c.stream,
                      data, c.plan[axis], c.d_tw[axis], ncols, CH, estr, cstr, bstride, sign);
   ROKS_HIP(hipGetLastError());
 }
@@ -784,7 +810,7 @@ void launch_fft3d(Ctx& c, double2* data, int sign) {
     const int n = c.N[axis];
     const int pts = (kAxisPoints / n) * n;  // CH n at most
     const int mp = pick_maxp(needed_points(std::max(n, pts), kAxisThreads));
-    ROKS_DISPATCH_MAXP(double, mp, run_fft_axis, c, data, sign, axis);
+    ROKS_DISPATCH_MAXP(double, mp, radix_set(c.plan[axis]), run_fft_axis, c, data, sign, axis);
   }
 }
 
