@@ -203,11 +203,57 @@ __device__ __forceinline__ void fft_stage(C2<R>* buf, int N, int Ns, int nlines,
   __syncthreads();
 }
 
-// Radix sets a kernel is built for: plans of radix-8 stages only (a length
-// that is a power of 8), or any of 8, 4, 2, 3, 5.  The stages a kernel can
-// meet are all inlined into its transform loop, and the general set needs
-// about twice the registers of the radix-8 one.
-constexpr int kRadix8 = 1, kRadixAny = 0;
+// The same pass with the length, the radix and the span Ns known at compile
+// time: every index comes from shifts and masks, and the first pass (Ns = 1)
+// has no twiddles.  Same arithmetic in the same order as fft_stage.
+template <typename R, int RX, int MAXBF, int N, int NS, typename LineMap>
+__device__ __forceinline__ void fft_stage_c(C2<R>* buf, int nlines, LineMap lm, int estride,
+                                            const C2<R>* tw, int sign) {
+  constexpr int NR = N / RX;
+  constexpr int TWSTEP = N / (NS * RX);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int nbf = nlines * NR;
+  C2<R> v[MAXBF][RX];
+#pragma unroll
+  for (int i = 0; i < MAXBF; ++i) {
+    const int b = tid + i * nthr;
+    if (b < nbf) {
+      const int line = b / NR, t = b % NR;
+      const C2<R>* src = buf + lm(line);
+#pragma unroll
+      for (int r = 0; r < RX; ++r) v[i][r] = src[(t + r * NR) * estride];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MAXBF; ++i) {
+    const int b = tid + i * nthr;
+    if (b < nbf) {
+      const int line = b / NR, t = b % NR;
+      const int k = t % NS;
+      if (NS > 1 && k != 0) {
+#pragma unroll
+        for (int r = 1; r < RX; ++r) {
+          C2<R> w = tw[k * r * TWSTEP];  // exp(-2 pi i k r / (Ns RX))
+          if (sign > 0) w.y = -w.y;
+          v[i][r] = cmul<R>(v[i][r], w);
+        }
+      }
+      Dft<R, RX>::run(v[i], sign);
+      const int j = (t / NS) * NS * RX + k;
+      C2<R>* dst = buf + lm(line);
+#pragma unroll
+      for (int r = 0; r < RX; ++r) dst[(j + r * NS) * estride] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Plan classes a kernel is built for: length 64 (two radix-8 passes with
+// compile-time indexing), or any length of radices 8, 4, 2, 3, 5.  The stages
+// a kernel can meet are all inlined into its transform loop, and the general
+// class needs about twice the registers.
+constexpr int kLen64 = 1, kRadixAny = 0;
 
 // Transform `nlines` lines in place; MAXP bounds ceil(nlines N / blockDim).
 template <typename R, int MAXP, int RS, typename LineMap>
@@ -216,8 +262,11 @@ __device__ void fft_lines(C2<R>* buf, const FftPlan1D& plan, int nlines, LineMap
   int Ns = 1;
   for (int s = 0; s < plan.nstages; ++s) {
     const int RX = plan.radix[s];
-    if constexpr (RS == kRadix8) {
-      fft_stage<R, 8, (MAXP + 7) / 8>(buf, plan.n, Ns, nlines, lm, estride, tw, sign);
+    if constexpr (RS == kLen64) {
+      if (s == 0)
+        fft_stage_c<R, 8, (MAXP + 7) / 8, 64, 1>(buf, nlines, lm, estride, tw, sign);
+      else
+        fft_stage_c<R, 8, (MAXP + 7) / 8, 64, 8>(buf, nlines, lm, estride, tw, sign);
     } else {
       switch (RX) {
         case 8: fft_stage<R, 8, (MAXP + 7) / 8>(buf, plan.n, Ns, nlines, lm, estride, tw, sign); break;
@@ -593,12 +642,17 @@ int pick_maxp(int need) {
   return 32;
 }
 
+// row stride of the LDS plane (complex elements): N2 plus a pad that spreads
+// the strided column accesses of the x transforms over the LDS banks
+constexpr int kPlanePad = 1;
+int plane_stride(const Ctx& c) { return c.N[1] + kPlanePad; }
+
 PlaneGeom geom(const Ctx& c) {
   PlaneGeom g;
   g.N1 = c.N[0];
   g.N2 = c.N[1];
   g.N3 = c.N[2];
-  g.PS = c.N[1] + 1;
+  g.PS = plane_stride(c);
   g.hmax = c.hmax;
   g.ncol = c.ncol;
   g.p1 = c.plan[0];
@@ -607,7 +661,7 @@ PlaneGeom geom(const Ctx& c) {
 }
 
 size_t plane_lds(const Ctx& c, int nthr, size_t elem) {
-  size_t b = (size_t)(c.N[0] + c.N[1] + c.N[0] * (c.N[1] + 1) + 1) * elem;
+  size_t b = (size_t)(c.N[0] + c.N[1] + c.N[0] * plane_stride(c) + 1) * elem;
   b += (size_t)2 * kMaxShell * (nthr / 64) * sizeof(double);
   return b;
 }
@@ -653,20 +707,18 @@ double grid_bytes(const Ctx& c) {
     default: KER<R, 32, RS>(__VA_ARGS__); break;          \
   }
 #define ROKS_DISPATCH_MAXP(R, mp, rs, KER, ...)                              \
-  if (rs == kRadix8) {                                                      \
-    ROKS_DISPATCH_MAXP_RS(R, mp, kRadix8, KER, __VA_ARGS__)                 \
+  if (rs == kLen64) {                                                       \
+    ROKS_DISPATCH_MAXP_RS(R, mp, kLen64, KER, __VA_ARGS__)                  \
   } else {                                                                  \
     ROKS_DISPATCH_MAXP_RS(R, mp, kRadixAny, KER, __VA_ARGS__)               \
   }
 
-// the radix set of one or two plans
+// the plan class of one or two plans
 int radix_set(const FftPlan1D& a) {
-  for (int s = 0; s < a.nstages; ++s)
-    if (a.radix[s] != 8) return kRadixAny;
-  return kRadix8;
+  return (a.n == 64 && a.nstages == 2 && a.radix[0] == 8 && a.radix[1] == 8) ? kLen64 : kRadixAny;
 }
 int radix_set(const FftPlan1D& a, const FftPlan1D& b) {
-  return (radix_set(a) == kRadix8 && radix_set(b) == kRadix8) ? kRadix8 : kRadixAny;
+  return (radix_set(a) == kLen64 && radix_set(b) == kLen64) ? kLen64 : kRadixAny;
 }
 
 template <typename R, int MP, int RS>
