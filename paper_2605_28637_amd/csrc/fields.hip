@@ -129,23 +129,17 @@ struct ProjP {
   double rp;
 };
 
-// naxes = 1: the table of `axis` (-1: the projectors themselves); naxes = 3:
-// the three derivative tables, axis-major [3][nproj][npw]
+// the table of projectors (axis = -1) or of their derivative along `axis`
 __global__ void k_projectors(Lattice L, const int32_t* __restrict__ miller, int npw,
                              const ProjP* __restrict__ proj, int nproj,
-                             const AtomP* __restrict__ atoms, int axis0, int naxes,
-                             double2* __restrict__ B) {
-  const size_t per = (size_t)nproj * npw;
-  const size_t total = per * naxes;
+                             const AtomP* __restrict__ atoms, int axis, double2* __restrict__ B) {
+  const size_t total = (size_t)nproj * npw;
   const double inv_sqrt_omega = 1.0 / sqrt(L.omega);
   const double c0 = 4.0 * M_PI;
   const double c1 = 4.0 * pow(M_PI, 0.75);
   for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
        t += (size_t)gridDim.x * blockDim.x) {
-    const int ax = (int)(t / per);
-    const size_t r = t - (size_t)ax * per;
-    const int axis = naxes == 3 ? ax : axis0;
-    const int i = (int)(r / npw), g = (int)(r - (size_t)i * npw);
+    const int i = (int)(t / npw), g = (int)(t - (size_t)i * npw);
     const int m[3] = {miller[3 * g], miller[3 * g + 1], miller[3 * g + 2]};
     double G[3];
     gvec(L, m, G);
@@ -171,6 +165,17 @@ __global__ void k_projectors(Lattice L, const int32_t* __restrict__ miller, int 
     }
     B[t] = v;
   }
+}
+
+// Cartesian G of every stored coefficient, [3][npw] (the derivative of a
+// projector's table is -i G_a times the table)
+__global__ void k_gcart(Lattice L, const int32_t* __restrict__ miller, int npw, double* __restrict__ out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= npw) return;
+  const int m[3] = {miller[3 * g], miller[3 * g + 1], miller[3 * g + 2]};
+  double G[3];
+  gvec(L, m, G);
+  for (int a = 0; a < 3; ++a) out[(size_t)a * npw + g] = G[a];
 }
 
 // ---------------------------------------------------------------------------
@@ -572,16 +577,14 @@ void launch_projectors(Ctx& c, double2* B, int axis) {
   if (n == 0) return;
   const ProjP* pp = reinterpret_cast<const ProjP*>(c.d_projinfo);
   hipLaunchKernelGGL(k_projectors, dim3(grid_blocks(n)), dim3(256), 0, c.stream, lattice(c), c.d_miller,
-                     c.npw, pp, c.nproj, atoms_dev(c), axis, 1, B);
+                     c.npw, pp, c.nproj, atoms_dev(c), axis, B);
   ROKS_HIP(hipGetLastError());
 }
 
-void launch_projector_gradients(Ctx& c, double2* dB) {
-  const size_t n = 3 * (size_t)c.nproj * c.npw;
-  if (n == 0) return;
-  const ProjP* pp = reinterpret_cast<const ProjP*>(c.d_projinfo);
-  hipLaunchKernelGGL(k_projectors, dim3(grid_blocks(n)), dim3(256), 0, c.stream, lattice(c), c.d_miller,
-                     c.npw, pp, c.nproj, atoms_dev(c), -1, 3, dB);
+void launch_gcart(Ctx& c, double* gcart) {
+  const size_t n = c.npw;
+  hipLaunchKernelGGL(k_gcart, dim3(grid_blocks(n)), dim3(256), 0, c.stream, lattice(c), c.d_miller,
+                     c.npw, gcart);
   ROKS_HIP(hipGetLastError());
 }
 

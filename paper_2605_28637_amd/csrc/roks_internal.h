@@ -193,7 +193,7 @@ struct Ctx {
   int32_t* d_flag = nullptr;     // device status flags
   double* d_force = nullptr;     // [natoms][3]
   double* d_force_loc = nullptr; // [natoms][3] local part (side stream)
-  double2* d_dB = nullptr;       // [3][nproj][npw] derivative projector tables (forces)
+  double* d_gcart = nullptr;     // [3][npw] Cartesian G of the stored coefficients (forces)
   double* d_dP3 = nullptr;       // [3][nproj][nb] derivative projections (forces)
   void* d_atoms = nullptr;       // per-atom position and local-well parameters
   void* d_projinfo = nullptr;    // per-projector atom, l, m, radius
@@ -364,11 +364,18 @@ size_t proj_info_bytes();
 // forces from the three derivative projections dP3 [3][nproj][nb]
 void launch_nl_force(Ctx& c, const double* dP3, const double* DP, const double* w, double* out);
 // the three derivative tables -i G_a beta, [3][nproj][npw]
-void launch_projector_gradients(Ctx& c, double2* dB);
+// the Cartesian components of every stored G, [3][npw]
+void launch_gcart(Ctx& c, double* gcart);
 
 // linalg.hip
 void gemm_wdot(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
                double* C, int ldc, double alpha, double beta, bool half_weights);
+// C[a np + i][n] = <d_a beta_i|x_n> (a = x, y, z; C is 3 np x N, row-major,
+// ldc = N) for projector rows B (np x K) and bands X (N x K) with stored-half
+// weights: d_a beta_i(G) = -i G_a beta_i(G), formed from B and gcart on the
+// fly (no derivative tables)
+void gemm_wdot_deriv(Ctx& c, int np, int N, int K, const double* B, int ldb, const double* X, int ldx,
+                     const double* gcart, double* C, int ldc);
 void gemm_expand(Ctx& c, int N, int K, int Mdim, const double* M, int ldm, bool transM,
                  const double* X, int ldx, double* Y, int ldy, double alpha, double beta);
 // C = alpha op(A) op(B) + beta C + diag I

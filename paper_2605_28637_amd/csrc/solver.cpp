@@ -548,11 +548,14 @@ void forces(Ctx& c, double* f_host) {
   // (P = <beta|psi> is current: the energy evaluation of these orbitals left it)
   ROKS_HIP(hipMemsetAsync(c.d_force, 0, 3 * (size_t)nat * sizeof(double), c.stream));
   if (c.nproj > 0) {
-    if (!c.d_dB) c.d_dB = dalloc<double2>(c, 3 * (size_t)c.nproj * c.npw);
+    if (!c.d_gcart) {
+      c.d_gcart = dalloc<double>(c, 3 * (size_t)c.npw);
+      launch_gcart(c, c.d_gcart);
+    }
     if (!c.d_dP3) c.d_dP3 = dalloc<double>(c, 3 * (size_t)c.nproj * nb);
     launch_apply_D(c, c.d_P, nullptr, c.d_DP);
-    launch_projector_gradients(c, c.d_dB);
-    gemm_wdot(c, 3 * c.nproj, nb, K, dbl(c.d_dB), K, dbl(c.d_psi), K, c.d_dP3, nb, 1.0, 0.0, true);
+    // <d_a beta_i|n> from the projector table, -i G_a applied on the fly
+    gemm_wdot_deriv(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(c.d_psi), K, c.d_gcart, c.d_dP3, nb);
     launch_nl_force(c, c.d_dP3, c.d_DP, c.d_kinw_shell, c.d_force);
   }
   // F = -dE/dR
