@@ -45,8 +45,8 @@ RESTART = 20
 # calibration); reported only while the family's source is the one measured.
 TRAFFIC = {
     "gemm_wdot": {"source": "paper_2605_28637_amd/csrc/gemm.hip",
-                  "sha256": "3296e6e962e91496a674a4ad455970a2dc795e0fd17e391d6cd076b93da448a4",
-                  "bytes_per_launch": 3.984317e+07,
+                  "sha256": "4ffac1e7ddd9c7e8e60c0b28f88d9cb3222e6aa1eda09955f7a09d5824fd674d",
+                  "bytes_per_launch": 2.4251e+07,
                   "profile": "profiles/gemm_wdot_molecule64_fp64_traffic.md"},
 }
 KERNELS = ("zpass_bwd", "plane_apply", "plane_density", "zpass_fwd", "fft3d", "gemm_wdot",
