@@ -104,7 +104,8 @@ void init_device(Ctx& c, void* stream) {
   c.d_S = dalloc<double2>(c, band);
   c.d_Sold = dalloc<double2>(c, band);
   c.d_Pt = dalloc<double2>(c, band);
-  c.d_trial = dalloc<double2>(c, 2 * band);
+  c.d_trial[0] = dalloc<double2>(c, band);
+  c.d_trial[1] = dalloc<double2>(c, band);
   c.d_w1 = dalloc<double2>(c, band);
   c.d_T = dalloc<double2>(c, (size_t)c.npairs * c.N[2] * c.ncol);
   c.d_rho_part = dalloc<double>(c, (size_t)c.nchunk * c.nsocc * ntot);

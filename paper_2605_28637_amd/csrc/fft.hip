@@ -584,10 +584,20 @@ __global__ void __launch_bounds__(512) k_plane_density(
 // bank), transforms them and writes them back.  Loads run along the
 // contiguous direction: j when estr == 1, else c.
 // ---------------------------------------------------------------------------
+// Hartree step inside the z pass: after the forward transform of a z line,
+// multiply by 4 pi / (|G|^2 N^3) (0 at G = 0) and transform back
+struct HartreeMul {
+  double b[3][3];  // reciprocal vectors (rows)
+  int N[3];
+  double inv;      // 1 / N^3
+  int on;
+};
+
 template <int MAXP, int RS>
 __global__ void __launch_bounds__(256) k_fft_axis(double2* __restrict__ data, FftPlan1D plan,
                                                   const double2* __restrict__ twg, int ncols, int CH,
-                                                  long estr, long cstr, long bstride, int sign) {
+                                                  long estr, long cstr, long bstride, int sign,
+                                                  HartreeMul hm) {
   extern __shared__ char smem_raw[];
   double2* smem = reinterpret_cast<double2*>(smem_raw);
   const int L = plan.n, LS = L + 1;
@@ -611,6 +621,24 @@ __global__ void __launch_bounds__(256) k_fft_axis(double2* __restrict__ data, Ff
   }
   __syncthreads();
   fft_lines<double, MAXP, RS>(buf, plan, CH, Strided{LS}, 1, tw, sign);
+  if (hm.on) {
+    // z lines: column c0 + c is (x, y) = divmod(c0 + c, N2), position j is z
+    for (int idx = tid; idx < CH * L; idx += nthr) {
+      const int j = idx / CH, c = idx - j * CH;
+      const int p = c0 + c;
+      const int x = p / hm.N[1], y = p - x * hm.N[1];
+      const int f[3] = {2 * x >= hm.N[0] ? x - hm.N[0] : x, 2 * y >= hm.N[1] ? y - hm.N[1] : y,
+                        2 * j >= hm.N[2] ? j - hm.N[2] : j};
+      double G[3];
+      for (int a = 0; a < 3; ++a) G[a] = f[0] * hm.b[0][a] + f[1] * hm.b[1][a] + f[2] * hm.b[2][a];
+      const double g2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+      const double sc = g2 > 0.0 ? 4.0 * M_PI * hm.inv / g2 : 0.0;
+      double2& v = buf[c * LS + j];
+      v = make_double2(v.x * sc, v.y * sc);
+    }
+    __syncthreads();
+    fft_lines<double, MAXP, RS>(buf, plan, CH, Strided{LS}, 1, tw, -sign);
+  }
   for (int idx = tid; idx < CH * L; idx += nthr) {
     int c, j;
     if (contig) {
@@ -824,7 +852,7 @@ constexpr int kAxisThreads = 256;
 constexpr int kAxisPoints = 2048;  // points per workgroup at most (8 per thread)
 
 template <typename R, int MP, int RS>
-static void run_fft_axis(Ctx& c, double2* data, int sign, int axis) {
+static void run_fft_axis(Ctx& c, double2* data, int sign, int axis, bool hartree) {
   const int n = c.N[axis];
   const int np2 = c.N[0] * c.N[1];
   // lines of this axis, their strides, and the batch (x lines: one z-plane each)
@@ -851,19 +879,42 @@ static void run_fft_axis(Ctx& c, double2* data, int sign, int axis) {
   const int CH = std::max(1, std::min(kAxisPoints / n, cdiv(lines, 1024)));
   const size_t lds = (size_t)(n + CH * (n + 1)) * sizeof(double2);
   allow_lds(k_fft_axis<MP, RS>, lds);
+  HartreeMul hm{};
+  hm.on = 0;
+  if (hartree) {
+    ROKS_CHECK(axis == 2, ROKS_ERR_ARG, "the Hartree step rides on the z pass");
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) hm.b[i][j] = c.recip[i][j];
+    for (int d = 0; d < 3; ++d) hm.N[d] = c.N[d];
+    hm.inv = 1.0 / (double)c.ntot;
+    hm.on = 1;
+  }
   hipLaunchKernelGGL((k_fft_axis<MP, RS>), dim3(cdiv(ncols, CH), nbatch), dim3(kAxisThreads), lds, c.stream,
-                     data, c.plan[axis], c.d_tw[axis], ncols, CH, estr, cstr, bstride, sign);
+                     data, c.plan[axis], c.d_tw[axis], ncols, CH, estr, cstr, bstride, sign, hm);
   ROKS_HIP(hipGetLastError());
+}
+
+// one axis pass of the full-grid transform (hartree: the z pass with the
+// Hartree multiply and the inverse z transform inside)
+static void fft_axis_pass(Ctx& c, double2* data, int sign, int axis, bool hartree) {
+  const int n = c.N[axis];
+  const int pts = (kAxisPoints / n) * n;  // CH n at most
+  const int mp = pick_maxp(needed_points(std::max(n, pts), kAxisThreads));
+  ROKS_DISPATCH_MAXP(double, mp, radix_set(c.plan[axis]), run_fft_axis, c, data, sign, axis, hartree);
 }
 
 void launch_fft3d(Ctx& c, double2* data, int sign) {
   KernelTimer kt(c, "fft3d", 6.0 * c.ntot * sizeof(double2));
-  for (int axis : {1, 0, 2}) {
-    const int n = c.N[axis];
-    const int pts = (kAxisPoints / n) * n;  // CH n at most
-    const int mp = pick_maxp(needed_points(std::max(n, pts), kAxisThreads));
-    ROKS_DISPATCH_MAXP(double, mp, radix_set(c.plan[axis]), run_fft_axis, c, data, sign, axis);
-  }
+  for (int axis : {1, 0, 2}) fft_axis_pass(c, data, sign, axis, false);
+}
+
+void launch_hartree_fft(Ctx& c, double2* data) {
+  KernelTimer kt(c, "fft3d", 10.0 * c.ntot * sizeof(double2));
+  fft_axis_pass(c, data, -1, 1, false);
+  fft_axis_pass(c, data, -1, 0, false);
+  fft_axis_pass(c, data, -1, 2, true);
+  fft_axis_pass(c, data, +1, 0, false);
+  fft_axis_pass(c, data, +1, 1, false);
 }
 
 }  // namespace roks

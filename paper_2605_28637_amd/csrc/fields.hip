@@ -218,21 +218,6 @@ __global__ void k_pack_rho(ShellArgs a, const double* __restrict__ rho, size_t n
   }
 }
 
-// V_H(G) = 4 pi rho(G) / G^2, rho(G) = FFT(rho)/N^3; G = 0 -> 0
-__global__ void k_hartree_mul(Lattice L, double2* __restrict__ f, size_t ntot) {
-  const double inv = 1.0 / (double)ntot;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
-       i += (size_t)gridDim.x * blockDim.x) {
-    int m[3];
-    grid_freq(L, i, m);
-    double G[3];
-    gvec(L, m, G);
-    const double g2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
-    const double s = g2 > 0.0 ? 4.0 * M_PI * inv / g2 : 0.0;
-    f[i] = make_double2(f[i].x * s, f[i].y * s);
-  }
-}
-
 // Hartree integrals sum_r V_H,L(r) rho_L(r) = sum_{G != 0} 4 pi |F_L(G)|^2 / (G^2 N^3)
 // straight from the packed transform F = FFT(rho_0 + i rho_1) (no inverse
 // transform): F_0 = (F(G) + F(-G)*)/2, F_1 = (F(G) - F(-G)*)/(2i); per-block
@@ -600,10 +585,9 @@ void launch_hartree(Ctx& c) {
   hipLaunchKernelGGL(k_pack_rho, dim3(grid_blocks(n)), dim3(256), 0, c.stream, shell_args(c), c.d_rho, n,
                      c.d_fft, 0);
   ROKS_HIP(hipGetLastError());
-  launch_fft3d(c, c.d_fft, -1);
-  hipLaunchKernelGGL(k_hartree_mul, dim3(grid_blocks(n)), dim3(256), 0, c.stream, lattice(c), c.d_fft, n);
-  ROKS_HIP(hipGetLastError());
-  launch_fft3d(c, c.d_fft, +1);
+  // forward transform, 4 pi / (G^2 N^3), inverse transform (the multiply
+  // rides on the z pass)
+  launch_hartree_fft(c, c.d_fft);
   hipLaunchKernelGGL(k_unpack_vh, dim3(grid_blocks(n)), dim3(256), 0, c.stream, c.d_fft, n, c.nconf,
                      c.d_vh);
   ROKS_HIP(hipGetLastError());

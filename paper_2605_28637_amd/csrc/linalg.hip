@@ -37,8 +37,8 @@ constexpr int kExpandRows = 64;  // rows of X (depth) per chunk
 template <int NB>
 __global__ void __launch_bounds__(256) k_expand_mfma(int N, int K, int Md, const double* __restrict__ Mt,
                                                      int ldm, int transM, const double* __restrict__ X,
-                                                     int ldx, double* __restrict__ Y, int ldy,
-                                                     double alpha, double beta) {
+                                                     int ldx, const double* Yin, int ldyin,
+                                                     double* Y, int ldy, double alpha, double beta) {
   constexpr int MC = kExpandRows, W = 16 * NB, NL = MC * W / 256;
   __shared__ double Ms[MC][W + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(256) k_expand_mfma(int N, int K, int Md, const
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int n = n0 + 16 * i + s + 4 * r;
-      yv[i][r] = (beta != 0.0 && active && n < N && k < K) ? Y[(size_t)n * ldy + k] : 0.0;
+      yv[i][r] = (beta != 0.0 && active && n < N && k < K) ? Yin[(size_t)n * ldyin + k] : 0.0;
     }
   d4 acc[NB];
 #pragma unroll
@@ -617,13 +617,22 @@ int blocks_for(size_t n) {
 
 void gemm_expand(Ctx& c, int N, int K, int Md, const double* M, int ldm, bool transM,
                  const double* X, int ldx, double* Y, int ldy, double alpha, double beta) {
+  gemm_expand_to(c, N, K, Md, M, ldm, transM, X, ldx, Y, ldy, Y, ldy, alpha, beta);
+}
+
+void gemm_expand_to(Ctx& c, int N, int K, int Md, const double* M, int ldm, bool transM,
+                    const double* X, int ldx, const double* Yin, int ldyin, double* Y, int ldy,
+                    double alpha, double beta) {
   if (N == 0 || K == 0) return;
   KernelTimer kt(c, "gemm_expand",
                  ((double)Md * K + (beta != 0.0 ? 2.0 : 1.0) * N * K) * sizeof(double),
                  2.0 * N * (double)K * Md);
   if (Md >= 128 && N >= 64) {
     // a compute-bound size: one library DGEMM on the column-major views,
-    // Y^T (K x N) = X^T (K x Md) M (Md x N)
+    // Y^T (K x N) = X^T (K x Md) M (Md x N), in place
+    if (beta != 0.0 && Yin != Y)
+      ROKS_HIP(hipMemcpy2DAsync(Y, (size_t)ldy * sizeof(double), Yin, (size_t)ldyin * sizeof(double),
+                                (size_t)K * sizeof(double), N, hipMemcpyDeviceToDevice, c.stream));
     ROKS_CHECK(rocblas_dgemm(static_cast<rocblas_handle>(blas_handle(c)), rocblas_operation_none,
                              transM ? rocblas_operation_none : rocblas_operation_transpose, K, N, Md,
                              &alpha, X, ldx, M, ldm, &beta, Y, ldy) == rocblas_status_success,
@@ -638,14 +647,14 @@ void gemm_expand(Ctx& c, int N, int K, int Md, const double* M, int ldm, bool tr
   dim3 grid(cdiv(K, 64), cdiv(N, 16 * nb));
   const int tm = transM ? 1 : 0;
   if (nb == 1)
-    hipLaunchKernelGGL(k_expand_mfma<1>, grid, dim3(256), 0, c.stream, N, K, Md, M, ldm, tm, X, ldx, Y,
-                       ldy, alpha, beta);
+    hipLaunchKernelGGL(k_expand_mfma<1>, grid, dim3(256), 0, c.stream, N, K, Md, M, ldm, tm, X, ldx, Yin,
+                       ldyin, Y, ldy, alpha, beta);
   else if (nb == 2)
-    hipLaunchKernelGGL(k_expand_mfma<2>, grid, dim3(256), 0, c.stream, N, K, Md, M, ldm, tm, X, ldx, Y,
-                       ldy, alpha, beta);
+    hipLaunchKernelGGL(k_expand_mfma<2>, grid, dim3(256), 0, c.stream, N, K, Md, M, ldm, tm, X, ldx, Yin,
+                       ldyin, Y, ldy, alpha, beta);
   else
-    hipLaunchKernelGGL(k_expand_mfma<3>, grid, dim3(256), 0, c.stream, N, K, Md, M, ldm, tm, X, ldx, Y,
-                       ldy, alpha, beta);
+    hipLaunchKernelGGL(k_expand_mfma<3>, grid, dim3(256), 0, c.stream, N, K, Md, M, ldm, tm, X, ldx, Yin,
+                       ldyin, Y, ldy, alpha, beta);
   ROKS_HIP(hipGetLastError());
 }
 

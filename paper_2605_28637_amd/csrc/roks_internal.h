@@ -162,7 +162,7 @@ struct Ctx {
   double2* d_S = nullptr;
   double2* d_Sold = nullptr;
   double2* d_Pt = nullptr;       // trial vectors
-  double2* d_trial = nullptr;    // trial orbitals
+  double2* d_trial[2] = {nullptr, nullptr};  // trial orbitals (an accepted one swaps with d_psi)
   double2* d_w1 = nullptr;       // scratch band array
   double2* d_T = nullptr;        // [npairs][N3][ncol] column buffer
   double* d_rho_part = nullptr;  // [nchunk][nsocc][ntot]
@@ -337,7 +337,10 @@ void launch_plane_apply(Ctx& c, void* T, int npairs, const void* pot, int npot,
 void launch_plane_density(Ctx& c, const void* T, int npairs, double* rho_part, int nchunk);
 void launch_zpass_fwd(Ctx& c, const void* T, int npairs, const double2* vecs, int nvec,
                       const double* kinw, double2* Y);
-void launch_fft3d(Ctx& c, double2* data, int sign);  // FP64 full-grid transform
+void launch_fft3d(Ctx& c, double2* data, int sign);
+// V_H(G) = 4 pi rho(G) / (G^2 N^3) (0 at G = 0) of a packed grid, in place:
+// the forward transform, the multiply and the inverse transform
+void launch_hartree_fft(Ctx& c, double2* data);  // FP64 full-grid transform
 
 // fields.hip
 void launch_vext(Ctx& c);
@@ -378,6 +381,11 @@ void gemm_wdot_deriv(Ctx& c, int np, int N, int K, const double* B, int ldb, con
                      const double* gcart, double* C, int ldc);
 void gemm_expand(Ctx& c, int N, int K, int Mdim, const double* M, int ldm, bool transM,
                  const double* X, int ldx, double* Y, int ldy, double alpha, double beta);
+// the same with the beta term read from Yin (Y = alpha M^T X + beta Yin;
+// Yin may be Y): saves a copy when the result goes to another buffer
+void gemm_expand_to(Ctx& c, int N, int K, int Md, const double* M, int ldm, bool transM,
+                    const double* X, int ldx, const double* Yin, int ldyin, double* Y, int ldy,
+                    double alpha, double beta);
 // C = alpha op(A) op(B) + beta C + diag I
 void gemm_small(Ctx& c, int M, int N, int K, const double* A, int lda, bool tA, const double* B,
                 int ldb, bool tB, double* C, int ldc, double alpha, double beta, double diag = 0.0);

@@ -293,8 +293,8 @@ void energy_gradient(Ctx& c, roks_energies* e) {
   if (e) *e = c.last_e;
   apply_operator(c, c.d_psi, 0, c.d_Y, true);
   gemm_wdot(c, nb, nb, K, dbl(c.d_psi), K, dbl(c.d_Y), K, c.d_theta, nb, 1.0, 0.0, true);
-  copy_dev(c, c.d_gI, c.d_Y, band * sizeof(double2));
-  gemm_expand(c, nb, K, nb, c.d_theta, nb, false, dbl(c.d_psi), K, dbl(c.d_gI), K, -1.0, 1.0);
+  gemm_expand_to(c, nb, K, nb, c.d_theta, nb, false, dbl(c.d_psi), K, dbl(c.d_Y), K, dbl(c.d_gI), K,
+                 -1.0, 1.0);
   launch_subspace(c);
 }
 
@@ -353,8 +353,8 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     else
       launch_teter(c, c.d_bandv, c.d_bandv + nb, c.d_gI, bandw, c.d_w1);
     gemm_wdot(c, nb, nb, K, dbl(c.d_psi), K, dbl(c.d_w1), K, c.d_m1, nb, 1.0, 0.0, true);
-    copy_dev(c, c.d_p, c.d_w1, band * sizeof(double2));
-    gemm_expand(c, nb, K, nb, c.d_m1, nb, false, dbl(c.d_psi), K, dbl(c.d_p), K, -1.0, 1.0);
+    gemm_expand_to(c, nb, K, nb, c.d_m1, nb, false, dbl(c.d_psi), K, dbl(c.d_w1), K, dbl(c.d_p), K,
+                   -1.0, 1.0);
     // <p|g> = sum <p_I|g_I> + 1/2 sum A (theta - theta^T)
     launch_asym_dot(c, c.d_A, c.d_theta, st);
     band_dots(c, c.d_p, c.d_gI, nb, 0, st + kStage);
@@ -380,8 +380,8 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   // Sold projected out of the current span (kept in d_w1)
   if (c.have_old) {
     gemm_wdot(c, nb, nb, K, dbl(c.d_psi), K, dbl(c.d_Sold), K, c.d_m1, nb, 1.0, 0.0, true);
-    copy_dev(c, c.d_w1, c.d_Sold, band * sizeof(double2));
-    gemm_expand(c, nb, K, nb, c.d_m1, nb, false, dbl(c.d_psi), K, dbl(c.d_w1), K, -1.0, 1.0);
+    gemm_expand_to(c, nb, K, nb, c.d_m1, nb, false, dbl(c.d_psi), K, dbl(c.d_Sold), K, dbl(c.d_w1), K,
+                   -1.0, 1.0);
   }
   auto directions = [&](double b) {
     if (b != 0.0) {
@@ -405,8 +405,8 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     dE0 = directions(0.0);
   }
 
-  Trial tr[2] = {{c.d_trial, c.d_M, c.d_U, 0, {}, false},
-                 {c.d_trial + band, c.d_Mkeep, c.d_Ukeep, 0, {}, false}};
+  Trial tr[2] = {{c.d_trial[0], c.d_M, c.d_U, 0, {}, false},
+                 {c.d_trial[1], c.d_Mkeep, c.d_Ukeep, 0, {}, false}};
   double tdelta[2] = {0.0, 0.0};
   // reading R7: trial step, parabola through E(0), E'(0), E(dt), keep the
   // lower of the two if it is below E(0), else halve the trial step
@@ -485,8 +485,9 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   const double delta = tdelta[best];
   r.E1 = t.E;
   r.delta = delta;
-  // commit: psi <- trial, S_old <- M S, D_old <- U^T D U
-  copy_dev(c, c.d_psi, t.psi, band * sizeof(double2));
+  // commit: psi <- trial (the buffers trade places), S_old <- M S,
+  // D_old <- U^T D U
+  std::swap(c.d_psi, c.d_trial[best]);
   gemm_expand(c, nb, K, nb, t.M, nb, true, dbl(c.d_S), K, dbl(c.d_Sold), K, 1.0, 0.0);
   gemm_small(c, nb, nb, nb, c.d_D, nb, false, t.U, nb, false, c.d_m4, nb, 1.0, 0.0);
   gemm_small(c, nb, nb, nb, t.U, nb, true, c.d_m4, nb, false, c.d_Dold, nb, 1.0, 0.0);
