@@ -431,15 +431,32 @@ __global__ void k_apply_D(const double* __restrict__ P, int nb, int nproj,
 // forces
 // ---------------------------------------------------------------------------
 // partial sums over G of v_s(G) G_a Im(e^{-iG.R_I} conj(rho(G))), rho(G) already / N^3
+// The structure factor e^{-i G.R} = prod_d e^{-i m_d (b_d . R)} comes from
+// three per-axis phase tables of the workgroup's atom (index = grid index,
+// frequency wrapped), built once per workgroup in LDS.
+constexpr int kMaxAxis = 256;
+
 __global__ void __launch_bounds__(256) k_local_force(Lattice L, const AtomP* __restrict__ atoms,
                                                      const double2* __restrict__ rg, size_t ntot,
                                                      double scale, double* __restrict__ part) {
   __shared__ double red[8 * 16];
+  __shared__ double2 ph[3][kMaxAxis];  // (cos, sin) of m_d (b_d . R)
   const int I = blockIdx.y;
   const AtomP p = atoms[I];
   const double s2 = p.sigma * p.sigma;
   const double pre = -p.A * pow(2.0 * M_PI * s2, 1.5);
+  for (int d = 0; d < 3; ++d) {
+    const double bR = L.b[d][0] * p.x + L.b[d][1] * p.y + L.b[d][2] * p.z;
+    for (int v = threadIdx.x; v < L.N[d]; v += blockDim.x) {
+      const int m = 2 * v >= L.N[d] ? v - L.N[d] : v;
+      double sn, cs;
+      sincos(m * bR, &sn, &cs);
+      ph[d][v] = make_double2(cs, sn);
+    }
+  }
+  __syncthreads();
   double acc[3] = {0, 0, 0};
+  const int np2 = L.N[0] * L.N[1];
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
        i += (size_t)gridDim.x * blockDim.x) {
     int m[3];
@@ -448,8 +465,14 @@ __global__ void __launch_bounds__(256) k_local_force(Lattice L, const AtomP* __r
     gvec(L, m, G);
     const double g2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
     const double vs = pre * exp(-0.5 * g2 * s2);
-    double sn, cs;
-    sincos(G[0] * p.x + G[1] * p.y + G[2] * p.z, &sn, &cs);
+    // grid indices of the frequencies (x, y, z) for the tables
+    const int z = (int)(i / np2);
+    const int rr = (int)(i - (size_t)z * np2);
+    const int x = rr / L.N[1], y = rr - x * L.N[1];
+    const double2 a = ph[0][x], b = ph[1][y], e = ph[2][z];
+    // e^{i th} = a b e (th = G.R): cos th and sin th
+    const double ab_c = a.x * b.x - a.y * b.y, ab_s = a.x * b.y + a.y * b.x;
+    const double cs = ab_c * e.x - ab_s * e.y, sn = ab_c * e.y + ab_s * e.x;
     const double2 r = make_double2(rg[i].x * scale, rg[i].y * scale);
     // e^{-i th} conj(r) = (cs - i sn)(r.x - i r.y): imaginary part
     const double im = -cs * r.y - sn * r.x;
@@ -665,6 +688,8 @@ void launch_pack_rho_weighted(Ctx& c) {
 
 void launch_local_force(Ctx& c, const double2* rhoG, double* out_part, int nblk) {
   if (c.natoms == 0) return;
+  ROKS_CHECK(c.N[0] <= kMaxAxis && c.N[1] <= kMaxAxis && c.N[2] <= kMaxAxis, ROKS_ERR_SHAPE,
+             "grid axis longer than the force kernel's phase tables");
   hipLaunchKernelGGL(k_local_force, dim3(nblk, c.natoms), dim3(256), 0, c.stream, lattice(c),
                      atoms_dev(c), rhoG, (size_t)c.ntot, 1.0 / (double)c.ntot, out_part);
   ROKS_HIP(hipGetLastError());
