@@ -433,25 +433,29 @@ __global__ void k_apply_D(const double* __restrict__ P, int nb, int nproj,
 // partial sums over G of v_s(G) G_a Im(e^{-iG.R_I} conj(rho(G))), rho(G) already / N^3
 // The structure factor e^{-i G.R} = prod_d e^{-i m_d (b_d . R)} comes from
 // three per-axis phase tables of the workgroup's atom (index = grid index,
-// frequency wrapped), built once per workgroup in LDS.
+// frequency wrapped), built once per workgroup in LDS.  With an orthogonal
+// reciprocal basis (orth) the Gaussian exp(-sigma^2 |G|^2 / 2) factorises
+// over the axes too and is folded into the tables.
 constexpr int kMaxAxis = 256;
 
 __global__ void __launch_bounds__(256) k_local_force(Lattice L, const AtomP* __restrict__ atoms,
                                                      const double2* __restrict__ rg, size_t ntot,
-                                                     double scale, double* __restrict__ part) {
+                                                     double scale, int orth, double* __restrict__ part) {
   __shared__ double red[8 * 16];
-  __shared__ double2 ph[3][kMaxAxis];  // (cos, sin) of m_d (b_d . R)
+  __shared__ double2 ph[3][kMaxAxis];  // (cos, sin) of m_d (b_d . R) [x Gaussian factor]
   const int I = blockIdx.y;
   const AtomP p = atoms[I];
   const double s2 = p.sigma * p.sigma;
   const double pre = -p.A * pow(2.0 * M_PI * s2, 1.5);
   for (int d = 0; d < 3; ++d) {
     const double bR = L.b[d][0] * p.x + L.b[d][1] * p.y + L.b[d][2] * p.z;
+    const double bb = L.b[d][0] * L.b[d][0] + L.b[d][1] * L.b[d][1] + L.b[d][2] * L.b[d][2];
     for (int v = threadIdx.x; v < L.N[d]; v += blockDim.x) {
       const int m = 2 * v >= L.N[d] ? v - L.N[d] : v;
       double sn, cs;
       sincos(m * bR, &sn, &cs);
-      ph[d][v] = make_double2(cs, sn);
+      const double gs = orth ? exp(-0.5 * s2 * (double)m * m * bb) : 1.0;
+      ph[d][v] = make_double2(gs * cs, gs * sn);
     }
   }
   __syncthreads();
@@ -463,8 +467,7 @@ __global__ void __launch_bounds__(256) k_local_force(Lattice L, const AtomP* __r
     if (grid_freq(L, i, m)) continue;
     double G[3];
     gvec(L, m, G);
-    const double g2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
-    const double vs = pre * exp(-0.5 * g2 * s2);
+    const double vs = orth ? pre : pre * exp(-0.5 * (G[0] * G[0] + G[1] * G[1] + G[2] * G[2]) * s2);
     // grid indices of the frequencies (x, y, z) for the tables
     const int z = (int)(i / np2);
     const int rr = (int)(i - (size_t)z * np2);
@@ -690,8 +693,20 @@ void launch_local_force(Ctx& c, const double2* rhoG, double* out_part, int nblk)
   if (c.natoms == 0) return;
   ROKS_CHECK(c.N[0] <= kMaxAxis && c.N[1] <= kMaxAxis && c.N[2] <= kMaxAxis, ROKS_ERR_SHAPE,
              "grid axis longer than the force kernel's phase tables");
+  // is the reciprocal basis orthogonal (the Gaussian then factorises)?
+  int orth = 1;
+  for (int i = 0; i < 3; ++i)
+    for (int j = i + 1; j < 3; ++j) {
+      double dij = 0, ni = 0, nj = 0;
+      for (int a = 0; a < 3; ++a) {
+        dij += c.recip[i][a] * c.recip[j][a];
+        ni += c.recip[i][a] * c.recip[i][a];
+        nj += c.recip[j][a] * c.recip[j][a];
+      }
+      if (std::fabs(dij) > 1e-14 * std::sqrt(ni * nj)) orth = 0;
+    }
   hipLaunchKernelGGL(k_local_force, dim3(nblk, c.natoms), dim3(256), 0, c.stream, lattice(c),
-                     atoms_dev(c), rhoG, (size_t)c.ntot, 1.0 / (double)c.ntot, out_part);
+                     atoms_dev(c), rhoG, (size_t)c.ntot, 1.0 / (double)c.ntot, orth, out_part);
   ROKS_HIP(hipGetLastError());
 }
 
