@@ -181,17 +181,6 @@ __global__ void k_gcart(Lattice L, const int32_t* __restrict__ miller, int npw, 
 // ---------------------------------------------------------------------------
 // densities
 // ---------------------------------------------------------------------------
-__global__ void k_density_reduce(const double* __restrict__ part, int nchunk, int nsocc,
-                                 size_t ntot, double inv_omega, double* __restrict__ rho) {
-  const size_t total = (size_t)nsocc * ntot;
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
-       t += (size_t)gridDim.x * blockDim.x) {
-    double s = 0;
-    for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * total + t];
-    rho[t] = s * inv_omega;
-  }
-}
-
 struct ShellArgs {
   int nconf, nsocc, xc;
   double f[3][kMaxConf][2];
@@ -215,6 +204,28 @@ __global__ void k_pack_rho(ShellArgs a, const double* __restrict__ rho, size_t n
     } else {
       out[i] = make_double2(r[0], a.nconf > 1 ? r[1] : 0.0);
     }
+  }
+}
+
+// the shell densities from the plane passes' chunk partials (summed in chunk
+// order, / Omega), and the same pass packs the configuration densities for
+// the Hartree transform as k_pack_rho (weighted = 0) does
+__global__ void k_density_reduce(ShellArgs a, const double* __restrict__ part, int nchunk,
+                                 size_t ntot, double inv_omega, double* __restrict__ rho,
+                                 double2* __restrict__ packed) {
+  const size_t total = (size_t)a.nsocc * ntot;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double r[kMaxConf] = {0, 0};
+    for (int X = 0; X < a.nsocc; ++X) {
+      const size_t t = (size_t)X * ntot + i;
+      double s = 0;
+      for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * total + t];
+      const double v = s * inv_omega;
+      rho[t] = v;
+      for (int L = 0; L < a.nconf; ++L) r[L] += (a.f[X][L][0] + a.f[X][L][1]) * v;
+    }
+    packed[i] = make_double2(r[0], a.nconf > 1 ? r[1] : 0.0);
   }
 }
 
@@ -600,17 +611,15 @@ void launch_gcart(Ctx& c, double* gcart) {
 }
 
 void launch_density_reduce(Ctx& c, const double* rho_part, int nchunk, double* rho) {
-  const size_t n = (size_t)c.nsocc * c.ntot;
-  hipLaunchKernelGGL(k_density_reduce, dim3(grid_blocks(n)), dim3(256), 0, c.stream, rho_part, nchunk,
-                     c.nsocc, (size_t)c.ntot, 1.0 / c.omega, rho);
+  const size_t n = c.ntot;
+  hipLaunchKernelGGL(k_density_reduce, dim3(grid_blocks(n)), dim3(256), 0, c.stream, shell_args(c),
+                     rho_part, nchunk, n, 1.0 / c.omega, rho, c.d_fft);
   ROKS_HIP(hipGetLastError());
 }
 
+// d_fft holds the packed configuration densities (launch_density_reduce)
 void launch_hartree(Ctx& c) {
   const size_t n = c.ntot;
-  hipLaunchKernelGGL(k_pack_rho, dim3(grid_blocks(n)), dim3(256), 0, c.stream, shell_args(c), c.d_rho, n,
-                     c.d_fft, 0);
-  ROKS_HIP(hipGetLastError());
   // forward transform, 4 pi / (G^2 N^3), inverse transform (the multiply
   // rides on the z pass)
   launch_hartree_fft(c, c.d_fft);
@@ -638,11 +647,9 @@ void launch_xc_energy(Ctx& c, double* part, int nblocks) {
   ROKS_HIP(hipGetLastError());
 }
 
+// d_fft holds the packed configuration densities (launch_density_reduce)
 void launch_hartree_energy(Ctx& c, double* part, int nblocks) {
   const size_t n = c.ntot;
-  hipLaunchKernelGGL(k_pack_rho, dim3(grid_blocks(n)), dim3(256), 0, c.stream, shell_args(c), c.d_rho, n,
-                     c.d_fft, 0);
-  ROKS_HIP(hipGetLastError());
   launch_fft3d(c, c.d_fft, -1);
   hipLaunchKernelGGL(k_hartree_energy, dim3(nblocks), dim3(256), 0, c.stream, lattice(c), c.d_fft, n,
                      c.nconf, part);

@@ -34,11 +34,12 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kExpandRows = 64;  // rows of X (depth) per chunk
 
-template <int NB>
+template <int NB, bool TWO>
 __global__ void __launch_bounds__(256) k_expand_mfma(int N, int K, int Md, const double* __restrict__ Mt,
                                                      int ldm, int transM, const double* __restrict__ X,
-                                                     int ldx, const double* Yin, int ldyin,
-                                                     double* Y, int ldy, double alpha, double beta) {
+                                                     int ldx, const double* __restrict__ X2, double dX2,
+                                                     const double* Yin, int ldyin, double* Y, int ldy,
+                                                     double alpha, double beta) {
   constexpr int MC = kExpandRows, W = 16 * NB, NL = MC * W / 256;
   __shared__ double Ms[MC][W + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -64,6 +65,17 @@ __global__ void __launch_bounds__(256) k_expand_mfma(int N, int K, int Md, const
     for (int t = 0; t < MC / 4; ++t) {
       const int m = mc + 4 * t + s;
       xb[t] = (active && m < Md && k < K) ? X[(size_t)m * ldx + k] : 0.0;
+    }
+    if (TWO) {
+      // the second input as its own batch of loads, then added
+      double x2[MC / 4];
+#pragma unroll
+      for (int t = 0; t < MC / 4; ++t) {
+        const int m = mc + 4 * t + s;
+        x2[t] = (active && m < Md && k < K) ? X2[(size_t)m * ldx + k] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < MC / 4; ++t) xb[t] += dX2 * x2[t];
     }
     double tv[NL];
 #pragma unroll
@@ -623,13 +635,25 @@ void gemm_expand(Ctx& c, int N, int K, int Md, const double* M, int ldm, bool tr
 void gemm_expand_to(Ctx& c, int N, int K, int Md, const double* M, int ldm, bool transM,
                     const double* X, int ldx, const double* Yin, int ldyin, double* Y, int ldy,
                     double alpha, double beta) {
+  gemm_expand_sum(c, N, K, Md, M, ldm, transM, X, nullptr, 0.0, ldx, Yin, ldyin, Y, ldy, alpha, beta);
+}
+
+void gemm_expand_sum(Ctx& c, int N, int K, int Md, const double* M, int ldm, bool transM,
+                     const double* X, const double* X2, double dX2, int ldx, const double* Yin,
+                     int ldyin, double* Y, int ldy, double alpha, double beta) {
   if (N == 0 || K == 0) return;
   KernelTimer kt(c, "gemm_expand",
                  ((double)Md * K + (beta != 0.0 ? 2.0 : 1.0) * N * K) * sizeof(double),
                  2.0 * N * (double)K * Md);
   if (Md >= 128 && N >= 64) {
     // a compute-bound size: one library DGEMM on the column-major views,
-    // Y^T (K x N) = X^T (K x Md) M (Md x N), in place
+    // Y^T (K x N) = X^T (K x Md) M (Md x N), in place (X + dX2 X2 formed
+    // first in the trial buffer)
+    if (X2) {
+      ROKS_CHECK(Md == c.nb && ldx == 2 * c.npw, ROKS_ERR_ARG, "two-input expansion of bands only");
+      axpby(c, (size_t)Md * ldx, 1.0, X, dX2, X2, reinterpret_cast<double*>(c.d_Pt));
+      X = reinterpret_cast<const double*>(c.d_Pt);
+    }
     if (beta != 0.0 && Yin != Y)
       ROKS_HIP(hipMemcpy2DAsync(Y, (size_t)ldy * sizeof(double), Yin, (size_t)ldyin * sizeof(double),
                                 (size_t)K * sizeof(double), N, hipMemcpyDeviceToDevice, c.stream));
@@ -646,15 +670,19 @@ void gemm_expand_to(Ctx& c, int N, int K, int Md, const double* M, int ldm, bool
     if (cdiv(n16, b) * b <= cdiv(n16, nb) * nb) nb = b;
   dim3 grid(cdiv(K, 64), cdiv(N, 16 * nb));
   const int tm = transM ? 1 : 0;
-  if (nb == 1)
-    hipLaunchKernelGGL(k_expand_mfma<1>, grid, dim3(256), 0, c.stream, N, K, Md, M, ldm, tm, X, ldx, Yin,
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, dim3(256), 0, c.stream, N, K, Md, M, ldm, tm, X, ldx, X2, dX2, Yin,
                        ldyin, Y, ldy, alpha, beta);
-  else if (nb == 2)
-    hipLaunchKernelGGL(k_expand_mfma<2>, grid, dim3(256), 0, c.stream, N, K, Md, M, ldm, tm, X, ldx, Yin,
-                       ldyin, Y, ldy, alpha, beta);
-  else
-    hipLaunchKernelGGL(k_expand_mfma<3>, grid, dim3(256), 0, c.stream, N, K, Md, M, ldm, tm, X, ldx, Yin,
-                       ldyin, Y, ldy, alpha, beta);
+  };
+  if (X2) {
+    if (nb == 1) go(k_expand_mfma<1, true>);
+    else if (nb == 2) go(k_expand_mfma<2, true>);
+    else go(k_expand_mfma<3, true>);
+  } else {
+    if (nb == 1) go(k_expand_mfma<1, false>);
+    else if (nb == 2) go(k_expand_mfma<2, false>);
+    else go(k_expand_mfma<3, false>);
+  }
   ROKS_HIP(hipGetLastError());
 }
 

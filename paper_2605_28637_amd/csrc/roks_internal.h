@@ -337,15 +337,18 @@ void launch_plane_apply(Ctx& c, void* T, int npairs, const void* pot, int npot,
 void launch_plane_density(Ctx& c, const void* T, int npairs, double* rho_part, int nchunk);
 void launch_zpass_fwd(Ctx& c, const void* T, int npairs, const double2* vecs, int nvec,
                       const double* kinw, double2* Y);
-void launch_fft3d(Ctx& c, double2* data, int sign);
+void launch_fft3d(Ctx& c, double2* data, int sign);  // FP64 full-grid transform
 // V_H(G) = 4 pi rho(G) / (G^2 N^3) (0 at G = 0) of a packed grid, in place:
 // the forward transform, the multiply and the inverse transform
-void launch_hartree_fft(Ctx& c, double2* data);  // FP64 full-grid transform
+void launch_hartree_fft(Ctx& c, double2* data);
 
 // fields.hip
 void launch_vext(Ctx& c);
 void launch_projectors(Ctx& c, double2* B, int deriv_axis);
+// shell densities from the chunk partials, and the packed configuration
+// densities in d_fft for the Hartree step that follows
 void launch_density_reduce(Ctx& c, const double* rho_part, int nchunk, double* rho);
+// V_H per configuration from the packed densities in d_fft
 void launch_hartree(Ctx& c);
 void launch_xc_potentials(Ctx& c, double* part, int nblocks);
 int xc_blocks(const Ctx& c);
@@ -386,6 +389,11 @@ void gemm_expand(Ctx& c, int N, int K, int Mdim, const double* M, int ldm, bool 
 void gemm_expand_to(Ctx& c, int N, int K, int Md, const double* M, int ldm, bool transM,
                     const double* X, int ldx, const double* Yin, int ldyin, double* Y, int ldy,
                     double alpha, double beta);
+// Y = alpha M^T (X + dX2 X2) + beta Yin, X2 (same layout as X) added while
+// loading
+void gemm_expand_sum(Ctx& c, int N, int K, int Md, const double* M, int ldm, bool transM,
+                     const double* X, const double* X2, double dX2, int ldx, const double* Yin,
+                     int ldyin, double* Y, int ldy, double alpha, double beta);
 // C = alpha op(A) op(B) + beta C + diag I
 void gemm_small(Ctx& c, int M, int N, int K, const double* A, int lda, bool tA, const double* B,
                 int ldb, bool tB, double* C, int ldc, double alpha, double beta, double diag = 0.0);

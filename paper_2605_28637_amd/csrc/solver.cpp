@@ -123,8 +123,6 @@ void prepare_line_search(Ctx& c, bool first) {
 // (a failed factorisation only makes the rest of the evaluation meaningless).
 void evaluate_trial(Ctx& c, double delta, Trial& t, bool energy_only) {
   const int nb = c.nb, K = 2 * c.npw;
-  const size_t band = (size_t)nb * c.npw;
-  axpby(c, 2 * band, 1.0, dbl(c.d_psi), delta, dbl(c.d_S), dbl(c.d_Pt));
   scale_shift(c, c.d_SS, nb, delta * delta, 1.0, c.d_gram);
   if (expm_in_lds(c)) {
     // factorisation and exponential side by side: one launch, two workgroups
@@ -136,7 +134,9 @@ void evaluate_trial(Ctx& c, double delta, Trial& t, bool energy_only) {
     expm(c, delta, c.d_D, t.U);
   }
   gemm_small(c, nb, nb, nb, t.U, nb, true, c.d_Linv, nb, false, t.M, nb, 1.0, 0.0);
-  gemm_expand(c, nb, K, nb, t.M, nb, true, dbl(c.d_Pt), K, dbl(t.psi), K, 1.0, 0.0);
+  // trial orbitals M^T (psi + delta S), the sum formed while loading
+  gemm_expand_sum(c, nb, K, nb, t.M, nb, true, dbl(c.d_psi), dbl(c.d_S), delta, K, dbl(t.psi), K,
+                  dbl(t.psi), K, 1.0, 0.0);
   if (c.nproj > 0) {
     axpby(c, (size_t)c.nproj * nb, 1.0, c.d_P0, delta, c.d_PS, c.d_Pq);
     gemm_small(c, c.nproj, nb, nb, c.d_Pq, nb, false, t.M, nb, true, c.d_P, nb, 1.0, 0.0);
