@@ -151,28 +151,42 @@ __global__ void __launch_bounds__(256) k_gemm_small(int M, int N, int K, const d
 // --------------------------------------------------------------------------
 // per-band weighted dots: mode 0: sum w x.y; mode 1: sum w |G|^2/2 x.y
 // --------------------------------------------------------------------------
+// Per-band dots <x_n|y_n> over the stored half sphere (weight 1 at G = 0, 2
+// elsewhere), out0 plain and out1 with the weight |G|^2/2 (either may be
+// null); one workgroup per band.  (Splitting a band over workgroups with a
+// last-arrival sum was slower: the device-scope fences it needs are costly on
+// a GPU whose L2 is split over XCDs.)
 __global__ void __launch_bounds__(1024) k_band_dots(const double2* __restrict__ X,
                                                    const double2* __restrict__ Yv, int npw,
-                                                   const double* __restrict__ g2, int mode,
-                                                   double* __restrict__ out) {
-  __shared__ double red[16];
+                                                   const double* __restrict__ g2,
+                                                   double* __restrict__ out0, double* __restrict__ out1) {
+  __shared__ double red[2][16];
   const int n = blockIdx.x;
   const double2* x = X + (size_t)n * npw;
   const double2* y = Yv + (size_t)n * npw;
-  double s = 0.0;
+  double s0 = 0.0, s1 = 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
     double v = x[g].x * y[g].x + x[g].y * y[g].y;
-    if (mode == 1) v *= g2[g];
-    s += (g == 0) ? v : 2.0 * v;
+    if (g != 0) v *= 2.0;
+    s0 += v;
+    if (out1) s1 += v * g2[g];
   }
-  s = wave_sum(s);
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) red[wid] = s;
+  if (lane == 0) {
+    red[0][wid] = s0;
+    red[1][wid] = s1;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
-    out[n] = t;
+    double t0 = 0.0, t1 = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      t0 += red[0][w];
+      t1 += red[1][w];
+    }
+    if (out0) out0[n] = t0;
+    if (out1) out1[n] = t1;
   }
 }
 
@@ -694,9 +708,17 @@ void gemm_small(Ctx& c, int M, int N, int K, const double* A, int lda, bool tA, 
   ROKS_HIP(hipGetLastError());
 }
 
-void band_dots(Ctx& c, const double2* X, const double2* Y, int nvec, int mode, double* out) {
-  hipLaunchKernelGGL(k_band_dots, dim3(nvec), dim3(1024), 0, c.stream, X, Y, c.npw, c.d_g2, mode, out);
+void band_dots2(Ctx& c, const double2* X, const double2* Y, int nvec, double* out0, double* out1) {
+  if (nvec == 0) return;
+  hipLaunchKernelGGL(k_band_dots, dim3(nvec), dim3(1024), 0, c.stream, X, Y, c.npw, c.d_g2, out0, out1);
   ROKS_HIP(hipGetLastError());
+}
+
+void band_dots(Ctx& c, const double2* X, const double2* Y, int nvec, int mode, double* out) {
+  if (mode == 1)
+    band_dots2(c, X, Y, nvec, nullptr, out);
+  else
+    band_dots2(c, X, Y, nvec, out, nullptr);
 }
 
 void axpby(Ctx& c, size_t n, double a, const double* x, double b, const double* y, double* out) {

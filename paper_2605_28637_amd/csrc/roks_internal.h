@@ -175,7 +175,7 @@ struct Ctx {
   double* d_DP = nullptr;        // [nproj][nb]
   double* d_part = nullptr;      // reduction partials
   double* d_red = nullptr;       // reduced scalars
-  double* d_gemm_part = nullptr; // split-K partials
+  double* d_gemm_part = nullptr;  // split-K partials
   double* d_Qpart = nullptr;     // [npairs][N3][2][nsocc]
   double* d_Q = nullptr;         // [nb][nsocc]
   double* d_kin = nullptr;       // [nb]
@@ -398,6 +398,8 @@ void gemm_expand_sum(Ctx& c, int N, int K, int Md, const double* M, int ldm, boo
 void gemm_small(Ctx& c, int M, int N, int K, const double* A, int lda, bool tA, const double* B,
                 int ldb, bool tB, double* C, int ldc, double alpha, double beta, double diag = 0.0);
 void band_dots(Ctx& c, const double2* X, const double2* Y, int nvec, int mode, double* out);
+// both weightings in one pass: out0 plain, out1 |G|^2/2 (either may be null)
+void band_dots2(Ctx& c, const double2* X, const double2* Y, int nvec, double* out0, double* out1);
 void axpby(Ctx& c, size_t n, double a, const double* x, double b, const double* y, double* out);
 void cholesky_inverse(Ctx& c, const double* G, int n, double* Linv, int32_t* flag);
 void set_identity(Ctx& c, double* A, int n, double diag);

@@ -323,8 +323,7 @@ void pcg_step(Ctx& c, roks_step_info* info) {
 
   // preconditioned out-of-subspace gradient p = (1 - P) K g_I; with a
   // network attached K carries the learned factor of (band, |G|^2 shell)
-  band_dots(c, c.d_gI, c.d_gI, nb, 1, c.d_bandv);
-  band_dots(c, c.d_gI, c.d_gI, nb, 0, c.d_bandv + nb);
+  band_dots2(c, c.d_gI, c.d_gI, nb, c.d_bandv + nb, c.d_bandv);
   const bool recording = c.rec_max > 0 && c.rec_count < c.rec_max &&
                          (c.iteration % std::max(1, c.rec_stride)) == 0;
   if (c.mlp || recording) {
