@@ -282,9 +282,8 @@ __global__ void k_unpack_vh(const double2* __restrict__ f, size_t ntot, int ncon
 // ---------------------------------------------------------------------------
 // spin LDA: Slater exchange + Perdew-Wang 1992 correlation
 // ---------------------------------------------------------------------------
-__device__ void pw92_G(double rs, double A, double a1, double b1, double b2, double b3, double b4,
-                       double* G, double* dG) {
-  const double srs = sqrt(rs);
+__device__ void pw92_G(double rs, double srs, double A, double a1, double b1, double b2, double b3,
+                       double b4, double* G, double* dG) {
   const double Q = 2.0 * A * (b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs);
   const double dQ = 2.0 * A * (0.5 * b1 / srs + b2 + 1.5 * b3 * srs + 2.0 * b4 * rs);
   const double lg = log1p(1.0 / Q);
@@ -304,7 +303,14 @@ __device__ void lda_point(double ru, double rd, int kind, double* e, double* vu,
   }
   const double third = 1.0 / 3.0;
   const double cx = cbrt(6.0 / M_PI);
-  const double cu = cbrt(ru), cd = cbrt(rd);
+  // three cube roots: rho, 1 + z, 1 - z; rho_up,down = rho (1 +- z) / 2 and
+  // rs = (3 / (4 pi))^(1/3) / rho^(1/3)
+  double z = (ru - rd) / rho;
+  z = fmin(1.0, fmax(-1.0, z));
+  const double opz = 1.0 + z, omz = 1.0 - z;
+  const double crho = cbrt(rho), copz = cbrt(opz), comz = cbrt(omz);
+  const double ch = crho * cbrt(0.5);
+  const double cu = ch * copz, cd = ch * comz;
   double ex = -0.75 * cx * (ru * cu + rd * cd);
   double vxu = -cx * cu, vxd = -cx * cd;
   if (kind == ROKS_XC_X) {
@@ -313,18 +319,15 @@ __device__ void lda_point(double ru, double rd, int kind, double* e, double* vu,
     *vd = vxd;
     return;
   }
-  double z = (ru - rd) / rho;
-  z = fmin(1.0, fmax(-1.0, z));
-  const double rs = cbrt(3.0 / (4.0 * M_PI * rho));
+  const double rs = cbrt(3.0 / (4.0 * M_PI)) / crho;
+  const double srs = sqrt(rs);
   double ec0, dec0, ec1, dec1, mac, dmac;
-  pw92_G(rs, 0.031091, 0.21370, 7.5957, 3.5876, 1.6382, 0.49294, &ec0, &dec0);
-  pw92_G(rs, 0.015545, 0.20548, 14.1189, 6.1977, 3.3662, 0.62517, &ec1, &dec1);
-  pw92_G(rs, 0.016887, 0.11125, 10.357, 3.6231, 0.88026, 0.49671, &mac, &dmac);
+  pw92_G(rs, srs, 0.031091, 0.21370, 7.5957, 3.5876, 1.6382, 0.49294, &ec0, &dec0);
+  pw92_G(rs, srs, 0.015545, 0.20548, 14.1189, 6.1977, 3.3662, 0.62517, &ec1, &dec1);
+  pw92_G(rs, srs, 0.016887, 0.11125, 10.357, 3.6231, 0.88026, 0.49671, &mac, &dmac);
   const double ac = -mac, dac = -dmac;
   const double fz20 = 1.709921;
   const double den = exp2(4.0 * third) - 2.0;
-  const double opz = 1.0 + z, omz = 1.0 - z;
-  const double copz = cbrt(opz), comz = cbrt(omz);
   const double f = (opz * copz + omz * comz - 2.0) / den;
   const double fp = (4.0 * third) * (copz - comz) / den;
   const double z3 = z * z * z, z4 = z3 * z;
@@ -523,14 +526,19 @@ __global__ void __launch_bounds__(256) k_nl_force(const double* __restrict__ dP,
 }
 
 // out[o][j] = scale * sum_i part[o][i][j]
-__global__ void k_reduce_strided(const double* __restrict__ part, int nouter, int ninner, int ncols,
-                                 double scale, double* __restrict__ out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// out[o][j] = scale sum_i part[o][i][j]: one wave per output, lanes over i,
+// a fixed butterfly across the wave
+__global__ void __launch_bounds__(256) k_reduce_strided(const double* __restrict__ part, int nouter,
+                                                        int ninner, int ncols, double scale,
+                                                        double* __restrict__ out) {
+  const int t = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
   if (t >= nouter * ncols) return;
   const int o = t / ncols, j = t - o * ncols;
   double s = 0;
-  for (int i = 0; i < ninner; ++i) s += part[((size_t)o * ninner + i) * ncols + j];
-  out[t] = scale * s;
+  for (int i = lane; i < ninner; i += 64) s += part[((size_t)o * ninner + i) * ncols + j];
+  s = wave_sum(s);
+  if (lane == 0) out[t] = scale * s;
 }
 
 int grid_blocks(size_t n, int nthr = 256) {
@@ -669,7 +677,7 @@ void launch_to_float(Ctx& c, const double* in, float* out, size_t n) {
 void launch_reduce_strided(Ctx& c, const double* part, int nouter, int ninner, int ncols,
                            double scale, double* out) {
   const int n = nouter * ncols;
-  hipLaunchKernelGGL(k_reduce_strided, dim3(cdiv(n, 128)), dim3(128), 0, c.stream, part, nouter, ninner,
+  hipLaunchKernelGGL(k_reduce_strided, dim3(cdiv(n, 4)), dim3(256), 0, c.stream, part, nouter, ninner,
                      ncols, scale, out);
   ROKS_HIP(hipGetLastError());
 }
