@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(512) k_zpass_bwd(const double2* __restrict__ v
                                                     C2<R>* __restrict__ T, int ncol, int CH) {
   extern __shared__ char smem_raw[];
   C2<R>* smem = reinterpret_cast<C2<R>*>(smem_raw);
-  const int N3 = plan.n;
+  const int N3 = plan.n, LS = N3 + 1;  // LDS line stride: N3 + 1 spreads the banks
   C2<R>* tw = smem;
   C2<R>* buf = smem + N3;
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -313,7 +313,7 @@ __global__ void __launch_bounds__(512) k_zpass_bwd(const double2* __restrict__ v
   const double2* c2 = vecs + (size_t)n2 * npw;
   const bool has2 = n2 < nvec;
   for (int i = tid; i < N3; i += nthr) tw[i] = twg[i];
-  for (int i = tid; i < 2 * CH * N3; i += nthr) buf[i] = mk<R>(0, 0);
+  for (int i = tid; i < 2 * CH * LS; i += nthr) buf[i] = mk<R>(0, 0);
   __syncthreads();
   for (int idx = tid; idx < CH * N3; idx += nthr) {
     const int c = idx / N3, e = idx - c * N3;
@@ -327,21 +327,21 @@ __global__ void __launch_bounds__(512) k_zpass_bwd(const double2* __restrict__ v
     const double2 b = has2 ? c2[g] : make_double2(0.0, 0.0);
     const C2<R> v = mk<R>((R)(a.x - b.y), (R)(a.y + b.x));    // c1 + i c2
     const C2<R> vm = mk<R>((R)(a.x + b.y), (R)(b.x - a.y));   // conj(c1) + i conj(c2)
-    buf[(2 * c) * N3 + wrap(l, N3)] = v;
+    buf[(2 * c) * LS + wrap(l, N3)] = v;
     if (j > 0)
-      buf[(2 * c + 1) * N3 + wrap(-l, N3)] = vm;
+      buf[(2 * c + 1) * LS + wrap(-l, N3)] = vm;
     else if (l > 0)
-      buf[(2 * c) * N3 + wrap(-l, N3)] = vm;
+      buf[(2 * c) * LS + wrap(-l, N3)] = vm;
   }
   __syncthreads();
-  fft_lines<R, MAXP, RS>(buf, plan, 2 * CH, Strided{N3}, 1, tw, +1);
+  fft_lines<R, MAXP, RS>(buf, plan, 2 * CH, Strided{LS}, 1, tw, +1);
   for (int idx = tid; idx < CH * N3; idx += nthr) {
     const int z = idx / CH, c = idx - z * CH;
     const int j = j0 + c;
     if (j >= ndesc) continue;
     const size_t row = ((size_t)pair * N3 + z) * ncol;
-    T[row + j] = buf[(2 * c) * N3 + z];
-    if (j > 0) T[row + nH + j] = buf[(2 * c + 1) * N3 + z];
+    T[row + j] = buf[(2 * c) * LS + z];
+    if (j > 0) T[row + nH + j] = buf[(2 * c + 1) * LS + z];
   }
 }
 
@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(512) k_zpass_fwd(
     double2* __restrict__ Y, int CH) {
   extern __shared__ char smem_raw[];
   C2<R>* smem = reinterpret_cast<C2<R>*>(smem_raw);
-  const int N3 = plan.n;
+  const int N3 = plan.n, LS = N3 + 1;  // LDS line stride: N3 + 1 spreads the banks
   C2<R>* tw = smem;
   C2<R>* buf = smem + N3;
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -374,11 +374,11 @@ __global__ void __launch_bounds__(512) k_zpass_fwd(
       s = T[row + j];
       if (j > 0) m = T[row + nH + j];
     }
-    buf[(2 * c) * N3 + z] = s;
-    buf[(2 * c + 1) * N3 + z] = m;
+    buf[(2 * c) * LS + z] = s;
+    buf[(2 * c + 1) * LS + z] = m;
   }
   __syncthreads();
-  fft_lines<R, MAXP, RS>(buf, plan, 2 * CH, Strided{N3}, 1, tw, -1);
+  fft_lines<R, MAXP, RS>(buf, plan, 2 * CH, Strided{LS}, 1, tw, -1);
   const double w1 = kinw[n1];
   const double w2 = has2 ? kinw[n2] : 0.0;
   for (int idx = tid; idx < CH * N3; idx += nthr) {
@@ -389,8 +389,8 @@ __global__ void __launch_bounds__(512) k_zpass_fwd(
     if (e > d.lmax - d.lmin) continue;
     const int l = d.lmin + e;
     const int g = d.base + e;
-    const C2<R> F = buf[(2 * c) * N3 + wrap(l, N3)];
-    const C2<R> Fm = (j == 0) ? buf[(2 * c) * N3 + wrap(-l, N3)] : buf[(2 * c + 1) * N3 + wrap(-l, N3)];
+    const C2<R> F = buf[(2 * c) * LS + wrap(l, N3)];
+    const C2<R> Fm = (j == 0) ? buf[(2 * c) * LS + wrap(-l, N3)] : buf[(2 * c + 1) * LS + wrap(-l, N3)];
     const double y1x = 0.5 * ((double)F.x + (double)Fm.x), y1y = 0.5 * ((double)F.y - (double)Fm.y);
     const double ddx = 0.5 * ((double)F.x - (double)Fm.x), ddy = 0.5 * ((double)F.y + (double)Fm.y);
     const double k = g2[g];
@@ -751,7 +751,7 @@ int radix_set(const FftPlan1D& a, const FftPlan1D& b) {
 
 template <typename R, int MP, int RS>
 static void run_zpass_bwd(Ctx& c, const double2* vecs, int nvec, void* T, int npairs, int CH) {
-  const size_t lds = (size_t)(c.N[2] + 2 * CH * c.N[2]) * sizeof(C2<R>);
+  const size_t lds = (size_t)(c.N[2] + 2 * CH * (c.N[2] + 1)) * sizeof(C2<R>);
   allow_lds(k_zpass_bwd<R, MP, RS>, lds);
   dim3 grid(cdiv(c.nH + 1, CH), npairs);
   hipLaunchKernelGGL((k_zpass_bwd<R, MP, RS>), grid, dim3(kZThreads), lds, c.stream, vecs, nvec, c.npw,
@@ -774,7 +774,7 @@ void launch_zpass_bwd(Ctx& c, const double2* vecs, int nvec, void* T, int npairs
 template <typename R, int MP, int RS>
 static void run_zpass_fwd(Ctx& c, const void* T, int npairs, const double2* vecs, int nvec,
                           const double* kinw, double2* Y, int CH) {
-  const size_t lds = (size_t)(c.N[2] + 2 * CH * c.N[2]) * sizeof(C2<R>);
+  const size_t lds = (size_t)(c.N[2] + 2 * CH * (c.N[2] + 1)) * sizeof(C2<R>);
   allow_lds(k_zpass_fwd<R, MP, RS>, lds);
   dim3 grid(cdiv(c.nH + 1, CH), npairs);
   hipLaunchKernelGGL((k_zpass_fwd<R, MP, RS>), grid, dim3(kZThreads), lds, c.stream,
