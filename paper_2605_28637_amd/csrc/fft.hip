@@ -172,7 +172,9 @@ __device__ __forceinline__ void fft_stage(C2<R>* buf, int N, int Ns, int nlines,
   for (int i = 0; i < MAXBF; ++i) {
     const int b = tid + i * nthr;
     if (b < nbf) {
-      const int line = b / NR, t = b - line * NR;
+      // lines fastest across lanes: neighbouring lanes hit neighbouring lines
+      // (distinct banks for both unit-stride and padded-stride lines)
+      const int t = b / nlines, line = b - t * nlines;
       const C2<R>* src = buf + lm(line);
 #pragma unroll
       for (int r = 0; r < RX; ++r) v[i][r] = src[(t + r * NR) * estride];
@@ -183,7 +185,7 @@ __device__ __forceinline__ void fft_stage(C2<R>* buf, int N, int Ns, int nlines,
   for (int i = 0; i < MAXBF; ++i) {
     const int b = tid + i * nthr;
     if (b < nbf) {
-      const int line = b / NR, t = b - line * NR;
+      const int t = b / nlines, line = b - t * nlines;
       const int k = t % Ns;
       if (k != 0) {
 #pragma unroll
@@ -218,7 +220,7 @@ __device__ __forceinline__ void fft_stage_c(C2<R>* buf, int nlines, LineMap lm, 
   for (int i = 0; i < MAXBF; ++i) {
     const int b = tid + i * nthr;
     if (b < nbf) {
-      const int line = b / NR, t = b % NR;
+      const int t = b / nlines, line = b - t * nlines;
       const C2<R>* src = buf + lm(line);
 #pragma unroll
       for (int r = 0; r < RX; ++r) v[i][r] = src[(t + r * NR) * estride];
@@ -229,7 +231,7 @@ __device__ __forceinline__ void fft_stage_c(C2<R>* buf, int nlines, LineMap lm, 
   for (int i = 0; i < MAXBF; ++i) {
     const int b = tid + i * nthr;
     if (b < nbf) {
-      const int line = b / NR, t = b % NR;
+      const int t = b / nlines, line = b - t * nlines;
       const int k = t % NS;
       if (NS > 1 && k != 0) {
 #pragma unroll
