@@ -296,6 +296,9 @@ __global__ void __launch_bounds__(1024) k_cholesky_inverse(const double* __restr
 // diagonal, or not finite, sets the flag and is replaced by 1).
 // Without inv_in_lds (97 <= n <= 128) the factor is scaled in place and
 // L^-1 is formed column by column from it.
+// LDS row stride of the single-workgroup Cholesky: n rounded up to odd
+__host__ __device__ inline int chol_ld(int n) { return n | 1; }
+
 __device__ void cholesky_lds_body(const double* __restrict__ G, int n, double* __restrict__ Linv,
                                   int32_t* __restrict__ flag, int inv_in_lds, double* A) {
   __shared__ int bad;
@@ -304,13 +307,14 @@ __device__ void cholesky_lds_body(const double* __restrict__ G, int n, double* _
   __shared__ double rsv[128];     // 1/L_jj
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int tx = tid & 31, ty = tid >> 5, ny = nthr >> 5;
-  double* X = A + n * n;
+  const int ld = chol_ld(n);  // odd row stride: a column read by a warp of rows spreads the banks
+  double* X = A + n * ld;
   for (int t = tid; t < n * n; t += nthr) {
+    const int r = t / n, q = t - r * n;
     const double g = G[t];
-    A[t] = g;
-    const bool dg = t / n == t % n;
-    if (dg) gdiag[t / n] = g;
-    if (inv_in_lds) X[t] = dg ? 1.0 : 0.0;
+    A[r * ld + q] = g;
+    if (r == q) gdiag[r] = g;
+    if (inv_in_lds) X[r * ld + q] = r == q ? 1.0 : 0.0;
   }
   auto pivot = [&](int j, double d) {
     if (!(d > 1e-12 * gdiag[j]) || !isfinite(d)) {
@@ -331,38 +335,41 @@ __device__ void cholesky_lds_body(const double* __restrict__ G, int n, double* _
     const double rd = piv[j & 1][0];
     // the previous row of the inverse is final: scale it
     if (inv_in_lds && j > 0)
-      for (int cc = tid; cc < j; cc += nthr) X[(j - 1) * n + cc] *= rsv[j - 1];
+      for (int cc = tid; cc < j; cc += nthr) X[(j - 1) * ld + cc] *= rsv[j - 1];
     for (int i = j + 1 + ty; i < n; i += ny) {
-      const double f = A[i * n + j] * rd;
+      const double f = A[i * ld + j] * rd;
       for (int k = j + 1 + tx; k <= i; k += 32) {
-        const double v = A[i * n + k] - f * A[k * n + j];
-        A[i * n + k] = v;
+        const double v = A[i * ld + k] - f * A[k * ld + j];
+        A[i * ld + k] = v;
         if (i == j + 1 && k == j + 1) pivot(j + 1, v);  // thread 0
       }
       if (inv_in_lds)
-        for (int cc = tx; cc <= j; cc += 32) X[i * n + cc] -= f * X[j * n + cc];
+        for (int cc = tx; cc <= j; cc += 32) X[i * ld + cc] -= f * X[j * ld + cc];
     }
     __syncthreads();
   }
   if (inv_in_lds) {
-    for (int cc = tid; cc < n; cc += nthr) X[(n - 1) * n + cc] *= rsv[n - 1];
+    for (int cc = tid; cc < n; cc += nthr) X[(n - 1) * ld + cc] *= rsv[n - 1];
     __syncthreads();
-    for (int t = tid; t < n * n; t += nthr) Linv[t] = (t % n <= t / n) ? X[t] : 0.0;
+    for (int t = tid; t < n * n; t += nthr) {
+      const int r = t / n, q = t - r * n;
+      Linv[t] = q <= r ? X[r * ld + q] : 0.0;
+    }
   } else {
     // L = column j of A scaled by 1/sqrt(d_j), diagonal sqrt(d_j)
     for (int t = tid; t < n * n; t += nthr) {
       const int i = t / n, k = t % n;
-      if (k < i) A[t] *= rsv[k];
-      else if (k == i) A[t] = 1.0 / rsv[k];
+      if (k < i) A[i * ld + k] *= rsv[k];
+      else if (k == i) A[i * ld + k] = 1.0 / rsv[k];
     }
     __syncthreads();
     for (int col = tid; col < n; col += nthr) {
       for (int i = 0; i < col; ++i) Linv[(size_t)i * n + col] = 0.0;
-      Linv[(size_t)col * n + col] = 1.0 / A[col * n + col];
+      Linv[(size_t)col * n + col] = 1.0 / A[col * ld + col];
       for (int i = col + 1; i < n; ++i) {
         double s = 0.0;
-        for (int k = col; k < i; ++k) s += A[i * n + k] * Linv[(size_t)k * n + col];
-        Linv[(size_t)i * n + col] = -s / A[i * n + i];
+        for (int k = col; k < i; ++k) s += A[i * ld + k] * Linv[(size_t)k * n + col];
+        Linv[(size_t)i * n + col] = -s / A[i * ld + i];
       }
     }
   }
@@ -748,7 +755,7 @@ void matrix_norm1(Ctx& c, const double* A, int n, double* out) {
 void cholesky_inverse(Ctx& c, const double* G, int n, double* Linv, int32_t* flag) {
   if (n <= 128) {
     const int inv = n <= 96 ? 1 : 0;
-    const size_t lds = (size_t)(inv ? 2 : 1) * n * n * sizeof(double);
+    const size_t lds = (size_t)(inv ? 2 : 1) * n * chol_ld(n) * sizeof(double);
     if (lds > 65536)
       ROKS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholesky_inverse_lds),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -766,7 +773,7 @@ void launch_chol_expm_lds(Ctx& c, const double* G, double* Linv, int32_t* flag, 
                           double delta, double* U) {
   const int n = c.nb;
   const int inv = n <= 96 ? 1 : 0;
-  const size_t lds = (size_t)std::max(inv ? 2 : 1, 3) * n * n * sizeof(double);
+  const size_t lds = std::max((size_t)(inv ? 2 : 1) * n * chol_ld(n), (size_t)3 * n * n) * sizeof(double);
   if (lds > 65536)
     ROKS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_chol_expm_lds),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
