@@ -137,13 +137,18 @@ void init_device(Ctx& c, void* stream) {
                      &c.d_Ukeep, &c.d_m4, &c.d_SS};
   for (double** m : mats) *m = dalloc<double>(c, nn);
   c.d_flag = dalloc<int32_t>(c, 16);
-  c.d_stage = dalloc<double>(c, kStage + 4 * (size_t)nb);
   ROKS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_scal), (16 + 2 * (size_t)nb) * sizeof(double),
                          hipHostMallocDefault));
+  // the step scalars and status flags are written by kernels straight into
+  // pinned, coherent host memory (read by the host after a synchronisation;
+  // no kernel reads them back), through the device views hd_*
   ROKS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_stage),
-                         (kStage + 4 * (size_t)nb) * sizeof(double), hipHostMallocDefault));
+                         (kStage + 4 * (size_t)nb) * sizeof(double),
+                         hipHostMallocMapped | hipHostMallocCoherent));
   ROKS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_flag), 16 * sizeof(int32_t),
-                         hipHostMallocDefault));
+                         hipHostMallocMapped | hipHostMallocCoherent));
+  ROKS_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c.hd_stage), c.h_stage, 0));
+  ROKS_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c.hd_flag), c.h_flag, 0));
   c.d_force = dalloc<double>(c, 3 * (size_t)std::max(1, c.natoms));
   c.d_kinw_shell = dalloc<double>(c, nb);
   c.d_ones = dalloc<double>(c, nb);
@@ -250,6 +255,8 @@ void free_device(Ctx& c) {
     if (h) (void)hipHostFree(h);
   c.h_scal = c.h_stage = nullptr;
   c.h_flag = nullptr;
+  c.hd_stage = nullptr;
+  c.hd_flag = nullptr;
   if (c.side) (void)hipStreamSynchronize(c.side);
   if (c.ev_fork) (void)hipEventDestroy(c.ev_fork);
   if (c.ev_join) (void)hipEventDestroy(c.ev_join);

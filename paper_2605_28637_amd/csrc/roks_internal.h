@@ -200,11 +200,12 @@ struct Ctx {
   double* d_dP = nullptr;        // [nproj][nb] derivative projections
   double2* d_hch = nullptr;      // [4][nb][npw] multi-channel apply output (lazy)
   double* d_scal = nullptr;      // [16 + 2 nb]: reduced energy sums, then kin, enl
-  double* d_stage = nullptr;     // [kStage + 4 nb] step scalars fetched together
   // pinned host mirrors (one stream-ordered copy, one synchronisation)
   double* h_scal = nullptr;      // [16 + 2 nb]
   double* h_stage = nullptr;     // [kStage + 4 nb]
   int32_t* h_flag = nullptr;     // [16]
+  double* hd_stage = nullptr;    // device view of h_stage (kernels write it directly)
+  int32_t* hd_flag = nullptr;    // device view of h_flag
   double* d_m4 = nullptr;
   double* d_kinw_shell = nullptr;  // [nb] shell weight of each band (0 for virtual)
   double* d_ones = nullptr;        // [nb] ones
@@ -460,7 +461,7 @@ T* dalloc(Ctx& c, size_t count) {
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-constexpr int kStage = 16;  // scalar slots ahead of the per-band ones in d_stage
+constexpr int kStage = 16;  // scalar slots ahead of the per-band ones in h_stage
 
 }  // namespace roks
 

@@ -126,11 +126,9 @@ void evaluate_trial(Ctx& c, double delta, Trial& t, bool energy_only) {
   scale_shift(c, c.d_SS, nb, delta * delta, 1.0, c.d_gram);
   if (expm_in_lds(c)) {
     // factorisation and exponential side by side: one launch, two workgroups
-    launch_chol_expm_lds(c, c.d_gram, c.d_Linv, c.d_flag, c.d_D, delta, t.U);
-    fetch(c, c.h_flag, c.d_flag, sizeof(int32_t));
+    launch_chol_expm_lds(c, c.d_gram, c.d_Linv, c.hd_flag, c.d_D, delta, t.U);
   } else {
-    cholesky_inverse(c, c.d_gram, nb, c.d_Linv, c.d_flag);
-    fetch(c, c.h_flag, c.d_flag, sizeof(int32_t));
+    cholesky_inverse(c, c.d_gram, nb, c.d_Linv, c.hd_flag);
     expm(c, delta, c.d_D, t.U);
   }
   gemm_small(c, nb, nb, nb, t.U, nb, true, c.d_Linv, nb, false, t.M, nb, 1.0, 0.0);
@@ -332,10 +330,12 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   }
   if (recording) record_iterate(c, c.d_bandv, c.d_bandv + nb, c.d_bandv + 4 * nb);
   const double* bandw = (c.flags & ROKS_FLAG_WEIGHT_PRECOND) ? c.d_kinw_shell : nullptr;
-  // step scalars in d_stage: [0] sum A (theta - theta^T), [1] the same for D,
-  // [2] max open-shell coupling, [kStage + n] <p_n|g_n>, [kStage + nb + n]
-  // <g_n|g_n>, [kStage + 2 nb + n] <S_n|g_n>; sums over bands in band order
-  double* st = c.d_stage;
+  // step scalars, written by the kernels straight into the pinned mirror
+  // (read after a synchronisation): [0] sum A (theta - theta^T), [1] the same
+  // for D, [2] max open-shell coupling, [kStage + n] <p_n|g_n>,
+  // [kStage + nb + n] <g_n|g_n>, [kStage + 2 nb + n] <S_n|g_n>; sums over
+  // bands in band order
+  double* st = c.hd_stage;
   const double* hs = c.h_stage;
   auto band_sum = [&](int off) {
     double v = 0.0;
@@ -359,11 +359,9 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     band_dots(c, c.d_p, c.d_gI, nb, 0, st + kStage);
     if (first_fetch) {
       // with the report's |g_I| and open-shell coupling
-      copy_dev(c, st + kStage + nb, c.d_bandv + nb, nb * sizeof(double));
+      ROKS_HIP(hipMemcpyAsync(st + kStage + nb, c.d_bandv + nb, nb * sizeof(double), hipMemcpyDefault,
+                              c.stream));
       if (no == 2) launch_open_coupling(c, opens[0], opens[1], st + 2);
-      fetch(c, c.h_stage, st, (kStage + 2 * (size_t)nb) * sizeof(double));
-    } else {
-      fetch(c, c.h_stage, st, (kStage + (size_t)nb) * sizeof(double));
     }
     sync(c);
     first_fetch = false;
@@ -392,8 +390,6 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     }
     launch_asym_dot(c, c.d_D, c.d_theta, st + 1);
     band_dots(c, c.d_S, c.d_gI, nb, 0, st + kStage + 2 * nb);
-    fetch(c, c.h_stage + 1, st + 1, sizeof(double));
-    fetch(c, c.h_stage + kStage + 2 * nb, st + kStage + 2 * nb, nb * sizeof(double));
     sync(c);
     return 2.0 * band_sum(2 * nb) + hs[1];
   };
