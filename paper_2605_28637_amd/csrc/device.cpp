@@ -119,7 +119,6 @@ void init_device(Ctx& c, void* stream) {
   c.d_dP = dalloc<double>(c, np * nb);
   c.d_P0 = dalloc<double>(c, np * nb);
   c.d_PS = dalloc<double>(c, np * nb);
-  c.d_Pq = dalloc<double>(c, np * nb);
   c.part_capacity = std::max<size_t>(8 * 1024, (size_t)c.natoms * 32 * 3) + 64;
   c.d_part = dalloc<double>(c, c.part_capacity);
   c.d_scal = dalloc<double>(c, 16 + 2 * nb);

@@ -119,9 +119,10 @@ __global__ void __launch_bounds__(256) k_expand_mfma(int N, int K, int Md, const
 // small products: C = alpha op(A) op(B) + beta C, 16 x 16 tiles
 // --------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_gemm_small(int M, int N, int K, const double* __restrict__ A,
-                                                    int lda, int tA, const double* __restrict__ B,
-                                                    int ldb, int tB, double* __restrict__ C, int ldc,
-                                                    double alpha, double beta, double diag) {
+                                                    const double* __restrict__ A2, double a2, int lda,
+                                                    int tA, const double* __restrict__ B, int ldb, int tB,
+                                                    double* __restrict__ C, int ldc, double alpha,
+                                                    double beta, double diag) {
   __shared__ double As[16][17];
   __shared__ double Bs[16][17];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -131,7 +132,11 @@ __global__ void __launch_bounds__(256) k_gemm_small(int M, int N, int K, const d
     const int ka = k0 + tx, kb = k0 + ty;
     // A(m, k) for this thread's row, B(k, n) for this thread's column
     double a = 0.0, b = 0.0;
-    if (m < M && ka < K) a = tA ? A[(size_t)ka * lda + m] : A[(size_t)m * lda + ka];
+    if (m < M && ka < K) {
+      const size_t ia = tA ? (size_t)ka * lda + m : (size_t)m * lda + ka;
+      a = A[ia];
+      if (A2) a += a2 * A2[ia];  // op(A + a2 A2)
+    }
     if (n < N && kb < K) b = tB ? B[(size_t)n * ldb + kb] : B[(size_t)kb * ldb + n];
     As[ty][tx] = a;
     Bs[ty][tx] = b;
@@ -299,8 +304,9 @@ __global__ void __launch_bounds__(1024) k_cholesky_inverse(const double* __restr
 // LDS row stride of the single-workgroup Cholesky: n rounded up to odd
 __host__ __device__ inline int chol_ld(int n) { return n | 1; }
 
-__device__ void cholesky_lds_body(const double* __restrict__ G, int n, double* __restrict__ Linv,
-                                  int32_t* __restrict__ flag, int inv_in_lds, double* A) {
+__device__ void cholesky_lds_body(const double* __restrict__ G, double ga, double gd, int n,
+                                  double* __restrict__ Linv, int32_t* __restrict__ flag, int inv_in_lds,
+                                  double* A) {
   __shared__ int bad;
   __shared__ double gdiag[128];   // the Gram diagonal, the reference of the pivot test
   __shared__ double piv[2][2];    // [step parity]: 1/d, 1/sqrt(d)
@@ -311,7 +317,7 @@ __device__ void cholesky_lds_body(const double* __restrict__ G, int n, double* _
   double* X = A + n * ld;
   for (int t = tid; t < n * n; t += nthr) {
     const int r = t / n, q = t - r * n;
-    const double g = G[t];
+    const double g = ga * G[t] + (r == q ? gd : 0.0);  // the matrix factorised: ga G + gd I
     A[r * ld + q] = g;
     if (r == q) gdiag[r] = g;
     if (inv_in_lds) X[r * ld + q] = r == q ? 1.0 : 0.0;
@@ -328,7 +334,7 @@ __device__ void cholesky_lds_body(const double* __restrict__ G, int n, double* _
   };
   if (tid == 0) {
     bad = 0;
-    pivot(0, G[0]);
+    pivot(0, ga * G[0] + gd);
   }
   __syncthreads();
   for (int j = 0; j < n; ++j) {
@@ -381,7 +387,7 @@ __global__ void __launch_bounds__(1024) k_cholesky_inverse_lds(const double* __r
                                                                int32_t* __restrict__ flag,
                                                                int inv_in_lds) {
   extern __shared__ double A[];
-  cholesky_lds_body(G, n, Linv, flag, inv_in_lds, A);
+  cholesky_lds_body(G, 1.0, 0.0, n, Linv, flag, inv_in_lds, A);
 }
 
 // U = exp(delta D) in one workgroup, the three n x n matrices in LDS:
@@ -504,14 +510,14 @@ __global__ void __launch_bounds__(1024) k_expm_lds(const double* __restrict__ D,
 
 // the two independent single-workgroup steps of a trial in one launch:
 // workgroup 0 factorises the Gram matrix, workgroup 1 exponentiates delta D
-__global__ void __launch_bounds__(1024) k_chol_expm_lds(const double* __restrict__ G, int n,
-                                                       double* __restrict__ Linv,
+__global__ void __launch_bounds__(1024) k_chol_expm_lds(const double* __restrict__ G, double ga,
+                                                       double gd, int n, double* __restrict__ Linv,
                                                        int32_t* __restrict__ flag, int inv_in_lds,
                                                        const double* __restrict__ D, double delta,
                                                        double* __restrict__ U) {
   extern __shared__ double S[];
   if (blockIdx.x == 0)
-    cholesky_lds_body(G, n, Linv, flag, inv_in_lds, S);
+    cholesky_lds_body(G, ga, gd, n, Linv, flag, inv_in_lds, S);
   else
     expm_lds_body(D, n, delta, U, S);
 }
@@ -709,9 +715,15 @@ void gemm_expand_sum(Ctx& c, int N, int K, int Md, const double* M, int ldm, boo
 
 void gemm_small(Ctx& c, int M, int N, int K, const double* A, int lda, bool tA, const double* B,
                 int ldb, bool tB, double* C, int ldc, double alpha, double beta, double diag) {
+  gemm_small2(c, M, N, K, A, nullptr, 0.0, lda, tA, B, ldb, tB, C, ldc, alpha, beta, diag);
+}
+
+void gemm_small2(Ctx& c, int M, int N, int K, const double* A, const double* A2, double a2, int lda,
+                 bool tA, const double* B, int ldb, bool tB, double* C, int ldc, double alpha,
+                 double beta, double diag) {
   dim3 grid(cdiv(N, 16), cdiv(M, 16));
-  hipLaunchKernelGGL(k_gemm_small, grid, dim3(256), 0, c.stream, M, N, K, A, lda, tA ? 1 : 0, B, ldb,
-                     tB ? 1 : 0, C, ldc, alpha, beta, diag);
+  hipLaunchKernelGGL(k_gemm_small, grid, dim3(256), 0, c.stream, M, N, K, A, A2, a2, lda, tA ? 1 : 0, B,
+                     ldb, tB ? 1 : 0, C, ldc, alpha, beta, diag);
   ROKS_HIP(hipGetLastError());
 }
 
@@ -769,16 +781,16 @@ void cholesky_inverse(Ctx& c, const double* G, int n, double* Linv, int32_t* fla
 
 bool expm_in_lds(const Ctx& c) { return c.nb <= 78; }
 
-void launch_chol_expm_lds(Ctx& c, const double* G, double* Linv, int32_t* flag, const double* D,
-                          double delta, double* U) {
+void launch_chol_expm_lds(Ctx& c, const double* G, double ga, double gd, double* Linv, int32_t* flag,
+                          const double* D, double delta, double* U) {
   const int n = c.nb;
   const int inv = n <= 96 ? 1 : 0;
   const size_t lds = std::max((size_t)(inv ? 2 : 1) * n * chol_ld(n), (size_t)3 * n * n) * sizeof(double);
   if (lds > 65536)
     ROKS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_chol_expm_lds),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_chol_expm_lds, dim3(2), dim3(1024), lds, c.stream, G, n, Linv, flag, inv, D,
-                     delta, U);
+  hipLaunchKernelGGL(k_chol_expm_lds, dim3(2), dim3(1024), lds, c.stream, G, ga, gd, n, Linv, flag, inv,
+                     D, delta, U);
   ROKS_HIP(hipGetLastError());
 }
 

@@ -189,7 +189,6 @@ struct Ctx {
   double* d_SS = nullptr;        // <S_m|S_n> of the current search direction
   double* d_P0 = nullptr;        // [nproj][nb] <beta|psi> at the start of the line search
   double* d_PS = nullptr;        // [nproj][nb] <beta|S>
-  double* d_Pq = nullptr;        // [nproj][nb] scratch
   int32_t* d_flag = nullptr;     // device status flags
   double* d_force = nullptr;     // [natoms][3]
   double* d_force_loc = nullptr; // [natoms][3] local part (side stream)
@@ -398,6 +397,10 @@ void gemm_expand_sum(Ctx& c, int N, int K, int Md, const double* M, int ldm, boo
 // C = alpha op(A) op(B) + beta C + diag I
 void gemm_small(Ctx& c, int M, int N, int K, const double* A, int lda, bool tA, const double* B,
                 int ldb, bool tB, double* C, int ldc, double alpha, double beta, double diag = 0.0);
+// the same with op(A + a2 A2) (A2 of A's layout, may be null)
+void gemm_small2(Ctx& c, int M, int N, int K, const double* A, const double* A2, double a2, int lda,
+                 bool tA, const double* B, int ldb, bool tB, double* C, int ldc, double alpha,
+                 double beta, double diag);
 void band_dots(Ctx& c, const double2* X, const double2* Y, int nvec, int mode, double* out);
 // both weightings in one pass: out0 plain, out1 |G|^2/2 (either may be null)
 void band_dots2(Ctx& c, const double2* X, const double2* Y, int nvec, double* out0, double* out1);
@@ -411,8 +414,8 @@ void launch_subspace(Ctx& c);
 bool expm_in_lds(const Ctx& c);
 // Cholesky inverse of G and U = exp(delta D) in one launch of two workgroups
 // (nb within the single-workgroup limits of both)
-void launch_chol_expm_lds(Ctx& c, const double* G, double* Linv, int32_t* flag, const double* D,
-                          double delta, double* U);
+void launch_chol_expm_lds(Ctx& c, const double* G, double ga, double gd, double* Linv, int32_t* flag,
+                          const double* D, double delta, double* U);
 void launch_expm_lds(Ctx& c, const double* D, double delta, double* U, hipStream_t stream);
 void launch_asym_dot(Ctx& c, const double* A, const double* theta, double* out);
 // max |theta_nm - theta_mn| over m of shell sa, n of shell sb (one value)

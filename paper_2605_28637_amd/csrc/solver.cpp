@@ -123,11 +123,12 @@ void prepare_line_search(Ctx& c, bool first) {
 // (a failed factorisation only makes the rest of the evaluation meaningless).
 void evaluate_trial(Ctx& c, double delta, Trial& t, bool energy_only) {
   const int nb = c.nb, K = 2 * c.npw;
-  scale_shift(c, c.d_SS, nb, delta * delta, 1.0, c.d_gram);
   if (expm_in_lds(c)) {
-    // factorisation and exponential side by side: one launch, two workgroups
-    launch_chol_expm_lds(c, c.d_gram, c.d_Linv, c.hd_flag, c.d_D, delta, t.U);
+    // factorisation of I + delta^2 <S|S> (formed while loading) and the
+    // exponential side by side: one launch, two workgroups
+    launch_chol_expm_lds(c, c.d_SS, delta * delta, 1.0, c.d_Linv, c.hd_flag, c.d_D, delta, t.U);
   } else {
+    scale_shift(c, c.d_SS, nb, delta * delta, 1.0, c.d_gram);
     cholesky_inverse(c, c.d_gram, nb, c.d_Linv, c.hd_flag);
     expm(c, delta, c.d_D, t.U);
   }
@@ -136,8 +137,8 @@ void evaluate_trial(Ctx& c, double delta, Trial& t, bool energy_only) {
   gemm_expand_sum(c, nb, K, nb, t.M, nb, true, dbl(c.d_psi), dbl(c.d_S), delta, K, dbl(t.psi), K,
                   dbl(t.psi), K, 1.0, 0.0);
   if (c.nproj > 0) {
-    axpby(c, (size_t)c.nproj * nb, 1.0, c.d_P0, delta, c.d_PS, c.d_Pq);
-    gemm_small(c, c.nproj, nb, nb, c.d_Pq, nb, false, t.M, nb, true, c.d_P, nb, 1.0, 0.0);
+    gemm_small2(c, c.nproj, nb, nb, c.d_P0, c.d_PS, delta, nb, false, t.M, nb, true, c.d_P, nb, 1.0,
+                0.0, 0.0);
   }
   compute_potentials_async(c, t.psi, true, energy_only);
   sync(c);
