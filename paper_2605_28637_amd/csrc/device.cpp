@@ -1,6 +1,7 @@
 // Device memory layout and the upload of the static tables.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include <rocblas/rocblas.h>
 
@@ -136,17 +137,25 @@ void init_device(Ctx& c, void* stream) {
                      &c.d_Ukeep, &c.d_m4, &c.d_SS};
   for (double** m : mats) *m = dalloc<double>(c, nn);
   c.d_flag = dalloc<int32_t>(c, 16);
+  // the energy sums, step scalars and status flags are written by kernels
+  // straight into pinned, coherent host memory (read by the host after a
+  // synchronisation; no kernel reads them back), through the device views hd_*
   ROKS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_scal), (16 + 2 * (size_t)nb) * sizeof(double),
-                         hipHostMallocDefault));
-  // the step scalars and status flags are written by kernels straight into
-  // pinned, coherent host memory (read by the host after a synchronisation;
-  // no kernel reads them back), through the device views hd_*
+                         hipHostMallocMapped | hipHostMallocCoherent));
   ROKS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_stage),
                          (kStage + 4 * (size_t)nb) * sizeof(double),
                          hipHostMallocMapped | hipHostMallocCoherent));
   ROKS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_flag), 16 * sizeof(int32_t),
                          hipHostMallocMapped | hipHostMallocCoherent));
+  ROKS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_force),
+                         3 * (size_t)std::max(1, c.natoms) * sizeof(double),
+                         hipHostMallocMapped | hipHostMallocCoherent));
+  ROKS_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c.hd_scal), c.h_scal, 0));
+  ROKS_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c.hd_force), c.h_force, 0));
   ROKS_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c.hd_stage), c.h_stage, 0));
+  // without projectors the nonlocal band energies stay zero
+  std::memset(c.h_scal, 0, (16 + 2 * (size_t)nb) * sizeof(double));
+  ROKS_HIP(hipMemsetAsync(c.d_scal, 0, (16 + 2 * (size_t)nb) * sizeof(double), c.stream));
   ROKS_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c.hd_flag), c.h_flag, 0));
   c.d_force = dalloc<double>(c, 3 * (size_t)std::max(1, c.natoms));
   c.d_kinw_shell = dalloc<double>(c, nb);
@@ -250,11 +259,11 @@ void free_device(Ctx& c) {
   if (c.stream || !c.allocations.empty()) (void)hipStreamSynchronize(c.stream);
   for (DevBuf& b : c.allocations) (void)hipFree(b.p);
   c.allocations.clear();
-  for (void* h : {(void*)c.h_scal, (void*)c.h_stage, (void*)c.h_flag})
+  for (void* h : {(void*)c.h_scal, (void*)c.h_stage, (void*)c.h_flag, (void*)c.h_force})
     if (h) (void)hipHostFree(h);
-  c.h_scal = c.h_stage = nullptr;
+  c.h_scal = c.h_stage = c.h_force = nullptr;
   c.h_flag = nullptr;
-  c.hd_stage = nullptr;
+  c.hd_scal = c.hd_stage = c.hd_force = nullptr;
   c.hd_flag = nullptr;
   if (c.side) (void)hipStreamSynchronize(c.side);
   if (c.ev_fork) (void)hipEventDestroy(c.ev_fork);

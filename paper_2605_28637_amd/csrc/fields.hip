@@ -388,27 +388,34 @@ __global__ void __launch_bounds__(256) k_xc(ShellArgs a, const double* __restric
     for (int j = 0; j < 6; ++j) part[(size_t)blockIdx.x * 6 + j] = acc[j];
 }
 
-// out[j] = sum_r part[r][j]; one workgroup per column, fixed summation tree
+// out[j] = sum_r part[r][j] (also into mirror[j] when given); one workgroup per
+// column, fixed summation tree
 __global__ void __launch_bounds__(256) k_reduce_columns(const double* __restrict__ part, int nrows,
-                                                        int ncols, double* __restrict__ out) {
+                                                        int ncols, double* __restrict__ out,
+                                                        double* __restrict__ mirror) {
   __shared__ double red[8 * 16];
   const int j = blockIdx.x;
   double v[1] = {0.0};
   for (int r = threadIdx.x; r < nrows; r += blockDim.x) v[0] += part[(size_t)r * ncols + j];
   block_sum<1>(v, red);
-  if (threadIdx.x == 0) out[j] = v[0];
+  if (threadIdx.x == 0) {
+    out[j] = v[0];
+    if (mirror) mirror[j] = v[0];
+  }
 }
 
 // ---------------------------------------------------------------------------
 // nonlocal energies and D application (per-atom dense blocks)
 // ---------------------------------------------------------------------------
-// e_n = sum_atoms sum_ij P_in D_ij P_jn: one wave per band, atoms split over lanes
+// e_n = sum_atoms sum_ij P_in D_ij P_jn (also into mirror[n] when given): one
+// wave per band, atoms split over lanes
 __global__ void __launch_bounds__(64) k_nl_energy(const double* __restrict__ P, int nb, int natoms,
                                                   const int32_t* __restrict__ off,
                                                   const int32_t* __restrict__ cnt,
                                                   const int32_t* __restrict__ doff,
                                                   const double* __restrict__ D,
-                                                  double* __restrict__ out) {
+                                                  double* __restrict__ out,
+                                                  double* __restrict__ mirror) {
   const int n = blockIdx.x;
   double s = 0;
   for (int a = threadIdx.x; a < natoms; a += blockDim.x) {
@@ -422,7 +429,10 @@ __global__ void __launch_bounds__(64) k_nl_energy(const double* __restrict__ P, 
     }
   }
   s = wave_sum(s);
-  if (threadIdx.x == 0) out[n] = s;
+  if (threadIdx.x == 0) {
+    out[n] = s;
+    if (mirror) mirror[n] = s;
+  }
 }
 
 __global__ void k_apply_D(const double* __restrict__ P, int nb, int nproj,
@@ -500,14 +510,16 @@ __global__ void __launch_bounds__(256) k_local_force(Lattice L, const AtomP* __r
     for (int a = 0; a < 3; ++a) part[((size_t)I * gridDim.x + blockIdx.x) * 3 + a] = acc[a];
 }
 
-// dE/dR_I,axis (nonlocal) = sum_{i in I} sum_n 2 w_n dP_in (D P)_in
-// out[I][a] += 2 sum_{i of atom I} sum_n w_n dP[a][i][n] DP[i][n]: one wave
-// per (atom, axis), lanes over (projector, band), fixed butterfly
+// dE/dR_I,axis (nonlocal) = sum_{i in I} sum_n 2 w_n dP_in (D P)_in, and the
+// force F = -(dE_loc/dR + dE_nl/dR) written in the same pass:
+// out[I][a] = -(loc[I][a] + 2 sum_{i of atom I} sum_n w_n dP[a][i][n] DP[i][n]).
+// One wave per (atom, axis), lanes over (projector, band), fixed butterfly.
 __global__ void __launch_bounds__(256) k_nl_force(const double* __restrict__ dP,
                                                   const double* __restrict__ DP, int nb, int nproj,
                                                   int natoms, const int32_t* __restrict__ off,
                                                   const int32_t* __restrict__ cnt,
                                                   const double* __restrict__ w,
+                                                  const double* __restrict__ loc,
                                                   double* __restrict__ out) {
   const int wave = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
@@ -522,7 +534,7 @@ __global__ void __launch_bounds__(256) k_nl_force(const double* __restrict__ dP,
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if (lane == 0) out[I * 3 + a] += s;
+  if (lane == 0) out[I * 3 + a] = -(loc[I * 3 + a] + s);
 }
 
 // out[o][j] = scale * sum_i part[o][i][j]
@@ -664,8 +676,10 @@ void launch_hartree_energy(Ctx& c, double* part, int nblocks) {
   ROKS_HIP(hipGetLastError());
 }
 
-void launch_reduce_columns(Ctx& c, const double* part, int nrows, int ncols, double* out) {
-  hipLaunchKernelGGL(k_reduce_columns, dim3(ncols), dim3(256), 0, c.stream, part, nrows, ncols, out);
+void launch_reduce_columns(Ctx& c, const double* part, int nrows, int ncols, double* out,
+                           double* mirror) {
+  hipLaunchKernelGGL(k_reduce_columns, dim3(ncols), dim3(256), 0, c.stream, part, nrows, ncols, out,
+                     mirror);
   ROKS_HIP(hipGetLastError());
 }
 
@@ -682,9 +696,9 @@ void launch_reduce_strided(Ctx& c, const double* part, int nouter, int ninner, i
   ROKS_HIP(hipGetLastError());
 }
 
-void launch_nl_energy(Ctx& c, const double* P, double* out) {
+void launch_nl_energy(Ctx& c, const double* P, double* out, double* mirror) {
   hipLaunchKernelGGL(k_nl_energy, dim3(c.nb), dim3(64), 0, c.stream, P, c.nb, c.natoms,
-                     c.d_atom_proj_off, c.d_atom_proj_cnt, c.d_Dblk_off, c.d_Dblk, out);
+                     c.d_atom_proj_off, c.d_atom_proj_cnt, c.d_Dblk_off, c.d_Dblk, out, mirror);
   ROKS_HIP(hipGetLastError());
 }
 
@@ -725,10 +739,11 @@ void launch_local_force(Ctx& c, const double2* rhoG, double* out_part, int nblk)
   ROKS_HIP(hipGetLastError());
 }
 
-void launch_nl_force(Ctx& c, const double* dP3, const double* DP, const double* w, double* out) {
+void launch_nl_force(Ctx& c, const double* dP3, const double* DP, const double* w,
+                     const double* loc, double* out) {
   if (c.natoms == 0) return;
   hipLaunchKernelGGL(k_nl_force, dim3(cdiv(3 * c.natoms, 4)), dim3(256), 0, c.stream, dP3, DP, c.nb,
-                     c.nproj, c.natoms, c.d_atom_proj_off, c.d_atom_proj_cnt, w, out);
+                     c.nproj, c.natoms, c.d_atom_proj_off, c.d_atom_proj_cnt, w, loc, out);
   ROKS_HIP(hipGetLastError());
 }
 

@@ -164,7 +164,9 @@ __global__ void __launch_bounds__(256) k_gemm_small(int M, int N, int K, const d
 __global__ void __launch_bounds__(1024) k_band_dots(const double2* __restrict__ X,
                                                    const double2* __restrict__ Yv, int npw,
                                                    const double* __restrict__ g2,
-                                                   double* __restrict__ out0, double* __restrict__ out1) {
+                                                   double* __restrict__ out0, double* __restrict__ out1,
+                                                   double* __restrict__ mirror0,
+                                                   double* __restrict__ mirror1) {
   __shared__ double red[2][16];
   const int n = blockIdx.x;
   const double2* x = X + (size_t)n * npw;
@@ -192,6 +194,8 @@ __global__ void __launch_bounds__(1024) k_band_dots(const double2* __restrict__ 
     }
     if (out0) out0[n] = t0;
     if (out1) out1[n] = t1;
+    if (mirror0) mirror0[n] = t0;
+    if (mirror1) mirror1[n] = t1;
   }
 }
 
@@ -727,9 +731,11 @@ void gemm_small2(Ctx& c, int M, int N, int K, const double* A, const double* A2,
   ROKS_HIP(hipGetLastError());
 }
 
-void band_dots2(Ctx& c, const double2* X, const double2* Y, int nvec, double* out0, double* out1) {
+void band_dots2(Ctx& c, const double2* X, const double2* Y, int nvec, double* out0, double* out1,
+                double* mirror0, double* mirror1) {
   if (nvec == 0) return;
-  hipLaunchKernelGGL(k_band_dots, dim3(nvec), dim3(1024), 0, c.stream, X, Y, c.npw, c.d_g2, out0, out1);
+  hipLaunchKernelGGL(k_band_dots, dim3(nvec), dim3(1024), 0, c.stream, X, Y, c.npw, c.d_g2, out0, out1,
+                     mirror0, mirror1);
   ROKS_HIP(hipGetLastError());
 }
 

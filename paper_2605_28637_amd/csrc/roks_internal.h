@@ -199,12 +199,16 @@ struct Ctx {
   double* d_dP = nullptr;        // [nproj][nb] derivative projections
   double2* d_hch = nullptr;      // [4][nb][npw] multi-channel apply output (lazy)
   double* d_scal = nullptr;      // [16 + 2 nb]: reduced energy sums, then kin, enl
-  // pinned host mirrors (one stream-ordered copy, one synchronisation)
-  double* h_scal = nullptr;      // [16 + 2 nb]
+  // pinned, coherent host mirrors written by the kernels (read after a
+  // synchronisation)
+  double* h_scal = nullptr;      // [16 + 2 nb]: mirror of d_scal
   double* h_stage = nullptr;     // [kStage + 4 nb]
   int32_t* h_flag = nullptr;     // [16]
+  double* h_force = nullptr;     // [natoms][3] forces (nonlocal kernel writes them)
+  double* hd_scal = nullptr;     // device view of h_scal
   double* hd_stage = nullptr;    // device view of h_stage (kernels write it directly)
   int32_t* hd_flag = nullptr;    // device view of h_flag
+  double* hd_force = nullptr;    // device view of h_force
   double* d_m4 = nullptr;
   double* d_kinw_shell = nullptr;  // [nb] shell weight of each band (0 for virtual)
   double* d_ones = nullptr;        // [nb] ones
@@ -353,13 +357,14 @@ void launch_hartree(Ctx& c);
 void launch_xc_potentials(Ctx& c, double* part, int nblocks);
 int xc_blocks(const Ctx& c);
 void launch_band_kinetic(Ctx& c, const double2* vecs, int nvec, double* out);
-void launch_nl_energy(Ctx& c, const double* P, double* out);
+void launch_nl_energy(Ctx& c, const double* P, double* out, double* mirror = nullptr);
 void launch_apply_D(Ctx& c, const double* P, const double* w, double* DP);
 // energy-only evaluation: xc and external sums without potentials, and the
 // Hartree integrals from the forward transform (partials [block][2])
 void launch_xc_energy(Ctx& c, double* part, int nblocks);
 void launch_hartree_energy(Ctx& c, double* part, int nblocks);
-void launch_reduce_columns(Ctx& c, const double* part, int nrows, int ncols, double* out);
+void launch_reduce_columns(Ctx& c, const double* part, int nrows, int ncols, double* out,
+                           double* mirror = nullptr);
 void launch_to_float(Ctx& c, const double* in, float* out, size_t n);
 void launch_reduce_strided(Ctx& c, const double* part, int nouter, int ninner, int ncols,
                            double scale, double* out);
@@ -368,7 +373,8 @@ void launch_pack_rho_weighted(Ctx& c);
 size_t atom_info_bytes();
 size_t proj_info_bytes();
 // forces from the three derivative projections dP3 [3][nproj][nb]
-void launch_nl_force(Ctx& c, const double* dP3, const double* DP, const double* w, double* out);
+void launch_nl_force(Ctx& c, const double* dP3, const double* DP, const double* w,
+                     const double* loc, double* out);
 // the three derivative tables -i G_a beta, [3][nproj][npw]
 // the Cartesian components of every stored G, [3][npw]
 void launch_gcart(Ctx& c, double* gcart);
@@ -403,7 +409,8 @@ void gemm_small2(Ctx& c, int M, int N, int K, const double* A, const double* A2,
                  double beta, double diag);
 void band_dots(Ctx& c, const double2* X, const double2* Y, int nvec, int mode, double* out);
 // both weightings in one pass: out0 plain, out1 |G|^2/2 (either may be null)
-void band_dots2(Ctx& c, const double2* X, const double2* Y, int nvec, double* out0, double* out1);
+void band_dots2(Ctx& c, const double2* X, const double2* Y, int nvec, double* out0, double* out1,
+                double* mirror0 = nullptr, double* mirror1 = nullptr);
 void axpby(Ctx& c, size_t n, double a, const double* x, double b, const double* y, double* out);
 void cholesky_inverse(Ctx& c, const double* G, int n, double* Linv, int32_t* flag);
 void set_identity(Ctx& c, double* A, int n, double diag);

@@ -3,10 +3,11 @@
 // matrices, the projected Teter preconditioner, Fletcher-Reeves directions,
 // the line search over Cholesky-orthonormalised and rotated trial orbitals,
 // and the Hellmann-Feynman forces.  Scalars that steer control flow (energies,
-// directional derivatives) are copied to the host; everything else stays on
-// the GPU.
+// directional derivatives) are written by the kernels into pinned host memory;
+// everything else stays on the GPU.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "roks_internal.h"
 
@@ -20,11 +21,6 @@ constexpr int kHalvings = 4;
 void to_host(Ctx& c, void* dst, const void* src, size_t bytes) {
   ROKS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c.stream));
   ROKS_HIP(hipStreamSynchronize(c.stream));
-}
-
-// stream-ordered copy into pinned host memory; read it after sync()
-void fetch(Ctx& c, void* dst, const void* src, size_t bytes) {
-  ROKS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c.stream));
 }
 
 void sync(Ctx& c) { ROKS_HIP(hipStreamSynchronize(c.stream)); }
@@ -158,7 +154,7 @@ void evaluate_trial(Ctx& c, double delta, Trial& t, bool energy_only) {
 // ---------------------------------------------------------------------------
 // densities, potentials and energies of `orb` (Sec. II A, H^{sigma L})
 // ---------------------------------------------------------------------------
-// every launch of the energy evaluation; the reduced sums are copied to the
+// every launch of the energy evaluation; the reduced sums also land in the
 // pinned mirror h_scal, read by assemble_energies after a synchronisation
 void compute_potentials_async(Ctx& c, const double2* orb, bool have_P, bool energy_only) {
   const int nb = c.nb, K = 2 * c.npw;
@@ -171,26 +167,24 @@ void compute_potentials_async(Ctx& c, const double2* orb, bool have_P, bool ener
     // xc and external sums without writing any potential
     launch_hartree_energy(c, c.d_part + 6 * (size_t)nblk, nblk);
     launch_xc_energy(c, c.d_part, nblk);
-    launch_reduce_columns(c, c.d_part, nblk, 6, c.d_red);
-    launch_reduce_columns(c, c.d_part + 6 * (size_t)nblk, nblk, 2, c.d_red + 6);
+    launch_reduce_columns(c, c.d_part, nblk, 6, c.d_red, c.hd_scal);
+    launch_reduce_columns(c, c.d_part + 6 * (size_t)nblk, nblk, 2, c.d_red + 6, c.hd_scal + 6);
   } else {
     launch_hartree(c);
     launch_xc_potentials(c, c.d_part, nblk);
-    launch_reduce_columns(c, c.d_part, nblk, 6, c.d_red);
+    launch_reduce_columns(c, c.d_part, nblk, 6, c.d_red, c.hd_scal);
   }
   if (c.prec == ROKS_FP32 && !energy_only) {
     // the plane passes of the FP32 tier read FP32 copies of the potentials
     launch_to_float(c, c.d_vsh, c.d_vsh32, (size_t)c.nsocc * c.ntot);
     launch_to_float(c, c.d_vloc, c.d_vloc32, (size_t)2 * c.nconf * c.ntot);
   }
-  band_dots(c, orb, orb, nb, 1, c.d_kin);
+  band_dots2(c, orb, orb, nb, nullptr, c.d_kin, nullptr, c.hd_scal + 16);
+  // (without projectors d_enl and its mirror hold the zeros set at creation)
   if (c.nproj > 0) {
     if (!have_P) gemm_wdot(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(orb), K, c.d_P, nb, 1.0, 0.0, true);
-    launch_nl_energy(c, c.d_P, c.d_enl);
-  } else {
-    ROKS_HIP(hipMemsetAsync(c.d_enl, 0, nb * sizeof(double), c.stream));
+    launch_nl_energy(c, c.d_P, c.d_enl, c.hd_scal + 16 + nb);
   }
-  fetch(c, c.h_scal, c.d_scal, (16 + 2 * (size_t)nb) * sizeof(double));
 }
 
 roks_energies assemble_energies(const Ctx& c, bool energy_only) {
@@ -320,9 +314,17 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   energy_gradient(c, &e0);
   const double E0 = e0.E;
 
+  // step scalars, written by the kernels straight into the pinned mirror
+  // (read after a synchronisation): [0] sum A (theta - theta^T), [1] the same
+  // for D, [2] max open-shell coupling, [kStage + n] <p_n|g_n>,
+  // [kStage + nb + n] <g_n|g_n>, [kStage + 2 nb + n] <S_n|g_n>; sums over
+  // bands in band order
+  double* st = c.hd_stage;
+  const double* hs = c.h_stage;
+
   // preconditioned out-of-subspace gradient p = (1 - P) K g_I; with a
   // network attached K carries the learned factor of (band, |G|^2 shell)
-  band_dots2(c, c.d_gI, c.d_gI, nb, c.d_bandv + nb, c.d_bandv);
+  band_dots2(c, c.d_gI, c.d_gI, nb, c.d_bandv + nb, c.d_bandv, st + kStage + nb, nullptr);
   const bool recording = c.rec_max > 0 && c.rec_count < c.rec_max &&
                          (c.iteration % std::max(1, c.rec_stride)) == 0;
   if (c.mlp || recording) {
@@ -331,13 +333,6 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   }
   if (recording) record_iterate(c, c.d_bandv, c.d_bandv + nb, c.d_bandv + 4 * nb);
   const double* bandw = (c.flags & ROKS_FLAG_WEIGHT_PRECOND) ? c.d_kinw_shell : nullptr;
-  // step scalars, written by the kernels straight into the pinned mirror
-  // (read after a synchronisation): [0] sum A (theta - theta^T), [1] the same
-  // for D, [2] max open-shell coupling, [kStage + n] <p_n|g_n>,
-  // [kStage + nb + n] <g_n|g_n>, [kStage + 2 nb + n] <S_n|g_n>; sums over
-  // bands in band order
-  double* st = c.hd_stage;
-  const double* hs = c.h_stage;
   auto band_sum = [&](int off) {
     double v = 0.0;
     for (int n = 0; n < nb; ++n) v += hs[kStage + off + n];
@@ -358,12 +353,8 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     // <p|g> = sum <p_I|g_I> + 1/2 sum A (theta - theta^T)
     launch_asym_dot(c, c.d_A, c.d_theta, st);
     band_dots(c, c.d_p, c.d_gI, nb, 0, st + kStage);
-    if (first_fetch) {
-      // with the report's |g_I| and open-shell coupling
-      ROKS_HIP(hipMemcpyAsync(st + kStage + nb, c.d_bandv + nb, nb * sizeof(double), hipMemcpyDefault,
-                              c.stream));
-      if (no == 2) launch_open_coupling(c, opens[0], opens[1], st + 2);
-    }
+    // with the report's open-shell coupling
+    if (first_fetch && no == 2) launch_open_coupling(c, opens[0], opens[1], st + 2);
     sync(c);
     first_fetch = false;
     return band_sum(0) + 0.5 * hs[0];
@@ -542,8 +533,8 @@ void forces(Ctx& c, double* f_host) {
   }
   ROKS_HIP(hipEventRecord(c.ev_join, c.side));
   // nonlocal part on the main stream: 2 sum_n w_n <d beta_i|n> (D P)_in
-  // (P = <beta|psi> is current: the energy evaluation of these orbitals left it)
-  ROKS_HIP(hipMemsetAsync(c.d_force, 0, 3 * (size_t)nat * sizeof(double), c.stream));
+  // (P = <beta|psi> is current: the energy evaluation of these orbitals left it);
+  // the last kernel also adds the local part and negates, F = -dE/dR
   if (c.nproj > 0) {
     if (!c.d_gcart) {
       c.d_gcart = dalloc<double>(c, 3 * (size_t)c.npw);
@@ -553,12 +544,16 @@ void forces(Ctx& c, double* f_host) {
     launch_apply_D(c, c.d_P, nullptr, c.d_DP);
     // <d_a beta_i|n> from the projector table, -i G_a applied on the fly
     gemm_wdot_deriv(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(c.d_psi), K, c.d_gcart, c.d_dP3, nb);
-    launch_nl_force(c, c.d_dP3, c.d_DP, c.d_kinw_shell, c.d_force);
+    ROKS_HIP(hipStreamWaitEvent(c.stream, c.ev_join, 0));
+    // straight into the pinned host mirror
+    launch_nl_force(c, c.d_dP3, c.d_DP, c.d_kinw_shell, c.d_force_loc, c.hd_force);
+    sync(c);
+    std::memcpy(f_host, c.h_force, 3 * (size_t)nat * sizeof(double));
+  } else {
+    ROKS_HIP(hipStreamWaitEvent(c.stream, c.ev_join, 0));
+    axpby(c, 3 * (size_t)nat, -1.0, c.d_force_loc, 0.0, c.d_force_loc, c.d_force);
+    to_host(c, f_host, c.d_force, 3 * (size_t)nat * sizeof(double));
   }
-  // F = -dE/dR
-  ROKS_HIP(hipStreamWaitEvent(c.stream, c.ev_join, 0));
-  axpby(c, 3 * (size_t)nat, -1.0, c.d_force_loc, -1.0, c.d_force, c.d_force);
-  to_host(c, f_host, c.d_force, 3 * (size_t)nat * sizeof(double));
 }
 
 }  // namespace roks
