@@ -654,6 +654,43 @@ __global__ void __launch_bounds__(256) k_fft_axis(double2* __restrict__ data, Ff
   }
 }
 
+// x and y transforms of whole z-planes of [z][x][y] data in one pass: a
+// workgroup loads plane blockIdx.x (contiguous) into LDS with row stride PS,
+// transforms its y lines and x lines (y first when yfirst, else x first) and
+// writes it back.  Per line the same butterflies as the axis passes.
+template <int MAXP, int RS>
+__global__ void __launch_bounds__(512) k_fft_plane(double2* __restrict__ data, FftPlan1D px,
+                                                   FftPlan1D py, const double2* __restrict__ twx,
+                                                   const double2* __restrict__ twy, int PS, int sign,
+                                                   int yfirst) {
+  extern __shared__ char smem_raw[];
+  double2* smem = reinterpret_cast<double2*>(smem_raw);
+  const int N0 = px.n, N1 = py.n, np2 = N0 * N1;
+  double2* tx = smem;
+  double2* ty = smem + N0;
+  double2* plane = smem + N0 + N1;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  double2* base = data + (size_t)blockIdx.x * np2;
+  for (int i = tid; i < N0; i += nthr) tx[i] = twx[i];
+  for (int i = tid; i < N1; i += nthr) ty[i] = twy[i];
+  for (int p = tid; p < np2; p += nthr) {
+    const int x = p / N1, y = p - x * N1;
+    plane[x * PS + y] = base[p];
+  }
+  __syncthreads();
+  if (yfirst) {
+    fft_lines<double, MAXP, RS>(plane, py, N0, Strided{PS}, 1, ty, sign);
+    fft_lines<double, MAXP, RS>(plane, px, N1, Strided{1}, PS, tx, sign);
+  } else {
+    fft_lines<double, MAXP, RS>(plane, px, N1, Strided{1}, PS, tx, sign);
+    fft_lines<double, MAXP, RS>(plane, py, N0, Strided{PS}, 1, ty, sign);
+  }
+  for (int p = tid; p < np2; p += nthr) {
+    const int x = p / N1, y = p - x * N1;
+    base[p] = plane[x * PS + y];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------
@@ -905,18 +942,56 @@ static void fft_axis_pass(Ctx& c, double2* data, int sign, int axis, bool hartre
   ROKS_DISPATCH_MAXP(double, mp, radix_set(c.plan[axis]), run_fft_axis, c, data, sign, axis, hartree);
 }
 
+constexpr int kPlaneFftThreads = 512;
+
+size_t fft_plane_lds(const Ctx& c) {
+  return (size_t)(c.N[0] + c.N[1] + c.N[0] * plane_stride(c)) * sizeof(double2);
+}
+
+// the x-y plane fits the LDS of one workgroup (160 KiB) and needs at most 16
+// points per thread (larger counts spill registers in the general-radix build,
+// and two axis passes are then faster)
+bool fft_plane_fits(const Ctx& c) {
+  return fft_plane_lds(c) <= 160 * 1024 &&
+         needed_points(c.N[0] * c.N[1], kPlaneFftThreads) <= 16;
+}
+
+template <typename R, int MP, int RS>
+static void run_fft_plane(Ctx& c, double2* data, int sign, bool yfirst) {
+  const size_t lds = fft_plane_lds(c);
+  allow_lds(k_fft_plane<MP, RS>, lds);
+  hipLaunchKernelGGL((k_fft_plane<MP, RS>), dim3(c.N[2]), dim3(kPlaneFftThreads), lds, c.stream, data,
+                     c.plan[0], c.plan[1], c.d_tw[0], c.d_tw[1], plane_stride(c), sign, yfirst ? 1 : 0);
+  ROKS_HIP(hipGetLastError());
+}
+
+// y and x transforms of the full grid: one plane pass when the plane fits the
+// LDS, else two axis passes (same order of the axes either way)
+static void fft_xy_pass(Ctx& c, double2* data, int sign, bool yfirst) {
+  if (fft_plane_fits(c)) {
+    const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], kPlaneFftThreads));
+    ROKS_DISPATCH_MAXP(double, mp, radix_set(c.plan[0], c.plan[1]), run_fft_plane, c, data, sign,
+                       yfirst);
+    return;
+  }
+  fft_axis_pass(c, data, sign, yfirst ? 1 : 0, false);
+  fft_axis_pass(c, data, sign, yfirst ? 0 : 1, false);
+}
+
+// bytes moved: every pass reads and writes the grid once
 void launch_fft3d(Ctx& c, double2* data, int sign) {
-  KernelTimer kt(c, "fft3d", 6.0 * c.ntot * sizeof(double2));
-  for (int axis : {1, 0, 2}) fft_axis_pass(c, data, sign, axis, false);
+  const int passes = fft_plane_fits(c) ? 2 : 3;
+  KernelTimer kt(c, "fft3d", 2.0 * passes * c.ntot * sizeof(double2));
+  fft_xy_pass(c, data, sign, true);
+  fft_axis_pass(c, data, sign, 2, false);
 }
 
 void launch_hartree_fft(Ctx& c, double2* data) {
-  KernelTimer kt(c, "fft3d", 10.0 * c.ntot * sizeof(double2));
-  fft_axis_pass(c, data, -1, 1, false);
-  fft_axis_pass(c, data, -1, 0, false);
+  const int passes = fft_plane_fits(c) ? 3 : 5;
+  KernelTimer kt(c, "fft3d", 2.0 * passes * c.ntot * sizeof(double2));
+  fft_xy_pass(c, data, -1, true);
   fft_axis_pass(c, data, -1, 2, true);
-  fft_axis_pass(c, data, +1, 0, false);
-  fft_axis_pass(c, data, +1, 1, false);
+  fft_xy_pass(c, data, +1, false);
 }
 
 }  // namespace roks

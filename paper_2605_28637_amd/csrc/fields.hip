@@ -183,6 +183,7 @@ __global__ void k_gcart(Lattice L, const int32_t* __restrict__ miller, int npw, 
 // ---------------------------------------------------------------------------
 struct ShellArgs {
   int nconf, nsocc, xc;
+  int same_rho;  // every configuration has the same total occupation of each shell
   double f[3][kMaxConf][2];
   double cL[kMaxConf];
 };
@@ -282,19 +283,52 @@ __global__ void k_unpack_vh(const double2* __restrict__ f, size_t ntot, int ncon
 // ---------------------------------------------------------------------------
 // spin LDA: Slater exchange + Perdew-Wang 1992 correlation
 // ---------------------------------------------------------------------------
-__device__ void pw92_G(double rs, double srs, double A, double a1, double b1, double b2, double b3,
-                       double b4, double* G, double* dG) {
+template <bool DERIV>
+__device__ void pw92_G(double rs, double srs, double isrs, double A, double a1, double b1, double b2,
+                       double b3, double b4, double* G, double* dG) {
   const double Q = 2.0 * A * (b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs);
-  const double dQ = 2.0 * A * (0.5 * b1 / srs + b2 + 1.5 * b3 * srs + 2.0 * b4 * rs);
   const double lg = log1p(1.0 / Q);
   *G = -2.0 * A * (1.0 + a1 * rs) * lg;
-  *dG = -2.0 * A * a1 * lg + 2.0 * A * (1.0 + a1 * rs) * dQ / (Q * Q + Q);
+  if (DERIV) {
+    const double dQ = 2.0 * A * (0.5 * b1 * isrs + b2 + 1.5 * b3 * srs + 2.0 * b4 * rs);
+    *dG = -2.0 * A * a1 * lg + 2.0 * A * (1.0 + a1 * rs) * dQ / (Q * Q + Q);
+  }
 }
 
-__device__ void lda_point(double ru, double rd, int kind, double* e, double* vu, double* vd) {
-  ru = fmax(ru, 0.0);
-  rd = fmax(rd, 0.0);
-  const double rho = ru + rd;
+// The parts of a spin-LDA point that depend on the total density only: rho^(1/3)
+// and the three PW92 G functions of r_s (with their r_s derivatives for the
+// potentials).  Configurations with the same total density share them.
+struct LdaRho {
+  double rho, crho, rs, ec0, dec0, ec1, dec1, ac, dac;
+};
+
+// (6/pi)^(1/3), 2^(-1/3), (3/(4 pi))^(1/3), 2^(4/3) - 2
+constexpr double kCx = 1.2407009817988, kCbrtHalf = 0.7937005259840998;
+constexpr double kRsCoef = 0.6203504908994, kFzDen = 0.5198420997897464;
+
+template <bool DERIV>
+__device__ void lda_rho(double rho, int kind, LdaRho* r) {
+  r->rho = rho;
+  if (rho < 1e-12) return;
+  r->crho = cbrt(rho);
+  if (kind == ROKS_XC_X) return;
+  const double rs = kRsCoef / r->crho;
+  const double srs = sqrt(rs), isrs = DERIV ? 1.0 / srs : 0.0;
+  r->rs = rs;
+  double mac, dmac = 0.0;
+  pw92_G<DERIV>(rs, srs, isrs, 0.031091, 0.21370, 7.5957, 3.5876, 1.6382, 0.49294, &r->ec0, &r->dec0);
+  pw92_G<DERIV>(rs, srs, isrs, 0.015545, 0.20548, 14.1189, 6.1977, 3.3662, 0.62517, &r->ec1, &r->dec1);
+  pw92_G<DERIV>(rs, srs, isrs, 0.016887, 0.11125, 10.357, 3.6231, 0.88026, 0.49671, &mac, &dmac);
+  r->ac = -mac;
+  r->dac = -dmac;
+}
+
+// energy density e and (DERIV) potentials of spin densities (ru, rd) whose sum
+// is r.rho: Slater exchange + PW92 correlation, spin interpolation f(zeta)
+template <bool DERIV>
+__device__ void lda_spin(double ru, double rd, const LdaRho& r, int kind, double* e, double* vu,
+                         double* vd) {
+  const double rho = r.rho;
   if (rho < 1e-12) {
     *e = 0.0;
     *vu = 0.0;
@@ -302,53 +336,49 @@ __device__ void lda_point(double ru, double rd, int kind, double* e, double* vu,
     return;
   }
   const double third = 1.0 / 3.0;
-  const double cx = cbrt(6.0 / M_PI);
-  // three cube roots: rho, 1 + z, 1 - z; rho_up,down = rho (1 +- z) / 2 and
-  // rs = (3 / (4 pi))^(1/3) / rho^(1/3)
+  // rho_up,down = rho (1 +- z) / 2, so (rho_up,down)^(1/3) = rho^(1/3) 2^(-1/3) (1 +- z)^(1/3)
   double z = (ru - rd) / rho;
   z = fmin(1.0, fmax(-1.0, z));
   const double opz = 1.0 + z, omz = 1.0 - z;
-  const double crho = cbrt(rho), copz = cbrt(opz), comz = cbrt(omz);
-  const double ch = crho * cbrt(0.5);
+  const double copz = cbrt(opz), comz = cbrt(omz);
+  const double ch = r.crho * kCbrtHalf;
   const double cu = ch * copz, cd = ch * comz;
-  double ex = -0.75 * cx * (ru * cu + rd * cd);
-  double vxu = -cx * cu, vxd = -cx * cd;
+  const double ex = -0.75 * kCx * (ru * cu + rd * cd);
+  const double vxu = -kCx * cu, vxd = -kCx * cd;
   if (kind == ROKS_XC_X) {
     *e = ex;
     *vu = vxu;
     *vd = vxd;
     return;
   }
-  const double rs = cbrt(3.0 / (4.0 * M_PI)) / crho;
-  const double srs = sqrt(rs);
-  double ec0, dec0, ec1, dec1, mac, dmac;
-  pw92_G(rs, srs, 0.031091, 0.21370, 7.5957, 3.5876, 1.6382, 0.49294, &ec0, &dec0);
-  pw92_G(rs, srs, 0.015545, 0.20548, 14.1189, 6.1977, 3.3662, 0.62517, &ec1, &dec1);
-  pw92_G(rs, srs, 0.016887, 0.11125, 10.357, 3.6231, 0.88026, 0.49671, &mac, &dmac);
-  const double ac = -mac, dac = -dmac;
   const double fz20 = 1.709921;
-  const double den = exp2(4.0 * third) - 2.0;
-  const double f = (opz * copz + omz * comz - 2.0) / den;
-  const double fp = (4.0 * third) * (copz - comz) / den;
+  const double f = (opz * copz + omz * comz - 2.0) / kFzDen;
   const double z3 = z * z * z, z4 = z3 * z;
+  const double ec0 = r.ec0, ec1 = r.ec1, ac = r.ac;
   const double eps = ec0 + ac * f / fz20 * (1.0 - z4) + (ec1 - ec0) * f * z4;
-  const double deps_rs = dec0 + dac * f / fz20 * (1.0 - z4) + (dec1 - dec0) * f * z4;
-  const double deps_z =
-      4.0 * z3 * f * (ec1 - ec0 - ac / fz20) + fp * (z4 * (ec1 - ec0) + (1.0 - z4) * ac / fz20);
-  const double common = eps - rs * third * deps_rs;
   *e = ex + rho * eps;
-  *vu = vxu + common + (1.0 - z) * deps_z;
-  *vd = vxd + common - (1.0 + z) * deps_z;
+  if (DERIV) {
+    const double fp = (4.0 * third) * (copz - comz) / kFzDen;
+    const double deps_rs = r.dec0 + r.dac * f / fz20 * (1.0 - z4) + (r.dec1 - r.dec0) * f * z4;
+    const double deps_z =
+        4.0 * z3 * f * (ec1 - ec0 - ac / fz20) + fp * (z4 * (ec1 - ec0) + (1.0 - z4) * ac / fz20);
+    const double common = eps - r.rs * third * deps_rs;
+    *vu = vxu + common + (1.0 - z) * deps_z;
+    *vd = vxd + common - (1.0 + z) * deps_z;
+  }
 }
 
 // per point: configuration spin densities, LDA, V_loc^{sigma L}, shell potentials
-// V^X = sum c_L f_X V_loc^{sigma L}; partial sums of e_xc, V_ext rho, V_H rho per L
-// write = 0: energy sums only (xc and external; no V_H read, no potentials)
+// V^X = sum c_L f_X V_loc^{sigma L}; partial sums of e_xc, V_ext rho, V_H rho per L.
+// WRITE = false: energy sums only (xc and external; no V_H read, no potentials,
+// no derivatives).  With a.same_rho every configuration has the total density
+// of configuration 0 and shares its r_s part.
+template <bool WRITE>
 __global__ void __launch_bounds__(256) k_xc(ShellArgs a, const double* __restrict__ rho,
                                             const double* __restrict__ vext,
                                             const double* __restrict__ vh, size_t ntot,
                                             double* __restrict__ vloc, double* __restrict__ vsh,
-                                            double* __restrict__ part, int write) {
+                                            double* __restrict__ part) {
   __shared__ double red[8 * 16];
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
@@ -357,17 +387,21 @@ __global__ void __launch_bounds__(256) k_xc(ShellArgs a, const double* __restric
     for (int X = 0; X < a.nsocc; ++X) rX[X] = rho[(size_t)X * ntot + i];
     const double ve = vext[i];
     double vl[kMaxConf][2];
+    LdaRho lr;
     for (int L = 0; L < a.nconf; ++L) {
       double ru = 0, rd = 0;
       for (int X = 0; X < a.nsocc; ++X) {
         ru += a.f[X][L][0] * rX[X];
         rd += a.f[X][L][1] * rX[X];
       }
+      ru = fmax(ru, 0.0);
+      rd = fmax(rd, 0.0);
+      if (L == 0 || !a.same_rho) lda_rho<WRITE>(ru + rd, a.xc, &lr);
       double e, vu, vd;
-      lda_point(ru, rd, a.xc, &e, &vu, &vd);
+      lda_spin<WRITE>(ru, rd, lr, a.xc, &e, &vu, &vd);
       acc[3 * L + 0] += e;
       acc[3 * L + 1] += ve * (ru + rd);
-      if (!write) continue;
+      if (!WRITE) continue;
       const double h = vh[(size_t)L * ntot + i];
       vl[L][0] = ve + h + vu;
       vl[L][1] = ve + h + vd;
@@ -375,7 +409,7 @@ __global__ void __launch_bounds__(256) k_xc(ShellArgs a, const double* __restric
       vloc[(size_t)(2 * L + 1) * ntot + i] = vl[L][1];
       acc[3 * L + 2] += h * (ru + rd);
     }
-    if (!write) continue;
+    if (!WRITE) continue;
     for (int X = 0; X < a.nsocc; ++X) {
       double s = 0;
       for (int L = 0; L < a.nconf; ++L)
@@ -567,6 +601,10 @@ ShellArgs shell_args(const Ctx& c) {
     for (int L = 0; L < kMaxConf; ++L)
       for (int s = 0; s < 2; ++s) a.f[X][L][s] = X < c.nsocc && L < c.nconf ? c.shell_f[X][L][s] : 0.0;
   for (int L = 0; L < kMaxConf; ++L) a.cL[L] = c.cL[L];
+  a.same_rho = 1;
+  for (int X = 0; X < c.nsocc; ++X)
+    for (int L = 1; L < c.nconf; ++L)
+      if (a.f[X][L][0] + a.f[X][L][1] != a.f[X][0][0] + a.f[X][0][1]) a.same_rho = 0;
   return a;
 }
 
@@ -656,14 +694,14 @@ int xc_blocks(const Ctx& c) {
 void launch_xc_potentials(Ctx& c, double* part, int nblocks) {
   // reads shell densities, V_ext, V_H; writes V_loc and the shell potentials
   KernelTimer kt(c, "xc", (double)(2 * c.nsocc + 1 + 3 * c.nconf) * c.ntot * sizeof(double));
-  hipLaunchKernelGGL(k_xc, dim3(nblocks), dim3(256), 0, c.stream, shell_args(c), c.d_rho, c.d_vext,
-                     c.d_vh, (size_t)c.ntot, c.d_vloc, c.d_vsh, part, 1);
+  hipLaunchKernelGGL(k_xc<true>, dim3(nblocks), dim3(256), 0, c.stream, shell_args(c), c.d_rho,
+                     c.d_vext, c.d_vh, (size_t)c.ntot, c.d_vloc, c.d_vsh, part);
   ROKS_HIP(hipGetLastError());
 }
 
 void launch_xc_energy(Ctx& c, double* part, int nblocks) {
-  hipLaunchKernelGGL(k_xc, dim3(nblocks), dim3(256), 0, c.stream, shell_args(c), c.d_rho, c.d_vext,
-                     c.d_vh, (size_t)c.ntot, c.d_vloc, c.d_vsh, part, 0);
+  hipLaunchKernelGGL(k_xc<false>, dim3(nblocks), dim3(256), 0, c.stream, shell_args(c), c.d_rho,
+                     c.d_vext, c.d_vh, (size_t)c.ntot, c.d_vloc, c.d_vsh, part);
   ROKS_HIP(hipGetLastError());
 }
 

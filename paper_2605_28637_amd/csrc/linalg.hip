@@ -316,9 +316,9 @@ __device__ void cholesky_lds_body(const double* __restrict__ G, double ga, doubl
   __shared__ double piv[2][2];    // [step parity]: 1/d, 1/sqrt(d)
   __shared__ double rsv[128];     // 1/L_jj
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int tx = tid & 31, ty = tid >> 5, ny = nthr >> 5;
   const int ld = chol_ld(n);  // odd row stride: a column read by a warp of rows spreads the banks
   double* X = A + n * ld;
+#pragma unroll 4
   for (int t = tid; t < n * n; t += nthr) {
     const int r = t / n, q = t - r * n;
     const double g = ga * G[t] + (r == q ? gd : 0.0);  // the matrix factorised: ga G + gd I
@@ -336,25 +336,43 @@ __device__ void cholesky_lds_body(const double* __restrict__ G, double ga, doubl
     piv[j & 1][1] = rs;
     rsv[j] = rs;
   };
-  if (tid == 0) {
+  // the last group of 32 threads stays off the trailing update: its first
+  // thread computes the next pivot as soon as a column starts (the critical
+  // path of the column), the others scale the finished row of the inverse
+  const int pivt = nthr - 32;
+  __syncthreads();  // gdiag, read by the pivot thread, is written by others
+  if (tid == pivt) {
     bad = 0;
     pivot(0, ga * G[0] + gd);
   }
   __syncthreads();
   for (int j = 0; j < n; ++j) {
     const double rd = piv[j & 1][0];
-    // the previous row of the inverse is final: scale it
-    if (inv_in_lds && j > 0)
-      for (int cc = tid; cc < j; cc += nthr) X[(j - 1) * ld + cc] *= rsv[j - 1];
-    for (int i = j + 1 + ty; i < n; i += ny) {
-      const double f = A[i * ld + j] * rd;
-      for (int k = j + 1 + tx; k <= i; k += 32) {
-        const double v = A[i * ld + k] - f * A[k * ld + j];
-        A[i * ld + k] = v;
-        if (i == j + 1 && k == j + 1) pivot(j + 1, v);  // thread 0
+    if (tid >= pivt) {
+      if (tid == pivt) {
+        if (j + 1 < n) {
+          // the update of element (j+1, j+1), as the update threads would do it
+          const double a = A[(j + 1) * ld + j];
+          const double f = a * rd;
+          const double v = A[(j + 1) * ld + j + 1] - f * a;
+          A[(j + 1) * ld + j + 1] = v;
+          pivot(j + 1, v);
+        }
+      } else if (inv_in_lds && j > 0) {
+        // the previous row of the inverse is final: scale it
+        for (int cc = tid - pivt - 1; cc < j; cc += 31) X[(j - 1) * ld + cc] *= rsv[j - 1];
       }
-      if (inv_in_lds)
-        for (int cc = tx; cc <= j; cc += 32) X[i * ld + cc] -= f * X[j * ld + cc];
+    } else {
+      const int tx = tid & 31, ty = tid >> 5, nyu = pivt >> 5;
+      for (int i = j + 1 + ty; i < n; i += nyu) {
+        const double f = A[i * ld + j] * rd;
+        for (int k = j + 1 + tx; k <= i; k += 32) {
+          if (i == j + 1 && k == j + 1) continue;  // the pivot thread's
+          A[i * ld + k] = A[i * ld + k] - f * A[k * ld + j];
+        }
+        if (inv_in_lds)
+          for (int cc = tx; cc <= j; cc += 32) X[i * ld + cc] -= f * X[j * ld + cc];
+      }
     }
     __syncthreads();
   }
@@ -408,13 +426,24 @@ __device__ void expm_lds_body(const double* __restrict__ D, int n, double delta,
   double* X = S;
   double* P = S + nn;
   double* Q = P + nn;
+#pragma unroll 4
   for (int t = tid; t < nn; t += nthr) X[t] = delta * D[t];
+  __syncthreads();
+  // column sums of |X|: C row-interleaved partial sums per column (kept in P,
+  // which is not yet in use), then one wave adds them and takes the maximum
+  const int C = n < 16 ? n : 16;
+  for (int t = tid; t < C * n; t += nthr) {
+    const int c = t / n, j = t - c * n;
+    double s = 0.0;
+    for (int i = c; i < n; i += C) s += fabs(X[i * n + j]);
+    P[c * n + j] = s;
+  }
   __syncthreads();
   if (tid < 64) {
     double mx = 0.0;
     for (int j = tid; j < n; j += 64) {
       double s = 0.0;
-      for (int i = 0; i < n; ++i) s += fabs(X[i * n + j]);
+      for (int c = 0; c < C; ++c) s += P[c * n + j];
       mx = fmax(mx, s);
     }
 #pragma unroll
