@@ -217,7 +217,11 @@ roks_status roks_subspace(roks_ctx ctx, double* R, double* kappa, double* A);
 
 /* One preconditioned CG iteration with line search (Eqs. orbital_update,
  * cg_search, prec_grad_I, prec_k and the conjugated rotation
- * U = exp(Delta (A^i + gamma A^{i-1}))). */
+ * U = exp(Delta (A^i + gamma A^{i-1}))).  info is complete on return; the
+ * update of the carried directions (S_old, D_old) may still run on the
+ * context's stream, ordered before the work of every later call (an
+ * exception to the synchronisation rule above: nothing the caller can read
+ * depends on it). */
 roks_status roks_pcg_step(roks_ctx ctx, roks_step_info* info);
 /* Forget the carried search directions (next step is steepest descent). */
 roks_status roks_reset_cg(roks_ctx ctx);

@@ -303,6 +303,7 @@ roks_status roks_solve(roks_ctx ctx, double tol, int32_t maxiter, roks_step_info
       hits = std::fabs(info.E1 - info.E0) < tol ? hits + 1 : 0;
       if (hits >= 2) break;
     }
+    ROKS_HIP(hipStreamSynchronize(c.stream));
     if (last) *last = info;
     if (iterations) *iterations = it;
   });

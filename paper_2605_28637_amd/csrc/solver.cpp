@@ -161,6 +161,20 @@ void compute_potentials_async(Ctx& c, const double2* orb, bool have_P, bool ener
   launch_zpass_bwd(c, orb, nb, c.d_T, c.npairs);
   launch_plane_density(c, c.d_T, c.npairs, c.d_rho_part, c.nchunk);
   launch_density_reduce(c, c.d_rho_part, c.nchunk, c.d_rho);
+  // with the projections at hand, the band kinetic and nonlocal energies run
+  // on the side stream beside the Hartree and xc chain (they need neither)
+  const bool side = have_P;
+  if (side) {
+    ensure_side_stream(c);
+    ROKS_HIP(hipEventRecord(c.ev_fork, c.stream));
+    ROKS_HIP(hipStreamWaitEvent(c.side, c.ev_fork, 0));
+    const hipStream_t main = c.stream;
+    c.stream = c.side;
+    band_dots2(c, orb, orb, nb, nullptr, c.d_kin, nullptr, c.hd_scal + 16);
+    if (c.nproj > 0) launch_nl_energy(c, c.d_P, c.d_enl, c.hd_scal + 16 + nb);
+    c.stream = main;
+    ROKS_HIP(hipEventRecord(c.ev_join, c.side));
+  }
   const int nblk = xc_blocks(c);
   if (energy_only) {
     // energies only: the Hartree integrals from the forward transform, the
@@ -179,10 +193,14 @@ void compute_potentials_async(Ctx& c, const double2* orb, bool have_P, bool ener
     launch_to_float(c, c.d_vsh, c.d_vsh32, (size_t)c.nsocc * c.ntot);
     launch_to_float(c, c.d_vloc, c.d_vloc32, (size_t)2 * c.nconf * c.ntot);
   }
-  band_dots2(c, orb, orb, nb, nullptr, c.d_kin, nullptr, c.hd_scal + 16);
   // (without projectors d_enl and its mirror hold the zeros set at creation)
+  if (side) {
+    ROKS_HIP(hipStreamWaitEvent(c.stream, c.ev_join, 0));
+    return;
+  }
+  band_dots2(c, orb, orb, nb, nullptr, c.d_kin, nullptr, c.hd_scal + 16);
   if (c.nproj > 0) {
-    if (!have_P) gemm_wdot(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(orb), K, c.d_P, nb, 1.0, 0.0, true);
+    gemm_wdot(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(orb), K, c.d_P, nb, 1.0, 0.0, true);
     launch_nl_energy(c, c.d_P, c.d_enl, c.hd_scal + 16 + nb);
   }
 }
@@ -488,7 +506,8 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   // orbitals (the same kernels on the same values), so they are kept
   c.potentials_valid = (best == 1);
   if (best == 1) c.last_e = t.e;
-  sync(c);
+  // no synchronisation: the updates above are stream-ordered before the next
+  // call's work, and info holds host values only
   if (info) *info = r;
 }
 
