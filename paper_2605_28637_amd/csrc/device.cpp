@@ -131,6 +131,7 @@ void init_device(Ctx& c, void* stream) {
   c.d_Qpart = dalloc<double>(c, (size_t)c.npairs * c.N[2] * 2 * c.nsocc);
   c.d_Q = dalloc<double>(c, 2 * (size_t)c.npairs * c.nsocc);
   c.d_bandv = dalloc<double>(c, 8 * nb);
+  c.d_cg = dalloc<double>(c, 8 + nb);
   const size_t nn = nb * nb;
   double** mats[] = {&c.d_theta, &c.d_R, &c.d_kappa, &c.d_A, &c.d_D, &c.d_Dold, &c.d_gram,
                      &c.d_Linv, &c.d_U, &c.d_M, &c.d_m1, &c.d_m2, &c.d_m3, &c.d_Mkeep,

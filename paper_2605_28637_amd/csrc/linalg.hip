@@ -618,7 +618,7 @@ __global__ void k_subspace(SubArgs a, const double* __restrict__ theta,
 
 // sum_mn A_mn (theta_mn - theta_nm), one workgroup
 __global__ void k_asym_dot(const double* __restrict__ A, const double* __restrict__ th, int nb,
-                           double* __restrict__ out) {
+                           double* __restrict__ out, double* __restrict__ mirror) {
   __shared__ double red[16];
   double s = 0.0;
   for (size_t t = threadIdx.x; t < (size_t)nb * nb; t += blockDim.x) {
@@ -632,6 +632,31 @@ __global__ void k_asym_dot(const double* __restrict__ A, const double* __restric
     double v = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w];
     *out = v;
+    if (mirror) *mirror = v;
+  }
+}
+
+// Fletcher-Reeves ratio on the device: pg = sum_n pgb[n] (band order) + asym / 2,
+// beta = pg / pg_old (the host forms the same sums from the mirrored values)
+__global__ void k_cg_beta(const double* __restrict__ asym, const double* __restrict__ pgb, int nb,
+                          double pg_old, double* __restrict__ beta) {
+  if (threadIdx.x != 0) return;
+  double v = 0.0;
+  for (int n = 0; n < nb; ++n) v += pgb[n];
+  v += 0.5 * asym[0];
+  beta[0] = v / pg_old;
+}
+
+// out = a x + b[0] y with the factor b read on the device
+__global__ void k_axpby_dev(size_t n, double a, const double* __restrict__ x,
+                            const double* __restrict__ b, const double* __restrict__ y,
+                            double* __restrict__ out) {
+  const double bb = b[0];
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double v = a * x[i];
+    v += bb * y[i];
+    out[i] = v;
   }
 }
 
@@ -861,8 +886,19 @@ void launch_subspace(Ctx& c) {
   ROKS_HIP(hipGetLastError());
 }
 
-void launch_asym_dot(Ctx& c, const double* A, const double* theta, double* out) {
-  hipLaunchKernelGGL(k_asym_dot, dim3(1), dim3(256), 0, c.stream, A, theta, c.nb, out);
+void launch_asym_dot(Ctx& c, const double* A, const double* theta, double* out, double* mirror) {
+  hipLaunchKernelGGL(k_asym_dot, dim3(1), dim3(256), 0, c.stream, A, theta, c.nb, out, mirror);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_cg_beta(Ctx& c, const double* asym, const double* pgb, double pg_old, double* beta) {
+  hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64), 0, c.stream, asym, pgb, c.nb, pg_old, beta);
+  ROKS_HIP(hipGetLastError());
+}
+
+void axpby_dev(Ctx& c, size_t n, double a, const double* x, const double* b, const double* y,
+               double* out) {
+  hipLaunchKernelGGL(k_axpby_dev, dim3(blocks_for(n)), dim3(256), 0, c.stream, n, a, x, b, y, out);
   ROKS_HIP(hipGetLastError());
 }
 

@@ -180,7 +180,8 @@ struct Ctx {
   double* d_Q = nullptr;         // [nb][nsocc]
   double* d_kin = nullptr;       // [nb]
   double* d_enl = nullptr;       // [nb]
-  double* d_bandv = nullptr;     // [4][nb] per-band scratch scalars
+  double* d_bandv = nullptr;     // [8][nb] per-band scratch scalars
+  double* d_cg = nullptr;        // [8 + nb]: [0] A-part of <p|g>, [1] beta, [8 + n] <p_n|g_n>
   // nb x nb matrices
   double *d_theta = nullptr, *d_R = nullptr, *d_kappa = nullptr, *d_A = nullptr, *d_D = nullptr,
          *d_Dold = nullptr, *d_gram = nullptr, *d_Linv = nullptr, *d_U = nullptr,
@@ -424,7 +425,13 @@ bool expm_in_lds(const Ctx& c);
 void launch_chol_expm_lds(Ctx& c, const double* G, double ga, double gd, double* Linv, int32_t* flag,
                           const double* D, double delta, double* U);
 void launch_expm_lds(Ctx& c, const double* D, double delta, double* U, hipStream_t stream);
-void launch_asym_dot(Ctx& c, const double* A, const double* theta, double* out);
+void launch_asym_dot(Ctx& c, const double* A, const double* theta, double* out,
+                     double* mirror = nullptr);
+// beta = (sum_n pgb[n] + asym[0] / 2) / pg_old on the device
+void launch_cg_beta(Ctx& c, const double* asym, const double* pgb, double pg_old, double* beta);
+// out = a x + b[0] y, b a device scalar
+void axpby_dev(Ctx& c, size_t n, double a, const double* x, const double* b, const double* y,
+               double* out);
 // max |theta_nm - theta_mn| over m of shell sa, n of shell sb (one value)
 void launch_open_coupling(Ctx& c, int sa, int sb, double* out);
 void launch_teter(Ctx& c, const double* gTg, const double* gg, const double2* g, const double* bandw,

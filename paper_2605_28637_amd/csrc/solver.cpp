@@ -360,7 +360,9 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   for (int X = 0; X < c.nshell; ++X)
     if (!c.shell_closed[X] && !c.shell_virtual[X]) opens[no++] = X;
   bool first_fetch = true;
-  auto precondition = [&](bool learned) {
+  // launches of p = (1 - P) K g_I and of the parts of <p|g> = sum <p_I|g_I> +
+  // 1/2 sum A (theta - theta^T), kept on the device (d_cg) and mirrored
+  auto precondition_async = [&](bool learned) {
     if (learned)
       launch_teter_scaled(c, c.d_bandv, c.d_bandv + nb, c.d_gI, bandw, c.d_w1);
     else
@@ -368,20 +370,19 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     gemm_wdot(c, nb, nb, K, dbl(c.d_psi), K, dbl(c.d_w1), K, c.d_m1, nb, 1.0, 0.0, true);
     gemm_expand_to(c, nb, K, nb, c.d_m1, nb, false, dbl(c.d_psi), K, dbl(c.d_w1), K, dbl(c.d_p), K,
                    -1.0, 1.0);
-    // <p|g> = sum <p_I|g_I> + 1/2 sum A (theta - theta^T)
-    launch_asym_dot(c, c.d_A, c.d_theta, st);
-    band_dots(c, c.d_p, c.d_gI, nb, 0, st + kStage);
+    launch_asym_dot(c, c.d_A, c.d_theta, c.d_cg, st);
+    band_dots2(c, c.d_p, c.d_gI, nb, c.d_cg + 8, nullptr, st + kStage, nullptr);
     // with the report's open-shell coupling
     if (first_fetch && no == 2) launch_open_coupling(c, opens[0], opens[1], st + 2);
-    sync(c);
     first_fetch = false;
-    return band_sum(0) + 0.5 * hs[0];
   };
+  // <p|g> from the mirrored parts, in the order of the device's sum
+  auto pg_host = [&]() { return band_sum(0) + 0.5 * hs[0]; };
   const bool learned = c.mlp != nullptr;
-  double pg = precondition(learned);
-  const double gnorm = std::sqrt(std::max(0.0, band_sum(nb)));
-  const double max_rab = no == 2 ? hs[2] : 0.0;
-  double beta = (c.have_old && c.pg_old != 0.0) ? pg / c.pg_old : 0.0;
+  // with carried directions the Fletcher-Reeves ratio is formed on the device
+  // and the directions follow without a round trip to the host
+  const bool dev_beta = c.have_old && c.pg_old != 0.0;
+  precondition_async(learned);
   bool restarted = periodic;
 
   // Sold projected out of the current span (kept in d_w1)
@@ -390,8 +391,13 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     gemm_expand_to(c, nb, K, nb, c.d_m1, nb, false, dbl(c.d_psi), K, dbl(c.d_Sold), K, dbl(c.d_w1), K,
                    -1.0, 1.0);
   }
-  auto directions = [&](double b) {
-    if (b != 0.0) {
+  // S = p + b S_old', D = A + b D_old (b = 0: plain copies); b_dev: the factor
+  // d_cg[1] formed on the device
+  auto directions_async = [&](double b, bool b_dev) {
+    if (b_dev) {
+      axpby_dev(c, 2 * band, 1.0, dbl(c.d_p), c.d_cg + 1, dbl(c.d_w1), dbl(c.d_S));
+      axpby_dev(c, nn, 1.0, c.d_A, c.d_cg + 1, c.d_Dold, c.d_D);
+    } else if (b != 0.0) {
       axpby(c, 2 * band, 1.0, dbl(c.d_p), b, dbl(c.d_w1), dbl(c.d_S));
       axpby(c, nn, 1.0, c.d_A, b, c.d_Dold, c.d_D);
     } else {
@@ -400,10 +406,31 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     }
     launch_asym_dot(c, c.d_D, c.d_theta, st + 1);
     band_dots(c, c.d_S, c.d_gI, nb, 0, st + kStage + 2 * nb);
-    sync(c);
-    return 2.0 * band_sum(2 * nb) + hs[1];
   };
-  double dE0 = directions(beta);
+  auto dE_host = [&]() { return 2.0 * band_sum(2 * nb) + hs[1]; };
+  auto directions = [&](double b) {
+    directions_async(b, false);
+    sync(c);
+    return dE_host();
+  };
+  double pg, beta, dE0;
+  if (dev_beta) {
+    launch_cg_beta(c, c.d_cg, c.d_cg + 8, c.pg_old, c.d_cg + 1);
+    directions_async(0.0, true);
+    sync(c);
+    pg = pg_host();
+    beta = pg / c.pg_old;
+    dE0 = dE_host();
+  } else {
+    // no carried directions (or pg_old = 0): beta = 0 without looking at pg
+    beta = 0.0;
+    directions_async(0.0, false);
+    sync(c);
+    pg = pg_host();
+    dE0 = dE_host();
+  }
+  const double gnorm = std::sqrt(std::max(0.0, band_sum(nb)));
+  const double max_rab = no == 2 ? hs[2] : 0.0;
   if (beta != 0.0 && dE0 >= 0.0) {
     beta = 0.0;
     restarted = true;
@@ -460,7 +487,9 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     // the learned direction found no decrease: redo the step with the plain
     // Teter preconditioner from the steepest-descent direction
     fallback = true;
-    pg = precondition(false);
+    precondition_async(false);
+    sync(c);
+    pg = pg_host();
     beta = 0.0;
     restarted = true;
     dE0 = directions(0.0);
