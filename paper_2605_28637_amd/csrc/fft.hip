@@ -21,6 +21,9 @@
 // the plane arithmetic and the potentials are in the tier's precision R.
 #include <algorithm>
 #include <cstdio>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "roks_internal.h"
 
@@ -740,11 +743,23 @@ int zchunk(const Ctx& c) {
   return CH;
 }
 
+// Raise a kernel's dynamic LDS limit past the 64 KiB default.  The largest
+// size set so far is remembered per (device, kernel), so steady-state
+// launches make no runtime call for it.
+std::mutex g_lds_mu;
+std::map<std::pair<int, const void*>, size_t> g_lds_set;
+
 template <typename K>
 void allow_lds(K kernel, size_t bytes) {
-  if (bytes > 65536)
-    ROKS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  if (bytes <= 65536) return;
+  int dev = 0;
+  ROKS_HIP(hipGetDevice(&dev));
+  const void* f = reinterpret_cast<const void*>(kernel);
+  std::lock_guard<std::mutex> lock(g_lds_mu);
+  size_t& done = g_lds_set[{dev, f}];
+  if (bytes <= done) return;
+  ROKS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  done = bytes;
 }
 
 template <typename R>

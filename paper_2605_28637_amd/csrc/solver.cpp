@@ -408,8 +408,18 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     band_dots(c, c.d_S, c.d_gI, nb, 0, st + kStage + 2 * nb);
   };
   auto dE_host = [&]() { return 2.0 * band_sum(2 * nb) + hs[1]; };
+  // the line search's products of S (<S|S>, <beta|S>) are queued with the
+  // directions, before the synchronisation that decides on the search;
+  // directions formed again drop them
+  bool prepared = false, first_search = true;
+  auto prepare = [&]() {
+    prepare_line_search(c, first_search);
+    first_search = false;
+    prepared = true;
+  };
   auto directions = [&](double b) {
     directions_async(b, false);
+    prepared = false;
     sync(c);
     return dE_host();
   };
@@ -417,6 +427,7 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   if (dev_beta) {
     launch_cg_beta(c, c.d_cg, c.d_cg + 8, c.pg_old, c.d_cg + 1);
     directions_async(0.0, true);
+    prepare();
     sync(c);
     pg = pg_host();
     beta = pg / c.pg_old;
@@ -425,6 +436,7 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     // no carried directions (or pg_old = 0): beta = 0 without looking at pg
     beta = 0.0;
     directions_async(0.0, false);
+    prepare();
     sync(c);
     pg = pg_host();
     dE0 = dE_host();
@@ -468,10 +480,8 @@ void pcg_step(Ctx& c, roks_step_info* info) {
 
   int evals = 0, best = -1;
   bool fallback = false;
-  bool first_search = true;
   auto search = [&]() {
-    prepare_line_search(c, first_search);
-    first_search = false;
+    if (!prepared) prepare();
     return line_search(c.dt, &evals);
   };
   if (dE0 < 0.0) {
