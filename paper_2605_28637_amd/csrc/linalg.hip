@@ -617,46 +617,100 @@ __global__ void k_subspace(SubArgs a, const double* __restrict__ theta,
 }
 
 // sum_mn A_mn (theta_mn - theta_nm), one workgroup
-__global__ void k_asym_dot(const double* __restrict__ A, const double* __restrict__ th, int nb,
-                           double* __restrict__ out, double* __restrict__ mirror) {
-  __shared__ double red[16];
+// sum_mn A_mn (th_mn - th_nm) by the first 256 threads of the workgroup
+// (fixed order: 256-strided partials, wave sums, the 4 waves in order)
+__device__ void asym_dot_body(const double* __restrict__ A, const double* __restrict__ th, int nb,
+                              double* __restrict__ out, double* __restrict__ mirror, double* red) {
   double s = 0.0;
-  for (size_t t = threadIdx.x; t < (size_t)nb * nb; t += blockDim.x) {
-    const int m = (int)(t / nb), n = (int)(t - (size_t)m * nb);
-    s += A[t] * (th[t] - th[(size_t)n * nb + m]);
-  }
+  if (threadIdx.x < 256)
+    for (size_t t = threadIdx.x; t < (size_t)nb * nb; t += 256) {
+      const int m = (int)(t / nb), n = (int)(t - (size_t)m * nb);
+      s += A[t] * (th[t] - th[(size_t)n * nb + m]);
+    }
   s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  if ((threadIdx.x & 63) == 0 && threadIdx.x < 256) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
     double v = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w];
+    for (int w = 0; w < 4; ++w) v += red[w];
     *out = v;
     if (mirror) *mirror = v;
   }
 }
 
-// Fletcher-Reeves ratio on the device: pg = sum_n pgb[n] (band order) + asym / 2,
-// beta = pg / pg_old (the host forms the same sums from the mirrored values)
-__global__ void k_cg_beta(const double* __restrict__ asym, const double* __restrict__ pgb, int nb,
-                          double pg_old, double* __restrict__ beta) {
-  if (threadIdx.x != 0) return;
-  double v = 0.0;
-  for (int n = 0; n < nb; ++n) v += pgb[n];
-  v += 0.5 * asym[0];
-  beta[0] = v / pg_old;
+__global__ void k_asym_dot(const double* __restrict__ A, const double* __restrict__ th, int nb,
+                           double* __restrict__ out, double* __restrict__ mirror) {
+  __shared__ double red[16];
+  asym_dot_body(A, th, nb, out, mirror, red);
 }
 
-// out = a x + b[0] y with the factor b read on the device
-__global__ void k_axpby_dev(size_t n, double a, const double* __restrict__ x,
-                            const double* __restrict__ b, const double* __restrict__ y,
-                            double* __restrict__ out) {
-  const double bb = b[0];
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+// band dots <x_n|y_n> (workgroups 0 .. nvec-1, as k_band_dots with out0) and
+// the antisymmetric contraction of A with th (workgroup nvec) in one launch
+__global__ void __launch_bounds__(1024) k_band_dots_asym(const double2* __restrict__ X,
+                                                        const double2* __restrict__ Yv, int npw,
+                                                        double* __restrict__ out0,
+                                                        double* __restrict__ mirror0,
+                                                        const double* __restrict__ A,
+                                                        const double* __restrict__ th, int nb,
+                                                        double* __restrict__ aout,
+                                                        double* __restrict__ amirror) {
+  __shared__ double red[16];
+  const int n = blockIdx.x;
+  if (n == (int)gridDim.x - 1) {
+    asym_dot_body(A, th, nb, aout, amirror, red);
+    return;
+  }
+  const double2* x = X + (size_t)n * npw;
+  const double2* y = Yv + (size_t)n * npw;
+  double s0 = 0.0;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) {
+    double v = x[g].x * y[g].x + x[g].y * y[g].y;
+    if (g != 0) v *= 2.0;
+    s0 += v;
+  }
+  s0 = wave_sum(s0);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) red[wid] = s0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t0 = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t0 += red[w];
+    if (out0) out0[n] = t0;
+    if (mirror0) mirror0[n] = t0;
+  }
+}
+
+// CG directions with the Fletcher-Reeves ratio formed in every workgroup
+// (beta = (sum_n pgb[n] + asym / 2) / pg_old, band order): S = p + beta w
+// over n1 values, then D = A + beta D_old over n2 values; workgroup 0 keeps
+// beta in beta_out
+__global__ void k_cg_directions(size_t n1, const double* __restrict__ p, const double* __restrict__ w,
+                                double* __restrict__ S, size_t n2, const double* __restrict__ A,
+                                const double* __restrict__ Dold, double* __restrict__ D,
+                                const double* __restrict__ asym, const double* __restrict__ pgb,
+                                int nb, double pg_old, double* __restrict__ beta_out) {
+  __shared__ double sb;
+  if (threadIdx.x == 0) {
+    double v = 0.0;
+    for (int n = 0; n < nb; ++n) v += pgb[n];
+    v += 0.5 * asym[0];
+    sb = v / pg_old;
+    if (blockIdx.x == 0) beta_out[0] = sb;
+  }
+  __syncthreads();
+  const double bb = sb;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n1 + n2;
        i += (size_t)gridDim.x * blockDim.x) {
-    double v = a * x[i];
-    v += bb * y[i];
-    out[i] = v;
+    if (i < n1) {
+      double v = 1.0 * p[i];
+      v += bb * w[i];
+      S[i] = v;
+    } else {
+      const size_t j = i - n1;
+      double v = 1.0 * A[j];
+      v += bb * Dold[j];
+      D[j] = v;
+    }
   }
 }
 
@@ -891,14 +945,19 @@ void launch_asym_dot(Ctx& c, const double* A, const double* theta, double* out, 
   ROKS_HIP(hipGetLastError());
 }
 
-void launch_cg_beta(Ctx& c, const double* asym, const double* pgb, double pg_old, double* beta) {
-  hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64), 0, c.stream, asym, pgb, c.nb, pg_old, beta);
+void band_dots_asym(Ctx& c, const double2* X, const double2* Y, int nvec, double* out0,
+                    double* mirror0, const double* A, const double* theta, double* aout,
+                    double* amirror) {
+  hipLaunchKernelGGL(k_band_dots_asym, dim3(nvec + 1), dim3(1024), 0, c.stream, X, Y, c.npw, out0,
+                     mirror0, A, theta, c.nb, aout, amirror);
   ROKS_HIP(hipGetLastError());
 }
 
-void axpby_dev(Ctx& c, size_t n, double a, const double* x, const double* b, const double* y,
-               double* out) {
-  hipLaunchKernelGGL(k_axpby_dev, dim3(blocks_for(n)), dim3(256), 0, c.stream, n, a, x, b, y, out);
+void cg_directions_dev(Ctx& c, size_t n1, const double* p, const double* w, double* S, size_t n2,
+                       const double* A, const double* Dold, double* D, const double* asym,
+                       const double* pgb, double pg_old, double* beta_out) {
+  hipLaunchKernelGGL(k_cg_directions, dim3(blocks_for(n1 + n2)), dim3(256), 0, c.stream, n1, p, w, S,
+                     n2, A, Dold, D, asym, pgb, c.nb, pg_old, beta_out);
   ROKS_HIP(hipGetLastError());
 }
 

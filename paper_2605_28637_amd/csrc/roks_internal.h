@@ -427,11 +427,16 @@ void launch_chol_expm_lds(Ctx& c, const double* G, double ga, double gd, double*
 void launch_expm_lds(Ctx& c, const double* D, double delta, double* U, hipStream_t stream);
 void launch_asym_dot(Ctx& c, const double* A, const double* theta, double* out,
                      double* mirror = nullptr);
-// beta = (sum_n pgb[n] + asym[0] / 2) / pg_old on the device
-void launch_cg_beta(Ctx& c, const double* asym, const double* pgb, double pg_old, double* beta);
-// out = a x + b[0] y, b a device scalar
-void axpby_dev(Ctx& c, size_t n, double a, const double* x, const double* b, const double* y,
-               double* out);
+// out0[n] = <X_n|Y_n> (and mirror0[n]) for n < nvec, and aout = sum A (theta -
+// theta^T) (and amirror), in one launch
+void band_dots_asym(Ctx& c, const double2* X, const double2* Y, int nvec, double* out0,
+                    double* mirror0, const double* A, const double* theta, double* aout,
+                    double* amirror);
+// S = p + beta w (n1 values), D = A + beta D_old (n2 values) with beta =
+// (sum_n pgb[n] + asym[0] / 2) / pg_old formed on the device (kept in beta_out)
+void cg_directions_dev(Ctx& c, size_t n1, const double* p, const double* w, double* S, size_t n2,
+                       const double* A, const double* Dold, double* D, const double* asym,
+                       const double* pgb, double pg_old, double* beta_out);
 // max |theta_nm - theta_mn| over m of shell sa, n of shell sb (one value)
 void launch_open_coupling(Ctx& c, int sa, int sb, double* out);
 void launch_teter(Ctx& c, const double* gTg, const double* gg, const double2* g, const double* bandw,

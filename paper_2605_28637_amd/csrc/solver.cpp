@@ -370,8 +370,7 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     gemm_wdot(c, nb, nb, K, dbl(c.d_psi), K, dbl(c.d_w1), K, c.d_m1, nb, 1.0, 0.0, true);
     gemm_expand_to(c, nb, K, nb, c.d_m1, nb, false, dbl(c.d_psi), K, dbl(c.d_w1), K, dbl(c.d_p), K,
                    -1.0, 1.0);
-    launch_asym_dot(c, c.d_A, c.d_theta, c.d_cg, st);
-    band_dots2(c, c.d_p, c.d_gI, nb, c.d_cg + 8, nullptr, st + kStage, nullptr);
+    band_dots_asym(c, c.d_p, c.d_gI, nb, c.d_cg + 8, st + kStage, c.d_A, c.d_theta, c.d_cg, st);
     // with the report's open-shell coupling
     if (first_fetch && no == 2) launch_open_coupling(c, opens[0], opens[1], st + 2);
     first_fetch = false;
@@ -395,8 +394,8 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   // d_cg[1] formed on the device
   auto directions_async = [&](double b, bool b_dev) {
     if (b_dev) {
-      axpby_dev(c, 2 * band, 1.0, dbl(c.d_p), c.d_cg + 1, dbl(c.d_w1), dbl(c.d_S));
-      axpby_dev(c, nn, 1.0, c.d_A, c.d_cg + 1, c.d_Dold, c.d_D);
+      cg_directions_dev(c, 2 * band, dbl(c.d_p), dbl(c.d_w1), dbl(c.d_S), nn, c.d_A, c.d_Dold, c.d_D,
+                        c.d_cg, c.d_cg + 8, c.pg_old, c.d_cg + 1);
     } else if (b != 0.0) {
       axpby(c, 2 * band, 1.0, dbl(c.d_p), b, dbl(c.d_w1), dbl(c.d_S));
       axpby(c, nn, 1.0, c.d_A, b, c.d_Dold, c.d_D);
@@ -404,8 +403,8 @@ void pcg_step(Ctx& c, roks_step_info* info) {
       copy_dev(c, c.d_S, c.d_p, band * sizeof(double2));
       copy_dev(c, c.d_D, c.d_A, nn * sizeof(double));
     }
-    launch_asym_dot(c, c.d_D, c.d_theta, st + 1);
-    band_dots(c, c.d_S, c.d_gI, nb, 0, st + kStage + 2 * nb);
+    band_dots_asym(c, c.d_S, c.d_gI, nb, nullptr, st + kStage + 2 * nb, c.d_D, c.d_theta, st + 1,
+                   nullptr);
   };
   auto dE_host = [&]() { return 2.0 * band_sum(2 * nb) + hs[1]; };
   // the line search's products of S (<S|S>, <beta|S>) are queued with the
@@ -425,7 +424,6 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   };
   double pg, beta, dE0;
   if (dev_beta) {
-    launch_cg_beta(c, c.d_cg, c.d_cg + 8, c.pg_old, c.d_cg + 1);
     directions_async(0.0, true);
     prepare();
     sync(c);
