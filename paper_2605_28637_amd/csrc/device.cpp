@@ -103,11 +103,12 @@ void init_device(Ctx& c, void* stream) {
   c.d_gI = dalloc<double2>(c, band);
   c.d_p = dalloc<double2>(c, band);
   c.d_S = dalloc<double2>(c, band);
-  c.d_Sold = dalloc<double2>(c, band);
   c.d_Pt = dalloc<double2>(c, band);
   c.d_trial[0] = dalloc<double2>(c, band);
   c.d_trial[1] = dalloc<double2>(c, band);
-  c.d_w1 = dalloc<double2>(c, band);
+  // w1 and S_old side by side: one band product covers both (preconditioner)
+  c.d_w1 = dalloc<double2>(c, 2 * band);
+  c.d_Sold = c.d_w1 + band;
   c.d_T = dalloc<double2>(c, (size_t)c.npairs * c.N[2] * c.ncol);
   c.d_rho_part = dalloc<double>(c, (size_t)c.nchunk * c.nsocc * ntot);
   c.d_rho = dalloc<double>(c, (size_t)c.nsocc * ntot);
@@ -133,6 +134,7 @@ void init_device(Ctx& c, void* stream) {
   c.d_bandv = dalloc<double>(c, 8 * nb);
   c.d_cg = dalloc<double>(c, 8 + nb);
   const size_t nn = nb * nb;
+  c.d_m12 = dalloc<double>(c, 2 * (size_t)nb * nb);
   double** mats[] = {&c.d_theta, &c.d_R, &c.d_kappa, &c.d_A, &c.d_D, &c.d_Dold, &c.d_gram,
                      &c.d_Linv, &c.d_U, &c.d_M, &c.d_m1, &c.d_m2, &c.d_m3, &c.d_Mkeep,
                      &c.d_Ukeep, &c.d_m4, &c.d_SS};

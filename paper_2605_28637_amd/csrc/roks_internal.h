@@ -163,7 +163,8 @@ struct Ctx {
   double2* d_Sold = nullptr;
   double2* d_Pt = nullptr;       // trial vectors
   double2* d_trial[2] = {nullptr, nullptr};  // trial orbitals (an accepted one swaps with d_psi)
-  double2* d_w1 = nullptr;       // scratch band array
+  double2* d_w1 = nullptr;       // scratch band array, followed by d_Sold
+  double* d_m12 = nullptr;       // [nb][2 nb]: <psi|w1> and <psi|S_old> side by side
   double2* d_T = nullptr;        // [npairs][N3][ncol] column buffer
   double* d_rho_part = nullptr;  // [nchunk][nsocc][ntot]
   double* d_rho = nullptr;       // [nsocc][ntot]

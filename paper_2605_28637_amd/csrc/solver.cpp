@@ -362,13 +362,16 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   bool first_fetch = true;
   // launches of p = (1 - P) K g_I and of the parts of <p|g> = sum <p_I|g_I> +
   // 1/2 sum A (theta - theta^T), kept on the device (d_cg) and mirrored
-  auto precondition_async = [&](bool learned) {
+  // with_sold: the same band product also gives <psi|S_old> (S_old follows w1
+  // in memory), in columns nb .. 2 nb - 1 of d_m12
+  auto precondition_async = [&](bool learned, bool with_sold) {
     if (learned)
       launch_teter_scaled(c, c.d_bandv, c.d_bandv + nb, c.d_gI, bandw, c.d_w1);
     else
       launch_teter(c, c.d_bandv, c.d_bandv + nb, c.d_gI, bandw, c.d_w1);
-    gemm_wdot(c, nb, nb, K, dbl(c.d_psi), K, dbl(c.d_w1), K, c.d_m1, nb, 1.0, 0.0, true);
-    gemm_expand_to(c, nb, K, nb, c.d_m1, nb, false, dbl(c.d_psi), K, dbl(c.d_w1), K, dbl(c.d_p), K,
+    const int nc = with_sold ? 2 * nb : nb;
+    gemm_wdot(c, nb, nc, K, dbl(c.d_psi), K, dbl(c.d_w1), K, c.d_m12, nc, 1.0, 0.0, true);
+    gemm_expand_to(c, nb, K, nb, c.d_m12, nc, false, dbl(c.d_psi), K, dbl(c.d_w1), K, dbl(c.d_p), K,
                    -1.0, 1.0);
     band_dots_asym(c, c.d_p, c.d_gI, nb, c.d_cg + 8, st + kStage, c.d_A, c.d_theta, c.d_cg, st);
     // with the report's open-shell coupling
@@ -381,15 +384,13 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   // with carried directions the Fletcher-Reeves ratio is formed on the device
   // and the directions follow without a round trip to the host
   const bool dev_beta = c.have_old && c.pg_old != 0.0;
-  precondition_async(learned);
+  precondition_async(learned, c.have_old);
   bool restarted = periodic;
 
   // Sold projected out of the current span (kept in d_w1)
-  if (c.have_old) {
-    gemm_wdot(c, nb, nb, K, dbl(c.d_psi), K, dbl(c.d_Sold), K, c.d_m1, nb, 1.0, 0.0, true);
-    gemm_expand_to(c, nb, K, nb, c.d_m1, nb, false, dbl(c.d_psi), K, dbl(c.d_Sold), K, dbl(c.d_w1), K,
-                   -1.0, 1.0);
-  }
+  if (c.have_old)
+    gemm_expand_to(c, nb, K, nb, c.d_m12 + nb, 2 * nb, false, dbl(c.d_psi), K, dbl(c.d_Sold), K,
+                   dbl(c.d_w1), K, -1.0, 1.0);
   // S = p + b S_old', D = A + b D_old (b = 0: plain copies); b_dev: the factor
   // d_cg[1] formed on the device
   auto directions_async = [&](double b, bool b_dev) {
@@ -495,7 +496,7 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     // the learned direction found no decrease: redo the step with the plain
     // Teter preconditioner from the steepest-descent direction
     fallback = true;
-    precondition_async(false);
+    precondition_async(false, false);
     sync(c);
     pg = pg_host();
     beta = 0.0;
