@@ -571,11 +571,22 @@ struct SubArgs {
   int virt[kMaxShell];
 };
 
+__device__ void open_coupling_body(const double* __restrict__ theta, int nb,
+                                   const int32_t* __restrict__ shell, int sa, int sb,
+                                   double* __restrict__ out, double* red);
+
+// oc: when not null, the last workgroup (256 threads) writes the open-shell
+// coupling max |theta_nm - theta_mn| (m in shell open_a, n in open_b) there
 __global__ void k_subspace(SubArgs a, const double* __restrict__ theta,
                            const int32_t* __restrict__ shell, const double* __restrict__ tkin,
                            const double* __restrict__ tnl, const double* __restrict__ Q,
                            double* __restrict__ R, double* __restrict__ kappa,
-                           double* __restrict__ A) {
+                           double* __restrict__ A, double* __restrict__ oc) {
+  if (oc && blockIdx.x == gridDim.x - 1) {
+    __shared__ double red[256];
+    open_coupling_body(theta, a.nb, shell, a.open_a, a.open_b, oc, red);
+    return;
+  }
   const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const int nb = a.nb;
   if (t >= (size_t)nb * nb) return;
@@ -740,10 +751,11 @@ __global__ void k_teter(const double2* __restrict__ g, int npw, int nb, const do
 }
 
 // max |theta_nm - theta_mn| over bands m of shell sa and n of shell sb
-__global__ void __launch_bounds__(256) k_open_coupling(const double* __restrict__ theta, int nb,
-                                                       const int32_t* __restrict__ shell, int sa,
-                                                       int sb, double* __restrict__ out) {
-  __shared__ double red[256];
+// max |theta_nm - theta_mn| over m in shell sa, n in shell sb, by a
+// 256-thread workgroup (fixed tree)
+__device__ void open_coupling_body(const double* __restrict__ theta, int nb,
+                                   const int32_t* __restrict__ shell, int sa, int sb,
+                                   double* __restrict__ out, double* red) {
   double mx = 0.0;
   for (int t = threadIdx.x; t < nb * nb; t += 256) {
     const int m = t / nb, n = t - m * nb;
@@ -918,7 +930,7 @@ void launch_expm_lds(Ctx& c, const double* D, double delta, double* U, hipStream
   ROKS_HIP(hipGetLastError());
 }
 
-void launch_subspace(Ctx& c) {
+void launch_subspace(Ctx& c, double* open_out) {
   SubArgs a{};
   a.nb = c.nb;
   a.nsocc = c.nsocc;
@@ -935,8 +947,11 @@ void launch_subspace(Ctx& c) {
     a.open_b = opens[1];
   }
   const size_t nn = (size_t)c.nb * c.nb;
-  hipLaunchKernelGGL(k_subspace, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, c.stream, a, c.d_theta,
-                     c.d_band_shell, c.d_kin, c.d_enl, c.d_Q, c.d_R, c.d_kappa, c.d_A);
+  // the open-shell coupling rides in one more workgroup when asked for
+  double* oc = (open_out && a.open_a >= 0) ? open_out : nullptr;
+  const unsigned nblk = (unsigned)((nn + 255) / 256) + (oc ? 1u : 0u);
+  hipLaunchKernelGGL(k_subspace, dim3(nblk), dim3(256), 0, c.stream, a, c.d_theta, c.d_band_shell,
+                     c.d_kin, c.d_enl, c.d_Q, c.d_R, c.d_kappa, c.d_A, oc);
   ROKS_HIP(hipGetLastError());
 }
 
@@ -958,12 +973,6 @@ void cg_directions_dev(Ctx& c, size_t n1, const double* p, const double* w, doub
                        const double* pgb, double pg_old, double* beta_out) {
   hipLaunchKernelGGL(k_cg_directions, dim3(blocks_for(n1 + n2)), dim3(256), 0, c.stream, n1, p, w, S,
                      n2, A, Dold, D, asym, pgb, c.nb, pg_old, beta_out);
-  ROKS_HIP(hipGetLastError());
-}
-
-void launch_open_coupling(Ctx& c, int sa, int sb, double* out) {
-  hipLaunchKernelGGL(k_open_coupling, dim3(1), dim3(256), 0, c.stream, c.d_theta, c.nb,
-                     c.d_band_shell, sa, sb, out);
   ROKS_HIP(hipGetLastError());
 }
 

@@ -419,7 +419,8 @@ void set_identity(Ctx& c, double* A, int n, double diag);
 // out = a in + d I (n x n)
 void scale_shift(Ctx& c, const double* in, int n, double a, double d, double* out);
 void matrix_norm1(Ctx& c, const double* A, int n, double* out);
-void launch_subspace(Ctx& c);
+// open_out: also the open-shell coupling (two open shells only)
+void launch_subspace(Ctx& c, double* open_out = nullptr);
 bool expm_in_lds(const Ctx& c);
 // Cholesky inverse of G and U = exp(delta D) in one launch of two workgroups
 // (nb within the single-workgroup limits of both)
@@ -438,8 +439,6 @@ void band_dots_asym(Ctx& c, const double2* X, const double2* Y, int nvec, double
 void cg_directions_dev(Ctx& c, size_t n1, const double* p, const double* w, double* S, size_t n2,
                        const double* A, const double* Dold, double* D, const double* asym,
                        const double* pgb, double pg_old, double* beta_out);
-// max |theta_nm - theta_mn| over m of shell sa, n of shell sb (one value)
-void launch_open_coupling(Ctx& c, int sa, int sb, double* out);
 void launch_teter(Ctx& c, const double* gTg, const double* gg, const double2* g, const double* bandw,
                   double2* out);
 
@@ -463,7 +462,7 @@ void collect_records(Ctx& c, Mlp& m, int* used, int* skipped);
 void compute_potentials(Ctx& c, const double2* orbitals, roks_energies* e);
 void ensure_potentials(Ctx& c);
 void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bool want_Q);
-void energy_gradient(Ctx& c, roks_energies* e);
+void energy_gradient(Ctx& c, roks_energies* e, double* open_out = nullptr);
 void pcg_step(Ctx& c, roks_step_info* info);
 void orthonormalize(Ctx& c, double2* vecs);
 void forces(Ctx& c, double* f_host);

@@ -106,7 +106,13 @@ void prepare_line_search(Ctx& c, bool first) {
   const int nb = c.nb, K = 2 * c.npw;
   gemm_wdot(c, nb, nb, K, dbl(c.d_S), K, dbl(c.d_S), K, c.d_SS, nb, 1.0, 0.0, true);
   if (c.nproj > 0) {
-    if (first) copy_dev(c, c.d_P0, c.d_P, (size_t)c.nproj * nb * sizeof(double));
+    // P0 <- the current projections by trading buffers: the trials write d_P,
+    // so P (with the densities and potentials, which the trials overwrite too)
+    // counts as stale until a step keeps its last trial
+    if (first) {
+      std::swap(c.d_P0, c.d_P);
+      c.potentials_valid = false;
+    }
     gemm_wdot(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(c.d_S), K, c.d_PS, nb, 1.0, 0.0, true);
   }
 }
@@ -295,7 +301,7 @@ void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bo
 // ---------------------------------------------------------------------------
 // energy, Y = F^n|n>, theta, g_I = (1 - P) Y, and R / kappa / A
 // ---------------------------------------------------------------------------
-void energy_gradient(Ctx& c, roks_energies* e) {
+void energy_gradient(Ctx& c, roks_energies* e, double* open_out) {
   ROKS_CHECK(c.have_orbitals, ROKS_ERR_STATE, "no orbitals set");
   const int nb = c.nb, K = 2 * c.npw;
   const size_t band = (size_t)nb * c.npw;
@@ -306,7 +312,7 @@ void energy_gradient(Ctx& c, roks_energies* e) {
   gemm_wdot(c, nb, nb, K, dbl(c.d_psi), K, dbl(c.d_Y), K, c.d_theta, nb, 1.0, 0.0, true);
   gemm_expand_to(c, nb, K, nb, c.d_theta, nb, false, dbl(c.d_psi), K, dbl(c.d_Y), K, dbl(c.d_gI), K,
                  -1.0, 1.0);
-  launch_subspace(c);
+  launch_subspace(c, open_out);
 }
 
 void reset_cg(Ctx& c) {
@@ -328,10 +334,6 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   const bool periodic = c.restart_period > 0 && c.since_restart >= c.restart_period;
   if (periodic) reset_cg(c);
   c.since_restart++;
-  roks_energies e0;
-  energy_gradient(c, &e0);
-  const double E0 = e0.E;
-
   // step scalars, written by the kernels straight into the pinned mirror
   // (read after a synchronisation): [0] sum A (theta - theta^T), [1] the same
   // for D, [2] max open-shell coupling, [kStage + n] <p_n|g_n>,
@@ -339,6 +341,13 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   // bands in band order
   double* st = c.hd_stage;
   const double* hs = c.h_stage;
+  int no = 0;  // open shells
+  for (int X = 0; X < c.nshell; ++X)
+    if (!c.shell_closed[X] && !c.shell_virtual[X]) ++no;
+  roks_energies e0;
+  // with the report's open-shell coupling (two open shells)
+  energy_gradient(c, &e0, no == 2 ? st + 2 : nullptr);
+  const double E0 = e0.E;
 
   // preconditioned out-of-subspace gradient p = (1 - P) K g_I; with a
   // network attached K carries the learned factor of (band, |G|^2 shell)
@@ -356,10 +365,6 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     for (int n = 0; n < nb; ++n) v += hs[kStage + off + n];
     return v;
   };
-  int opens[kMaxShell], no = 0;
-  for (int X = 0; X < c.nshell; ++X)
-    if (!c.shell_closed[X] && !c.shell_virtual[X]) opens[no++] = X;
-  bool first_fetch = true;
   // launches of p = (1 - P) K g_I and of the parts of <p|g> = sum <p_I|g_I> +
   // 1/2 sum A (theta - theta^T), kept on the device (d_cg) and mirrored
   // with_sold: the same band product also gives <psi|S_old> (S_old follows w1
@@ -374,9 +379,6 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     gemm_expand_to(c, nb, K, nb, c.d_m12, nc, false, dbl(c.d_psi), K, dbl(c.d_w1), K, dbl(c.d_p), K,
                    -1.0, 1.0);
     band_dots_asym(c, c.d_p, c.d_gI, nb, c.d_cg + 8, st + kStage, c.d_A, c.d_theta, c.d_cg, st);
-    // with the report's open-shell coupling
-    if (first_fetch && no == 2) launch_open_coupling(c, opens[0], opens[1], st + 2);
-    first_fetch = false;
   };
   // <p|g> from the mirrored parts, in the order of the device's sum
   auto pg_host = [&]() { return band_sum(0) + 0.5 * hs[0]; };
