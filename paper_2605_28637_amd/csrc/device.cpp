@@ -114,7 +114,6 @@ void init_device(Ctx& c, void* stream) {
   c.d_rho = dalloc<double>(c, (size_t)c.nsocc * ntot);
   c.d_vloc = dalloc<double>(c, (size_t)2 * c.nconf * ntot);
   c.d_vsh = dalloc<double>(c, (size_t)c.nsocc * ntot);
-  c.d_vh = dalloc<double>(c, (size_t)c.nconf * ntot);
   c.d_fft = dalloc<double2>(c, ntot);
   c.d_P = dalloc<double>(c, np * nb);
   c.d_DP = dalloc<double>(c, np * nb);

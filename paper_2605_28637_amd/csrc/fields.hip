@@ -271,15 +271,6 @@ __global__ void __launch_bounds__(256) k_hartree_energy(Lattice L, const double2
   }
 }
 
-__global__ void k_unpack_vh(const double2* __restrict__ f, size_t ntot, int nconf,
-                            double* __restrict__ vh) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
-       i += (size_t)gridDim.x * blockDim.x) {
-    vh[i] = f[i].x;
-    if (nconf > 1) vh[ntot + i] = f[i].y;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // spin LDA: Slater exchange + Perdew-Wang 1992 correlation
 // ---------------------------------------------------------------------------
@@ -372,11 +363,12 @@ __device__ void lda_spin(double ru, double rd, const LdaRho& r, int kind, double
 // V^X = sum c_L f_X V_loc^{sigma L}; partial sums of e_xc, V_ext rho, V_H rho per L.
 // WRITE = false: energy sums only (xc and external; no V_H read, no potentials,
 // no derivatives).  With a.same_rho every configuration has the total density
-// of configuration 0 and shares its r_s part.
+// of configuration 0 and shares its r_s part.  vh: the Hartree potentials as
+// the inverse transform leaves them, V_H^0 + i V_H^1 per point.
 template <bool WRITE>
 __global__ void __launch_bounds__(256) k_xc(ShellArgs a, const double* __restrict__ rho,
                                             const double* __restrict__ vext,
-                                            const double* __restrict__ vh, size_t ntot,
+                                            const double2* __restrict__ vh, size_t ntot,
                                             double* __restrict__ vloc, double* __restrict__ vsh,
                                             double* __restrict__ part) {
   __shared__ double red[8 * 16];
@@ -386,6 +378,7 @@ __global__ void __launch_bounds__(256) k_xc(ShellArgs a, const double* __restric
     double rX[3] = {0, 0, 0};
     for (int X = 0; X < a.nsocc; ++X) rX[X] = rho[(size_t)X * ntot + i];
     const double ve = vext[i];
+    const double2 vhp = WRITE ? vh[i] : make_double2(0.0, 0.0);
     double vl[kMaxConf][2];
     LdaRho lr;
     for (int L = 0; L < a.nconf; ++L) {
@@ -402,7 +395,7 @@ __global__ void __launch_bounds__(256) k_xc(ShellArgs a, const double* __restric
       acc[3 * L + 0] += e;
       acc[3 * L + 1] += ve * (ru + rd);
       if (!WRITE) continue;
-      const double h = vh[(size_t)L * ntot + i];
+      const double h = L == 0 ? vhp.x : vhp.y;
       vl[L][0] = ve + h + vu;
       vl[L][1] = ve + h + vd;
       vloc[(size_t)(2 * L) * ntot + i] = vl[L][0];
@@ -423,18 +416,24 @@ __global__ void __launch_bounds__(256) k_xc(ShellArgs a, const double* __restric
 }
 
 // out[j] = sum_r part[r][j] (also into mirror[j] when given); one workgroup per
-// column, fixed summation tree
+// column, fixed summation tree.  Workgroups past ncols take the columns of a
+// second array part2 [nrows][gridDim.x - ncols], continuing out and mirror.
 __global__ void __launch_bounds__(256) k_reduce_columns(const double* __restrict__ part, int nrows,
                                                         int ncols, double* __restrict__ out,
-                                                        double* __restrict__ mirror) {
+                                                        double* __restrict__ mirror,
+                                                        const double* __restrict__ part2) {
   __shared__ double red[8 * 16];
-  const int j = blockIdx.x;
+  const int jo = blockIdx.x;
+  const bool second = jo >= ncols;
+  const double* src = second ? part2 : part;
+  const int nc = second ? (int)gridDim.x - ncols : ncols;
+  const int j = second ? jo - ncols : jo;
   double v[1] = {0.0};
-  for (int r = threadIdx.x; r < nrows; r += blockDim.x) v[0] += part[(size_t)r * ncols + j];
+  for (int r = threadIdx.x; r < nrows; r += blockDim.x) v[0] += src[(size_t)r * nc + j];
   block_sum<1>(v, red);
   if (threadIdx.x == 0) {
-    out[j] = v[0];
-    if (mirror) mirror[j] = v[0];
+    out[jo] = v[0];
+    if (mirror) mirror[jo] = v[0];
   }
 }
 
@@ -677,13 +676,10 @@ void launch_density_reduce(Ctx& c, const double* rho_part, int nchunk, double* r
 
 // d_fft holds the packed configuration densities (launch_density_reduce)
 void launch_hartree(Ctx& c) {
-  const size_t n = c.ntot;
   // forward transform, 4 pi / (G^2 N^3), inverse transform (the multiply
-  // rides on the z pass)
+  // rides on the z pass); the xc pass reads V_H^0 + i V_H^1 from d_fft as the
+  // transform leaves it
   launch_hartree_fft(c, c.d_fft);
-  hipLaunchKernelGGL(k_unpack_vh, dim3(grid_blocks(n)), dim3(256), 0, c.stream, c.d_fft, n, c.nconf,
-                     c.d_vh);
-  ROKS_HIP(hipGetLastError());
 }
 
 int xc_blocks(const Ctx& c) {
@@ -695,13 +691,13 @@ void launch_xc_potentials(Ctx& c, double* part, int nblocks) {
   // reads shell densities, V_ext, V_H; writes V_loc and the shell potentials
   KernelTimer kt(c, "xc", (double)(2 * c.nsocc + 1 + 3 * c.nconf) * c.ntot * sizeof(double));
   hipLaunchKernelGGL(k_xc<true>, dim3(nblocks), dim3(256), 0, c.stream, shell_args(c), c.d_rho,
-                     c.d_vext, c.d_vh, (size_t)c.ntot, c.d_vloc, c.d_vsh, part);
+                     c.d_vext, c.d_fft, (size_t)c.ntot, c.d_vloc, c.d_vsh, part);
   ROKS_HIP(hipGetLastError());
 }
 
 void launch_xc_energy(Ctx& c, double* part, int nblocks) {
   hipLaunchKernelGGL(k_xc<false>, dim3(nblocks), dim3(256), 0, c.stream, shell_args(c), c.d_rho,
-                     c.d_vext, c.d_vh, (size_t)c.ntot, c.d_vloc, c.d_vsh, part);
+                     c.d_vext, c.d_fft, (size_t)c.ntot, c.d_vloc, c.d_vsh, part);
   ROKS_HIP(hipGetLastError());
 }
 
@@ -715,9 +711,9 @@ void launch_hartree_energy(Ctx& c, double* part, int nblocks) {
 }
 
 void launch_reduce_columns(Ctx& c, const double* part, int nrows, int ncols, double* out,
-                           double* mirror) {
-  hipLaunchKernelGGL(k_reduce_columns, dim3(ncols), dim3(256), 0, c.stream, part, nrows, ncols, out,
-                     mirror);
+                           double* mirror, const double* part2, int ncols2) {
+  hipLaunchKernelGGL(k_reduce_columns, dim3(ncols + (part2 ? ncols2 : 0)), dim3(256), 0, c.stream, part,
+                     nrows, ncols, out, mirror, part2);
   ROKS_HIP(hipGetLastError());
 }
 

@@ -170,7 +170,6 @@ struct Ctx {
   double* d_rho = nullptr;       // [nsocc][ntot]
   double* d_vloc = nullptr;      // [nconf][2][ntot]
   double* d_vsh = nullptr;       // [nsocc][ntot]
-  double* d_vh = nullptr;        // [nconf][ntot]
   double2* d_fft = nullptr;      // [ntot]
   double* d_P = nullptr;         // [nproj][nb]
   double* d_DP = nullptr;        // [nproj][nb]
@@ -365,8 +364,11 @@ void launch_apply_D(Ctx& c, const double* P, const double* w, double* DP);
 // Hartree integrals from the forward transform (partials [block][2])
 void launch_xc_energy(Ctx& c, double* part, int nblocks);
 void launch_hartree_energy(Ctx& c, double* part, int nblocks);
+// column sums of part [nrows][ncols] into out (and mirror); with part2, its
+// ncols2 columns ([nrows][ncols2]) follow in out in the same launch
 void launch_reduce_columns(Ctx& c, const double* part, int nrows, int ncols, double* out,
-                           double* mirror = nullptr);
+                           double* mirror = nullptr, const double* part2 = nullptr,
+                           int ncols2 = 0);
 void launch_to_float(Ctx& c, const double* in, float* out, size_t n);
 void launch_reduce_strided(Ctx& c, const double* part, int nouter, int ninner, int ncols,
                            double scale, double* out);

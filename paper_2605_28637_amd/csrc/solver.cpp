@@ -187,8 +187,7 @@ void compute_potentials_async(Ctx& c, const double2* orb, bool have_P, bool ener
     // xc and external sums without writing any potential
     launch_hartree_energy(c, c.d_part + 6 * (size_t)nblk, nblk);
     launch_xc_energy(c, c.d_part, nblk);
-    launch_reduce_columns(c, c.d_part, nblk, 6, c.d_red, c.hd_scal);
-    launch_reduce_columns(c, c.d_part + 6 * (size_t)nblk, nblk, 2, c.d_red + 6, c.hd_scal + 6);
+    launch_reduce_columns(c, c.d_part, nblk, 6, c.d_red, c.hd_scal, c.d_part + 6 * (size_t)nblk, 2);
   } else {
     launch_hartree(c);
     launch_xc_potentials(c, c.d_part, nblk);
