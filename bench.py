@@ -46,7 +46,7 @@ RESTART = 20
 TRAFFIC = {
     "gemm_wdot": {"source": "paper_2605_28637_amd/csrc/gemm.hip",
                   "sha256": "4ffac1e7ddd9c7e8e60c0b28f88d9cb3222e6aa1eda09955f7a09d5824fd674d",
-                  "bytes_per_launch": 2.4251e+07,
+                  "bytes_per_launch": 3.0663e+07,
                   "profile": "profiles/gemm_wdot_molecule64_fp64_traffic.md"},
 }
 KERNELS = ("zpass_bwd", "plane_apply", "plane_density", "zpass_fwd", "fft3d", "gemm_wdot",
