@@ -281,6 +281,7 @@ def batch_report(steps=8, workers=8):
     for r in seq:
         for _ in range(steps):
             r.pcg_step()
+        r.synchronize()  # one context after another: its last step's tail included
     t_seq = time.perf_counter() - t0
     par = make()
     b = rb.Batch(par, workers=workers)
@@ -322,8 +323,10 @@ def oxide_report(reps=3):
         r.synchronize()
         t_apply = (time.perf_counter() - t0) / reps
         r.pcg_step()
+        r.synchronize()
         t0 = time.perf_counter()
         info = r.pcg_step()
+        r.synchronize()  # the step's stream-ordered tail included
         t_step = time.perf_counter() - t0
         out[name] = {"ms_per_all_band_apply": 1e3 * t_apply,
                      "band_applies_per_s": r.nb / t_apply,
