@@ -244,54 +244,10 @@ __global__ void k_norm1(const double* A, int n, double* out) {
 }
 
 // --------------------------------------------------------------------------
-// Cholesky G = L L^T and L^-1 (lower), one workgroup, global memory.
-// flag[0] = 1 if G is not numerically positive definite.
+// Cholesky G = L L^T and L^-1 (lower); flag[0] = 1 if G is not numerically
+// positive definite.  One workgroup in LDS up to 128 bands, blocked beyond
+// (cholesky_inverse_blocked).
 // --------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_cholesky_inverse(const double* __restrict__ G, int n,
-                                                           double* __restrict__ A,
-                                                           double* __restrict__ X,
-                                                           int32_t* __restrict__ flag) {
-  // right-looking factorisation in global memory (A := L) with the forward
-  // elimination of L X = I fused in, as in the LDS variant; every step's work
-  // is spread over the workgroup
-  __shared__ int bad;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  if (tid == 0) bad = 0;
-  for (size_t t = tid; t < (size_t)n * n; t += nthr) {
-    A[t] = G[t];
-    X[t] = (t / n == t % n) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    if (tid == 0) {
-      double d = A[(size_t)j * n + j];
-      // numerically dependent: less than 1e-12 of the vector's own norm^2 is left
-      if (!(d > 1e-12 * G[(size_t)j * n + j]) || !isfinite(d)) {
-        bad = 1;
-        d = 1.0;
-      }
-      A[(size_t)j * n + j] = sqrt(d);
-    }
-    __syncthreads();
-    const double dj = A[(size_t)j * n + j];
-    for (int i = j + 1 + tid; i < n; i += nthr) A[(size_t)i * n + j] /= dj;
-    for (int cc = tid; cc <= j; cc += nthr) X[(size_t)j * n + cc] /= dj;
-    __syncthreads();
-    const int r = n - j - 1, w = j + 1;
-    for (int idx = tid; idx < r * r; idx += nthr) {
-      const int i = j + 1 + idx / r, k = j + 1 + idx % r;
-      if (k <= i) A[(size_t)i * n + k] -= A[(size_t)i * n + j] * A[(size_t)k * n + j];
-    }
-    for (int idx = tid; idx < r * w; idx += nthr) {
-      const int i = j + 1 + idx / w, cc = idx % w;
-      X[(size_t)i * n + cc] -= A[(size_t)i * n + j] * X[(size_t)j * n + cc];
-    }
-    __syncthreads();
-  }
-  for (size_t t = tid; t < (size_t)n * n; t += nthr)
-    if (t % n > t / n) X[t] = 0.0;
-  if (tid == 0) flag[0] = bad;
-}
 
 // Cholesky factorisation G = L L^T and (inv_in_lds, n <= 96) the inverse
 // L^-1 in one workgroup, right-looking, one barrier per column.  Threads sit
@@ -308,9 +264,10 @@ __global__ void __launch_bounds__(1024) k_cholesky_inverse(const double* __restr
 // LDS row stride of the single-workgroup Cholesky: n rounded up to odd
 __host__ __device__ inline int chol_ld(int n) { return n | 1; }
 
+// acc_flag: OR the status into flag[0] (blocks of a larger factorisation)
 __device__ void cholesky_lds_body(const double* __restrict__ G, double ga, double gd, int n,
                                   double* __restrict__ Linv, int32_t* __restrict__ flag, int inv_in_lds,
-                                  double* A) {
+                                  double* A, int acc_flag = 0) {
   __shared__ int bad;
   __shared__ double gdiag[128];   // the Gram diagonal, the reference of the pivot test
   __shared__ double piv[2][2];    // [step parity]: 1/d, 1/sqrt(d)
@@ -401,15 +358,23 @@ __device__ void cholesky_lds_body(const double* __restrict__ G, double ga, doubl
       }
     }
   }
-  if (tid == 0) flag[0] = bad;
+  if (tid == 0) flag[0] = acc_flag ? (flag[0] | bad) : bad;
 }
 
 __global__ void __launch_bounds__(1024) k_cholesky_inverse_lds(const double* __restrict__ G, int n,
                                                                double* __restrict__ Linv,
                                                                int32_t* __restrict__ flag,
-                                                               int inv_in_lds) {
+                                                               int inv_in_lds, int acc_flag) {
   extern __shared__ double A[];
-  cholesky_lds_body(G, 1.0, 0.0, n, Linv, flag, inv_in_lds, A);
+  cholesky_lds_body(G, 1.0, 0.0, n, Linv, flag, inv_in_lds, A, acc_flag);
+}
+
+// rows j0 .. j0+rows-1 of the n x n identity, [rows][n]
+__global__ void k_eye_rows(double* __restrict__ R, int rows, int n, int j0) {
+  const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (t >= (size_t)rows * n) return;
+  const int r = (int)(t / n), col = (int)(t - (size_t)r * n);
+  R[t] = (j0 + r == col) ? 1.0 : 0.0;
 }
 
 // U = exp(delta D) in one workgroup, the three n x n matrices in LDS:
@@ -890,6 +855,66 @@ void matrix_norm1(Ctx& c, const double* A, int n, double* out) {
   ROKS_HIP(hipGetLastError());
 }
 
+// row-major C (M x N) = alpha op(A) op(B) + beta C with the library DGEMM
+// (column-major: C^T = op(B)^T op(A)^T)
+static void gemm_rm(Ctx& c, bool tA, bool tB, int M, int N, int K, double alpha, const double* A,
+                    int lda, const double* B, int ldb, double beta, double* C, int ldc) {
+  if (M == 0 || N == 0 || K == 0) return;
+  ROKS_CHECK(rocblas_dgemm(static_cast<rocblas_handle>(blas_handle(c)),
+                           tB ? rocblas_operation_transpose : rocblas_operation_none,
+                           tA ? rocblas_operation_transpose : rocblas_operation_none, N, M, K, &alpha, B,
+                           ldb, A, lda, &beta, C, ldc) == rocblas_status_success,
+             ROKS_ERR_HIP, "rocblas_dgemm failed");
+}
+
+// L^-1 of G = L L^T for n > 128, blocked by 64: the diagonal block of each
+// panel factorised and inverted by the single-workgroup kernel (its status
+// ORed into flag[0]; the dependency test refers to the block's updated
+// diagonal), the panel below L21 = A21 L11^-T and the trailing update
+// A22 -= L21 L21^T as GEMMs; then L^-1 by block rows, X_i = L_ii^-1 (I_i -
+// L_i,<i X_<i).  Scratch: d_m3 (the updated matrix), d_m4 (L below the
+// diagonal blocks), d_m1 (the diagonal blocks' inverses), d_m2 (a block, then
+// a block row).
+static void cholesky_inverse_blocked(Ctx& c, const double* G, int n, double* Linv, int32_t* flag) {
+  constexpr int b = 64;
+  double* A = c.d_m3;
+  double* Lb = c.d_m4;
+  double* Dinv = c.d_m1;
+  double* T = c.d_m2;
+  const size_t lds = (size_t)2 * b * chol_ld(b) * sizeof(double);
+  if (lds > 65536)
+    ROKS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholesky_inverse_lds),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  ROKS_HIP(hipMemcpyAsync(A, G, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+  const int P = cdiv(n, b);
+  for (int p = 0; p < P; ++p) {
+    const int j0 = p * b, bs = std::min(b, n - j0), j1 = j0 + bs, m = n - j1;
+    ROKS_HIP(hipMemcpy2DAsync(T, (size_t)bs * sizeof(double), A + (size_t)j0 * n + j0,
+                              (size_t)n * sizeof(double), (size_t)bs * sizeof(double), bs,
+                              hipMemcpyDeviceToDevice, c.stream));
+    double* Di = Dinv + (size_t)p * b * b;
+    hipLaunchKernelGGL(k_cholesky_inverse_lds, dim3(1), dim3(1024), lds, c.stream, T, bs, Di, flag, 1,
+                       p > 0 ? 1 : 0);
+    ROKS_HIP(hipGetLastError());
+    if (m > 0) {
+      double* L21 = Lb + (size_t)j1 * n + j0;
+      gemm_rm(c, false, true, m, bs, bs, 1.0, A + (size_t)j1 * n + j0, n, Di, bs, 0.0, L21, n);
+      gemm_rm(c, false, true, m, m, bs, -1.0, L21, n, L21, n, 1.0, A + (size_t)j1 * n + j1, n);
+    }
+  }
+  for (int p = 0; p < P; ++p) {
+    const int j0 = p * b, bs = std::min(b, n - j0);
+    double* R = T;
+    const size_t nr = (size_t)bs * n;
+    hipLaunchKernelGGL(k_eye_rows, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, c.stream, R, bs, n,
+                       j0);
+    ROKS_HIP(hipGetLastError());
+    gemm_rm(c, false, false, bs, n, j0, -1.0, Lb + (size_t)j0 * n, n, Linv, n, 1.0, R, n);
+    gemm_rm(c, false, false, bs, n, bs, 1.0, Dinv + (size_t)p * b * b, bs, R, n, 0.0,
+            Linv + (size_t)j0 * n, n);
+  }
+}
+
 void cholesky_inverse(Ctx& c, const double* G, int n, double* Linv, int32_t* flag) {
   if (n <= 128) {
     const int inv = n <= 96 ? 1 : 0;
@@ -898,11 +923,11 @@ void cholesky_inverse(Ctx& c, const double* G, int n, double* Linv, int32_t* fla
       ROKS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholesky_inverse_lds),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(k_cholesky_inverse_lds, dim3(1), dim3(1024), lds, c.stream, G, n, Linv, flag,
-                       inv);
+                       inv, 0);
+    ROKS_HIP(hipGetLastError());
   } else {
-    hipLaunchKernelGGL(k_cholesky_inverse, dim3(1), dim3(1024), 0, c.stream, G, n, c.d_m3, Linv, flag);
+    cholesky_inverse_blocked(c, G, n, Linv, flag);
   }
-  ROKS_HIP(hipGetLastError());
 }
 
 bool expm_in_lds(const Ctx& c) { return c.nb <= 78; }

@@ -3,7 +3,8 @@ conventional cells, 215 atoms, 96^3 grid, 28 889 stored plane waves, 1 720
 projectors, 432 bands): energies of both configurations over all bands, and
 F^n|n> on sampled bands (every band class: closed, both open, virtual, and
 the last closed band of an odd/even pair), which the oracle computes one by
-one.  FP64 at 1e-10, the FP32 tier at 2e-6 (relative)."""
+one; the orthonormalised start of the sampled bands.  FP64 at 1e-10, the
+FP32 tier at 2e-6 (relative)."""
 import numpy as np
 import pytest
 
@@ -31,18 +32,23 @@ def oxide():
         ref[n] = (np.zeros(m.npw, complex) if m.shell_virtual[X]
                   else orc.apply_shell_operator(m, pot, X, psi[n:n + 1])[0])
     print("oracle reference ready", flush=True)
-    return s, m, pot, ref
+    return s, m, pot, ref, {n: psi[n].copy() for n in SAMPLE}
 
 
 @pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 2e-6)])
 def test_oxide_energies_and_sampled_apply(oxide, precision, tol):
     rb = ensure_built()
-    s, m, pot, ref = oxide
+    s, m, pot, ref, psi_s = oxide
     print("gpu precision", precision, flush=True)
     g = rb.Roks(s, precision=precision)
     assert (g.npw, g.nproj, g.nb) == ((m.npw + 1) // 2, 1720, 432)
     mp = SphereMap(g.miller(), m.miller)
     g.set_coeffs(inputs.random_coefficients(g.miller(), s["cell"], g.nb, s["seed"]), True)
+    # the GPU's Cholesky orthonormalisation of 432 bands (the blocked
+    # factorisation) against the oracle's, band by band (FP64 in both tiers)
+    c = g.get_coeffs()
+    for n in SAMPLE:
+        assert rel(mp.to_full(c[n])[0], psi_s[n]) < 1e-10, n
     e, _, _ = g.energy_gradient()
     scale = max(abs(v) for t in pot.terms.values() for v in t)
     assert abs(e["E"] - pot.E) < tol * scale
