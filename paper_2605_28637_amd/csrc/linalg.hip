@@ -224,14 +224,23 @@ __global__ void k_scale_shift(const double* __restrict__ in, int n, double a, do
   out[t] = a * in[t] + ((i == j) ? d : 0.0);
 }
 
-__global__ void k_norm1(const double* A, int n, double* out) {
+// ||A||_1 = max_j sum_i |A_ij| by one 1024-thread workgroup: four
+// row-interleaved partial column sums (dynamic LDS [4][n]), then their sum
+// per column and the maximum
+__global__ void __launch_bounds__(1024) k_norm1(const double* A, int n, double* out) {
+  extern __shared__ double part[];
   __shared__ double red[16];
-  double mx = 0.0;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+  const int g = threadIdx.x >> 8, tl = threadIdx.x & 255;
+  for (int j = tl; j < n; j += 256) {
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += fabs(A[(size_t)i * n + j]);
-    mx = fmax(mx, s);
+#pragma unroll 8
+    for (int i = g; i < n; i += 4) s += fabs(A[(size_t)i * n + j]);
+    part[g * n + j] = s;
   }
+  __syncthreads();
+  double mx = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x)
+    mx = fmax(mx, ((part[j] + part[n + j]) + part[2 * n + j]) + part[3 * n + j]);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
@@ -593,22 +602,24 @@ __global__ void k_subspace(SubArgs a, const double* __restrict__ theta,
 }
 
 // sum_mn A_mn (theta_mn - theta_nm), one workgroup
-// sum_mn A_mn (th_mn - th_nm) by the first 256 threads of the workgroup
-// (fixed order: 256-strided partials, wave sums, the 4 waves in order)
+// sum_mn A_mn (th_mn - th_nm) by the first nt threads of the workgroup, nt =
+// 256, or every thread (up to 1024) beyond 128 bands (fixed order: nt-strided
+// partials, wave sums, the waves in order)
 __device__ void asym_dot_body(const double* __restrict__ A, const double* __restrict__ th, int nb,
                               double* __restrict__ out, double* __restrict__ mirror, double* red) {
+  const int nt = (nb > 128 && blockDim.x >= 1024) ? 1024 : 256;
   double s = 0.0;
-  if (threadIdx.x < 256)
-    for (size_t t = threadIdx.x; t < (size_t)nb * nb; t += 256) {
+  if ((int)threadIdx.x < nt)
+    for (size_t t = threadIdx.x; t < (size_t)nb * nb; t += nt) {
       const int m = (int)(t / nb), n = (int)(t - (size_t)m * nb);
       s += A[t] * (th[t] - th[(size_t)n * nb + m]);
     }
   s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0 && threadIdx.x < 256) red[threadIdx.x >> 6] = s;
+  if ((threadIdx.x & 63) == 0 && (int)threadIdx.x < nt) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
     double v = 0.0;
-    for (int w = 0; w < 4; ++w) v += red[w];
+    for (int w = 0; w < nt / 64; ++w) v += red[w];
     *out = v;
     if (mirror) *mirror = v;
   }
@@ -807,9 +818,28 @@ void gemm_small(Ctx& c, int M, int N, int K, const double* A, int lda, bool tA, 
   gemm_small2(c, M, N, K, A, nullptr, 0.0, lda, tA, B, ldb, tB, C, ldc, alpha, beta, diag);
 }
 
+static void gemm_rm(Ctx& c, bool tA, bool tB, int M, int N, int K, double alpha, const double* A,
+                    int lda, const double* B, int ldb, double beta, double* C, int ldc);
+
+// C[i][i] += d for i < n
+__global__ void k_add_diag(double* __restrict__ C, int n, int ldc, double d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) C[(size_t)i * ldc + i] += d;
+}
+
 void gemm_small2(Ctx& c, int M, int N, int K, const double* A, const double* A2, double a2, int lda,
                  bool tA, const double* B, int ldb, bool tB, double* C, int ldc, double alpha,
                  double beta, double diag) {
+  if (!A2 && M >= 128 && N >= 128 && K >= 128) {
+    // a compute-bound size (the large-band exponential): the library DGEMM
+    gemm_rm(c, tA, tB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    if (diag != 0.0) {
+      const int nd = std::min(M, N);
+      hipLaunchKernelGGL(k_add_diag, dim3(cdiv(nd, 256)), dim3(256), 0, c.stream, C, nd, ldc, diag);
+      ROKS_HIP(hipGetLastError());
+    }
+    return;
+  }
   dim3 grid(cdiv(N, 16), cdiv(M, 16));
   hipLaunchKernelGGL(k_gemm_small, grid, dim3(256), 0, c.stream, M, N, K, A, A2, a2, lda, tA ? 1 : 0, B,
                      ldb, tB ? 1 : 0, C, ldc, alpha, beta, diag);
@@ -851,7 +881,8 @@ void scale_shift(Ctx& c, const double* in, int n, double a, double d, double* ou
 }
 
 void matrix_norm1(Ctx& c, const double* A, int n, double* out) {
-  hipLaunchKernelGGL(k_norm1, dim3(1), dim3(256), 0, c.stream, A, n, out);
+  ROKS_CHECK(n <= 2048, ROKS_ERR_SHAPE, "matrix too large for the 1-norm kernel");
+  hipLaunchKernelGGL(k_norm1, dim3(1), dim3(1024), (size_t)4 * n * sizeof(double), c.stream, A, n, out);
   ROKS_HIP(hipGetLastError());
 }
 
