@@ -891,6 +891,15 @@ static void run_plane_density(Ctx& c, const void* T, int npairs, double* rho_par
   ROKS_HIP(hipGetLastError());
 }
 
+// The FP32 tier's density planes: only where the plane kernel needs at most
+// 16 points per thread or is the length-64 build.  Beyond, the general-radix
+// FP32 density kernel spills far more than the FP64 one (96^2 planes: 13.7
+// against 4.2 ms per all-band density), so the tier takes the FP64 density.
+bool fp32_density_planes(const Ctx& c) {
+  const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], plane_threads(c)));
+  return mp <= 16 || radix_set(c.plan[0], c.plan[1]) == kLen64;
+}
+
 void launch_plane_density(Ctx& c, const void* T, int npairs, double* rho_part, int nchunk) {
   KernelTimer kt(c, "plane_density",
                  colbuf_bytes(c, npairs) + (double)nchunk * c.nsocc * c.ntot * sizeof(double));

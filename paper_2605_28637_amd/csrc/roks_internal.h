@@ -339,6 +339,8 @@ void launch_zpass_bwd(Ctx& c, const double2* vecs, int nvec, void* T, int npairs
 // nQ > 0 also accumulates <n|V^X|n> for the first nQ grids into Qpart
 void launch_plane_apply(Ctx& c, void* T, int npairs, const void* pot, int npot,
                         const int32_t* potidx, int nvec, double* Qpart, int nQ);
+// whether the FP32 tier runs the density planes in FP32 (else FP64)
+bool fp32_density_planes(const Ctx& c);
 void launch_plane_density(Ctx& c, const void* T, int npairs, double* rho_part, int nchunk);
 void launch_zpass_fwd(Ctx& c, const void* T, int npairs, const double2* vecs, int nvec,
                       const double* kinw, double2* Y);

@@ -164,8 +164,14 @@ void evaluate_trial(Ctx& c, double delta, Trial& t, bool energy_only) {
 // pinned mirror h_scal, read by assemble_energies after a synchronisation
 void compute_potentials_async(Ctx& c, const double2* orb, bool have_P, bool energy_only) {
   const int nb = c.nb, K = 2 * c.npw;
-  launch_zpass_bwd(c, orb, nb, c.d_T, c.npairs);
-  launch_plane_density(c, c.d_T, c.npairs, c.d_rho_part, c.nchunk);
+  {
+    // the FP32 tier's densities in FP64 where its FP32 planes would be slower
+    const int prec = c.prec;
+    if (prec == ROKS_FP32 && !fp32_density_planes(c)) c.prec = ROKS_FP64;
+    launch_zpass_bwd(c, orb, nb, c.d_T, c.npairs);
+    launch_plane_density(c, c.d_T, c.npairs, c.d_rho_part, c.nchunk);
+    c.prec = prec;
+  }
   launch_density_reduce(c, c.d_rho_part, c.nchunk, c.d_rho);
   // with the projections at hand, the band kinetic and nonlocal energies run
   // on the side stream beside the Hartree and xc chain (they need neither)
