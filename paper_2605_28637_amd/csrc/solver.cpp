@@ -166,11 +166,15 @@ void compute_potentials_async(Ctx& c, const double2* orb, bool have_P, bool ener
   const int nb = c.nb, K = 2 * c.npw;
   {
     // the FP32 tier's densities in FP64 where its FP32 planes would be slower
-    const int prec = c.prec;
-    if (prec == ROKS_FP32 && !fp32_density_planes(c)) c.prec = ROKS_FP64;
+    // (the tier is restored on every exit from this block)
+    struct TierScope {
+      Ctx& c;
+      int prec;
+      ~TierScope() { c.prec = prec; }
+    } scope{c, c.prec};
+    if (scope.prec == ROKS_FP32 && !fp32_density_planes(c)) c.prec = ROKS_FP64;
     launch_zpass_bwd(c, orb, nb, c.d_T, c.npairs);
     launch_plane_density(c, c.d_T, c.npairs, c.d_rho_part, c.nchunk);
-    c.prec = prec;
   }
   launch_density_reduce(c, c.d_rho_part, c.nchunk, c.d_rho);
   // with the projections at hand, the band kinetic and nonlocal energies run
