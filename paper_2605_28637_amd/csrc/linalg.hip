@@ -643,7 +643,7 @@ __global__ void __launch_bounds__(1024) k_band_dots_asym(const double2* __restri
                                                         double* __restrict__ amirror) {
   __shared__ double red[16];
   const int n = blockIdx.x;
-  if (n == (int)gridDim.x - 1) {
+  if (A && n == (int)gridDim.x - 1) {
     asym_dot_body(A, th, nb, aout, amirror, red);
     return;
   }
@@ -1016,11 +1016,66 @@ void launch_asym_dot(Ctx& c, const double* A, const double* theta, double* out, 
   ROKS_HIP(hipGetLastError());
 }
 
+// sum over one 32 x 32 tile of A_mn (th_mn - th_nm), the transposed tile of
+// th staged in LDS; one partial per tile, tiles row-major
+__global__ void __launch_bounds__(256) k_asym_tiles(const double* __restrict__ A,
+                                                    const double* __restrict__ th, int nb,
+                                                    double* __restrict__ part) {
+  __shared__ double tt[32][33];
+  __shared__ double red[16];
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 8 rows of 32 per pass
+  // tt[r][c] = th[(bj 32 + r)][(bi 32 + c)]: rows of the mirrored tile
+  for (int r = ty; r < 32; r += 8) {
+    const int m = bj * 32 + r, n = bi * 32 + tx;
+    tt[r][tx] = (m < nb && n < nb) ? th[(size_t)m * nb + n] : 0.0;
+  }
+  __syncthreads();
+  double s = 0.0;
+  for (int r = ty; r < 32; r += 8) {
+    const int m = bi * 32 + r, n = bj * 32 + tx;
+    if (m < nb && n < nb) s += A[(size_t)m * nb + n] * (th[(size_t)m * nb + n] - tt[tx][r]);
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v = 0.0;
+    for (int w = 0; w < 4; ++w) v += red[w];
+    part[(size_t)bi * gridDim.x + bj] = v;
+  }
+}
+
+// out = sum of the np tile partials in order (also into mirror)
+__global__ void k_sum_ordered(const double* __restrict__ part, int np, double* __restrict__ out,
+                              double* __restrict__ mirror) {
+  if (threadIdx.x != 0) return;
+  double v = 0.0;
+  for (int i = 0; i < np; ++i) v += part[i];
+  if (out) out[0] = v;
+  if (mirror) mirror[0] = v;
+}
+
 void band_dots_asym(Ctx& c, const double2* X, const double2* Y, int nvec, double* out0,
                     double* mirror0, const double* A, const double* theta, double* aout,
                     double* amirror) {
-  hipLaunchKernelGGL(k_band_dots_asym, dim3(nvec + 1), dim3(1024), 0, c.stream, X, Y, c.npw, out0,
-                     mirror0, A, theta, c.nb, aout, amirror);
+  if (c.nb <= 128) {
+    hipLaunchKernelGGL(k_band_dots_asym, dim3(nvec + 1), dim3(1024), 0, c.stream, X, Y, c.npw, out0,
+                       mirror0, A, theta, c.nb, aout, amirror);
+    ROKS_HIP(hipGetLastError());
+    return;
+  }
+  // many bands: the contraction over 32 x 32 tiles (coalesced transposed
+  // reads through LDS) and an ordered sum of the tiles' partials
+  if (nvec > 0) {
+    hipLaunchKernelGGL(k_band_dots_asym, dim3(nvec), dim3(1024), 0, c.stream, X, Y, c.npw, out0,
+                       mirror0, nullptr, theta, c.nb, aout, amirror);
+    ROKS_HIP(hipGetLastError());
+  }
+  const int t = cdiv(c.nb, 32);
+  hipLaunchKernelGGL(k_asym_tiles, dim3(t, t), dim3(256), 0, c.stream, A, theta, c.nb, c.d_gemm_part);
+  ROKS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(64), 0, c.stream, c.d_gemm_part, t * t, aout, amirror);
   ROKS_HIP(hipGetLastError());
 }
 
