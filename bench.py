@@ -1,9 +1,10 @@
 #!/usr/bin/env python
 """Benchmark of the ROKS hot path on one MI355X.
 
-Workload: the molecule-in-box cell (cubic 24 bohr box, 64^3 grid at the
-grid-rule cutoff of 8.77 Ha, 8 539 stored plane waves, 20 seeded atoms with
-4 Gaussian projectors each, 40 bands = 36 closed + 2 open + 2 virtual,
+Headline workload: the rocksalt oxide-vacancy supercell (3 x 3 x 3
+conventional cells, a = 8 bohr, one anion removed: 215 atoms, 96^3 grid at
+the grid-rule cutoff of 19.74 Ha, 28 889 stored plane waves, 8 Gaussian
+projectors per atom = 1 720, 432 bands = 428 closed + 2 open + 2 virtual,
 mixed-spin and triplet configurations of the singlet), FP64.
 
 One step = one pass of the whole hot path: densities, potentials and
@@ -18,6 +19,12 @@ Kernel times come from HIP events the library records on its own stream
 pass with every kernel family recorded (the per-family table), then the
 timed region with events only around the dominant family (the roofline
 entry), so the other launches run undisturbed.
+
+Extras on the same line: the FP32 tier on the same workload, the 64^3 /
+40-band molecule-in-box (configuration of the earlier headline), ROKS
+time-to-converge (plain FP64 against the FP32 ladder and the learned
+preconditioner, each judged by plain FP64 iterations), the uneven batch, and
+the oracle's rate on the host cores.
 
 Prints ONE JSON line.  Inputs are resident on the GPU when timing starts.
 """
@@ -38,56 +45,87 @@ from paper_2605_28637_amd import roks as rb  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 RESTART = 20
 
-# HBM traffic per launch of a kernel family, from the rocprofv3 FETCH_SIZE /
-# WRITE_SIZE passes summarised in profiles/ (scaled by the copy-kernel
-# calibration); reported only while the family's source is the one measured.
-TRAFFIC = {
-    "gemm_wdot": {"source": "paper_2605_28637_amd/csrc/gemm.hip",
-                  "sha256": "4ffac1e7ddd9c7e8e60c0b28f88d9cb3222e6aa1eda09955f7a09d5824fd674d",
-                  "bytes_per_launch": 3.0663e+07,
-                  "profile": "profiles/gemm_wdot_molecule64_fp64_traffic.md"},
-}
+# HBM traffic per launch of a kernel family on a workload, from the rocprofv3
+# FETCH_SIZE / WRITE_SIZE passes summarised in profiles/ (scaled by the
+# copy-kernel calibration); reported only while the sources of the family's
+# kernels are the ones measured.
+TRAFFIC = {}
 KERNELS = ("zpass_bwd", "plane_apply", "plane_density", "zpass_fwd", "fft3d", "gemm_wdot",
            "gemm_expand", "xc")
 
 
-def roofline(name, k):
-    """Roofline entry of one kernel family from its summed time and work."""
+def roofline(name, k, fp32=False):
+    """Roofline entry of one kernel family from its summed time and work: the
+    band products and expansions (gemm_*) against the FP64 matrix cores, the
+    transforms and pointwise passes against the vector units of their tier
+    (FP64 78.6, FP32 157.3 TFLOP/s), each against HBM when its algorithmic
+    flop/byte lies below that peak's ridge."""
     if not k["launches"] or k["ms_total"] <= 0:
         return None
     avg_s = k["ms_total"] * 1e-3 / k["launches"]
     by, fl = k["bytes"] / k["launches"], k["flops"] / k["launches"]
-    ridge = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    mfma = name.startswith("gemm")
+    peak = FP64_PEAK_TFLOPS if (mfma or not fp32) else FP32_VECTOR_PEAK_TFLOPS
+    ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)
     if fl > 0 and fl / by > ridge:
         ach = fl / avg_s / 1e12
-        return {"bound": "mfma", "kernel": name, "achieved": ach, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
-                "flops_per_launch": fl, "avg_launch_ms": avg_s * 1e3}
+        return {"bound": "mfma" if mfma else "alu", "kernel": name, "achieved": ach, "peak": peak,
+                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                "flops_per_launch": fl, "bytes_per_launch": by, "avg_launch_ms": avg_s * 1e3}
     ach = by / avg_s / 1e9
     return {"bound": "hbm", "kernel": name, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": by,
-            "avg_launch_ms": avg_s * 1e3}
+            "flops_per_launch": fl, "avg_launch_ms": avg_s * 1e3}
 
 
-def cpu_baseline(system):
-    """The oracle, as it stands, on a bounded sample: one CG iteration of the
-    same workload from the same start, on one host thread."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(system, nsample=12):
+    """The oracle, as it stands, on a bounded sample of the headline
+    workload: the band H-applications F^{X(n)}|n> (shell mode, what a CG step
+    applies per band) of `nsample` bands spread over every shell, timed with
+    the BLAS threads on all host cores and then on one; the potentials of the
+    same orbitals (one energy evaluation, part of every step) timed apart."""
     from threadpoolctl import threadpool_limits
 
     from oracle import roks as orc
-    with threadpool_limits(limits=1):
-        m = orc.Model(system)
-        psi = orc.orthonormalize(inputs.random_coefficients(m.miller, m.cell, m.nb, system["seed"]))
-        st = orc.CGState(psi=psi)
-        t0 = time.perf_counter()
-        orc.pcg_step(m, st)
-        dt = time.perf_counter() - t0
-    return {"value": m.nb / dt, "unit": "band H-applies/s", "cores": 1, "kind": "oracle",
-            "sample": "one oracle CG iteration (%d band applications of F^n plus line search) "
-                      "on the same 64^3 / 40-band workload, single host thread, %.1f s"
-                      % (m.nb, dt)}
+    cores = len(os.sched_getaffinity(0))
+    m = orc.Model(system)
+    psi = orc.orthonormalize(inputs.random_coefficients(m.miller, m.cell, m.nb, system["seed"]))
+    t0 = time.perf_counter()
+    pot = orc.potentials(m, psi)
+    t_pot = time.perf_counter() - t0
+    pot.u = None
+    idx = np.unique(np.linspace(0, m.nb - 1, nsample).astype(int))
+
+    def rate(limit):
+        with threadpool_limits(limits=limit):
+            t0 = time.perf_counter()
+            for n in idx:
+                X = m.band_shell[n]
+                if not m.shell_virtual[X]:
+                    orc.apply_shell_operator(m, pot, X, psi[n:n + 1])
+            return len(idx) / (time.perf_counter() - t0)
+
+    r_all, r_one = rate(cores), rate(1)
+    return {"value": r_all, "unit": "band H-applies/s", "cores": cores, "kind": "oracle",
+            "one_core_value": r_one, "cpu_model": _cpu_model(),
+            "energy_evaluation_s": t_pot,
+            "sample": "oracle F^{X(n)}|n> of %d of the %d oxide bands (every shell; 96^3, 1 720 "
+                      "projectors), BLAS threads on all %d host cores (one_core_value: one "
+                      "thread); the potentials of those orbitals formed beforehand, %.1f s, "
+                      "not in the rate" % (len(idx), m.nb, cores, t_pot)}
 
 
 def _converge(rb_system, c0, tol, precision, net, restart, switch_tol=1e-5, maxiter=3000):
@@ -100,38 +138,70 @@ def _converge(rb_system, c0, tol, precision, net, restart, switch_tol=1e-5, maxi
         r.set_mlp(net)
     it = 0
     if precision == rb.FP32:
-        _, n = r.solve(tol=switch_tol, maxiter=maxiter)
-        it += n
+        try:
+            _, n = r.solve(tol=switch_tol, maxiter=maxiter)
+            it += n
+        except rb.RoksError as e:
+            if e.status != 6:  # a stall above the FP32 resolution: move on to FP64
+                raise
         r.set_precision(rb.FP64)
     info, n = r.solve(tol=tol, maxiter=maxiter)
     return r, info, it + n
 
 
+def _judged(r, info, tol, net, restart, max_rounds=6, maxiter=3000):
+    """The plain FP64 method judges the result: three plain iterations (no
+    network, no restarts, fresh directions) from it must each stay within tol
+    of its energy; otherwise the variant solves on and is judged again.
+    Returns the judged energy, the iterations the judging took (its plain
+    iterations and any further solves) and the rounds."""
+    extra, rounds = 0, 0
+    E = info["E1"]
+    while True:
+        rounds += 1
+        r.set_mlp(None)
+        r.set_precision(rb.FP64)
+        r.set_restart(0)
+        r.reset_cg()
+        Es = [r.pcg_step()["E1"] for _ in range(3)]
+        extra += 3
+        drift = max(abs(e - E) for e in Es)
+        E = Es[-1]
+        if drift < tol or rounds >= max_rounds:
+            return E, extra, rounds, drift
+        r.set_restart(restart)
+        if net is not None:
+            r.set_mlp(net)
+        i2, n = r.solve(tol=tol, maxiter=maxiter)
+        extra += n
+        E = i2["E1"]
+
+
 def time_to_converge(system, tol, precision, net, restart):
     """Ground state from the seeded start, then the singlet from the
-    ground-state orbitals, then the singlet forces; wall time of all of it."""
+    ground-state orbitals, each judged by plain FP64 iterations, then the
+    singlet forces; wall time of all of it."""
     gs = inputs.with_configuration(system, "gs")
-    t0 = time.perf_counter()
     rg = rb.Roks(gs)
     c0 = inputs.random_coefficients(rg.miller(), gs["cell"], rg.nb, gs["seed"])
     rg.close()
+    t0 = time.perf_counter()
     rg, ig, itg = _converge(gs, c0, tol, precision, net, restart)
+    E_gs, jg, rounds_g, drift_g = _judged(rg, ig, tol, net, restart)
     c = rg.get_coeffs()
     rg.close()
     r, ie, ite = _converge(system, c, tol, precision, net, restart)
+    E_s, js, rounds_s, drift_s = _judged(r, ie, tol, net, restart)
     F = r.forces()
     r.synchronize()
     dt = time.perf_counter() - t0
-    # the plain FP64 method judges the final energy: three more iterations
-    r.set_mlp(None)
-    r.set_precision(rb.FP64)
-    r.set_restart(0)
-    r.reset_cg()
-    drift = max(abs(r.pcg_step()["E1"] - ie["E1"]) for _ in range(3))
     r.close()
-    return {"seconds": dt, "gs_iterations": itg, "singlet_iterations": ite, "E_gs": ig["E1"],
-            "E_singlet": ie["E1"], "excitation_Ha": ie["E1"] - ig["E1"], "forces": F,
-            "plain_fp64_drift_3_iterations_Ha": drift, "tol_Ha": tol,
+    return {"seconds": dt, "gs_iterations": itg + jg, "singlet_iterations": ite + js,
+            "E_gs": E_gs, "E_singlet": E_s, "excitation_Ha": E_s - E_gs, "forces": F,
+            "judge": {"plain_fp64_iterations": 3, "rounds_gs": rounds_g, "rounds_singlet": rounds_s,
+                      "drift_gs_Ha": drift_g, "drift_singlet_Ha": drift_s,
+                      "passed": bool(drift_g < tol and drift_s < tol)},
+            "tol_Ha": tol,
             "arithmetic": "fp32 tier to |dE| < 1e-5 Ha, then fp64" if precision == rb.FP32 else "fp64",
             "preconditioner": "learned rescaling of Teter" if net is not None else "Teter",
             "cg_restart_period": restart}
@@ -253,10 +323,16 @@ def converge_report(system, tol=1e-6):
         out[k] = v
     net.close()
     out["training"] = tr
-    out["speedup_mixed_learned_vs_plain_fp64"] = {
-        "stopping_rule": out["plain_fp64"]["seconds"] / out["mixed_learned"]["seconds"],
-        "to_reference": (out["plain_fp64"]["to_reference"]["seconds"]
-                         / out["mixed_learned"]["to_reference"]["seconds"])}
+    sec = {k: out[k]["seconds"] for k in ("plain_fp64", "plain_fp64_restart", "mixed_plain_restart",
+                                          "fp64_learned", "mixed_learned")}
+    out["speedups_judged"] = {
+        "mixed_learned_vs_plain_fp64": sec["plain_fp64"] / sec["mixed_learned"],
+        "mixed_learned_vs_plain_fp64_restart": sec["plain_fp64_restart"] / sec["mixed_learned"],
+        "learned_vs_plain_restart_fp64": sec["plain_fp64_restart"] / sec["fp64_learned"],
+        "fp32_tier_vs_fp64_restart": sec["plain_fp64_restart"] / sec["mixed_plain_restart"],
+        "fp32_tier_with_learned_vs_fp64_learned": sec["fp64_learned"] / sec["mixed_learned"]}
+    out["speedup_mixed_learned_vs_plain_fp64_to_reference"] = (
+        out["plain_fp64"]["to_reference"]["seconds"] / out["mixed_learned"]["to_reference"]["seconds"])
     return out
 
 
@@ -303,41 +379,6 @@ def batch_report(steps=8, workers=8):
             "batched_equals_sequential": bool(same)}
 
 
-def oxide_report(reps=3):
-    """The rocksalt oxide-vacancy supercell at full size (96^3, 28 889 stored
-    plane waves, 432 bands, 1 720 projectors): the all-band shell-operator
-    application F^n|n> (device in, device out) and one CG iteration, FP64 and
-    FP32 tier."""
-    import torch
-    s = inputs.oxide_vacancy()
-    out = {}
-    for name, prec in (("fp64", rb.FP64), ("fp32", rb.FP32)):
-        r = rb.Roks(s, precision=prec)
-        r.set_coeffs(inputs.random_coefficients(r.miller(), s["cell"], r.nb, s["seed"]), True)
-        y = torch.empty((r.nb, r.npw, 2), dtype=torch.float64, device="cuda")
-        r.apply_h_d(None, 0, y.data_ptr())  # energies and potentials, then one apply
-        r.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            r.apply_h_d(None, 0, y.data_ptr())
-        r.synchronize()
-        t_apply = (time.perf_counter() - t0) / reps
-        r.pcg_step()
-        r.synchronize()
-        t0 = time.perf_counter()
-        info = r.pcg_step()
-        r.synchronize()  # the step's stream-ordered tail included
-        t_step = time.perf_counter() - t0
-        out[name] = {"ms_per_all_band_apply": 1e3 * t_apply,
-                     "band_applies_per_s": r.nb / t_apply,
-                     "ms_per_cg_iteration": 1e3 * t_step, "trial_energies": info["evaluations"]}
-        del y
-        r.close()
-    out["workload"] = ("rocksalt 3x3x3 supercell, a = 8 bohr, one anion removed (215 atoms), "
-                       "96^3 grid, 432 bands, 8 projectors per atom")
-    return out
-
-
 def calibrate_copy(mib=512, reps=3):
     """A plain copy kernel of known size (y = 1.0 * x, FP32, contiguous) for
     scaling the FETCH_SIZE / WRITE_SIZE counters: it reads and writes
@@ -353,6 +394,71 @@ def calibrate_copy(mib=512, reps=3):
                       "read_bytes_per_launch": 4 * n, "write_bytes_per_launch": 4 * n}))
 
 
+def measure(system, precision, steps, warmup, table_steps=None):
+    """Steps of the whole hot path (one CG iteration + forces each) on one
+    context: a pass with every kernel family event-timed (the table), then the
+    timed region with events around the dominant family only."""
+    r = rb.Roks(system, precision=precision)
+    r.set_coeffs(inputs.random_coefficients(r.miller(), system["cell"], r.nb, system["seed"]), True)
+    for _ in range(warmup):
+        r.pcg_step()
+        r.forces()
+    r.synchronize()
+    r.timing_enable(True)
+    for _ in range(table_steps or steps):
+        r.pcg_step()
+        r.forces()
+    r.synchronize()
+    kernels = {k: r.timing_read(k) for k in KERNELS}
+    r.timing_enable(False)
+    fp32 = precision == rb.FP32
+    roofs = {k: roofline(k, v, fp32) for k, v in kernels.items()}
+    dom = max((k for k in kernels if roofs[k]), key=lambda k: kernels[k]["ms_total"])
+    r.timing_only(dom)
+    r.timing_enable(True)
+    r.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r.pcg_step()
+        r.forces()
+    r.synchronize()
+    elapsed = time.perf_counter() - t0
+    dom_live = r.timing_read(dom)
+    r.timing_enable(False)
+    r.timing_only(None)
+    nb, npw = r.nb, r.npw
+    r.close()
+    roof_live = roofline(dom, dom_live, fp32)
+    key = (dom, system["name"], precision)
+    if roof_live and key in TRAFFIC:
+        t = TRAFFIC[key]
+        digest = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read()
+                                         for f in t["sources"])).hexdigest()
+        if digest == t["sha256"]:
+            roof_live["traffic"] = t["bytes_per_launch"]
+            roof_live["traffic_source"] = t["profile"]
+    # the band H-apply pipeline (z pass G->r, plane multiply, z pass r->G);
+    # the G->r z pass also serves every density evaluation, so its time and
+    # bytes are prorated to the H-apply launches
+    na = kernels["plane_apply"]["launches"]
+    zb = kernels["zpass_bwd"]
+    frac_zb = na / max(1, zb["launches"])
+    happ_ms = (kernels["plane_apply"]["ms_total"] + kernels["zpass_fwd"]["ms_total"]
+               + frac_zb * zb["ms_total"])
+    happ_bytes = (kernels["plane_apply"]["bytes"] + kernels["zpass_fwd"]["bytes"]
+                  + frac_zb * zb["bytes"])
+    pipeline = {"achieved_GBs": happ_bytes / (happ_ms * 1e-3) / 1e9 if happ_ms else None,
+                "frac_hbm": happ_bytes / (happ_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if happ_ms else None,
+                "ms_per_all_band_apply": happ_ms / max(1, na),
+                "band_applies_per_s": nb * na / (happ_ms * 1e-3) if happ_ms else None}
+    return {"nb": nb, "npw": npw, "elapsed": elapsed, "steps": steps,
+            "band_applies_per_s": nb * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
+            "roofline": roof_live,
+            "kernels": {k: dict(v, roofline_frac=(roofs[k] or {}).get("frac"))
+                        for k, v in kernels.items()},
+            "h_apply_pipeline": pipeline}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -361,7 +467,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--no-oxide", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="the headline line only (no FP32 tier, molecule, converge, batch, CPU legs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the copy kernel that scales the HBM byte counters")
     args = ap.parse_args()
@@ -373,98 +480,48 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    if not args.no_oxide:
-        # PyTorch (device buffers of the oxide leg) carries its own HIP
-        # runtime: its GPU context first
-        import torch
-        torch.zeros(1, device="cuda")
-        torch.cuda.synchronize()
-    system = inputs.molecule_box()
-    r = rb.Roks(system)
-    r.set_coeffs(inputs.random_coefficients(r.miller(), system["cell"], r.nb, system["seed"]), True)
-    for _ in range(args.warmup):
-        r.pcg_step()
-        r.forces()
-    r.synchronize()
-    # per-family figures: every launch bracketed by events (which slow the
-    # step), so this pass is not the timed one
-    r.timing_enable(True)
-    for _ in range(args.steps):
-        r.pcg_step()
-        r.forces()
-    r.synchronize()
-    kernels = {k: r.timing_read(k) for k in KERNELS}
-    r.timing_enable(False)
-    roofs = {k: roofline(k, v) for k, v in kernels.items()}
-    dom = max((k for k in kernels if roofs[k]), key=lambda k: kernels[k]["ms_total"])
-    # the timed region: events only around the dominant family's launches
-    r.timing_only(dom)
-    r.timing_enable(True)
-    r.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        r.pcg_step()
-        r.forces()
-    r.synchronize()
-    elapsed = time.perf_counter() - t0
-    dom_live = r.timing_read(dom)
-    r.timing_enable(False)
-    r.timing_only(None)
-    nb, npw = r.nb, r.npw
-    r.close()
-    roof_live = roofline(dom, dom_live)
-    if roof_live and dom in TRAFFIC:
-        t = TRAFFIC[dom]
-        src = os.path.join(ROOT, t["source"])
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if digest == t["sha256"]:
-            roof_live["traffic"] = t["bytes_per_launch"]
-            roof_live["traffic_source"] = t["profile"]
-
-    # the band H-apply pipeline (z pass G->r, plane multiply, z pass r->G);
-    # the G->r z pass also serves every density evaluation, so its time and
-    # bytes are prorated to the H-apply launches
-    na = kernels["plane_apply"]["launches"]
-    zb = kernels["zpass_bwd"]
-    frac_zb = na / max(1, zb["launches"])
-    happ_ms = (kernels["plane_apply"]["ms_total"] + kernels["zpass_fwd"]["ms_total"]
-               + frac_zb * zb["ms_total"])
-    happ_bytes = (kernels["plane_apply"]["bytes"] + kernels["zpass_fwd"]["bytes"]
-                  + frac_zb * zb["bytes"])
-
+    system = inputs.oxide_vacancy()
+    head = measure(system, rb.FP64, args.steps, args.warmup, table_steps=min(args.steps, 4))
     out = {
         "metric": "band H-applies/s",
-        "value": nb * args.steps / elapsed,
+        "value": head["band_applies_per_s"],
         "unit": "band H-applies/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "molecule-in-box: cubic 24 bohr, 64^3 grid, ecut 8.77 Ha, "
-                               "%d stored plane waves, 20 atoms x 4 projectors, %d bands "
-                               "(36 closed + 2 open + 2 virtual), mixed-spin + triplet; step = "
-                               "one ROKS CG iteration + forces" % (npw, nb),
-                   "precision": "fp64", "bands": nb, "grid": [64, 64, 64]},
-        "roofline": roof_live,
-        "kernels": {k: dict(v, roofline_frac=(roofs[k] or {}).get("frac"))
-                    for k, v in kernels.items()},
-        "h_apply_pipeline": {"achieved_GBs": happ_bytes / (happ_ms * 1e-3) / 1e9 if happ_ms else None,
-                             "frac_hbm": (happ_bytes / (happ_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
-                                          if happ_ms else None),
-                             "ms_per_all_band_apply": happ_ms / max(1, na),
-                             "band_applies_per_s": nb * na / (happ_ms * 1e-3) if happ_ms else None},
+        "config": {"workload": "rocksalt oxide-vacancy supercell: 3x3x3 conventional cells, "
+                               "a = 8 bohr, one anion removed (215 atoms), 96^3 grid, ecut "
+                               "19.74 Ha, %d stored plane waves, 8 Gaussian projectors per atom "
+                               "(1 720), %d bands (428 closed + 2 open + 2 virtual), mixed-spin "
+                               "+ triplet; step = one ROKS CG iteration + forces"
+                               % (head["npw"], head["nb"]),
+                   "precision": "fp64", "bands": head["nb"], "grid": [96, 96, 96]},
+        "roofline": head["roofline"],
+        "kernels": head["kernels"],
+        "h_apply_pipeline": head["h_apply_pipeline"],
     }
-    if not args.no_converge:
-        out["time_to_converge"] = converge_report(system)
-    if not args.no_batch:
-        out["batch"] = batch_report()
-    if not args.no_oxide:
-        out["oxide"] = oxide_report()
+    if not args.no_extras:
+        t32 = measure(system, rb.FP32, args.steps, args.warmup, table_steps=2)
+        out["oxide_fp32_tier"] = {k: t32[k] for k in ("band_applies_per_s", "ms_per_step",
+                                                       "roofline", "h_apply_pipeline")}
+        mol = inputs.molecule_box()
+        m = measure(mol, rb.FP64, max(args.steps, 20), args.warmup, table_steps=10)
+        out["molecule_64"] = {
+            "workload": "molecule-in-box: cubic 24 bohr, 64^3 grid, ecut 8.77 Ha, %d stored plane "
+                        "waves, 20 atoms x 4 projectors, %d bands; step = one ROKS CG iteration "
+                        "+ forces, fp64" % (m["npw"], m["nb"]),
+            **{k: m[k] for k in ("band_applies_per_s", "ms_per_step", "roofline", "kernels",
+                                 "h_apply_pipeline")}}
+        if not args.no_converge:
+            out["time_to_converge"] = converge_report(mol)
+        if not args.no_batch:
+            out["batch"] = batch_report()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(system)
     print(json.dumps(out))

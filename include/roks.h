@@ -118,7 +118,9 @@ typedef struct {
 typedef struct {
   double cell[3][3];  /* rows a1, a2, a3 (bohr); non-singular               */
   double ecut;        /* Ha, sphere |G|^2/2 <= ecut                        */
-  int32_t grid[3];    /* FFT grid; every size of the form 2^a 3^b 5^c <= 128 */
+  int32_t grid[3];    /* FFT grid; every size of the form 2^a 3^b 5^c <= 128;
+                         {0, 0, 0}: the grid rule G_cut = pi N_d / (2 |a_d|),
+                         N_d the next such size >= 2 sqrt(2 ecut) |a_d| / pi  */
   int32_t natoms;
   const int32_t* species; /* [natoms] index into spec                     */
   const double* pos;      /* [natoms][3] Cartesian bohr                   */
@@ -170,6 +172,12 @@ roks_status roks_destroy(roks_ctx ctx);
 const char* roks_last_error(roks_ctx ctx);
 const char* roks_version(void);
 
+/* The FFT grid of the grid rule (Sec. III's cells: the density-exact grid
+ * of the cutoff sphere), what roks_create takes for grid = {0, 0, 0}:
+ * N_d = the smallest 2^a 3^b 5^c >= 2 sqrt(2 ecut) |a_d| / pi.  Host only,
+ * no device needed.  ROKS_ERR_ARG for ecut <= 0 or NULL pointers. */
+roks_status roks_grid_rule(const double cell[3][3], double ecut, int32_t grid[3]);
+
 /* Sizes: stored plane waves, FFT grid, projectors (l = 1 counts 3), bands. */
 roks_status roks_sizes(roks_ctx ctx, int32_t* npw, int32_t grid[3], int32_t* nproj,
                        int32_t* nbands);
@@ -178,7 +186,11 @@ roks_status roks_gvectors(roks_ctx ctx, int32_t* miller);
 
 /* Set the orbitals from c [nbands][npw][2]; orthonormalize != 0 applies the
  * Cholesky orthonormalisation in band order (Gram-Schmidt).  Resets the CG
- * state.  roks_pcg_step / roks_solve take the orbitals to be orthonormal
+ * state.  The G = 0 coefficient of a real orbital is real: roks_set_coeffs
+ * rejects a nonzero Im c_n(0) with ROKS_ERR_ARG; roks_set_coeffs_d (which
+ * does not read the data on the host) sets Im c_n(0) to zero.  Linearly
+ * dependent bands (a Cholesky pivot below 1e-12 of its Gram diagonal) give
+ * ROKS_ERR_NOT_PD.  roks_pcg_step / roks_solve take the orbitals to be orthonormal
  * (every step keeps them so): pass orthonormalize = 0 only for orthonormal
  * input.  roks_get_coeffs copies the current orbitals out. */
 roks_status roks_set_coeffs(roks_ctx ctx, const double* c, int32_t orthonormalize);
@@ -197,11 +209,14 @@ roks_status roks_set_positions(roks_ctx ctx, const double* pos);
  *     bands); h_out is [nbands][npw][2].
  *   channel_mask != 0: bit (2 L + s) selects H^{sigma L} (Eq. for H^{sigma L}:
  *     T + V_NL + V_ext + V_H[rho_L] + v_xc^sigma[rho_L]); h_out is
- *     [popcount(mask)][nbands][npw][2] in increasing bit order. */
+ *     [popcount(mask)][nbands][npw][2] in increasing bit order.
+ * Input bands are real orbitals: roks_apply_h rejects a nonzero Im c_n(0)
+ * (ROKS_ERR_ARG); roks_apply_h_d does not read it (takes it as zero). */
 roks_status roks_apply_h(roks_ctx ctx, const double* c_in, uint32_t channel_mask,
                          double* h_out);
 roks_status roks_apply_h_d(roks_ctx ctx, const void* c_in_dev, uint32_t channel_mask,
                            void* h_out_dev);
+
 
 /* Energies of the current orbitals and, if grad != NULL, the out-of-subspace
  * gradient g_I,n = (1 - sum_m |m><m|) F^n|n> (Eq. gradient), [nbands][npw][2];
@@ -211,8 +226,10 @@ roks_status roks_energy_gradient(roks_ctx ctx, roks_energies* e, double* grad,
                                  double* theta);
 
 /* Subspace matrices of the current orbitals, each [nbands][nbands]
- * row-major: R_mn (Eq. r_matrix_singlet), the pair curvature kappa_mn and the
- * rotation generator A_mn (Eqs. prec_grad_IIb/c).  Any pointer may be NULL. */
+ * row-major: R_mn (Eq. r_matrix_singlet, with <m|F^c|n> in the block of the
+ * virtual bands, zero there without a closed shell), the pair curvature
+ * kappa_mn and the rotation generator A_mn (Eqs. prec_grad_IIb/c).  Any
+ * pointer may be NULL. */
 roks_status roks_subspace(roks_ctx ctx, double* R, double* kappa, double* A);
 
 /* One preconditioned CG iteration with line search (Eqs. orbital_update,
@@ -236,7 +253,13 @@ roks_status roks_set_restart(roks_ctx ctx, int32_t period);
 roks_status roks_set_precision(roks_ctx ctx, int32_t precision);
 /* Iterate roks_pcg_step until |E_{i+1} - E_i| < tol on two consecutive
  * iterations or maxiter; *iterations receives the count, *last the final
- * step's info (either may be NULL). */
+ * step's info (either may be NULL).  A stalled step (no decrease found) does
+ * not count toward the two: the carried directions are dropped and the step
+ * is retried from the preconditioned gradient.  If that stalls too, the solve
+ * ends with ROKS_OK when the first-order decrease the line search could reach,
+ * |dE0| times its smallest trial step, is below max(tol, r |E|) (r = 1e-12 in
+ * FP64, 2e-6 in the FP32 tier: the energy's resolution), and otherwise with
+ * ROKS_ERR_LINESEARCH (orbitals of the last accepted step). */
 roks_status roks_solve(roks_ctx ctx, double tol, int32_t maxiter, roks_step_info* last,
                        int32_t* iterations);
 

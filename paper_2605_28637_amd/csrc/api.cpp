@@ -81,11 +81,26 @@ void check_finite_host(const roks::Ctx& c, const double* v, size_t n) {
     ROKS_CHECK(std::isfinite(v[i]), ROKS_ERR_NAN, "non-finite input coefficient");
 }
 
+// c(-G) = conj(c(G)) makes c(0) real: a nonzero Im c_n(0) is no real orbital
+void check_g0_real_host(const roks::Ctx& c, const double* v) {
+  for (int n = 0; n < c.nb; ++n)
+    ROKS_CHECK(v[(size_t)n * c.npw * 2 + 1] == 0.0, ROKS_ERR_ARG,
+               "Im c_n(G = 0) must be zero (real orbitals)");
+}
+
 }  // namespace
 
 extern "C" {
 
-const char* roks_version(void) { return "roks-gfx950 0.1 (fp64 tier)"; }
+const char* roks_version(void) { return "roks-gfx950 0.2"; }
+
+roks_status roks_grid_rule(const double cell[3][3], double ecut, int32_t grid[3]) {
+  if (!cell || !grid || !(ecut > 0) || !std::isfinite(ecut)) return ROKS_ERR_ARG;
+  int g[3];
+  roks::grid_rule(cell, ecut, g);
+  for (int d = 0; d < 3; ++d) grid[d] = g[d];
+  return ROKS_OK;
+}
 
 roks_status roks_create(const roks_system* sys, void* hip_stream, roks_ctx* out) {
   if (!out) return ROKS_ERR_ARG;
@@ -146,6 +161,7 @@ roks_status roks_set_coeffs(roks_ctx ctx, const double* cf, int32_t orthonormali
   return guard(ctx, [&](roks::Ctx& c) {
     ROKS_CHECK(cf, ROKS_ERR_ARG, "coefficients are NULL");
     check_finite_host(c, cf, (size_t)c.nb * c.npw * 2);
+    check_g0_real_host(c, cf);
     upload_bands(c, c.d_psi, cf);
     if (orthonormalize) roks::orthonormalize(c, c.d_psi);
     ROKS_HIP(hipStreamSynchronize(c.stream));
@@ -160,6 +176,7 @@ roks_status roks_set_coeffs_d(roks_ctx ctx, const void* cf, int32_t orthonormali
     ROKS_CHECK(cf, ROKS_ERR_ARG, "coefficients are NULL");
     ROKS_HIP(hipMemcpyAsync(c.d_psi, cf, (size_t)c.nb * c.npw * sizeof(double2),
                             hipMemcpyDeviceToDevice, c.stream));
+    roks::launch_zero_g0_imag(c, c.d_psi, c.nb);
     if (orthonormalize) roks::orthonormalize(c, c.d_psi);
     c.have_orbitals = true;
     c.potentials_valid = false;
@@ -213,6 +230,7 @@ roks_status roks_apply_h(roks_ctx ctx, const double* c_in, uint32_t mask, double
     const double2* src = c.d_psi;
     if (c_in) {
       check_finite_host(c, c_in, (size_t)c.nb * c.npw * 2);
+      check_g0_real_host(c, c_in);
       upload_bands(c, c.d_in, c_in);
       src = c.d_in;
     }
@@ -255,7 +273,7 @@ roks_status roks_energy_gradient(roks_ctx ctx, roks_energies* e, double* grad, d
 
 roks_status roks_subspace(roks_ctx ctx, double* R, double* kappa, double* A) {
   return guard(ctx, [&](roks::Ctx& c) {
-    roks::energy_gradient(c, nullptr);
+    roks::energy_gradient(c, nullptr, nullptr, true);
     const size_t nn = (size_t)c.nb * c.nb * sizeof(double);
     if (R) ROKS_HIP(hipMemcpyAsync(R, c.d_R, nn, hipMemcpyDeviceToHost, c.stream));
     if (kappa) ROKS_HIP(hipMemcpyAsync(kappa, c.d_kappa, nn, hipMemcpyDeviceToHost, c.stream));
@@ -296,16 +314,33 @@ roks_status roks_solve(roks_ctx ctx, double tol, int32_t maxiter, roks_step_info
   return guard(ctx, [&](roks::Ctx& c) {
     ROKS_CHECK(tol > 0 && maxiter > 0, ROKS_ERR_ARG, "tol and maxiter must be > 0");
     int hits = 0, it = 0;
+    bool retried = false, linesearch_failed = false;
     roks_step_info info{};
     while (it < maxiter) {
       roks::pcg_step(c, &info);
       ++it;
+      if (info.stalled) {
+        // a stall moves nothing: drop the carried directions and retry once
+        // from the preconditioned gradient before judging it
+        if (!retried) {
+          roks::reset_cg(c);
+          retried = true;
+          continue;
+        }
+        const double resolution = (c.prec == ROKS_FP32 ? 2e-6 : 1e-12) * std::max(1.0, std::fabs(info.E0));
+        if (std::fabs(info.dE0) * roks::smallest_trial_step(c) >= std::max(tol, resolution))
+          linesearch_failed = true;
+        break;
+      }
+      retried = false;
       hits = std::fabs(info.E1 - info.E0) < tol ? hits + 1 : 0;
       if (hits >= 2) break;
     }
     ROKS_HIP(hipStreamSynchronize(c.stream));
     if (last) *last = info;
     if (iterations) *iterations = it;
+    ROKS_CHECK(!linesearch_failed, ROKS_ERR_LINESEARCH,
+               "no energy decrease found although the gradient predicts one above the tolerance");
   });
 }
 

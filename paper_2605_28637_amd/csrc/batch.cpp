@@ -128,7 +128,9 @@ roks_status roks_batch_solve(roks_batch b, double tol, int32_t maxiter, double s
     roks_status st = ROKS_OK;
     if (switch_tol > 0 && ctx->c.prec == ROKS_FP32) {
       st = roks_solve(ctx, switch_tol, maxiter, &info, &it);
-      if (st == ROKS_OK) st = roks_set_precision(ctx, ROKS_FP64);
+      // a search that stalls in the FP32 tier above its resolution moves to
+      // FP64 all the same (the orbitals are those of the last accepted step)
+      if (st == ROKS_OK || st == ROKS_ERR_LINESEARCH) st = roks_set_precision(ctx, ROKS_FP64);
     }
     if (st == ROKS_OK) st = roks_solve(ctx, tol, maxiter, &info, &it2);
     if (iterations) iterations[i] = it + it2;

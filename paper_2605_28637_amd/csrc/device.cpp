@@ -3,7 +3,6 @@
 #include <cmath>
 #include <cstring>
 
-#include <rocblas/rocblas.h>
 
 #include "roks_internal.h"
 
@@ -30,26 +29,6 @@ static int plane_chunks(int n3, int npairs, int cus) {
   return best;
 }
 
-void* blas_handle(Ctx& c) {
-  if (!c.blas) {
-    rocblas_handle h = nullptr;
-    ROKS_CHECK(rocblas_create_handle(&h) == rocblas_status_success, ROKS_ERR_HIP,
-               "rocblas_create_handle failed");
-    c.blas = h;
-    c.blas_stream = nullptr;
-    // deterministic sums: no atomics
-    ROKS_CHECK(rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed) == rocblas_status_success,
-               ROKS_ERR_HIP, "rocblas_set_atomics_mode failed");
-  }
-  if (c.blas_stream != c.stream) {
-    ROKS_CHECK(rocblas_set_stream(static_cast<rocblas_handle>(c.blas), c.stream) ==
-                   rocblas_status_success,
-               ROKS_ERR_HIP, "rocblas_set_stream failed");
-    c.blas_stream = c.stream;
-  }
-  return c.blas;
-}
-
 void ensure_side_stream(Ctx& c) {
   if (c.side) return;
   ROKS_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
@@ -72,6 +51,15 @@ void init_device(Ctx& c, void* stream) {
   int cus = 0;
   ROKS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device));
   c.nchunk = plane_chunks(c.N[2], c.npairs, std::max(1, cus));
+  if (c.N[0] == c.N[1] && line_split(c.N[0], &c.lines_G, &c.lines_P)) {
+    // several line-kernel workgroups share a CU: about two rounds of them
+    const int n = c.N[0], nh = 2 * c.hmax + 1;
+    const size_t lds = (size_t)(n + nh * (n + 1)) * 16 + 1024;
+    const int per_cu = std::max(1, std::min(8, (int)((160 * 1024) / lds)));
+    c.nchunk = std::max(1, std::min(c.npairs, cdiv(2 * cus * per_cu, c.N[2])));
+  } else {
+    c.lines_G = c.lines_P = 0;
+  }
 
   c.d_miller = dalloc<int32_t>(c, 3 * npw);
   c.d_g2 = dalloc<double>(c, npw);
@@ -162,7 +150,8 @@ void init_device(Ctx& c, void* stream) {
   c.d_force = dalloc<double>(c, 3 * (size_t)std::max(1, c.natoms));
   c.d_kinw_shell = dalloc<double>(c, nb);
   c.d_ones = dalloc<double>(c, nb);
-  c.d_potidx = dalloc<int32_t>(c, (size_t)5 * nb);
+  c.d_potidx = dalloc<int32_t>(c, (size_t)6 * nb);
+  c.d_kinw_closed = dalloc<double>(c, nb);
 }
 
 void upload_static(Ctx& c) {
@@ -183,6 +172,43 @@ void upload_static(Ctx& c) {
     }
   }
   up(c.d_colpos, colpos.data(), colpos.size() * sizeof(int32_t));
+  // line kernels: LDS position of every column in the pruned plane (row
+  // h + hmax, stride N + 1) and the k range of each row, which must be one
+  // contiguous run (else the LDS-plane kernels are used)
+  if (c.lines_G > 0) {
+    const int n = c.N[0], nh = 2 * c.hmax + 1, PS = n + 1;
+    std::vector<int32_t> colidx(c.ncol), kr(2 * (size_t)nh);
+    std::vector<int32_t> cnt(nh, 0);
+    for (int r = 0; r < nh; ++r) {
+      kr[2 * r] = 1 << 20;
+      kr[2 * r + 1] = -(1 << 20);
+    }
+    bool ok = true;
+    for (int col = 0; col < c.ncol; ++col) {
+      int h = colpos[2 * col], k = colpos[2 * col + 1];
+      const int hs = 2 * h > n ? h - n : h, ks = 2 * k > n ? k - n : k;
+      if (hs < -c.hmax || hs > c.hmax) {
+        ok = false;
+        break;
+      }
+      const int r = hs + c.hmax;
+      colidx[col] = r * PS + k;
+      kr[2 * r] = std::min(kr[2 * r], ks);
+      kr[2 * r + 1] = std::max(kr[2 * r + 1], ks);
+      cnt[r]++;
+    }
+    for (int r = 0; ok && r < nh; ++r)
+      if (cnt[r] > 0 && cnt[r] != kr[2 * r + 1] - kr[2 * r] + 1) ok = false;
+    if (ok) {
+      c.d_colidx = dalloc<int32_t>(c, colidx.size());
+      c.d_krange = dalloc<int32_t>(c, kr.size());
+      up(c.d_colidx, colidx.data(), colidx.size() * sizeof(int32_t));
+      up(c.d_krange, kr.data(), kr.size() * sizeof(int32_t));
+      ROKS_HIP(hipStreamSynchronize(c.stream));
+    } else {
+      c.lines_G = c.lines_P = 0;
+    }
+  }
   std::vector<double2> tw[3];  // host sources stay alive until the stream synchronises below
   std::vector<float2> tw32[3];
   for (int d = 0; d < 3; ++d) {
@@ -203,18 +229,26 @@ void upload_static(Ctx& c) {
   up(c.d_atom_proj_cnt, c.atom_proj_cnt.data(), c.atom_proj_cnt.size() * sizeof(int32_t));
   up(c.d_band_shell, c.band_shell.data(), c.band_shell.size() * sizeof(int32_t));
   // shell-mode kinetic weights and potential indices; channel-mode indices
-  std::vector<double> kw, ones;
+  std::vector<double> kw, ones, kwc;
   std::vector<int32_t> pidx;
   kw.assign(c.nb, 0.0);
   ones.assign(c.nb, 1.0);
-  pidx.assign((size_t)5 * c.nb, -1);
+  kwc.assign(c.nb, 0.0);
+  pidx.assign((size_t)6 * c.nb, -1);
+  int Xc = -1;
+  for (int X = 0; X < c.nshell; ++X)
+    if (c.shell_closed[X] && Xc < 0) Xc = X;
   for (int n = 0; n < c.nb; ++n) {
     const int X = c.band_shell[n];
     kw[n] = c.shell_virtual[X] ? 0.0 : c.shell_w[X];
     pidx[n] = c.shell_virtual[X] ? -1 : X;
     for (int ch = 0; ch < 4; ++ch) pidx[(size_t)(1 + ch) * c.nb + n] = ch;
+    // row 5: the closed-shell operator F^c for every band
+    pidx[(size_t)5 * c.nb + n] = Xc;
+    kwc[n] = Xc >= 0 ? c.shell_w[Xc] : 0.0;
   }
   up(c.d_kinw_shell, kw.data(), kw.size() * sizeof(double));
+  up(c.d_kinw_closed, kwc.data(), kwc.size() * sizeof(double));
   up(c.d_ones, ones.data(), ones.size() * sizeof(double));
   up(c.d_potidx, pidx.data(), pidx.size() * sizeof(int32_t));
   ROKS_HIP(hipStreamSynchronize(c.stream));
@@ -273,8 +307,6 @@ void free_device(Ctx& c) {
   if (c.side) (void)hipStreamDestroy(c.side);
   c.side = nullptr;
   c.ev_fork = c.ev_join = nullptr;
-  if (c.blas) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(c.blas));
-  c.blas = nullptr;
   if (c.own_stream && c.stream) (void)hipStreamDestroy(c.stream);
   c.stream = nullptr;
   c.own_stream = false;

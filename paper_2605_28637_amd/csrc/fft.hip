@@ -20,6 +20,7 @@
 // Band coefficients in and out are FP64 in both tiers; the column buffer,
 // the plane arithmetic and the potentials are in the tier's precision R.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <map>
 #include <mutex>
@@ -328,8 +329,9 @@ __global__ void __launch_bounds__(512) k_zpass_bwd(const double2* __restrict__ v
     if (e > d.lmax - d.lmin) continue;
     const int l = d.lmin + e;
     const int g = d.base + e;
-    const double2 a = c1[g];
-    const double2 b = has2 ? c2[g] : make_double2(0.0, 0.0);
+    double2 a = c1[g];
+    double2 b = has2 ? c2[g] : make_double2(0.0, 0.0);
+    if (g == 0) a.y = b.y = 0.0;  // c(0) of a real orbital is real: Im c(0) is not read
     const C2<R> v = mk<R>((R)(a.x - b.y), (R)(a.y + b.x));    // c1 + i c2
     const C2<R> vm = mk<R>((R)(a.x + b.y), (R)(b.x - a.y));   // conj(c1) + i conj(c2)
     buf[(2 * c) * LS + wrap(l, N3)] = v;
@@ -695,6 +697,395 @@ __global__ void __launch_bounds__(512) k_fft_plane(double2* __restrict__ data, F
 }
 
 // ---------------------------------------------------------------------------
+// plane pass with the lines in registers ("line kernels")
+//
+// For square planes N1 = N2 = N = G P (G a power of two, P <= 16) the plane
+// work of a band pair runs on a pruned intermediate: only the nh = 2 hmax + 1
+// rows |h| <= hmax ever hold data, so LDS holds nh x N values (not N x N).
+//   y inverse : per row h, the length-N transform along k;
+//   x phase   : per column y, the length-N transform along h (nh nonzero
+//               inputs), the potential multiply (apply) or |u|^2 (density),
+//               and for apply the forward transform, keeping rows |h| <= hmax;
+//   y forward : per row, back along k (apply).
+// Each line is owned by a group of G consecutive lanes, each lane holding P
+// points in registers: the four-step split N = G x P, a length-P transform in
+// registers, the twiddle exp(+-2 pi i t k / N), and a length-G transform
+// across the group's lanes as a radix-2 network on lane shuffles (decimation
+// in frequency: lane l ends with the outputs k + P bitrev(l)).  The forward
+// transform is the exact conjugate transpose of the inverse (the network run
+// backwards), so it takes its input in the order the inverse leaves it.  No
+// stage barrier inside a line; three workgroup barriers per pair.
+// ---------------------------------------------------------------------------
+template <int P>
+struct RegFac {
+  // the first factor of a composite length: the largest of 8, 4, 2 dividing
+  // it (3 or 5 for odd lengths)
+  static constexpr int A = (P % 8 == 0 && P > 8) ? 8 : (P % 4 == 0 && P > 4) ? 4 : (P % 2 == 0 && P > 2) ? 2
+                           : (P % 3 == 0 && P > 3) ? 3 : (P % 5 == 0 && P > 5) ? 5 : P;
+};
+
+// length-P DFT of v (kernel exp(s 2 pi i n k / P)) in registers; tw[m] =
+// exp(-2 pi i m / Ntw) with Ntw = P * tws
+template <typename R, int P, int A = RegFac<P>::A>
+struct RegDft {
+  static constexpr int B = P / A;
+  static __device__ __forceinline__ void run(C2<R>* v, int s, const C2<R>* tw, int tws) {
+    // n = B n1 + n2, k = k1 + A k2
+    C2<R> y[B][A];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+      C2<R> a[A];
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) a[n1] = v[B * n1 + n2];
+      RegDft<R, A>::run(a, s, tw, tws * B);
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) {
+        C2<R> w = tw[(n2 * k1) * tws];
+        if (s > 0) w.y = -w.y;
+        y[n2][k1] = (n2 * k1 == 0) ? a[k1] : cmul<R>(a[k1], w);
+      }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      C2<R> b[B];
+#pragma unroll
+      for (int n2 = 0; n2 < B; ++n2) b[n2] = y[n2][k1];
+      RegDft<R, B>::run(b, s, tw, tws * A);
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = b[k2];
+    }
+  }
+};
+template <typename R, int P>
+struct RegDft<R, P, P> {
+  static __device__ __forceinline__ void run(C2<R>* v, int s, const C2<R>*, int) {
+    if constexpr (P > 1) Dft<R, P>::run(v, s);
+  }
+};
+
+// the value of lane (lane ^ m) for m in {1, 2, 4, 8}, by DPP moves within a
+// row of 16 lanes: quad permutations for 1 and 2; for 4 and 8 the row shifted
+// both ways (row_shl: lane i reads lane i + m, row_shr: lane i - m) and the
+// side picked by the lane's bit m
+__device__ __forceinline__ int xor_lane(int v, int m, int lane) {
+  switch (m) {
+    case 1: return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
+    case 2: return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
+    case 4: {
+      // banks (groups of 4 lanes) 0, 2 read lane + 4, banks 1, 3 lane - 4
+      const int up = __builtin_amdgcn_update_dpp(0, v, 0x104, 0xF, 0x5, false);   // row_shl:4
+      return __builtin_amdgcn_update_dpp(up, v, 0x114, 0xF, 0xA, false);          // row_shr:4
+    }
+    case 8: {
+      // banks 0, 1 read lane + 8, banks 2, 3 lane - 8
+      const int up = __builtin_amdgcn_update_dpp(0, v, 0x108, 0xF, 0x3, false);   // row_shl:8
+      return __builtin_amdgcn_update_dpp(up, v, 0x118, 0xF, 0xC, false);          // row_shr:8
+    }
+    default: return __shfl_xor(v, m, 64);
+  }
+}
+__device__ __forceinline__ float xor_lane(float v, int m, int lane) {
+  return __int_as_float(xor_lane(__float_as_int(v), m, lane));
+}
+__device__ __forceinline__ double xor_lane(double v, int m, int lane) {
+  const int lo = xor_lane(__double2loint(v), m, lane);
+  const int hi = xor_lane(__double2hiint(v), m, lane);
+  return __hiloint2double(hi, lo);
+}
+template <typename R>
+__device__ __forceinline__ C2<R> shfl_xor2(C2<R> v, int m, int lane) {
+  return mk<R>(xor_lane(v.x, m, lane), xor_lane(v.y, m, lane));
+}
+
+// one line of length N = G P over the G lanes of a group (t: lane in group)
+template <typename R, int G, int P>
+struct LineFft {
+  static constexpr int N = G * P;
+  // G->r, kernel exp(+2 pi i h x / N): on entry v[j] = in[t + G j]; on exit
+  // v[k] = out[k + P bitrev(t)]
+  static __device__ __forceinline__ void inv(C2<R>* v, int t, const C2<R>* tw0) {
+    // the twiddles are re-read from LDS for every line (an opaque offset keeps
+    // the compiler from holding all of them in registers across the pairs)
+    int o = 0;
+    asm volatile("" : "+v"(o));
+    const C2<R>* tw = tw0 + o;
+    RegDft<R, P>::run(v, +1, tw, G);
+#pragma unroll
+    for (int k = 1; k < P; ++k) {
+      C2<R> w = tw[t * k];
+      w.y = -w.y;
+      v[k] = cmul<R>(v[k], w);
+    }
+    // radix-2 stages across the lanes, without branches: a lane with bit h
+    // clear keeps v + p, one with it set (p - v) w, as (p + sg v) w' with
+    // sg = +-1 and w' = 1 or w
+#pragma unroll
+    for (int h = G / 2; h >= 1; h /= 2) {
+      const bool hi = (t & h) != 0;
+      C2<R> w = tw[(t % h) * (G / (2 * h)) * P];
+      w.y = -w.y;
+      const R sg = hi ? (R)-1 : (R)1;
+      const C2<R> wl = hi ? w : mk<R>(1, 0);
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        const C2<R> p = shfl_xor2<R>(v[k], h, t);
+        const C2<R> d = mk<R>(fma(sg, v[k].x, p.x), fma(sg, v[k].y, p.y));
+        v[k] = cmul<R>(d, wl);
+      }
+    }
+  }
+  // r->G, kernel exp(-2 pi i h x / N), the conjugate transpose of inv: on
+  // entry v[k] = in[k + P bitrev(t)]; on exit v[j] = out[t + G j]
+  static __device__ __forceinline__ void fwd(C2<R>* v, int t, const C2<R>* tw0) {
+    int o = 0;
+    asm volatile("" : "+v"(o));
+    const C2<R>* tw = tw0 + o;
+    // the transposed stages: bit clear v + w p, bit set p - w v, as
+    // al v + be p with (al, be) = (1, w) or (-w, 1)
+#pragma unroll
+    for (int h = 1; h < G; h *= 2) {
+      const bool hi = (t & h) != 0;
+      const C2<R> w = tw[(t % h) * (G / (2 * h)) * P];
+      const C2<R> al = hi ? mk<R>(-w.x, -w.y) : mk<R>(1, 0);
+      const C2<R> be = hi ? mk<R>(1, 0) : w;
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        const C2<R> p = shfl_xor2<R>(v[k], h, t);
+        const C2<R> a = v[k];
+        v[k] = mk<R>(fma(be.x, p.x, fma(-be.y, p.y, fma(al.x, a.x, -al.y * a.y))),
+                     fma(be.x, p.y, fma(be.y, p.x, fma(al.x, a.y, al.y * a.x))));
+      }
+    }
+#pragma unroll
+    for (int k = 1; k < P; ++k) v[k] = cmul<R>(v[k], tw[t * k]);
+    RegDft<R, P>::run(v, -1, tw, G);
+  }
+};
+
+template <int G>
+__device__ __forceinline__ int bitrev_lane(int t) {
+  int r = 0;
+#pragma unroll
+  for (int b = 1; b < G; b <<= 1) r = (r << 1) | ((t & b) ? 1 : 0);
+  return r;
+}
+
+constexpr int kModeApply = 0, kModeDensity = 1, kModeDensityOpen = 2;
+
+struct LineGeom {
+  int N3, PS, hmax, ncol;
+};
+
+// MODE apply: T is transformed in place (F: potential multiply of each band
+// by its potential grid, potidx; nQ > 0 also accumulates <n|V^X|n>, X < nQ,
+// into Qpart).  MODE density: pairs without an open-shell band, the closed
+// shell's |u|^2 summed in registers into rho_part slice (chunk, 0), the open
+// slices of the chunk zeroed.  MODE density-open (one chunk, run after it):
+// the pairs holding an open-shell band, each band added into its shell's
+// slice of chunk 0.
+template <typename R, int G, int P, int MODE, int NT>
+__global__ void __launch_bounds__(NT, 512 / NT) k_plane_lines(
+    C2<R>* __restrict__ T, const int32_t* __restrict__ colidx, const int2* __restrict__ krange,
+    LineGeom g, const C2<R>* __restrict__ twg, const R* __restrict__ pot, size_t ntot,
+    const int32_t* __restrict__ potidx, int nvec, int nQ, double* __restrict__ Qpart,
+    const int32_t* __restrict__ band_shell, int nsocc, double* __restrict__ rho_part, int pair0,
+    int pair_end, int per_chunk) {
+  constexpr int N = G * P;
+  constexpr int NGRP = NT / G;        // line groups per workgroup
+  constexpr int RHO = (N + NGRP - 1) / NGRP;    // x-phase columns per group
+  constexpr int NW = NT / 64;
+  extern __shared__ char smem_raw[];
+  C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
+  C2<R>* buf = tw + N;
+  const int nh = 2 * g.hmax + 1;
+  const int PS = g.PS;
+  double* red = reinterpret_cast<double*>(buf + (size_t)nh * PS);  // [6][NW]
+  int2* kr = reinterpret_cast<int2*>(red + 6 * NW);                 // [nh]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int t = lane & (G - 1);
+  const int grp = tid / G;
+  const int brt = bitrev_lane<G>(t);
+  const int z = blockIdx.x, chunk = blockIdx.y;
+  const size_t zoff = (size_t)z * N * N;
+  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  for (int i = tid; i < nh; i += NT) kr[i] = krange[i];
+  const int p0 = pair0 + chunk * per_chunk;
+  const int p1 = min(pair_end, p0 + per_chunk);
+  double acc[MODE == kModeDensity ? RHO : 1][MODE == kModeDensity ? P : 1];  // closed-shell sum
+  if constexpr (MODE == kModeDensity) {
+#pragma unroll
+    for (int q = 0; q < RHO; ++q)
+#pragma unroll
+      for (int k = 0; k < P; ++k) acc[q][k] = 0.0;
+    for (int X = 1; X < nsocc; ++X) {
+      double* out = rho_part + ((size_t)chunk * nsocc + X) * ntot + zoff;
+      for (int pt = tid; pt < N * N; pt += NT) out[pt] = 0.0;
+    }
+  }
+  C2<R>* Tprev = nullptr;
+  for (int pair = p0; pair < p1; ++pair) {
+    if constexpr (MODE == kModeDensity) {
+      const int a = band_shell[2 * pair];
+      const int b = 2 * pair + 1 < nvec ? band_shell[2 * pair + 1] : 99;
+      if ((a >= 1 && a < nsocc) || (b >= 1 && b < nsocc)) continue;  // uniform
+    }
+    C2<R>* Tz = T + ((size_t)pair * g.N3 + z) * g.ncol;
+    // the previous pair's result out, this pair's columns in (each position
+    // belongs to one column, so one thread does both)
+    for (int col = tid; col < g.ncol; col += NT) {
+      const int at = colidx[col];
+      if (MODE == kModeApply && Tprev) Tprev[col] = buf[at];
+      buf[at] = Tz[col];
+    }
+    Tprev = Tz;
+    __syncthreads();
+    // y inverse, row r = h + hmax; positions outside the row's k range are zero
+    for (int r = grp; r < nh; r += NGRP) {
+      const int2 kk = kr[r];
+      C2<R> v[P];
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const int k = t + G * j;
+        const int ks = 2 * k > N ? k - N : k;
+        const C2<R> b = buf[r * PS + k];
+        const bool in = ks >= kk.x && ks <= kk.y;
+        v[j] = mk<R>(in ? b.x : (R)0, in ? b.y : (R)0);
+      }
+      LineFft<R, G, P>::inv(v, t, tw);
+#pragma unroll
+      for (int k = 0; k < P; ++k) buf[r * PS + k + P * brt] = v[k];
+    }
+    __syncthreads();
+    // x phase, column y
+    const int n1 = 2 * pair, n2 = 2 * pair + 1;
+    int s1 = 0, s2 = 0;
+    if constexpr (MODE == kModeApply) {
+      s1 = potidx[n1];
+      s2 = n2 < nvec ? potidx[n2] : -1;
+    } else {
+      s1 = band_shell[n1];
+      s2 = n2 < nvec ? band_shell[n2] : 99;
+    }
+    R q1[3] = {0, 0, 0}, q2[3] = {0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < RHO; ++q) {
+      const int y = grp + NGRP * q;
+      if (RHO * NGRP == N || y < N) {
+        C2<R> v[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          const int h = t + G * j;
+          const int hs = 2 * h > N ? h - N : h;
+          const bool in = hs >= -g.hmax && hs <= g.hmax;
+          const C2<R> b = buf[(in ? hs + g.hmax : 0) * PS + y];
+          v[j] = mk<R>(in ? b.x : (R)0, in ? b.y : (R)0);
+        }
+        LineFft<R, G, P>::inv(v, t, tw);
+        if constexpr (MODE == kModeApply) {
+#pragma unroll
+          for (int k = 0; k < P; ++k) {
+            const int x = k + P * brt;
+            const size_t pt = zoff + (size_t)x * N + y;
+            const R u1 = v[k].x, u2 = v[k].y;
+            const R a = s1 >= 0 ? pot[(size_t)s1 * ntot + pt] : (R)0;
+            const R b = s2 >= 0 ? (s2 == s1 ? a : pot[(size_t)s2 * ntot + pt]) : (R)0;
+            if (nQ > 0) {
+#pragma unroll
+              for (int X = 0; X < 3; ++X) {
+                if (X < nQ) {
+                  const R vx = X == s1 ? a : (X == s2 ? b : pot[(size_t)X * ntot + pt]);
+                  q1[X] += vx * u1 * u1;
+                  q2[X] += vx * u2 * u2;
+                }
+              }
+            }
+            v[k] = mk<R>(a * u1, b * u2);
+          }
+          LineFft<R, G, P>::fwd(v, t, tw);
+#pragma unroll
+          for (int j = 0; j < P; ++j) {
+            const int h = t + G * j;
+            const int hs = 2 * h > N ? h - N : h;
+            if (hs >= -g.hmax && hs <= g.hmax) buf[(hs + g.hmax) * PS + y] = v[j];
+          }
+        } else if constexpr (MODE == kModeDensity) {
+          const double w1 = s1 == 0 ? 1.0 : 0.0, w2 = s2 == 0 ? 1.0 : 0.0;
+#pragma unroll
+          for (int k = 0; k < P; ++k) {
+            const double u1 = (double)v[k].x, u2 = (double)v[k].y;
+            acc[q][k] += w1 * u1 * u1 + w2 * u2 * u2;
+          }
+        } else {
+          // open pairs (one or two per system): every band of the pair adds
+          // into its shell's slice of chunk 0 (after the closed-pair launch)
+#pragma unroll
+          for (int k = 0; k < P; ++k) {
+            const int x = k + P * brt;
+            const size_t pt = zoff + (size_t)x * N + y;
+            const double u1 = (double)v[k].x, u2 = (double)v[k].y;
+            if (s1 >= 0 && s1 < nsocc) rho_part[(size_t)s1 * ntot + pt] += u1 * u1;
+            if (s2 >= 0 && s2 < nsocc) rho_part[(size_t)s2 * ntot + pt] += u2 * u2;
+          }
+        }
+      }
+      // one column at a time: interleaving the unrolled columns would hold
+      // several lines in registers
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (MODE == kModeApply) {
+      if (nQ > 0) {
+#pragma unroll
+        for (int X = 0; X < 3; ++X) {
+          if (X < nQ) {
+            const double t1 = wave_sum((double)q1[X]);
+            const double t2 = wave_sum((double)q2[X]);
+            if (lane == 0) {
+              red[(2 * X) * NW + wid] = t1;
+              red[(2 * X + 1) * NW + wid] = t2;
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (nQ > 0 && tid < 2 * nQ) {
+        double s = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += red[tid * NW + w];
+        const int X = tid >> 1, b = tid & 1;
+        Qpart[(((size_t)pair * g.N3 + z) * 2 + b) * nQ + X] = s;
+      }
+      // y forward: the row as the inverse left it
+      for (int r = grp; r < nh; r += NGRP) {
+        C2<R> v[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) v[k] = buf[r * PS + k + P * brt];
+        LineFft<R, G, P>::fwd(v, t, tw);
+#pragma unroll
+        for (int j = 0; j < P; ++j) buf[r * PS + t + G * j] = v[j];
+      }
+    }
+    __syncthreads();
+  }
+  if constexpr (MODE == kModeApply) {
+    if (Tprev)
+      for (int col = tid; col < g.ncol; col += NT) Tprev[col] = buf[colidx[col]];
+  } else if constexpr (MODE == kModeDensity) {
+    if (nsocc > 0) {
+      double* out = rho_part + ((size_t)chunk * nsocc) * ntot + zoff;
+#pragma unroll
+      for (int q = 0; q < RHO; ++q) {
+        const int y = grp + NGRP * q;
+        if (RHO * NGRP == N || y < N) {
+#pragma unroll
+          for (int k = 0; k < P; ++k) out[(size_t)(k + P * brt) * N + y] = acc[q][k];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------
 // 512 threads keep every thread at <= 8 (N <= 64) or <= 18 (N <= 96) points
@@ -775,6 +1166,13 @@ double colbuf_bytes(const Ctx& c, int npairs) {
   return (double)npairs * c.N[2] * c.ncol * (c.prec == ROKS_FP32 ? sizeof(float2) : sizeof(double2));
 }
 double band_bytes(const Ctx& c, int nvec) { return (double)nvec * c.npw * sizeof(double2); }
+// algorithmic flops of a complex line transform of length n (5 n log2 n)
+double line_flops(int n) { return 5.0 * n * std::log2((double)n); }
+// the plane passes' lines per band pair and z-plane: the rows |h| <= hmax
+// along y and every column along x, once per direction
+double plane_lines_flops(const Ctx& c, int directions) {
+  return directions * ((2.0 * c.hmax + 1) * line_flops(c.N[1]) + (double)c.N[1] * line_flops(c.N[0]));
+}
 double grid_bytes(const Ctx& c) {
   return (double)c.ntot * (c.prec == ROKS_FP32 ? sizeof(float) : sizeof(double));
 }
@@ -815,7 +1213,8 @@ static void run_zpass_bwd(Ctx& c, const double2* vecs, int nvec, void* T, int np
 }
 
 void launch_zpass_bwd(Ctx& c, const double2* vecs, int nvec, void* T, int npairs) {
-  KernelTimer kt(c, "zpass_bwd", band_bytes(c, nvec) + colbuf_bytes(c, npairs));
+  KernelTimer kt(c, "zpass_bwd", band_bytes(c, nvec) + colbuf_bytes(c, npairs),
+                 (double)npairs * c.ncol * line_flops(c.N[2]));
   const int CH = zchunk(c);
   const int mp = pick_maxp(needed_points(2 * CH * c.N[2], kZThreads));
   if (c.prec == ROKS_FP32) {
@@ -839,7 +1238,8 @@ static void run_zpass_fwd(Ctx& c, const void* T, int npairs, const double2* vecs
 
 void launch_zpass_fwd(Ctx& c, const void* T, int npairs, const double2* vecs, int nvec,
                       const double* kinw, double2* Y) {
-  KernelTimer kt(c, "zpass_fwd", colbuf_bytes(c, npairs) + 2.0 * band_bytes(c, nvec));
+  KernelTimer kt(c, "zpass_fwd", colbuf_bytes(c, npairs) + 2.0 * band_bytes(c, nvec),
+                 (double)npairs * c.ncol * line_flops(c.N[2]));
   const int CH = zchunk(c);
   const int mp = pick_maxp(needed_points(2 * CH * c.N[2], kZThreads));
   if (c.prec == ROKS_FP32) {
@@ -865,10 +1265,109 @@ static void run_plane_apply(Ctx& c, void* T, int npairs, const void* pot, int np
   ROKS_HIP(hipGetLastError());
 }
 
+// ---- line kernels ----
+bool line_split(int n, int* G, int* P) {
+  // the square sizes the line kernels are built for
+  static const int table[][3] = {{16, 8, 2}, {24, 8, 3}, {32, 8, 4}, {40, 8, 5}, {48, 8, 6},
+                                 {64, 8, 8}, {72, 8, 9}, {80, 16, 5}, {96, 16, 6}};
+  for (const auto& e : table)
+    if (e[0] == n) {
+      *G = e[1];
+      *P = e[2];
+      return true;
+    }
+  return false;
+}
+
+size_t lines_lds(const Ctx& c, size_t elem, int nt) {
+  const int n = c.N[0], nh = 2 * c.hmax + 1;
+  return (size_t)(n + nh * (n + 1)) * elem + 6 * (nt / 64) * sizeof(double) +
+         (size_t)nh * sizeof(int2);
+}
+
+LineGeom line_geom(const Ctx& c) {
+  LineGeom g;
+  g.N3 = c.N[2];
+  g.PS = c.N[0] + 1;
+  g.hmax = c.hmax;
+  g.ncol = c.ncol;
+  return g;
+}
+
+// apply: 256 threads, two or more workgroups per CU; density: 512 threads
+// (the closed-shell sums of a lane's points stay in registers, half as many)
+template <int MODE>
+constexpr int line_threads() { return MODE == kModeApply ? 256 : 512; }
+
+template <typename R, int G, int P, int MODE>
+void run_lines_range(Ctx& c, void* T, int pair0, int pair_end, int nchunk, const void* pot,
+                     const int32_t* potidx, int nvec, int nQ, double* Qpart, double* rho_part) {
+  constexpr int NT = line_threads<MODE>();
+  const size_t lds = lines_lds(c, sizeof(C2<R>), NT);
+  allow_lds(k_plane_lines<R, G, P, MODE, NT>, lds);
+  // every chunk runs (an empty one still writes its zero density slice)
+  const int per = std::max(1, cdiv(pair_end - pair0, nchunk));
+  dim3 grid(c.N[2], nchunk);
+  hipLaunchKernelGGL((k_plane_lines<R, G, P, MODE, NT>), grid, dim3(NT), lds, c.stream,
+                     reinterpret_cast<C2<R>*>(T), c.d_colidx,
+                     reinterpret_cast<const int2*>(c.d_krange), line_geom(c), twiddles<R>(c, 0),
+                     reinterpret_cast<const R*>(pot), (size_t)c.ntot, potidx, nvec, nQ, Qpart,
+                     c.d_band_shell, c.nsocc, rho_part, pair0, pair_end, per);
+  ROKS_HIP(hipGetLastError());
+}
+
+template <typename R, int G, int P, int MODE>
+void run_lines(Ctx& c, void* T, int npairs, int nchunk, const void* pot, const int32_t* potidx,
+               int nvec, int nQ, double* Qpart, double* rho_part) {
+  if constexpr (MODE == kModeApply) {
+    run_lines_range<R, G, P, kModeApply>(c, T, 0, npairs, nchunk, pot, potidx, nvec, nQ, Qpart,
+                                         nullptr);
+  } else {
+    run_lines_range<R, G, P, kModeDensity>(c, T, 0, npairs, nchunk, nullptr, nullptr, nvec, 0,
+                                           nullptr, rho_part);
+    // the pairs that hold an open-shell band, one workgroup per plane
+    int pa = -1, pb = -1;
+    for (int n = 0; n < std::min(nvec, 2 * npairs); ++n) {
+      const int X = c.band_shell[n];
+      if (X >= 1 && X < c.nsocc) {
+        if (pa < 0) pa = n / 2;
+        pb = n / 2;
+      }
+    }
+    if (pa >= 0)
+      run_lines_range<R, G, P, kModeDensityOpen>(c, T, pa, pb + 1, 1, nullptr, nullptr, nvec, 0,
+                                                 nullptr, rho_part);
+  }
+}
+
+template <typename R, int MODE>
+void dispatch_lines(Ctx& c, void* T, int npairs, int nchunk, const void* pot,
+                    const int32_t* potidx, int nvec, int nQ, double* Qpart, double* rho_part) {
+#define ROKS_LINES(GG, PP)                                                                         \
+  if (c.lines_G == GG && c.lines_P == PP) {                                                        \
+    run_lines<R, GG, PP, MODE>(c, T, npairs, nchunk, pot, potidx, nvec, nQ, Qpart, rho_part);      \
+    return;                                                                                        \
+  }
+  ROKS_LINES(8, 2) ROKS_LINES(8, 3) ROKS_LINES(8, 4) ROKS_LINES(8, 5) ROKS_LINES(8, 6)
+  ROKS_LINES(8, 8) ROKS_LINES(8, 9) ROKS_LINES(16, 5) ROKS_LINES(16, 6)
+#undef ROKS_LINES
+  ROKS_CHECK(false, ROKS_ERR_SHAPE, "no line kernel for this plane");
+}
+
 void launch_plane_apply(Ctx& c, void* T, int npairs, const void* pot, int npot,
                         const int32_t* potidx, int nvec, double* Qpart, int nQ) {
   ROKS_CHECK(npot >= 1 && npot <= 3 && nQ <= npot, ROKS_ERR_ARG, "plane pass takes 1..3 potentials");
-  KernelTimer kt(c, "plane_apply", 2.0 * colbuf_bytes(c, npairs) + npot * grid_bytes(c));
+  KernelTimer kt(c, "plane_apply", 2.0 * colbuf_bytes(c, npairs) + npot * grid_bytes(c),
+                 (double)npairs * c.N[2] * plane_lines_flops(c, 2));
+  if (c.lines_G > 0) {
+    // about two rounds of workgroups over the device
+    const int nchunk = std::max(1, std::min(npairs, c.nchunk));
+    if (c.prec == ROKS_FP32)
+      dispatch_lines<float, kModeApply>(c, T, npairs, nchunk, pot, potidx, nvec, nQ, Qpart, nullptr);
+    else
+      dispatch_lines<double, kModeApply>(c, T, npairs, nchunk, pot, potidx, nvec, nQ, Qpart, nullptr);
+    return;
+  }
   const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], plane_threads(c)));
   if (c.prec == ROKS_FP32) {
     ROKS_DISPATCH_MAXP(float, mp, radix_set(c.plan[0], c.plan[1]), run_plane_apply, c, T, npairs, pot, npot, potidx, nvec, Qpart, nQ);
@@ -896,13 +1395,23 @@ static void run_plane_density(Ctx& c, const void* T, int npairs, double* rho_par
 // FP32 density kernel spills far more than the FP64 one (96^2 planes: 13.7
 // against 4.2 ms per all-band density), so the tier takes the FP64 density.
 bool fp32_density_planes(const Ctx& c) {
+  if (c.lines_G > 0) return true;
   const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], plane_threads(c)));
   return mp <= 16 || radix_set(c.plan[0], c.plan[1]) == kLen64;
 }
 
 void launch_plane_density(Ctx& c, const void* T, int npairs, double* rho_part, int nchunk) {
   KernelTimer kt(c, "plane_density",
-                 colbuf_bytes(c, npairs) + (double)nchunk * c.nsocc * c.ntot * sizeof(double));
+                 colbuf_bytes(c, npairs) + (double)nchunk * c.nsocc * c.ntot * sizeof(double),
+                 (double)npairs * c.N[2] * plane_lines_flops(c, 1));
+  if (c.lines_G > 0) {
+    void* Tm = const_cast<void*>(T);
+    if (c.prec == ROKS_FP32)
+      dispatch_lines<float, kModeDensity>(c, Tm, npairs, nchunk, nullptr, nullptr, c.nb, 0, nullptr, rho_part);
+    else
+      dispatch_lines<double, kModeDensity>(c, Tm, npairs, nchunk, nullptr, nullptr, c.nb, 0, nullptr, rho_part);
+    return;
+  }
   const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], plane_threads(c)));
   if (c.prec == ROKS_FP32) {
     ROKS_DISPATCH_MAXP(float, mp, radix_set(c.plan[0], c.plan[1]), run_plane_density, c, T, npairs, rho_part, nchunk);
@@ -1005,14 +1514,16 @@ static void fft_xy_pass(Ctx& c, double2* data, int sign, bool yfirst) {
 // bytes moved: every pass reads and writes the grid once
 void launch_fft3d(Ctx& c, double2* data, int sign) {
   const int passes = fft_plane_fits(c) ? 2 : 3;
-  KernelTimer kt(c, "fft3d", 2.0 * passes * c.ntot * sizeof(double2));
+  KernelTimer kt(c, "fft3d", 2.0 * passes * c.ntot * sizeof(double2),
+                 5.0 * c.ntot * std::log2((double)c.ntot));
   fft_xy_pass(c, data, sign, true);
   fft_axis_pass(c, data, sign, 2, false);
 }
 
 void launch_hartree_fft(Ctx& c, double2* data) {
   const int passes = fft_plane_fits(c) ? 3 : 5;
-  KernelTimer kt(c, "fft3d", 2.0 * passes * c.ntot * sizeof(double2));
+  KernelTimer kt(c, "fft3d", 2.0 * passes * c.ntot * sizeof(double2),
+                 10.0 * c.ntot * std::log2((double)c.ntot));
   fft_xy_pass(c, data, -1, true);
   fft_axis_pass(c, data, -1, 2, true);
   fft_xy_pass(c, data, +1, false);

@@ -6,15 +6,13 @@
 // partials are summed in a fixed order (bitwise reproducible); the split
 // count comes from a heuristic or, with ROKS_FLAG_AUTOTUNE, from timing
 // candidates once per shape.  Products with M, N >= 128 are compute-bound and
-// go to the rocBLAS DGEMM instead.
+// go to the LDS-tiled product of tile_gemm.hip instead.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <map>
 #include <mutex>
 #include <tuple>
-
-#include <rocblas/rocblas.h>
 
 #include "roks_internal.h"
 
@@ -203,60 +201,9 @@ __global__ void __launch_bounds__(1024) k_splitk_reduce16(const double* __restri
   }
 }
 
-// C[m][n] -= a (A[m][0] B[n][0] + A[m][1] B[n][1]): the G = 0 doubles weigh
-// 1, not the 2 a library product with doubled alpha gave them
-__global__ void k_g0_correction(int M, int N, const double* __restrict__ A, int lda,
-                                const double* __restrict__ B, int ldb, double* __restrict__ C,
-                                int ldc, double a) {
-  const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  if (t >= (size_t)M * N) return;
-  const int m = (int)(t / N), n = (int)(t - (size_t)m * N);
-  C[(size_t)m * ldc + n] -=
-      a * (A[(size_t)m * lda] * B[(size_t)n * ldb] + A[(size_t)m * lda + 1] * B[(size_t)n * ldb + 1]);
-}
-
 }  // namespace
 
 namespace {
-
-// C (row-major M x N) = alpha A W B^T + beta C with the rocBLAS DGEMM on the
-// column-major views (C^T = B_cm^T A_cm): K is cut into nchunk equal chunks
-// (one strided-batched call; the rest of K, if any, in one more call), each
-// giving a partial product in d_gemm_part, summed in chunk order with alpha
-// doubled (the stored-half weight), then the G = 0 correction.  rocBLAS runs
-// without atomics, so the sums are reproducible.
-void gemm_wdot_blas(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B,
-                    int ldb, double* C, int ldc, double alpha, double beta, bool half_weights,
-                    int nchunk) {
-  const rocblas_handle h = static_cast<rocblas_handle>(blas_handle(c));
-  const double one = 1.0, zero = 0.0;
-  const size_t mn = (size_t)M * N;
-  nchunk = std::max(1, std::min<int>(nchunk, (int)(c.gemm_part_capacity / mn) - 1));
-  const int kc = K / nchunk;
-  const int rest = K - kc * nchunk;
-  ROKS_CHECK(rocblas_dgemm_strided_batched(h, rocblas_operation_transpose, rocblas_operation_none, N,
-                                           M, kc, &one, B, ldb, (rocblas_stride)kc, A, lda,
-                                           (rocblas_stride)kc, &zero, c.d_gemm_part, N,
-                                           (rocblas_stride)mn, nchunk) == rocblas_status_success,
-             ROKS_ERR_HIP, "rocblas_dgemm_strided_batched failed");
-  int ks = nchunk;
-  if (rest > 0) {
-    ROKS_CHECK(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, N, M, rest, &one,
-                             B + (size_t)kc * nchunk, ldb, A + (size_t)kc * nchunk, lda, &zero,
-                             c.d_gemm_part + (size_t)nchunk * mn, N) == rocblas_status_success,
-               ROKS_ERR_HIP, "rocblas_dgemm failed");
-    ++ks;
-  }
-  const double a = half_weights ? 2.0 * alpha : alpha;
-  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, c.stream,
-                     c.d_gemm_part, ks, M, N, C, ldc, a, beta);
-  ROKS_HIP(hipGetLastError());
-  if (half_weights && K >= 2) {
-    hipLaunchKernelGGL(k_g0_correction, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, c.stream, M,
-                       N, A, lda, B, ldb, C, ldc, alpha);
-    ROKS_HIP(hipGetLastError());
-  }
-}
 
 // blocks of 16 per tile side: the count in 1..cap with the least padding,
 // the larger on ties
@@ -301,13 +248,14 @@ void splitk_sum(Ctx& c, int ks, int rows, int N, double* C, int ldc, double alph
   ROKS_HIP(hipGetLastError());
 }
 
-// the launches of one split count (ks_req < 0: the library DGEMM in -ks_req
-// chunks of K): partials then the ordered sum, or one pass
+// the launches of one split count (ks_req < 0: the LDS-tiled product in
+// -ks_req chunks of K): partials then the ordered sum, or one pass
 void gemm_wdot_launch(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B,
                       int ldb, double* C, int ldc, double alpha, double beta, bool half_weights,
                       int ks_req) {
   if (ks_req < 0) {
-    gemm_wdot_blas(c, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, half_weights, -ks_req);
+    tile_gemm(c, M, N, K, A, lda, 0, B, ldb, 0, nullptr, 0.0, C, ldc, nullptr, 0, alpha, beta,
+              half_weights, -ks_req);
     return;
   }
   const int RB = tile_blocks(cdiv(M, 16), 5), CB = tile_blocks(cdiv(N, 16), 3);
@@ -341,9 +289,8 @@ int max_splits(const Ctx& c, int M, int N, int K) {
 // A workgroup reads its K chunk once per tile; the smallest chunk (one step,
 // 128 columns) is used until the tiles times chunks reach ~256 workgroups.
 int heuristic_splits(const Ctx& c, int M, int N, int K) {
-  // compute-bound sizes: the library DGEMM, K cut so ~1 000 tiles fill the GPU
-  if (M >= 128 && N >= 128)
-    return -std::max(1, std::min(32, cdiv(1024, cdiv(M, 64) * cdiv(N, 64))));
+  // compute-bound sizes: the LDS-tiled product, K cut so the tiles fill the GPU
+  if (M >= 128 && N >= 128) return -tile_gemm_splits(c, M, N, K);
   const int tiles = cdiv(M, 16 * tile_blocks(cdiv(M, 16), 5)) * cdiv(N, 16 * tile_blocks(cdiv(N, 16), 3));
   const int ks = std::max(1, std::min(cdiv(K, kWdotStep), cdiv(256, tiles)));
   return std::min(ks, max_splits(c, M, N, K));
@@ -362,8 +309,8 @@ int tuned_splits(Ctx& c, int M, int N, int K, const double* A, int lda, const do
   const int h = heuristic_splits(c, M, N, K), hi = max_splits(c, M, N, K);
   std::vector<int> cand;
   if (M >= 64 && N >= 64)
-    for (int v : {-1, -4, -8, -16, -32})  // the library DGEMM in |v| chunks of K
-      if ((size_t)(-v + 1) * M * N <= c.gemm_part_capacity) cand.push_back(v);
+    for (int v : {-1, -4, -8, -16, -32, -64})  // the LDS-tiled product in |v| chunks of K
+      if ((size_t)(-v) * M * N <= c.gemm_part_capacity) cand.push_back(v);
   const int hh = std::max(1, std::abs(h));
   for (int v : {hh / 4, hh / 2, hh, 2 * hh, 4 * hh, 1, 32, 64})
     if (v >= 1 && v <= hi && std::find(cand.begin(), cand.end(), v) == cand.end()) cand.push_back(v);
@@ -414,6 +361,13 @@ void gemm_wdot_deriv(Ctx& c, int np, int N, int K, const double* B, int ldb, con
   ROKS_CHECK(K % 2 == 0, ROKS_ERR_ARG, "derivative products need whole complex coefficients");
   KernelTimer kt(c, "gemm_wdot", ((double)np + N) * K * sizeof(double) + 3.0 * np * N * sizeof(double),
                  6.0 * np * N * (double)K);
+  if (np >= 128 && N >= 128) {
+    // compute-bound: the LDS-tiled product, one launch per axis
+    for (int a = 0; a < 3; ++a)
+      tile_gemm(c, np, N, K, B, ldb, 0, X, ldx, 0, nullptr, 0.0, C + (size_t)a * np * ldc, ldc, nullptr,
+                0, 1.0, 0.0, true, 0, gcart + (size_t)a * (K / 2));
+    return;
+  }
   const int RB = tile_blocks(cdiv(np, 16), 5), CB = tile_blocks(cdiv(N, 16), 3);
   const WdotLaunch launch = wdot_table<true>()[RB - 1][CB - 1];
   const int vec = ((reinterpret_cast<uintptr_t>(B) | reinterpret_cast<uintptr_t>(X)) % 16 == 0 &&

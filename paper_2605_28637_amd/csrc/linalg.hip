@@ -7,7 +7,6 @@
 #include <algorithm>
 #include <cmath>
 
-#include <rocblas/rocblas.h>
 
 #include "roks_internal.h"
 
@@ -199,6 +198,12 @@ __global__ void __launch_bounds__(1024) k_band_dots(const double2* __restrict__ 
   }
 }
 
+// Im c_n(G = 0) = 0 (G = 0 is entry 0 of every band)
+__global__ void k_zero_g0_imag(double2* __restrict__ v, int nvec, int npw) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < nvec) v[(size_t)n * npw].y = 0.0;
+}
+
 __global__ void k_axpby(size_t n, double a, const double* __restrict__ x, double b,
                         const double* __restrict__ y, double* __restrict__ out) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
@@ -273,10 +278,13 @@ __global__ void __launch_bounds__(1024) k_norm1(const double* A, int n, double* 
 // LDS row stride of the single-workgroup Cholesky: n rounded up to odd
 __host__ __device__ inline int chol_ld(int n) { return n | 1; }
 
-// acc_flag: OR the status into flag[0] (blocks of a larger factorisation)
+// acc_flag: OR the status into flag[0] (blocks of a larger factorisation);
+// gref (stride gref_ld, nullable): the diagonal the pivot test refers to,
+// when G is a Schur complement of a larger Gram matrix (its diagonal there)
 __device__ void cholesky_lds_body(const double* __restrict__ G, double ga, double gd, int n,
                                   double* __restrict__ Linv, int32_t* __restrict__ flag, int inv_in_lds,
-                                  double* A, int acc_flag = 0) {
+                                  double* A, int acc_flag = 0, const double* __restrict__ gref = nullptr,
+                                  int gref_ld = 0) {
   __shared__ int bad;
   __shared__ double gdiag[128];   // the Gram diagonal, the reference of the pivot test
   __shared__ double piv[2][2];    // [step parity]: 1/d, 1/sqrt(d)
@@ -289,7 +297,7 @@ __device__ void cholesky_lds_body(const double* __restrict__ G, double ga, doubl
     const int r = t / n, q = t - r * n;
     const double g = ga * G[t] + (r == q ? gd : 0.0);  // the matrix factorised: ga G + gd I
     A[r * ld + q] = g;
-    if (r == q) gdiag[r] = g;
+    if (r == q) gdiag[r] = gref ? gref[(size_t)r * gref_ld] : g;
     if (inv_in_lds) X[r * ld + q] = r == q ? 1.0 : 0.0;
   }
   auto pivot = [&](int j, double d) {
@@ -373,9 +381,11 @@ __device__ void cholesky_lds_body(const double* __restrict__ G, double ga, doubl
 __global__ void __launch_bounds__(1024) k_cholesky_inverse_lds(const double* __restrict__ G, int n,
                                                                double* __restrict__ Linv,
                                                                int32_t* __restrict__ flag,
-                                                               int inv_in_lds, int acc_flag) {
+                                                               int inv_in_lds, int acc_flag,
+                                                               const double* __restrict__ gref,
+                                                               int gref_ld) {
   extern __shared__ double A[];
-  cholesky_lds_body(G, 1.0, 0.0, n, Linv, flag, inv_in_lds, A, acc_flag);
+  cholesky_lds_body(G, 1.0, 0.0, n, Linv, flag, inv_in_lds, A, acc_flag, gref, gref_ld);
 }
 
 // rows j0 .. j0+rows-1 of the n x n identity, [rows][n]
@@ -601,6 +611,27 @@ __global__ void k_subspace(SubArgs a, const double* __restrict__ theta,
   A[t] = ang;
 }
 
+// the virtual block of R: R[n][m] = R[m][n] for v0 <= m < n (products in
+// the upper triangle); with canonicalisation kappa = R_nn - R_mm and the
+// Jacobi angle A_mn = 1/2 atan(2 R_mn / kappa) (+-pi/4 for kappa = 0)
+__global__ void k_virtual_block(double* __restrict__ R, double* __restrict__ kappa,
+                                double* __restrict__ A, int nb, int v0, int canon) {
+  const int nv = nb - v0;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nv * nv) return;
+  const int m = v0 + t / nv, n = v0 + t % nv;
+  if (m >= n) return;
+  const double r = R[(size_t)m * nb + n];
+  R[(size_t)n * nb + m] = r;
+  if (canon) {
+    const double k = R[(size_t)n * nb + n] - R[(size_t)m * nb + m];
+    const double a = k != 0.0 ? 0.5 * atan(2.0 * r / k) : (r > 0 ? M_PI / 4 : (r < 0 ? -M_PI / 4 : 0.0));
+    kappa[(size_t)m * nb + n] = kappa[(size_t)n * nb + m] = k;
+    A[(size_t)m * nb + n] = a;
+    A[(size_t)n * nb + m] = -a;
+  }
+}
+
 // sum_mn A_mn (theta_mn - theta_nm), one workgroup
 // sum_mn A_mn (th_mn - th_nm) by the first nt threads of the workgroup, nt =
 // 256, or every thread (up to 1024) beyond 128 bands (fixed order: nt-strided
@@ -773,21 +804,11 @@ void gemm_expand_sum(Ctx& c, int N, int K, int Md, const double* M, int ldm, boo
                  ((double)Md * K + (beta != 0.0 ? 2.0 : 1.0) * N * K) * sizeof(double),
                  2.0 * N * (double)K * Md);
   if (Md >= 128 && N >= 64) {
-    // a compute-bound size: one library DGEMM on the column-major views,
-    // Y^T (K x N) = X^T (K x Md) M (Md x N), in place (X + dX2 X2 formed
-    // first in the trial buffer)
-    if (X2) {
-      ROKS_CHECK(Md == c.nb && ldx == 2 * c.npw, ROKS_ERR_ARG, "two-input expansion of bands only");
-      axpby(c, (size_t)Md * ldx, 1.0, X, dX2, X2, reinterpret_cast<double*>(c.d_Pt));
-      X = reinterpret_cast<const double*>(c.d_Pt);
-    }
-    if (beta != 0.0 && Yin != Y)
-      ROKS_HIP(hipMemcpy2DAsync(Y, (size_t)ldy * sizeof(double), Yin, (size_t)ldyin * sizeof(double),
-                                (size_t)K * sizeof(double), N, hipMemcpyDeviceToDevice, c.stream));
-    ROKS_CHECK(rocblas_dgemm(static_cast<rocblas_handle>(blas_handle(c)), rocblas_operation_none,
-                             transM ? rocblas_operation_none : rocblas_operation_transpose, K, N, Md,
-                             &alpha, X, ldx, M, ldm, &beta, Y, ldy) == rocblas_status_success,
-               ROKS_ERR_HIP, "rocblas_dgemm failed");
+    // a compute-bound size: the LDS-tiled product, Y[n][k] = alpha sum_i
+    // M^(T)[n][i] (X + dX2 X2)[i][k] + beta Yin[n][k], the sum formed while
+    // staging X
+    tile_gemm(c, N, K, Md, M, ldm, transM ? 0 : 1, X, ldx, 1, X2, dX2, Y, ldy, Yin, ldyin, alpha,
+              beta, false, 1);
     return;
   }
   // 16-row blocks of Y per wave: 1..3, the least padding, the larger on ties
@@ -831,7 +852,7 @@ void gemm_small2(Ctx& c, int M, int N, int K, const double* A, const double* A2,
                  bool tA, const double* B, int ldb, bool tB, double* C, int ldc, double alpha,
                  double beta, double diag) {
   if (!A2 && M >= 128 && N >= 128 && K >= 128) {
-    // a compute-bound size (the large-band exponential): the library DGEMM
+    // a compute-bound size (the large-band exponential): the LDS-tiled product
     gemm_rm(c, tA, tB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
     if (diag != 0.0) {
       const int nd = std::min(M, N);
@@ -861,6 +882,20 @@ void band_dots(Ctx& c, const double2* X, const double2* Y, int nvec, int mode, d
     band_dots2(c, X, Y, nvec, out, nullptr);
 }
 
+void launch_virtual_block(Ctx& c, int v0) {
+  const int nv = c.nb - v0;
+  if (nv <= 1) return;
+  hipLaunchKernelGGL(k_virtual_block, dim3(cdiv(nv * nv, 256)), dim3(256), 0, c.stream, c.d_R,
+                     c.d_kappa, c.d_A, c.nb, v0, (c.flags & ROKS_FLAG_CANONICALIZE) ? 1 : 0);
+  ROKS_HIP(hipGetLastError());
+}
+
+void launch_zero_g0_imag(Ctx& c, double2* vecs, int nvec) {
+  if (nvec <= 0) return;
+  hipLaunchKernelGGL(k_zero_g0_imag, dim3(cdiv(nvec, 256)), dim3(256), 0, c.stream, vecs, nvec, c.npw);
+  ROKS_HIP(hipGetLastError());
+}
+
 void axpby(Ctx& c, size_t n, double a, const double* x, double b, const double* y, double* out) {
   hipLaunchKernelGGL(k_axpby, dim3(blocks_for(n)), dim3(256), 0, c.stream, n, a, x, b, y, out);
   ROKS_HIP(hipGetLastError());
@@ -886,22 +921,17 @@ void matrix_norm1(Ctx& c, const double* A, int n, double* out) {
   ROKS_HIP(hipGetLastError());
 }
 
-// row-major C (M x N) = alpha op(A) op(B) + beta C with the library DGEMM
-// (column-major: C^T = op(B)^T op(A)^T)
+// row-major C (M x N) = alpha op(A) op(B) + beta C, the LDS-tiled product
 static void gemm_rm(Ctx& c, bool tA, bool tB, int M, int N, int K, double alpha, const double* A,
                     int lda, const double* B, int ldb, double beta, double* C, int ldc) {
   if (M == 0 || N == 0 || K == 0) return;
-  ROKS_CHECK(rocblas_dgemm(static_cast<rocblas_handle>(blas_handle(c)),
-                           tB ? rocblas_operation_transpose : rocblas_operation_none,
-                           tA ? rocblas_operation_transpose : rocblas_operation_none, N, M, K, &alpha, B,
-                           ldb, A, lda, &beta, C, ldc) == rocblas_status_success,
-             ROKS_ERR_HIP, "rocblas_dgemm failed");
+  tile_gemm(c, M, N, K, A, lda, tA ? 1 : 0, B, ldb, tB ? 0 : 1, nullptr, 0.0, C, ldc, nullptr, 0, alpha,
+            beta, false, 0);
 }
 
 // L^-1 of G = L L^T for n > 128, blocked by 64: the diagonal block of each
 // panel factorised and inverted by the single-workgroup kernel (its status
-// ORed into flag[0]; the dependency test refers to the block's updated
-// diagonal), the panel below L21 = A21 L11^-T and the trailing update
+// ORed into flag[0]; the dependency test refers to the diagonal of G), the panel below L21 = A21 L11^-T and the trailing update
 // A22 -= L21 L21^T as GEMMs; then L^-1 by block rows, X_i = L_ii^-1 (I_i -
 // L_i,<i X_<i).  Scratch: d_m3 (the updated matrix), d_m4 (L below the
 // diagonal blocks), d_m1 (the diagonal blocks' inverses), d_m2 (a block, then
@@ -924,8 +954,11 @@ static void cholesky_inverse_blocked(Ctx& c, const double* G, int n, double* Lin
                               (size_t)n * sizeof(double), (size_t)bs * sizeof(double), bs,
                               hipMemcpyDeviceToDevice, c.stream));
     double* Di = Dinv + (size_t)p * b * b;
+    // pivots are tested against the diagonal of the original Gram matrix: a
+    // band dependent on bands of earlier panels leaves a rounding-level pivot
+    // in the updated block
     hipLaunchKernelGGL(k_cholesky_inverse_lds, dim3(1), dim3(1024), lds, c.stream, T, bs, Di, flag, 1,
-                       p > 0 ? 1 : 0);
+                       p > 0 ? 1 : 0, G + (size_t)j0 * n + j0, n + 1);
     ROKS_HIP(hipGetLastError());
     if (m > 0) {
       double* L21 = Lb + (size_t)j1 * n + j0;
@@ -954,7 +987,7 @@ void cholesky_inverse(Ctx& c, const double* G, int n, double* Linv, int32_t* fla
       ROKS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cholesky_inverse_lds),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(k_cholesky_inverse_lds, dim3(1), dim3(1024), lds, c.stream, G, n, Linv, flag,
-                       inv, 0);
+                       inv, 0, static_cast<const double*>(nullptr), 0);
     ROKS_HIP(hipGetLastError());
   } else {
     cholesky_inverse_blocked(c, G, n, Linv, flag);

@@ -58,6 +58,9 @@ struct FftPlan1D {
 
 FftPlan1D make_plan(int n);  // radices 8, 4, 2, 3, 5 (throws if n has other factors)
 
+// the line-kernel split N = G P of a square plane (false: none built)
+bool line_split(int n, int* G, int* P);
+
 // ---------------------------------------------------------------------------
 // the context
 // ---------------------------------------------------------------------------
@@ -123,10 +126,8 @@ struct Ctx {
   // ---- device ----
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  // created on first use (blas_handle, side_stream): every stream a context
-  // holds takes a share of the device's few hardware queues, idle or not
-  void* blas = nullptr;                 // rocblas_handle (large plain DGEMMs)
-  hipStream_t blas_stream = nullptr;    // the stream the handle was last set to
+  // created on first use (side_stream): every stream a context holds takes a
+  // share of the device's few hardware queues, idle or not
   // a second stream for the local force part beside the nonlocal part,
   // joined through events
   hipStream_t side = nullptr;
@@ -213,10 +214,17 @@ struct Ctx {
   double* d_m4 = nullptr;
   double* d_kinw_shell = nullptr;  // [nb] shell weight of each band (0 for virtual)
   double* d_ones = nullptr;        // [nb] ones
-  int32_t* d_potidx = nullptr;     // [5][nb]: shell potential per band, channel 0..3
+  int32_t* d_potidx = nullptr;     // [6][nb]: shell potential per band, channel 0..3, closed shell
+  double* d_kinw_closed = nullptr; // [nb] weight of the closed shell (F^c for every band)
 
   int npairs = 0;
   int nchunk = 0;
+  // plane passes with the lines in registers (square planes N = G P): G and
+  // P (0: not available, the LDS-plane kernels run), per-column LDS index and
+  // per-row k range of the pruned [2 hmax + 1][N + 1] plane
+  int lines_G = 0, lines_P = 0;
+  int32_t* d_colidx = nullptr;   // [ncol]
+  int32_t* d_krange = nullptr;   // [2 hmax + 1][2] signed k range of each row
   size_t part_capacity = 0;      // doubles in d_part
   size_t gemm_part_capacity = 0;
 
@@ -315,6 +323,7 @@ struct KernelTimer {
 };
 
 // host setup (setup.cpp)
+void grid_rule(const double cell[3][3], double ecut, int grid[3]);
 void build_problem(Ctx& c, const roks_system* sys);
 void build_sphere(Ctx& c);
 void build_projectors(Ctx& c);
@@ -322,8 +331,6 @@ void build_projectors(Ctx& c);
 // device setup and memory (device.cpp)
 void init_device(Ctx& c, void* stream);
 void free_device(Ctx& c);
-// the library handle, created on first use and pointed at c.stream
-void* blas_handle(Ctx& c);
 // the side stream and its fork/join events, created on first use
 void ensure_side_stream(Ctx& c);
 void clear_timing(Ctx& c);
@@ -385,6 +392,20 @@ void launch_nl_force(Ctx& c, const double* dP3, const double* DP, const double* 
 // the Cartesian components of every stored G, [3][npw]
 void launch_gcart(Ctx& c, double* gcart);
 
+// tile_gemm.hip: C = alpha op(A) op(B) + beta Cin on the FP64 matrix cores,
+// 128 x 128 tiles staged in LDS, split-K over ks chunks (ks <= 0: chosen
+// from the shape) summed in chunk order.  alay 0: op(A)[m][k] = A[m lda + k],
+// 1: A[k lda + m]; blay 0: op(B)[k][n] = B[n ldb + k], 1: B[k ldb + n];
+// B2 (blay 1, nullable): op(B) + b2 op(B2); half_weights (alay = blay = 0):
+// the Gamma weight of k (1 for k < 2, else 2); Cin nullable (C); ga
+// (nullable, weighted inner products only): A's coefficients multiplied by
+// -i G_a with G_a = ga[k / 2] (derivative projections)
+void tile_gemm(Ctx& c, int M, int N, int K, const double* A, int lda, int alay, const double* B,
+               int ldb, int blay, const double* B2, double b2, double* C, int ldc, const double* Cin,
+               int ldcin, double alpha, double beta, bool half_weights, int ks,
+               const double* ga = nullptr);
+int tile_gemm_splits(const Ctx& c, int M, int N, int K);
+
 // linalg.hip
 void gemm_wdot(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
                double* C, int ldc, double alpha, double beta, bool half_weights);
@@ -425,6 +446,9 @@ void scale_shift(Ctx& c, const double* in, int n, double a, double d, double* ou
 void matrix_norm1(Ctx& c, const double* A, int n, double* out);
 // open_out: also the open-shell coupling (two open shells only)
 void launch_subspace(Ctx& c, double* open_out = nullptr);
+// the virtual block of R from <m|F^c|n> already in R[v0.., v0..] (upper
+// triangle mirrored; with canonicalisation kappa and the Jacobi angles)
+void launch_virtual_block(Ctx& c, int v0);
 bool expm_in_lds(const Ctx& c);
 // Cholesky inverse of G and U = exp(delta D) in one launch of two workgroups
 // (nb within the single-workgroup limits of both)
@@ -466,9 +490,16 @@ void collect_records(Ctx& c, Mlp& m, int* used, int* skipped);
 void compute_potentials(Ctx& c, const double2* orbitals, roks_energies* e);
 void ensure_potentials(Ctx& c);
 void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bool want_Q);
-void energy_gradient(Ctx& c, roks_energies* e, double* open_out = nullptr);
+// want_vv: also the virtual-virtual block of R, <m|F^c|n> (always with
+// ROKS_FLAG_CANONICALIZE, whose Jacobi angles rotate that block)
+void energy_gradient(Ctx& c, roks_energies* e, double* open_out = nullptr, bool want_vv = false);
 void pcg_step(Ctx& c, roks_step_info* info);
 void orthonormalize(Ctx& c, double2* vecs);
+// the smallest trial step the next line search can take (its halvings of the
+// current trial step)
+double smallest_trial_step(const Ctx& c);
+// Im c_n(0) = 0 for nvec bands (real orbitals)
+void launch_zero_g0_imag(Ctx& c, double2* vecs, int nvec);
 void forces(Ctx& c, double* f_host);
 void reset_cg(Ctx& c);
 

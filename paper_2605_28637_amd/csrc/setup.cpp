@@ -46,6 +46,24 @@ static void invert3(const double a[3][3], double inv[3][3]) {
   inv[2][2] = (a[0][0] * a[1][1] - a[0][1] * a[1][0]) / det;
 }
 
+void grid_rule(const double cell[3][3], double ecut, int grid[3]) {
+  // G_cut = pi N / (2 |a_d|), i.e. N >= 2 G_cut |a_d| / pi, rounded up to the
+  // next size with factors 2, 3, 5 only (relative slack 1e-12 for the
+  // rounding of an exact product)
+  auto smooth = [](int v) {
+    for (int f : {2, 3, 5})
+      while (v % f == 0) v /= f;
+    return v == 1;
+  };
+  for (int d = 0; d < 3; ++d) {
+    const double ad = std::sqrt(cell[d][0] * cell[d][0] + cell[d][1] * cell[d][1] + cell[d][2] * cell[d][2]);
+    const double need = 2.0 * std::sqrt(2.0 * ecut) * ad / M_PI;
+    int n = need < 1e9 ? std::max(4, (int)std::ceil(need * (1.0 - 1e-12))) : (1 << 30);
+    while (n < (1 << 30) && !smooth(n)) ++n;
+    grid[d] = n;
+  }
+}
+
 void build_problem(Ctx& c, const roks_system* s) {
   ROKS_CHECK(s != nullptr, ROKS_ERR_ARG, "system is NULL");
   std::memcpy(c.cell, s->cell, sizeof(c.cell));
@@ -60,9 +78,14 @@ void build_problem(Ctx& c, const roks_system* s) {
   c.omega = std::fabs(det);
   ROKS_CHECK(s->ecut > 0 && std::isfinite(s->ecut), ROKS_ERR_ARG, "ecut must be > 0");
   c.ecut = s->ecut;
+  const bool auto_grid = s->grid[0] == 0 && s->grid[1] == 0 && s->grid[2] == 0;
+  int rule[3] = {0, 0, 0};
+  if (auto_grid) grid_rule(c.cell, c.ecut, rule);
   for (int d = 0; d < 3; ++d) {
-    ROKS_CHECK(s->grid[d] >= 4 && s->grid[d] <= 128, ROKS_ERR_SHAPE, "grid sizes must be in [4, 128]");
-    c.N[d] = s->grid[d];
+    const int n = auto_grid ? rule[d] : s->grid[d];
+    ROKS_CHECK(n >= 4 && n <= 128, ROKS_ERR_SHAPE,
+               "grid sizes must be in [4, 128] (or all 0 for the grid rule)");
+    c.N[d] = n;
     c.plan[d] = make_plan(c.N[d]);
   }
   c.ntot = c.N[0] * c.N[1] * c.N[2];

@@ -310,7 +310,37 @@ void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bo
 // ---------------------------------------------------------------------------
 // energy, Y = F^n|n>, theta, g_I = (1 - P) Y, and R / kappa / A
 // ---------------------------------------------------------------------------
-void energy_gradient(Ctx& c, roks_energies* e, double* open_out) {
+// Eq. r_matrix_singlet puts F^c in the virtual-virtual block of R: F^c is
+// applied to the virtual bands (into d_w1) and their band products fill the
+// block (needs the potentials and projections of the current orbitals)
+static void virtual_block(Ctx& c) {
+  const int nb = c.nb, K = 2 * c.npw;
+  int v0 = nb, Xc = -1;
+  for (int n = 0; n < nb; ++n)
+    if (c.shell_virtual[c.band_shell[n]]) {
+      v0 = n;
+      break;
+    }
+  for (int X = 0; X < c.nshell; ++X)
+    if (c.shell_closed[X] && Xc < 0) Xc = X;
+  const int nv = nb - v0;
+  if (nv == 0 || Xc < 0) return;  // no closed shell: the block stays zero
+  const double2* vv = c.d_psi + (size_t)v0 * c.npw;
+  double2* out = c.d_w1;
+  const int np = (nv + 1) / 2;
+  launch_zpass_bwd(c, vv, nv, c.d_T, np);
+  const void* vsh = c.prec == ROKS_FP32 ? (const void*)c.d_vsh32 : (const void*)c.d_vsh;
+  launch_plane_apply(c, c.d_T, np, vsh, c.nsocc, c.d_potidx + (size_t)5 * nb, nv, c.d_Qpart, 0);
+  launch_zpass_fwd(c, c.d_T, np, vv, nv, c.d_kinw_closed, out);
+  if (c.nproj > 0) {
+    launch_apply_D(c, c.d_P, c.d_kinw_closed, c.d_DP);
+    gemm_expand(c, nv, K, c.nproj, c.d_DP + v0, nb, false, dbl(c.d_B), K, dbl(out), K, 1.0, 1.0);
+  }
+  gemm_wdot(c, nv, nv, K, dbl(vv), K, dbl(out), K, c.d_R + (size_t)v0 * nb + v0, nb, 1.0, 0.0, true);
+  launch_virtual_block(c, v0);
+}
+
+void energy_gradient(Ctx& c, roks_energies* e, double* open_out, bool want_vv) {
   ROKS_CHECK(c.have_orbitals, ROKS_ERR_STATE, "no orbitals set");
   const int nb = c.nb, K = 2 * c.npw;
   const size_t band = (size_t)nb * c.npw;
@@ -322,7 +352,10 @@ void energy_gradient(Ctx& c, roks_energies* e, double* open_out) {
   gemm_expand_to(c, nb, K, nb, c.d_theta, nb, false, dbl(c.d_psi), K, dbl(c.d_Y), K, dbl(c.d_gI), K,
                  -1.0, 1.0);
   launch_subspace(c, open_out);
+  if (want_vv || (c.flags & ROKS_FLAG_CANONICALIZE)) virtual_block(c);
 }
+
+double smallest_trial_step(const Ctx& c) { return c.dt / std::ldexp(1.0, kHalvings); }
 
 void reset_cg(Ctx& c) {
   c.have_old = false;
@@ -585,7 +618,6 @@ void forces(Ctx& c, double* f_host) {
   if (nat == 0) return;
   if (!c.d_force_loc) c.d_force_loc = dalloc<double>(c, 3 * (size_t)nat);
   // local part, dE/dR_I from rho_w = sum_L c_L rho_L, on the side stream
-  // (no GEMMs there, so the library handle's stream is not involved)
   ensure_side_stream(c);
   ROKS_HIP(hipEventRecord(c.ev_fork, c.stream));
   ROKS_HIP(hipStreamWaitEvent(c.side, c.ev_fork, 0));

@@ -83,6 +83,7 @@ _SIGS = {
     "roks_destroy": (C.c_int, [_P]),
     "roks_last_error": (C.c_char_p, [_P]),
     "roks_version": (C.c_char_p, []),
+    "roks_grid_rule": (C.c_int, [C.POINTER(C.c_double), C.c_double, C.POINTER(C.c_int32)]),
     "roks_sizes": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                              C.POINTER(C.c_int32)]),
     "roks_gvectors": (C.c_int, [_P, C.POINTER(C.c_int32)]),
@@ -146,6 +147,16 @@ def lib() -> C.CDLL:
             f.argtypes = args
         _LIB = L
     return _LIB
+
+
+def grid_rule(cell: np.ndarray, ecut: float) -> tuple:
+    """The grid roks_create takes for grid = (0, 0, 0) (host only)."""
+    c = np.ascontiguousarray(np.asarray(cell, dtype=np.float64).reshape(3, 3))
+    g = (C.c_int32 * 3)()
+    st = lib().roks_grid_rule(_dptr(c), float(ecut), g)
+    if st != 0:
+        raise RoksError(st, "roks_grid_rule failed")
+    return tuple(int(v) for v in g)
 
 
 def _dptr(a: np.ndarray):

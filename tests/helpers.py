@@ -60,3 +60,25 @@ def orthorhombic_cell(seed=2500):
     s["pos"] = np.array([[2.5, 3.0, 4.0], [6.0, 7.5, 9.0], [4.0, 9.0, 12.0], [7.5, 4.0, 6.5]])
     s["pos"] = s["pos"] + rng.normal(0, 0.05, size=s["pos"].shape)
     return s
+
+
+def band_rel(a, b):
+    """Largest per-band error: max over bands n of max_G |a_n - b_n| / ||b_n||
+    (a band whose reference is zero is measured against the largest reference
+    norm), so an error confined to one band or to small coefficients is not
+    hidden under the norm of the whole array."""
+    a, b = np.atleast_2d(np.asarray(a)), np.atleast_2d(np.asarray(b))
+    nb = np.linalg.norm(b, axis=-1)
+    floor = max(float(nb.max()), 1e-300)
+    err = np.abs(a - b).max(axis=-1)
+    return float((err / np.where(nb > 0, nb, floor)).max())
+
+
+def half_sphere_probe(miller, cell_unused, c_half, seed):
+    """s_n = <r|psi_n> over the full sphere from half-sphere coefficients:
+    r(G) the counter-based random vector keyed on (seed, band 0, G), c(-G) =
+    conj(c(G)), so s_n = r(0) c_n(0) + 2 Re sum_{G != 0, stored} conj(r) c_n."""
+    r = inputs.gaussian_pairs(seed, 0, miller)
+    w = np.full(len(miller), 2.0)
+    w[(np.asarray(miller) == 0).all(axis=1)] = 1.0
+    return np.real(np.conj(r * w)[None, :] * np.atleast_2d(c_half)).sum(axis=1)

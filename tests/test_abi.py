@@ -98,3 +98,18 @@ def test_nonfinite_position_rejected():
 def test_precision_tier_validated():
     st, msg = _create_status(inputs.tiny_cell(), precision=7)
     assert st == 1, msg
+
+
+def test_grid_rule_gives_the_workload_grids():
+    """grid = (0, 0, 0) at create: G_cut = pi N / (2 L) with N the next
+    2^a 3^b 5^c size; the molecule, oxide and batch cells were set up with
+    exactly that rule, the tiny cell (7.5 Ha on 16^3) with a larger cutoff."""
+    rb = ensure_built()
+    for s in (inputs.molecule_box(), inputs.oxide_vacancy(), *inputs.batch_systems()[:6]):
+        assert rb.grid_rule(s["cell"], s["ecut"]) == tuple(s["grid"]), s["name"]
+    # a cutoff just above the rule's value for 64 needs the next size (72)
+    assert rb.grid_rule(np.eye(3) * 24.0, inputs.grid_rule_ecut(24.0, 64) * 1.001) == (72, 72, 72)
+    # non-cubic: each axis on its own
+    g = rb.grid_rule(np.diag([10.0, 12.0, 15.0]), inputs.grid_rule_ecut(15.0, 30))
+    assert g == (20, 24, 30)
+    assert rb.lib().roks_grid_rule(None, 1.0, None) == 1
