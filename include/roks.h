@@ -217,6 +217,26 @@ roks_status roks_apply_h(roks_ctx ctx, const double* c_in, uint32_t channel_mask
 roks_status roks_apply_h_d(roks_ctx ctx, const void* c_in_dev, uint32_t channel_mask,
                            void* h_out_dev);
 
+/* For callers that cannot allocate device memory while they run (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * roks_apply_h_d with every scratch buffer of its kernels -- the FFT column
+ * buffer, the projections <beta|c_in> and D<beta|c_in>, the split-K partials
+ * of the projection product -- taken from one static device array of
+ * ROKS_NOALLOC_SCRATCH_BYTES per GPU (held from the first context on that GPU
+ * until the process ends) instead of the context's buffers; the bands go
+ * through the column buffer in as many chunks of band pairs as needed.  It
+ * calls no allocator (the split autotuner is bypassed).  Same arguments,
+ * layouts and results as roks_apply_h_d (c_in_dev NULL: the orbitals).
+ * Requires the potentials of the current orbitals (after roks_energy_gradient,
+ * roks_apply_h or a CG step; else ROKS_ERR_STATE); ROKS_ERR_SHAPE when the
+ * system's projections (two nproj x nbands arrays, one with c_in_dev NULL)
+ * and one band pair's column buffer do not fit the array.  Every call on one
+ * GPU uses that GPU's array and leaves its contents behind (nothing in it
+ * has to start at zero): calls that overlap on one GPU, from any contexts or
+ * streams, race and must be serialised by the caller. */
+#define ROKS_NOALLOC_SCRATCH_BYTES (64u << 20)
+roks_status roks_apply_h_noalloc_d(roks_ctx ctx, const void* c_in_dev, uint32_t channel_mask,
+                                   void* h_out_dev);
 
 /* Energies of the current orbitals and, if grad != NULL, the out-of-subspace
  * gradient g_I,n = (1 - sum_m |m><m|) F^n|n> (Eq. gradient), [nbands][npw][2];

@@ -256,6 +256,15 @@ roks_status roks_apply_h_d(roks_ctx ctx, const void* c_in, uint32_t mask, void* 
   });
 }
 
+roks_status roks_apply_h_noalloc_d(roks_ctx ctx, const void* c_in, uint32_t mask, void* h_out) {
+  return guard(ctx, [&](roks::Ctx& c) {
+    ROKS_CHECK(h_out, ROKS_ERR_ARG, "output is NULL");
+    if (mask) channel_count(c, mask);
+    roks::apply_noalloc(c, reinterpret_cast<const double2*>(c_in), mask,
+                        reinterpret_cast<double2*>(h_out));
+  });
+}
+
 roks_status roks_energy_gradient(roks_ctx ctx, roks_energies* e, double* grad, double* theta) {
   return guard(ctx, [&](roks::Ctx& c) {
     roks_energies en;

@@ -47,6 +47,8 @@ void init_device(Ctx& c, void* stream) {
     c.own_stream = true;
   }
   const size_t nb = c.nb, npw = c.npw, ntot = c.ntot, np = c.nproj;
+  // the static scratch of the allocation-free apply on this device
+  init_noalloc_scratch(c);
   c.npairs = (c.nb + 1) / 2;
   int cus = 0;
   ROKS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device));

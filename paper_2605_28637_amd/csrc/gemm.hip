@@ -347,7 +347,8 @@ int tuned_splits(Ctx& c, int M, int N, int K, const double* A, int lda, const do
 void gemm_wdot(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
                double* C, int ldc, double alpha, double beta, bool half_weights) {
   if (M == 0 || N == 0) return;
-  const int ks = (c.flags & ROKS_FLAG_AUTOTUNE)
+  // (the autotuner allocates a timing buffer: not inside an allocation-free call)
+  const int ks = ((c.flags & ROKS_FLAG_AUTOTUNE) && !c.no_alloc)
                      ? tuned_splits(c, M, N, K, A, lda, B, ldb, half_weights)
                      : heuristic_splits(c, M, N, K);
   KernelTimer kt(c, "gemm_wdot", ((double)M + N) * K * sizeof(double) + (double)M * N * sizeof(double),

@@ -219,6 +219,10 @@ struct Ctx {
 
   int npairs = 0;
   int nchunk = 0;
+  // the device's static scratch of the allocation-free apply (its address on
+  // this context's device) and whether a call runs on it (no autotuning then)
+  void* d_noalloc = nullptr;
+  bool no_alloc = false;
   // plane passes with the lines in registers (square planes N = G P): G and
   // P (0: not available, the LDS-plane kernels run), per-column LDS index and
   // per-row k range of the pruned [2 hmax + 1][N + 1] plane
@@ -495,6 +499,13 @@ void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bo
 void energy_gradient(Ctx& c, roks_energies* e, double* open_out = nullptr, bool want_vv = false);
 void pcg_step(Ctx& c, roks_step_info* info);
 void orthonormalize(Ctx& c, double2* vecs);
+// the allocation-free operator application (noalloc.hip): its scratch is a
+// file-scope device array of this size on every device
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+void init_noalloc_scratch(Ctx& c);
+// roks_apply_h_d's work with the scratch in that array (vecs NULL: the
+// orbitals); the potentials must be current
+void apply_noalloc(Ctx& c, const double2* vecs, uint32_t mask, double2* out);
 // the smallest trial step the next line search can take (its halvings of the
 // current trial step)
 double smallest_trial_step(const Ctx& c);

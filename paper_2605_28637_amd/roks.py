@@ -94,6 +94,7 @@ _SIGS = {
     "roks_set_positions": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "roks_apply_h": (C.c_int, [_P, C.POINTER(C.c_double), C.c_uint32, C.POINTER(C.c_double)]),
     "roks_apply_h_d": (C.c_int, [_P, _P, C.c_uint32, _P]),
+    "roks_apply_h_noalloc_d": (C.c_int, [_P, _P, C.c_uint32, _P]),
     "roks_energy_gradient": (C.c_int, [_P, C.POINTER(Energies), C.POINTER(C.c_double),
                                        C.POINTER(C.c_double)]),
     "roks_subspace": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -367,6 +368,9 @@ class Roks:
     # device-pointer variants (torch tensors or raw ints)
     def apply_h_d(self, c_in_ptr: Optional[int], mask: int, out_ptr: int):
         self._check(self._L.roks_apply_h_d(self._h, _P(c_in_ptr or 0), mask, _P(out_ptr)))
+
+    def apply_h_noalloc_d(self, c_in_ptr: Optional[int], mask: int, out_ptr: int):
+        self._check(self._L.roks_apply_h_noalloc_d(self._h, _P(c_in_ptr or 0), mask, _P(out_ptr)))
 
 
 class Mlp:
