@@ -67,8 +67,23 @@ typedef enum {
 } roks_status;
 
 /* Arithmetic tier of the FFT, pointwise and projector work.  Gram, Cholesky,
- * rotation, energy sums and the line search are FP64 in every tier. */
-typedef enum { ROKS_FP64 = 0, ROKS_FP32 = 1 } roks_precision;
+ * rotation, energy sums and the line search are FP64 in every tier, and so
+ * are the band overlaps (Theta, <S|S>, the preconditioner's projections).
+ *   ROKS_FP64         everything FP64.
+ *   ROKS_FP32         FFTs, potentials and the pointwise work in FP32; the
+ *                     products with the projector table FP64.
+ *   ROKS_FP32_BF16X3  as ROKS_FP32, and the products with the projector
+ *                     table (<beta|psi>, <d beta|psi>, sum_p (D P) beta_p;
+ *                     Sec. II A and Eq. force_hf) on the BF16 matrix cores:
+ *                     both operands split as x = hi + lo with hi = bf16(x),
+ *                     lo = bf16(x - hi), the three terms lo.hi + hi.lo +
+ *                     hi.hi accumulated in FP32 over K chunks of at most
+ *                     4096 that are added in FP64, an error of at most
+ *                     (3 2^-16 + 4096 2^-24) sum_k |a_k b_k| per inner
+ *                     product.  The first use splits the projector table
+ *                     (4 bytes per entry in each of two orientations) and
+ *                     allocates a band-sized BF16 buffer. */
+typedef enum { ROKS_FP64 = 0, ROKS_FP32 = 1, ROKS_FP32_BF16X3 = 2 } roks_precision;
 
 enum {
   ROKS_XC_PW92 = 0, /* spin LDA: Slater exchange + Perdew-Wang 1992 correlation */
@@ -228,7 +243,8 @@ roks_status roks_apply_h_d(roks_ctx ctx, const void* c_in_dev, uint32_t channel_
  * calls no allocator (the split autotuner is bypassed).  Same arguments,
  * layouts and results as roks_apply_h_d (c_in_dev NULL: the orbitals).
  * Requires the potentials of the current orbitals (after roks_energy_gradient,
- * roks_apply_h or a CG step; else ROKS_ERR_STATE); ROKS_ERR_SHAPE when the
+ * roks_apply_h or a CG step; else ROKS_ERR_STATE) and the FP64 or FP32
+ * tier (ROKS_ERR_STATE in ROKS_FP32_BF16X3); ROKS_ERR_SHAPE when the
  * system's projections (two nproj x nbands arrays, one with c_in_dev NULL)
  * and one band pair's column buffer do not fit the array.  Every call on one
  * GPU uses that GPU's array and leaves its contents behind (nothing in it
@@ -267,9 +283,9 @@ roks_status roks_reset_cg(roks_ctx ctx);
  * and resets the trial step length; the step reports restarted = 1.  The
  * count starts at roks_set_coeffs / roks_reset_cg. */
 roks_status roks_set_restart(roks_ctx ctx, int32_t period);
-/* Switch the arithmetic tier of the FFT / pointwise work (roks_precision)
- * for the following calls, keeping the orbitals and the CG state: a
- * precision ladder runs FP32 iterations first and polishes in FP64. */
+/* Switch the arithmetic tier (roks_precision) for the following calls,
+ * keeping the orbitals and the CG state: a precision ladder runs FP32 (or
+ * FP32_BF16X3) iterations first and polishes in FP64. */
 roks_status roks_set_precision(roks_ctx ctx, int32_t precision);
 /* Iterate roks_pcg_step until |E_{i+1} - E_i| < tol on two consecutive
  * iterations or maxiter; *iterations receives the count, *last the final

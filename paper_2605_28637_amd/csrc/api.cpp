@@ -308,13 +308,18 @@ roks_status roks_set_restart(roks_ctx ctx, int32_t period) {
 
 roks_status roks_set_precision(roks_ctx ctx, int32_t precision) {
   return guard(ctx, [&](roks::Ctx& c) {
-    ROKS_CHECK(precision == ROKS_FP64 || precision == ROKS_FP32, ROKS_ERR_ARG, "unknown precision");
-    if (precision == ROKS_FP32 && !c.d_vsh32) {
+    ROKS_CHECK(precision == ROKS_FP64 || precision == ROKS_FP32 || precision == ROKS_FP32_BF16X3,
+               ROKS_ERR_ARG, "unknown precision");
+    // the FFT tier and the projector-product tier
+    const int fft = precision == ROKS_FP64 ? ROKS_FP64 : ROKS_FP32;
+    const bool bf3 = precision == ROKS_FP32_BF16X3;
+    if (fft == ROKS_FP32 && !c.d_vsh32) {
       c.d_vsh32 = roks::dalloc<float>(c, (size_t)c.nsocc * c.ntot);
       c.d_vloc32 = roks::dalloc<float>(c, (size_t)2 * c.nconf * c.ntot);
     }
-    if (precision != c.prec) c.potentials_valid = false;
-    c.prec = precision;
+    if (fft != c.prec || bf3 != c.bf3) c.potentials_valid = false;
+    c.prec = fft;
+    c.bf3 = bf3;
   });
 }
 
@@ -336,7 +341,9 @@ roks_status roks_solve(roks_ctx ctx, double tol, int32_t maxiter, roks_step_info
           retried = true;
           continue;
         }
-        const double resolution = (c.prec == ROKS_FP32 ? 2e-6 : 1e-12) * std::max(1.0, std::fabs(info.E0));
+        // the energy resolution of the tier
+        const double rel = c.bf3 ? 2e-5 : c.prec == ROKS_FP32 ? 2e-6 : 1e-12;
+        const double resolution = rel * std::max(1.0, std::fabs(info.E0));
         if (std::fabs(info.dE0) * roks::smallest_trial_step(c) >= std::max(tol, resolution))
           linesearch_failed = true;
         break;

@@ -638,6 +638,7 @@ void upload_positions(Ctx& c) {
   ROKS_HIP(hipStreamSynchronize(c.stream));  // the host vectors go out of scope
   launch_vext(c);
   if (c.nproj > 0) launch_projectors(c, c.d_B, -1);
+  c.bsplit_valid = false;  // the BF16x3 split of the table is stale
   c.potentials_valid = false;
 }
 

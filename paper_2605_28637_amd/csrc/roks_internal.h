@@ -148,6 +148,14 @@ struct Ctx {
   float* d_vloc32 = nullptr;
   double* d_vext = nullptr;      // [N3][N1][N2]
   double2* d_B = nullptr;        // [nproj][npw]
+  // BF16x3 tier: the projector table split into hi / lo BF16 rows of a
+  // multiple of 64, projector-major [2][nproj][Kp] and coefficient-major
+  // [2][2 npw][npp], and the band-side split buffer [2][nb][max(Kp, npp)]
+  bool bf3 = false;
+  bool bsplit_valid = false;
+  uint16_t* d_bsplit = nullptr;
+  uint16_t* d_bsplit_t = nullptr;
+  uint16_t* d_xsplit = nullptr;
   int32_t* d_proj_atom = nullptr;
   double* d_Dblk = nullptr;
   int32_t* d_Dblk_off = nullptr;
@@ -409,6 +417,20 @@ void tile_gemm(Ctx& c, int M, int N, int K, const double* A, int lda, int alay, 
                int ldcin, double alpha, double beta, bool half_weights, int ks,
                const double* ga = nullptr);
 int tile_gemm_splits(const Ctx& c, int M, int N, int K);
+// C = alpha (sum of the ks split-K chunks in d_gemm_part, each M x N) +
+// beta Cin, the chunks added in order
+void launch_tile_reduce(Ctx& c, int ks, int M, int N, double* C, int ldc, const double* Cin, int ldcin,
+                        double alpha, double beta);
+
+// bf16x3.hip: the products with the projector table, in FP64 or, with the
+// BF16x3 tier on (c.bf3), on the BF16 matrix cores over split operands.
+// nrows <= nb rows of X (length 2 npw, leading dimension ldx):
+// C[p][n] = <beta_p|x_n> (stored-half weights)
+void proj_wdot(Ctx& c, int nrows, const double* X, int ldx, double* C, int ldc);
+// C[a nproj + p][n] = <d_a beta_p|x_n>, d_a beta(G) = -i G_a beta(G), G_a = gcart[a npw + q]
+void proj_deriv(Ctx& c, int nrows, const double* X, int ldx, const double* gcart, double* C, int ldc);
+// Y[n] += sum_p DP[p][n] beta_p (DP nproj x nrows, leading dimension lddp)
+void proj_expand(Ctx& c, int nrows, const double* DP, int lddp, double* Y, int ldy);
 
 // linalg.hip
 void gemm_wdot(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B, int ldb,

@@ -136,9 +136,11 @@ void build_problem(Ctx& c, const roks_system* s) {
   }
   ROKS_CHECK(s->xc == ROKS_XC_PW92 || s->xc == ROKS_XC_X, ROKS_ERR_ARG, "unknown xc");
   c.xc = s->xc;
-  ROKS_CHECK(s->precision == ROKS_FP64 || s->precision == ROKS_FP32, ROKS_ERR_ARG,
-             "precision tier not available");
-  c.prec = s->precision;
+  ROKS_CHECK(s->precision == ROKS_FP64 || s->precision == ROKS_FP32 || s->precision == ROKS_FP32_BF16X3,
+             ROKS_ERR_ARG, "precision tier not available");
+  // the FFT tier; the projector products follow the BF16x3 flag
+  c.prec = s->precision == ROKS_FP64 ? ROKS_FP64 : ROKS_FP32;
+  c.bf3 = s->precision == ROKS_FP32_BF16X3;
   ROKS_CHECK((s->flags & ~15u) == 0, ROKS_ERR_ARG, "unknown flag bits");
   c.flags = s->flags;
 

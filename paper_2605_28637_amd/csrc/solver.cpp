@@ -113,7 +113,7 @@ void prepare_line_search(Ctx& c, bool first) {
       std::swap(c.d_P0, c.d_P);
       c.potentials_valid = false;
     }
-    gemm_wdot(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(c.d_S), K, c.d_PS, nb, 1.0, 0.0, true);
+    proj_wdot(c, nb, dbl(c.d_S), K, c.d_PS, nb);
   }
 }
 
@@ -215,7 +215,7 @@ void compute_potentials_async(Ctx& c, const double2* orb, bool have_P, bool ener
   }
   band_dots2(c, orb, orb, nb, nullptr, c.d_kin, nullptr, c.hd_scal + 16);
   if (c.nproj > 0) {
-    gemm_wdot(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(orb), K, c.d_P, nb, 1.0, 0.0, true);
+    proj_wdot(c, nb, dbl(orb), K, c.d_P, nb);
     launch_nl_energy(c, c.d_P, c.d_enl, c.hd_scal + 16 + nb);
   }
 }
@@ -270,7 +270,7 @@ void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bo
   const bool have_P = vecs == c.d_psi && c.potentials_valid;
   const double* P = have_P ? c.d_P : c.d_dP;
   if (c.nproj > 0 && !have_P)
-    gemm_wdot(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(vecs), K, c.d_dP, nb, 1.0, 0.0, true);
+    proj_wdot(c, nb, dbl(vecs), K, c.d_dP, nb);
   if (mask == 0) {
     launch_zpass_bwd(c, vecs, nb, c.d_T, c.npairs);
     const void* vsh = c.prec == ROKS_FP32 ? (const void*)c.d_vsh32 : (const void*)c.d_vsh;
@@ -279,7 +279,7 @@ void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bo
     launch_zpass_fwd(c, c.d_T, c.npairs, vecs, nb, c.d_kinw_shell, out);
     if (c.nproj > 0) {
       launch_apply_D(c, P, c.d_kinw_shell, c.d_DP);
-      gemm_expand(c, nb, K, c.nproj, c.d_DP, nb, false, dbl(c.d_B), K, dbl(out), K, 1.0, 1.0);
+      proj_expand(c, nb, c.d_DP, nb, dbl(out), K);
     }
     if (want_Q) {
       // Q[n][X] = N^-3 sum_z Qpart[pair][z][b][X], n = 2 pair + b; d_Q holds
@@ -301,7 +301,7 @@ void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bo
     launch_zpass_fwd(c, c.d_T, c.npairs, vecs, nb, c.d_ones, o);
     if (c.nproj > 0) {
       launch_apply_D(c, P, nullptr, c.d_DP);
-      gemm_expand(c, nb, K, c.nproj, c.d_DP, nb, false, dbl(c.d_B), K, dbl(o), K, 1.0, 1.0);
+      proj_expand(c, nb, c.d_DP, nb, dbl(o), K);
     }
     ++idx;
   }
@@ -334,7 +334,7 @@ static void virtual_block(Ctx& c) {
   launch_zpass_fwd(c, c.d_T, np, vv, nv, c.d_kinw_closed, out);
   if (c.nproj > 0) {
     launch_apply_D(c, c.d_P, c.d_kinw_closed, c.d_DP);
-    gemm_expand(c, nv, K, c.nproj, c.d_DP + v0, nb, false, dbl(c.d_B), K, dbl(out), K, 1.0, 1.0);
+    proj_expand(c, nv, c.d_DP + v0, nb, dbl(out), K);
   }
   gemm_wdot(c, nv, nv, K, dbl(vv), K, dbl(out), K, c.d_R + (size_t)v0 * nb + v0, nb, 1.0, 0.0, true);
   launch_virtual_block(c, v0);
@@ -643,7 +643,7 @@ void forces(Ctx& c, double* f_host) {
     if (!c.d_dP3) c.d_dP3 = dalloc<double>(c, 3 * (size_t)c.nproj * nb);
     launch_apply_D(c, c.d_P, nullptr, c.d_DP);
     // <d_a beta_i|n> from the projector table, -i G_a applied on the fly
-    gemm_wdot_deriv(c, c.nproj, nb, K, dbl(c.d_B), K, dbl(c.d_psi), K, c.d_gcart, c.d_dP3, nb);
+    proj_deriv(c, nb, dbl(c.d_psi), K, c.d_gcart, c.d_dP3, nb);
     ROKS_HIP(hipStreamWaitEvent(c.stream, c.ev_join, 0));
     // straight into the pinned host mirror
     launch_nl_force(c, c.d_dP3, c.d_DP, c.d_kinw_shell, c.d_force_loc, c.hd_force);

@@ -322,4 +322,13 @@ void tile_gemm(Ctx& c, int M, int N, int K, const double* A, int lda, int alay, 
   }
 }
 
+void launch_tile_reduce(Ctx& c, int ks, int M, int N, double* C, int ldc, const double* Cin, int ldcin,
+                        double alpha, double beta) {
+  const size_t mn = (size_t)M * N;
+  if (mn == 0) return;
+  hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, c.stream, c.d_gemm_part,
+                     ks, M, N, C, ldc, Cin, ldcin, alpha, beta);
+  ROKS_HIP(hipGetLastError());
+}
+
 }  // namespace roks

@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libroks.so")
 
-FP64, FP32 = 0, 1
+FP64, FP32, FP32_BF16X3 = 0, 1, 2
 XC = {"pw92": 0, "x": 1}
 FLAG_SUPPRESS_OPEN_COUPLING = 1
 FLAG_CANONICALIZE = 2

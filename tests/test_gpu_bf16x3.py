@@ -1,0 +1,191 @@
+"""The BF16x3 tier (FP32 FFTs and potentials; the products with the
+projector table -- projections, their derivatives, the nonlocal expansion --
+on the BF16 matrix cores from hi/lo splits) against the FP64 oracle.
+
+Tolerances follow from the split product's error bound (P19): an inner
+product of the tier differs from the exact one by at most
+    EPS sum_k |a_k b_k|,  EPS = 3 u^2 (1 + 2u) + kc 2^-24,
+u = 2^-8 and kc = 4096 the longest FP32 accumulation.  With
+S_pn = sum_G |beta_p(G)| |x_n(G)| over the full sphere (the stored half with
+weight 2 covers the same terms), the projections carry |dP| <= EPS S, and
+the nonlocal part of an apply, sum_p beta_p(G) (D P)_pn -- itself a split
+product -- carries at most, to first order,
+    B_n(G) = EPS sum_p |beta_p(G)| ((|D| S)_pn + |(D P)_pn|).
+What remains after that bound is taken off elementwise is the FP32 local
+part's error, held to the FP32 tier's 2e-6 (relative, Frobenius).  Energies
+and forces take the same bound through E_NL = sum_n f_n P_n^T D P_n and
+Eq. force_hf.  End to end, the ladder (BF16x3 iterations, then FP64) meets
+the FP64 oracle's excitation energy within 1 meV and its forces within
+1e-4 Ha/bohr."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from helpers import ROOT, SphereMap, ensure_built, small_molecule
+from oracle import roks as orc
+from paper_2605_28637_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -8
+EPS = 3 * U * U * (1 + 2 * U) + 4096 * 2.0 ** -24
+MEV = 1.0 / 27211.386
+
+CASES = {
+    "small_odd_bands": lambda: small_molecule(),
+    "molecule_box": lambda: inputs.molecule_box(),
+}
+
+
+def _pair(system, rb):
+    print("case", system.get("name"), system["grid"], system["nbands"], "bf16x3", flush=True)
+    g = rb.Roks(system, precision=rb.FP32_BF16X3)
+    m = orc.Model(system)
+    mp = SphereMap(g.miller(), m.miller)
+    g.set_coeffs(inputs.random_coefficients(g.miller(), system["cell"], g.nb, system["seed"]), True)
+    psi = orc.orthonormalize(inputs.random_coefficients(m.miller, m.cell, m.nb, system["seed"]))
+    return g, m, mp, psi
+
+
+def _excess(got, want, bound):
+    """Frobenius norm of what the error leaves beyond the elementwise bound,
+    relative to the reference."""
+    over = np.maximum(np.abs(got - want) - bound, 0.0)
+    return float(np.linalg.norm(over) / np.linalg.norm(want))
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_bf16x3_apply_energy_forces(case):
+    rb = ensure_built()
+    s = CASES[case]()
+    g, m, mp, psi = _pair(s, rb)
+    absB = np.abs(m.beta)
+    absD = np.abs(m.D)
+    # energies: E_NL of configuration L sums f P^T D P; |d(P^T D P)| <= 2 |P|^T |D| EPS S
+    e, _, _ = g.energy_gradient()
+    pot = orc.potentials(m, psi)
+    P = orc.projections(m, psi)
+    S = absB @ np.abs(psi).T
+    dEn = 2.0 * np.einsum("in,ij,jn->n", np.abs(P), absD, EPS * S)
+    w = np.abs(m.band_w)
+    bound_E = float(w @ dEn)
+    scale = max(1.0, max(abs(v) for t in pot.terms.values() for v in t))
+    err_E = abs(e["E"] - pot.E)
+    print("E err %.3e, split bound %.3e, FP32 part %.3e" % (err_E, bound_E, 2e-6 * scale))
+    assert err_E < bound_E + 2e-6 * scale
+    # channel applies on arbitrary vectors
+    nconf = m.nconf
+    mask = (1 << (2 * nconf)) - 1
+    v = inputs.random_coefficients(g.miller(), s["cell"], g.nb, 77)
+    H = g.apply_h(v, mask)
+    vf = mp.to_full(v)
+    Pv = orc.projections(m, vf)
+    Sv = absB @ np.abs(vf).T
+    bound_Y = EPS * (((absD @ Sv) + np.abs(m.D @ Pv)).T @ absB)
+    k = 0
+    worst = 0.0
+    for L in range(nconf):
+        for sp in range(2):
+            ref = orc.apply_channel(m, pot, L, sp, vf)
+            got = mp.to_full(H[k])
+            worst = max(worst, float(np.abs(got - ref).max() / np.abs(ref).max()))
+            assert _excess(got, ref, bound_Y) < 2e-6, (L, sp)
+            k += 1
+    print("apply: largest error %.3e of the largest entry; largest bound %.3e"
+          % (worst, bound_Y.max() / np.abs(ref).max()))
+    # the bound is a worst case; the rounding errors of the split terms have
+    # random signs and grow like the root of the term count, so the error
+    # actually seen is near u^2 of the largest entry (about 1e-6 with the
+    # FP32 part), where a product missing one cross term is off by u (4e-3)
+    assert worst < 1e-5
+    # forces at the same orbitals (Eq. force_hf): the nonlocal part
+    # 2 sum_n w_n dP_a D P, with |d dP_a| <= EPS S_a, S_a = sum_G |G_a| |beta| |psi|
+    F = g.forces()
+    Fo = orc.forces(m, psi)
+    bound_F = np.zeros_like(Fo)
+    DP = np.abs(m.D @ P)
+    for a in range(3):
+        dbeta = -1j * m.G[:, a][None, :] * m.beta
+        dP = np.abs(np.real(np.conj(dbeta) @ psi.T))
+        Sa = (np.abs(m.G[:, a])[None, :] * absB) @ np.abs(psi).T
+        per = 2.0 * ((EPS * Sa) * DP + dP * (absD @ (EPS * S))) @ w
+        for i in range(m.nproj):
+            bound_F[m.proj_atom[i], a] += per[i]
+    errF = np.abs(F - Fo)
+    print("forces: largest error %.3e, largest bound %.3e" % (errF.max(), bound_F.max()))
+    assert (errF <= bound_F + 1e-5 * max(1.0, np.abs(Fo).max())).all()
+    g.close()
+
+
+def test_bf16x3_ladder_excitation_energy_and_forces():
+    """Ground state then singlet from the ground-state orbitals, BF16x3
+    iterations to |dE| < 1e-5 Ha and an FP64 polish, against the FP64 oracle
+    on the same protocol."""
+    rb = ensure_built()
+    s = small_molecule(nb=12)
+    tol = 1e-12
+
+    def ladder(r):
+        r.solve(tol=1e-5, maxiter=800)
+        r.set_precision(rb.FP64)
+        info, _ = r.solve(tol=tol, maxiter=800)
+        return info
+
+    gs = inputs.with_configuration(s, "gs")
+    g = rb.Roks(gs, precision=rb.FP32_BF16X3)
+    g.set_coeffs(inputs.random_coefficients(g.miller(), gs["cell"], g.nb, gs["seed"]), True)
+    eg = ladder(g)["E1"]
+    c = g.get_coeffs()
+    g.close()
+    r = rb.Roks(s, precision=rb.FP32_BF16X3)
+    r.set_coeffs(c, True)
+    es = ladder(r)["E1"]
+    F = r.forces()
+    r.close()
+    mg = orc.Model(gs)
+    st, hg = orc.solve(mg, inputs.random_coefficients(mg.miller, mg.cell, mg.nb, gs["seed"]),
+                       tol=tol, maxiter=800)
+    m = orc.Model(s)
+    st2, he = orc.solve(m, st.psi, tol=tol, maxiter=800)
+    Fo = orc.forces(m, st2.psi)
+    exc, exco = es - eg, he[-1].E1 - hg[-1].E1
+    print("excitation %.9f oracle %.9f Ha; force diff %.2e" % (exc, exco, np.abs(F - Fo).max()))
+    assert abs(exc - exco) < MEV
+    assert np.abs(F - Fo).max() < 1e-4
+
+
+def test_bf16x3_oxide_three_cg_steps():
+    """The oxide-vacancy supercell (96^3, 432 bands, 1 720 projectors): three
+    CG steps of the BF16x3 tier against the oracle's (stored by
+    tests/golden/make_oxide_golden.py), at the tier's energy resolution
+    2e-5 relative."""
+    rb = ensure_built()
+    with open(os.path.join(ROOT, "tests", "golden", "oxide_cg3.json")) as f:
+        gold = json.load(f)
+    s = inputs.oxide_vacancy()
+    print("oxide bf16x3", flush=True)
+    g = rb.Roks(s, precision=rb.FP32_BF16X3)
+    g.set_coeffs(inputs.random_coefficients(g.miller(), s["cell"], g.nb, s["seed"]), True)
+    for i, o in enumerate(gold["steps"]):
+        gi = g.pcg_step()
+        err = abs(gi["E1"] - o["E1"]) / max(abs(o["E1"]), abs(o["E0"]))
+        print("step", i, "E1", gi["E1"], "oracle", o["E1"], "rel %.2e" % err, flush=True)
+        assert err < 2e-5, i
+    g.close()
+
+
+def test_noalloc_entry_rejects_the_bf16x3_tier():
+    import torch
+    rb = ensure_built()
+    s = small_molecule()
+    g = rb.Roks(s, precision=rb.FP32_BF16X3)
+    g.set_coeffs(inputs.random_coefficients(g.miller(), s["cell"], g.nb, s["seed"]), True)
+    g.energy_gradient()
+    out = torch.empty((g.nb, g.npw, 2), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    with pytest.raises(rb.RoksError) as ei:
+        g.apply_h_noalloc_d(None, 0, out.data_ptr())
+    assert ei.value.status == 8
+    g.close()
