@@ -20,7 +20,7 @@ pass with every kernel family recorded (the per-family table), then the
 timed region with events only around the dominant family (the roofline
 entry), so the other launches run undisturbed.
 
-Extras on the same line: the FP32 tier on the same workload, the 64^3 /
+Extras on the same line: the FP32 and BF16x3 tiers on the same workload, the 64^3 /
 40-band molecule-in-box (configuration of the earlier headline), ROKS
 time-to-converge (plain FP64 against the FP32 ladder and the learned
 preconditioner, each judged by plain FP64 iterations), the uneven batch, and
@@ -45,6 +45,7 @@ from paper_2605_28637_amd import roks as rb  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 RESTART = 20
 
@@ -54,21 +55,26 @@ RESTART = 20
 # kernels are the ones measured.
 TRAFFIC = {}
 KERNELS = ("zpass_bwd", "plane_apply", "plane_density", "zpass_fwd", "fft3d", "gemm_wdot",
-           "gemm_expand", "xc")
+           "gemm_expand", "xc", "proj_bf3")
 
 
 def roofline(name, k, fp32=False):
     """Roofline entry of one kernel family from its summed time and work: the
     band products and expansions (gemm_*) against the FP64 matrix cores, the
-    transforms and pointwise passes against the vector units of their tier
-    (FP64 78.6, FP32 157.3 TFLOP/s), each against HBM when its algorithmic
-    flop/byte lies below that peak's ridge."""
+    BF16x3 projector products (proj_bf3, flops of the three BF16 products)
+    against the dense BF16 matrix cores (2.5 PFLOP/s), the transforms and
+    pointwise passes against the vector units of their tier (FP64 78.6, FP32
+    157.3 TFLOP/s), each against HBM when its algorithmic flop/byte lies
+    below that peak's ridge."""
     if not k["launches"] or k["ms_total"] <= 0:
         return None
     avg_s = k["ms_total"] * 1e-3 / k["launches"]
     by, fl = k["bytes"] / k["launches"], k["flops"] / k["launches"]
-    mfma = name.startswith("gemm")
-    peak = FP64_PEAK_TFLOPS if (mfma or not fp32) else FP32_VECTOR_PEAK_TFLOPS
+    mfma = name.startswith("gemm") or name == "proj_bf3"
+    if name == "proj_bf3":
+        peak = BF16_PEAK_TFLOPS
+    else:
+        peak = FP64_PEAK_TFLOPS if (mfma or not fp32) else FP32_VECTOR_PEAK_TFLOPS
     ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)
     if fl > 0 and fl / by > ridge:
         ach = fl / avg_s / 1e12
@@ -411,7 +417,7 @@ def measure(system, precision, steps, warmup, table_steps=None):
     r.synchronize()
     kernels = {k: r.timing_read(k) for k in KERNELS}
     r.timing_enable(False)
-    fp32 = precision == rb.FP32
+    fp32 = precision != rb.FP64
     roofs = {k: roofline(k, v, fp32) for k, v in kernels.items()}
     dom = max((k for k in kernels if roofs[k]), key=lambda k: kernels[k]["ms_total"])
     r.timing_only(dom)
@@ -469,6 +475,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="the headline line only (no FP32 tier, molecule, converge, batch, CPU legs)")
+    ap.add_argument("--tier", choices=("fp64", "fp32", "bf16x3"), default="fp64",
+                    help="arithmetic tier of the headline measurement (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the copy kernel that scales the HBM byte counters")
     args = ap.parse_args()
@@ -481,7 +489,8 @@ def main():
         sys.exit(2)
 
     system = inputs.oxide_vacancy()
-    head = measure(system, rb.FP64, args.steps, args.warmup, table_steps=min(args.steps, 4))
+    tier = {"fp64": rb.FP64, "fp32": rb.FP32, "bf16x3": rb.FP32_BF16X3}[args.tier]
+    head = measure(system, tier, args.steps, args.warmup, table_steps=min(args.steps, 4))
     out = {
         "metric": "band H-applies/s",
         "value": head["band_applies_per_s"],
@@ -493,7 +502,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[args.tier],
         "data": "synthetic",
         "config": {"workload": "rocksalt oxide-vacancy supercell: 3x3x3 conventional cells, "
                                "a = 8 bohr, one anion removed (215 atoms), 96^3 grid, ecut "
@@ -501,7 +510,7 @@ def main():
                                "(1 720), %d bands (428 closed + 2 open + 2 virtual), mixed-spin "
                                "+ triplet; step = one ROKS CG iteration + forces"
                                % (head["npw"], head["nb"]),
-                   "precision": "fp64", "bands": head["nb"], "grid": [96, 96, 96]},
+                   "precision": args.tier, "bands": head["nb"], "grid": [96, 96, 96]},
         "roofline": head["roofline"],
         "kernels": head["kernels"],
         "h_apply_pipeline": head["h_apply_pipeline"],
@@ -510,6 +519,13 @@ def main():
         t32 = measure(system, rb.FP32, args.steps, args.warmup, table_steps=2)
         out["oxide_fp32_tier"] = {k: t32[k] for k in ("band_applies_per_s", "ms_per_step",
                                                        "roofline", "h_apply_pipeline")}
+        tb = measure(system, rb.FP32_BF16X3, args.steps, args.warmup, table_steps=2)
+        out["oxide_bf16x3_tier"] = {
+            "arithmetic": "fp32 FFTs and potentials; projector products BF16x3 on the BF16 "
+                          "matrix cores; band overlaps, Gram, rotation, energies fp64",
+            **{k: tb[k] for k in ("band_applies_per_s", "ms_per_step", "roofline",
+                                  "h_apply_pipeline")},
+            "proj_bf3": tb["kernels"]["proj_bf3"]}
         mol = inputs.molecule_box()
         m = measure(mol, rb.FP64, max(args.steps, 20), args.warmup, table_steps=10)
         out["molecule_64"] = {

@@ -311,7 +311,9 @@ roks_status roks_synchronize(roks_ctx ctx);
  * launch.  roks_timing_enable(ctx, 1) clears the totals and starts
  * recording, 0 stops.  roks_timing_read() synchronises the stream and
  * returns, for one kernel family ("zpass_bwd", "plane_apply",
- * "plane_density", "zpass_fwd", "fft3d", "gemm_wdot", "gemm_expand", "xc"),
+ * "plane_density", "zpass_fwd", "fft3d", "gemm_wdot", "gemm_expand", "xc",
+ * "proj_bf3": the split and product launches of a BF16x3 projector product,
+ * its flops those of the three BF16 products),
  * the summed milliseconds, the launch count and the summed algorithmic HBM
  * bytes and flops of those launches (the minimum traffic and arithmetic the
  * launches' inputs and outputs imply); unknown names give zero.  Any output

@@ -1,8 +1,9 @@
 // The BF16x3 tier of the projector contractions (ROKS_FP32_BF16X3).
 //
 // The products with the projector table -- <beta_p|X> (the projections of
-// the separable nonlocal potential, Sec. II A), <d_a beta_p|X> (the nonlocal
-// part of Eq. force_hf) and the expansion sum_p (D P)_pn beta_p -- run on the
+// the separable nonlocal potential, Sec. II A), the expansion
+// sum_p (D P)_pn beta_p, and the force field sum_n w_n (D P)_pn psi_n of
+// Eq. force_hf's nonlocal part -- run on the
 // BF16 matrix cores (v_mfma_f32_16x16x32_bf16) with FP32 accumulation and a
 // split-precision correction.  Each FP64 operand x is split once into
 // hi = bf16(x) and lo = bf16(x - hi), so |x - hi - lo| <= 2^-16 |x|; a
@@ -292,8 +293,10 @@ void product(Ctx& c, int M, int N, int Kp, const uint16_t* Ah, const uint16_t* A
   const int steps = Kp / kQK;
   int ks = 1;
   if (split) {
-    // about two rounds of the chip, whole rounds of the 8 XCDs
-    ks = std::max(1, std::min(steps, cdiv(1024, tiles)));
+    // one resident round of the chip (two workgroups per CU), whole rounds
+    // of the 8 XCDs: a chunk's workgroups run together on one XCD and read
+    // its operand slices from HBM once
+    ks = std::max(1, std::min(steps, cdiv(512, tiles)));
     if (ks > 8) ks = ks / 8 * 8;
   }
   ks = std::max(ks, cdiv(Kp, kQChunk));
@@ -359,7 +362,9 @@ void proj_wdot(Ctx& c, int nrows, const double* X, int ldx, double* C, int ldc) 
   ROKS_CHECK(nrows <= c.nb, ROKS_ERR_ARG, "more rows than bands");
   ensure_tables(c);
   const int Kp = split_ld(K);
-  KernelTimer kt(c, "proj_bf3", ((double)c.nproj * Kp + (double)nrows * Kp) * 4.0 + (double)c.nproj * nrows * 8.0,
+  // algorithmic work: the split table (4 bytes an entry), X in FP64, C; the
+  // three BF16 products
+  KernelTimer kt(c, "proj_bf3", (double)c.nproj * Kp * 4.0 + (double)nrows * K * 8.0 + (double)c.nproj * nrows * 8.0,
                  6.0 * c.nproj * (double)nrows * K);
   uint16_t* xh = c.d_xsplit;
   uint16_t* xl = xh + (size_t)c.nb * Kp;
@@ -368,27 +373,28 @@ void proj_wdot(Ctx& c, int nrows, const double* X, int ldx, double* C, int ldc) 
           nullptr, 0, 1.0, 0.0, true);
 }
 
-void proj_deriv(Ctx& c, int nrows, const double* X, int ldx, const double* gcart, double* C, int ldc) {
-  const int K = 2 * c.npw;
-  if (c.nproj == 0 || nrows == 0) return;
+void proj_field(Ctx& c, const double* DPw, int lddp, const double* X, int ldx, double* Phi) {
+  const int K = 2 * c.npw, nb = c.nb;
+  if (c.nproj == 0) return;
   if (!c.bf3) {
-    gemm_wdot_deriv(c, c.nproj, nrows, K, reinterpret_cast<const double*>(c.d_B), K, X, ldx, gcart, C,
-                    ldc);
+    gemm_expand(c, c.nproj, K, nb, DPw, lddp, true, X, ldx, Phi, K, 1.0, 0.0);
     return;
   }
-  ROKS_CHECK(nrows <= c.nb, ROKS_ERR_ARG, "more rows than bands");
-  ensure_tables(c);
-  const int Kp = split_ld(K);
-  KernelTimer kt(c, "proj_bf3",
-                 3.0 * (((double)c.nproj * Kp + (double)nrows * Kp) * 4.0 + (double)c.nproj * nrows * 8.0),
-                 18.0 * c.nproj * (double)nrows * K);
-  uint16_t* xh = c.d_xsplit;
-  uint16_t* xl = xh + (size_t)c.nb * Kp;
-  for (int a = 0; a < 3; ++a) {
-    split_rows(c, X, ldx, nrows, K, Kp, 2, gcart + (size_t)a * c.npw, xh, xl);
-    product(c, c.nproj, nrows, Kp, c.d_bsplit, c.d_bsplit + (size_t)c.nproj * Kp, Kp, xh, xl, Kp,
-            C + (size_t)a * c.nproj * ldc, ldc, nullptr, 0, 1.0, 0.0, true);
+  // Phi[p][k] = sum_n DPw[p][n] X[n][k]: rows of DPw and of X^T, nb padded
+  const int nbp = split_ld(nb);
+  if (!c.d_fsplit) {
+    ROKS_CHECK(!c.no_alloc, ROKS_ERR_STATE, "the BF16x3 force buffers are not formed");
+    c.d_fsplit = dalloc<uint16_t>(c, 2 * ((size_t)c.nproj + K) * nbp);
   }
+  KernelTimer kt(c, "proj_bf3", (double)c.nproj * nb * 8.0 + (double)nb * K * 8.0 + (double)c.nproj * K * 8.0,
+                 6.0 * c.nproj * (double)nb * K);
+  uint16_t* ah = c.d_fsplit;
+  uint16_t* al = ah + (size_t)c.nproj * nbp;
+  uint16_t* bh = al + (size_t)c.nproj * nbp;
+  uint16_t* bl = bh + (size_t)K * nbp;
+  split_rows(c, DPw, lddp, c.nproj, nb, nbp, 0, nullptr, ah, al);
+  split_cols(c, X, ldx, nb, K, nbp, bh, bl);
+  product(c, c.nproj, K, nbp, ah, al, nbp, bh, bl, nbp, Phi, K, nullptr, 0, 1.0, 0.0, false);
 }
 
 void proj_expand(Ctx& c, int nrows, const double* DP, int lddp, double* Y, int ldy) {
@@ -402,7 +408,8 @@ void proj_expand(Ctx& c, int nrows, const double* DP, int lddp, double* Y, int l
   ROKS_CHECK(nrows <= c.nb, ROKS_ERR_ARG, "more rows than bands");
   ensure_tables(c);
   const int npp = split_ld(c.nproj);
-  KernelTimer kt(c, "proj_bf3", ((double)K * npp + (double)nrows * npp) * 4.0 + 16.0 * nrows * (double)K,
+  // the split table, D P in FP64, Y read and written
+  KernelTimer kt(c, "proj_bf3", (double)K * npp * 4.0 + (double)c.nproj * nrows * 8.0 + 16.0 * nrows * (double)K,
                  6.0 * c.nproj * (double)nrows * K);
   uint16_t* dh = c.d_xsplit;
   uint16_t* dl = dh + (size_t)c.nb * npp;

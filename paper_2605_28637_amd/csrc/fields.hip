@@ -543,31 +543,45 @@ __global__ void __launch_bounds__(256) k_local_force(Lattice L, const AtomP* __r
     for (int a = 0; a < 3; ++a) part[((size_t)I * gridDim.x + blockIdx.x) * 3 + a] = acc[a];
 }
 
-// dE/dR_I,axis (nonlocal) = sum_{i in I} sum_n 2 w_n dP_in (D P)_in, and the
-// force F = -(dE_loc/dR + dE_nl/dR) written in the same pass:
-// out[I][a] = -(loc[I][a] + 2 sum_{i of atom I} sum_n w_n dP[a][i][n] DP[i][n]).
-// One wave per (atom, axis), lanes over (projector, band), fixed butterfly.
-__global__ void __launch_bounds__(256) k_nl_force(const double* __restrict__ dP,
-                                                  const double* __restrict__ DP, int nb, int nproj,
-                                                  int natoms, const int32_t* __restrict__ off,
-                                                  const int32_t* __restrict__ cnt,
-                                                  const double* __restrict__ w,
-                                                  const double* __restrict__ loc,
-                                                  double* __restrict__ out) {
-  const int wave = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
-  const int lane = threadIdx.x & 63;
-  if (wave >= 3 * natoms) return;
-  const int I = wave / 3, a = wave - 3 * I;
-  const int i0 = off[I], len = cnt[I] * nb;
-  const double* d = dP + (size_t)a * nproj * nb;
-  double s = 0.0;
-  for (int j = lane; j < len; j += 64) {
-    const int i = i0 + j / nb, n = j - (j / nb) * nb;
-    s += 2.0 * w[n] * d[(size_t)i * nb + n] * DP[(size_t)i * nb + n];
-  }
+// Nonlocal force through the force field Phi_i = sum_n w_n (D P)_in psi_n
+// (Eq. force_hf, the band sum taken first):
+//   dE_nl/dR_I,a = 2 sum_{i of I} sum_n w_n <d_a beta_i|n> (D P)_in
+//                = 2 sum_{i of I} <d_a beta_i|Phi_i>,  d_a beta(G) = -i G_a beta(G).
+// Over the stored half with the Gamma weights (1 at G = 0, else 2) the inner
+// product of coefficient q is wt_q G_a(q) (Im beta Re Phi - Re beta Im Phi).
+// One workgroup per projector: the three axes' sums, fixed-order tree.
+__global__ void __launch_bounds__(256) k_nl_force_proj(const double2* __restrict__ B,
+                                                       const double2* __restrict__ Phi,
+                                                       const double* __restrict__ gcart, int npw,
+                                                       double* __restrict__ part) {
+  __shared__ double red[3 * 16];
+  const int i = blockIdx.x;
+  const double2* b = B + (size_t)i * npw;
+  const double2* f = Phi + (size_t)i * npw;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int q = threadIdx.x; q < npw; q += blockDim.x) {
+    const double2 bb = b[q], ff = f[q];
+    const double x = (q == 0 ? 1.0 : 2.0) * (bb.y * ff.x - bb.x * ff.y);
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if (lane == 0) out[I * 3 + a] = -(loc[I * 3 + a] + s);
+    for (int a = 0; a < 3; ++a) acc[a] = fma(gcart[(size_t)a * npw + q], x, acc[a]);
+  }
+  block_sum<3>(acc, red);
+  if (threadIdx.x == 0)
+    for (int a = 0; a < 3; ++a) part[(size_t)i * 3 + a] = acc[a];
+}
+
+// F[I][a] = -(loc[I][a] + 2 sum_{i of atom I} part[i][a]), projectors in order
+__global__ void __launch_bounds__(256) k_nl_force_sum(const double* __restrict__ part, int natoms,
+                                                      const int32_t* __restrict__ off,
+                                                      const int32_t* __restrict__ cnt,
+                                                      const double* __restrict__ loc,
+                                                      double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * natoms) return;
+  const int I = t / 3, a = t - 3 * I;
+  double s = 0.0;
+  for (int j = 0; j < cnt[I]; ++j) s += part[(size_t)(off[I] + j) * 3 + a];
+  out[t] = -(loc[t] + 2.0 * s);
 }
 
 // out[o][j] = scale * sum_i part[o][i][j]
@@ -774,11 +788,15 @@ void launch_local_force(Ctx& c, const double2* rhoG, double* out_part, int nblk)
   ROKS_HIP(hipGetLastError());
 }
 
-void launch_nl_force(Ctx& c, const double* dP3, const double* DP, const double* w,
-                     const double* loc, double* out) {
+void launch_nl_force(Ctx& c, const double* phi, double* part, const double* loc, double* out) {
   if (c.natoms == 0) return;
-  hipLaunchKernelGGL(k_nl_force, dim3(cdiv(3 * c.natoms, 4)), dim3(256), 0, c.stream, dP3, DP, c.nb,
-                     c.nproj, c.natoms, c.d_atom_proj_off, c.d_atom_proj_cnt, w, loc, out);
+  if (c.nproj > 0) {
+    hipLaunchKernelGGL(k_nl_force_proj, dim3(c.nproj), dim3(256), 0, c.stream, c.d_B,
+                       reinterpret_cast<const double2*>(phi), c.d_gcart, c.npw, part);
+    ROKS_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_nl_force_sum, dim3(cdiv(3 * c.natoms, 256)), dim3(256), 0, c.stream, part,
+                     c.natoms, c.d_atom_proj_off, c.d_atom_proj_cnt, loc, out);
   ROKS_HIP(hipGetLastError());
 }
 

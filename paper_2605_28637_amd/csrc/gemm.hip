@@ -53,25 +53,17 @@ __device__ inline void load4(const double* __restrict__ p, bool row_ok, int k, i
 // of 16 columns dealt to the 4 waves in turn, two groups per wave and
 // iteration with every load issued before the MFMAs; the waves' sums are
 // added in LDS in wave order, so the result does not depend on timing.
-// direct: C = alpha sum + beta C; else the sum goes to out[z][rows][N].
-// DERIV: A holds projector tables (M rows) and the output has 3 M rows,
-// a M + m for axis a = blockIdx.x / tpa: the A values are replaced by those
-// of -i G_a A (the pair (re, im) of coefficient g becomes (G_a im, -G_a re),
-// G_a = gcart[a][g]).
-template <int RB, int CB, bool DERIV>
+// direct: C = alpha sum + beta C; else the sum goes to out[z][M][N].
+template <int RB, int CB>
 __global__ void __launch_bounds__(256) k_wdot_mfma(int M, int N, int K, const double* __restrict__ A,
                                                    int lda, const double* __restrict__ B, int ldb,
                                                    double* __restrict__ out, int ldo, int kchunk,
                                                    int hw, int vec, double alpha, double beta,
-                                                   int direct, const double* __restrict__ gcart,
-                                                   int tpa) {
+                                                   int direct) {
   __shared__ double red[RB * CB * 4 * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int axis = DERIV ? (int)blockIdx.x / tpa : 0;
-  const int m0 = (DERIV ? (int)blockIdx.x - axis * tpa : (int)blockIdx.x) * 16 * RB;
+  const int m0 = (int)blockIdx.x * 16 * RB;
   const int n0 = blockIdx.y * 16 * CB;
-  const int rows = DERIV ? 3 * M : M;
-  const double* ga = DERIV ? gcart + (size_t)axis * (K / 2) : nullptr;
   const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
   const int r16 = lane & 15, s = lane >> 4;
   d4 acc[RB][CB];
@@ -88,16 +80,6 @@ __global__ void __launch_bounds__(256) k_wdot_mfma(int M, int N, int K, const do
       for (int i = 0; i < RB; ++i) {
         const int row = m0 + 16 * i + r16;
         load4(A + (size_t)row * lda + k, row < M, k, ke, vec != 0, a[q][i]);
-        if (DERIV) {
-          // k is even: the lane holds coefficients k/2 and k/2 + 1
-          const double g0 = k < ke ? ga[k >> 1] : 0.0;
-          const double g1 = k + 2 < ke ? ga[(k >> 1) + 1] : 0.0;
-          const double re0 = a[q][i][0], im0 = a[q][i][1], re1 = a[q][i][2], im1 = a[q][i][3];
-          a[q][i][0] = g0 * im0;
-          a[q][i][1] = -g0 * re0;
-          a[q][i][2] = g1 * im1;
-          a[q][i][3] = -g1 * re1;
-        }
         if (hw) {
 #pragma unroll
           for (int t = 0; t < 4; ++t)
@@ -149,13 +131,12 @@ __global__ void __launch_bounds__(256) k_wdot_mfma(int M, int N, int K, const do
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + 16 * i + s + 4 * r, n = n0 + 16 * j + r16;
         if (m >= M || n >= N) continue;
-        const int mo = DERIV ? axis * M + m : m;
         if (direct) {
           double v = alpha * acc[i][j][r];
-          if (beta != 0.0) v += beta * out[(size_t)mo * ldo + n];
-          out[(size_t)mo * ldo + n] = v;
+          if (beta != 0.0) v += beta * out[(size_t)m * ldo + n];
+          out[(size_t)m * ldo + n] = v;
         } else {
-          out[((size_t)blockIdx.z * rows + mo) * N + n] = acc[i][j][r];
+          out[((size_t)blockIdx.z * M + m) * N + n] = acc[i][j][r];
         }
       }
 }
@@ -214,25 +195,24 @@ int tile_blocks(int n16, int cap) {
   return best;
 }
 
-template <int RB, int CB, bool DERIV>
+template <int RB, int CB>
 void launch_wdot_mfma(Ctx& c, dim3 grid, int M, int N, int K, const double* A, int lda, const double* B,
                       int ldb, double* out, int ldo, int kchunk, int hw, int vec, double alpha,
-                      double beta, int direct, const double* gcart, int tpa) {
-  hipLaunchKernelGGL((k_wdot_mfma<RB, CB, DERIV>), grid, dim3(256), 0, c.stream, M, N, K, A, lda, B, ldb,
-                     out, ldo, kchunk, hw, vec, alpha, beta, direct, gcart, tpa);
+                      double beta, int direct) {
+  hipLaunchKernelGGL((k_wdot_mfma<RB, CB>), grid, dim3(256), 0, c.stream, M, N, K, A, lda, B, ldb, out,
+                     ldo, kchunk, hw, vec, alpha, beta, direct);
 }
 
 using WdotLaunch = void (*)(Ctx&, dim3, int, int, int, const double*, int, const double*, int, double*,
-                            int, int, int, int, double, double, int, const double*, int);
+                            int, int, int, int, double, double, int);
 
-template <bool D>
 const WdotLaunch (&wdot_table())[5][3] {
   static const WdotLaunch t[5][3] = {
-      {launch_wdot_mfma<1, 1, D>, launch_wdot_mfma<1, 2, D>, launch_wdot_mfma<1, 3, D>},
-      {launch_wdot_mfma<2, 1, D>, launch_wdot_mfma<2, 2, D>, launch_wdot_mfma<2, 3, D>},
-      {launch_wdot_mfma<3, 1, D>, launch_wdot_mfma<3, 2, D>, launch_wdot_mfma<3, 3, D>},
-      {launch_wdot_mfma<4, 1, D>, launch_wdot_mfma<4, 2, D>, launch_wdot_mfma<4, 3, D>},
-      {launch_wdot_mfma<5, 1, D>, launch_wdot_mfma<5, 2, D>, launch_wdot_mfma<5, 3, D>}};
+      {launch_wdot_mfma<1, 1>, launch_wdot_mfma<1, 2>, launch_wdot_mfma<1, 3>},
+      {launch_wdot_mfma<2, 1>, launch_wdot_mfma<2, 2>, launch_wdot_mfma<2, 3>},
+      {launch_wdot_mfma<3, 1>, launch_wdot_mfma<3, 2>, launch_wdot_mfma<3, 3>},
+      {launch_wdot_mfma<4, 1>, launch_wdot_mfma<4, 2>, launch_wdot_mfma<4, 3>},
+      {launch_wdot_mfma<5, 1>, launch_wdot_mfma<5, 2>, launch_wdot_mfma<5, 3>}};
   return t;
 }
 
@@ -259,7 +239,7 @@ void gemm_wdot_launch(Ctx& c, int M, int N, int K, const double* A, int lda, con
     return;
   }
   const int RB = tile_blocks(cdiv(M, 16), 5), CB = tile_blocks(cdiv(N, 16), 3);
-  const WdotLaunch launch = wdot_table<false>()[RB - 1][CB - 1];
+  const WdotLaunch launch = wdot_table()[RB - 1][CB - 1];
   // 16-byte loads need 16-byte aligned rows
   const int vec = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) % 16 == 0 &&
                    lda % 2 == 0 && ldb % 2 == 0)
@@ -270,11 +250,11 @@ void gemm_wdot_launch(Ctx& c, int M, int N, int K, const double* A, int lda, con
   const int ks = cdiv(K, kchunk);
   dim3 grid(cdiv(M, 16 * RB), cdiv(N, 16 * CB), ks);
   if (ks == 1) {
-    launch(c, grid, M, N, K, A, lda, B, ldb, C, ldc, kchunk, hw, vec, alpha, beta, 1, nullptr, 1);
+    launch(c, grid, M, N, K, A, lda, B, ldb, C, ldc, kchunk, hw, vec, alpha, beta, 1);
     ROKS_HIP(hipGetLastError());
     return;
   }
-  launch(c, grid, M, N, K, A, lda, B, ldb, c.d_gemm_part, N, kchunk, hw, vec, 1.0, 0.0, 0, nullptr, 1);
+  launch(c, grid, M, N, K, A, lda, B, ldb, c.d_gemm_part, N, kchunk, hw, vec, 1.0, 0.0, 0);
   ROKS_HIP(hipGetLastError());
   splitk_sum(c, ks, M, N, C, ldc, alpha, beta);
 }
@@ -354,42 +334,6 @@ void gemm_wdot(Ctx& c, int M, int N, int K, const double* A, int lda, const doub
   KernelTimer kt(c, "gemm_wdot", ((double)M + N) * K * sizeof(double) + (double)M * N * sizeof(double),
                  2.0 * M * N * (double)K);
   gemm_wdot_launch(c, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, half_weights, ks);
-}
-
-void gemm_wdot_deriv(Ctx& c, int np, int N, int K, const double* B, int ldb, const double* X, int ldx,
-                     const double* gcart, double* C, int ldc) {
-  if (np == 0 || N == 0) return;
-  ROKS_CHECK(K % 2 == 0, ROKS_ERR_ARG, "derivative products need whole complex coefficients");
-  KernelTimer kt(c, "gemm_wdot", ((double)np + N) * K * sizeof(double) + 3.0 * np * N * sizeof(double),
-                 6.0 * np * N * (double)K);
-  if (np >= 128 && N >= 128) {
-    // compute-bound: the LDS-tiled product, one launch per axis
-    for (int a = 0; a < 3; ++a)
-      tile_gemm(c, np, N, K, B, ldb, 0, X, ldx, 0, nullptr, 0.0, C + (size_t)a * np * ldc, ldc, nullptr,
-                0, 1.0, 0.0, true, 0, gcart + (size_t)a * (K / 2));
-    return;
-  }
-  const int RB = tile_blocks(cdiv(np, 16), 5), CB = tile_blocks(cdiv(N, 16), 3);
-  const WdotLaunch launch = wdot_table<true>()[RB - 1][CB - 1];
-  const int vec = ((reinterpret_cast<uintptr_t>(B) | reinterpret_cast<uintptr_t>(X)) % 16 == 0 &&
-                   ldb % 2 == 0 && ldx % 2 == 0)
-                      ? 1
-                      : 0;
-  const int tpa = cdiv(np, 16 * RB);
-  const int tiles = 3 * tpa * cdiv(N, 16 * CB);
-  int ks = std::max(1, std::min(cdiv(K, kWdotStep), cdiv(256, tiles)));
-  while ((size_t)ks * 3 * np * N > c.gemm_part_capacity && ks > 1) --ks;
-  const int kchunk = cdiv(cdiv(K, ks), kWdotStep) * kWdotStep;
-  ks = cdiv(K, kchunk);
-  dim3 grid(3 * tpa, cdiv(N, 16 * CB), ks);
-  if (ks == 1) {
-    launch(c, grid, np, N, K, B, ldb, X, ldx, C, ldc, kchunk, 1, vec, 1.0, 0.0, 1, gcart, tpa);
-    ROKS_HIP(hipGetLastError());
-    return;
-  }
-  launch(c, grid, np, N, K, B, ldb, X, ldx, c.d_gemm_part, N, kchunk, 1, vec, 1.0, 0.0, 0, gcart, tpa);
-  ROKS_HIP(hipGetLastError());
-  splitk_sum(c, ks, 3 * np, N, C, ldc, 1.0, 0.0);
 }
 
 }  // namespace roks

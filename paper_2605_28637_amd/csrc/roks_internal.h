@@ -156,6 +156,7 @@ struct Ctx {
   uint16_t* d_bsplit = nullptr;
   uint16_t* d_bsplit_t = nullptr;
   uint16_t* d_xsplit = nullptr;
+  uint16_t* d_fsplit = nullptr;   // force field operands [2][nproj + 2 npw][nbp]
   int32_t* d_proj_atom = nullptr;
   double* d_Dblk = nullptr;
   int32_t* d_Dblk_off = nullptr;
@@ -203,7 +204,7 @@ struct Ctx {
   double* d_force = nullptr;     // [natoms][3]
   double* d_force_loc = nullptr; // [natoms][3] local part (side stream)
   double* d_gcart = nullptr;     // [3][npw] Cartesian G of the stored coefficients (forces)
-  double* d_dP3 = nullptr;       // [3][nproj][nb] derivative projections (forces)
+  double* d_phi = nullptr;       // [nproj][npw] force field sum_n w_n (D P)_in psi_n, then 3 nproj sums
   void* d_atoms = nullptr;       // per-atom position and local-well parameters
   void* d_projinfo = nullptr;    // per-projector atom, l, m, radius
   double* d_dP = nullptr;        // [nproj][nb] derivative projections
@@ -397,10 +398,9 @@ void launch_local_force(Ctx& c, const double2* rhoG, double* out_part, int nblk)
 void launch_pack_rho_weighted(Ctx& c);
 size_t atom_info_bytes();
 size_t proj_info_bytes();
-// forces from the three derivative projections dP3 [3][nproj][nb]
-void launch_nl_force(Ctx& c, const double* dP3, const double* DP, const double* w,
-                     const double* loc, double* out);
-// the three derivative tables -i G_a beta, [3][nproj][npw]
+// forces: out = -(loc + nonlocal part) from the force field phi [nproj][npw]
+// (Phi_i = sum_n w_n (D P)_in psi_n); part: 3 nproj doubles of scratch
+void launch_nl_force(Ctx& c, const double* phi, double* part, const double* loc, double* out);
 // the Cartesian components of every stored G, [3][npw]
 void launch_gcart(Ctx& c, double* gcart);
 
@@ -409,13 +409,10 @@ void launch_gcart(Ctx& c, double* gcart);
 // from the shape) summed in chunk order.  alay 0: op(A)[m][k] = A[m lda + k],
 // 1: A[k lda + m]; blay 0: op(B)[k][n] = B[n ldb + k], 1: B[k ldb + n];
 // B2 (blay 1, nullable): op(B) + b2 op(B2); half_weights (alay = blay = 0):
-// the Gamma weight of k (1 for k < 2, else 2); Cin nullable (C); ga
-// (nullable, weighted inner products only): A's coefficients multiplied by
-// -i G_a with G_a = ga[k / 2] (derivative projections)
+// the Gamma weight of k (1 for k < 2, else 2); Cin nullable (C)
 void tile_gemm(Ctx& c, int M, int N, int K, const double* A, int lda, int alay, const double* B,
                int ldb, int blay, const double* B2, double b2, double* C, int ldc, const double* Cin,
-               int ldcin, double alpha, double beta, bool half_weights, int ks,
-               const double* ga = nullptr);
+               int ldcin, double alpha, double beta, bool half_weights, int ks);
 int tile_gemm_splits(const Ctx& c, int M, int N, int K);
 // C = alpha (sum of the ks split-K chunks in d_gemm_part, each M x N) +
 // beta Cin, the chunks added in order
@@ -427,20 +424,15 @@ void launch_tile_reduce(Ctx& c, int ks, int M, int N, double* C, int ldc, const 
 // nrows <= nb rows of X (length 2 npw, leading dimension ldx):
 // C[p][n] = <beta_p|x_n> (stored-half weights)
 void proj_wdot(Ctx& c, int nrows, const double* X, int ldx, double* C, int ldc);
-// C[a nproj + p][n] = <d_a beta_p|x_n>, d_a beta(G) = -i G_a beta(G), G_a = gcart[a npw + q]
-void proj_deriv(Ctx& c, int nrows, const double* X, int ldx, const double* gcart, double* C, int ldc);
+// the force field Phi[p] = sum_n DPw[p][n] x_n (all nb bands of X; DPw
+// nproj x nb, leading dimension lddp), [nproj][2 npw]
+void proj_field(Ctx& c, const double* DPw, int lddp, const double* X, int ldx, double* Phi);
 // Y[n] += sum_p DP[p][n] beta_p (DP nproj x nrows, leading dimension lddp)
 void proj_expand(Ctx& c, int nrows, const double* DP, int lddp, double* Y, int ldy);
 
 // linalg.hip
 void gemm_wdot(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
                double* C, int ldc, double alpha, double beta, bool half_weights);
-// C[a np + i][n] = <d_a beta_i|x_n> (a = x, y, z; C is 3 np x N, row-major,
-// ldc = N) for projector rows B (np x K) and bands X (N x K) with stored-half
-// weights: d_a beta_i(G) = -i G_a beta_i(G), formed from B and gcart on the
-// fly (no derivative tables)
-void gemm_wdot_deriv(Ctx& c, int np, int N, int K, const double* B, int ldb, const double* X, int ldx,
-                     const double* gcart, double* C, int ldc);
 void gemm_expand(Ctx& c, int N, int K, int Mdim, const double* M, int ldm, bool transM,
                  const double* X, int ldx, double* Y, int ldy, double alpha, double beta);
 // the same with the beta term read from Yin (Y = alpha M^T X + beta Yin;

@@ -640,13 +640,16 @@ void forces(Ctx& c, double* f_host) {
       c.d_gcart = dalloc<double>(c, 3 * (size_t)c.npw);
       launch_gcart(c, c.d_gcart);
     }
-    if (!c.d_dP3) c.d_dP3 = dalloc<double>(c, 3 * (size_t)c.nproj * nb);
-    launch_apply_D(c, c.d_P, nullptr, c.d_DP);
-    // <d_a beta_i|n> from the projector table, -i G_a applied on the fly
-    proj_deriv(c, nb, dbl(c.d_psi), K, c.d_gcart, c.d_dP3, nb);
+    // the field, then 3 nproj partial sums (the side stream's local part
+    // uses d_part meanwhile)
+    if (!c.d_phi) c.d_phi = dalloc<double>(c, (size_t)c.nproj * (K + 3));
+    // w_n (D P)_in, then the force field Phi_i = sum_n w_n (D P)_in psi_n: one
+    // product over the bands in place of three derivative projections
+    launch_apply_D(c, c.d_P, c.d_kinw_shell, c.d_DP);
+    proj_field(c, c.d_DP, nb, dbl(c.d_psi), K, c.d_phi);
     ROKS_HIP(hipStreamWaitEvent(c.stream, c.ev_join, 0));
     // straight into the pinned host mirror
-    launch_nl_force(c, c.d_dP3, c.d_DP, c.d_kinw_shell, c.d_force_loc, c.hd_force);
+    launch_nl_force(c, c.d_phi, c.d_phi + (size_t)c.nproj * K, c.d_force_loc, c.hd_force);
     sync(c);
     std::memcpy(f_host, c.h_force, 3 * (size_t)nat * sizeof(double));
   } else {

@@ -32,13 +32,11 @@ constexpr int kTPer = kTM * kTK / kTThreads;  // doubles of each operand a threa
 
 // the 4 doubles of op(X) a thread stages per 16-k step: LAY 0 (k
 // contiguous) row r = t / 4, k = 4 (t % 4) .. + 4; LAY 1 (row contiguous)
-// k = t / 32, rows 4 (t % 32) .. + 4.  DERIV (LAY 0, rows of projector
-// coefficients): the pair (re, im) of coefficient g becomes (G_a im, -G_a re),
-// G_a = ga[g] (-i G_a beta).
-template <int LAY, bool HW, bool SUM, bool DERIV = false>
+// k = t / 32, rows 4 (t % 32) .. + 4.
+template <int LAY, bool HW, bool SUM>
 __device__ __forceinline__ void tile_load(const double* __restrict__ X, const double* __restrict__ X2,
                                           double x2, int ld, int r0, int rows, int k0, int ke,
-                                          int vec, double* v, const double* __restrict__ ga = nullptr) {
+                                          int vec, double* v) {
   const int t = threadIdx.x;
   if (LAY == 0) {
     const int r = r0 + (t >> 2), kb = k0 + 4 * (t & 3);
@@ -54,16 +52,6 @@ __device__ __forceinline__ void tile_load(const double* __restrict__ X, const do
     } else {
 #pragma unroll
       for (int j = 0; j < 4; ++j) v[j] = (rok && kb + j < ke) ? p[j] : 0.0;
-    }
-    if (DERIV) {
-      // kb is a multiple of 4: the thread holds coefficients kb/2, kb/2 + 1
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const double g = (rok && kb + 2 * q < ke) ? ga[(kb >> 1) + q] : 0.0;
-        const double re = v[2 * q], im = v[2 * q + 1];
-        v[2 * q] = g * im;
-        v[2 * q + 1] = -g * re;
-      }
     }
     if (HW) {
 #pragma unroll
@@ -125,12 +113,12 @@ struct TileOrder {
 };
 
 // DIRECT: C = alpha sum + beta Cin; else the chunk's sum to part[z][M][N]
-template <int ALAY, int BLAY, bool HW, bool SUM, bool DERIV = false>
+template <int ALAY, int BLAY, bool HW, bool SUM>
 __global__ void __launch_bounds__(kTThreads, 2) k_tile_gemm(
     int M, int N, int K, const double* __restrict__ A, int lda, const double* __restrict__ B,
     const double* __restrict__ B2, double b2, int ldb, double* __restrict__ C, int ldc,
     const double* __restrict__ Cin, int ldcin, double alpha, double beta, int kchunk, int direct,
-    int avec, int bvec, double* __restrict__ part, TileOrder ord, const double* __restrict__ ga = nullptr) {
+    int avec, int bvec, double* __restrict__ part, TileOrder ord) {
   __shared__ double As[2][kTK * kTLd];
   __shared__ double Bs[2][kTK * kTLd];
   // XCD-aware order: workgroup L runs on XCD L % 8 (round-robin dispatch);
@@ -164,7 +152,7 @@ __global__ void __launch_bounds__(kTThreads, 2) k_tile_gemm(
   double va[kTPer], vb[kTPer];
   int buf = 0;
   if (kb < ke) {
-    tile_load<ALAY, HW, false, DERIV>(A, nullptr, 0.0, lda, m0, M, kb, ke, avec, va, ga);
+    tile_load<ALAY, HW, false>(A, nullptr, 0.0, lda, m0, M, kb, ke, avec, va);
     tile_load<BLAY, false, SUM>(B, B2, b2, ldb, n0, N, kb, ke, bvec, vb);
     tile_store<ALAY>(As[0], va);
     tile_store<BLAY>(Bs[0], vb);
@@ -174,7 +162,7 @@ __global__ void __launch_bounds__(kTThreads, 2) k_tile_gemm(
     const bool more = k0 + kTK < ke;
     if (more) {
       // the next step's loads in flight while this step's MFMAs run
-      tile_load<ALAY, HW, false, DERIV>(A, nullptr, 0.0, lda, m0, M, k0 + kTK, ke, avec, va, ga);
+      tile_load<ALAY, HW, false>(A, nullptr, 0.0, lda, m0, M, k0 + kTK, ke, avec, va);
       tile_load<BLAY, false, SUM>(B, B2, b2, ldb, n0, N, k0 + kTK, ke, bvec, vb);
     }
     const double* as = As[buf];
@@ -235,20 +223,19 @@ __global__ void __launch_bounds__(256) k_tile_reduce(const double* __restrict__ 
   C[(size_t)m * ldc + n] = v;
 }
 
-template <int ALAY, int BLAY, bool HW, bool SUM, bool DERIV = false>
+template <int ALAY, int BLAY, bool HW, bool SUM>
 void launch_tile(Ctx& c, dim3 grid, int M, int N, int K, const double* A, int lda, const double* B,
                  const double* B2, double b2, int ldb, double* C, int ldc, const double* Cin, int ldcin,
-                 double alpha, double beta, int kchunk, int direct, int avec, int bvec, double* part,
-                 const double* ga = nullptr) {
+                 double alpha, double beta, int kchunk, int direct, int avec, int bvec, double* part) {
   TileOrder ord;
   ord.gx = (int)grid.x;
   ord.by_chunk = grid.z > 1 ? 1 : 0;
   ord.groups = ord.by_chunk ? (int)grid.z : (int)grid.y;
   ord.members = ord.by_chunk ? (int)(grid.x * grid.y) : (int)grid.x;
   const unsigned nwg = 8u * (unsigned)cdiv(ord.groups, 8) * (unsigned)ord.members;
-  hipLaunchKernelGGL((k_tile_gemm<ALAY, BLAY, HW, SUM, DERIV>), dim3(nwg), dim3(kTThreads), 0, c.stream,
-                     M, N, K, A, lda, B, B2, b2, ldb, C, ldc, Cin, ldcin, alpha, beta, kchunk, direct,
-                     avec, bvec, part, ord, ga);
+  hipLaunchKernelGGL((k_tile_gemm<ALAY, BLAY, HW, SUM>), dim3(nwg), dim3(kTThreads), 0, c.stream, M,
+                     N, K, A, lda, B, B2, b2, ldb, C, ldc, Cin, ldcin, alpha, beta, kchunk, direct, avec,
+                     bvec, part, ord);
 }
 
 bool aligned16(const void* p, int ld) {
@@ -257,12 +244,15 @@ bool aligned16(const void* p, int ld) {
 
 }  // namespace
 
-// The split count: enough (tile, chunk) workgroups for about two rounds over
-// the device's CUs at two per CU, each chunk at least 64 k (four steps), a
+// The split count: enough (tile, chunk) workgroups for one round over the
+// device's CUs at two per CU, each chunk at least 64 k (four steps), a
 // multiple of 8 chunks beyond 8, within the partial buffer.
 int tile_gemm_splits(const Ctx& c, int M, int N, int K) {
   const int tiles = cdiv(M, kTM) * cdiv(N, kTN);
-  int ks = std::max(1, std::min(cdiv(1024, tiles), cdiv(K, 64)));
+  // one resident round (two workgroups per CU): a chunk's workgroups then
+  // run together on their XCD and read its operand slices from HBM once (a
+  // chunk split over two rounds reads them twice)
+  int ks = std::max(1, std::min(cdiv(512, tiles), cdiv(K, 64)));
   // whole rounds of the 8 XCDs (one chunk's workgroups share an XCD)
   if (ks > 8) ks = ks / 8 * 8;
   while (ks > 1 && (size_t)ks * M * N > c.gemm_part_capacity) --ks;
@@ -271,10 +261,8 @@ int tile_gemm_splits(const Ctx& c, int M, int N, int K) {
 
 void tile_gemm(Ctx& c, int M, int N, int K, const double* A, int lda, int alay, const double* B,
                int ldb, int blay, const double* B2, double b2, double* C, int ldc, const double* Cin,
-               int ldcin, double alpha, double beta, bool half_weights, int ks, const double* ga) {
+               int ldcin, double alpha, double beta, bool half_weights, int ks) {
   if (M == 0 || N == 0) return;
-  ROKS_CHECK(!ga || (half_weights && alay == 0 && blay == 0 && !B2 && K % 2 == 0), ROKS_ERR_ARG,
-             "derivative products are weighted inner products of whole coefficients");
   ROKS_CHECK(!(half_weights && B2), ROKS_ERR_ARG, "weighted products take one B operand");
   if (!Cin) {
     Cin = C;
@@ -293,10 +281,7 @@ void tile_gemm(Ctx& c, int M, int N, int K, const double* A, int lda, int alay, 
 #define ROKS_TILE(AL, BL, HWV, SUMV)                                                                \
   launch_tile<AL, BL, HWV, SUMV>(c, grid, M, N, K, A, lda, B, B2, b2, ldb, C, ldc, Cin, ldcin, alpha, \
                                  beta, kchunk, direct, avec, bvec, part)
-  if (ga) {
-    launch_tile<0, 0, true, false, true>(c, grid, M, N, K, A, lda, B, B2, b2, ldb, C, ldc, Cin, ldcin,
-                                         alpha, beta, kchunk, direct, avec, bvec, part, ga);
-  } else if (half_weights) {
+  if (half_weights) {
     ROKS_CHECK(alay == 0 && blay == 0, ROKS_ERR_ARG, "weighted products are inner products");
     ROKS_TILE(0, 0, true, false);
   } else if (B2) {

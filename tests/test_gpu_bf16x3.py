@@ -100,17 +100,18 @@ def test_bf16x3_apply_energy_forces(case):
     # actually seen is near u^2 of the largest entry (about 1e-6 with the
     # FP32 part), where a product missing one cross term is off by u (4e-3)
     assert worst < 1e-5
-    # forces at the same orbitals (Eq. force_hf): the nonlocal part
-    # 2 sum_n w_n dP_a D P, with |d dP_a| <= EPS S_a, S_a = sum_G |G_a| |beta| |psi|
+    # forces at the same orbitals (Eq. force_hf): the nonlocal part is
+    # 2 sum_p <d_a beta_p|Phi_p> with the force field Phi_p = sum_n w_n (D P)_pn
+    # psi_n, a split product (|dPhi_p| <= EPS sum_n |w_n (D P)_pn| |psi_n|) of
+    # projections that carry EPS S; with S_a = sum_G |G_a| |beta| |psi| the
+    # error is at most 2 sum_pn w_n S_a (EPS |D P| + |D| EPS S)
     F = g.forces()
     Fo = orc.forces(m, psi)
     bound_F = np.zeros_like(Fo)
     DP = np.abs(m.D @ P)
     for a in range(3):
-        dbeta = -1j * m.G[:, a][None, :] * m.beta
-        dP = np.abs(np.real(np.conj(dbeta) @ psi.T))
         Sa = (np.abs(m.G[:, a])[None, :] * absB) @ np.abs(psi).T
-        per = 2.0 * ((EPS * Sa) * DP + dP * (absD @ (EPS * S))) @ w
+        per = 2.0 * (Sa * (EPS * DP + absD @ (EPS * S))) @ w
         for i in range(m.nproj):
             bound_F[m.proj_atom[i], a] += per[i]
     errF = np.abs(F - Fo)
