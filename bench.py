@@ -53,7 +53,13 @@ RESTART = 20
 # FETCH_SIZE / WRITE_SIZE passes summarised in profiles/ (scaled by the
 # copy-kernel calibration); reported only while the sources of the family's
 # kernels are the ones measured.
-TRAFFIC = {}
+TRAFFIC = {
+    ("gemm_expand", "oxide", 0): {
+        "bytes_per_launch": 1.04283e+09,
+        "profile": "profiles/gemm_expand_oxide_fp64_traffic.md",
+        "sources": ["paper_2605_28637_amd/csrc/tile_gemm.hip"],
+        "sha256": "a1c4a30d25f4987e8179827f8686bc85d96fa48881ef4402e07facc2abb96a42"},
+}
 KERNELS = ("zpass_bwd", "plane_apply", "plane_density", "zpass_fwd", "fft3d", "gemm_wdot",
            "gemm_expand", "xc", "proj_bf3")
 
