@@ -299,6 +299,50 @@ roks_status roks_set_precision(roks_ctx ctx, int32_t precision);
 roks_status roks_solve(roks_ctx ctx, double tol, int32_t maxiter, roks_step_info* last,
                        int32_t* iterations);
 
+/* DIIS on the residual of Eq. residual_frank (Sec. II A; the DIIS method of
+ * Hutter, Luthi and Parrinello that the paper names), an alternative to the
+ * CG step that can also converge onto saddle points of the functional.
+ * Each step, from the current orbitals:
+ *   r_n = F^n|n> - sum_m |m> Lambda_mn, Lambda_mn = theta_mn -
+ *         lambda_mn (theta_mn - theta_nm), theta_mn = <m|F^n|n>, with
+ *         lambda_mn = 1/2 (r is then the full gradient of Eq. gradient) or,
+ *         with `asymmetric`, lambda_ab = 1/2 and lambda_ba = -1/2 for the two
+ *         open bands a < b (the coupling the paper uses to steer away from
+ *         the triplet-like collapse; lambda_mn multiplies the coefficient of
+ *         |m> in the residual of band n);
+ *   e_n = K_n r_n, the Teter preconditioner of Eq. prec_k with E_ref =
+ *         1.5 <r_n|T|r_n> / <r_n|r_n> and no projection;
+ *   the orbitals and e of the last `history` steps are kept; c minimises
+ *         c^T B c subject to sum c = 1, B_ij = sum_n <e^i_n|e^j_n> (the
+ *         oldest iterates are dropped while that system is singular);
+ *   psi = sum_i c_i (psi^i + step e^i), orthonormalised by the Cholesky
+ *         factor of its Gram matrix in band order.
+ * The kept iterates stay with the context until roks_diis_reset,
+ * roks_set_coeffs, roks_set_positions, a CG step, or a call with another
+ * history or coupling; a DIIS step drops the carried CG directions.  The
+ * first step allocates 2 ROKS_DIIS_MAX_HISTORY band arrays.  If the new
+ * orbitals are linearly dependent (ROKS_ERR_NOT_PD) the step's input
+ * orbitals are kept and the history is dropped. */
+#define ROKS_DIIS_MAX_HISTORY 8
+typedef struct {
+  int32_t history;    /* iterates combined, 1 .. ROKS_DIIS_MAX_HISTORY    */
+  double step;        /* length of the preconditioned residual step, > 0  */
+  int32_t asymmetric; /* 1: lambda_ab = 1/2, lambda_ba = -1/2             */
+} roks_diis_params;
+typedef struct {
+  double E;             /* energy of the step's input orbitals            */
+  double rnorm2;        /* sum_n <r_n|r_n>                                */
+  double open_coupling; /* theta_ab - theta_ba of the open pair (0 without) */
+  int32_t used;         /* iterates combined                              */
+  double coeffs[ROKS_DIIS_MAX_HISTORY]; /* their coefficients, oldest first */
+} roks_diis_info;
+roks_status roks_diis_step(roks_ctx ctx, const roks_diis_params* params, roks_diis_info* info);
+/* roks_diis_step until |E_{i+1} - E_i| < tol on two consecutive steps or
+ * maxiter (the CG solve's rule); *last and *iterations as in roks_solve. */
+roks_status roks_diis_solve(roks_ctx ctx, const roks_diis_params* params, double tol,
+                            int32_t maxiter, roks_diis_info* last, int32_t* iterations);
+roks_status roks_diis_reset(roks_ctx ctx);
+
 /* Hellmann-Feynman forces F_I = -dE/dR_I (Eq. force_hf; the overlap term
  * vanishes for S = 1) at the current orbitals, [natoms][3] Ha/bohr. */
 roks_status roks_forces(roks_ctx ctx, double* f);

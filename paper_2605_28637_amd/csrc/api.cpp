@@ -168,6 +168,7 @@ roks_status roks_set_coeffs(roks_ctx ctx, const double* cf, int32_t orthonormali
     c.have_orbitals = true;
     c.potentials_valid = false;
     roks::reset_cg(c);
+    roks::reset_diis(c);
   });
 }
 
@@ -181,6 +182,7 @@ roks_status roks_set_coeffs_d(roks_ctx ctx, const void* cf, int32_t orthonormali
     c.have_orbitals = true;
     c.potentials_valid = false;
     roks::reset_cg(c);
+    roks::reset_diis(c);
   });
 }
 
@@ -212,6 +214,7 @@ roks_status roks_set_positions(roks_ctx ctx, const double* pos) {
     roks::upload_positions(c);
     ROKS_HIP(hipStreamSynchronize(c.stream));
     roks::reset_cg(c);
+    roks::reset_diis(c);
   });
 }
 
@@ -293,6 +296,37 @@ roks_status roks_subspace(roks_ctx ctx, double* R, double* kappa, double* A) {
 
 roks_status roks_pcg_step(roks_ctx ctx, roks_step_info* info) {
   return guard(ctx, [&](roks::Ctx& c) { roks::pcg_step(c, info); });
+}
+
+roks_status roks_diis_step(roks_ctx ctx, const roks_diis_params* params, roks_diis_info* info) {
+  return guard(ctx, [&](roks::Ctx& c) {
+    ROKS_CHECK(params, ROKS_ERR_ARG, "params is NULL");
+    roks::diis_step(c, *params, info);
+  });
+}
+
+roks_status roks_diis_solve(roks_ctx ctx, const roks_diis_params* params, double tol, int32_t maxiter,
+                            roks_diis_info* last, int32_t* iterations) {
+  return guard(ctx, [&](roks::Ctx& c) {
+    ROKS_CHECK(params, ROKS_ERR_ARG, "params is NULL");
+    ROKS_CHECK(tol > 0 && maxiter > 0, ROKS_ERR_ARG, "tol and maxiter must be > 0");
+    roks_diis_info info{}, prev{};
+    int it = 0, hits = 0;
+    while (it < maxiter) {
+      roks::diis_step(c, *params, &info);
+      if (it > 0 && std::fabs(info.E - prev.E) < tol) ++hits;
+      else hits = 0;
+      prev = info;
+      ++it;
+      if (hits >= 2) break;
+    }
+    if (last) *last = info;
+    if (iterations) *iterations = it;
+  });
+}
+
+roks_status roks_diis_reset(roks_ctx ctx) {
+  return guard(ctx, [&](roks::Ctx& c) { roks::reset_diis(c); });
 }
 
 roks_status roks_reset_cg(roks_ctx ctx) {

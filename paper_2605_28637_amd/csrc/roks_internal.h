@@ -71,6 +71,8 @@ struct DevBuf {
 
 struct Mlp;
 
+constexpr int kDiisMaxHistory = ROKS_DIIS_MAX_HISTORY;
+
 struct Ctx {
   // ---- problem description (host) ----
   double cell[3][3];
@@ -254,6 +256,15 @@ struct Ctx {
   // periodic CG restart (0: never) and the steps since the last one
   int restart_period = 0;
   int since_restart = 0;
+  // DIIS (diis.hip): kept iterates [slot][psi, e][nb][npw] for up to
+  // kDiisMaxHistory slots, per-band dots [1 + history][nb], B over slots,
+  // the kept slots oldest first
+  double2* d_diis = nullptr;
+  double* d_diis_dots = nullptr;
+  std::vector<double> diis_B;
+  std::vector<int> diis_order;
+  int diis_hist = 0;
+  bool diis_asym = false;
 
   // ---- learned preconditioner ----
   Mlp* mlp = nullptr;               // attached network (not owned)
@@ -512,6 +523,22 @@ void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bo
 // ROKS_FLAG_CANONICALIZE, whose Jacobi angles rotate that block)
 void energy_gradient(Ctx& c, roks_energies* e, double* open_out = nullptr, bool want_vv = false);
 void pcg_step(Ctx& c, roks_step_info* info);
+// stream-ordered helpers of the host-side solvers
+inline void to_host(Ctx& c, void* dst, const void* src, size_t bytes) {
+  ROKS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c.stream));
+  ROKS_HIP(hipStreamSynchronize(c.stream));
+}
+inline void sync(Ctx& c) { ROKS_HIP(hipStreamSynchronize(c.stream)); }
+inline void copy_dev(Ctx& c, void* dst, const void* src, size_t bytes) {
+  ROKS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c.stream));
+}
+inline double* dbl(double2* p) { return reinterpret_cast<double*>(p); }
+inline const double* dbl(const double2* p) { return reinterpret_cast<const double*>(p); }
+
+// DIIS on the residual of Eq. residual_frank (diis.hip); reset_diis drops
+// the kept iterates
+void diis_step(Ctx& c, const roks_diis_params& p, roks_diis_info* info);
+void reset_diis(Ctx& c);
 void orthonormalize(Ctx& c, double2* vecs);
 // the allocation-free operator application (noalloc.hip): its scratch is a
 // file-scope device array of this size on every device

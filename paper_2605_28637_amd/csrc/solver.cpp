@@ -18,20 +18,6 @@ namespace {
 constexpr double kDtMin = 0.1, kDtMax = 2.0, kDtInit = 0.5;
 constexpr int kHalvings = 4;
 
-void to_host(Ctx& c, void* dst, const void* src, size_t bytes) {
-  ROKS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c.stream));
-  ROKS_HIP(hipStreamSynchronize(c.stream));
-}
-
-void sync(Ctx& c) { ROKS_HIP(hipStreamSynchronize(c.stream)); }
-
-void copy_dev(Ctx& c, void* dst, const void* src, size_t bytes) {
-  ROKS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c.stream));
-}
-
-double* dbl(double2* p) { return reinterpret_cast<double*>(p); }
-const double* dbl(const double2* p) { return reinterpret_cast<const double*>(p); }
-
 
 // U = exp(X) for X = delta * D (antisymmetric): scaling and squaring around a
 // Taylor polynomial in Horner form, the degree m and squarings s chosen as in
@@ -373,6 +359,7 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   const size_t band = (size_t)nb * c.npw, nn = (size_t)nb * nb;
   // periodic restart: every restart_period steps the carried directions and
   // the step length estimate are dropped (a fresh preconditioned gradient)
+  reset_diis(c);  // the kept DIIS iterates do not lead to these orbitals
   const bool periodic = c.restart_period > 0 && c.since_restart >= c.restart_period;
   if (periodic) reset_cg(c);
   c.since_restart++;

@@ -74,6 +74,22 @@ class StepInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+DIIS_MAX_HISTORY = 8
+
+
+class DiisParams(C.Structure):
+    _fields_ = [("history", C.c_int32), ("step", C.c_double), ("asymmetric", C.c_int32)]
+
+
+class DiisInfo(C.Structure):
+    _fields_ = [("E", C.c_double), ("rnorm2", C.c_double), ("open_coupling", C.c_double),
+                ("used", C.c_int32), ("coeffs", C.c_double * DIIS_MAX_HISTORY)]
+
+    def as_dict(self) -> Dict:
+        return {"E": self.E, "rnorm2": self.rnorm2, "open_coupling": self.open_coupling,
+                "used": self.used, "coeffs": list(self.coeffs[: self.used])}
+
+
 _LIB = None
 
 # name -> (restype, argtypes)
@@ -101,6 +117,10 @@ _SIGS = {
                                 C.POINTER(C.c_double)]),
     "roks_pcg_step": (C.c_int, [_P, C.POINTER(StepInfo)]),
     "roks_reset_cg": (C.c_int, [_P]),
+    "roks_diis_step": (C.c_int, [_P, C.POINTER(DiisParams), C.POINTER(DiisInfo)]),
+    "roks_diis_solve": (C.c_int, [_P, C.POINTER(DiisParams), C.c_double, C.c_int32,
+                                  C.POINTER(DiisInfo), C.POINTER(C.c_int32)]),
+    "roks_diis_reset": (C.c_int, [_P]),
     "roks_set_restart": (C.c_int, [_P, C.c_int32]),
     "roks_set_precision": (C.c_int, [_P, C.c_int32]),
     "roks_solve": (C.c_int, [_P, C.c_double, C.c_int32, C.POINTER(StepInfo), C.POINTER(C.c_int32)]),
@@ -337,6 +357,24 @@ class Roks:
         it = C.c_int32()
         self._check(self._L.roks_solve(self._h, tol, maxiter, C.byref(info), C.byref(it)))
         return info.as_dict(), it.value
+
+    def diis_step(self, history: int = 6, step: float = 0.3, asymmetric: bool = False) -> Dict:
+        p = DiisParams(history, step, 1 if asymmetric else 0)
+        info = DiisInfo()
+        self._check(self._L.roks_diis_step(self._h, C.byref(p), C.byref(info)))
+        return info.as_dict()
+
+    def diis_solve(self, tol: float = 1e-6, maxiter: int = 500, history: int = 6, step: float = 0.3,
+                   asymmetric: bool = False):
+        p = DiisParams(history, step, 1 if asymmetric else 0)
+        info = DiisInfo()
+        it = C.c_int32()
+        self._check(self._L.roks_diis_solve(self._h, C.byref(p), tol, maxiter, C.byref(info),
+                                            C.byref(it)))
+        return info.as_dict(), it.value
+
+    def diis_reset(self):
+        self._check(self._L.roks_diis_reset(self._h))
 
     def forces(self) -> np.ndarray:
         f = np.empty((max(1, self.natoms), 3))
