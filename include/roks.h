@@ -347,6 +347,62 @@ roks_status roks_diis_reset(roks_ctx ctx);
  * vanishes for S = 1) at the current orbitals, [natoms][3] Ha/bohr. */
 roks_status roks_forces(roks_ctx ctx, double* f);
 
+/* Geometry relaxation and the Franck-Condon cycle (Sec. IV B).  The total
+ * energy of a geometry is the electronic E at its minimum (roks_solve from
+ * the current orbitals with the CG restarted every scf_restart iterations:
+ * without restarts an excited state's solve from ground-state orbitals can
+ * stall far above its minimum; the context's own restart period is restored
+ * afterwards) plus an ion-ion pair repulsion
+ *   sum_{I<J} sum_t pair_B exp(-|R_I - R_J - t| / pair_rho)
+ * over the 27 nearest cell translations t (the synthetic Gaussian-well
+ * atoms carry no ionic charge, and the paper's total energies include the
+ * ions' repulsion; pair_B = 0 drops it); the forces are Eq. force_hf's plus
+ * that term's.  Positions move by BFGS on the Cartesian coordinates (fixed
+ * cell): inverse Hessian h0 I to start, step s = H F scaled so that no atom
+ * moves more than max_step, the BFGS update of H when s.(F_old - F_new) > 0
+ * (else h0 I again); a step that raises the energy is halved, at most four
+ * times, from the accepted geometry's orbitals, with H reset.  Stops when
+ * max_I |F_I| < fmax or after maxsteps steps.  Units: Ha, bohr. */
+typedef struct {
+  double fmax;          /* force threshold, Ha/bohr                       */
+  int32_t maxsteps;     /* BFGS steps                                     */
+  double scf_tol;       /* roks_solve tolerance at every geometry, Ha     */
+  int32_t scf_maxiter;  /* roks_solve iteration limit                     */
+  int32_t scf_restart;  /* CG restart period of those solves (0: none)    */
+  double max_step;      /* largest atomic displacement of a step, bohr    */
+  double h0;            /* initial inverse Hessian, bohr^2 / Ha           */
+  double pair_B;        /* pair repulsion amplitude, Ha (>= 0)            */
+  double pair_rho;      /* pair repulsion range, bohr (> 0)               */
+} roks_relax_params;
+typedef struct {
+  double E;             /* total energy at the last geometry              */
+  double fmax;          /* its largest atomic force                       */
+  int32_t steps;        /* BFGS steps taken                               */
+  int32_t scf_iterations; /* CG iterations over all geometries            */
+  int32_t converged;    /* fmax reached                                   */
+} roks_relax_info;
+/* Relax the context's positions (and orbitals); needs orbitals. */
+roks_status roks_relax(roks_ctx ctx, const roks_relax_params* params, roks_relax_info* info);
+/* The current positions [natoms][3]. */
+roks_status roks_get_positions(roks_ctx ctx, double* pos);
+typedef struct {
+  double E_gs_at_gs, E_ex_at_gs, E_ex_at_ex, E_gs_at_ex; /* total energies  */
+  double E_abs;   /* E^ex(R_gs) - E^gs(R_gs), vertical absorption          */
+  double E_FC_ex; /* E^ex(R_gs) - E^ex(R_ex)                               */
+  double E_FC_gs; /* E^gs(R_ex) - E^gs(R_gs)                               */
+  double E_emi;   /* E_abs - E_FC_ex - E_FC_gs                             */
+  double dQ;      /* [sum_I M_I |R^ex_I - R^gs_I|^2]^1/2, amu^1/2 bohr      */
+  int32_t gs_steps, ex_steps, converged;
+} roks_fc_result;
+/* The cycle of Sec. IV B on two contexts of one system, `gs` with the
+ * ground-state occupations (its orbitals the start) and `ex` with the
+ * excited ones: relax gs (R_gs); solve ex at R_gs from the relaxed
+ * ground-state orbitals; relax ex from there (R_ex); solve gs at R_ex from
+ * its relaxed orbitals.  masses [natoms] in amu.  Both contexts end at R_ex
+ * with their last orbitals. */
+roks_status roks_franck_condon(roks_ctx gs, roks_ctx ex, const roks_relax_params* params,
+                               const double* masses, roks_fc_result* out);
+
 /* Wait for all work enqueued on the context's stream. */
 roks_status roks_synchronize(roks_ctx ctx);
 

@@ -212,6 +212,20 @@ def tiny_cell(seed: int = 1000, ecut: float = 7.5, xc: str = "pw92", n_closed: i
                    n_closed)
 
 
+def dimer(seed: int = 1100, d: float = 1.8, configuration: str = "roks", xc: str = "pw92") -> Dict:
+    """Two unlike Gaussian-well atoms (depths 2.5 / 1.6 Ha, widths 0.8 /
+    0.7 bohr, one s projector each) d bohr apart, slightly off axis, in the
+    8 bohr box of the tiny cell (16^3 grid, 7.5 Ha): 2 closed + 2 open + 1
+    virtual bands.  The geometry-relaxation workload: with the pair
+    repulsion 1.0 exp(-r / 0.4) Ha its ground-state bond is about 1.4 bohr."""
+    L = 8.0
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos = np.array([[4.0 - d / 2, 4.0, 4.0], [4.0 + d / 2, 4.1, 3.9]]) + rng.normal(0, 0.02, (2, 3))
+    sp = [_species(2.5, 0.8, [(0, 0.8)], [1.0]), _species(1.6, 0.7, [(0, 0.7)], [0.8])]
+    occ, cL = _occupations(configuration, 2, 1)
+    return _system("dimer", np.eye(3) * L, 7.5, (16, 16, 16), sp, [0, 1], pos, occ, cL, xc, seed, 2)
+
+
 def _occupations(configuration: str, n_closed: int, n_virtual: int):
     if configuration == "roks":
         return roks_occupations(n_closed, n_virtual)

@@ -90,6 +90,42 @@ class DiisInfo(C.Structure):
                 "used": self.used, "coeffs": list(self.coeffs[: self.used])}
 
 
+class RelaxParams(C.Structure):
+    _fields_ = [("fmax", C.c_double), ("maxsteps", C.c_int32), ("scf_tol", C.c_double),
+                ("scf_maxiter", C.c_int32), ("scf_restart", C.c_int32), ("max_step", C.c_double),
+                ("h0", C.c_double), ("pair_B", C.c_double), ("pair_rho", C.c_double)]
+
+
+RELAX_DEFAULTS = {"fmax": 1e-4, "maxsteps": 60, "scf_tol": 1e-11, "scf_maxiter": 800,
+                  "scf_restart": 20, "max_step": 0.2, "h0": 1.0, "pair_B": 1.0, "pair_rho": 0.4}
+
+
+def relax_params(**kw) -> RelaxParams:
+    v = dict(RELAX_DEFAULTS)
+    for k in kw:
+        if k not in v:
+            raise KeyError(k)
+    v.update(kw)
+    return RelaxParams(**v)
+
+
+class RelaxInfo(C.Structure):
+    _fields_ = [("E", C.c_double), ("fmax", C.c_double), ("steps", C.c_int32),
+                ("scf_iterations", C.c_int32), ("converged", C.c_int32)]
+
+    def as_dict(self) -> Dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class FcResult(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("E_gs_at_gs", "E_ex_at_gs", "E_ex_at_ex", "E_gs_at_ex",
+                                          "E_abs", "E_FC_ex", "E_FC_gs", "E_emi", "dQ")] + \
+               [("gs_steps", C.c_int32), ("ex_steps", C.c_int32), ("converged", C.c_int32)]
+
+    def as_dict(self) -> Dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _LIB = None
 
 # name -> (restype, argtypes)
@@ -121,6 +157,10 @@ _SIGS = {
     "roks_diis_solve": (C.c_int, [_P, C.POINTER(DiisParams), C.c_double, C.c_int32,
                                   C.POINTER(DiisInfo), C.POINTER(C.c_int32)]),
     "roks_diis_reset": (C.c_int, [_P]),
+    "roks_relax": (C.c_int, [_P, C.POINTER(RelaxParams), C.POINTER(RelaxInfo)]),
+    "roks_get_positions": (C.c_int, [_P, C.POINTER(C.c_double)]),
+    "roks_franck_condon": (C.c_int, [_P, _P, C.POINTER(RelaxParams), C.POINTER(C.c_double),
+                                     C.POINTER(FcResult)]),
     "roks_set_restart": (C.c_int, [_P, C.c_int32]),
     "roks_set_precision": (C.c_int, [_P, C.c_int32]),
     "roks_solve": (C.c_int, [_P, C.c_double, C.c_int32, C.POINTER(StepInfo), C.POINTER(C.c_int32)]),
@@ -376,6 +416,17 @@ class Roks:
     def diis_reset(self):
         self._check(self._L.roks_diis_reset(self._h))
 
+    def relax(self, **params) -> Dict:
+        p = relax_params(**params)
+        info = RelaxInfo()
+        self._check(self._L.roks_relax(self._h, C.byref(p), C.byref(info)))
+        return info.as_dict()
+
+    def get_positions(self) -> np.ndarray:
+        pos = np.empty((max(1, self.natoms), 3))
+        self._check(self._L.roks_get_positions(self._h, _dptr(pos)))
+        return pos[: self.natoms]
+
     def forces(self) -> np.ndarray:
         f = np.empty((max(1, self.natoms), 3))
         self._check(self._L.roks_forces(self._h, _dptr(f)))
@@ -409,6 +460,15 @@ class Roks:
 
     def apply_h_noalloc_d(self, c_in_ptr: Optional[int], mask: int, out_ptr: int):
         self._check(self._L.roks_apply_h_noalloc_d(self._h, _P(c_in_ptr or 0), mask, _P(out_ptr)))
+
+
+def franck_condon(gs: "Roks", ex: "Roks", masses, **params) -> Dict:
+    """The Franck-Condon cycle of Sec. IV B on two contexts (roks_franck_condon)."""
+    p = relax_params(**params)
+    out = FcResult()
+    m = np.ascontiguousarray(masses, dtype=np.float64)
+    gs._check(gs._L.roks_franck_condon(gs._h, ex._h, C.byref(p), _dptr(m), C.byref(out)))
+    return out.as_dict()
 
 
 class Mlp:
