@@ -47,6 +47,11 @@ Where the paper is silent or garbled the oracle takes these readings:
 * R9  Orthonormalisation by Cholesky of the Gram matrix (Gram-Schmidt in band
       order), applied after the out-of-subspace step, before the rotation.
 * R12 LDA = Slater exchange + PW92 correlation (oracle.xc).
+* R13 PBE (xc "pbe", oracle.xc): gradients and the divergence of the
+      gradient terms are spectral on the full FFT grid, i G_a with the
+      Nyquist components zeroed on even grids; v_xc^sigma = d e/d rho_sigma
+      - div(2 de/d sigma_ss grad rho_s + de/d sigma_ud grad rho_s'), the exact
+      derivative of the grid sum of e.
 * R15 Nyquist components of V_ext are zeroed on even grids.
 * R21 No ion-ion term; V_H(G = 0) = 0; V_ext(G = 0) kept.
 
@@ -292,6 +297,30 @@ def band_nonlocal(model: Model, psi: np.ndarray) -> np.ndarray:
     return np.einsum("in,ij,jn->n", P, model.D, P)
 
 
+def spectral_gradient(model: Model, f: np.ndarray) -> np.ndarray:
+    """[3][grid] d_a f = IFFT(i G_a FFT f), Nyquist components zeroed (R13)."""
+    fg = np.fft.fftn(f)
+    out = np.empty((3,) + model.grid)
+    for a in range(3):
+        ga = np.where(model.nyquist, 0.0, model.grid_G[..., a])
+        out[a] = np.fft.ifftn(1j * ga * fg).real
+    return out
+
+
+def gga_xc(model: Model, ru: np.ndarray, rd: np.ndarray):
+    """PBE energy density and spin potentials on the grid (R13)."""
+    gu, gd = spectral_gradient(model, ru), spectral_gradient(model, rd)
+    suu = (gu * gu).sum(axis=0)
+    sud = (gu * gd).sum(axis=0)
+    sdd = (gd * gd).sum(axis=0)
+    e, fu, fd, fuu, fud, fdd = xcmod.pbe_point_derivatives(ru, rd, suu, sud, sdd)
+    hu = 2.0 * fuu * gu + fud * gd
+    hd = 2.0 * fdd * gd + fud * gu
+    div_u = sum(spectral_gradient(model, hu[a])[a] for a in range(3))
+    div_d = sum(spectral_gradient(model, hd[a])[a] for a in range(3))
+    return e, fu - div_u, fd - div_d
+
+
 def potentials(model: Model, psi: np.ndarray) -> Potentials:
     """Densities rho^{sigma L} = Omega^-1 sum_n f_n^{sigma L} |u_n|^2, the
     configuration potentials and the energies E_L and E = sum_L c_L E_L."""
@@ -308,7 +337,10 @@ def potentials(model: Model, psi: np.ndarray) -> Potentials:
     for L in range(model.nconf):
         rl = rho[L, 0] + rho[L, 1]
         vh[L], eh = hartree(model, rl)
-        e, vu, vd = xcmod.lda(rho[L, 0], rho[L, 1], model.xc)
+        if model.xc == "pbe":
+            e, vu, vd = gga_xc(model, rho[L, 0], rho[L, 1])
+        else:
+            e, vu, vd = xcmod.lda(rho[L, 0], rho[L, 1], model.xc)
         vloc[L, 0] = model.vext_r + vh[L] + vu
         vloc[L, 1] = model.vext_r + vh[L] + vd
         f = model.occ[L].sum(axis=0)
