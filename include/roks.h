@@ -87,7 +87,12 @@ typedef enum { ROKS_FP64 = 0, ROKS_FP32 = 1, ROKS_FP32_BF16X3 = 2 } roks_precisi
 
 enum {
   ROKS_XC_PW92 = 0, /* spin LDA: Slater exchange + Perdew-Wang 1992 correlation */
-  ROKS_XC_X = 1     /* spin LDA exchange only                                   */
+  ROKS_XC_X = 1,    /* spin LDA exchange only                                   */
+  ROKS_XC_PBE = 2   /* spin GGA: Perdew-Burke-Ernzerhof 1996 exchange and
+                       correlation (the functional of the paper's Sec. III);
+                       density gradients and the divergence of the gradient
+                       terms spectral on the FFT grid, Nyquist components
+                       zeroed on even grids                                    */
 };
 
 enum {

@@ -621,6 +621,322 @@ ShellArgs shell_args(const Ctx& c) {
   return a;
 }
 
+// ---------------------------------------------------------------------------
+// PBE (spin-polarised GGA; Perdew, Burke and Ernzerhof 1996): the energy
+// density e(rho_up, rho_dn, sigma_uu, sigma_ud, sigma_dd) in one template over
+// the scalar type, evaluated on forward-mode dual numbers carrying the five
+// partial derivatives for the potentials (plain doubles for energies only).
+// Exchange by spin scaling, e_x = sum_s n_s eps_x^unif(n_s) F_x(s_s) / 2 with
+// n_s = 2 rho_s, F_x = 1 + kappa - kappa / (1 + mu s^2 / kappa),
+// s^2 = |grad n_s|^2 / (4 k_F^2 n_s^2); correlation rho (eps_c^PW92 + H),
+// H = gamma phi^3 ln(1 + beta/gamma t^2 (1 + A t^2) / (1 + A t^2 + A^2 t^4)),
+// A = beta/gamma / (exp(-eps_c / (gamma phi^3)) - 1), t^2 = |grad rho|^2 /
+// (4 phi^2 k_s^2 rho^2), k_s^2 = 4 k_F / pi.
+// ---------------------------------------------------------------------------
+struct D5 {
+  double v;
+  double d[5];
+};
+__device__ __forceinline__ D5 d5c(double v) {
+  D5 r;
+  r.v = v;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) r.d[k] = 0.0;
+  return r;
+}
+__device__ __forceinline__ D5 d5var(double v, int k) {
+  D5 r = d5c(v);
+  r.d[k] = 1.0;
+  return r;
+}
+// x -> (f(x), f'(x)) applied to a dual
+__device__ __forceinline__ D5 d5chain(const D5& x, double f, double fp) {
+  D5 r;
+  r.v = f;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) r.d[k] = fp * x.d[k];
+  return r;
+}
+__device__ __forceinline__ D5 operator+(const D5& a, const D5& b) {
+  D5 r;
+  r.v = a.v + b.v;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) r.d[k] = a.d[k] + b.d[k];
+  return r;
+}
+__device__ __forceinline__ D5 operator-(const D5& a, const D5& b) {
+  D5 r;
+  r.v = a.v - b.v;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) r.d[k] = a.d[k] - b.d[k];
+  return r;
+}
+__device__ __forceinline__ D5 operator*(const D5& a, const D5& b) {
+  D5 r;
+  r.v = a.v * b.v;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  return r;
+}
+__device__ __forceinline__ D5 operator/(const D5& a, const D5& b) {
+  const double ib = 1.0 / b.v;
+  D5 r;
+  r.v = a.v * ib;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * ib;
+  return r;
+}
+__device__ __forceinline__ D5 operator*(double a, const D5& b) {
+  D5 r;
+  r.v = a * b.v;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) r.d[k] = a * b.d[k];
+  return r;
+}
+__device__ __forceinline__ D5 operator+(const D5& a, double b) { return a + d5c(b); }
+__device__ __forceinline__ D5 operator+(double a, const D5& b) { return d5c(a) + b; }
+__device__ __forceinline__ D5 operator-(const D5& a, double b) { return a - d5c(b); }
+__device__ __forceinline__ D5 operator-(double a, const D5& b) { return d5c(a) - b; }
+__device__ __forceinline__ D5 operator*(const D5& a, double b) { return b * a; }
+__device__ __forceinline__ D5 operator/(const D5& a, double b) { return (1.0 / b) * a; }
+__device__ __forceinline__ D5 operator/(double a, const D5& b) { return d5c(a) / b; }
+__device__ __forceinline__ D5 operator-(const D5& a) { return -1.0 * a; }
+__device__ __forceinline__ D5 gpow(const D5& x, double p) {
+  const double v = pow(x.v, p);
+  return d5chain(x, v, p * v / x.v);
+}
+__device__ __forceinline__ D5 gsqrt(const D5& x) {
+  const double v = sqrt(x.v);
+  return d5chain(x, v, 0.5 / v);
+}
+__device__ __forceinline__ D5 glog(const D5& x) { return d5chain(x, log(x.v), 1.0 / x.v); }
+__device__ __forceinline__ D5 gexp(const D5& x) {
+  const double v = exp(x.v);
+  return d5chain(x, v, v);
+}
+__device__ __forceinline__ double gpow(double x, double p) { return pow(x, p); }
+__device__ __forceinline__ double gsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ double glog(double x) { return log(x); }
+__device__ __forceinline__ double gexp(double x) { return exp(x); }
+
+constexpr double kPbeKappa = 0.804, kPbeBeta = 0.06672455060314922;
+constexpr double kPi = 3.141592653589793;
+
+template <typename T>
+__device__ T pw92_g_t(const T& rs, const T& srs, double A, double a1, double b1, double b2, double b3,
+                      double b4) {
+  const T Q = 2.0 * A * (b1 * srs + b2 * rs + b3 * (rs * srs) + b4 * (rs * rs));
+  return -2.0 * A * (1.0 + a1 * rs) * glog(1.0 + 1.0 / Q);
+}
+
+template <typename T>
+__device__ T pbe_ex_spin(const T& r, const T& sig) {
+  const double mu = kPbeBeta * kPi * kPi / 3.0;
+  const T n = 2.0 * r;
+  const T kf = gpow(3.0 * kPi * kPi * n, 1.0 / 3.0);
+  const T s2 = sig / (kf * kf * (n * n));  // 4 sigma / (4 k_F^2 n^2)
+  const T Fx = (1.0 + kPbeKappa) - kPbeKappa / (1.0 + (mu / kPbeKappa) * s2);
+  const T exu = -0.75 * gpow(3.0 / kPi, 1.0 / 3.0) * gpow(n, 1.0 / 3.0);
+  return 0.5 * n * exu * Fx;
+}
+
+template <typename T>
+__device__ T pbe_energy(const T& ru, const T& rd, const T& suu, const T& sud, const T& sdd) {
+  const double gam = (1.0 - 0.6931471805599453) / (kPi * kPi);
+  const T rho = ru + rd;
+  const T z = (ru - rd) / rho;
+  const T rs = gpow(3.0 / (4.0 * kPi) / rho, 1.0 / 3.0);
+  const T srs = gsqrt(rs);
+  const T ec0 = pw92_g_t(rs, srs, 0.031091, 0.21370, 7.5957, 3.5876, 1.6382, 0.49294);
+  const T ec1 = pw92_g_t(rs, srs, 0.015545, 0.20548, 14.1189, 6.1977, 3.3662, 0.62517);
+  const T ac = -pw92_g_t(rs, srs, 0.016887, 0.11125, 10.357, 3.6231, 0.88026, 0.49671);
+  const double fz20 = 1.709921, fzden = 0.5198420997897464;
+  const T opz = 1.0 + z, omz = 1.0 - z;
+  const T f = (gpow(opz, 4.0 / 3.0) + gpow(omz, 4.0 / 3.0) - 2.0) / fzden;
+  const T z2 = z * z;
+  const T z4 = z2 * z2;
+  const T eps = ec0 + ac * f / fz20 * (1.0 - z4) + (ec1 - ec0) * f * z4;
+  const T phi = 0.5 * (gpow(opz, 2.0 / 3.0) + gpow(omz, 2.0 / 3.0));
+  const T kf = gpow(3.0 * kPi * kPi * rho, 1.0 / 3.0);
+  const T ks2 = (4.0 / kPi) * kf;
+  const T g2 = suu + 2.0 * sud + sdd;
+  const T t2 = g2 / (4.0 * (phi * phi) * ks2 * (rho * rho));
+  const T phi3 = phi * phi * phi;
+  const T A = (kPbeBeta / gam) / (gexp(-eps / (gam * phi3)) - 1.0);
+  const T At2 = A * t2;
+  const T H = gam * phi3 * glog(1.0 + (kPbeBeta / gam) * t2 * (1.0 + At2) / (1.0 + At2 + At2 * At2));
+  return pbe_ex_spin(ru, suu) + pbe_ex_spin(rd, sdd) + rho * (eps + H);
+}
+
+// configuration L's spin densities (clamped at 0) packed as rho_up + i rho_dn
+__global__ void k_gga_pack(ShellArgs a, const double* __restrict__ rho, int L, size_t ntot,
+                           double2* __restrict__ out) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double ru = 0, rd = 0;
+    for (int X = 0; X < a.nsocc; ++X) {
+      const double v = rho[(size_t)X * ntot + i];
+      ru += a.f[X][L][0] * v;
+      rd += a.f[X][L][1] * v;
+    }
+    out[i] = make_double2(fmax(ru, 0.0), fmax(rd, 0.0));
+  }
+}
+
+// out_a = i G_a S scale for a = 0, 1, 2 (zero on Nyquist planes): the spectra
+// of the three Cartesian derivatives of the two real fields packed in S
+__global__ void k_gga_grad(Lattice Lt, const double2* __restrict__ S, size_t ntot, double scale,
+                           double2* __restrict__ o0, double2* __restrict__ o1,
+                           double2* __restrict__ o2) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
+       i += (size_t)gridDim.x * blockDim.x) {
+    int m[3];
+    const bool nyq = grid_freq(Lt, i, m);
+    double G[3];
+    gvec(Lt, m, G);
+    const double2 v = S[i];
+    double g = nyq ? 0.0 : G[0] * scale;
+    o0[i] = make_double2(-g * v.y, g * v.x);
+    g = nyq ? 0.0 : G[1] * scale;
+    o1[i] = make_double2(-g * v.y, g * v.x);
+    g = nyq ? 0.0 : G[2] * scale;
+    o2[i] = make_double2(-g * v.y, g * v.x);
+  }
+}
+
+// out = sum_a i G_a H_a scale (zero on Nyquist planes): the spectrum of the
+// divergence of the two real vector fields packed in H_0..2
+__global__ void k_gga_div(Lattice Lt, const double2* __restrict__ H0, const double2* __restrict__ H1,
+                          const double2* __restrict__ H2, size_t ntot, double scale,
+                          double2* __restrict__ out) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
+       i += (size_t)gridDim.x * blockDim.x) {
+    int m[3];
+    const bool nyq = grid_freq(Lt, i, m);
+    double G[3];
+    gvec(Lt, m, G);
+    double re = 0.0, im = 0.0;
+    if (!nyq) {
+      const double2 h0 = H0[i], h1 = H1[i], h2 = H2[i];
+      re = -(G[0] * h0.y + G[1] * h1.y + G[2] * h2.y);
+      im = G[0] * h0.x + G[1] * h1.x + G[2] * h2.x;
+    }
+    out[i] = make_double2(re * scale, im * scale);
+  }
+}
+
+// per point of configuration L: the PBE energy density into e; with WRITE the
+// density derivatives into vu / vd and the gradient terms
+// h_s = 2 de/dsigma_ss grad rho_s + de/dsigma_ud grad rho_s' over the
+// gradients g_a (packed up + i down, overwritten by h_up + i h_dn)
+template <bool WRITE>
+__global__ void __launch_bounds__(256) k_gga_point(ShellArgs a, const double* __restrict__ rho, int L,
+                                                   size_t ntot, double2* __restrict__ g0,
+                                                   double2* __restrict__ g1, double2* __restrict__ g2,
+                                                   double* __restrict__ e, double* __restrict__ vu,
+                                                   double* __restrict__ vd) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double ru = 0, rd = 0;
+    for (int X = 0; X < a.nsocc; ++X) {
+      const double v = rho[(size_t)X * ntot + i];
+      ru += a.f[X][L][0] * v;
+      rd += a.f[X][L][1] * v;
+    }
+    ru = fmax(ru, 0.0);
+    rd = fmax(rd, 0.0);
+    const double2 x0 = g0[i], x1 = g1[i], x2 = g2[i];
+    const double suu = x0.x * x0.x + x1.x * x1.x + x2.x * x2.x;
+    const double sud = x0.x * x0.y + x1.x * x1.y + x2.x * x2.y;
+    const double sdd = x0.y * x0.y + x1.y * x1.y + x2.y * x2.y;
+    const bool live = ru + rd >= 1e-12;
+    ru = fmax(ru, 1e-30);
+    rd = fmax(rd, 1e-30);
+    if (!WRITE) {
+      e[i] = live ? pbe_energy<double>(ru, rd, suu, sud, sdd) : 0.0;
+      continue;
+    }
+    double ev = 0.0, fu = 0.0, fd = 0.0, fuu = 0.0, fud = 0.0, fdd = 0.0;
+    if (live) {
+      const D5 r =
+          pbe_energy<D5>(d5var(ru, 0), d5var(rd, 1), d5var(suu, 2), d5var(sud, 3), d5var(sdd, 4));
+      ev = r.v;
+      fu = r.d[0];
+      fd = r.d[1];
+      fuu = r.d[2];
+      fud = r.d[3];
+      fdd = r.d[4];
+    }
+    e[i] = ev;
+    vu[i] = fu;
+    vd[i] = fd;
+    g0[i] = make_double2(2.0 * fuu * x0.x + fud * x0.y, 2.0 * fdd * x0.y + fud * x0.x);
+    g1[i] = make_double2(2.0 * fuu * x1.x + fud * x1.y, 2.0 * fdd * x1.y + fud * x1.x);
+    g2[i] = make_double2(2.0 * fuu * x2.x + fud * x2.y, 2.0 * fdd * x2.y + fud * x2.x);
+  }
+}
+
+// vu -= Re div, vd -= Im div
+__global__ void k_gga_sub(const double2* __restrict__ div, size_t ntot, double* __restrict__ vu,
+                          double* __restrict__ vd) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const double2 d = div[i];
+    vu[i] -= d.x;
+    vd[i] -= d.y;
+  }
+}
+
+// the GGA counterpart of k_xc's assembly: v_xc^{sigma L} already in vloc
+// (WRITE) becomes V_loc = V_ext + V_H^L + v_xc, then the shell potentials;
+// partial sums of e_xc (from e), V_ext rho and V_H rho per configuration
+template <bool WRITE>
+__global__ void __launch_bounds__(256) k_gga_assemble(ShellArgs a, const double* __restrict__ rho,
+                                                      const double* __restrict__ vext,
+                                                      const double2* __restrict__ vh,
+                                                      const double* __restrict__ e, size_t ntot,
+                                                      double* __restrict__ vloc, double* __restrict__ vsh,
+                                                      double* __restrict__ part) {
+  __shared__ double red[8 * 16];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double rX[3] = {0, 0, 0};
+    for (int X = 0; X < a.nsocc; ++X) rX[X] = rho[(size_t)X * ntot + i];
+    const double ve = vext[i];
+    const double2 vhp = WRITE ? vh[i] : make_double2(0.0, 0.0);
+    double vl[kMaxConf][2];
+    for (int L = 0; L < a.nconf; ++L) {
+      double ru = 0, rd = 0;
+      for (int X = 0; X < a.nsocc; ++X) {
+        ru += a.f[X][L][0] * rX[X];
+        rd += a.f[X][L][1] * rX[X];
+      }
+      ru = fmax(ru, 0.0);
+      rd = fmax(rd, 0.0);
+      acc[3 * L + 0] += e[(size_t)L * ntot + i];
+      acc[3 * L + 1] += ve * (ru + rd);
+      if (!WRITE) continue;
+      const double h = L == 0 ? vhp.x : vhp.y;
+      vl[L][0] = ve + h + vloc[(size_t)(2 * L) * ntot + i];
+      vl[L][1] = ve + h + vloc[(size_t)(2 * L + 1) * ntot + i];
+      vloc[(size_t)(2 * L) * ntot + i] = vl[L][0];
+      vloc[(size_t)(2 * L + 1) * ntot + i] = vl[L][1];
+      acc[3 * L + 2] += h * (ru + rd);
+    }
+    if (!WRITE) continue;
+    for (int X = 0; X < a.nsocc; ++X) {
+      double s = 0;
+      for (int L = 0; L < a.nconf; ++L)
+        s += a.cL[L] * (a.f[X][L][0] * vl[L][0] + a.f[X][L][1] * vl[L][1]);
+      vsh[(size_t)X * ntot + i] = s;
+    }
+  }
+  block_sum<6>(acc, red);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < 6; ++j) part[(size_t)blockIdx.x * 6 + j] = acc[j];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -797,6 +1113,57 @@ void launch_nl_force(Ctx& c, const double* phi, double* part, const double* loc,
   }
   hipLaunchKernelGGL(k_nl_force_sum, dim3(cdiv(3 * c.natoms, 256)), dim3(256), 0, c.stream, part,
                      c.natoms, c.d_atom_proj_off, c.d_atom_proj_cnt, loc, out);
+  ROKS_HIP(hipGetLastError());
+}
+
+// PBE potentials (write) or energies: per configuration the spin densities'
+// spectral gradients, the pointwise functional, and (write) the divergence
+// of its gradient terms; then the assembly of V_loc, the shell potentials and
+// the energy sums (the layout of the LDA pass)
+void launch_gga(Ctx& c, double* part, int nblocks, bool write) {
+  const size_t n = c.ntot;
+  if (!c.d_gga) {
+    c.d_gga = dalloc<double2>(c, 4 * n);
+    c.d_gga_e = dalloc<double>(c, (size_t)c.nconf * n);
+  }
+  KernelTimer kt(c, "xc", (double)(2 * c.nsocc + 1 + 3 * c.nconf) * n * sizeof(double) +
+                              (double)c.nconf * (write ? 16.0 : 8.0) * n * sizeof(double2));
+  const ShellArgs a = shell_args(c);
+  const Lattice Lt = lattice(c);
+  const unsigned gb = (unsigned)grid_blocks(n);
+  double2* S = c.d_gga;
+  double2* g[3] = {c.d_gga + n, c.d_gga + 2 * n, c.d_gga + 3 * n};
+  const double scale = 1.0 / (double)n;
+  for (int L = 0; L < c.nconf; ++L) {
+    double* vu = c.d_vloc + (size_t)(2 * L) * n;
+    double* vd = c.d_vloc + (size_t)(2 * L + 1) * n;
+    hipLaunchKernelGGL(k_gga_pack, dim3(gb), dim3(256), 0, c.stream, a, c.d_rho, L, n, S);
+    ROKS_HIP(hipGetLastError());
+    launch_fft3d(c, S, -1);
+    hipLaunchKernelGGL(k_gga_grad, dim3(gb), dim3(256), 0, c.stream, Lt, S, n, scale, g[0], g[1], g[2]);
+    ROKS_HIP(hipGetLastError());
+    for (int k = 0; k < 3; ++k) launch_fft3d(c, g[k], +1);
+    if (write)
+      hipLaunchKernelGGL(k_gga_point<true>, dim3(gb), dim3(256), 0, c.stream, a, c.d_rho, L, n, g[0], g[1],
+                         g[2], c.d_gga_e + (size_t)L * n, vu, vd);
+    else
+      hipLaunchKernelGGL(k_gga_point<false>, dim3(gb), dim3(256), 0, c.stream, a, c.d_rho, L, n, g[0],
+                         g[1], g[2], c.d_gga_e + (size_t)L * n, vu, vd);
+    ROKS_HIP(hipGetLastError());
+    if (!write) continue;
+    for (int k = 0; k < 3; ++k) launch_fft3d(c, g[k], -1);
+    hipLaunchKernelGGL(k_gga_div, dim3(gb), dim3(256), 0, c.stream, Lt, g[0], g[1], g[2], n, scale, S);
+    ROKS_HIP(hipGetLastError());
+    launch_fft3d(c, S, +1);
+    hipLaunchKernelGGL(k_gga_sub, dim3(gb), dim3(256), 0, c.stream, S, n, vu, vd);
+    ROKS_HIP(hipGetLastError());
+  }
+  if (write)
+    hipLaunchKernelGGL(k_gga_assemble<true>, dim3(nblocks), dim3(256), 0, c.stream, a, c.d_rho, c.d_vext,
+                       c.d_fft, c.d_gga_e, n, c.d_vloc, c.d_vsh, part);
+  else
+    hipLaunchKernelGGL(k_gga_assemble<false>, dim3(nblocks), dim3(256), 0, c.stream, a, c.d_rho, c.d_vext,
+                       c.d_fft, c.d_gga_e, n, c.d_vloc, c.d_vsh, part);
   ROKS_HIP(hipGetLastError());
 }
 

@@ -182,6 +182,8 @@ struct Ctx {
   double* d_rho = nullptr;       // [nsocc][ntot]
   double* d_vloc = nullptr;      // [nconf][2][ntot]
   double* d_vsh = nullptr;       // [nsocc][ntot]
+  double2* d_gga = nullptr;      // PBE: [4][ntot] packed spin fields (spectra, gradients)
+  double* d_gga_e = nullptr;     // PBE: [nconf][ntot] energy densities
   double2* d_fft = nullptr;      // [ntot]
   double* d_P = nullptr;         // [nproj][nb]
   double* d_DP = nullptr;        // [nproj][nb]
@@ -388,6 +390,9 @@ void launch_projectors(Ctx& c, double2* B, int deriv_axis);
 void launch_density_reduce(Ctx& c, const double* rho_part, int nchunk, double* rho);
 // V_H per configuration from the packed densities in d_fft
 void launch_hartree(Ctx& c);
+// PBE (ROKS_XC_PBE): write = true forms V_loc, the shell potentials and the
+// energy partial sums (after launch_hartree), false the energy sums only
+void launch_gga(Ctx& c, double* part, int nblocks, bool write);
 void launch_xc_potentials(Ctx& c, double* part, int nblocks);
 int xc_blocks(const Ctx& c);
 void launch_band_kinetic(Ctx& c, const double2* vecs, int nvec, double* out);

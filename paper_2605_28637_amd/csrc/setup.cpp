@@ -134,7 +134,8 @@ void build_problem(Ctx& c, const roks_system* s) {
     ROKS_CHECK(std::isfinite(s->cL[L]), ROKS_ERR_ARG, "non-finite c_L");
     c.cL[L] = s->cL[L];
   }
-  ROKS_CHECK(s->xc == ROKS_XC_PW92 || s->xc == ROKS_XC_X, ROKS_ERR_ARG, "unknown xc");
+  ROKS_CHECK(s->xc == ROKS_XC_PW92 || s->xc == ROKS_XC_X || s->xc == ROKS_XC_PBE, ROKS_ERR_ARG,
+             "unknown xc");
   c.xc = s->xc;
   ROKS_CHECK(s->precision == ROKS_FP64 || s->precision == ROKS_FP32 || s->precision == ROKS_FP32_BF16X3,
              ROKS_ERR_ARG, "precision tier not available");

@@ -182,11 +182,17 @@ void compute_potentials_async(Ctx& c, const double2* orb, bool have_P, bool ener
     // energies only: the Hartree integrals from the forward transform, the
     // xc and external sums without writing any potential
     launch_hartree_energy(c, c.d_part + 6 * (size_t)nblk, nblk);
-    launch_xc_energy(c, c.d_part, nblk);
+    if (c.xc == ROKS_XC_PBE)
+      launch_gga(c, c.d_part, nblk, false);
+    else
+      launch_xc_energy(c, c.d_part, nblk);
     launch_reduce_columns(c, c.d_part, nblk, 6, c.d_red, c.hd_scal, c.d_part + 6 * (size_t)nblk, 2);
   } else {
     launch_hartree(c);
-    launch_xc_potentials(c, c.d_part, nblk);
+    if (c.xc == ROKS_XC_PBE)
+      launch_gga(c, c.d_part, nblk, true);
+    else
+      launch_xc_potentials(c, c.d_part, nblk);
     launch_reduce_columns(c, c.d_part, nblk, 6, c.d_red, c.hd_scal);
   }
   if (c.prec == ROKS_FP32 && !energy_only) {

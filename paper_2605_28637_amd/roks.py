@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libroks.so")
 
 FP64, FP32, FP32_BF16X3 = 0, 1, 2
-XC = {"pw92": 0, "x": 1}
+XC = {"pw92": 0, "x": 1, "pbe": 2}
 FLAG_SUPPRESS_OPEN_COUPLING = 1
 FLAG_CANONICALIZE = 2
 FLAG_WEIGHT_PRECOND = 4

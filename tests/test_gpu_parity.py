@@ -26,6 +26,11 @@ CASES = {
     "exchange_only": lambda: dict(inputs.tiny_cell(), xc="x"),
     # an odd grid (45^3 = 3^2 5): no Nyquist plane, the LDS-plane kernels
     "odd_grid": lambda: inputs.molecule_box(seed=2007, natoms=4, nb=9, N=45, L=14.0),
+    # PBE (ROKS_XC_PBE): spectral gradients with the Nyquist planes of an even
+    # grid, and on an odd grid without them
+    "pbe": lambda: dict(inputs.tiny_cell(), xc="pbe"),
+    "pbe_molecule": lambda: dict(small_molecule(), xc="pbe"),
+    "pbe_odd_grid": lambda: dict(inputs.molecule_box(seed=2007, natoms=4, nb=9, N=45, L=14.0), xc="pbe"),
 }
 
 
