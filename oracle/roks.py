@@ -47,7 +47,7 @@ Where the paper is silent or garbled the oracle takes these readings:
 * R9  Orthonormalisation by Cholesky of the Gram matrix (Gram-Schmidt in band
       order), applied after the out-of-subspace step, before the rotation.
 * R12 LDA = Slater exchange + PW92 correlation (oracle.xc).
-* R13 PBE (xc "pbe", oracle.xc): gradients and the divergence of the
+* R25 PBE (xc "pbe", oracle.xc): gradients and the divergence of the
       gradient terms are spectral on the full FFT grid, i G_a with the
       Nyquist components zeroed on even grids; v_xc^sigma = d e/d rho_sigma
       - div(2 de/d sigma_ss grad rho_s + de/d sigma_ud grad rho_s'), the exact
@@ -298,7 +298,7 @@ def band_nonlocal(model: Model, psi: np.ndarray) -> np.ndarray:
 
 
 def spectral_gradient(model: Model, f: np.ndarray) -> np.ndarray:
-    """[3][grid] d_a f = IFFT(i G_a FFT f), Nyquist components zeroed (R13)."""
+    """[3][grid] d_a f = IFFT(i G_a FFT f), Nyquist components zeroed (R25)."""
     fg = np.fft.fftn(f)
     out = np.empty((3,) + model.grid)
     for a in range(3):
@@ -308,7 +308,7 @@ def spectral_gradient(model: Model, f: np.ndarray) -> np.ndarray:
 
 
 def gga_xc(model: Model, ru: np.ndarray, rd: np.ndarray):
-    """PBE energy density and spin potentials on the grid (R13)."""
+    """PBE energy density and spin potentials on the grid (R25)."""
     gu, gd = spectral_gradient(model, ru), spectral_gradient(model, rd)
     suu = (gu * gu).sum(axis=0)
     sud = (gu * gd).sum(axis=0)

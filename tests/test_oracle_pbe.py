@@ -1,4 +1,4 @@
-"""Pins of the oracle's PBE exchange-correlation (oracle/xc.py, reading R13
+"""Pins of the oracle's PBE exchange-correlation (oracle/xc.py, reading R25
 of oracle/roks.py) on the CPU:
 
 * with zero gradients PBE is the spin LDA (Slater + PW92) exactly, energy
