@@ -47,6 +47,11 @@ Where the paper is silent or garbled the oracle takes these readings:
 * R9  Orthonormalisation by Cholesky of the Gram matrix (Gram-Schmidt in band
       order), applied after the out-of-subspace step, before the rotation.
 * R12 LDA = Slater exchange + PW92 correlation (oracle.xc).
+* R26 hybrid (xc "pbe" with exx = a > 0; Sec. III's PBE0 / DDH): E_xc =
+      a E_x^HF + (1 - a) E_x^PBE + E_c^PBE per configuration, E_x^HF[L] =
+      -1/2 sum_sigma sum_mn f_m f_n int rho_mn V[rho_mn], rho_mn = psi_m psi_n,
+      the Coulomb kernel without its G = 0 term (as V_H); H^{sigma L} gains
+      a K^{sigma L}, K|v> = -sum_m f_m^{sigma L} psi_m V[psi_m v].
 * R25 PBE (xc "pbe", oracle.xc): gradients and the divergence of the
       gradient terms are spectral on the full FFT grid, i G_a with the
       Nyquist components zeroed on even grids; v_xc^sigma = d e/d rho_sigma
@@ -89,6 +94,10 @@ class Model:
         self.grid = tuple(int(n) for n in system["grid"])
         self.ntot = int(np.prod(self.grid))
         self.xc = system.get("xc", "pw92")
+        # fraction of exact exchange (R26): hybrids are built on PBE
+        self.exx = float(system.get("exx", 0.0))
+        if self.exx != 0.0 and self.xc != "pbe":
+            raise ValueError("exact exchange is mixed with PBE only")
         self._build_sphere()
         self._build_grid_vectors()
         self.set_positions(np.asarray(system["pos"], dtype=np.float64))
@@ -308,17 +317,48 @@ def spectral_gradient(model: Model, f: np.ndarray) -> np.ndarray:
 
 
 def gga_xc(model: Model, ru: np.ndarray, rd: np.ndarray):
-    """PBE energy density and spin potentials on the grid (R25)."""
+    """PBE energy density and spin potentials on the grid (R25), the
+    exchange scaled by 1 - exx (R26)."""
     gu, gd = spectral_gradient(model, ru), spectral_gradient(model, rd)
     suu = (gu * gu).sum(axis=0)
     sud = (gu * gd).sum(axis=0)
     sdd = (gd * gd).sum(axis=0)
-    e, fu, fd, fuu, fud, fdd = xcmod.pbe_point_derivatives(ru, rd, suu, sud, sdd)
+    e, fu, fd, fuu, fud, fdd = xcmod.pbe_point_derivatives(ru, rd, suu, sud, sdd,
+                                                         xscale=1.0 - model.exx)
     hu = 2.0 * fuu * gu + fud * gd
     hd = 2.0 * fdd * gd + fud * gu
     div_u = sum(spectral_gradient(model, hu[a])[a] for a in range(3))
     div_d = sum(spectral_gradient(model, hd[a])[a] for a in range(3))
     return e, fu - div_u, fd - div_d
+
+
+def exx_energy(model: Model, u: np.ndarray, L: int) -> float:
+    """E_x^HF of configuration L (R26) from the real-space orbitals u (psi =
+    u / sqrt(Omega)): -sum_sigma sum_mn f_m f_n E_H[rho_mn], rho_mn =
+    u_m u_n / Omega, every ordered pair."""
+    occ = model.occ[L]
+    E = 0.0
+    for m in range(model.nb):
+        for n in range(model.nb):
+            w = float(occ[0, m] * occ[0, n] + occ[1, m] * occ[1, n])
+            if w != 0.0:
+                E -= w * hartree(model, u[m] * u[n] / model.omega)[1]
+    return E
+
+
+def exx_apply(model: Model, u: np.ndarray, L: int, s: int, vecs: np.ndarray) -> np.ndarray:
+    """K^{sigma L}|v> = -sum_m f_m^{sigma L} psi_m V[psi_m v] for every row v
+    (R26), in the coefficient convention of apply_channel."""
+    out = np.zeros_like(vecs)
+    for j in range(len(vecs)):
+        uv = model.to_real(vecs[j])
+        acc = np.zeros(model.grid)
+        for m in range(model.nb):
+            f = float(model.occ[L, s, m])
+            if f != 0.0:
+                acc -= f * u[m] * hartree(model, u[m] * uv / model.omega)[0]
+        out[j] = model.from_real(acc)
+    return out
 
 
 def potentials(model: Model, psi: np.ndarray) -> Potentials:
@@ -349,6 +389,8 @@ def potentials(model: Model, psi: np.ndarray) -> Potentials:
         t["ext"][L] = model.integrate(model.vext_r * rl)
         t["hartree"][L] = eh
         t["xc"][L] = model.integrate(e)
+        if model.exx != 0.0:
+            t["xc"][L] += model.exx * exx_energy(model, u, L)
         E_L[L] = sum(t[k][L] for k in t)
     E = float(model.cL @ E_L)
     return Potentials(u, rho, vloc, vh, E_L, E, t)
@@ -371,6 +413,8 @@ def apply_channel(model: Model, pot: Potentials, L: int, s: int, vecs: np.ndarra
     for n in range(len(vecs)):
         u = model.to_real(vecs[n])
         out[n] = 0.5 * model.g2 * vecs[n] + nl[n] + model.from_real(pot.vloc[L, s] * u)
+    if model.exx != 0.0:
+        out += model.exx * exx_apply(model, pot.u, L, s, vecs)
     return out
 
 

@@ -134,9 +134,11 @@ def _pw92_eps(rho, z):
     return ec0 + ac * f / FZ20 * (1.0 - z4) + (ec1 - ec0) * f * z4
 
 
-def pbe_energy_density(ru, rd, suu, sud, sdd):
+def pbe_energy_density(ru, rd, suu, sud, sdd, xscale=1.0):
     """e_xc(rho_up, rho_dn, sigma_uu, sigma_ud, sigma_dd), sigma_ab =
-    grad rho_a . grad rho_b; all densities above the floor."""
+    grad rho_a . grad rho_b, with the exchange part scaled by xscale (1 - a
+    for a hybrid with a fraction a of exact exchange); all densities above
+    the floor."""
     def ex_spin(r, s):
         n = 2.0 * r
         kf = (3.0 * np.pi ** 2 * n) ** (1.0 / 3.0)
@@ -158,10 +160,10 @@ def pbe_energy_density(ru, rd, suu, sud, sdd):
     At2 = A * t2
     H = PBE_GAMMA * phi3 * np.log(1.0 + PBE_BETA / PBE_GAMMA * t2 * (1.0 + At2)
                                   / (1.0 + At2 + At2 * At2))
-    return ex_spin(ru, suu) + ex_spin(rd, sdd) + rho * (eps_c + H)
+    return xscale * (ex_spin(ru, suu) + ex_spin(rd, sdd)) + rho * (eps_c + H)
 
 
-def pbe_point_derivatives(ru, rd, suu, sud, sdd):
+def pbe_point_derivatives(ru, rd, suu, sud, sdd, xscale=1.0):
     """e and its partial derivatives (d/d rho_up, d/d rho_dn, d/d sigma_uu,
     d/d sigma_ud, d/d sigma_dd) by the complex step, per point; points whose
     total density is below the floor give zeros."""
@@ -170,11 +172,11 @@ def pbe_point_derivatives(ru, rd, suu, sud, sdd):
     floor = 1e-30
     a = [np.where(live, np.maximum(args[0], floor), 1.0), np.where(live, np.maximum(args[1], floor), 1.0),
          np.where(live, args[2], 0.0), np.where(live, args[3], 0.0), np.where(live, args[4], 0.0)]
-    e = np.real(pbe_energy_density(*a))
+    e = np.real(pbe_energy_density(*a, xscale=xscale))
     d = []
     for k in range(5):
         h = 1e-20 * np.maximum(np.abs(a[k]), 1e-20)
         b = [x.astype(complex) for x in a]
         b[k] = b[k] + 1j * h
-        d.append(np.imag(pbe_energy_density(*b)) / h)
+        d.append(np.imag(pbe_energy_density(*b, xscale=xscale)) / h)
     return (np.where(live, e, 0.0),) + tuple(np.where(live, x, 0.0) for x in d)
