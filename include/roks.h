@@ -153,6 +153,18 @@ typedef struct {
   int32_t xc;             /* ROKS_XC_*                                     */
   int32_t precision;      /* roks_precision                                */
   uint32_t flags;         /* ROKS_FLAG_*                                   */
+  double exx;             /* fraction a of exact (Fock) exchange mixed into
+                             PBE (xc = ROKS_XC_PBE; 0: none; 0.25 is PBE0,
+                             1/eps_inf a dielectric-dependent hybrid, Sec.
+                             III): E_xc = a E_x^HF + (1 - a) E_x^PBE + E_c^PBE
+                             per configuration, E_x^HF[L] = -1/2 sum_sigma
+                             sum_mn f_m f_n int psi_m psi_n V[psi_m psi_n]
+                             with the Coulomb kernel without G = 0, and
+                             H^{sigma L} += a K^{sigma L}, K|v> = -sum_m
+                             f_m^{sigma L} psi_m V[psi_m v].  Costs one
+                             Poisson transform per (band pair, occupied
+                             orbital) in every apply and energy
+                             evaluation.  In [0, 1].                       */
 } roks_system;
 
 /* Energies of the current orbitals (Sec. II A, constrained functional). */

@@ -741,7 +741,7 @@ __device__ T pbe_ex_spin(const T& r, const T& sig) {
 }
 
 template <typename T>
-__device__ T pbe_energy(const T& ru, const T& rd, const T& suu, const T& sud, const T& sdd) {
+__device__ T pbe_energy(const T& ru, const T& rd, const T& suu, const T& sud, const T& sdd, double xs) {
   const double gam = (1.0 - 0.6931471805599453) / (kPi * kPi);
   const T rho = ru + rd;
   const T z = (ru - rd) / rho;
@@ -765,7 +765,7 @@ __device__ T pbe_energy(const T& ru, const T& rd, const T& suu, const T& sud, co
   const T A = (kPbeBeta / gam) / (gexp(-eps / (gam * phi3)) - 1.0);
   const T At2 = A * t2;
   const T H = gam * phi3 * glog(1.0 + (kPbeBeta / gam) * t2 * (1.0 + At2) / (1.0 + At2 + At2 * At2));
-  return pbe_ex_spin(ru, suu) + pbe_ex_spin(rd, sdd) + rho * (eps + H);
+  return xs * (pbe_ex_spin(ru, suu) + pbe_ex_spin(rd, sdd)) + rho * (eps + H);
 }
 
 // configuration L's spin densities (clamped at 0) packed as rho_up + i rho_dn
@@ -825,7 +825,8 @@ __global__ void k_gga_div(Lattice Lt, const double2* __restrict__ H0, const doub
   }
 }
 
-// per point of configuration L: the PBE energy density into e; with WRITE the
+// per point of configuration L: the PBE energy density (exchange scaled by
+// xs: 1 - a for a hybrid) into e; with WRITE the
 // density derivatives into vu / vd and the gradient terms
 // h_s = 2 de/dsigma_ss grad rho_s + de/dsigma_ud grad rho_s' over the
 // gradients g_a (packed up + i down, overwritten by h_up + i h_dn)
@@ -834,7 +835,7 @@ __global__ void __launch_bounds__(256) k_gga_point(ShellArgs a, const double* __
                                                    size_t ntot, double2* __restrict__ g0,
                                                    double2* __restrict__ g1, double2* __restrict__ g2,
                                                    double* __restrict__ e, double* __restrict__ vu,
-                                                   double* __restrict__ vd) {
+                                                   double* __restrict__ vd, double xs) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ntot;
        i += (size_t)gridDim.x * blockDim.x) {
     double ru = 0, rd = 0;
@@ -853,13 +854,13 @@ __global__ void __launch_bounds__(256) k_gga_point(ShellArgs a, const double* __
     ru = fmax(ru, 1e-30);
     rd = fmax(rd, 1e-30);
     if (!WRITE) {
-      e[i] = live ? pbe_energy<double>(ru, rd, suu, sud, sdd) : 0.0;
+      e[i] = live ? pbe_energy<double>(ru, rd, suu, sud, sdd, xs) : 0.0;
       continue;
     }
     double ev = 0.0, fu = 0.0, fd = 0.0, fuu = 0.0, fud = 0.0, fdd = 0.0;
     if (live) {
       const D5 r =
-          pbe_energy<D5>(d5var(ru, 0), d5var(rd, 1), d5var(suu, 2), d5var(sud, 3), d5var(sdd, 4));
+          pbe_energy<D5>(d5var(ru, 0), d5var(rd, 1), d5var(suu, 2), d5var(sud, 3), d5var(sdd, 4), xs);
       ev = r.v;
       fu = r.d[0];
       fd = r.d[1];
@@ -1145,10 +1146,10 @@ void launch_gga(Ctx& c, double* part, int nblocks, bool write) {
     for (int k = 0; k < 3; ++k) launch_fft3d(c, g[k], +1);
     if (write)
       hipLaunchKernelGGL(k_gga_point<true>, dim3(gb), dim3(256), 0, c.stream, a, c.d_rho, L, n, g[0], g[1],
-                         g[2], c.d_gga_e + (size_t)L * n, vu, vd);
+                         g[2], c.d_gga_e + (size_t)L * n, vu, vd, 1.0 - c.exx);
     else
       hipLaunchKernelGGL(k_gga_point<false>, dim3(gb), dim3(256), 0, c.stream, a, c.d_rho, L, n, g[0],
-                         g[1], g[2], c.d_gga_e + (size_t)L * n, vu, vd);
+                         g[1], g[2], c.d_gga_e + (size_t)L * n, vu, vd, 1.0 - c.exx);
     ROKS_HIP(hipGetLastError());
     if (!write) continue;
     for (int k = 0; k < 3; ++k) launch_fft3d(c, g[k], -1);

@@ -59,6 +59,9 @@ void init_noalloc_scratch(Ctx& c) {
 
 void apply_noalloc(Ctx& c, const double2* vecs, uint32_t mask, double2* out) {
   ROKS_CHECK(c.d_noalloc, ROKS_ERR_STATE, "the static scratch of this device is not set up");
+  ROKS_CHECK(c.exx == 0.0, ROKS_ERR_STATE,
+             "roks_apply_h_noalloc_d does not apply exact exchange (its pair potentials need "
+             "band-sized buffers)");
   ROKS_CHECK(!c.bf3, ROKS_ERR_STATE,
              "roks_apply_h_noalloc_d runs in the FP64 and FP32 tiers (the BF16x3 products need "
              "band-sized split buffers)");

@@ -182,6 +182,17 @@ struct Ctx {
   double* d_rho = nullptr;       // [nsocc][ntot]
   double* d_vloc = nullptr;      // [nconf][2][ntot]
   double* d_vsh = nullptr;       // [nsocc][ntot]
+  // hybrid exact exchange (exx.hip): real-space orbitals [nb][ntot] of the
+  // last potentials' orbitals, 3 complex work grids, pair integrals,
+  // reduction partials, the weights W[X][m] = sum_L c_L sum_s f_X f_m, and
+  // E_x^HF per configuration (host)
+  double exx = 0.0;
+  double* d_exx_u = nullptr;
+  double2* d_exx_g = nullptr;
+  double* d_exx_I = nullptr;
+  double* d_exx_part = nullptr;
+  double* d_exx_W = nullptr;
+  double exx_E[kMaxConf] = {0.0, 0.0};
   double2* d_gga = nullptr;      // PBE: [4][ntot] packed spin fields (spectra, gradients)
   double* d_gga_e = nullptr;     // PBE: [nconf][ntot] energy densities
   double2* d_fft = nullptr;      // [ntot]
@@ -390,6 +401,16 @@ void launch_projectors(Ctx& c, double2* B, int deriv_axis);
 void launch_density_reduce(Ctx& c, const double* rho_part, int nchunk, double* rho);
 // V_H per configuration from the packed densities in d_fft
 void launch_hartree(Ctx& c);
+// hybrid exact exchange (exx.hip).  exx_orbitals: the real-space orbitals
+// of orb (kept for the applies of the same orbitals); exx_energies: E_x^HF
+// per configuration into exx_E (synchronises); exx_apply: out[n] += a
+// sum_m rowW[n][m] psi_m V[psi_m v_n] for the nvec rows of vecs (rowW host
+// [nvec][nb], the minus sign of K included), with Iout the pair integrals
+// I[n][m] kept for exx_shell_expectations, which adds a <n|K^X|n> to d_Q
+void exx_orbitals(Ctx& c, const double2* orb);
+void exx_energies(Ctx& c);
+void exx_apply(Ctx& c, const double2* vecs, int nvec, const double* rowW, double2* out, double* Iout);
+void exx_shell_expectations(Ctx& c);
 // PBE (ROKS_XC_PBE): write = true forms V_loc, the shell potentials and the
 // energy partial sums (after launch_hartree), false the energy sums only
 void launch_gga(Ctx& c, double* part, int nblocks, bool write);

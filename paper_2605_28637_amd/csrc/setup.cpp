@@ -137,6 +137,10 @@ void build_problem(Ctx& c, const roks_system* s) {
   ROKS_CHECK(s->xc == ROKS_XC_PW92 || s->xc == ROKS_XC_X || s->xc == ROKS_XC_PBE, ROKS_ERR_ARG,
              "unknown xc");
   c.xc = s->xc;
+  ROKS_CHECK(std::isfinite(s->exx) && s->exx >= 0.0 && s->exx <= 1.0, ROKS_ERR_ARG,
+             "exact-exchange fraction outside [0, 1]");
+  ROKS_CHECK(s->exx == 0.0 || s->xc == ROKS_XC_PBE, ROKS_ERR_ARG, "exact exchange is mixed with PBE only");
+  c.exx = s->exx;
   ROKS_CHECK(s->precision == ROKS_FP64 || s->precision == ROKS_FP32 || s->precision == ROKS_FP32_BF16X3,
              ROKS_ERR_ARG, "precision tier not available");
   // the FFT tier; the projector products follow the BF16x3 flag

@@ -148,6 +148,26 @@ void evaluate_trial(Ctx& c, double delta, Trial& t, bool energy_only) {
 // ---------------------------------------------------------------------------
 // every launch of the energy evaluation; the reduced sums also land in the
 // pinned mirror h_scal, read by assemble_energies after a synchronisation
+// rowW of exx_apply for the shell operators: row n takes -W[X][m], X the
+// shell of band n (zero for virtual bands) or, with Xfixed >= 0, that shell
+std::vector<double> exx_shell_weights(const Ctx& c, int Xfixed) {
+  const int nb = c.nb;
+  std::vector<double> W((size_t)nb * nb, 0.0);
+  for (int n = 0; n < nb; ++n) {
+    const int X = Xfixed >= 0 ? Xfixed : c.band_shell[n];
+    if (X >= c.nsocc) continue;
+    for (int m = 0; m < nb; ++m) {
+      const int Y = c.band_shell[m];
+      if (Y >= c.nsocc) continue;
+      double w = 0.0;
+      for (int L = 0; L < c.nconf; ++L)
+        for (int sp = 0; sp < 2; ++sp) w += c.cL[L] * c.shell_f[X][L][sp] * c.shell_f[Y][L][sp];
+      W[(size_t)n * nb + m] = -w;
+    }
+  }
+  return W;
+}
+
 void compute_potentials_async(Ctx& c, const double2* orb, bool have_P, bool energy_only) {
   const int nb = c.nb, K = 2 * c.npw;
   {
@@ -163,6 +183,12 @@ void compute_potentials_async(Ctx& c, const double2* orb, bool have_P, bool ener
     launch_plane_density(c, c.d_T, c.npairs, c.d_rho_part, c.nchunk);
   }
   launch_density_reduce(c, c.d_rho_part, c.nchunk, c.d_rho);
+  if (c.exx != 0.0) {
+    // exact exchange: the real-space orbitals (kept for the applies of these
+    // orbitals) and E_x^HF of every configuration
+    exx_orbitals(c, orb);
+    exx_energies(c);
+  }
   // with the projections at hand, the band kinetic and nonlocal energies run
   // on the side stream beside the Hartree and xc chain (they need neither)
   const bool side = have_P;
@@ -229,7 +255,7 @@ roks_energies assemble_energies(const Ctx& c, bool energy_only) {
     }
     out.kinetic[L] = k;
     out.nonlocal[L] = nl;
-    out.xc[L] = dv * h[3 * L + 0];
+    out.xc[L] = dv * h[3 * L + 0] + c.exx * c.exx_E[L];
     out.external[L] = dv * h[3 * L + 1];
     out.hartree[L] = 0.5 * dv * (energy_only ? h[6 + L] : h[3 * L + 2]);
     out.E_L[L] = k + nl + out.external[L] + out.hartree[L] + out.xc[L];
@@ -273,11 +299,13 @@ void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bo
       launch_apply_D(c, P, c.d_kinw_shell, c.d_DP);
       proj_expand(c, nb, c.d_DP, nb, dbl(out), K);
     }
+    if (c.exx != 0.0) exx_apply(c, vecs, nb, exx_shell_weights(c, -1).data(), out, want_Q ? c.d_exx_I : nullptr);
     if (want_Q) {
       // Q[n][X] = N^-3 sum_z Qpart[pair][z][b][X], n = 2 pair + b; d_Q holds
       // 2 npairs rows so an odd band count needs no special case
       launch_reduce_strided(c, c.d_Qpart, c.npairs, c.N[2], 2 * c.nsocc, 1.0 / (double)c.ntot,
                             c.d_Q);
+      if (c.exx != 0.0) exx_shell_expectations(c);  // + a <n|K^X|n>
     }
     return;
   }
@@ -294,6 +322,16 @@ void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bo
     if (c.nproj > 0) {
       launch_apply_D(c, P, nullptr, c.d_DP);
       proj_expand(c, nb, c.d_DP, nb, dbl(o), K);
+    }
+    if (c.exx != 0.0) {
+      // channel b = 2 L + s: K^{sL}, weights -f_m^{sL}
+      std::vector<double> W((size_t)nb * nb, 0.0);
+      for (int n = 0; n < nb; ++n)
+        for (int m = 0; m < nb; ++m) {
+          const int Y = c.band_shell[m];
+          W[(size_t)n * nb + m] = Y < c.nsocc ? -c.shell_f[Y][b / 2][b % 2] : 0.0;
+        }
+      exx_apply(c, vecs, nb, W.data(), o, nullptr);
     }
     ++idx;
   }
@@ -327,6 +365,11 @@ static void virtual_block(Ctx& c) {
   if (c.nproj > 0) {
     launch_apply_D(c, c.d_P, c.d_kinw_closed, c.d_DP);
     proj_expand(c, nv, c.d_DP + v0, nb, dbl(out), K);
+  }
+  if (c.exx != 0.0) {
+    // F^c's exchange on the virtual rows
+    const std::vector<double> W = exx_shell_weights(c, Xc);
+    exx_apply(c, vv, nv, W.data() + (size_t)v0 * nb, out, nullptr);
   }
   gemm_wdot(c, nv, nv, K, dbl(vv), K, dbl(out), K, c.d_R + (size_t)v0 * nb + v0, nb, 1.0, 0.0, true);
   launch_virtual_block(c, v0);

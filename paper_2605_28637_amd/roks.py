@@ -48,7 +48,7 @@ class System(C.Structure):
                 ("pos", C.POINTER(C.c_double)), ("nspecies", C.c_int32),
                 ("spec", C.POINTER(Species)), ("nbands", C.c_int32), ("nconfig", C.c_int32),
                 ("occ", C.POINTER(C.c_uint8)), ("cL", C.POINTER(C.c_double)), ("xc", C.c_int32),
-                ("precision", C.c_int32), ("flags", C.c_uint32)]
+                ("precision", C.c_int32), ("flags", C.c_uint32), ("exx", C.c_double)]
 
 
 class Energies(C.Structure):
@@ -284,6 +284,7 @@ class _SystemBuffers:
         st.occ = self.occ.ctypes.data_as(C.POINTER(C.c_uint8))
         st.cL = _dptr(self.cL)
         st.xc = XC[s.get("xc", "pw92")]
+        st.exx = float(s.get("exx", 0.0))
         st.precision = precision
         st.flags = flags
         self.struct = st

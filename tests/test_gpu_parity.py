@@ -31,6 +31,10 @@ CASES = {
     "pbe": lambda: dict(inputs.tiny_cell(), xc="pbe"),
     "pbe_molecule": lambda: dict(small_molecule(), xc="pbe"),
     "pbe_odd_grid": lambda: dict(inputs.molecule_box(seed=2007, natoms=4, nb=9, N=45, L=14.0), xc="pbe"),
+    # hybrids: a quarter (PBE0) and 0.36 (the dielectric-dependent fraction
+    # the paper takes for MgO) of exact exchange
+    "pbe0": lambda: dict(inputs.tiny_cell(), xc="pbe", exx=0.25),
+    "ddh_molecule": lambda: dict(small_molecule(), xc="pbe", exx=0.36),
 }
 
 
