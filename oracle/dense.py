@@ -9,11 +9,14 @@ computes with FFTs:
   exact matrix of the grid-based local operator.
 * A closed-shell self-consistent-field loop by dense diagonalisation with
   Pulay mixing of the density: a different algorithm from the CG of the
-  paper's Sec. II A that must reach the same ground-state energy.
+  paper's Sec. II A that must reach the same ground-state energy.  With
+  overlap coefficients it solves the generalised problem H c = eps S c with
+  the explicit S_{GG'} = delta_GG' + sum_kl beta_k(G) q_kl beta_l(G')*.
 """
 from __future__ import annotations
 
 import numpy as np
+import scipy.linalg
 
 from . import roks, xc as xcmod
 
@@ -26,6 +29,14 @@ def local_matrix(model: "roks.Model", vloc: np.ndarray) -> np.ndarray:
 
 def nonlocal_matrix(model: "roks.Model") -> np.ndarray:
     return model.beta.T @ model.D @ np.conj(model.beta)
+
+
+def overlap_matrix(model: "roks.Model") -> np.ndarray:
+    """The explicit S on the full sphere (the identity without q)."""
+    S = np.eye(model.npw, dtype=complex)
+    if model.nproj:
+        S += model.beta.T @ model.Q @ np.conj(model.beta)
+    return S
 
 
 def hamiltonian_matrix(model: "roks.Model", vloc: np.ndarray) -> np.ndarray:
@@ -56,15 +67,21 @@ def scf_closed_shell(model: "roks.Model", n_occ: int, tol: float = 1e-12, maxite
         _, vu, _ = xcmod.lda(0.5 * rho, 0.5 * rho, model.xc)
         return model.vext_r + vh + vu
 
+    Smat = overlap_matrix(model)
+
+    def eig(H):
+        # S-orthonormal eigenvectors of H c = eps S c
+        return scipy.linalg.eigh(H, Smat)
+
     H = hamiltonian_matrix(model, model.vext_r)
-    w, V = np.linalg.eigh(H)
+    w, V = eig(H)
     C = V[:, :n_occ].T
     rho = density_of(C)
     rhos, resid = [], []
     E_old = None
     for it in range(maxiter):
         H = hamiltonian_matrix(model, potential_of(rho))
-        w, V = np.linalg.eigh(H)
+        w, V = eig(H)
         C = V[:, :n_occ].T
         rho_out = density_of(C)
         E = energy_of(C, rho_out)

@@ -13,7 +13,8 @@ below are this build's reading, in this order (D1-D5):
 
 D1  residual r_n = F^n|n> - sum_m |m> Lambda_mn with
     Lambda_mn = theta_mn - lambda_mn (theta_mn - theta_nm) (real Gamma-point
-    orbitals: theta*_nm = theta_nm; S = 1).  The printed equation carries the
+    orbitals: theta*_nm = theta_nm; with the overlap S of reading R27 the
+    sum runs over S|m>, as in Eq. gradient).  The printed equation carries the
     antisymmetric term with a plus sign and a second sum over m; the reading
     takes the sign that makes it Eq. gradient's zero: with every
     lambda_mn = 1/2, r_n is the full gradient g_I + g_II.  With the
@@ -30,8 +31,8 @@ D3  B_ij = sum_n <e^i_n|e^j_n> over the kept iterates (at most `history`,
     sum_i c_i = 1 (the bordered linear system of DIIS).  If that system is
     singular, the oldest iterates are dropped until it is not.
 D4  psi' = sum_i c_i (psi^i + step e^i).
-D5  psi'' = psi' orthonormalised by the Cholesky factor of its Gram matrix,
-    band order kept (the CG's reading R9).
+D5  psi'' = psi' orthonormalised by the Cholesky factor of its Gram matrix
+    (of <m|S|n> under R27), band order kept (the CG's reading R9).
 """
 from __future__ import annotations
 
@@ -65,10 +66,10 @@ def couplings(model: orc.Model, asymmetric: bool) -> np.ndarray:
 
 
 def residual(model: orc.Model, gr: orc.Gradient, asymmetric: bool = False) -> np.ndarray:
-    """D1: r_n = F^n|n> - sum_m |m> Lambda_mn."""
+    """D1: r_n = F^n|n> - sum_m S|m> Lambda_mn."""
     th = gr.theta
     Lam = th - couplings(model, asymmetric) * (th - th.T)
-    return gr.Y - Lam.T @ gr.psi
+    return gr.Y - Lam.T @ orc.apply_S(model, gr.psi)
 
 
 def error_vectors(model: orc.Model, r: np.ndarray) -> np.ndarray:
@@ -135,7 +136,7 @@ def diis_step(model: orc.Model, state: DiisState, history: int = 6, step: float 
     if c is None:
         c = np.ones(1)
     new = sum(c[i] * (state.kept[i][0] + step * state.kept[i][1]) for i in range(len(c)))
-    state.psi = orc.orthonormalize(new)
+    state.psi = orc.orthonormalize(new, model)
     ob = open_bands(model)
     oc = float(gr.theta[ob[0], ob[1]] - gr.theta[ob[1], ob[0]]) if len(ob) == 2 else 0.0
     return DiisInfo(gr.pot.E, float(sum(orc.dot(r[n], r[n]) for n in range(model.nb))),
@@ -146,7 +147,7 @@ def diis_solve(model: orc.Model, psi0: np.ndarray, tol: float = 1e-10, maxiter: 
                history: int = 6, step: float = 0.3, asymmetric: bool = False):
     """DIIS steps until the energy changes by less than tol on two consecutive
     steps (the CG's rule); returns the state and the step records."""
-    st = DiisState(orc.orthonormalize(psi0))
+    st = DiisState(orc.orthonormalize(psi0, model))
     hist: List[DiisInfo] = []
     hits = 0
     for _ in range(maxiter):

@@ -95,8 +95,10 @@ class RelaxResult:
 
 def _electrons(model: orc.Model, psi: np.ndarray, p: RelaxParams):
     """G2 and G0: the orbitals, the total energy and the CG iterations."""
-    st, h = orc.solve(model, psi, tol=p.scf_tol, maxiter=p.scf_maxiter, orthonormalize_start=False,
-                      restart_period=p.scf_restart)
+    # with overlap coefficients (R27) S moves with the atoms: the start
+    # orbitals are S-orthonormalised for this geometry first
+    st, h = orc.solve(model, psi, tol=p.scf_tol, maxiter=p.scf_maxiter,
+                      orthonormalize_start=model.has_q, restart_period=p.scf_restart)
     Ep, _ = pair_repulsion(model.pos, model.cell, p.pair_B, p.pair_rho)
     return st.psi, h[-1].E1 + Ep, len(h)
 

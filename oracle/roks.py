@@ -22,8 +22,9 @@ equations are cited by their LaTeX labels):
 * Eqs. (r_matrix_singlet), (prec_grad_IIa-c) and the conjugated rotation
   U = exp(Delta (A^i + gamma A^{i-1})): the in-subspace rotation.
 * Eqs. (orbital_update), (cg_search): Fletcher-Reeves CG with a line search.
-* Eq. (force_hf): Hellmann-Feynman ROKS forces (the overlap term vanishes
-  for S = 1).
+* Eq. (force_hf) / (force_hf2) and SI section S2: Hellmann-Feynman ROKS
+  forces; the overlap term -sum_{mn in occ} gamma_mn <m|dS/dR|n> is taken in
+  the basis that diagonalises gamma (it vanishes for S = 1).
 
 Where the paper is silent or garbled the oracle takes these readings:
 
@@ -57,6 +58,16 @@ Where the paper is silent or garbled the oracle takes these readings:
       Nyquist components zeroed on even grids; v_xc^sigma = d e/d rho_sigma
       - div(2 de/d sigma_ss grad rho_s + de/d sigma_ud grad rho_s'), the exact
       derivative of the grid sum of e.
+* R27 general overlap (a species' optional "q", Sec. II A's PAW overlap
+      S = 1 + sum_kl q_kl |beta_l><beta_k| per atom, q symmetric, coupling
+      like D only channels of one l and m): S enters the constraint
+      <m|S|n> = delta_mn and with it the gradient (g_I = (1 - sum_m S|m><m|)
+      F^n|n>, Eq. gradient), the projection of the preconditioned gradient
+      (Eq. prec_grad_I, <m|S K|g>), the projection of carried directions,
+      the Cholesky orthonormalisation (of the S-Gram matrix) and the overlap
+      term of the forces.  The synthetic atoms carry no augmentation
+      charges Q_kl(r): the density stays sum_n f_n |psi_n|^2, so the
+      energy depends on q only through the constraint.
 * R15 Nyquist components of V_ext are zeroed on even grids.
 * R21 No ion-ion term; V_H(G = 0) = 0; V_ext(G = 0) kept.
 
@@ -180,7 +191,7 @@ class Model:
 
     def _build_projectors(self):
         """beta_i(G) = Omega^-1/2 f_i(G) e^{-iG.R_I}; D block diagonal per atom."""
-        betas, atom_of, blocks = [], [], []
+        betas, atom_of, blocks, qblocks = [], [], [], []
         for I, R in enumerate(self.pos):
             sp = self.species[self.spec_of[I]]
             phase = np.exp(-1j * (self.G @ R)) / np.sqrt(self.omega)
@@ -191,6 +202,8 @@ class Model:
                     atom_of.append(I)
                     chan.append((p, len(chan)))
             D = np.asarray(sp["D"], dtype=float)
+            q = sp.get("q")
+            q = np.zeros_like(D) if q is None else np.asarray(q, dtype=float)
             ls = [sp["proj"][p][0] for p, _ in chan]
             ms = []
             cnt = {}
@@ -199,14 +212,20 @@ class Model:
                 ms.append(cnt[p])
             nb_ = len(chan)
             Db = np.zeros((nb_, nb_))
+            Qb = np.zeros((nb_, nb_))
             for i in range(nb_):
                 for j in range(nb_):
                     if ls[i] == ls[j] and ms[i] == ms[j]:
                         Db[i, j] = D[chan[i][0], chan[j][0]]
+                        Qb[i, j] = q[chan[i][0], chan[j][0]]
             blocks.append(Db)
+            qblocks.append(Qb)
         self.beta = np.array(betas) if betas else np.zeros((0, self.npw), complex)
         self.proj_atom = np.array(atom_of, dtype=int)
         self.D = scipy.linalg.block_diag(*blocks) if blocks else np.zeros((0, 0))
+        # R27: the overlap coefficients, block diagonal per atom like D
+        self.Q = scipy.linalg.block_diag(*qblocks) if qblocks else np.zeros((0, 0))
+        self.has_q = bool(np.any(self.Q != 0.0))
         self.nproj = len(self.beta)
 
     # -- occupations and shells (Sec. II A, text after Eq. r_matrix_singlet)
@@ -304,6 +323,18 @@ def projections(model: Model, psi: np.ndarray) -> np.ndarray:
 def band_nonlocal(model: Model, psi: np.ndarray) -> np.ndarray:
     P = projections(model, psi)
     return np.einsum("in,ij,jn->n", P, model.D, P)
+
+
+def apply_S(model: Model, vecs: np.ndarray) -> np.ndarray:
+    """S|v> = |v> + sum_kl |beta_k> q_kl <beta_l|v> (Sec. II A, reading R27)."""
+    if not model.has_q:
+        return vecs.copy()
+    return vecs + (model.Q @ projections(model, vecs)).T @ model.beta
+
+
+def overlap_S(model: Model, A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """M_mn = <A_m|S|B_n>."""
+    return overlap(A, apply_S(model, B))
 
 
 def spectral_gradient(model: Model, f: np.ndarray) -> np.ndarray:
@@ -478,10 +509,11 @@ def gradient(model: Model, psi: np.ndarray, flags: Flags = Flags()) -> Gradient:
     theta = overlap(psi, Y)
     # Eq. gamma_def: gamma_nm = 1/2 sum_{L sigma} (f_n + f_m) c_L <m|H|n>
     gamma = 0.5 * (theta + theta.T)
-    # Eq. gradient: g_I = f (1 - sum_m |m><m|) H|n>, summed with c_L -> (1 - P) F^n|n>
-    gI = Y - theta.T @ psi
-    # g_II,n = 1/2 sum_m (theta_mn - theta_nm) |m>
-    gII = 0.5 * ((theta - theta.T).T @ psi)
+    Spsi = apply_S(model, psi)
+    # Eq. gradient: g_I = f (1 - sum_m S|m><m|) H|n>, summed with c_L
+    gI = Y - theta.T @ Spsi
+    # g_II,n = 1/2 sum_m (theta_mn - theta_nm) S|m>
+    gII = 0.5 * ((theta - theta.T).T @ Spsi)
     FXdiag = np.array([[dot(psi[n], FX[X, n]) for n in range(nb)] for X in range(ns)])
     closed = [X for X in range(ns) if model.shell_closed[X]]
     opens = [X for X in range(ns) if not model.shell_closed[X] and not model.shell_virtual[X]]
@@ -550,7 +582,7 @@ def teter_reference_energy(model: Model, g: np.ndarray) -> float:
 
 def precondition(model: Model, psi: np.ndarray, gI: np.ndarray, flags: Flags = Flags(),
                  scale: Optional[np.ndarray] = None) -> np.ndarray:
-    """p_I = K g_I - sum_m |m><m|K g_I> with the Teter K per band.
+    """p_I = K g_I - sum_m |m><m|S K g_I> with the Teter K per band.
 
     ``scale`` [nb][npw] optionally rescales K per coefficient (learned
     rescaling); None is the plain Teter preconditioner."""
@@ -566,7 +598,7 @@ def precondition(model: Model, psi: np.ndarray, gI: np.ndarray, flags: Flags = F
         if scale is not None:
             K = K * scale[n]
         Kg[n] = K * gI[n]
-    return Kg - overlap(psi, Kg).T @ psi
+    return Kg - overlap_S(model, psi, Kg).T @ psi
 
 
 # ---------------------------------------------------------------------------
@@ -574,19 +606,28 @@ def precondition(model: Model, psi: np.ndarray, gI: np.ndarray, flags: Flags = F
 # ---------------------------------------------------------------------------
 
 
-def orthonormalize(psi: np.ndarray) -> np.ndarray:
-    """Cholesky of the Gram matrix: rows become orthonormal, band order kept."""
-    Lc = np.linalg.cholesky(overlap(psi, psi))
+def gram(psi: np.ndarray, model: Optional[Model] = None) -> np.ndarray:
+    """<m|n>, or <m|S|n> when a model with overlap coefficients is given (R27)."""
+    if model is not None and model.has_q:
+        return overlap_S(model, psi, psi)
+    return overlap(psi, psi)
+
+
+def orthonormalize(psi: np.ndarray, model: Optional[Model] = None) -> np.ndarray:
+    """Cholesky of the Gram matrix (the S-Gram matrix for a model with
+    overlap coefficients): rows become (S-)orthonormal, band order kept."""
+    Lc = np.linalg.cholesky(gram(psi, model))
     return scipy.linalg.solve_triangular(Lc, psi, lower=True)
 
 
-def trial_orbitals(psi: np.ndarray, S: np.ndarray, D: np.ndarray, delta: float):
+def trial_orbitals(psi: np.ndarray, S: np.ndarray, D: np.ndarray, delta: float,
+                   model: Optional[Model] = None):
     """Psi(delta) = U^T L^-1 (Psi + delta S), U = expm(delta D); also M = U^T L^-1.
 
     Eq. (orbital_update) for the out-of-subspace step, Eq. (inspace_rot)
     with U = exp(delta D) for the in-subspace step."""
     Pt = psi + delta * S
-    Lc = np.linalg.cholesky(overlap(Pt, Pt))
+    Lc = np.linalg.cholesky(gram(Pt, model))
     Linv = scipy.linalg.solve_triangular(Lc, np.eye(len(psi)), lower=True)
     U = scipy.linalg.expm(delta * D)
     M = U.T @ Linv
@@ -633,7 +674,7 @@ def _line_search(model: Model, psi, S, D, E0, dE0, dt):
     evals = 0
     for attempt in range(LS_HALVINGS + 1):
         t = dt / (2.0 ** attempt)
-        pt, Mt, Ut = trial_orbitals(psi, S, D, t)
+        pt, Mt, Ut = trial_orbitals(psi, S, D, t, model)
         Et = energy(model, pt)
         evals += 1
         curv = (Et - E0 - dE0 * t) / (t * t)
@@ -641,7 +682,7 @@ def _line_search(model: Model, psi, S, D, E0, dE0, dt):
             ts = min(-dE0 / (2.0 * curv), 4.0 * t)
         else:
             ts = 2.0 * t
-        ps, Ms, Us = trial_orbitals(psi, S, D, ts)
+        ps, Ms, Us = trial_orbitals(psi, S, D, ts, model)
         Es = energy(model, ps)
         evals += 1
         if Es <= Et:
@@ -678,7 +719,7 @@ def pcg_step(model: Model, state: CGState, flags: Flags = Flags(),
         S = p.copy()
         D = gr.A.copy()
         if b != 0.0:
-            So = state.S_old - overlap(psi, state.S_old).T @ psi
+            So = state.S_old - overlap_S(model, psi, state.S_old).T @ psi
             S = S + b * So
             D = D + b * state.D_old
         dE0 = 2.0 * float(np.sum(np.real(np.conj(S) * gr.gI))) + float(np.sum(D * asym))
@@ -730,7 +771,7 @@ def solve(model: Model, psi0: np.ndarray, tol: float = 1e-10, maxiter: int = 500
           flags: Flags = Flags(), orthonormalize_start: bool = True, log=None,
           restart_period: int = 0):
     """Iterate pcg_step until |E_{i+1} - E_i| < tol on two consecutive steps."""
-    psi = orthonormalize(psi0) if orthonormalize_start else psi0.copy()
+    psi = orthonormalize(psi0, model) if orthonormalize_start else psi0.copy()
     state = CGState(psi=psi, dt=DT_INIT, restart_period=restart_period)
     hits = 0
     history: List[StepInfo] = []
@@ -746,13 +787,52 @@ def solve(model: Model, psi0: np.ndarray, tol: float = 1e-10, maxiter: int = 500
 
 
 # ---------------------------------------------------------------------------
-# forces (Eq. force_hf with S = 1)
+# forces (Eq. force_hf; its overlap term by SI section S2)
 # ---------------------------------------------------------------------------
 
 
+def occupied_bands(model: Model) -> np.ndarray:
+    """Bands occupied in some configuration and spin (closed and open shells)."""
+    return np.array([n for n in range(model.nb) if not model.shell_virtual[model.band_shell[n]]],
+                    dtype=int)
+
+
+def overlap_multipliers(model: Model, psi: np.ndarray) -> np.ndarray:
+    """gamma_mn of Eq. (gamma_def) over the occupied bands (real at Gamma)."""
+    pot = potentials(model, psi)
+    Y = apply_shells(model, pot, psi)
+    theta = overlap(psi, Y)
+    occ = occupied_bands(model)
+    return 0.5 * (theta + theta.T)[np.ix_(occ, occ)]
+
+
+def overlap_force_term(model: Model, psi: np.ndarray) -> np.ndarray:
+    """[natoms][3] sum_{m,n in occ} gamma_mn <m|dS/dR_I|n> in the form of
+    Eq. (force_hf2): gamma (real symmetric at Gamma, so gamma-bar = gamma)
+    is diagonalised, gamma = U Lambda U^T, the occupied orbitals rotated to
+    |n'> = sum_m U_mn |m>, and the term is sum_n Lambda_nn <n'|dS/dR|n'>
+    with <n'|dS/dR|n'> = 2 sum_kl q_kl <d beta_k|n'> <beta_l|n'> (beta_k of
+    atom I, d beta_k / dR_I = -i G beta_k)."""
+    out = np.zeros((len(model.pos), 3))
+    if not model.has_q:
+        return out
+    occ = occupied_bands(model)
+    lam, U = np.linalg.eigh(overlap_multipliers(model, psi))
+    rot = U.T @ psi[occ]                        # rows |n'>
+    P = projections(model, rot)                  # <beta_l|n'>
+    for a in range(3):
+        dbeta = -1j * model.G[:, a][None, :] * model.beta
+        dP = np.real(np.conj(dbeta) @ rot.T)     # <d beta_k|n'>
+        contrib = 2.0 * np.einsum("kn,kl,ln,n->k", dP, model.Q, P, lam)
+        for k in range(model.nproj):
+            out[model.proj_atom[k], a] += contrib[k]
+    return out
+
+
 def forces(model: Model, psi: np.ndarray) -> np.ndarray:
-    """F_I = -dE/dR_I = -[int dV_ext/dR_I rho_w + sum_n w_n d<n|V_NL|n>/dR_I],
-    rho_w = sum_L c_L rho_L, w_n = sum_{sigma L} c_L f_n^{sigma L}."""
+    """F_I = -dE/dR_I = -[int dV_ext/dR_I rho_w + sum_n w_n d<n|V_NL|n>/dR_I
+    - sum_{mn in occ} gamma_mn <m|dS/dR_I|n>], rho_w = sum_L c_L rho_L,
+    w_n = sum_{sigma L} c_L f_n^{sigma L} (Eq. force_hf)."""
     pot = potentials(model, psi)
     rho_w = np.einsum("l,lsxyz->xyz", model.cL, pot.rho)
     rg = np.fft.fftn(rho_w) / model.ntot
@@ -773,4 +853,5 @@ def forces(model: Model, psi: np.ndarray) -> np.ndarray:
         contrib = 2.0 * np.einsum("in,ij,jn,n->i", dP, model.D, P, model.band_w)
         for i in range(model.nproj):
             dE[model.proj_atom[i], a] += contrib[i]
+    dE -= overlap_force_term(model, psi)
     return -dE

@@ -12,7 +12,9 @@ Conventions (Hartree atomic units, lengths in bohr, energies in Ha):
 * A species is a dict ``{"A", "sigma", "proj": [(l, rp), ...], "D": [[...]]}``
   describing a Gaussian local well v(r) = -A exp(-r^2 / (2 sigma^2)) and
   separable Gaussian projectors of angular momentum l in {0, 1} and radius rp
-  with the symmetric coupling matrix D over the radial channels.
+  with the symmetric coupling matrix D over the radial channels; an optional
+  symmetric ``"q"`` of the same shape gives the overlap coefficients of
+  S = 1 + sum q |beta><beta| (absent: S = 1).
 * ``occ[L][s][n]`` in {0, 1} is the occupation f_n^{sigma L} of band n in
   configuration L and spin s (0 = up, 1 = down); ``cL[L]`` the configuration
   weights.  For the singlet the configurations are the mixed-spin
@@ -314,6 +316,25 @@ def batch_systems(seed: int = 4000, count: int = 32, xc: str = "pw92") -> List[D
         out.append(_system("batch%02d" % s, np.eye(3) * L, grid_rule_ecut(L, N), (N, N, N),
                            MOLECULE_SPECIES, np.arange(natoms) % 2, pos, occ, cL, xc, seed + s,
                            nb - 4))
+    return out
+
+
+def with_overlap(system: Dict, scale: float = 0.5) -> Dict:
+    """Copy of ``system`` whose species carry overlap coefficients q (the
+    PAW-like S = 1 + sum q |beta><beta|): q = scale * diag(1, 0.6, 0.4, 0.3)
+    over the radial channels, plus scale / 5 between the first two channels
+    when both have l = 0."""
+    out = dict(system)
+    spec = []
+    for sp in system["species"]:
+        n = len(sp["proj"])
+        q = np.diag(scale * np.array([1.0, 0.6, 0.4, 0.3][:n]))
+        if n >= 2 and sp["proj"][0][0] == 0 and sp["proj"][1][0] == 0:
+            q[0, 1] = q[1, 0] = 0.2 * scale
+        t = dict(sp)
+        t["q"] = q
+        spec.append(t)
+    out["species"] = spec
     return out
 
 
