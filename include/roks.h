@@ -121,13 +121,24 @@ typedef struct {
 
 /* Species: local Gaussian well v(r) = -A exp(-r^2/(2 sigma^2)) and nproj
  * radial channels with the symmetric coupling D[nproj][nproj] (Ha) of
- * V_NL = sum_ij |beta_i> D_ij <beta_j|; D_ij must vanish when l_i != l_j. */
+ * V_NL = sum_ij |beta_i> D_ij <beta_j|; D_ij must vanish when l_i != l_j.
+ * q[nproj][nproj] (NULL: zeros) are the overlap coefficients of Sec. II A's
+ * PAW overlap S = 1 + sum_kl q_kl |beta_l><beta_k| over each atom's
+ * projectors: symmetric, zero when l_k != l_l, S positive definite.  S
+ * enters the orthonormality constraint <m|S|n> = delta_mn and with it the
+ * gradient (Eq. gradient: g_I = (1 - sum_m S|m><m|) F^n|n>), the projection
+ * of the preconditioned gradient (Eq. prec_grad_I), the orthonormalisation
+ * and the overlap term of the forces (Eq. force_hf); the density carries no
+ * augmentation charge (sum_n f_n |psi_n|^2), so the energy depends on q only
+ * through the constraint.  With q != 0 the orbitals move with the atoms:
+ * roks_set_positions S-orthonormalises them for the new S. */
 typedef struct {
   double A;
   double sigma;
   int32_t nproj;
   const roks_proj* proj;
   const double* D;
+  const double* q;
 } roks_species;
 
 /* The problem statement (Sec. II A / III): cell, cutoff, atoms, projectors,
@@ -217,7 +228,8 @@ roks_status roks_sizes(roks_ctx ctx, int32_t* npw, int32_t grid[3], int32_t* npr
 roks_status roks_gvectors(roks_ctx ctx, int32_t* miller);
 
 /* Set the orbitals from c [nbands][npw][2]; orthonormalize != 0 applies the
- * Cholesky orthonormalisation in band order (Gram-Schmidt).  Resets the CG
+ * Cholesky orthonormalisation in band order (Gram-Schmidt; of <m|S|n> with
+ * overlap coefficients q, so that the orbitals are S-orthonormal).  Resets the CG
  * state.  The G = 0 coefficient of a real orbital is real: roks_set_coeffs
  * rejects a nonzero Im c_n(0) with ROKS_ERR_ARG; roks_set_coeffs_d (which
  * does not read the data on the host) sets Im c_n(0) to zero.  Linearly
@@ -231,7 +243,9 @@ roks_status roks_set_coeffs_d(roks_ctx ctx, const void* c_dev, int32_t orthonorm
 roks_status roks_get_coeffs_d(roks_ctx ctx, void* c_dev);
 
 /* Move the atoms ([natoms][3] bohr): rebuilds V_ext and the projector tables
- * and resets the CG state; orbitals are kept. */
+ * and resets the CG state; orbitals are kept (with overlap coefficients q
+ * they are S-orthonormalised for the new S, ROKS_ERR_NOT_PD as in
+ * roks_set_coeffs). */
 roks_status roks_set_positions(roks_ctx ctx, const double* pos);
 
 /* Apply the Kohn-Sham operators of the current orbitals' density to the
@@ -272,7 +286,7 @@ roks_status roks_apply_h_noalloc_d(roks_ctx ctx, const void* c_in_dev, uint32_t 
                                    void* h_out_dev);
 
 /* Energies of the current orbitals and, if grad != NULL, the out-of-subspace
- * gradient g_I,n = (1 - sum_m |m><m|) F^n|n> (Eq. gradient), [nbands][npw][2];
+ * gradient g_I,n = (1 - sum_m S|m><m|) F^n|n> (Eq. gradient), [nbands][npw][2];
  * if theta != NULL the matrix theta_mn = <m|F^n|n> (Sec. II A, theta form of
  * the gradient), [nbands][nbands] row-major (row m). */
 roks_status roks_energy_gradient(roks_ctx ctx, roks_energies* e, double* grad,
@@ -360,8 +374,12 @@ roks_status roks_diis_solve(roks_ctx ctx, const roks_diis_params* params, double
                             int32_t maxiter, roks_diis_info* last, int32_t* iterations);
 roks_status roks_diis_reset(roks_ctx ctx);
 
-/* Hellmann-Feynman forces F_I = -dE/dR_I (Eq. force_hf; the overlap term
- * vanishes for S = 1) at the current orbitals, [natoms][3] Ha/bohr. */
+/* Hellmann-Feynman forces F_I = -dE/dR_I (Eq. force_hf) at the current
+ * orbitals, [natoms][3] Ha/bohr.  With overlap coefficients q the overlap
+ * term -sum_{m,n occupied} gamma_mn <m|dS/dR_I|n>, gamma_mn = (theta_mn +
+ * theta_nm) / 2 (Eq. gamma_def), is included; it costs one more application
+ * of the shell operators.  The term is contracted as Tr(gamma S'), equal to
+ * the gamma-diagonalised form of SI section S2. */
 roks_status roks_forces(roks_ctx ctx, double* f);
 
 /* Geometry relaxation and the Franck-Condon cycle (Sec. IV B).  The total

@@ -215,6 +215,11 @@ roks_status roks_set_positions(roks_ctx ctx, const double* pos) {
     ROKS_HIP(hipStreamSynchronize(c.stream));
     roks::reset_cg(c);
     roks::reset_diis(c);
+    if (c.has_q && c.have_orbitals) {
+      // S moves with the atoms: the orbitals become S-orthonormal again
+      c.potentials_valid = false;
+      roks::orthonormalize(c, c.d_psi);
+    }
   });
 }
 

@@ -80,6 +80,7 @@ void init_device(Ctx& c, void* stream) {
   c.d_proj_atom = dalloc<int32_t>(c, np);
   c.d_Dblk = dalloc<double>(c, c.Dblk.size());
   c.d_Dblk_off = dalloc<int32_t>(c, c.natoms);
+  if (c.has_q) c.d_Qblk = dalloc<double>(c, c.Qblk.size());
   c.d_atom_proj_off = dalloc<int32_t>(c, c.natoms);
   c.d_atom_proj_cnt = dalloc<int32_t>(c, c.natoms);
   c.d_band_shell = dalloc<int32_t>(c, nb);
@@ -91,6 +92,7 @@ void init_device(Ctx& c, void* stream) {
   c.d_in = dalloc<double2>(c, band);
   c.d_Y = dalloc<double2>(c, band);
   c.d_gI = dalloc<double2>(c, band);
+  if (c.has_q) c.d_Spsi = dalloc<double2>(c, band);
   c.d_p = dalloc<double2>(c, band);
   c.d_S = dalloc<double2>(c, band);
   c.d_Pt = dalloc<double2>(c, band);
@@ -227,6 +229,7 @@ void upload_static(Ctx& c) {
   up(c.d_proj_atom, c.proj_atom.data(), c.proj_atom.size() * sizeof(int32_t));
   up(c.d_Dblk, c.Dblk.data(), c.Dblk.size() * sizeof(double));
   up(c.d_Dblk_off, c.Dblk_off.data(), c.Dblk_off.size() * sizeof(int32_t));
+  if (c.has_q) up(c.d_Qblk, c.Qblk.data(), c.Qblk.size() * sizeof(double));
   up(c.d_atom_proj_off, c.atom_proj_off.data(), c.atom_proj_off.size() * sizeof(int32_t));
   up(c.d_atom_proj_cnt, c.atom_proj_cnt.data(), c.atom_proj_cnt.size() * sizeof(int32_t));
   up(c.d_band_shell, c.band_shell.data(), c.band_shell.size() * sizeof(int32_t));

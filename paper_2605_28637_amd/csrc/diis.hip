@@ -3,13 +3,13 @@
 // energy and F^n|n> of the CG step, its band products, the Teter
 // preconditioner and the Cholesky orthonormalisation.  Steps (the oracle's
 // readings D1-D5):
-//   r_n = F^n|n> - sum_m |m> Lambda_mn,
+//   r_n = F^n|n> - sum_m S|m> Lambda_mn,
 //         Lambda_mn = theta_mn - lambda_mn (theta_mn - theta_nm),
 //         lambda = 1/2, or 1/2 / -1/2 for the open pair (a, b) / (b, a);
 //   e_n = K_n r_n (Teter, E_ref from r_n, no projection);
 //   c = argmin c^T B c, sum c = 1, B_ij = sum_n <e^i_n|e^j_n> over the kept
 //       iterates (the oldest dropped while the bordered system is singular);
-//   psi = orth(sum_i c_i (psi^i + step e^i)).
+//   psi = orth(sum_i c_i (psi^i + step e^i)) (in the metric of S).
 // The kept orbitals and error vectors live in device arrays of the context
 // (2 x 8 band arrays, allocated on the first step); B is kept on the host,
 // one new row per step, each entry a band-ordered sum of per-band dots.
@@ -135,7 +135,8 @@ void diis_step(Ctx& c, const roks_diis_params& p, roks_diis_info* info) {
                      (pair && c.diis_asym) ? a : -1, (pair && c.diis_asym) ? b : -1, c.d_m1);
   ROKS_HIP(hipGetLastError());
   double2* r = c.d_p;
-  gemm_expand_to(c, nb, K, nb, c.d_m1, nb, false, dbl(c.d_psi), K, dbl(c.d_Y), K, dbl(r), K, -1.0, 1.0);
+  gemm_expand_to(c, nb, K, nb, c.d_m1, nb, false, dbl(overlap_psi(c)), K, dbl(c.d_Y), K, dbl(r), K,
+                 -1.0, 1.0);
   // the slot of the new iterate (the oldest is dropped at full history)
   if ((int)c.diis_order.size() == p.history) c.diis_order.erase(c.diis_order.begin());
   int slot = 0;

@@ -1077,6 +1077,32 @@ void launch_apply_D(Ctx& c, const double* P, const double* w, double* DP) {
   ROKS_HIP(hipGetLastError());
 }
 
+void launch_apply_Q(Ctx& c, const double* P, double* QP) {
+  const size_t n = (size_t)c.nproj * c.nb;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_apply_D, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, P, c.nb,
+                     c.nproj, c.d_proj_atom, c.d_atom_proj_off, c.d_atom_proj_cnt, c.d_Dblk_off,
+                     c.d_Qblk, nullptr, QP);
+  ROKS_HIP(hipGetLastError());
+}
+
+// the multipliers of Eq. gamma_def restricted to the occupied bands
+__global__ void k_overlap_multipliers(const double* __restrict__ theta, int nb,
+                                      const int32_t* __restrict__ band_shell, int nsocc,
+                                      double* __restrict__ G) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nb * nb) return;
+  const int m = t / nb, n = t - m * nb;
+  const bool occ = band_shell[m] < nsocc && band_shell[n] < nsocc;
+  G[t] = occ ? 0.5 * (theta[t] + theta[n * nb + m]) : 0.0;
+}
+
+void launch_overlap_multipliers(Ctx& c, const double* theta, double* G) {
+  hipLaunchKernelGGL(k_overlap_multipliers, dim3(cdiv(c.nb * c.nb, 256)), dim3(256), 0, c.stream,
+                     theta, c.nb, c.d_band_shell, c.nsocc, G);
+  ROKS_HIP(hipGetLastError());
+}
+
 void launch_pack_rho_weighted(Ctx& c) {
   const size_t n = c.ntot;
   hipLaunchKernelGGL(k_pack_rho, dim3(grid_blocks(n)), dim3(256), 0, c.stream, shell_args(c), c.d_rho, n,

@@ -8,8 +8,9 @@
 //   G1 BFGS on the Cartesian positions, H_0 = h0 I, s = H F capped at
 //      max_step per atom, the BFGS update of H when s.y > 0 (y = F_old -
 //      F_new), else H = h0 I;
-//   G2 each geometry's orbitals by the CG solve from the previous ones,
-//      restarted every scf_restart iterations;
+//   G2 each geometry's orbitals by the CG solve from the previous ones
+//      (S-orthonormalised first with overlap coefficients, S moving with
+//      the atoms), restarted every scf_restart iterations;
 //   G3 a step that raises the energy is halved (at most four times, H reset);
 //   G4 stop at max_I |F_I| < fmax or after maxsteps.
 #include <cmath>
@@ -69,6 +70,11 @@ Geometry electrons(roks_ctx ctx, const roks_relax_params& p, bool want_forces) {
   int32_t it = 0;
   // a search that stalls at the arithmetic's resolution ends the solve
   // there; the context's restart period is restored afterwards
+  if (c.has_q) {
+    c.potentials_valid = false;
+    roks::reset_cg(c);
+    roks::orthonormalize(c, c.d_psi);
+  }
   const int keep_period = c.restart_period;
   c.restart_period = p.scf_restart;
   c.since_restart = 0;
@@ -232,7 +238,7 @@ roks_status roks_franck_condon(roks_ctx gs, roks_ctx ex, const roks_relax_params
     std::vector<double> cbuf((size_t)cg.nb * cg.npw * 2);
     check(roks_get_coeffs(gs, cbuf.data()));
     set_positions(ex, Rgs);
-    check(roks_set_coeffs(ex, cbuf.data(), 0));
+    check(roks_set_coeffs(ex, cbuf.data(), ce.has_q ? 1 : 0));
     const Geometry eg = electrons(ex, *params, false);
     // excited-state relaxation from there: R_ex, E^ex(R_ex)
     roks_relax_info ie{};
@@ -240,7 +246,7 @@ roks_status roks_franck_condon(roks_ctx gs, roks_ctx ex, const roks_relax_params
     const std::vector<double> Rex = ce.pos;
     // the ground state at R_ex from its relaxed orbitals: E^gs(R_ex)
     set_positions(gs, Rex);
-    check(roks_set_coeffs(gs, cbuf.data(), 0));
+    check(roks_set_coeffs(gs, cbuf.data(), cg.has_q ? 1 : 0));
     const Geometry ge = electrons(gs, *params, false);
     out->E_gs_at_gs = ig.E;
     out->E_ex_at_gs = eg.E;

@@ -89,6 +89,7 @@ struct Ctx {
     std::vector<int32_t> l;
     std::vector<double> rp;
     std::vector<double> D;  // [nproj][nproj]
+    std::vector<double> q;  // [nproj][nproj] overlap coefficients (zeros: S = 1)
   };
   std::vector<Species> species;
   int nb = 0;
@@ -124,6 +125,10 @@ struct Ctx {
   std::vector<int32_t> atom_proj_off, atom_proj_cnt;  // [natoms]
   std::vector<double> Dblk;       // per atom dense block, concatenated
   std::vector<int32_t> Dblk_off;  // [natoms]
+  // overlap coefficients of S = 1 + sum q |beta><beta|, blocks laid out as
+  // Dblk (same offsets); has_q: some q_kl != 0
+  std::vector<double> Qblk;
+  bool has_q = false;
 
   // ---- device ----
   hipStream_t stream = nullptr;
@@ -162,6 +167,8 @@ struct Ctx {
   int32_t* d_proj_atom = nullptr;
   double* d_Dblk = nullptr;
   int32_t* d_Dblk_off = nullptr;
+  double* d_Qblk = nullptr;      // with has_q
+  double2* d_Spsi = nullptr;     // with has_q: [nb][npw] S|psi_n> of the last gradient
   int32_t* d_atom_proj_off = nullptr;
   int32_t* d_atom_proj_cnt = nullptr;
   int32_t* d_band_shell = nullptr;
@@ -419,6 +426,10 @@ int xc_blocks(const Ctx& c);
 void launch_band_kinetic(Ctx& c, const double2* vecs, int nvec, double* out);
 void launch_nl_energy(Ctx& c, const double* P, double* out, double* mirror = nullptr);
 void launch_apply_D(Ctx& c, const double* P, const double* w, double* DP);
+// QP[i][n] = sum_j q_ij P[j][n] over the atom's projectors (has_q)
+void launch_apply_Q(Ctx& c, const double* P, double* QP);
+// G[m][n] = (theta_mn + theta_nm) / 2 for occupied m and n, else 0
+void launch_overlap_multipliers(Ctx& c, const double* theta, double* G);
 // energy-only evaluation: xc and external sums without potentials, and the
 // Hartree integrals from the forward transform (partials [block][2])
 void launch_xc_energy(Ctx& c, double* part, int nblocks);
@@ -565,6 +576,9 @@ inline const double* dbl(const double2* p) { return reinterpret_cast<const doubl
 // the kept iterates
 void diis_step(Ctx& c, const roks_diis_params& p, roks_diis_info* info);
 void reset_diis(Ctx& c);
+// S|psi_n> of the current orbitals as left by the last energy_gradient
+// (d_Spsi with overlap coefficients, else the orbitals themselves)
+const double2* overlap_psi(const Ctx& c);
 void orthonormalize(Ctx& c, double2* vecs);
 // the allocation-free operator application (noalloc.hip): its scratch is a
 // file-scope device array of this size on every device

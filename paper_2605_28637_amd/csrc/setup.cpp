@@ -116,6 +116,17 @@ void build_problem(Ctx& c, const roks_system* s) {
                    "D must be symmetric");
         ROKS_CHECK(o.l[p] == o.l[q] || a == 0.0, ROKS_ERR_ARG, "D couples different l");
       }
+    // overlap coefficients (NULL: S = 1), checked like D
+    o.q.assign((size_t)sp.nproj * sp.nproj, 0.0);
+    if (sp.q && sp.nproj > 0) o.q.assign(sp.q, sp.q + (size_t)sp.nproj * sp.nproj);
+    for (int p = 0; p < sp.nproj; ++p)
+      for (int q = 0; q < sp.nproj; ++q) {
+        double a = o.q[p * sp.nproj + q], b = o.q[q * sp.nproj + p];
+        ROKS_CHECK(std::isfinite(a), ROKS_ERR_ARG, "non-finite q");
+        ROKS_CHECK(std::fabs(a - b) <= 1e-14 * (std::fabs(a) + std::fabs(b)), ROKS_ERR_ARG,
+                   "q must be symmetric");
+        ROKS_CHECK(o.l[p] == o.l[q] || a == 0.0, ROKS_ERR_ARG, "q couples different l");
+      }
     c.species.push_back(o);
   }
   c.spec_of.assign(s->species, s->species + c.natoms);
@@ -271,6 +282,8 @@ void build_projectors(Ctx& c) {
   c.atom_proj_off.assign(c.natoms, 0);
   c.atom_proj_cnt.assign(c.natoms, 0);
   c.Dblk.clear();
+  c.Qblk.clear();
+  c.has_q = false;
   c.Dblk_off.assign(c.natoms, 0);
   for (int a = 0; a < c.natoms; ++a) {
     const Ctx::Species& sp = c.species[c.spec_of[a]];
@@ -293,9 +306,14 @@ void build_projectors(Ctx& c) {
     const int np = (int)sp.l.size();
     for (int i = 0; i < na; ++i)
       for (int j = 0; j < na; ++j) {
-        double v = 0;
-        if (sp.l[chan[i]] == sp.l[chan[j]] && mm[i] == mm[j]) v = sp.D[chan[i] * np + chan[j]];
+        double v = 0, w = 0;
+        if (sp.l[chan[i]] == sp.l[chan[j]] && mm[i] == mm[j]) {
+          v = sp.D[chan[i] * np + chan[j]];
+          w = sp.q[chan[i] * np + chan[j]];
+        }
         c.Dblk.push_back(v);
+        c.Qblk.push_back(w);
+        c.has_q = c.has_q || w != 0.0;
       }
   }
   c.nproj = (int)c.proj_atom.size();

@@ -100,12 +100,18 @@ void prepare_line_search(Ctx& c, bool first) {
       c.potentials_valid = false;
     }
     proj_wdot(c, nb, dbl(c.d_S), K, c.d_PS, nb);
+    if (c.has_q) {
+      // <S|S|S> = <S|S> + PS^T q PS: the trial Gram matrix in the S metric
+      launch_apply_Q(c, c.d_PS, c.d_DP);
+      gemm_small(c, nb, nb, c.nproj, c.d_PS, nb, true, c.d_DP, nb, false, c.d_SS, nb, 1.0, 1.0);
+    }
   }
 }
 
 // Psi(delta) = U^T L^-1 (Psi + delta S), U = exp(delta D); its energy.
-// The orbitals are orthonormal and S is orthogonal to them, so the Gram
-// matrix of Psi + delta S is I + delta^2 <S|S>, and the trial's projections
+// The orbitals are orthonormal and S is orthogonal to them (both in the
+// metric of the overlap operator when it is not 1), so the Gram matrix of
+// Psi + delta S is I + delta^2 <S|S>, and the trial's projections
 // are <beta|Psi + delta S> = P0 + delta PS rotated by M.  One
 // synchronisation: the Cholesky status and the energy sums come back together
 // (a failed factorisation only makes the rest of the evaluation meaningless).
@@ -375,6 +381,27 @@ static void virtual_block(Ctx& c) {
   launch_virtual_block(c, v0);
 }
 
+// S|psi_n> of the current orbitals into d_Spsi (needs their projections in
+// d_P); without overlap coefficients S = 1 and the orbitals serve as they are
+static void make_overlap_psi(Ctx& c) {
+  if (!c.has_q) return;
+  const int K = 2 * c.npw;
+  copy_dev(c, c.d_Spsi, c.d_psi, (size_t)c.nb * c.npw * sizeof(double2));
+  launch_apply_Q(c, c.d_P, c.d_DP);
+  proj_expand(c, c.nb, c.d_DP, c.nb, dbl(c.d_Spsi), K);
+}
+
+const double2* overlap_psi(const Ctx& c) { return c.has_q ? c.d_Spsi : c.d_psi; }
+
+// the occupied block of gamma (Eq. gamma_def) of the current orbitals into G
+// [nb][nb]: theta from one application of the shell operators
+static void overlap_multipliers(Ctx& c, double* G) {
+  const int nb = c.nb, K = 2 * c.npw;
+  apply_operator(c, c.d_psi, 0, c.d_Y, false);
+  gemm_wdot(c, nb, nb, K, dbl(c.d_psi), K, dbl(c.d_Y), K, c.d_theta, nb, 1.0, 0.0, true);
+  launch_overlap_multipliers(c, c.d_theta, G);
+}
+
 void energy_gradient(Ctx& c, roks_energies* e, double* open_out, bool want_vv) {
   ROKS_CHECK(c.have_orbitals, ROKS_ERR_STATE, "no orbitals set");
   const int nb = c.nb, K = 2 * c.npw;
@@ -383,9 +410,11 @@ void energy_gradient(Ctx& c, roks_energies* e, double* open_out, bool want_vv) {
   ROKS_CHECK(std::isfinite(c.last_e.E), ROKS_ERR_NAN, "non-finite energy");
   if (e) *e = c.last_e;
   apply_operator(c, c.d_psi, 0, c.d_Y, true);
+  make_overlap_psi(c);
   gemm_wdot(c, nb, nb, K, dbl(c.d_psi), K, dbl(c.d_Y), K, c.d_theta, nb, 1.0, 0.0, true);
-  gemm_expand_to(c, nb, K, nb, c.d_theta, nb, false, dbl(c.d_psi), K, dbl(c.d_Y), K, dbl(c.d_gI), K,
-                 -1.0, 1.0);
+  // g_I = Y - sum_m S|m> theta_mn (Eq. gradient)
+  gemm_expand_to(c, nb, K, nb, c.d_theta, nb, false, dbl(overlap_psi(c)), K, dbl(c.d_Y), K,
+                 dbl(c.d_gI), K, -1.0, 1.0);
   launch_subspace(c, open_out);
   if (want_vv || (c.flags & ROKS_FLAG_CANONICALIZE)) virtual_block(c);
 }
@@ -453,7 +482,8 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     else
       launch_teter(c, c.d_bandv, c.d_bandv + nb, c.d_gI, bandw, c.d_w1);
     const int nc = with_sold ? 2 * nb : nb;
-    gemm_wdot(c, nb, nc, K, dbl(c.d_psi), K, dbl(c.d_w1), K, c.d_m12, nc, 1.0, 0.0, true);
+    // <m|S K g_I> (and <m|S S_old>): the projections of Eq. prec_grad_I
+    gemm_wdot(c, nb, nc, K, dbl(overlap_psi(c)), K, dbl(c.d_w1), K, c.d_m12, nc, 1.0, 0.0, true);
     gemm_expand_to(c, nb, K, nb, c.d_m12, nc, false, dbl(c.d_psi), K, dbl(c.d_w1), K, dbl(c.d_p), K,
                    -1.0, 1.0);
     band_dots_asym(c, c.d_p, c.d_gI, nb, c.d_cg + 8, st + kStage, c.d_A, c.d_theta, c.d_cg, st);
@@ -636,6 +666,12 @@ void orthonormalize(Ctx& c, double2* vecs) {
   const int nb = c.nb, K = 2 * c.npw;
   const size_t band = (size_t)nb * c.npw;
   gemm_wdot(c, nb, nb, K, dbl(vecs), K, dbl(vecs), K, c.d_gram, nb, 1.0, 0.0, true);
+  if (c.has_q) {
+    // the Gram matrix of the overlap operator: + P^T q P
+    proj_wdot(c, nb, dbl(vecs), K, c.d_dP, nb);
+    launch_apply_Q(c, c.d_dP, c.d_DP);
+    gemm_small(c, nb, nb, c.nproj, c.d_dP, nb, true, c.d_DP, nb, false, c.d_gram, nb, 1.0, 1.0);
+  }
   cholesky_inverse(c, c.d_gram, nb, c.d_Linv, c.d_flag);
   int32_t flag = 0;
   to_host(c, &flag, c.d_flag, sizeof(int32_t));
@@ -645,7 +681,7 @@ void orthonormalize(Ctx& c, double2* vecs) {
 }
 
 // ---------------------------------------------------------------------------
-// forces (Eq. force_hf, S = 1)
+// forces (Eq. force_hf)
 // ---------------------------------------------------------------------------
 void forces(Ctx& c, double* f_host) {
   ensure_potentials(c);
@@ -653,6 +689,8 @@ void forces(Ctx& c, double* f_host) {
   const int nat = c.natoms;
   if (nat == 0) return;
   if (!c.d_force_loc) c.d_force_loc = dalloc<double>(c, 3 * (size_t)nat);
+  // with overlap coefficients: gamma of the occupied bands (Eq. gamma_def)
+  if (c.has_q && c.nproj > 0) overlap_multipliers(c, c.d_m1);
   // local part, dE/dR_I from rho_w = sum_L c_L rho_L, on the side stream
   ensure_side_stream(c);
   ROKS_HIP(hipEventRecord(c.ev_fork, c.stream));
@@ -682,6 +720,14 @@ void forces(Ctx& c, double* f_host) {
     // w_n (D P)_in, then the force field Phi_i = sum_n w_n (D P)_in psi_n: one
     // product over the bands in place of three derivative projections
     launch_apply_D(c, c.d_P, c.d_kinw_shell, c.d_DP);
+    if (c.has_q) {
+      // the overlap term -sum_{mn occ} gamma_mn <m|dS/dR|n> enters the same
+      // field as -(q P gamma)_in: Tr(gamma S'), which SI S2 evaluates in the
+      // eigenbasis of gamma, contracted here by one product instead (gamma
+      // in d_m1, formed before the side stream started)
+      launch_apply_Q(c, c.d_P, c.d_dP);
+      gemm_small(c, c.nproj, nb, nb, c.d_dP, nb, false, c.d_m1, nb, false, c.d_DP, nb, -1.0, 1.0);
+    }
     proj_field(c, c.d_DP, nb, dbl(c.d_psi), K, c.d_phi);
     ROKS_HIP(hipStreamWaitEvent(c.stream, c.ev_join, 0));
     // straight into the pinned host mirror

@@ -39,7 +39,8 @@ class Proj(C.Structure):
 
 class Species(C.Structure):
     _fields_ = [("A", C.c_double), ("sigma", C.c_double), ("nproj", C.c_int32),
-                ("proj", C.POINTER(Proj)), ("D", C.POINTER(C.c_double))]
+                ("proj", C.POINTER(Proj)), ("D", C.POINTER(C.c_double)),
+                ("q", C.POINTER(C.c_double))]
 
 
 class System(C.Structure):
@@ -268,6 +269,13 @@ class _SystemBuffers:
             self.specs[i].nproj = npj
             self.specs[i].proj = C.cast(pj, C.POINTER(Proj))
             self.specs[i].D = _dptr(D)
+            # overlap coefficients (absent: NULL, S = 1)
+            if sp.get("q") is not None and npj > 0:
+                q = np.ascontiguousarray(np.asarray(sp["q"], dtype=np.float64).reshape(-1))
+                self.keep.append(q)
+                self.specs[i].q = _dptr(q)
+            else:
+                self.specs[i].q = None
         st = System()
         for i in range(9):
             st.cell[i] = self.cell[i]

@@ -35,6 +35,12 @@ CASES = {
     # the paper takes for MgO) of exact exchange
     "pbe0": lambda: dict(inputs.tiny_cell(), xc="pbe", exx=0.25),
     "ddh_molecule": lambda: dict(small_molecule(), xc="pbe", exx=0.36),
+    # the overlap S = 1 + sum q |beta><beta|: one s channel, s + p channels,
+    # and two coupled s channels (q_01 != 0) in the one-cell oxide
+    "overlap": lambda: inputs.with_overlap(inputs.tiny_cell(), 0.5),
+    "overlap_molecule": lambda: inputs.with_overlap(small_molecule(), 0.4),
+    "overlap_oxide_cell": lambda: inputs.with_overlap(
+        inputs.oxide_vacancy(reps=1, N=24, nb=16), 0.3),
 }
 
 
@@ -50,7 +56,7 @@ class Pair:
         self.gpu.set_coeffs(inputs.random_coefficients(self.gpu.miller(), system["cell"],
                                                        self.gpu.nb, seed), True)
         self.psi = orc.orthonormalize(inputs.random_coefficients(self.m.miller, self.m.cell,
-                                                                 self.m.nb, seed))
+                                                                 self.m.nb, seed), self.m)
 
 
 @pytest.fixture(scope="module", params=list(CASES))
