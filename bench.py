@@ -532,6 +532,15 @@ def main():
             **{k: tb[k] for k in ("band_applies_per_s", "ms_per_step", "roofline",
                                   "h_apply_pipeline")},
             "proj_bf3": tb["kernels"]["proj_bf3"]}
+        tq = measure(inputs.with_overlap(system, 0.3), rb.FP64, args.steps, args.warmup,
+                     table_steps=2)
+        out["oxide_overlap"] = {
+            "workload": "the same supercell with overlap coefficients q (S = 1 + sum q "
+                        "|beta><beta|, q = 0.3 diag(1, 0.6, 0.4, 0.3) + 0.06 between the s "
+                        "channels), fp64",
+            **{k: tq[k] for k in ("band_applies_per_s", "ms_per_step", "roofline")},
+            "cost_vs_s_equal_1": tq["ms_per_step"] / head["ms_per_step"]
+            if args.tier == "fp64" else None}
         mol = inputs.molecule_box()
         m = measure(mol, rb.FP64, max(args.steps, 20), args.warmup, table_steps=10)
         out["molecule_64"] = {

@@ -14,7 +14,14 @@ and sampled coefficients; the Hellmann-Feynman forces after the third step
 (Eq. force_hf).
 
 Runs in ~15-30 min on one CPU socket:  python tests/golden/make_oxide_golden.py
+
+With --overlap SCALE the species carry the overlap coefficients of
+inputs.with_overlap(system, SCALE) (S = 1 + sum q |beta><beta|, Sec. II A),
+the start is S-orthonormalised, and --steps CG iterations are stored in
+tests/golden/oxide_overlap_cg<steps>.json:
+python tests/golden/make_oxide_golden.py --overlap 0.3 --steps 1
 """
+import argparse
 import json
 import os
 import sys
@@ -28,7 +35,7 @@ sys.path.insert(0, ROOT)
 from oracle import roks as orc  # noqa: E402
 from paper_2605_28637_amd import inputs  # noqa: E402
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oxide_cg3.json")
+HERE = os.path.dirname(os.path.abspath(__file__))
 PROBE_SEED = 31337
 SAMPLE_BANDS = [0, 1, 107, 213, 214, 320, 427, 428, 429, 430, 431]
 ROW_BANDS = [0, 427, 428, 429, 430, 431]
@@ -53,15 +60,25 @@ def state_record(m, psi, probe, millers):
 
 
 def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--overlap", type=float, default=0.0)
+    ap.add_argument("--steps", type=int, default=3)
+    args = ap.parse_args()
     t0 = time.time()
     s = inputs.oxide_vacancy()
+    if args.overlap:
+        s = inputs.with_overlap(s, args.overlap)
+        out_path = os.path.join(HERE, "oxide_overlap_cg%d.json" % args.steps)
+    else:
+        out_path = os.path.join(HERE, "oxide_cg%d.json" % args.steps)
     m = orc.Model(s)
     print("model: npw %d nproj %d nb %d (%.0f s)" % (m.npw, m.nproj, m.nb, time.time() - t0),
           flush=True)
     probe = inputs.gaussian_pairs(PROBE_SEED, 0, m.miller)
     millers = sample_millers(m)
-    psi = orc.orthonormalize(inputs.random_coefficients(m.miller, m.cell, m.nb, s["seed"]))
-    out = {"system": "oxide_vacancy(seed=%d)" % s["seed"], "probe_seed": PROBE_SEED,
+    psi = orc.orthonormalize(inputs.random_coefficients(m.miller, m.cell, m.nb, s["seed"]), m)
+    out = {"system": "oxide_vacancy(seed=%d)" % s["seed"], "overlap_scale": args.overlap,
+           "probe_seed": PROBE_SEED,
            "sample_bands": SAMPLE_BANDS, "row_bands": ROW_BANDS, "millers": millers,
            "start": state_record(m, psi, probe, millers)}
     gr = orc.gradient(m, psi)
@@ -77,7 +94,7 @@ def main():
     del gr
     st = orc.CGState(psi=psi)
     steps = []
-    for it in range(3):
+    for it in range(args.steps):
         info = orc.pcg_step(m, st)
         steps.append({"E0": info.E0, "E1": info.E1, "delta": info.delta, "beta": info.beta,
                       "dE0": info.dE0, "norm_gI": info.norm_gI, "max_Rab": info.max_Rab,
@@ -88,9 +105,9 @@ def main():
     out["final"] = state_record(m, st.psi, probe, millers)
     out["final"]["forces"] = orc.forces(m, st.psi).tolist()
     print("forces (%.0f s)" % (time.time() - t0), flush=True)
-    with open(OUT, "w") as f:
+    with open(out_path, "w") as f:
         json.dump(out, f, indent=0)
-    print("wrote", OUT)
+    print("wrote", out_path)
 
 
 if __name__ == "__main__":
