@@ -54,13 +54,14 @@ void init_device(Ctx& c, void* stream) {
   ROKS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device));
   c.nchunk = plane_chunks(c.N[2], c.npairs, std::max(1, cus));
   if (c.N[0] == c.N[1] && line_split(c.N[0], &c.lines_G, &c.lines_P)) {
+    line_split_density(c.N[0], &c.dlines_G, &c.dlines_P);
     // several line-kernel workgroups share a CU: about two rounds of them
     const int n = c.N[0], nh = 2 * c.hmax + 1;
     const size_t lds = (size_t)(n + nh * (n + 1)) * 16 + 1024;
     const int per_cu = std::max(1, std::min(8, (int)((160 * 1024) / lds)));
     c.nchunk = std::max(1, std::min(c.npairs, cdiv(2 * cus * per_cu, c.N[2])));
   } else {
-    c.lines_G = c.lines_P = 0;
+    c.lines_G = c.lines_P = c.dlines_G = c.dlines_P = 0;
   }
 
   c.d_miller = dalloc<int32_t>(c, 3 * npw);
@@ -210,7 +211,7 @@ void upload_static(Ctx& c) {
       up(c.d_krange, kr.data(), kr.size() * sizeof(int32_t));
       ROKS_HIP(hipStreamSynchronize(c.stream));
     } else {
-      c.lines_G = c.lines_P = 0;
+      c.lines_G = c.lines_P = c.dlines_G = c.dlines_P = 0;
     }
   }
   std::vector<double2> tw[3];  // host sources stay alive until the stream synchronises below

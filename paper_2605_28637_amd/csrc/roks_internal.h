@@ -60,6 +60,7 @@ FftPlan1D make_plan(int n);  // radices 8, 4, 2, 3, 5 (throws if n has other fac
 
 // the line-kernel split N = G P of a square plane (false: none built)
 bool line_split(int n, int* G, int* P);
+bool line_split_density(int n, int* G, int* P);
 
 // ---------------------------------------------------------------------------
 // the context
@@ -258,6 +259,7 @@ struct Ctx {
   // P (0: not available, the LDS-plane kernels run), per-column LDS index and
   // per-row k range of the pruned [2 hmax + 1][N + 1] plane
   int lines_G = 0, lines_P = 0;
+  int dlines_G = 0, dlines_P = 0;  // the split of the density passes
   int32_t* d_colidx = nullptr;   // [ncol]
   int32_t* d_krange = nullptr;   // [2 hmax + 1][2] signed k range of each row
   size_t part_capacity = 0;      // doubles in d_part

@@ -8,7 +8,9 @@ steps (a probe sum of every band and sampled coefficients, per band) and the
 Hellmann-Feynman forces of every atom (Eq. force_hf).  FP64: 1e-10 relative
 on energies and matrices, 1e-8 on the orbitals and forces after three steps
 (the line search's step lengths carry the energies' rounding); the FP32 tier
-at its stated 2e-6 relative on energies and 1e-4 Ha/bohr on forces."""
+at its stated 2e-6 relative on energies and 1e-4 Ha/bohr on forces.  With
+overlap coefficients (tests/golden/oxide_overlap_cg1.json, same script with
+--overlap 0.3 --steps 1): the start, one step and the forces at the FP64 bar."""
 import json
 import os
 
@@ -115,4 +117,46 @@ def test_oxide_three_cg_steps_fp32_tier(gold):
     F = g.forces()
     Fo = np.array(gold["final"]["forces"])
     assert np.abs(F - Fo).max() < 1e-4
+    g.close()
+
+
+GOLD_Q = os.path.join(ROOT, "tests", "golden", "oxide_overlap_cg1.json")
+
+
+def test_oxide_with_overlap_one_cg_step_and_forces():
+    """The same supercell with overlap coefficients (S = 1 + sum q
+    |beta><beta|, inputs.with_overlap(.., 0.3)) against the oracle's
+    tests/golden/oxide_overlap_cg1.json: the S-orthonormalised start (probe
+    sums, sampled coefficients), its energy, theta diagonal and per-band
+    ||g_I,n||^2 (g_I with S|m>), one CG step (the S-metric trial Gram) and
+    the forces with the overlap term, at the FP64 bar."""
+    with open(GOLD_Q) as f:
+        gq = json.load(f)
+    rb = ensure_built()
+    s = inputs.with_overlap(inputs.oxide_vacancy(), gq["overlap_scale"])
+    print("oxide with overlap", flush=True)
+    g = rb.Roks(s)
+    g.set_coeffs(inputs.random_coefficients(g.miller(), s["cell"], g.nb, s["seed"]), True)
+    st = gq["start"]
+    _check_state(g, st, gq, 1e-10)
+    e, gI, th = g.energy_gradient()
+    assert abs(e["E"] - st["E"]) < 1e-10 * abs(st["E"])
+    np.testing.assert_allclose(np.diag(th), st["theta_diag"], rtol=0,
+                               atol=1e-10 * np.abs(st["theta_diag"]).max())
+    gn2 = np.abs(gI) ** 2
+    gn2 = 2.0 * gn2.sum(axis=1) - gn2[:, 0]
+    np.testing.assert_allclose(gn2, st["gI_norm2"], rtol=1e-9, atol=1e-12 * max(st["gI_norm2"]))
+    for i, o in enumerate(gq["steps"]):
+        gi = g.pcg_step()
+        print("step", i, gi["E0"], gi["E1"], gi["delta"], flush=True)
+        sc = max(1.0, abs(o["E0"]))
+        assert abs(gi["E0"] - o["E0"]) < 1e-10 * sc, i
+        assert abs(gi["E1"] - o["E1"]) < 1e-10 * sc, i
+        assert abs(gi["delta"] - o["delta"]) < 1e-8 * max(1.0, o["delta"]), i
+        assert abs(gi["dE0"] - o["dE0"]) < 1e-9 * abs(o["dE0"]), i
+        assert abs(gi["norm_gI"] - o["norm_gI"]) < 1e-9 * o["norm_gI"], i
+    _check_state(g, gq["final"], gq, 1e-9)
+    F = g.forces()
+    Fo = np.array(gq["final"]["forces"])
+    assert np.abs(F - Fo).max() < 1e-8 * max(1.0, np.abs(Fo).max())
     g.close()
