@@ -112,43 +112,17 @@ struct TileOrder {
   int by_chunk;
 };
 
-// DIRECT: C = alpha sum + beta Cin; else the chunk's sum to part[z][M][N]
-template <int ALAY, int BLAY, bool HW, bool SUM>
-__global__ void __launch_bounds__(kTThreads, 2) k_tile_gemm(
-    int M, int N, int K, const double* __restrict__ A, int lda, const double* __restrict__ B,
-    const double* __restrict__ B2, double b2, int ldb, double* __restrict__ C, int ldc,
-    const double* __restrict__ Cin, int ldcin, double alpha, double beta, int kchunk, int direct,
-    int avec, int bvec, double* __restrict__ part, TileOrder ord) {
-  __shared__ double As[2][kTK * kTLd];
-  __shared__ double Bs[2][kTK * kTLd];
-  // XCD-aware order: workgroup L runs on XCD L % 8 (round-robin dispatch);
-  // the workgroups sharing operand slices (one K chunk: all tiles; no split:
-  // all m tiles of one column tile) form a group, and each group is placed
-  // on one XCD so its L2 serves the re-reads
-  const int L = blockIdx.x;
-  const int s8 = L >> 3;
-  const int g = (L & 7) + 8 * (s8 / ord.members), mem = s8 % ord.members;
-  if (g >= ord.groups) return;
-  int tx, ty, tz;
-  if (ord.by_chunk) {
-    tz = g;
-    tx = mem % ord.gx;
-    ty = mem / ord.gx;
-  } else {
-    tz = 0;
-    ty = g;
-    tx = mem;
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave >> 2, wn = wave & 3;  // 2 x 4 waves of 64 x 32
-  const int m0 = tx * kTM, n0 = ty * kTN;
-  const int kb = tz * kchunk, ke = min(K, kb + kchunk);
-  const int r16 = lane & 15, s = lane >> 4;
-  d4 acc[4][2];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+// the K loop of one workgroup: per step of 16 k the A and B slices staged in
+// LDS (double-buffered, the next step's global loads in registers while this
+// step's products run); GUARD skips the blocks that vi / vj mark as past the
+// matrix
+template <int ALAY, int BLAY, bool HW, bool SUM, bool GUARD>
+__device__ __forceinline__ void tile_main(const double* __restrict__ A, int lda,
+                                          const double* __restrict__ B, const double* __restrict__ B2,
+                                          double b2, int ldb, int M, int N, int m0, int n0, int kb,
+                                          int ke, int avec, int bvec, int wm, int wn, int r16, int s,
+                                          const bool* vi, const bool* vj, double (*As)[kTK * kTLd],
+                                          double (*Bs)[kTK * kTLd], d4 (*acc)[2]) {
   double va[kTPer], vb[kTPer];
   int buf = 0;
   if (kb < ke) {
@@ -177,7 +151,9 @@ __global__ void __launch_bounds__(kTThreads, 2) k_tile_gemm(
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j)
+          if (!GUARD || (vi[i] && vj[j]))
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (more) {
       tile_store<ALAY>(As[buf ^ 1], va);
@@ -186,6 +162,60 @@ __global__ void __launch_bounds__(kTThreads, 2) k_tile_gemm(
     __syncthreads();
     buf ^= 1;
   }
+}
+
+// DIRECT: C = alpha sum + beta Cin; else the chunk's sum to part[z][M][N]
+template <int ALAY, int BLAY, bool HW, bool SUM>
+__global__ void __launch_bounds__(kTThreads, 2) k_tile_gemm(
+    int M, int N, int K, const double* __restrict__ A, int lda, const double* __restrict__ B,
+    const double* __restrict__ B2, double b2, int ldb, double* __restrict__ C, int ldc,
+    const double* __restrict__ Cin, int ldcin, double alpha, double beta, int kchunk, int direct,
+    int avec, int bvec, double* __restrict__ part, TileOrder ord) {
+  __shared__ double As[2][kTK * kTLd];
+  __shared__ double Bs[2][kTK * kTLd];
+  // XCD-aware order: workgroup L runs on XCD L % 8 (round-robin dispatch);
+  // the workgroups sharing operand slices (one K chunk: all tiles; no split:
+  // all m tiles of one column tile) form a group, and each group is placed
+  // on one XCD so its L2 serves the re-reads
+  const int L = blockIdx.x;
+  const int s8 = L >> 3;
+  const int g = (L & 7) + 8 * (s8 / ord.members), mem = s8 % ord.members;
+  if (g >= ord.groups) return;
+  int tx, ty, tz;
+  if (ord.by_chunk) {
+    tz = g;
+    tx = mem % ord.gx;
+    ty = mem / ord.gx;
+  } else {
+    tz = 0;
+    ty = g;
+    tx = mem;
+  }
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = wave >> 2, wn = wave & 3;  // 2 x 4 waves of 64 x 32
+  const int m0 = tx * kTM, n0 = ty * kTN;
+  const int kb = tz * kchunk, ke = min(K, kb + kchunk);
+  const int r16 = lane & 15, s = lane >> 4;
+  d4 acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  // interior tiles run the plain loop; edge tiles skip the 16 x 16 blocks
+  // wholly past M or N (the test is uniform over the wave, so the matrix
+  // cores go to other waves)
+  bool vi[4], vj[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) vi[i] = m0 + wm * 64 + 16 * i < M;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) vj[j] = n0 + wn * 32 + 16 * j < N;
+  if (vi[3] && vj[1])
+    tile_main<ALAY, BLAY, HW, SUM, false>(A, lda, B, B2, b2, ldb, M, N, m0, n0, kb, ke, avec, bvec, wm,
+                                          wn, r16, s, vi, vj, As, Bs, acc);
+  else
+    tile_main<ALAY, BLAY, HW, SUM, true>(A, lda, B, B2, b2, ldb, M, N, m0, n0, kb, ke, avec, bvec, wm,
+                                         wn, r16, s, vi, vj, As, Bs, acc);
   // accumulator r of lane l in block (i, j): row 16 i + l/16 + 4 r, column 16 j + l%16
 #pragma unroll
   for (int i = 0; i < 4; ++i)
