@@ -763,38 +763,45 @@ struct RegDft<R, P, P> {
   }
 };
 
-// the value of lane (lane ^ m) for m in {1, 2, 4, 8}, by DPP moves within a
-// row of 16 lanes: quad permutations for 1 and 2; for 4 and 8 the row shifted
-// both ways (row_shl: lane i reads lane i + m, row_shr: lane i - m) and the
-// side picked by the lane's bit m
-__device__ __forceinline__ int xor_lane(int v, int m, int lane) {
-  switch (m) {
-    case 1: return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
-    case 2: return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
-    case 4: {
-      // banks (groups of 4 lanes) 0, 2 read lane + 4, banks 1, 3 lane - 4
-      const int up = __builtin_amdgcn_update_dpp(0, v, 0x104, 0xF, 0x5, false);   // row_shl:4
-      return __builtin_amdgcn_update_dpp(up, v, 0x114, 0xF, 0xA, false);          // row_shr:4
-    }
-    case 8: {
-      // banks 0, 1 read lane + 8, banks 2, 3 lane - 8
-      const int up = __builtin_amdgcn_update_dpp(0, v, 0x108, 0xF, 0x3, false);   // row_shl:8
-      return __builtin_amdgcn_update_dpp(up, v, 0x118, 0xF, 0xC, false);          // row_shr:8
-    }
-    default: return __shfl_xor(v, m, 64);
+// The lanes of a line group carry a logical index t (the butterfly
+// position) that differs from the physical lane p: p = t0 ^ 2 t1 ^ 7 t2 ^
+// 8 t3 for t = t0 + 2 t1 + 4 t2 + 8 t3 (a linear map over GF(2), so the
+// partner of t along logical bit m is the physical lane p ^ mask(m), mask =
+// 1, 2, 7, 8).  Each partner is then one DPP move per dword: quad
+// permutations for 1 and 2, row_half_mirror (lane i reads 7 - i within its
+// eight) for 7, row_ror:8 (lane i reads (i + 8) mod 16) for 8; the plain
+// xor by 4 or 8 would take two moves with bank masks.
+template <int G>
+__device__ __forceinline__ int logical_lane(int p) {
+  if constexpr (G >= 8) {
+    const int c = (p >> 2) & 1;  // only mask 7 sets physical bit 2
+    const int q = p ^ (c ? 7 : 0);
+    return (q & 3) | (c << 2) | (q & 8);
+  } else {
+    return p;
   }
 }
-__device__ __forceinline__ float xor_lane(float v, int m, int lane) {
-  return __int_as_float(xor_lane(__float_as_int(v), m, lane));
+
+// the value held by the partner along logical bit m in {1, 2, 4, 8}
+__device__ __forceinline__ int partner(int v, int m) {
+  switch (m) {
+    case 1: return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
+    case 2: return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
+    case 4: return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true);  // row_half_mirror
+    default: return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, true); // row_ror:8
+  }
 }
-__device__ __forceinline__ double xor_lane(double v, int m, int lane) {
-  const int lo = xor_lane(__double2loint(v), m, lane);
-  const int hi = xor_lane(__double2hiint(v), m, lane);
+__device__ __forceinline__ float partner(float v, int m) {
+  return __int_as_float(partner(__float_as_int(v), m));
+}
+__device__ __forceinline__ double partner(double v, int m) {
+  const int lo = partner(__double2loint(v), m);
+  const int hi = partner(__double2hiint(v), m);
   return __hiloint2double(hi, lo);
 }
 template <typename R>
-__device__ __forceinline__ C2<R> shfl_xor2(C2<R> v, int m, int lane) {
-  return mk<R>(xor_lane(v.x, m, lane), xor_lane(v.y, m, lane));
+__device__ __forceinline__ C2<R> partner2(C2<R> v, int m) {
+  return mk<R>(partner(v.x, m), partner(v.y, m));
 }
 
 // one line of length N = G P over the G lanes of a group (t: lane in group)
@@ -828,7 +835,7 @@ struct LineFft {
       const C2<R> wl = hi ? w : mk<R>(1, 0);
 #pragma unroll
       for (int k = 0; k < P; ++k) {
-        const C2<R> p = shfl_xor2<R>(v[k], h, t);
+        const C2<R> p = partner2<R>(v[k], h);
         const C2<R> d = mk<R>(fma(sg, v[k].x, p.x), fma(sg, v[k].y, p.y));
         v[k] = cmul<R>(d, wl);
       }
@@ -850,7 +857,7 @@ struct LineFft {
       const C2<R> be = hi ? mk<R>(1, 0) : w;
 #pragma unroll
       for (int k = 0; k < P; ++k) {
-        const C2<R> p = shfl_xor2<R>(v[k], h, t);
+        const C2<R> p = partner2<R>(v[k], h);
         const C2<R> a = v[k];
         v[k] = mk<R>(fma(be.x, p.x, fma(-be.y, p.y, fma(al.x, a.x, -al.y * a.y))),
                      fma(be.x, p.y, fma(be.y, p.x, fma(al.x, a.y, al.y * a.x))));
@@ -903,7 +910,7 @@ __global__ void __launch_bounds__(NT, 512 / NT) k_plane_lines(
   int2* kr = reinterpret_cast<int2*>(red + 6 * NW);                 // [nh]
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
-  const int t = lane & (G - 1);
+  const int t = logical_lane<G>(lane & (G - 1));
   const int grp = tid / G;
   const int brt = bitrev_lane<G>(t);
   const int z = blockIdx.x, chunk = blockIdx.y;
