@@ -316,7 +316,12 @@ roks_status roks_reset_cg(roks_ctx ctx);
 roks_status roks_set_restart(roks_ctx ctx, int32_t period);
 /* Switch the arithmetic tier (roks_precision) for the following calls,
  * keeping the orbitals and the CG state: a precision ladder runs FP32 (or
- * FP32_BF16X3) iterations first and polishes in FP64. */
+ * FP32_BF16X3) iterations first and polishes in FP64.  With overlap
+ * coefficients q, leaving FP32_BF16X3 S-orthonormalises the orbitals again
+ * in the new tier and resets the CG state (that tier forms the q part of
+ * the S-Gram matrix from split-precision projections, so its orbitals are
+ * S-orthonormal only to that rounding); ROKS_ERR_NOT_PD as in
+ * roks_set_coeffs. */
 roks_status roks_set_precision(roks_ctx ctx, int32_t precision);
 /* Iterate roks_pcg_step until |E_{i+1} - E_i| < tol on two consecutive
  * iterations or maxiter; *iterations receives the count, *last the final

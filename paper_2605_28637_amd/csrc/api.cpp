@@ -357,8 +357,14 @@ roks_status roks_set_precision(roks_ctx ctx, int32_t precision) {
       c.d_vloc32 = roks::dalloc<float>(c, (size_t)2 * c.nconf * c.ntot);
     }
     if (fft != c.prec || bf3 != c.bf3) c.potentials_valid = false;
+    const bool left_bf3 = c.bf3 && !bf3;
     c.prec = fft;
     c.bf3 = bf3;
+    if (left_bf3 && c.has_q && c.have_orbitals) {
+      // the BF16x3 products left the S-Gram's q part at their rounding
+      roks::reset_cg(c);
+      roks::orthonormalize(c, c.d_psi);
+    }
   });
 }
 

@@ -4,7 +4,8 @@ of test_gpu_parity.py: the S-orthonormalisation after a move of the atoms,
 DIIS steps, a converged ground state against the dense generalised
 eigenproblem, the forces with their overlap term at convergence, the first
 relaxation steps, and the checks of q at creation.  FP64 bar as in the other
-parity tests."""
+parity tests; the FP32 and BF16x3 tiers at their per-call bar and the
+ladder's end-to-end targets (1 meV, 1e-4 Ha/bohr)."""
 import numpy as np
 import pytest
 
@@ -114,3 +115,74 @@ def test_overlap_coefficients_are_checked(bad):
     with pytest.raises(rb.RoksError) as ei:
         rb.Roks(s)
     assert ei.value.status == 1
+
+
+MEV = 1.0 / 27211.386
+
+
+def test_fp32_tier_with_overlap_per_call():
+    """The FP32 tier with overlap coefficients against the FP64 oracle at the
+    tier's per-call bar (2e-6 relative; the Gram, S|psi> and every band-space
+    product stay FP64, so the S-orthonormal start matches at 1e-12)."""
+    rb = ensure_built()
+    s = inputs.with_overlap(small_molecule(), 0.4)
+    g = rb.Roks(s, precision=rb.FP32)
+    m = orc.Model(s)
+    mp = SphereMap(g.miller(), m.miller)
+    g.set_coeffs(inputs.random_coefficients(g.miller(), s["cell"], g.nb, s["seed"]), True)
+    psi = orc.orthonormalize(inputs.random_coefficients(m.miller, m.cell, m.nb, s["seed"]), m)
+    assert band_rel(mp.to_full(g.get_coeffs()), psi) < 1e-12
+    e, gi, th = g.energy_gradient()
+    gr = orc.gradient(m, psi)
+    scale = max(1.0, max(abs(v) for t in gr.pot.terms.values() for v in t))
+    assert abs(e["E"] - gr.pot.E) < 2e-6 * scale
+    assert np.linalg.norm(mp.to_full(gi) - gr.gI) < 2e-6 * np.linalg.norm(gr.Y)
+    assert np.abs(th - gr.theta).max() < 2e-6 * np.abs(gr.theta).max()
+    g.close()
+
+
+@pytest.fixture(scope="module")
+def overlap_protocol_oracle():
+    """Ground state then the singlet from its orbitals (the paper's protocol)
+    with overlap coefficients, FP64 oracle, |dE| < 1e-12 Ha."""
+    s = inputs.with_overlap(small_molecule(nb=12), 0.4)
+    gs = inputs.with_configuration(s, "gs")
+    mg = orc.Model(gs)
+    st, hg = orc.solve(mg, inputs.random_coefficients(mg.miller, mg.cell, mg.nb, gs["seed"]),
+                       tol=1e-12, maxiter=800)
+    m = orc.Model(s)
+    st2, he = orc.solve(m, st.psi, tol=1e-12, maxiter=800)
+    return s, he[-1].E1 - hg[-1].E1, orc.forces(m, st2.psi)
+
+
+@pytest.mark.parametrize("tier", ["fp32", "bf16x3"])
+def test_tier_ladder_with_overlap(tier, overlap_protocol_oracle):
+    """Both reduced tiers with overlap coefficients: iterations to |dE| <
+    1e-5 Ha in the tier, an FP64 polish to 1e-12, for the ground state and
+    then the singlet: excitation energy within 1 meV and forces within 1e-4
+    Ha/bohr of the FP64 oracle's."""
+    rb = ensure_built()
+    s, exc_o, F_o = overlap_protocol_oracle
+    prec = rb.FP32 if tier == "fp32" else rb.FP32_BF16X3
+
+    def ladder(r):
+        r.solve(tol=1e-5, maxiter=800)
+        r.set_precision(rb.FP64)
+        info, _ = r.solve(tol=1e-12, maxiter=800)
+        return info
+
+    gs = inputs.with_configuration(s, "gs")
+    g = rb.Roks(gs, precision=prec)
+    g.set_coeffs(inputs.random_coefficients(g.miller(), gs["cell"], g.nb, gs["seed"]), True)
+    eg = ladder(g)["E1"]
+    c = g.get_coeffs()
+    g.close()
+    r = rb.Roks(s, precision=prec)
+    r.set_coeffs(c, True)
+    es = ladder(r)["E1"]
+    F = r.forces()
+    r.close()
+    print(tier, "excitation %.9f oracle %.9f Ha; force diff %.2e"
+          % (es - eg, exc_o, np.abs(F - F_o).max()), flush=True)
+    assert abs((es - eg) - exc_o) < MEV
+    assert np.abs(F - F_o).max() < 1e-4
