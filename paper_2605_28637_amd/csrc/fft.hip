@@ -1415,10 +1415,12 @@ static void run_plane_density(Ctx& c, const void* T, int npairs, double* rho_par
   ROKS_HIP(hipGetLastError());
 }
 
-// The FP32 tier's density planes: only where the plane kernel needs at most
-// 16 points per thread or is the length-64 build.  Beyond, the general-radix
-// FP32 density kernel spills far more than the FP64 one (96^2 planes: 13.7
-// against 4.2 ms per all-band density), so the tier takes the FP64 density.
+// The FP32 tier's density planes: always with the line kernels (the square
+// sizes of their table, 96^2 included); with the LDS-plane kernels only where
+// they need at most 16 points per thread or are the length-64 build.  Beyond,
+// the general-radix FP32 LDS-plane density kernel spills far more than the
+// FP64 one (96^2 planes: 13.7 against 4.2 ms per all-band density), so such
+// grids take the FP64 density.
 bool fp32_density_planes(const Ctx& c) {
   if (c.lines_G > 0) return true;
   const int mp = pick_maxp(needed_points(c.N[0] * c.N[1], plane_threads(c)));
