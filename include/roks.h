@@ -107,7 +107,13 @@ enum {
   /* choose the split count of the band-space GEMMs by timing candidates on
    * the first use of each (M, N, K) shape; the choice is shared by all the
    * process's contexts.  It changes the order of the FP64 sums, so results
-   * agree to rounding, not bit for bit, between processes. */
+   * agree to rounding, not bit for bit, between processes.  With the
+   * environment variable ROKS_TUNE_CACHE naming a file, the choices are read
+   * from it on the first use (entries of the same GPU architecture and
+   * compute-unit count only) and the file is rewritten (JSON, through a
+   * temporary file and a rename) after every newly timed shape, so processes
+   * that share the file make the same choices and agree bit for bit; an
+   * unreadable or unwritable file only means timing again. */
   ROKS_FLAG_AUTOTUNE = 8u
 };
 

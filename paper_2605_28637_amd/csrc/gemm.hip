@@ -10,8 +10,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 
 #include "roks_internal.h"
@@ -276,16 +280,84 @@ int heuristic_splits(const Ctx& c, int M, int N, int K) {
   return std::min(ks, max_splits(c, M, N, K));
 }
 
-// autotuner: the split count of each (M, N, K) timed once per process
+// autotuner: the product kernel and split count of each (M, N, K), timed
+// once per process, or read from the cache file named by the environment
+// variable ROKS_TUNE_CACHE (choices of the same device architecture and
+// compute-unit count only; the file is rewritten, through a temporary file
+// and a rename, after every new choice).  Format, one entry per line:
+//   {"arch": "gfx950", "cus": 256, "wdot": [
+//   [M, N, K, choice],
+//   ...]}
+// choice > 0: the small-output product split over K in that many chunks;
+// choice < 0: the LDS-tiled product in -choice chunks of K.
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, int> g_tuned;
+bool g_cache_read = false;
+
+std::string device_tag(const Ctx& c, int* cus) {
+  hipDeviceProp_t p;
+  ROKS_HIP(hipGetDeviceProperties(&p, c.device));
+  *cus = p.multiProcessorCount;
+  std::string arch(p.gcnArchName);
+  const size_t colon = arch.find(':');
+  return colon == std::string::npos ? arch : arch.substr(0, colon);
+}
+
+void read_tune_cache(const Ctx& c) {
+  g_cache_read = true;
+  const char* path = std::getenv("ROKS_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  int cus = 0;
+  const std::string arch = device_tag(c, &cus);
+  char line[512];
+  bool ok = false;
+  if (std::fgets(line, sizeof line, f)) {
+    char a[128] = {0};
+    int fc = 0;
+    ok = std::sscanf(line, " {\"arch\": \"%127[^\"]\", \"cus\": %d", a, &fc) == 2 && arch == a &&
+         fc == cus;
+  }
+  while (ok && std::fgets(line, sizeof line, f)) {
+    int M, N, K, v;
+    if (std::sscanf(line, " [%d, %d, %d, %d]", &M, &N, &K, &v) == 4 && M > 0 && N > 0 && K > 0 && v != 0)
+      g_tuned.emplace(std::make_tuple(M, N, K), v);
+  }
+  std::fclose(f);
+}
+
+void write_tune_cache(const Ctx& c) {
+  const char* path = std::getenv("ROKS_TUNE_CACHE");
+  if (!path || !*path) return;
+  int cus = 0;
+  const std::string arch = device_tag(c, &cus);
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;  // the cache is an optimisation: an unwritable path only costs retuning
+  std::fprintf(f, "{\"arch\": \"%s\", \"cus\": %d, \"wdot\": [\n", arch.c_str(), cus);
+  size_t i = 0;
+  for (const auto& e : g_tuned)
+    std::fprintf(f, "[%d, %d, %d, %d]%s\n", std::get<0>(e.first), std::get<1>(e.first),
+                 std::get<2>(e.first), e.second, ++i < g_tuned.size() ? "," : "");
+  std::fprintf(f, "]}\n");
+  const bool good = std::fclose(f) == 0;
+  if (good) std::rename(tmp.c_str(), path);
+}
 
 int tuned_splits(Ctx& c, int M, int N, int K, const double* A, int lda, const double* B, int ldb,
                  bool half_weights) {
   std::lock_guard<std::mutex> lock(g_tune_mu);
+  if (!g_cache_read) read_tune_cache(c);
   const auto key = std::make_tuple(M, N, K);
   auto it = g_tuned.find(key);
-  if (it != g_tuned.end()) return it->second;
+  if (it != g_tuned.end()) {
+    // a cached choice the buffers of this context cannot take is timed again
+    const int v = it->second;
+    const bool fits = v < 0 ? (size_t)(-v) * M * N <= c.gemm_part_capacity
+                            : v <= max_splits(c, M, N, K);
+    if (fits) return v;
+  }
   const int h = heuristic_splits(c, M, N, K), hi = max_splits(c, M, N, K);
   std::vector<int> cand;
   if (M >= 64 && N >= 64)
@@ -319,6 +391,7 @@ int tuned_splits(Ctx& c, int M, int N, int K, const double* A, int lda, const do
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   g_tuned[key] = best;
+  write_tune_cache(c);
   return best;
 }
 

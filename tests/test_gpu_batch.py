@@ -105,3 +105,58 @@ def test_batch_rejects_repeated_contexts():
     with pytest.raises(rb.RoksError):
         rb.Batch([r, r])
     r.close()
+
+
+_TUNE_CHILD = r"""
+import sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from paper_2605_28637_amd import inputs, roks as rb
+s = sorted(inputs.batch_systems(count=12), key=lambda s: s["nbands"])[0]
+r = rb.Roks(s, flags=rb.FLAG_AUTOTUNE)
+r.set_coeffs(inputs.random_coefficients(r.miller(), s["cell"], r.nb, s["seed"]), True)
+for _ in range(3):
+    r.pcg_step()
+np.save(sys.argv[2], r.get_coeffs())
+r.close()
+"""
+
+
+def test_tuning_cache_file_is_written_and_read(tmp_path):
+    """ROKS_TUNE_CACHE: a first process times the shapes and writes the file
+    (JSON for this device); a second process sharing it makes the same
+    choices and reproduces the first bit for bit; a third, given the file with
+    every choice changed to another valid one, differs at the rounding level
+    only, which shows the choices come from the file."""
+    import json
+    import os
+    import subprocess
+    import sys
+
+    from helpers import ROOT
+    cache = tmp_path / "tune.json"
+    env = dict(os.environ, ROKS_TUNE_CACHE=str(cache))
+
+    def child(out):
+        print("child process", out, flush=True)
+        subprocess.run([sys.executable, "-c", _TUNE_CHILD, ROOT, str(out)], env=env, check=True,
+                       timeout=300)
+        return np.load(out)
+
+    c1 = child(tmp_path / "a.npy")
+    with open(cache) as f:
+        doc = json.load(f)
+    assert doc["arch"].startswith("gfx") and doc["cus"] > 0 and len(doc["wdot"]) > 0
+    assert all(len(e) == 4 and e[3] != 0 for e in doc["wdot"])
+    c2 = child(tmp_path / "b.npy")
+    np.testing.assert_array_equal(c1, c2)
+    for e in doc["wdot"]:
+        v = e[3]
+        e[3] = (1 if v != 1 else 2) if v > 0 else (-1 if v != -1 else -2)
+    with open(cache, "w") as f:
+        f.write('{"arch": "%s", "cus": %d, "wdot": [\n' % (doc["arch"], doc["cus"]))
+        f.write(",\n".join("[%d, %d, %d, %d]" % tuple(e) for e in doc["wdot"]))
+        f.write("]}\n")
+    c3 = child(tmp_path / "c.npy")
+    assert not np.array_equal(c1, c3)
+    assert np.abs(c1 - c3).max() < 1e-8 * np.abs(c1).max()
