@@ -391,6 +391,57 @@ def batch_report(steps=8, workers=8):
             "batched_equals_sequential": bool(same)}
 
 
+def graph_report(reps=20):
+    """The H-application (shell mode, both configurations' operators) of all
+    32 uneven batch systems, FP32 tier, through the allocation-free entry
+    point on one stream: eager calls one system after another, then the same
+    calls captured once into a hipGraph and replayed."""
+    import torch
+    systems = inputs.batch_systems()
+    stream = torch.cuda.Stream()
+    ctxs, outs = [], []
+    for s in systems:
+        r = rb.Roks(s, precision=rb.FP32, stream=stream.cuda_stream)
+        r.set_coeffs(inputs.random_coefficients(r.miller(), s["cell"], r.nb, s["seed"]), True)
+        r.energy_gradient()
+        outs.append(torch.empty((r.nb, r.npw, 2), dtype=torch.float64, device="cuda"))
+        ctxs.append(r)
+    total_bands = sum(r.nb for r in ctxs)
+
+    def eager():
+        for r, o in zip(ctxs, outs):
+            r.apply_h_noalloc_d(None, 0, o.data_ptr())
+
+    eager()
+    torch.cuda.synchronize()
+    ref = [o.clone() for o in outs]
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        eager()
+    torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t0) / reps
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        eager()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / reps
+    same = all(torch.equal(o, r) for o, r in zip(outs, ref))
+    del g
+    for r in ctxs:
+        r.close()
+    return {"systems": len(systems), "bands_total": total_bands, "arithmetic": "fp32 tier",
+            "launches": "roks_apply_h_noalloc_d per system, one stream",
+            "eager_ms_per_round": 1e3 * t_eager, "graph_ms_per_round": 1e3 * t_graph,
+            "eager_band_applies_per_s": total_bands / t_eager,
+            "graph_band_applies_per_s": total_bands / t_graph, "speedup": t_eager / t_graph,
+            "graph_equals_eager": bool(same)}
+
+
 def calibrate_copy(mib=512, reps=3):
     """A plain copy kernel of known size (y = 1.0 * x, FP32, contiguous) for
     scaling the FETCH_SIZE / WRITE_SIZE counters: it reads and writes
@@ -553,6 +604,7 @@ def main():
             out["time_to_converge"] = converge_report(mol)
         if not args.no_batch:
             out["batch"] = batch_report()
+            out["batch_apply_graph"] = graph_report()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(system)
     print(json.dumps(out))
