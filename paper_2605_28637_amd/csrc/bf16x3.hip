@@ -45,12 +45,9 @@ __device__ __forceinline__ void split_one(double x, __bf16& hi, __bf16& lo) {
 
 // rows of X (nrows x K, leading dimension ldx) split into hi / lo rows of
 // length ldo, 8 consecutive k per thread.  mode 0: as they are; 1: with the
-// Gamma-point weights (2 beyond the first two reals, the G = 0 coefficient);
-// 2: the weights and the derivative factor, coefficient q's pair (re, im)
-// becoming g_q (-im, re) (moves -i G_a from the projector onto X)
+// Gamma-point weights (2 beyond the first two reals, the G = 0 coefficient)
 __global__ void __launch_bounds__(256) k_split_rows(const double* __restrict__ X, int ldx, int nrows,
                                                     int K, int ldo, int mode, int vec,
-                                                    const double* __restrict__ g,
                                                     __bf16* __restrict__ hi, __bf16* __restrict__ lo) {
   const int segs = ldo >> 3;
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -69,16 +66,7 @@ __global__ void __launch_bounds__(256) k_split_rows(const double* __restrict__ X
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = k0 + j < K ? x[j] : 0.0;
   }
-  if (mode == 2) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const double gq = k0 + 2 * q < K ? g[(k0 >> 1) + q] : 0.0;
-      const double re = v[2 * q], im = v[2 * q + 1];
-      v[2 * q] = -gq * im;
-      v[2 * q + 1] = gq * re;
-    }
-  }
-  if (mode >= 1) {
+  if (mode == 1) {
 #pragma unroll
     for (int j = 0; j < 8; ++j)
       if (k0 + j >= 2) v[j] *= 2.0;
@@ -263,13 +251,13 @@ __global__ void __launch_bounds__(kQThreads, 4) k_bf3_nt(
 
 __bf16* bf(uint16_t* p) { return reinterpret_cast<__bf16*>(p); }
 
-void split_rows(Ctx& c, const double* X, int ldx, int nrows, int K, int ldo, int mode, const double* g,
-                uint16_t* hi, uint16_t* lo) {
+void split_rows(Ctx& c, const double* X, int ldx, int nrows, int K, int ldo, int mode, uint16_t* hi,
+                uint16_t* lo) {
   const size_t n = (size_t)nrows * (ldo / 8);
   if (n == 0) return;
   const int vec = (reinterpret_cast<uintptr_t>(X) % 16 == 0 && ldx % 2 == 0) ? 1 : 0;
   hipLaunchKernelGGL(k_split_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, X, ldx,
-                     nrows, K, ldo, mode, vec, g, bf(hi), bf(lo));
+                     nrows, K, ldo, mode, vec, bf(hi), bf(lo));
   ROKS_HIP(hipGetLastError());
 }
 
@@ -344,7 +332,7 @@ void ensure_tables(Ctx& c) {
   }
   if (c.bsplit_valid) return;
   const double* B = reinterpret_cast<const double*>(c.d_B);
-  split_rows(c, B, K, c.nproj, K, Kp, 0, nullptr, c.d_bsplit, c.d_bsplit + (size_t)c.nproj * Kp);
+  split_rows(c, B, K, c.nproj, K, Kp, 0, c.d_bsplit, c.d_bsplit + (size_t)c.nproj * Kp);
   split_cols(c, B, K, c.nproj, K, npp, c.d_bsplit_t, c.d_bsplit_t + (size_t)K * npp);
   c.bsplit_valid = true;
 }
@@ -368,7 +356,7 @@ void proj_wdot(Ctx& c, int nrows, const double* X, int ldx, double* C, int ldc) 
                  6.0 * c.nproj * (double)nrows * K);
   uint16_t* xh = c.d_xsplit;
   uint16_t* xl = xh + (size_t)c.nb * Kp;
-  split_rows(c, X, ldx, nrows, K, Kp, 1, nullptr, xh, xl);
+  split_rows(c, X, ldx, nrows, K, Kp, 1, xh, xl);
   product(c, c.nproj, nrows, Kp, c.d_bsplit, c.d_bsplit + (size_t)c.nproj * Kp, Kp, xh, xl, Kp, C, ldc,
           nullptr, 0, 1.0, 0.0, true);
 }
@@ -392,7 +380,7 @@ void proj_field(Ctx& c, const double* DPw, int lddp, const double* X, int ldx, d
   uint16_t* al = ah + (size_t)c.nproj * nbp;
   uint16_t* bh = al + (size_t)c.nproj * nbp;
   uint16_t* bl = bh + (size_t)K * nbp;
-  split_rows(c, DPw, lddp, c.nproj, nb, nbp, 0, nullptr, ah, al);
+  split_rows(c, DPw, lddp, c.nproj, nb, nbp, 0, ah, al);
   split_cols(c, X, ldx, nb, K, nbp, bh, bl);
   product(c, c.nproj, K, nbp, ah, al, nbp, bh, bl, nbp, Phi, K, nullptr, 0, 1.0, 0.0, false);
 }

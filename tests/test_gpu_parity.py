@@ -41,6 +41,9 @@ CASES = {
     "overlap_molecule": lambda: inputs.with_overlap(small_molecule(), 0.4),
     "overlap_oxide_cell": lambda: inputs.with_overlap(
         inputs.oxide_vacancy(reps=1, N=24, nb=16), 0.3),
+    # the overlap with the other functionals: PBE, and a hybrid on PBE
+    "overlap_pbe": lambda: dict(inputs.with_overlap(small_molecule(), 0.4), xc="pbe"),
+    "overlap_pbe0": lambda: dict(inputs.with_overlap(inputs.tiny_cell(), 0.5), xc="pbe", exx=0.25),
 }
 
 
