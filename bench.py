@@ -442,6 +442,18 @@ def graph_report(reps=20):
             "graph_equals_eager": bool(same)}
 
 
+def graph_report_child(timeout=600):
+    """graph_report in a child process whose PyTorch GPU context is created
+    before the library's (this process has the library's runtime already)."""
+    import subprocess
+    code = ("import json, sys; sys.path.insert(0, %r); import bench; bench.init_torch_gpu(); "
+            "print(json.dumps(bench.graph_report()))" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=timeout)
+    if r.returncode != 0:
+        return {"error": r.stderr.strip().splitlines()[-1] if r.stderr.strip() else "failed"}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def calibrate_copy(mib=512, reps=3):
     """A plain copy kernel of known size (y = 1.0 * x, FP32, contiguous) for
     scaling the FETCH_SIZE / WRITE_SIZE counters: it reads and writes
@@ -520,6 +532,14 @@ def measure(system, precision, steps, warmup, table_steps=None):
             "kernels": {k: dict(v, roofline_frac=(roofs[k] or {}).get("frac"))
                         for k, v in kernels.items()},
             "h_apply_pipeline": pipeline}
+
+
+def init_torch_gpu():
+    """PyTorch carries its own HIP runtime: its GPU context must exist before
+    the library's when a leg hands it torch streams or buffers."""
+    import torch
+    torch.zeros(1, device="cuda")
+    torch.cuda.synchronize()
 
 
 def main():
@@ -604,7 +624,7 @@ def main():
             out["time_to_converge"] = converge_report(mol)
         if not args.no_batch:
             out["batch"] = batch_report()
-            out["batch_apply_graph"] = graph_report()
+            out["batch_apply_graph"] = graph_report_child()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(system)
     print(json.dumps(out))
