@@ -241,6 +241,7 @@ struct Ctx {
   double* h_force = nullptr;     // [natoms][3] forces (nonlocal kernel writes them)
   double* hd_scal = nullptr;     // device view of h_scal
   double* hd_stage = nullptr;    // device view of h_stage (kernels write it directly)
+  bool normD_pending = false;    // ||D||_1 queued into h_stage, not yet synchronised
   int32_t* hd_flag = nullptr;    // device view of h_flag
   double* hd_force = nullptr;    // device view of h_force
   double* d_m4 = nullptr;
@@ -613,6 +614,7 @@ T* dalloc(Ctx& c, size_t count) {
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 constexpr int kStage = 16;  // scalar slots ahead of the per-band ones in h_stage
+constexpr int kStageNormD = 3;  // h_stage slot of ||D||_1 for the line search
 
 }  // namespace roks
 

@@ -31,9 +31,14 @@ void expm(Ctx& c, double delta, const double* D, double* U) {
   const int n = c.nb;
   const size_t nn = (size_t)n * n;
   axpby(c, nn, delta, D, 0.0, nullptr, c.d_m1);
-  matrix_norm1(c, c.d_m1, n, c.d_bandv);
-  double nrm = 0.0;
-  to_host(c, &nrm, c.d_bandv, sizeof(double));
+  // ||delta D||_1 = |delta| ||D||_1: the norm of the search's D was queued by
+  // prepare_line_search into the pinned mirror and is read after the
+  // synchronisation that follows it (one more only if D changed since)
+  if (c.normD_pending) {
+    sync(c);
+    c.normD_pending = false;
+  }
+  const double nrm = std::fabs(delta) * c.h_stage[kStageNormD];
   ROKS_CHECK(std::isfinite(nrm), ROKS_ERR_NAN, "non-finite rotation generator");
   int s = 0, m = 30, best = 1 << 30;
   for (int sq = 0; sq <= 60; ++sq) {
@@ -91,6 +96,11 @@ struct Trial {
 void prepare_line_search(Ctx& c, bool first) {
   const int nb = c.nb, K = 2 * c.npw;
   gemm_wdot(c, nb, nb, K, dbl(c.d_S), K, dbl(c.d_S), K, c.d_SS, nb, 1.0, 0.0, true);
+  if (!expm_in_lds(c)) {
+    // ||D||_1 for the exponentials of the trials, straight into the mirror
+    matrix_norm1(c, c.d_D, nb, c.hd_stage + kStageNormD);
+    c.normD_pending = true;
+  }
   if (c.nproj > 0) {
     // P0 <- the current projections by trading buffers: the trials write d_P,
     // so P (with the densities and potentials, which the trials overwrite too)
@@ -538,6 +548,7 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     directions_async(0.0, true);
     prepare();
     sync(c);
+    c.normD_pending = false;
     pg = pg_host();
     beta = pg / c.pg_old;
     dE0 = dE_host();
@@ -547,6 +558,7 @@ void pcg_step(Ctx& c, roks_step_info* info) {
     directions_async(0.0, false);
     prepare();
     sync(c);
+    c.normD_pending = false;
     pg = pg_host();
     dE0 = dE_host();
   }
