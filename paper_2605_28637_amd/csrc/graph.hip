@@ -1,0 +1,518 @@
+// Graph mode: CG iterations whose every decision is taken on the device, so
+// that k of them form one fixed launch sequence, captured once as a HIP graph
+// and replayed (one context, or every context of a batch in one graph).
+//
+// The iteration is roks_pcg_step's (Eqs. orbital_update, cg_search,
+// prec_grad_I, prec_k and the conjugated rotation; readings R1-R7, R9) with
+// the scalars that steer it kept in a device state block instead of host
+// variables: the energy of the orbitals (assembled on the device in the
+// host's order of sums), the Fletcher-Reeves ratio and the directional
+// derivative (the restart to steepest descent when it is not negative), the
+// trial step (the previous step length), the parabola's step, the choice of
+// the lower trial and its acceptance below E(0), and the new step length.
+// Each trial is formed as on the host (Cholesky of I + t^2 <S|S>, exp(t D),
+// M^T (psi + t S)) with the scaled inputs prepared by small kernels that read
+// t, so the existing launchers run with constant arguments; the projections
+// of a trial are recomputed from its orbitals.  The commit (new orbitals,
+// carried directions S_old = M S, D_old = U^T D U) is a set of copies made
+// only when the device accepted the step, so a rejected step leaves the state
+// as it was and the iterations after it repeat the same rejected search.
+// What the host path does beyond this (halving the trial step, the steepest
+// descent retry after a failed search) is left to it: the caller sees the
+// first rejected iteration and continues with roks_pcg_step.
+//
+// Scope (checked before capture): up to 78 bands (the single-workgroup
+// Cholesky and exponential), FP64 or FP32 tier, LDA or PBE without exact
+// exchange, no overlap coefficients, no network, no recording, no
+// canonicalisation, no periodic restart, no autotuning.
+#include <cmath>
+#include <cstring>
+
+#include "roks_internal.h"
+
+namespace roks {
+
+namespace {
+
+// slots of the device state block
+enum : int {
+  gE0 = 0, gEt, gEts, gT, gTs, gDt, gPg, gPgOld, gBeta, gDE0, gDelta, gE1, gHaveOld, gAccept,
+  gBest, gOkT, gOkTs, gHalt, gNormG, gRestart, gNSlots
+};
+constexpr int kRecLen = 8;  // per iteration: E0, E1, delta, beta, dE0, accepted, |g_I|, restarted
+
+__device__ inline double mul(double a, double b) { return __dmul_rn(a, b); }
+__device__ inline double add(double a, double b) { return __dadd_rn(a, b); }
+__device__ inline double sub(double a, double b) { return __dsub_rn(a, b); }
+__device__ inline double dvd(double a, double b) { return __ddiv_rn(a, b); }
+
+__global__ void k_g_begin(double* __restrict__ gs) {
+  if (threadIdx.x || blockIdx.x) return;
+  gs[gAccept] = 0.0;
+  gs[gBest] = 0.0;
+}
+
+// E = sum_L c_L (T_L + NL_L + ext_L + H_L + xc_L) from the reduced partial
+// sums, in the host's order (assemble_energies); a failed Cholesky (flag)
+// makes the trial's energy +inf
+__global__ void k_g_energy(const double* __restrict__ scal, int nb, int nconf,
+                           const double* __restrict__ focc, double c0, double c1, double dv,
+                           int energy_only, const int32_t* __restrict__ flag, double* __restrict__ gs,
+                           int slot, int okslot) {
+  if (threadIdx.x || blockIdx.x) return;
+  const double* kin = scal + 16;
+  const double* enl = scal + 16 + nb;
+  double E = 0.0;
+  for (int L = 0; L < nconf; ++L) {
+    double k = 0.0, nl = 0.0;
+    for (int n = 0; n < nb; ++n) {
+      const double f = focc[L * nb + n];
+      k = add(k, mul(f, kin[n]));
+      nl = add(nl, mul(f, enl[n]));
+    }
+    const double xc = mul(dv, scal[3 * L + 0]);
+    const double ext = mul(dv, scal[3 * L + 1]);
+    const double har = mul(mul(0.5, dv), energy_only ? scal[6 + L] : scal[3 * L + 2]);
+    const double EL = add(add(add(add(k, nl), ext), har), xc);
+    E = add(E, mul(L == 0 ? c0 : c1, EL));
+  }
+  const bool ok = !flag || flag[0] == 0;
+  if (!ok || !isfinite(E)) E = INFINITY;
+  gs[slot] = E;
+  if (okslot >= 0) gs[okslot] = ok ? 1.0 : 0.0;
+}
+
+// sum_n x[n] in band order
+__device__ inline double band_sum(const double* __restrict__ x, int nb) {
+  double s = 0.0;
+  for (int n = 0; n < nb; ++n) s = add(s, x[n]);
+  return s;
+}
+
+// <p|g> and the Fletcher-Reeves ratio; the directional derivative of the
+// directions S = p + beta w, D = A + beta D_old from the band sums of p and
+// w against g_I and the rotation terms; beta = 0 when it is not a descent
+// direction; the first trial step is the step length kept from before
+__global__ void k_g_beta(const double* __restrict__ pgb, const double* __restrict__ asymA,
+                         const double* __restrict__ wgb, const double* __restrict__ asymD,
+                         const double* __restrict__ gg, int nb, double* __restrict__ gs) {
+  if (threadIdx.x || blockIdx.x) return;
+  const double spg = band_sum(pgb, nb);
+  const double swg = band_sum(wgb, nb);
+  const double pg = add(spg, mul(0.5, asymA[0]));
+  double beta = 0.0;
+  if (gs[gHaveOld] != 0.0 && gs[gPgOld] != 0.0) beta = dvd(pg, gs[gPgOld]);
+  double dE0 = add(mul(2.0, add(spg, mul(beta, swg))), add(asymA[0], mul(beta, asymD[0])));
+  const bool restart = beta != 0.0 && dE0 >= 0.0;
+  if (restart) {
+    beta = 0.0;
+    dE0 = add(mul(2.0, spg), asymA[0]);
+  }
+  gs[gRestart] = restart ? 1.0 : 0.0;
+  gs[gPg] = pg;
+  gs[gBeta] = beta;
+  gs[gDE0] = dE0;
+  gs[gT] = gs[gDt];
+  gs[gNormG] = sqrt(fmax(0.0, band_sum(gg, nb)));
+}
+
+// out = x + gs[slot] y
+__global__ void __launch_bounds__(256) k_g_axpy(size_t n, const double* __restrict__ x,
+                                                const double* __restrict__ y, double* __restrict__ out,
+                                                const double* __restrict__ gs, int slot) {
+  const double b = gs[slot];
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    double v = 1.0 * x[i];
+    v += b * y[i];
+    out[i] = v;
+  }
+}
+
+// the scaled inputs of a trial at t = gs[slot]: gram = t^2 <S|S> + I,
+// Dt = t D (n x n), St = t S (m values)
+__global__ void __launch_bounds__(256) k_g_prep(int nb, const double* __restrict__ SS,
+                                                double* __restrict__ gram, const double* __restrict__ D,
+                                                double* __restrict__ Dt, size_t m,
+                                                const double* __restrict__ S, double* __restrict__ St,
+                                                const double* __restrict__ gs, int slot) {
+  const double t = gs[slot];
+  const double t2 = t * t;
+  const size_t nn = (size_t)nb * nb;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nn + m;
+       i += (size_t)gridDim.x * blockDim.x) {
+    if (i < nn) {
+      const int r = (int)(i / nb), q = (int)(i - (size_t)r * nb);
+      gram[i] = t2 * SS[i] + (r == q ? 1.0 : 0.0);
+      Dt[i] = t * D[i];
+    } else {
+      St[i - nn] = t * S[i - nn];
+    }
+  }
+}
+
+// reading R7 on the device: the parabola through E(0), E'(0), E(t)
+__global__ void k_g_parabola(double* __restrict__ gs) {
+  if (threadIdx.x || blockIdx.x) return;
+  const double t = gs[gT], E0 = gs[gE0], dE0 = gs[gDE0];
+  double ts;
+  if (gs[gOkT] != 0.0) {
+    const double curv = dvd(sub(sub(gs[gEt], E0), mul(dE0, t)), mul(t, t));
+    ts = curv > 0.0 ? fmin(dvd(-dE0, mul(2.0, curv)), mul(4.0, t)) : mul(2.0, t);
+  } else {
+    ts = mul(0.5, t);
+  }
+  gs[gTs] = ts;
+}
+
+// the lower trial, kept if it lies below E(0) and the direction descends
+__global__ void k_g_accept(double* __restrict__ gs) {
+  if (threadIdx.x || blockIdx.x) return;
+  const double Et = gs[gEt], Ets = gs[gEts];
+  const int best = Ets <= Et ? 1 : 0;
+  const double Eb = best ? Ets : Et;
+  const bool acc = gs[gHalt] == 0.0 && gs[gDE0] < 0.0 && Eb < gs[gE0];
+  gs[gBest] = best;
+  gs[gAccept] = acc ? 1.0 : 0.0;
+  gs[gDelta] = best ? gs[gTs] : gs[gT];
+  gs[gE1] = acc ? Eb : gs[gE0];
+}
+
+// dst = (best ? t1 : t0) when the step is accepted
+__global__ void __launch_bounds__(256) k_g_take(size_t n, const double* __restrict__ t0,
+                                                const double* __restrict__ t1, double* __restrict__ dst,
+                                                const double* __restrict__ gs, int need_accept) {
+  if (need_accept && gs[gAccept] == 0.0) return;
+  const double* src = gs[gBest] != 0.0 ? t1 : t0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// the carried state of an accepted step and the iteration's record; the
+// first rejected step halts the rest (they commit nothing)
+__global__ void k_g_finish(double* __restrict__ gs, double* __restrict__ rec,
+                           double* __restrict__ mirror, double dt_min, double dt_max) {
+  if (threadIdx.x || blockIdx.x) return;
+  const bool acc = gs[gAccept] != 0.0;
+  if (acc) {
+    gs[gPgOld] = gs[gPg];
+    gs[gHaveOld] = 1.0;
+    gs[gDt] = fmin(dt_max, fmax(dt_min, gs[gDelta]));
+  } else {
+    gs[gHalt] = 1.0;
+  }
+  rec[0] = gs[gE0];
+  rec[1] = gs[gE1];
+  rec[2] = acc ? gs[gDelta] : 0.0;
+  rec[3] = gs[gBeta];
+  rec[4] = gs[gDE0];
+  rec[5] = acc ? 1.0 : 0.0;
+  rec[6] = gs[gNormG];
+  rec[7] = gs[gRestart];
+  for (int i = 0; i < gNSlots; ++i) mirror[i] = gs[i];
+}
+
+size_t grid_for(size_t n) { return std::min<size_t>(4096, (n + 255) / 256); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// one iteration, every launch on c.stream, no host reads
+// ---------------------------------------------------------------------------
+static void graph_trial(Ctx& c, int tslot, double2* out, double* M, double* U, bool energy_only,
+                        int eslot, int okslot) {
+  const int nb = c.nb, K = 2 * c.npw;
+  const size_t band = (size_t)nb * c.npw, nn = (size_t)nb * nb;
+  hipLaunchKernelGGL(k_g_prep, dim3((unsigned)grid_for(nn + 2 * band)), dim3(256), 0, c.stream, nb,
+                     c.d_SS, c.d_gram, c.d_D, c.d_m1, 2 * band, dbl(c.d_S), dbl(c.d_Pt), c.d_gstate, tslot);
+  ROKS_HIP(hipGetLastError());
+  launch_chol_expm_lds(c, c.d_gram, 1.0, 0.0, c.d_Linv, c.d_flag, c.d_m1, 1.0, U);
+  gemm_small(c, nb, nb, nb, U, nb, true, c.d_Linv, nb, false, M, nb, 1.0, 0.0);
+  gemm_expand_sum(c, nb, K, nb, M, nb, true, dbl(c.d_psi), dbl(c.d_Pt), 1.0, K, dbl(out), K, dbl(out),
+                  K, 1.0, 0.0);
+  compute_potentials_async(c, out, false, energy_only);
+  hipLaunchKernelGGL(k_g_energy, dim3(1), dim3(64), 0, c.stream, c.d_scal, nb, c.nconf, c.d_gfocc,
+                     c.cL[0], c.cL[1], c.omega / (double)c.ntot, energy_only ? 1 : 0, c.d_flag,
+                     c.d_gstate, eslot, okslot);
+  ROKS_HIP(hipGetLastError());
+}
+
+static void graph_step(Ctx& c, int step) {
+  const int nb = c.nb, K = 2 * c.npw;
+  const size_t band = (size_t)nb * c.npw, nn = (size_t)nb * nb;
+  double* gs = c.d_gstate;
+  hipLaunchKernelGGL(k_g_begin, dim3(1), dim3(64), 0, c.stream, gs);
+  ROKS_HIP(hipGetLastError());
+  // energy, Y = F^n|n>, theta, g_I = (1 - P) Y, R / kappa / A
+  compute_potentials_async(c, c.d_psi, false, false);
+  hipLaunchKernelGGL(k_g_energy, dim3(1), dim3(64), 0, c.stream, c.d_scal, nb, c.nconf, c.d_gfocc,
+                     c.cL[0], c.cL[1], c.omega / (double)c.ntot, 0, static_cast<const int32_t*>(nullptr),
+                     gs, (int)gE0, -1);
+  ROKS_HIP(hipGetLastError());
+  c.potentials_valid = true;  // the apply reads the projections just formed
+  apply_operator(c, c.d_psi, 0, c.d_Y, true);
+  gemm_wdot(c, nb, nb, K, dbl(c.d_psi), K, dbl(c.d_Y), K, c.d_theta, nb, 1.0, 0.0, true);
+  gemm_expand_to(c, nb, K, nb, c.d_theta, nb, false, dbl(c.d_psi), K, dbl(c.d_Y), K, dbl(c.d_gI), K,
+                 -1.0, 1.0);
+  launch_subspace(c, nullptr);
+  // p = (1 - P) K g_I and the projected carried direction (S_old is zero
+  // until a step has been accepted)
+  band_dots2(c, c.d_gI, c.d_gI, nb, c.d_bandv + nb, c.d_bandv, nullptr, nullptr);
+  const double* bandw = (c.flags & ROKS_FLAG_WEIGHT_PRECOND) ? c.d_kinw_shell : nullptr;
+  launch_teter(c, c.d_bandv, c.d_bandv + nb, c.d_gI, bandw, c.d_w1);
+  gemm_wdot(c, nb, 2 * nb, K, dbl(c.d_psi), K, dbl(c.d_w1), K, c.d_m12, 2 * nb, 1.0, 0.0, true);
+  gemm_expand_to(c, nb, K, nb, c.d_m12, 2 * nb, false, dbl(c.d_psi), K, dbl(c.d_w1), K, dbl(c.d_p), K,
+                 -1.0, 1.0);
+  band_dots_asym(c, c.d_p, c.d_gI, nb, c.d_cg + 8, nullptr, c.d_A, c.d_theta, c.d_cg, nullptr);
+  gemm_expand_to(c, nb, K, nb, c.d_m12 + nb, 2 * nb, false, dbl(c.d_psi), K, dbl(c.d_Sold), K,
+                 dbl(c.d_w1), K, -1.0, 1.0);
+  double* wgb = gs + gNSlots;          // [nb] <w_n|g_n>
+  double* asymD = gs + gNSlots + nb;   // [1] sum D_old (theta - theta^T)
+  band_dots_asym(c, c.d_w1, c.d_gI, nb, wgb, nullptr, c.d_Dold, c.d_theta, asymD, nullptr);
+  hipLaunchKernelGGL(k_g_beta, dim3(1), dim3(64), 0, c.stream, c.d_cg + 8, c.d_cg, wgb, asymD,
+                     c.d_bandv + nb, nb, gs);
+  ROKS_HIP(hipGetLastError());
+  // S = p + beta S_old', D = A + beta D_old
+  hipLaunchKernelGGL(k_g_axpy, dim3((unsigned)grid_for(2 * band)), dim3(256), 0, c.stream, 2 * band,
+                     dbl(c.d_p), dbl(c.d_w1), dbl(c.d_S), gs, (int)gBeta);
+  hipLaunchKernelGGL(k_g_axpy, dim3((unsigned)grid_for(nn)), dim3(256), 0, c.stream, nn, c.d_A, c.d_Dold,
+                     c.d_D, gs, (int)gBeta);
+  ROKS_HIP(hipGetLastError());
+  gemm_wdot(c, nb, nb, K, dbl(c.d_S), K, dbl(c.d_S), K, c.d_SS, nb, 1.0, 0.0, true);
+  // the two trials of reading R7's first attempt
+  graph_trial(c, gT, c.d_trial[0], c.d_M, c.d_U, true, gEt, gOkT);
+  hipLaunchKernelGGL(k_g_parabola, dim3(1), dim3(64), 0, c.stream, gs);
+  ROKS_HIP(hipGetLastError());
+  graph_trial(c, gTs, c.d_trial[1], c.d_Mkeep, c.d_Ukeep, false, gEts, gOkTs);
+  hipLaunchKernelGGL(k_g_accept, dim3(1), dim3(64), 0, c.stream, gs);
+  ROKS_HIP(hipGetLastError());
+  // commit when accepted: psi, then S_old = M^T S and D_old = U^T D U of the
+  // trial kept (formed in scratch, copied only when accepted)
+  hipLaunchKernelGGL(k_g_take, dim3((unsigned)grid_for(2 * band)), dim3(256), 0, c.stream, 2 * band,
+                     dbl(c.d_trial[0]), dbl(c.d_trial[1]), dbl(c.d_psi), gs, 1);
+  hipLaunchKernelGGL(k_g_take, dim3((unsigned)grid_for(nn)), dim3(256), 0, c.stream, nn, c.d_M, c.d_Mkeep,
+                     c.d_m3, gs, 0);
+  hipLaunchKernelGGL(k_g_take, dim3((unsigned)grid_for(nn)), dim3(256), 0, c.stream, nn, c.d_U, c.d_Ukeep,
+                     c.d_m4, gs, 0);
+  ROKS_HIP(hipGetLastError());
+  gemm_expand(c, nb, K, nb, c.d_m3, nb, true, dbl(c.d_S), K, dbl(c.d_trial[0]), K, 1.0, 0.0);
+  hipLaunchKernelGGL(k_g_take, dim3((unsigned)grid_for(2 * band)), dim3(256), 0, c.stream, 2 * band,
+                     dbl(c.d_trial[0]), dbl(c.d_trial[0]), dbl(c.d_Sold), gs, 1);
+  gemm_small(c, nb, nb, nb, c.d_D, nb, false, c.d_m4, nb, false, c.d_m2, nb, 1.0, 0.0);
+  gemm_small(c, nb, nb, nb, c.d_m4, nb, true, c.d_m2, nb, false, c.d_m1, nb, 1.0, 0.0);
+  hipLaunchKernelGGL(k_g_take, dim3((unsigned)grid_for(nn)), dim3(256), 0, c.stream, nn, c.d_m1, c.d_m1,
+                     c.d_Dold, gs, 1);
+  hipLaunchKernelGGL(k_g_finish, dim3(1), dim3(64), 0, c.stream, gs, c.hd_grec + (size_t)step * kRecLen,
+                     c.hd_gmirror, kDtMin, kDtMax);
+  ROKS_HIP(hipGetLastError());
+  c.potentials_valid = false;
+}
+
+// ---------------------------------------------------------------------------
+// host side: checks, buffers, capture, replay
+// ---------------------------------------------------------------------------
+namespace {
+
+void graph_check(const Ctx& c) {
+  ROKS_CHECK(c.have_orbitals, ROKS_ERR_STATE, "no orbitals set");
+  ROKS_CHECK(expm_in_lds(c), ROKS_ERR_STATE,
+             "graph mode takes at most 78 bands (the single-workgroup Cholesky and exponential)");
+  ROKS_CHECK(!c.bf3 && (c.prec == ROKS_FP64 || c.prec == ROKS_FP32), ROKS_ERR_STATE,
+             "graph mode runs in the FP64 or FP32 tier");
+  ROKS_CHECK(c.exx == 0.0 && !c.has_q && !c.mlp && c.rec_max == 0, ROKS_ERR_STATE,
+             "graph mode excludes exact exchange, overlap coefficients, a network and recording");
+  ROKS_CHECK(c.restart_period == 0, ROKS_ERR_STATE, "graph mode runs without periodic restarts");
+  ROKS_CHECK(!(c.flags & (ROKS_FLAG_CANONICALIZE | ROKS_FLAG_AUTOTUNE)), ROKS_ERR_STATE,
+             "graph mode excludes canonicalisation and autotuning");
+}
+
+void graph_buffers(Ctx& c, int k) {
+  const int nb = c.nb;
+  if (!c.d_gstate) {
+    c.d_gstate = dalloc<double>(c, gNSlots + nb + 8);
+    std::vector<double> focc((size_t)c.nconf * nb);
+    for (int L = 0; L < c.nconf; ++L)
+      for (int n = 0; n < nb; ++n)
+        focc[(size_t)L * nb + n] =
+            (double)c.occ[(L * 2 + 0) * nb + n] + (double)c.occ[(L * 2 + 1) * nb + n];
+    c.d_gfocc = dalloc<double>(c, focc.size());
+    ROKS_HIP(hipMemcpyAsync(c.d_gfocc, focc.data(), focc.size() * sizeof(double), hipMemcpyHostToDevice,
+                            c.stream));
+    ROKS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_gmirror), gNSlots * sizeof(double),
+                           hipHostMallocMapped | hipHostMallocCoherent));
+    ROKS_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c.hd_gmirror), c.h_gmirror, 0));
+    ROKS_HIP(hipStreamSynchronize(c.stream));
+  }
+  if (k > c.grec_cap) {
+    free_graph(c);  // the records move: capture again
+    if (c.h_grec) (void)hipHostFree(c.h_grec);
+    c.h_grec = c.hd_grec = nullptr;
+    c.grec_cap = 0;
+    ROKS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_grec), (size_t)k * kRecLen * sizeof(double),
+                           hipHostMallocMapped | hipHostMallocCoherent));
+    ROKS_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c.hd_grec), c.h_grec, 0));
+    c.grec_cap = k;
+  }
+}
+
+// the host CG state into the device block; halt: nothing may be committed
+void graph_load_state(Ctx& c, bool halt) {
+  double s[gNSlots] = {0};
+  s[gDt] = c.dt;
+  s[gPgOld] = c.pg_old;
+  s[gHaveOld] = c.have_old ? 1.0 : 0.0;
+  s[gHalt] = halt ? 1.0 : 0.0;
+  ROKS_HIP(hipMemcpyAsync(c.d_gstate, s, sizeof s, hipMemcpyHostToDevice, c.stream));
+  if (!c.have_old) {
+    // no carried direction: S_old and D_old enter with beta = 0, as zeros
+    ROKS_HIP(hipMemsetAsync(c.d_Sold, 0, (size_t)c.nb * c.npw * sizeof(double2), c.stream));
+    ROKS_HIP(hipMemsetAsync(c.d_Dold, 0, (size_t)c.nb * c.nb * sizeof(double), c.stream));
+  }
+  ROKS_HIP(hipStreamSynchronize(c.stream));
+}
+
+void* const* current_bufs(const Ctx& c, void* out[5]) {
+  out[0] = c.d_psi;
+  out[1] = c.d_trial[0];
+  out[2] = c.d_trial[1];
+  out[3] = c.d_P;
+  out[4] = c.d_P0;
+  return out;
+}
+
+// the graph's buffers are the context's, possibly traded by the host CG
+// since: {orbitals, trials} and {P, P0} as sets
+bool same_sets(void* const* a, void* const* b) {
+  auto in = [](void* p, void* const* set, int n) {
+    for (int i = 0; i < n; ++i)
+      if (set[i] == p) return true;
+    return false;
+  };
+  for (int i = 0; i < 3; ++i)
+    if (!in(a[i], b, 3)) return false;
+  for (int i = 3; i < 5; ++i)
+    if (!in(a[i], b + 3, 2)) return false;
+  return true;
+}
+
+// put the orbitals in the buffer the graph reads them from and the pointers
+// back in the captured arrangement
+void restore_bufs(Ctx& c) {
+  void** g = c.graph_bufs;
+  if (c.d_psi != g[0])
+    ROKS_HIP(hipMemcpyAsync(g[0], c.d_psi, (size_t)c.nb * c.npw * sizeof(double2),
+                            hipMemcpyDeviceToDevice, c.stream));
+  c.d_psi = static_cast<double2*>(g[0]);
+  c.d_trial[0] = static_cast<double2*>(g[1]);
+  c.d_trial[1] = static_cast<double2*>(g[2]);
+  c.d_P = static_cast<double*>(g[3]);
+  c.d_P0 = static_cast<double*>(g[4]);
+}
+
+void capture(Ctx& c, int k) {
+  free_graph(c);
+  // one iteration outside the capture that commits nothing: first-use work
+  // of every launcher (tables, LDS limits) happens here
+  graph_load_state(c, true);
+  graph_step(c, 0);
+  ROKS_HIP(hipStreamSynchronize(c.stream));
+  hipStream_t st = nullptr;
+  ROKS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  const hipStream_t own = c.stream;
+  const bool timing = c.timing;
+  c.stream = st;
+  c.timing = false;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    try {
+      for (int i = 0; i < k; ++i) graph_step(c, i);
+    } catch (...) {
+      (void)hipStreamEndCapture(st, &g);
+      if (g) (void)hipGraphDestroy(g);
+      c.stream = own;
+      c.timing = timing;
+      (void)hipStreamDestroy(st);
+      throw;
+    }
+    e = hipStreamEndCapture(st, &g);
+  }
+  c.stream = own;
+  c.timing = timing;
+  (void)hipStreamDestroy(st);
+  ROKS_HIP(e);
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  ROKS_HIP(e);
+  c.graph_exec = ex;
+  c.graph_k = k;
+  c.graph_prec = c.prec;
+  c.graph_flags = c.flags;
+  current_bufs(c, c.graph_bufs);
+}
+
+}  // namespace
+
+void free_graph(Ctx& c) {
+  if (c.graph_exec) (void)hipGraphExecDestroy(c.graph_exec);
+  c.graph_exec = nullptr;
+  c.graph_k = 0;
+}
+
+void free_graph_mode(Ctx& c) {
+  free_graph(c);
+  for (void* h : {(void*)c.h_gmirror, (void*)c.h_grec})
+    if (h) (void)hipHostFree(h);
+  c.h_gmirror = c.hd_gmirror = c.h_grec = c.hd_grec = nullptr;
+  c.grec_cap = 0;
+  c.d_gstate = c.d_gfocc = nullptr;  // freed with the other allocations
+}
+
+int graph_steps(Ctx& c, int k, roks_step_info* info) {
+  ROKS_CHECK(k >= 1 && k <= 100000, ROKS_ERR_ARG, "k must be 1 .. 100000");
+  graph_check(c);
+  reset_diis(c);  // the kept DIIS iterates do not lead to these orbitals
+  graph_buffers(c, k);
+  void* cur[5];
+  current_bufs(c, cur);
+  const bool reuse = c.graph_exec && c.graph_k == k && c.graph_prec == c.prec &&
+                     c.graph_flags == c.flags && same_sets(cur, c.graph_bufs);
+  if (reuse)
+    restore_bufs(c);
+  else
+    capture(c, k);
+  c.potentials_valid = false;
+  graph_load_state(c, false);
+  ROKS_HIP(hipGraphLaunch(c.graph_exec, c.stream));
+  ROKS_HIP(hipStreamSynchronize(c.stream));
+  int acc = 0;
+  while (acc < k && c.h_grec[(size_t)acc * kRecLen + 5] != 0.0) ++acc;
+  if (info) {
+    for (int i = 0; i < k; ++i) {
+      const double* r = c.h_grec + (size_t)i * kRecLen;
+      roks_step_info s{};
+      s.E0 = r[0];
+      s.E1 = r[1];
+      s.delta = r[2];
+      s.beta = r[3];
+      s.dE0 = r[4];
+      s.stalled = r[5] != 0.0 ? 0 : 1;
+      s.norm_gI = r[6];
+      s.restarted = r[7] != 0.0 ? 1 : 0;
+      s.evaluations = i <= acc ? 2 : 0;
+      s.iteration = c.iteration + std::min(i + 1, acc);
+      info[i] = s;
+    }
+  }
+  if (acc > 0) {
+    const double* m = c.h_gmirror;
+    c.dt = m[gDt];
+    c.pg_old = m[gPgOld];
+    c.have_old = true;
+    c.iteration += acc;
+  }
+  c.potentials_valid = false;
+  return acc;
+}
+
+}  // namespace roks
