@@ -391,6 +391,66 @@ def batch_report(steps=8, workers=8):
             "batched_equals_sequential": bool(same)}
 
 
+def cg_graph_report(steps=8, workers=8):
+    """CG iterations in graph mode (every decision on the device, k
+    iterations captured once per context and replayed) against the same
+    iterations driven from the host, FP32 tier: the uneven batch members of
+    at most 78 bands (one graph per member, replayed on the workers'
+    streams), and one of them alone on its own stream."""
+    systems = [s for s in inputs.batch_systems() if s["nbands"] <= 78]
+
+    def make():
+        out = []
+        for s in systems:
+            r = rb.Roks(s, precision=rb.FP32)
+            r.set_coeffs(inputs.random_coefficients(r.miller(), s["cell"], r.nb, s["seed"]), True)
+            out.append(r)
+        return out
+    total_bands = sum(s["nbands"] for s in systems)
+    res = {"systems": len(systems), "bands_total": total_bands,
+           "grids": sorted({s["grid"][0] for s in systems}), "steps_each": steps,
+           "workers": workers, "arithmetic": "fp32 tier"}
+    host = make()
+    b = rb.Batch(host, workers=workers)
+    b.steps(steps)  # warm-up
+    t0 = time.perf_counter()
+    st = b.steps(steps)
+    t_host = time.perf_counter() - t0
+    b.close()
+    graph = make()
+    b = rb.Batch(graph, workers=workers)
+    b.graph_steps(steps)  # capture (and one replay)
+    t0 = time.perf_counter()
+    st2, acc = b.graph_steps(steps)
+    t_graph = time.perf_counter() - t0
+    b.close()
+    res.update({"host_seconds": t_host, "graph_seconds": t_graph,
+                "host_band_applies_per_s": total_bands * steps / t_host,
+                "graph_band_applies_per_s": total_bands * steps / t_graph,
+                "speedup": t_host / t_graph,
+                "all_ok": all(x == 0 for x in st + st2),
+                "graph_steps_accepted": int(sum(acc)), "graph_steps_run": steps * len(systems)})
+    # one member alone: host steps against graph replays on its own stream
+    one_h, one_g = host[0], graph[0]
+    for _ in range(2):
+        one_h.pcg_step()
+    one_h.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_h.pcg_step()
+    one_h.synchronize()
+    t1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    a1, _ = one_g.graph_steps(steps)
+    t2 = time.perf_counter() - t0
+    res["single"] = {"grid": systems[0]["grid"][0], "nbands": systems[0]["nbands"],
+                     "host_ms_per_step": 1e3 * t1 / steps, "graph_ms_per_step": 1e3 * t2 / steps,
+                     "accepted": a1}
+    for r in host + graph:
+        r.close()
+    return res
+
+
 def graph_report(reps=20):
     """The H-application (shell mode, both configurations' operators) of all
     32 uneven batch systems, FP32 tier, through the allocation-free entry
@@ -625,6 +685,7 @@ def main():
         if not args.no_batch:
             out["batch"] = batch_report()
             out["batch_apply_graph"] = graph_report_child()
+            out["batch_cg_graph"] = cg_graph_report()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(system)
     print(json.dumps(out))

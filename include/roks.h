@@ -313,6 +313,32 @@ roks_status roks_subspace(roks_ctx ctx, double* R, double* kappa, double* A);
  * exception to the synchronisation rule above: nothing the caller can read
  * depends on it). */
 roks_status roks_pcg_step(roks_ctx ctx, roks_step_info* info);
+/* Graph mode: k CG iterations with every decision taken on the device, so
+ * that they form one fixed launch sequence, captured once as a HIP graph
+ * (kept with the context, captured again when k, the tier or the flags
+ * change) and replayed by each call.  Each iteration is roks_pcg_step's
+ * (the same equations, the same first line-search attempt: trial at the
+ * kept step length, the parabola's step, the lower of the two taken if it
+ * lies below E(0) with dE0 < 0, the Fletcher-Reeves ratio dropped when the
+ * direction does not descend), with the energy sums, the ratio, the trial
+ * steps and the choice formed by small kernels from device scalars, and
+ * the new orbitals and carried directions copied in only when the step is
+ * accepted.  The first rejected iteration halts the rest (they change
+ * nothing): *accepted receives the number of leading accepted iterations,
+ * and a caller continues with roks_pcg_step, whose halvings of the trial
+ * step and steepest-descent retry graph mode does not take.  info (nullable)
+ * receives k records (stalled = 1 from the first rejected one; evaluations
+ * 2 for each iteration run before the halt).  Within rounding the results
+ * are those of roks_pcg_step (the trial projections are formed from the
+ * trial orbitals, the energy of each iteration's orbitals is evaluated
+ * again instead of kept from the trial).  Scope (else ROKS_ERR_STATE): at
+ * most 78 bands, the FP64 or FP32 tier, no exact exchange, overlap
+ * coefficients, network, recording, periodic restart, canonicalisation or
+ * autotuning; ROKS_ERR_ARG for k outside 1 .. 100000.  The call
+ * synchronizes the context's stream; the first call for a k also runs one
+ * iteration that commits nothing (first-use set-up outside the capture). */
+roks_status roks_graph_steps(roks_ctx ctx, int32_t k, roks_step_info* info, int32_t* accepted);
+
 /* Forget the carried search directions (next step is steepest descent). */
 roks_status roks_reset_cg(roks_ctx ctx);
 /* Restart the CG recursion every `period` steps (0, the default: never, the
@@ -585,6 +611,10 @@ roks_status roks_batch_solve(roks_batch batch, double tol, int32_t maxiter, doub
                              roks_status* status, int32_t* iterations, roks_step_info* last);
 /* `steps` CG steps on every context (a fixed amount of work). */
 roks_status roks_batch_steps(roks_batch batch, int32_t steps, roks_status* status);
+/* roks_graph_steps(k) on every context, each graph replayed on its
+ * worker's stream: status [n] and accepted [n] (both nullable). */
+roks_status roks_batch_graph_steps(roks_batch batch, int32_t k, roks_status* status,
+                                   int32_t* accepted);
 
 #ifdef __cplusplus
 }

@@ -303,6 +303,13 @@ roks_status roks_pcg_step(roks_ctx ctx, roks_step_info* info) {
   return guard(ctx, [&](roks::Ctx& c) { roks::pcg_step(c, info); });
 }
 
+roks_status roks_graph_steps(roks_ctx ctx, int32_t k, roks_step_info* info, int32_t* accepted) {
+  return guard(ctx, [&](roks::Ctx& c) {
+    const int a = roks::graph_steps(c, k, info);
+    if (accepted) *accepted = a;
+  });
+}
+
 roks_status roks_diis_step(roks_ctx ctx, const roks_diis_params* params, roks_diis_info* info) {
   return guard(ctx, [&](roks::Ctx& c) {
     ROKS_CHECK(params, ROKS_ERR_ARG, "params is NULL");

@@ -150,4 +150,15 @@ roks_status roks_batch_steps(roks_batch b, int32_t steps, roks_status* status) {
   return ROKS_OK;
 }
 
+roks_status roks_batch_graph_steps(roks_batch b, int32_t k, roks_status* status, int32_t* accepted) {
+  if (!b || k < 1) return ROKS_ERR_ARG;
+  run_queue(b, status, [&](int i) {
+    int32_t a = 0;
+    const roks_status st = roks_graph_steps(b->ctxs[i], k, nullptr, &a);
+    if (accepted) accepted[i] = a;
+    return st;
+  });
+  return ROKS_OK;
+}
+
 }  // extern "C"

@@ -299,6 +299,7 @@ void clear_timing(Ctx& c) {
 void free_device(Ctx& c) {
   clear_timing(c);
   if (c.stream || !c.allocations.empty()) (void)hipStreamSynchronize(c.stream);
+  free_graph_mode(c);
   for (DevBuf& b : c.allocations) (void)hipFree(b.p);
   c.allocations.clear();
   for (void* h : {(void*)c.h_scal, (void*)c.h_stage, (void*)c.h_flag, (void*)c.h_force})

@@ -1186,6 +1186,8 @@ double grid_bytes(const Ctx& c) {
 
 }  // namespace
 
+void allow_dynamic_lds(const void* kernel, size_t bytes) { allow_lds(kernel, bytes); }
+
 #define ROKS_DISPATCH_MAXP_RS(R, mp, RS, KER, ...)        \
   switch (mp) {                                           \
     case 8: KER<R, 8, RS>(__VA_ARGS__); break;            \

@@ -46,8 +46,11 @@ __device__ inline double add(double a, double b) { return __dadd_rn(a, b); }
 __device__ inline double sub(double a, double b) { return __dsub_rn(a, b); }
 __device__ inline double dvd(double a, double b) { return __ddiv_rn(a, b); }
 
-__global__ void k_g_begin(double* __restrict__ gs) {
+// carry: the orbitals are the previous iteration's accepted trial, whose
+// energy is E(0) (its potentials and projections were kept)
+__global__ void k_g_begin(double* __restrict__ gs, int carry) {
   if (threadIdx.x || blockIdx.x) return;
+  if (carry) gs[gE0] = gs[gE1];
   gs[gAccept] = 0.0;
   gs[gBest] = 0.0;
 }
@@ -177,12 +180,15 @@ __global__ void k_g_accept(double* __restrict__ gs) {
   gs[gE1] = acc ? Eb : gs[gE0];
 }
 
-// dst = (best ? t1 : t0) when the step is accepted
-__global__ void __launch_bounds__(256) k_g_take(size_t n, const double* __restrict__ t0,
-                                                const double* __restrict__ t1, double* __restrict__ dst,
-                                                const double* __restrict__ gs, int need_accept) {
+// dst = (best ? t1 : t0), with need_accept only when the step is accepted,
+// with only_first only when the first trial is the one taken
+template <typename T>
+__global__ void __launch_bounds__(256) k_g_take(size_t n, const T* t0, const T* t1, T* dst,
+                                                const double* __restrict__ gs, int need_accept,
+                                                int only_first) {
   if (need_accept && gs[gAccept] == 0.0) return;
-  const double* src = gs[gBest] != 0.0 ? t1 : t0;
+  if (only_first && gs[gBest] != 0.0) return;
+  const T* src = gs[gBest] != 0.0 ? t1 : t0;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
 }
@@ -218,8 +224,35 @@ size_t grid_for(size_t n) { return std::min<size_t>(4096, (n + 255) / 256); }
 // ---------------------------------------------------------------------------
 // one iteration, every launch on c.stream, no host reads
 // ---------------------------------------------------------------------------
-static void graph_trial(Ctx& c, int tslot, double2* out, double* M, double* U, bool energy_only,
-                        int eslot, int okslot) {
+template <typename T>
+static void take(Ctx& c, size_t n, const T* t0, const T* t1, T* dst, int need_accept, int only_first) {
+  hipLaunchKernelGGL(k_g_take<T>, dim3((unsigned)grid_for(n)), dim3(256), 0, c.stream, n, t0, t1, dst,
+                     c.d_gstate, need_accept, only_first);
+  ROKS_HIP(hipGetLastError());
+}
+
+// the first trial's potentials, projections and reduced sums (with the
+// band kinetic and nonlocal energies, which the subspace matrices read) go
+// to the second set of buffers (captured pointers: the members are only
+// swapped while the launches are made)
+struct AltPotentials {
+  Ctx& c;
+  AltPotentials(Ctx& cc) : c(cc) { swap(); }
+  ~AltPotentials() { swap(); }
+  void swap() {
+    std::swap(c.d_vsh, c.d_gvsh);
+    std::swap(c.d_vloc, c.d_gvloc);
+    std::swap(c.d_vsh32, c.d_gvsh32);
+    std::swap(c.d_vloc32, c.d_gvloc32);
+    std::swap(c.d_P, c.d_gP);
+    std::swap(c.d_red, c.d_gscal);
+    c.d_kin = c.d_red + 16;
+    c.d_enl = c.d_red + 16 + c.nb;
+  }
+};
+
+static void graph_trial(Ctx& c, int tslot, double2* out, double* M, double* U, bool alt, int eslot,
+                        int okslot) {
   const int nb = c.nb, K = 2 * c.npw;
   const size_t band = (size_t)nb * c.npw, nn = (size_t)nb * nb;
   hipLaunchKernelGGL(k_g_prep, dim3((unsigned)grid_for(nn + 2 * band)), dim3(256), 0, c.stream, nb,
@@ -229,26 +262,35 @@ static void graph_trial(Ctx& c, int tslot, double2* out, double* M, double* U, b
   gemm_small(c, nb, nb, nb, U, nb, true, c.d_Linv, nb, false, M, nb, 1.0, 0.0);
   gemm_expand_sum(c, nb, K, nb, M, nb, true, dbl(c.d_psi), dbl(c.d_Pt), 1.0, K, dbl(out), K, dbl(out),
                   K, 1.0, 0.0);
-  compute_potentials_async(c, out, false, energy_only);
-  hipLaunchKernelGGL(k_g_energy, dim3(1), dim3(64), 0, c.stream, c.d_scal, nb, c.nconf, c.d_gfocc,
-                     c.cL[0], c.cL[1], c.omega / (double)c.ntot, energy_only ? 1 : 0, c.d_flag,
-                     c.d_gstate, eslot, okslot);
+  if (alt) {
+    AltPotentials swap(c);
+    compute_potentials_async(c, out, false, false);
+  } else {
+    compute_potentials_async(c, out, false, false);
+  }
+  hipLaunchKernelGGL(k_g_energy, dim3(1), dim3(64), 0, c.stream, alt ? c.d_gscal : c.d_scal, nb, c.nconf,
+                     c.d_gfocc, c.cL[0], c.cL[1], c.omega / (double)c.ntot, 0, c.d_flag, c.d_gstate,
+                     eslot, okslot);
   ROKS_HIP(hipGetLastError());
 }
 
-static void graph_step(Ctx& c, int step) {
+// carry: the previous iteration (of the same graph) left the potentials and
+// projections of the orbitals it accepted, and their energy, in place
+static void graph_step(Ctx& c, int step, bool carry) {
   const int nb = c.nb, K = 2 * c.npw;
   const size_t band = (size_t)nb * c.npw, nn = (size_t)nb * nb;
   double* gs = c.d_gstate;
-  hipLaunchKernelGGL(k_g_begin, dim3(1), dim3(64), 0, c.stream, gs);
+  hipLaunchKernelGGL(k_g_begin, dim3(1), dim3(64), 0, c.stream, gs, carry ? 1 : 0);
   ROKS_HIP(hipGetLastError());
   // energy, Y = F^n|n>, theta, g_I = (1 - P) Y, R / kappa / A
-  compute_potentials_async(c, c.d_psi, false, false);
-  hipLaunchKernelGGL(k_g_energy, dim3(1), dim3(64), 0, c.stream, c.d_scal, nb, c.nconf, c.d_gfocc,
-                     c.cL[0], c.cL[1], c.omega / (double)c.ntot, 0, static_cast<const int32_t*>(nullptr),
-                     gs, (int)gE0, -1);
-  ROKS_HIP(hipGetLastError());
-  c.potentials_valid = true;  // the apply reads the projections just formed
+  if (!carry) {
+    compute_potentials_async(c, c.d_psi, false, false);
+    hipLaunchKernelGGL(k_g_energy, dim3(1), dim3(64), 0, c.stream, c.d_scal, nb, c.nconf, c.d_gfocc,
+                       c.cL[0], c.cL[1], c.omega / (double)c.ntot, 0,
+                       static_cast<const int32_t*>(nullptr), gs, (int)gE0, -1);
+    ROKS_HIP(hipGetLastError());
+  }
+  c.potentials_valid = true;  // the apply reads the projections in d_P
   apply_operator(c, c.d_psi, 0, c.d_Y, true);
   gemm_wdot(c, nb, nb, K, dbl(c.d_psi), K, dbl(c.d_Y), K, c.d_theta, nb, 1.0, 0.0, true);
   gemm_expand_to(c, nb, K, nb, c.d_theta, nb, false, dbl(c.d_psi), K, dbl(c.d_Y), K, dbl(c.d_gI), K,
@@ -278,29 +320,34 @@ static void graph_step(Ctx& c, int step) {
                      c.d_D, gs, (int)gBeta);
   ROKS_HIP(hipGetLastError());
   gemm_wdot(c, nb, nb, K, dbl(c.d_S), K, dbl(c.d_S), K, c.d_SS, nb, 1.0, 0.0, true);
-  // the two trials of reading R7's first attempt
+  // the two trials of the line search's first attempt (reading R7)
   graph_trial(c, gT, c.d_trial[0], c.d_M, c.d_U, true, gEt, gOkT);
   hipLaunchKernelGGL(k_g_parabola, dim3(1), dim3(64), 0, c.stream, gs);
   ROKS_HIP(hipGetLastError());
   graph_trial(c, gTs, c.d_trial[1], c.d_Mkeep, c.d_Ukeep, false, gEts, gOkTs);
   hipLaunchKernelGGL(k_g_accept, dim3(1), dim3(64), 0, c.stream, gs);
   ROKS_HIP(hipGetLastError());
-  // commit when accepted: psi, then S_old = M^T S and D_old = U^T D U of the
-  // trial kept (formed in scratch, copied only when accepted)
-  hipLaunchKernelGGL(k_g_take, dim3((unsigned)grid_for(2 * band)), dim3(256), 0, c.stream, 2 * band,
-                     dbl(c.d_trial[0]), dbl(c.d_trial[1]), dbl(c.d_psi), gs, 1);
-  hipLaunchKernelGGL(k_g_take, dim3((unsigned)grid_for(nn)), dim3(256), 0, c.stream, nn, c.d_M, c.d_Mkeep,
-                     c.d_m3, gs, 0);
-  hipLaunchKernelGGL(k_g_take, dim3((unsigned)grid_for(nn)), dim3(256), 0, c.stream, nn, c.d_U, c.d_Ukeep,
-                     c.d_m4, gs, 0);
-  ROKS_HIP(hipGetLastError());
+  // commit when accepted: psi (and, for the first trial, its potentials and
+  // projections; the second trial's are in place), then S_old = M^T S and
+  // D_old = U^T D U of the trial kept (formed in scratch, copied only when
+  // accepted)
+  take(c, 2 * band, dbl(c.d_trial[0]), dbl(c.d_trial[1]), dbl(c.d_psi), 1, 0);
+  const size_t ng = (size_t)c.ntot;
+  take(c, (size_t)c.nsocc * ng, c.d_gvsh, c.d_vsh, c.d_vsh, 1, 1);
+  take(c, (size_t)2 * c.nconf * ng, c.d_gvloc, c.d_vloc, c.d_vloc, 1, 1);
+  if (c.prec == ROKS_FP32) {
+    take(c, (size_t)c.nsocc * ng, c.d_gvsh32, c.d_vsh32, c.d_vsh32, 1, 1);
+    take(c, (size_t)2 * c.nconf * ng, c.d_gvloc32, c.d_vloc32, c.d_vloc32, 1, 1);
+  }
+  if (c.nproj > 0) take(c, (size_t)c.nproj * nb, c.d_gP, c.d_P, c.d_P, 1, 1);
+  take(c, (size_t)2 * nb, c.d_gscal + 16, c.d_scal + 16, c.d_scal + 16, 1, 1);
+  take(c, nn, c.d_M, c.d_Mkeep, c.d_m3, 0, 0);
+  take(c, nn, c.d_U, c.d_Ukeep, c.d_m4, 0, 0);
   gemm_expand(c, nb, K, nb, c.d_m3, nb, true, dbl(c.d_S), K, dbl(c.d_trial[0]), K, 1.0, 0.0);
-  hipLaunchKernelGGL(k_g_take, dim3((unsigned)grid_for(2 * band)), dim3(256), 0, c.stream, 2 * band,
-                     dbl(c.d_trial[0]), dbl(c.d_trial[0]), dbl(c.d_Sold), gs, 1);
+  take(c, 2 * band, dbl(c.d_trial[0]), dbl(c.d_trial[0]), dbl(c.d_Sold), 1, 0);
   gemm_small(c, nb, nb, nb, c.d_D, nb, false, c.d_m4, nb, false, c.d_m2, nb, 1.0, 0.0);
   gemm_small(c, nb, nb, nb, c.d_m4, nb, true, c.d_m2, nb, false, c.d_m1, nb, 1.0, 0.0);
-  hipLaunchKernelGGL(k_g_take, dim3((unsigned)grid_for(nn)), dim3(256), 0, c.stream, nn, c.d_m1, c.d_m1,
-                     c.d_Dold, gs, 1);
+  take(c, nn, c.d_m1, c.d_m1, c.d_Dold, 1, 0);
   hipLaunchKernelGGL(k_g_finish, dim3(1), dim3(64), 0, c.stream, gs, c.hd_grec + (size_t)step * kRecLen,
                      c.hd_gmirror, kDtMin, kDtMax);
   ROKS_HIP(hipGetLastError());
@@ -335,11 +382,20 @@ void graph_buffers(Ctx& c, int k) {
         focc[(size_t)L * nb + n] =
             (double)c.occ[(L * 2 + 0) * nb + n] + (double)c.occ[(L * 2 + 1) * nb + n];
     c.d_gfocc = dalloc<double>(c, focc.size());
+    c.d_gvsh = dalloc<double>(c, (size_t)c.nsocc * c.ntot);
+    c.d_gvloc = dalloc<double>(c, (size_t)2 * c.nconf * c.ntot);
+    c.d_gP = dalloc<double>(c, (size_t)std::max(1, c.nproj) * nb);
+    c.d_gscal = dalloc<double>(c, 16 + 2 * (size_t)nb);
     ROKS_HIP(hipMemcpyAsync(c.d_gfocc, focc.data(), focc.size() * sizeof(double), hipMemcpyHostToDevice,
                             c.stream));
     ROKS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_gmirror), gNSlots * sizeof(double),
                            hipHostMallocMapped | hipHostMallocCoherent));
     ROKS_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c.hd_gmirror), c.h_gmirror, 0));
+    ROKS_HIP(hipStreamSynchronize(c.stream));
+  }
+  if (c.d_vsh32 && !c.d_gvsh32) {
+    c.d_gvsh32 = dalloc<float>(c, (size_t)c.nsocc * c.ntot);
+    c.d_gvloc32 = dalloc<float>(c, (size_t)2 * c.nconf * c.ntot);
     ROKS_HIP(hipStreamSynchronize(c.stream));
   }
   if (k > c.grec_cap) {
@@ -413,7 +469,7 @@ void capture(Ctx& c, int k) {
   // one iteration outside the capture that commits nothing: first-use work
   // of every launcher (tables, LDS limits) happens here
   graph_load_state(c, true);
-  graph_step(c, 0);
+  graph_step(c, 0, false);
   ROKS_HIP(hipStreamSynchronize(c.stream));
   hipStream_t st = nullptr;
   ROKS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -425,7 +481,7 @@ void capture(Ctx& c, int k) {
   hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     try {
-      for (int i = 0; i < k; ++i) graph_step(c, i);
+      for (int i = 0; i < k; ++i) graph_step(c, i, i > 0);
     } catch (...) {
       (void)hipStreamEndCapture(st, &g);
       if (g) (void)hipGraphDestroy(g);
@@ -465,7 +521,8 @@ void free_graph_mode(Ctx& c) {
     if (h) (void)hipHostFree(h);
   c.h_gmirror = c.hd_gmirror = c.h_grec = c.hd_grec = nullptr;
   c.grec_cap = 0;
-  c.d_gstate = c.d_gfocc = nullptr;  // freed with the other allocations
+  c.d_gstate = c.d_gfocc = c.d_gvsh = c.d_gvloc = c.d_gP = c.d_gscal = nullptr;  // freed with the others
+  c.d_gvsh32 = c.d_gvloc32 = nullptr;
 }
 
 int graph_steps(Ctx& c, int k, roks_step_info* info) {

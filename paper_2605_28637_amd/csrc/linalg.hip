@@ -1001,9 +1001,7 @@ void launch_chol_expm_lds(Ctx& c, const double* G, double ga, double gd, double*
   const int n = c.nb;
   const int inv = n <= 96 ? 1 : 0;
   const size_t lds = std::max((size_t)(inv ? 2 : 1) * n * chol_ld(n), (size_t)3 * n * n) * sizeof(double);
-  if (lds > 65536)
-    ROKS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_chol_expm_lds),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  allow_dynamic_lds(reinterpret_cast<const void*>(k_chol_expm_lds), lds);
   hipLaunchKernelGGL(k_chol_expm_lds, dim3(2), dim3(1024), lds, c.stream, G, ga, gd, n, Linv, flag, inv,
                      D, delta, U);
   ROKS_HIP(hipGetLastError());
@@ -1012,9 +1010,7 @@ void launch_chol_expm_lds(Ctx& c, const double* G, double ga, double gd, double*
 void launch_expm_lds(Ctx& c, const double* D, double delta, double* U, hipStream_t stream) {
   const int n = c.nb;
   const size_t lds = (size_t)3 * n * n * sizeof(double);
-  if (lds > 65536)
-    ROKS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_expm_lds),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  allow_dynamic_lds(reinterpret_cast<const void*>(k_expm_lds), lds);
   hipLaunchKernelGGL(k_expm_lds, dim3(1), dim3(1024), lds, stream, D, n, delta, U);
   ROKS_HIP(hipGetLastError());
 }

@@ -272,6 +272,30 @@ struct Ctx {
   double dt = 0.5;
   int iteration = 0;
 
+  // ---- graph mode (graph.hip): CG iterations decided on the device ----
+  double* d_gstate = nullptr;      // state block and per-band scratch
+  double* d_gfocc = nullptr;       // [nconf][nb] occupation of each band
+  // the first trial's potentials and projections (kept for the next
+  // iteration when that trial is taken)
+  double* d_gvsh = nullptr;
+  double* d_gvloc = nullptr;
+  float* d_gvsh32 = nullptr;
+  float* d_gvloc32 = nullptr;
+  double* d_gP = nullptr;
+  double* d_gscal = nullptr;       // reduced sums, as d_scal
+  double* h_gmirror = nullptr;     // pinned copy of the state block
+  double* hd_gmirror = nullptr;    // its device view
+  double* h_grec = nullptr;        // pinned per-iteration records
+  double* hd_grec = nullptr;
+  int grec_cap = 0;                // iterations the records hold
+  hipGraphExec_t graph_exec = nullptr;  // the captured iterations
+  int graph_k = 0;                 // how many (0: none captured)
+  int graph_prec = 0;              // the tier and flags it was captured with
+  uint32_t graph_flags = 0;
+  // the buffers the capture baked in (orbitals, trials, projections, which
+  // the host CG trades by pointer)
+  void* graph_bufs[5] = {};
+
   // ---- cached results of the last energy evaluation ----
   roks_energies last_e{};
   std::string last_error;
@@ -519,6 +543,9 @@ void launch_subspace(Ctx& c, double* open_out = nullptr);
 // triangle mirrored; with canonicalisation kappa and the Jacobi angles)
 void launch_virtual_block(Ctx& c, int v0);
 bool expm_in_lds(const Ctx& c);
+// raise a kernel's dynamic LDS limit to bytes (a runtime call only the first
+// time a larger size is asked for on the current device)
+void allow_dynamic_lds(const void* kernel, size_t bytes);
 // Cholesky inverse of G and U = exp(delta D) in one launch of two workgroups
 // (nb within the single-workgroup limits of both)
 void launch_chol_expm_lds(Ctx& c, const double* G, double ga, double gd, double* Linv, int32_t* flag,
@@ -557,6 +584,9 @@ void collect_records(Ctx& c, Mlp& m, int* used, int* skipped);
 
 // solver (solver.cpp)
 void compute_potentials(Ctx& c, const double2* orbitals, roks_energies* e);
+// every launch of it, no synchronisation (energies reduced into d_scal and
+// its pinned mirror); have_P: the projections of orb are already in d_P
+void compute_potentials_async(Ctx& c, const double2* orb, bool have_P, bool energy_only);
 void ensure_potentials(Ctx& c);
 void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bool want_Q);
 // want_vv: also the virtual-virtual block of R, <m|F^c|n> (always with
@@ -597,6 +627,11 @@ double smallest_trial_step(const Ctx& c);
 void launch_zero_g0_imag(Ctx& c, double2* vecs, int nvec);
 void forces(Ctx& c, double* f_host);
 void reset_cg(Ctx& c);
+// graph mode (graph.hip): k device-decided CG iterations replayed from one
+// captured graph; returns the leading accepted ones (info: k records)
+int graph_steps(Ctx& c, int k, roks_step_info* info);
+void free_graph(Ctx& c);       // the captured graph
+void free_graph_mode(Ctx& c);  // and the pinned records
 
 // helpers
 template <typename T>
@@ -612,6 +647,11 @@ T* dalloc(Ctx& c, size_t count) {
 }
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// the CG trial step: its bounds, its first value and the halvings of one
+// line search
+constexpr double kDtMin = 0.1, kDtMax = 2.0, kDtInit = 0.5;
+constexpr int kHalvings = 4;
 
 constexpr int kStage = 16;  // scalar slots ahead of the per-band ones in h_stage
 constexpr int kStageNormD = 3;  // h_stage slot of ||D||_1 for the line search

@@ -15,9 +15,6 @@ namespace roks {
 
 namespace {
 
-constexpr double kDtMin = 0.1, kDtMax = 2.0, kDtInit = 0.5;
-constexpr int kHalvings = 4;
-
 
 // U = exp(X) for X = delta * D (antisymmetric): scaling and squaring around a
 // Taylor polynomial in Horner form, the degree m and squarings s chosen as in

@@ -153,6 +153,7 @@ _SIGS = {
     "roks_subspace": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                 C.POINTER(C.c_double)]),
     "roks_pcg_step": (C.c_int, [_P, C.POINTER(StepInfo)]),
+    "roks_graph_steps": (C.c_int, [_P, C.c_int32, C.POINTER(StepInfo), C.POINTER(C.c_int32)]),
     "roks_reset_cg": (C.c_int, [_P]),
     "roks_diis_step": (C.c_int, [_P, C.POINTER(DiisParams), C.POINTER(DiisInfo)]),
     "roks_diis_solve": (C.c_int, [_P, C.POINTER(DiisParams), C.c_double, C.c_int32,
@@ -191,6 +192,7 @@ _SIGS = {
     "roks_batch_solve": (C.c_int, [_P, C.c_double, C.c_int32, C.c_double, C.POINTER(C.c_int),
                                    C.POINTER(C.c_int32), C.POINTER(StepInfo)]),
     "roks_batch_steps": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int)]),
+    "roks_batch_graph_steps": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int), C.POINTER(C.c_int32)]),
 }
 
 MLP_PARAMS = 4481
@@ -391,6 +393,14 @@ class Roks:
         info = StepInfo()
         self._check(self._L.roks_pcg_step(self._h, C.byref(info)))
         return info.as_dict()
+
+    def graph_steps(self, k: int):
+        """k device-decided CG iterations replayed from one captured graph:
+        (the leading accepted count, the k step records)."""
+        info = (StepInfo * k)()
+        acc = C.c_int32()
+        self._check(self._L.roks_graph_steps(self._h, k, info, C.byref(acc)))
+        return acc.value, [info[i].as_dict() for i in range(k)]
 
     def reset_cg(self):
         self._check(self._L.roks_reset_cg(self._h))
@@ -610,3 +620,13 @@ class Batch:
         if rc != 0:
             raise RoksError(rc, "roks_batch_steps failed")
         return list(st)
+
+    def graph_steps(self, k: int):
+        """roks_graph_steps(k) on every context: (statuses, accepted counts)."""
+        n = len(self.systems)
+        st = (C.c_int * n)()
+        acc = (C.c_int32 * n)()
+        rc = self._L.roks_batch_graph_steps(self._h, k, st, acc)
+        if rc != 0:
+            raise RoksError(rc, "roks_batch_graph_steps failed")
+        return list(st), list(acc)

@@ -1,0 +1,168 @@
+"""CG iterations with every decision taken on the device, replayed from one
+captured HIP graph (roks_graph_steps), against the oracle's CG (Sec. II A,
+readings R1-R7, R9) and against the host-driven roks_pcg_step: the same
+equations and the same first line-search attempt, within rounding (the
+trial projections come from the trial orbitals, and each iteration's energy
+is evaluated again instead of being kept from the trial).  Graphs are
+replayed several times, with host steps (which trade the orbital buffers)
+in between, in both tiers, and for a batch of uneven systems."""
+import numpy as np
+import pytest
+
+from helpers import SphereMap, band_rel, ensure_built, small_molecule
+from oracle import roks as orc
+from paper_2605_28637_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+CASES = {
+    "small_odd_bands": lambda: small_molecule(),
+    "ground_state": lambda: inputs.with_configuration(inputs.tiny_cell(), "gs"),
+    "pbe_molecule": lambda: dict(small_molecule(), xc="pbe"),
+    "triplet": lambda: inputs.with_configuration(small_molecule(), "triplet"),
+}
+
+
+def _ctx(rb, s, precision=None):
+    g = rb.Roks(s) if precision is None else rb.Roks(s, precision=precision)
+    g.set_coeffs(inputs.random_coefficients(g.miller(), s["cell"], g.nb, s["seed"]), True)
+    return g
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_graph_steps_match_the_oracle(case):
+    rb = ensure_built()
+    s = CASES[case]()
+    print("graph case", case, s["grid"], s["nbands"], flush=True)
+    g = _ctx(rb, s)
+    m = orc.Model(s)
+    mp = SphereMap(g.miller(), m.miller)
+    st = orc.CGState(psi=orc.orthonormalize(
+        inputs.random_coefficients(m.miller, m.cell, m.nb, s["seed"])))
+    acc, recs = g.graph_steps(4)
+    assert acc == 4
+    for i, r in enumerate(recs):
+        oi = orc.pcg_step(m, st)
+        scale = max(1.0, abs(oi.E0))
+        print(i, r["E0"], oi.E0, r["E1"], oi.E1, r["delta"], oi.delta, flush=True)
+        assert abs(r["E0"] - oi.E0) < TOL * scale, i
+        assert abs(r["E1"] - oi.E1) < TOL * scale, i
+        assert abs(r["delta"] - oi.delta) < 1e-8 * max(1.0, oi.delta), i
+        assert abs(r["beta"] - oi.beta) < 1e-8 * max(1.0, abs(oi.beta)), i
+        assert r["stalled"] == 0 and r["evaluations"] == 2 and r["iteration"] == i + 1
+    assert band_rel(mp.to_full(g.get_coeffs()), st.psi) < 1e-8
+    F = g.forces()
+    Fo = orc.forces(m, st.psi)
+    assert np.abs(F - Fo).max() < 1e-8 * max(1.0, np.abs(Fo).max())
+    g.close()
+
+
+def test_replays_interleaved_with_host_steps():
+    """graph(3), graph(3) (the same graph replayed), a host step (which
+    trades the orbital and trial buffers), graph(3) (the graph's buffers
+    restored), then a host step again: every step against ten host steps of
+    a twin context."""
+    rb = ensure_built()
+    s = small_molecule(nb=12)
+    a = _ctx(rb, s)
+    b = _ctx(rb, s)
+    seq = []
+    for kind in ("g", "g", "h", "g", "h"):
+        if kind == "g":
+            acc, recs = a.graph_steps(3)
+            assert acc == 3
+            seq += recs
+        else:
+            seq.append(a.pcg_step())
+    ref = [b.pcg_step() for _ in range(len(seq))]
+    for i, (x, y) in enumerate(zip(seq, ref)):
+        scale = max(1.0, abs(y["E0"]))
+        print(i, x["E1"], y["E1"], x["delta"], y["delta"], flush=True)
+        assert abs(x["E1"] - y["E1"]) < TOL * scale, i
+        assert abs(x["delta"] - y["delta"]) < 1e-8 * max(1.0, y["delta"]), i
+        assert x["iteration"] == y["iteration"] == i + 1
+    assert band_rel(a.get_coeffs(), b.get_coeffs()) < 1e-8
+    ea, _, _ = a.energy_gradient()
+    eb, _, _ = b.energy_gradient()
+    assert abs(ea["E"] - eb["E"]) < TOL * max(1.0, abs(eb["E"]))
+    a.close()
+    b.close()
+
+
+def test_fp32_tier_graph_steps_follow_the_host_steps():
+    """The FP32 tier: graph iterations against host iterations at the tier's
+    per-call bar (2e-6 relative), after a capture, a replay and a tier
+    change back to FP64 (captured again)."""
+    rb = ensure_built()
+    s = small_molecule()
+    a = _ctx(rb, s, rb.FP32)
+    b = _ctx(rb, s, rb.FP32)
+    acc1, r1 = a.graph_steps(4)
+    acc2, r2 = a.graph_steps(4)
+    assert acc1 == acc2 == 4
+    ref = [b.pcg_step() for _ in range(8)]
+    for i, (x, y) in enumerate(zip(r1 + r2, ref)):
+        assert abs(x["E1"] - y["E1"]) < 2e-6 * max(1.0, abs(y["E1"])), i
+    a.set_precision(rb.FP64)
+    b.set_precision(rb.FP64)
+    acc, r3 = a.graph_steps(4)
+    ref = [b.pcg_step() for _ in range(acc)]
+    for x, y in zip(r3, ref):
+        assert abs(x["E1"] - y["E1"]) < 2e-6 * max(1.0, abs(y["E1"]))
+    assert acc >= 1
+    a.close()
+    b.close()
+
+
+def test_batch_graph_steps_follow_the_batch_steps():
+    """The uneven batch members of at most 78 bands: one graph per member,
+    replayed on the workers' streams, against host steps of the same batch
+    on twin contexts; members past 78 bands are refused per member
+    (ROKS_ERR_STATE) without stopping the others."""
+    rb = ensure_built()
+    systems = inputs.batch_systems(count=12)
+    systems.sort(key=lambda s: s["nbands"])
+    small = [s for s in systems if s["nbands"] <= 78][:4]
+    big = [s for s in systems if s["nbands"] > 78][:1]
+    members = small + big
+    print("graph batch", [(s["grid"][0], s["nbands"]) for s in members], flush=True)
+    par = [_ctx(rb, s, rb.FP32) for s in members]
+    seq = [_ctx(rb, s, rb.FP32) for s in small]
+    b = rb.Batch(par, workers=4)
+    for _ in range(2):
+        st, acc = b.graph_steps(3)
+        assert st[: len(small)] == [0] * len(small)
+        assert acc[: len(small)] == [3] * len(small)
+        assert st[len(small):] == [8] * len(big)
+    for r in seq:
+        for _ in range(6):
+            r.pcg_step()
+    for r1, r2 in zip(seq, par):
+        e1, _, _ = r1.energy_gradient()
+        e2, _, _ = r2.energy_gradient()
+        print(e1["E"], e2["E"], flush=True)
+        assert abs(e1["E"] - e2["E"]) < 2e-6 * max(1.0, abs(e1["E"]))
+    b.close()
+    for r in par + seq:
+        r.close()
+
+
+@pytest.mark.parametrize("what", ["exx", "overlap", "bf16x3", "k"])
+def test_graph_mode_scope_is_checked(what):
+    rb = ensure_built()
+    s = small_molecule()
+    prec = None
+    if what == "exx":
+        s = dict(s, xc="pbe", exx=0.25)
+    elif what == "overlap":
+        s = inputs.with_overlap(s, 0.4)
+    elif what == "bf16x3":
+        prec = rb.FP32_BF16X3
+    g = _ctx(rb, s, prec)
+    with pytest.raises(rb.RoksError) as ei:
+        g.graph_steps(0 if what == "k" else 2)
+    assert ei.value.status == (1 if what == "k" else 8)
+    g.pcg_step()  # the context still works
+    g.close()
