@@ -429,7 +429,12 @@ def cg_graph_report(steps=8, workers=8):
                 "graph_band_applies_per_s": total_bands * steps / t_graph,
                 "speedup": t_host / t_graph,
                 "all_ok": all(x == 0 for x in st + st2),
-                "graph_steps_accepted": int(sum(acc)), "graph_steps_run": steps * len(systems)})
+                "graph_steps_accepted": int(sum(acc)), "graph_steps_run": steps * len(systems),
+                # members that reach the tier's resolution stop accepting
+                # steps (a graph halts at its first rejection): the rate of
+                # accepted band-steps only
+                "graph_accepted_band_steps_per_s":
+                    sum(a * s["nbands"] for a, s in zip(acc, systems)) / t_graph})
     # one member alone: host steps against graph replays on its own stream
     one_h, one_g = host[0], graph[0]
     for _ in range(2):

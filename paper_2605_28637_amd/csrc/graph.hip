@@ -92,53 +92,78 @@ __device__ inline double band_sum(const double* __restrict__ x, int nb) {
   return s;
 }
 
+// Scalars every block of a fused kernel needs are formed by its thread 0
+// from state slots that the kernel does not write, and only block 0 stores
+// them; the parallel part follows a barrier.
+
 // <p|g> and the Fletcher-Reeves ratio; the directional derivative of the
 // directions S = p + beta w, D = A + beta D_old from the band sums of p and
 // w against g_I and the rotation terms; beta = 0 when it is not a descent
-// direction; the first trial step is the step length kept from before
-__global__ void k_g_beta(const double* __restrict__ pgb, const double* __restrict__ asymA,
-                         const double* __restrict__ wgb, const double* __restrict__ asymD,
-                         const double* __restrict__ gg, int nb, double* __restrict__ gs) {
-  if (threadIdx.x || blockIdx.x) return;
-  const double spg = band_sum(pgb, nb);
-  const double swg = band_sum(wgb, nb);
-  const double pg = add(spg, mul(0.5, asymA[0]));
-  double beta = 0.0;
-  if (gs[gHaveOld] != 0.0 && gs[gPgOld] != 0.0) beta = dvd(pg, gs[gPgOld]);
-  double dE0 = add(mul(2.0, add(spg, mul(beta, swg))), add(asymA[0], mul(beta, asymD[0])));
-  const bool restart = beta != 0.0 && dE0 >= 0.0;
-  if (restart) {
-    beta = 0.0;
-    dE0 = add(mul(2.0, spg), asymA[0]);
+// direction; the first trial step is the step length kept from before.
+// Then S (n1 values) and D (n2 values).
+__global__ void __launch_bounds__(256) k_g_directions(
+    const double* __restrict__ pgb, const double* __restrict__ asymA, const double* __restrict__ wgb,
+    const double* __restrict__ asymD, const double* __restrict__ gg, int nb, double* __restrict__ gs,
+    size_t n1, const double* __restrict__ p, const double* __restrict__ w, double* __restrict__ S,
+    size_t n2, const double* __restrict__ A, const double* __restrict__ Dold, double* __restrict__ D) {
+  __shared__ double sb;
+  if (threadIdx.x == 0) {
+    const double spg = band_sum(pgb, nb);
+    const double swg = band_sum(wgb, nb);
+    const double pg = add(spg, mul(0.5, asymA[0]));
+    double beta = 0.0;
+    if (gs[gHaveOld] != 0.0 && gs[gPgOld] != 0.0) beta = dvd(pg, gs[gPgOld]);
+    double dE0 = add(mul(2.0, add(spg, mul(beta, swg))), add(asymA[0], mul(beta, asymD[0])));
+    const bool restart = beta != 0.0 && dE0 >= 0.0;
+    if (restart) {
+      beta = 0.0;
+      dE0 = add(mul(2.0, spg), asymA[0]);
+    }
+    sb = beta;
+    if (blockIdx.x == 0) {
+      gs[gRestart] = restart ? 1.0 : 0.0;
+      gs[gPg] = pg;
+      gs[gBeta] = beta;
+      gs[gDE0] = dE0;
+      gs[gT] = gs[gDt];
+      gs[gNormG] = sqrt(fmax(0.0, band_sum(gg, nb)));
+    }
   }
-  gs[gRestart] = restart ? 1.0 : 0.0;
-  gs[gPg] = pg;
-  gs[gBeta] = beta;
-  gs[gDE0] = dE0;
-  gs[gT] = gs[gDt];
-  gs[gNormG] = sqrt(fmax(0.0, band_sum(gg, nb)));
+  __syncthreads();
+  const double b = sb;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n1 + n2;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const bool first = i < n1;
+    const size_t k = first ? i : i - n1;
+    double v = 1.0 * (first ? p[k] : A[k]);
+    v += b * (first ? w[k] : Dold[k]);
+    (first ? S : D)[k] = v;
+  }
 }
 
-// out = x + gs[slot] y
-__global__ void __launch_bounds__(256) k_g_axpy(size_t n, const double* __restrict__ x,
-                                                const double* __restrict__ y, double* __restrict__ out,
-                                                const double* __restrict__ gs, int slot) {
-  const double b = gs[slot];
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    double v = 1.0 * x[i];
-    v += b * y[i];
-    out[i] = v;
-  }
+// reading R7 on the device: the parabola through E(0), E'(0), E(t)
+__device__ inline double parabola_step(const double* gs) {
+  const double t = gs[gT], E0 = gs[gE0], dE0 = gs[gDE0];
+  if (gs[gOkT] == 0.0) return mul(0.5, t);
+  const double curv = dvd(sub(sub(gs[gEt], E0), mul(dE0, t)), mul(t, t));
+  return curv > 0.0 ? fmin(dvd(-dE0, mul(2.0, curv)), mul(4.0, t)) : mul(2.0, t);
 }
 
-// the scaled inputs of a trial at t = gs[slot]: gram = t^2 <S|S> + I,
-// Dt = t D (n x n), St = t S (m values)
+// the scaled inputs of a trial: gram = t^2 <S|S> + I, Dt = t D (n x n),
+// St = t S (m values), at t = gs[gT] (first trial) or at the parabola's step
+// (second trial, stored in gs[gTs])
 __global__ void __launch_bounds__(256) k_g_prep(int nb, const double* __restrict__ SS,
                                                 double* __restrict__ gram, const double* __restrict__ D,
                                                 double* __restrict__ Dt, size_t m,
                                                 const double* __restrict__ S, double* __restrict__ St,
-                                                const double* __restrict__ gs, int slot) {
-  const double t = gs[slot];
+                                                double* __restrict__ gs, int second) {
+  __shared__ double st;
+  if (threadIdx.x == 0) {
+    st = second ? parabola_step(gs) : gs[gT];
+    if (second && blockIdx.x == 0) gs[gTs] = st;
+  }
+  __syncthreads();
+  const double t = st;
   const double t2 = t * t;
   const size_t nn = (size_t)nb * nb;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nn + m;
@@ -153,52 +178,65 @@ __global__ void __launch_bounds__(256) k_g_prep(int nb, const double* __restrict
   }
 }
 
-// reading R7 on the device: the parabola through E(0), E'(0), E(t)
-__global__ void k_g_parabola(double* __restrict__ gs) {
-  if (threadIdx.x || blockIdx.x) return;
-  const double t = gs[gT], E0 = gs[gE0], dE0 = gs[gDE0];
-  double ts;
-  if (gs[gOkT] != 0.0) {
-    const double curv = dvd(sub(sub(gs[gEt], E0), mul(dE0, t)), mul(t, t));
-    ts = curv > 0.0 ? fmin(dvd(-dE0, mul(2.0, curv)), mul(4.0, t)) : mul(2.0, t);
-  } else {
-    ts = mul(0.5, t);
+// conditional copies dst = (best ? t1 : t0), in 4-byte words: always, when
+// the step is accepted, or when it is accepted with the first trial
+enum : int { kAlways = 0, kAccepted = 1, kFirstTaken = 2 };
+constexpr int kMaxSegs = 10;
+struct Seg {
+  const uint32_t* t0;
+  const uint32_t* t1;
+  uint32_t* dst;
+  size_t n;
+  int cond;
+};
+struct Segs {
+  Seg s[kMaxSegs];
+  int count;
+};
+
+__device__ inline void copy_segs(const Segs& g, bool acc, bool best) {
+  const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (int k = 0; k < g.count; ++k) {
+    const Seg& q = g.s[k];
+    if (q.cond != kAlways && !acc) continue;
+    if (q.cond == kFirstTaken && best) continue;
+    const uint32_t* src = best ? q.t1 : q.t0;
+    for (size_t i = tid; i < q.n; i += stride) q.dst[i] = src[i];
   }
-  gs[gTs] = ts;
 }
 
-// the lower trial, kept if it lies below E(0) and the direction descends
-__global__ void k_g_accept(double* __restrict__ gs) {
-  if (threadIdx.x || blockIdx.x) return;
-  const double Et = gs[gEt], Ets = gs[gEts];
-  const int best = Ets <= Et ? 1 : 0;
-  const double Eb = best ? Ets : Et;
-  const bool acc = gs[gHalt] == 0.0 && gs[gDE0] < 0.0 && Eb < gs[gE0];
-  gs[gBest] = best;
-  gs[gAccept] = acc ? 1.0 : 0.0;
-  gs[gDelta] = best ? gs[gTs] : gs[gT];
-  gs[gE1] = acc ? Eb : gs[gE0];
+// the lower trial, kept if it lies below E(0) and the direction descends;
+// then the copies that depend on that choice
+__global__ void __launch_bounds__(256) k_g_accept(double* __restrict__ gs, Segs g) {
+  __shared__ int sflags;
+  if (threadIdx.x == 0) {
+    const double Et = gs[gEt], Ets = gs[gEts];
+    const int best = Ets <= Et ? 1 : 0;
+    const double Eb = best ? Ets : Et;
+    const bool acc = gs[gHalt] == 0.0 && gs[gDE0] < 0.0 && Eb < gs[gE0];
+    sflags = (acc ? 1 : 0) | (best << 1);
+    if (blockIdx.x == 0) {
+      gs[gBest] = best;
+      gs[gAccept] = acc ? 1.0 : 0.0;
+      gs[gDelta] = best ? gs[gTs] : gs[gT];
+      gs[gE1] = acc ? Eb : gs[gE0];
+    }
+  }
+  __syncthreads();
+  copy_segs(g, (sflags & 1) != 0, (sflags & 2) != 0);
 }
 
-// dst = (best ? t1 : t0), with need_accept only when the step is accepted,
-// with only_first only when the first trial is the one taken
-template <typename T>
-__global__ void __launch_bounds__(256) k_g_take(size_t n, const T* t0, const T* t1, T* dst,
-                                                const double* __restrict__ gs, int need_accept,
-                                                int only_first) {
-  if (need_accept && gs[gAccept] == 0.0) return;
-  if (only_first && gs[gBest] != 0.0) return;
-  const T* src = gs[gBest] != 0.0 ? t1 : t0;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    dst[i] = src[i];
-}
-
-// the carried state of an accepted step and the iteration's record; the
-// first rejected step halts the rest (they commit nothing)
-__global__ void k_g_finish(double* __restrict__ gs, double* __restrict__ rec,
-                           double* __restrict__ mirror, double dt_min, double dt_max) {
-  if (threadIdx.x || blockIdx.x) return;
+// the remaining copies of an accepted step, its carried scalars and the
+// iteration's record; the first rejected step halts the rest (they commit
+// nothing)
+__global__ void __launch_bounds__(256) k_g_finish(double* __restrict__ gs, Segs g,
+                                                  double* __restrict__ rec, double* __restrict__ mirror,
+                                                  double dt_min, double dt_max) {
   const bool acc = gs[gAccept] != 0.0;
+  const bool best = gs[gBest] != 0.0;
+  copy_segs(g, acc, best);
+  if (threadIdx.x || blockIdx.x) return;
   if (acc) {
     gs[gPgOld] = gs[gPg];
     gs[gHaveOld] = 1.0;
@@ -224,12 +262,18 @@ size_t grid_for(size_t n) { return std::min<size_t>(4096, (n + 255) / 256); }
 // ---------------------------------------------------------------------------
 // one iteration, every launch on c.stream, no host reads
 // ---------------------------------------------------------------------------
-template <typename T>
-static void take(Ctx& c, size_t n, const T* t0, const T* t1, T* dst, int need_accept, int only_first) {
-  hipLaunchKernelGGL(k_g_take<T>, dim3((unsigned)grid_for(n)), dim3(256), 0, c.stream, n, t0, t1, dst,
-                     c.d_gstate, need_accept, only_first);
-  ROKS_HIP(hipGetLastError());
-}
+// a list of conditional copies for k_g_accept / k_g_finish
+struct SegList {
+  Segs g{};
+  size_t most = 0;
+  void add(const void* t0, const void* t1, void* dst, size_t bytes, int cond) {
+    ROKS_CHECK(g.count < kMaxSegs && bytes % 4 == 0, ROKS_ERR_STATE, "copy list overflow");
+    g.s[g.count++] = Seg{static_cast<const uint32_t*>(t0), static_cast<const uint32_t*>(t1),
+                         static_cast<uint32_t*>(dst), bytes / 4, cond};
+    most = std::max(most, bytes / 4);
+  }
+  unsigned grid() const { return (unsigned)std::max<size_t>(1, grid_for(most)); }
+};
 
 // the first trial's potentials, projections and reduced sums (with the
 // band kinetic and nonlocal energies, which the subspace matrices read) go
@@ -251,12 +295,13 @@ struct AltPotentials {
   }
 };
 
-static void graph_trial(Ctx& c, int tslot, double2* out, double* M, double* U, bool alt, int eslot,
+static void graph_trial(Ctx& c, double2* out, double* M, double* U, bool alt, int eslot,
                         int okslot) {
   const int nb = c.nb, K = 2 * c.npw;
   const size_t band = (size_t)nb * c.npw, nn = (size_t)nb * nb;
   hipLaunchKernelGGL(k_g_prep, dim3((unsigned)grid_for(nn + 2 * band)), dim3(256), 0, c.stream, nb,
-                     c.d_SS, c.d_gram, c.d_D, c.d_m1, 2 * band, dbl(c.d_S), dbl(c.d_Pt), c.d_gstate, tslot);
+                     c.d_SS, c.d_gram, c.d_D, c.d_m1, 2 * band, dbl(c.d_S), dbl(c.d_Pt), c.d_gstate,
+                     alt ? 0 : 1);
   ROKS_HIP(hipGetLastError());
   launch_chol_expm_lds(c, c.d_gram, 1.0, 0.0, c.d_Linv, c.d_flag, c.d_m1, 1.0, U);
   gemm_small(c, nb, nb, nb, U, nb, true, c.d_Linv, nb, false, M, nb, 1.0, 0.0);
@@ -310,46 +355,44 @@ static void graph_step(Ctx& c, int step, bool carry) {
   double* wgb = gs + gNSlots;          // [nb] <w_n|g_n>
   double* asymD = gs + gNSlots + nb;   // [1] sum D_old (theta - theta^T)
   band_dots_asym(c, c.d_w1, c.d_gI, nb, wgb, nullptr, c.d_Dold, c.d_theta, asymD, nullptr);
-  hipLaunchKernelGGL(k_g_beta, dim3(1), dim3(64), 0, c.stream, c.d_cg + 8, c.d_cg, wgb, asymD,
-                     c.d_bandv + nb, nb, gs);
-  ROKS_HIP(hipGetLastError());
-  // S = p + beta S_old', D = A + beta D_old
-  hipLaunchKernelGGL(k_g_axpy, dim3((unsigned)grid_for(2 * band)), dim3(256), 0, c.stream, 2 * band,
-                     dbl(c.d_p), dbl(c.d_w1), dbl(c.d_S), gs, (int)gBeta);
-  hipLaunchKernelGGL(k_g_axpy, dim3((unsigned)grid_for(nn)), dim3(256), 0, c.stream, nn, c.d_A, c.d_Dold,
-                     c.d_D, gs, (int)gBeta);
+  // beta, dE0 and the directions S = p + beta S_old', D = A + beta D_old
+  hipLaunchKernelGGL(k_g_directions, dim3((unsigned)grid_for(2 * band + nn)), dim3(256), 0, c.stream,
+                     c.d_cg + 8, c.d_cg, wgb, asymD, c.d_bandv + nb, nb, gs, 2 * band, dbl(c.d_p),
+                     dbl(c.d_w1), dbl(c.d_S), nn, c.d_A, c.d_Dold, c.d_D);
   ROKS_HIP(hipGetLastError());
   gemm_wdot(c, nb, nb, K, dbl(c.d_S), K, dbl(c.d_S), K, c.d_SS, nb, 1.0, 0.0, true);
   // the two trials of the line search's first attempt (reading R7)
-  graph_trial(c, gT, c.d_trial[0], c.d_M, c.d_U, true, gEt, gOkT);
-  hipLaunchKernelGGL(k_g_parabola, dim3(1), dim3(64), 0, c.stream, gs);
-  ROKS_HIP(hipGetLastError());
-  graph_trial(c, gTs, c.d_trial[1], c.d_Mkeep, c.d_Ukeep, false, gEts, gOkTs);
-  hipLaunchKernelGGL(k_g_accept, dim3(1), dim3(64), 0, c.stream, gs);
-  ROKS_HIP(hipGetLastError());
-  // commit when accepted: psi (and, for the first trial, its potentials and
-  // projections; the second trial's are in place), then S_old = M^T S and
-  // D_old = U^T D U of the trial kept (formed in scratch, copied only when
-  // accepted)
-  take(c, 2 * band, dbl(c.d_trial[0]), dbl(c.d_trial[1]), dbl(c.d_psi), 1, 0);
+  graph_trial(c, c.d_trial[0], c.d_M, c.d_U, true, gEt, gOkT);
+  graph_trial(c, c.d_trial[1], c.d_Mkeep, c.d_Ukeep, false, gEts, gOkTs);
+  // the choice, and the copies that depend on it: psi (and, for the first
+  // trial, its potentials, projections and band energies; the second
+  // trial's are in place) when accepted, M and U of the trial kept into
+  // scratch
   const size_t ng = (size_t)c.ntot;
-  take(c, (size_t)c.nsocc * ng, c.d_gvsh, c.d_vsh, c.d_vsh, 1, 1);
-  take(c, (size_t)2 * c.nconf * ng, c.d_gvloc, c.d_vloc, c.d_vloc, 1, 1);
+  SegList a;
+  a.add(c.d_trial[0], c.d_trial[1], c.d_psi, band * sizeof(double2), kAccepted);
+  a.add(c.d_gvsh, c.d_vsh, c.d_vsh, c.nsocc * ng * sizeof(double), kFirstTaken);
+  a.add(c.d_gvloc, c.d_vloc, c.d_vloc, 2 * c.nconf * ng * sizeof(double), kFirstTaken);
   if (c.prec == ROKS_FP32) {
-    take(c, (size_t)c.nsocc * ng, c.d_gvsh32, c.d_vsh32, c.d_vsh32, 1, 1);
-    take(c, (size_t)2 * c.nconf * ng, c.d_gvloc32, c.d_vloc32, c.d_vloc32, 1, 1);
+    a.add(c.d_gvsh32, c.d_vsh32, c.d_vsh32, c.nsocc * ng * sizeof(float), kFirstTaken);
+    a.add(c.d_gvloc32, c.d_vloc32, c.d_vloc32, 2 * c.nconf * ng * sizeof(float), kFirstTaken);
   }
-  if (c.nproj > 0) take(c, (size_t)c.nproj * nb, c.d_gP, c.d_P, c.d_P, 1, 1);
-  take(c, (size_t)2 * nb, c.d_gscal + 16, c.d_scal + 16, c.d_scal + 16, 1, 1);
-  take(c, nn, c.d_M, c.d_Mkeep, c.d_m3, 0, 0);
-  take(c, nn, c.d_U, c.d_Ukeep, c.d_m4, 0, 0);
+  if (c.nproj > 0) a.add(c.d_gP, c.d_P, c.d_P, (size_t)c.nproj * nb * sizeof(double), kFirstTaken);
+  a.add(c.d_gscal + 16, c.d_scal + 16, c.d_scal + 16, 2 * (size_t)nb * sizeof(double), kFirstTaken);
+  a.add(c.d_M, c.d_Mkeep, c.d_m3, nn * sizeof(double), kAlways);
+  a.add(c.d_U, c.d_Ukeep, c.d_m4, nn * sizeof(double), kAlways);
+  hipLaunchKernelGGL(k_g_accept, dim3(a.grid()), dim3(256), 0, c.stream, gs, a.g);
+  ROKS_HIP(hipGetLastError());
+  // S_old = M^T S and D_old = U^T D U of the trial kept (formed in scratch,
+  // copied in only when accepted)
   gemm_expand(c, nb, K, nb, c.d_m3, nb, true, dbl(c.d_S), K, dbl(c.d_trial[0]), K, 1.0, 0.0);
-  take(c, 2 * band, dbl(c.d_trial[0]), dbl(c.d_trial[0]), dbl(c.d_Sold), 1, 0);
   gemm_small(c, nb, nb, nb, c.d_D, nb, false, c.d_m4, nb, false, c.d_m2, nb, 1.0, 0.0);
   gemm_small(c, nb, nb, nb, c.d_m4, nb, true, c.d_m2, nb, false, c.d_m1, nb, 1.0, 0.0);
-  take(c, nn, c.d_m1, c.d_m1, c.d_Dold, 1, 0);
-  hipLaunchKernelGGL(k_g_finish, dim3(1), dim3(64), 0, c.stream, gs, c.hd_grec + (size_t)step * kRecLen,
-                     c.hd_gmirror, kDtMin, kDtMax);
+  SegList f;
+  f.add(c.d_trial[0], c.d_trial[0], c.d_Sold, band * sizeof(double2), kAccepted);
+  f.add(c.d_m1, c.d_m1, c.d_Dold, nn * sizeof(double), kAccepted);
+  hipLaunchKernelGGL(k_g_finish, dim3(f.grid()), dim3(256), 0, c.stream, gs, f.g,
+                     c.hd_grec + (size_t)step * kRecLen, c.hd_gmirror, kDtMin, kDtMax);
   ROKS_HIP(hipGetLastError());
   c.potentials_valid = false;
 }
