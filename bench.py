@@ -394,10 +394,10 @@ def batch_report(steps=8, workers=8):
 def cg_graph_report(steps=8, workers=8):
     """CG iterations in graph mode (every decision on the device, k
     iterations captured once per context and replayed) against the same
-    iterations driven from the host, FP32 tier: the uneven batch members of
-    at most 78 bands (one graph per member, replayed on the workers'
-    streams), and one of them alone on its own stream."""
-    systems = [s for s in inputs.batch_systems() if s["nbands"] <= 78]
+    iterations driven from the host, FP32 tier: the 32 uneven batch members
+    (one graph per member, replayed on the workers' streams), and the
+    smallest alone on its own stream."""
+    systems = sorted(inputs.batch_systems(), key=lambda s: s["nbands"])
 
     def make():
         out = []
@@ -453,6 +453,39 @@ def cg_graph_report(steps=8, workers=8):
                      "accepted": a1}
     for r in host + graph:
         r.close()
+    return res
+
+
+def oxide_graph_report(system, steps=4):
+    """Graph mode on the oxide supercell (FP64): `steps` CG iterations
+    replayed from one graph against the same iterations driven from the
+    host, from the same start (forces not included)."""
+    res = {}
+    for mode in ("host", "graph"):
+        r = rb.Roks(system)
+        r.set_coeffs(inputs.random_coefficients(r.miller(), system["cell"], r.nb, system["seed"]), True)
+        if mode == "host":
+            r.pcg_step()
+            r.synchronize()
+            t0 = time.perf_counter()
+            infos = [r.pcg_step() for _ in range(steps)]
+            r.synchronize()
+        else:
+            r.pcg_step()
+            r.graph_steps(steps)  # capture (and one replay)
+            r.reset_cg()
+            r.set_coeffs(inputs.random_coefficients(r.miller(), system["cell"], r.nb,
+                                                    system["seed"]), True)
+            r.pcg_step()
+            r.synchronize()
+            t0 = time.perf_counter()
+            acc, infos = r.graph_steps(steps)
+            res["graph_accepted"] = acc
+        res[mode + "_ms_per_iteration"] = 1e3 * (time.perf_counter() - t0) / steps
+        res[mode + "_E1"] = infos[-1]["E1"]
+        r.close()
+    res["speedup"] = res["host_ms_per_iteration"] / res["graph_ms_per_iteration"]
+    res["nbands"] = system["nbands"]
     return res
 
 
@@ -677,6 +710,7 @@ def main():
             **{k: tq[k] for k in ("band_applies_per_s", "ms_per_step", "roofline")},
             "cost_vs_s_equal_1": tq["ms_per_step"] / head["ms_per_step"]
             if args.tier == "fp64" else None}
+        out["oxide_graph_cg"] = oxide_graph_report(system)
         mol = inputs.molecule_box()
         m = measure(mol, rb.FP64, max(args.steps, 20), args.warmup, table_steps=10)
         out["molecule_64"] = {

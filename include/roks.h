@@ -329,10 +329,12 @@ roks_status roks_pcg_step(roks_ctx ctx, roks_step_info* info);
  * step and steepest-descent retry graph mode does not take.  info (nullable)
  * receives k records (stalled = 1 from the first rejected one; evaluations
  * 2 for each iteration run before the halt).  Within rounding the results
- * are those of roks_pcg_step (the trial projections are formed from the
- * trial orbitals, the energy of each iteration's orbitals is evaluated
- * again instead of kept from the trial).  Scope (else ROKS_ERR_STATE): at
- * most 78 bands, the FP64 or FP32 tier, no exact exchange, overlap
+ * are those of roks_pcg_step (the first trial's potentials are formed too
+ * and kept when it is taken, the energy of the orbitals a replay starts
+ * from is evaluated again, and past 78 bands the trial rotation exp(delta
+ * D) takes a Taylor polynomial of degree 18 and the squarings (at most 12,
+ * else the trial fails) chosen on the device).  Scope (else
+ * ROKS_ERR_STATE): the FP64 or FP32 tier, no exact exchange, overlap
  * coefficients, network, recording, periodic restart, canonicalisation or
  * autotuning; ROKS_ERR_ARG for k outside 1 .. 100000.  The call
  * synchronizes the context's stream; the first call for a k also runs one

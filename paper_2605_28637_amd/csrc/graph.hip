@@ -1,6 +1,7 @@
 // Graph mode: CG iterations whose every decision is taken on the device, so
-// that k of them form one fixed launch sequence, captured once as a HIP graph
-// and replayed (one context, or every context of a batch in one graph).
+// that k of them form one fixed launch sequence, captured once per context as
+// a HIP graph and replayed (for a batch, each context's graph on its worker's
+// stream).
 //
 // The iteration is roks_pcg_step's (Eqs. orbital_update, cg_search,
 // prec_grad_I, prec_k and the conjugated rotation; readings R1-R7, R9) with
@@ -12,18 +13,20 @@
 // the lower trial and its acceptance below E(0), and the new step length.
 // Each trial is formed as on the host (Cholesky of I + t^2 <S|S>, exp(t D),
 // M^T (psi + t S)) with the scaled inputs prepared by small kernels that read
-// t, so the existing launchers run with constant arguments; the projections
-// of a trial are recomputed from its orbitals.  The commit (new orbitals,
-// carried directions S_old = M S, D_old = U^T D U) is a set of copies made
-// only when the device accepted the step, so a rejected step leaves the state
-// as it was and the iterations after it repeat the same rejected search.
-// What the host path does beyond this (halving the trial step, the steepest
-// descent retry after a failed search) is left to it: the caller sees the
-// first rejected iteration and continues with roks_pcg_step.
+// t, so the existing launchers run with constant arguments; a trial's
+// projections are M^T-rotated from those of psi + t S, as on the host.  Past
+// 78 bands the exponential
+// takes a fixed Taylor degree and a squaring count chosen on the device
+// (squaring launches past it undone), where the host chooses both from the
+// norm.  The commit (new orbitals, carried directions S_old = M S, D_old =
+// U^T D U, and the potentials of the trial taken) is a set of copies made
+// only when the device accepted the step.  The first rejected step halts the
+// replay (later iterations commit nothing); what the host path does then
+// (halving the trial step, the steepest descent retry) is left to it: the
+// caller sees the first rejected iteration and continues with roks_pcg_step.
 //
-// Scope (checked before capture): up to 78 bands (the single-workgroup
-// Cholesky and exponential), FP64 or FP32 tier, LDA or PBE without exact
-// exchange, no overlap coefficients, no network, no recording, no
+// Scope (checked before capture): FP64 or FP32 tier, LDA or PBE without
+// exact exchange, no overlap coefficients, no network, no recording, no
 // canonicalisation, no periodic restart, no autotuning.
 #include <cmath>
 #include <cstring>
@@ -37,7 +40,7 @@ namespace {
 // slots of the device state block
 enum : int {
   gE0 = 0, gEt, gEts, gT, gTs, gDt, gPg, gPgOld, gBeta, gDE0, gDelta, gE1, gHaveOld, gAccept,
-  gBest, gOkT, gOkTs, gHalt, gNormG, gRestart, gNSlots
+  gBest, gOkT, gOkTs, gHalt, gNormG, gRestart, gNormD, gSq, gNSlots
 };
 constexpr int kRecLen = 8;  // per iteration: E0, E1, delta, beta, dE0, accepted, |g_I|, restarted
 
@@ -150,13 +153,15 @@ __device__ inline double parabola_step(const double* gs) {
 }
 
 // the scaled inputs of a trial: gram = t^2 <S|S> + I, Dt = t D (n x n),
-// St = t S (m values), at t = gs[gT] (first trial) or at the parabola's step
-// (second trial, stored in gs[gTs])
+// St = t S (m values), PSt = t <beta|S> (mp values), at t = gs[gT] (first
+// trial) or at the parabola's step (second trial, stored in gs[gTs])
 __global__ void __launch_bounds__(256) k_g_prep(int nb, const double* __restrict__ SS,
                                                 double* __restrict__ gram, const double* __restrict__ D,
                                                 double* __restrict__ Dt, size_t m,
                                                 const double* __restrict__ S, double* __restrict__ St,
-                                                double* __restrict__ gs, int second) {
+                                                size_t mp, const double* __restrict__ PS,
+                                                double* __restrict__ PSt, double* __restrict__ gs,
+                                                int second) {
   __shared__ double st;
   if (threadIdx.x == 0) {
     st = second ? parabola_step(gs) : gs[gT];
@@ -166,16 +171,63 @@ __global__ void __launch_bounds__(256) k_g_prep(int nb, const double* __restrict
   const double t = st;
   const double t2 = t * t;
   const size_t nn = (size_t)nb * nb;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nn + m;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nn + m + mp;
        i += (size_t)gridDim.x * blockDim.x) {
     if (i < nn) {
       const int r = (int)(i / nb), q = (int)(i - (size_t)r * nb);
       gram[i] = t2 * SS[i] + (r == q ? 1.0 : 0.0);
-      Dt[i] = t * D[i];
-    } else {
+      if (Dt) Dt[i] = t * D[i];
+    } else if (i < nn + m) {
       St[i - nn] = t * S[i - nn];
+    } else {
+      PSt[i - nn - m] = t * PS[i - nn - m];
     }
   }
+}
+
+// Past the single-workgroup exponential: exp(X) by scaling and squaring
+// around a Taylor polynomial of fixed degree kTaylor (the launches are fixed)
+// with a squaring count s chosen on the device, the smallest with
+// ||X||_1 / 2^s <= 1 (so the truncation error stays below
+// 1 / (kTaylor + 1)! < 1e-17); kSqMax squaring launches, those past s undone.
+// A count past kSqMax or a non-finite norm marks the trial failed (flag).
+constexpr int kTaylor = 18;
+constexpr int kSqMax = 12;
+
+// X = t D / 2^s at the trial's t (gs[gTs] for the second trial)
+__global__ void __launch_bounds__(256) k_g_expm_prep(int n, const double* __restrict__ D,
+                                                     double* __restrict__ X, double* __restrict__ gs,
+                                                     int second, int32_t* __restrict__ flag) {
+  __shared__ double sc;
+  if (threadIdx.x == 0) {
+    const double t = second ? gs[gTs] : gs[gT];
+    double nrm = fabs(t) * gs[gNormD];
+    int sq = 0;
+    while (nrm > 1.0 && sq <= kSqMax) {
+      nrm *= 0.5;
+      ++sq;
+    }
+    const bool ok = isfinite(nrm) && sq <= kSqMax;
+    sc = ok ? ldexp(t, -sq) : 0.0;
+    if (blockIdx.x == 0) {
+      gs[gSq] = ok ? sq : 0;
+      if (!ok) flag[0] |= 2;
+    }
+  }
+  __syncthreads();
+  const double f = sc;
+  const size_t nn = (size_t)n * n;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nn; i += (size_t)gridDim.x * blockDim.x)
+    X[i] = f * D[i];
+}
+
+// squaring number `index`: kept only when index < s, else its input stays
+__global__ void __launch_bounds__(256) k_g_keep(size_t nn, double* __restrict__ nxt,
+                                                const double* __restrict__ cur,
+                                                const double* __restrict__ gs, int index) {
+  if (index < (int)gs[gSq]) return;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nn; i += (size_t)gridDim.x * blockDim.x)
+    nxt[i] = cur[i];
 }
 
 // conditional copies dst = (best ? t1 : t0), in 4-byte words: always, when
@@ -299,19 +351,53 @@ static void graph_trial(Ctx& c, double2* out, double* M, double* U, bool alt, in
                         int okslot) {
   const int nb = c.nb, K = 2 * c.npw;
   const size_t band = (size_t)nb * c.npw, nn = (size_t)nb * nb;
-  hipLaunchKernelGGL(k_g_prep, dim3((unsigned)grid_for(nn + 2 * band)), dim3(256), 0, c.stream, nb,
-                     c.d_SS, c.d_gram, c.d_D, c.d_m1, 2 * band, dbl(c.d_S), dbl(c.d_Pt), c.d_gstate,
-                     alt ? 0 : 1);
+  const bool lds = expm_in_lds(c);
+  const size_t mp = (size_t)c.nproj * nb;
+  hipLaunchKernelGGL(k_g_prep, dim3((unsigned)grid_for(nn + 2 * band + mp)), dim3(256), 0, c.stream, nb,
+                     c.d_SS, c.d_gram, c.d_D, lds ? c.d_m1 : nullptr, 2 * band, dbl(c.d_S), dbl(c.d_Pt),
+                     mp, c.d_PS, c.d_gPSt, c.d_gstate, alt ? 0 : 1);
   ROKS_HIP(hipGetLastError());
-  launch_chol_expm_lds(c, c.d_gram, 1.0, 0.0, c.d_Linv, c.d_flag, c.d_m1, 1.0, U);
+  if (lds) {
+    launch_chol_expm_lds(c, c.d_gram, 1.0, 0.0, c.d_Linv, c.d_flag, c.d_m1, 1.0, U);
+  } else {
+    // the factorisation first (its panels use d_m1 .. d_m4 as scratch)
+    cholesky_inverse(c, c.d_gram, nb, c.d_Linv, c.d_flag);
+    hipLaunchKernelGGL(k_g_expm_prep, dim3((unsigned)grid_for(nn)), dim3(256), 0, c.stream, nb, c.d_D,
+                       c.d_m1, c.d_gstate, alt ? 0 : 1, c.d_flag);
+    ROKS_HIP(hipGetLastError());
+    // P_m = I + X / m, P_q = I + X P_{q+1} / q, ..., P_1
+    set_identity(c, c.d_m2, nb, 1.0);
+    axpby(c, nn, 1.0 / kTaylor, c.d_m1, 1.0, c.d_m2, c.d_m2);
+    double* cur = c.d_m2;
+    double* nxt = c.d_m4;
+    for (int q = kTaylor - 1; q >= 1; --q) {
+      gemm_small(c, nb, nb, nb, c.d_m1, nb, false, cur, nb, false, nxt, nb, 1.0 / q, 0.0, 1.0);
+      std::swap(cur, nxt);
+    }
+    for (int i = 0; i < kSqMax; ++i) {
+      gemm_small(c, nb, nb, nb, cur, nb, false, cur, nb, false, nxt, nb, 1.0, 0.0);
+      hipLaunchKernelGGL(k_g_keep, dim3((unsigned)grid_for(nn)), dim3(256), 0, c.stream, nn, nxt, cur,
+                         c.d_gstate, i);
+      ROKS_HIP(hipGetLastError());
+      std::swap(cur, nxt);
+    }
+    copy_dev(c, U, cur, nn * sizeof(double));
+  }
   gemm_small(c, nb, nb, nb, U, nb, true, c.d_Linv, nb, false, M, nb, 1.0, 0.0);
   gemm_expand_sum(c, nb, K, nb, M, nb, true, dbl(c.d_psi), dbl(c.d_Pt), 1.0, K, dbl(out), K, dbl(out),
                   K, 1.0, 0.0);
+  // the trial's projections M^T-rotated from those of psi + t S (P0 + t PS)
+  auto evaluate = [&]() {
+    if (c.nproj > 0)
+      gemm_small2(c, c.nproj, nb, nb, c.d_P0, c.d_gPSt, 1.0, nb, false, M, nb, true, c.d_P, nb, 1.0, 0.0,
+                  0.0);
+    compute_potentials_async(c, out, true, false);
+  };
   if (alt) {
     AltPotentials swap(c);
-    compute_potentials_async(c, out, false, false);
+    evaluate();
   } else {
-    compute_potentials_async(c, out, false, false);
+    evaluate();
   }
   hipLaunchKernelGGL(k_g_energy, dim3(1), dim3(64), 0, c.stream, alt ? c.d_gscal : c.d_scal, nb, c.nconf,
                      c.d_gfocc, c.cL[0], c.cL[1], c.omega / (double)c.ntot, 0, c.d_flag, c.d_gstate,
@@ -322,6 +408,11 @@ static void graph_trial(Ctx& c, double2* out, double* M, double* U, bool alt, in
 // carry: the previous iteration (of the same graph) left the potentials and
 // projections of the orbitals it accepted, and their energy, in place
 static void graph_step(Ctx& c, int step, bool carry) {
+  struct InGraph {
+    Ctx& c;
+    InGraph(Ctx& cc) : c(cc) { c.in_graph = true; }
+    ~InGraph() { c.in_graph = false; }
+  } in_graph(c);
   const int nb = c.nb, K = 2 * c.npw;
   const size_t band = (size_t)nb * c.npw, nn = (size_t)nb * nb;
   double* gs = c.d_gstate;
@@ -361,6 +452,13 @@ static void graph_step(Ctx& c, int step, bool carry) {
                      dbl(c.d_w1), dbl(c.d_S), nn, c.d_A, c.d_Dold, c.d_D);
   ROKS_HIP(hipGetLastError());
   gemm_wdot(c, nb, nb, K, dbl(c.d_S), K, dbl(c.d_S), K, c.d_SS, nb, 1.0, 0.0, true);
+  if (!expm_in_lds(c)) matrix_norm1(c, c.d_D, nb, gs + gNormD);
+  if (c.nproj > 0) {
+    // <beta|S> once per search, and the projections of psi kept as P0 (the
+    // trials write d_P)
+    proj_wdot(c, nb, dbl(c.d_S), K, c.d_PS, nb);
+    copy_dev(c, c.d_P0, c.d_P, (size_t)c.nproj * nb * sizeof(double));
+  }
   // the two trials of the line search's first attempt (reading R7)
   graph_trial(c, c.d_trial[0], c.d_M, c.d_U, true, gEt, gOkT);
   graph_trial(c, c.d_trial[1], c.d_Mkeep, c.d_Ukeep, false, gEts, gOkTs);
@@ -404,8 +502,6 @@ namespace {
 
 void graph_check(const Ctx& c) {
   ROKS_CHECK(c.have_orbitals, ROKS_ERR_STATE, "no orbitals set");
-  ROKS_CHECK(expm_in_lds(c), ROKS_ERR_STATE,
-             "graph mode takes at most 78 bands (the single-workgroup Cholesky and exponential)");
   ROKS_CHECK(!c.bf3 && (c.prec == ROKS_FP64 || c.prec == ROKS_FP32), ROKS_ERR_STATE,
              "graph mode runs in the FP64 or FP32 tier");
   ROKS_CHECK(c.exx == 0.0 && !c.has_q && !c.mlp && c.rec_max == 0, ROKS_ERR_STATE,
@@ -429,6 +525,7 @@ void graph_buffers(Ctx& c, int k) {
     c.d_gvloc = dalloc<double>(c, (size_t)2 * c.nconf * c.ntot);
     c.d_gP = dalloc<double>(c, (size_t)std::max(1, c.nproj) * nb);
     c.d_gscal = dalloc<double>(c, 16 + 2 * (size_t)nb);
+    c.d_gPSt = dalloc<double>(c, (size_t)std::max(1, c.nproj) * nb);
     ROKS_HIP(hipMemcpyAsync(c.d_gfocc, focc.data(), focc.size() * sizeof(double), hipMemcpyHostToDevice,
                             c.stream));
     ROKS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_gmirror), gNSlots * sizeof(double),
@@ -564,7 +661,7 @@ void free_graph_mode(Ctx& c) {
     if (h) (void)hipHostFree(h);
   c.h_gmirror = c.hd_gmirror = c.h_grec = c.hd_grec = nullptr;
   c.grec_cap = 0;
-  c.d_gstate = c.d_gfocc = c.d_gvsh = c.d_gvloc = c.d_gP = c.d_gscal = nullptr;  // freed with the others
+  c.d_gstate = c.d_gfocc = c.d_gvsh = c.d_gvloc = c.d_gP = c.d_gscal = c.d_gPSt = nullptr;  // freed with the others
   c.d_gvsh32 = c.d_gvloc32 = nullptr;
 }
 

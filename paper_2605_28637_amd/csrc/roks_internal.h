@@ -144,6 +144,7 @@ struct Ctx {
   std::vector<DevBuf> allocations;
   bool have_orbitals = false;
   bool potentials_valid = false;
+  bool in_graph = false;  // launches being made for graph mode (one stream)
 
   // device arrays (FP64 tier; FP32 copies live in the *_f32 members)
   int32_t* d_miller = nullptr;
@@ -283,6 +284,7 @@ struct Ctx {
   float* d_gvloc32 = nullptr;
   double* d_gP = nullptr;
   double* d_gscal = nullptr;       // reduced sums, as d_scal
+  double* d_gPSt = nullptr;        // t <beta|S> of a trial
   double* h_gmirror = nullptr;     // pinned copy of the state block
   double* hd_gmirror = nullptr;    // its device view
   double* h_grec = nullptr;        // pinned per-iteration records

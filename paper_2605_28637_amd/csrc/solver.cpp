@@ -203,8 +203,9 @@ void compute_potentials_async(Ctx& c, const double2* orb, bool have_P, bool ener
     exx_energies(c);
   }
   // with the projections at hand, the band kinetic and nonlocal energies run
-  // on the side stream beside the Hartree and xc chain (they need neither)
-  const bool side = have_P;
+  // on the side stream beside the Hartree and xc chain (they need neither;
+  // graph mode keeps every launch on one stream)
+  const bool side = have_P && !c.in_graph;
   if (side) {
     ensure_side_stream(c);
     ROKS_HIP(hipEventRecord(c.ev_fork, c.stream));
@@ -246,7 +247,7 @@ void compute_potentials_async(Ctx& c, const double2* orb, bool have_P, bool ener
   }
   band_dots2(c, orb, orb, nb, nullptr, c.d_kin, nullptr, c.hd_scal + 16);
   if (c.nproj > 0) {
-    proj_wdot(c, nb, dbl(orb), K, c.d_P, nb);
+    if (!have_P) proj_wdot(c, nb, dbl(orb), K, c.d_P, nb);
     launch_nl_energy(c, c.d_P, c.d_enl, c.hd_scal + 16 + nb);
   }
 }

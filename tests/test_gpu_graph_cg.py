@@ -2,10 +2,12 @@
 captured HIP graph (roks_graph_steps), against the oracle's CG (Sec. II A,
 readings R1-R7, R9) and against the host-driven roks_pcg_step: the same
 equations and the same first line-search attempt, within rounding (the
-trial projections come from the trial orbitals, and each iteration's energy
-is evaluated again instead of being kept from the trial).  Graphs are
-replayed several times, with host steps (which trade the orbital buffers)
-in between, in both tiers, and for a batch of uneven systems."""
+first trial's potentials are formed and kept when it is taken, and past 78
+bands the
+trial rotation takes a fixed Taylor degree).  Graphs are replayed several
+times, with host steps (which trade the orbital buffers) in between, in
+both tiers, past the single-workgroup rotation and factorisation, and for a
+batch of uneven systems."""
 import numpy as np
 import pytest
 
@@ -57,6 +59,41 @@ def test_graph_steps_match_the_oracle(case):
     Fo = orc.forces(m, st.psi)
     assert np.abs(F - Fo).max() < 1e-8 * max(1.0, np.abs(Fo).max())
     g.close()
+
+
+@pytest.mark.parametrize("nb", [90, 140])
+def test_graph_steps_with_many_bands_match_the_oracle(nb):
+    """Past 78 bands the trial rotation takes the fixed-degree exponential
+    with the squarings chosen on the device, and at 140 the trial Gram
+    matrix the panel factorisation: two graph iterations against the
+    oracle's at the FP64 bar, then a replay against host steps."""
+    rb = ensure_built()
+    s = small_molecule(nb=nb)
+    print("graph many-band case", nb, flush=True)
+    g = _ctx(rb, s)
+    m = orc.Model(s)
+    mp = SphereMap(g.miller(), m.miller)
+    st = orc.CGState(psi=orc.orthonormalize(
+        inputs.random_coefficients(m.miller, m.cell, m.nb, s["seed"])))
+    acc, recs = g.graph_steps(2)
+    assert acc == 2
+    for i, r in enumerate(recs):
+        oi = orc.pcg_step(m, st)
+        scale = max(1.0, abs(oi.E0))
+        print(i, r["E0"], oi.E0, r["E1"], oi.E1, r["delta"], oi.delta, flush=True)
+        assert abs(r["E0"] - oi.E0) < TOL * scale, i
+        assert abs(r["E1"] - oi.E1) < TOL * scale, i
+        assert abs(r["delta"] - oi.delta) < 1e-8 * max(1.0, oi.delta), i
+    assert band_rel(mp.to_full(g.get_coeffs()), st.psi) < 1e-8
+    h = _ctx(rb, s)
+    ref = [h.pcg_step() for _ in range(4)]
+    acc, recs = g.graph_steps(2)
+    assert acc == 2
+    for x, y in zip(recs, ref[2:]):
+        assert abs(x["E1"] - y["E1"]) < TOL * max(1.0, abs(y["E0"]))
+    assert band_rel(g.get_coeffs(), h.get_coeffs()) < 1e-8
+    g.close()
+    h.close()
 
 
 def test_replays_interleaved_with_host_steps():
@@ -117,25 +154,24 @@ def test_fp32_tier_graph_steps_follow_the_host_steps():
 
 
 def test_batch_graph_steps_follow_the_batch_steps():
-    """The uneven batch members of at most 78 bands: one graph per member,
-    replayed on the workers' streams, against host steps of the same batch
-    on twin contexts; members past 78 bands are refused per member
-    (ROKS_ERR_STATE) without stopping the others."""
+    """Uneven batch members (up to and past 78 bands): one graph per member,
+    replayed on the workers' streams, against host steps on twin contexts;
+    a member outside graph mode's scope (exact exchange) is refused with
+    ROKS_ERR_STATE without stopping the others."""
     rb = ensure_built()
     systems = inputs.batch_systems(count=12)
     systems.sort(key=lambda s: s["nbands"])
-    small = [s for s in systems if s["nbands"] <= 78][:4]
-    big = [s for s in systems if s["nbands"] > 78][:1]
-    members = small + big
-    print("graph batch", [(s["grid"][0], s["nbands"]) for s in members], flush=True)
-    par = [_ctx(rb, s, rb.FP32) for s in members]
+    small = [s for s in systems if s["nbands"] <= 78][:3] + [s for s in systems if s["nbands"] > 78][:1]
+    bad = [dict(inputs.tiny_cell(), xc="pbe", exx=0.25)]
+    print("graph batch", [(s["grid"][0], s["nbands"]) for s in small], flush=True)
+    par = [_ctx(rb, s, rb.FP32) for s in small + bad]
     seq = [_ctx(rb, s, rb.FP32) for s in small]
     b = rb.Batch(par, workers=4)
     for _ in range(2):
         st, acc = b.graph_steps(3)
         assert st[: len(small)] == [0] * len(small)
         assert acc[: len(small)] == [3] * len(small)
-        assert st[len(small):] == [8] * len(big)
+        assert st[len(small):] == [8] * len(bad)
     for r in seq:
         for _ in range(6):
             r.pcg_step()
