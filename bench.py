@@ -140,10 +140,10 @@ def cpu_baseline(system, nsample=12):
                       "not in the rate" % (len(idx), m.nb, cores, t_pot)}
 
 
-def _converge(rb_system, c0, tol, precision, net, restart, switch_tol=1e-5, maxiter=3000):
+def _converge(rb_system, c0, tol, precision, net, restart, switch_tol=1e-5, maxiter=3000, flags=0):
     """One solve: FP32 iterations to |dE| < switch_tol, then FP64 to tol (a pure
     FP64 solve when precision is FP64)."""
-    r = rb.Roks(rb_system, precision=precision)
+    r = rb.Roks(rb_system, precision=precision, flags=flags)
     r.set_coeffs(c0, True)
     r.set_restart(restart)
     if net is not None:
@@ -189,7 +189,7 @@ def _judged(r, info, tol, net, restart, max_rounds=6, maxiter=3000):
         E = i2["E1"]
 
 
-def time_to_converge(system, tol, precision, net, restart):
+def time_to_converge(system, tol, precision, net, restart, flags=0):
     """Ground state from the seeded start, then the singlet from the
     ground-state orbitals, each judged by plain FP64 iterations, then the
     singlet forces; wall time of all of it."""
@@ -198,11 +198,11 @@ def time_to_converge(system, tol, precision, net, restart):
     c0 = inputs.random_coefficients(rg.miller(), gs["cell"], rg.nb, gs["seed"])
     rg.close()
     t0 = time.perf_counter()
-    rg, ig, itg = _converge(gs, c0, tol, precision, net, restart)
+    rg, ig, itg = _converge(gs, c0, tol, precision, net, restart, flags=flags)
     E_gs, jg, rounds_g, drift_g = _judged(rg, ig, tol, net, restart)
     c = rg.get_coeffs()
     rg.close()
-    r, ie, ite = _converge(system, c, tol, precision, net, restart)
+    r, ie, ite = _converge(system, c, tol, precision, net, restart, flags=flags)
     E_s, js, rounds_s, drift_s = _judged(r, ie, tol, net, restart)
     F = r.forces()
     r.synchronize()
@@ -216,7 +216,9 @@ def time_to_converge(system, tol, precision, net, restart):
             "tol_Ha": tol,
             "arithmetic": "fp32 tier to |dE| < 1e-5 Ha, then fp64" if precision == rb.FP32 else "fp64",
             "preconditioner": "learned rescaling of Teter" if net is not None else "Teter",
-            "cg_restart_period": restart}
+            "cg_restart_period": restart,
+            "iterations_driven": "graph mode (device decisions, replays of 8)"
+            if flags & rb.FLAG_GRAPH else "host"}
 
 
 def train_network(seeds, steps=600, lr=3e-3):
@@ -334,6 +336,13 @@ def converge_report(system, tol=1e-6):
         v["to_reference"] = time_to_reference(system, ref, prec, nn, rs)
         out[k] = v
     net.close()
+    # the plain variants again with their iterations in graph mode
+    for k, prec in (("plain_fp64_restart_graph", rb.FP64), ("mixed_plain_restart_graph", rb.FP32)):
+        v = time_to_converge(system, tol, prec, None, RESTART, flags=rb.FLAG_GRAPH)
+        F = v.pop("forces")
+        v["dE_singlet_vs_reference_Ha"] = v["E_singlet"] - ref["E_singlet"]
+        v["max_force_diff_vs_reference"] = float(np.abs(F - ref["forces"]).max())
+        out[k] = v
     out["training"] = tr
     sec = {k: out[k]["seconds"] for k in ("plain_fp64", "plain_fp64_restart", "mixed_plain_restart",
                                           "fp64_learned", "mixed_learned")}
@@ -342,7 +351,10 @@ def converge_report(system, tol=1e-6):
         "mixed_learned_vs_plain_fp64_restart": sec["plain_fp64_restart"] / sec["mixed_learned"],
         "learned_vs_plain_restart_fp64": sec["plain_fp64_restart"] / sec["fp64_learned"],
         "fp32_tier_vs_fp64_restart": sec["plain_fp64_restart"] / sec["mixed_plain_restart"],
-        "fp32_tier_with_learned_vs_fp64_learned": sec["fp64_learned"] / sec["mixed_learned"]}
+        "fp32_tier_with_learned_vs_fp64_learned": sec["fp64_learned"] / sec["mixed_learned"],
+        "graph_vs_host_fp64_restart": sec["plain_fp64_restart"] / out["plain_fp64_restart_graph"]["seconds"],
+        "graph_vs_host_fp32_tier_restart":
+            sec["mixed_plain_restart"] / out["mixed_plain_restart_graph"]["seconds"]}
     out["speedup_mixed_learned_vs_plain_fp64_to_reference"] = (
         out["plain_fp64"]["to_reference"]["seconds"] / out["mixed_learned"]["to_reference"]["seconds"])
     return out

@@ -114,7 +114,13 @@ enum {
    * temporary file and a rename) after every newly timed shape, so processes
    * that share the file make the same choices and agree bit for bit; an
    * unreadable or unwritable file only means timing again. */
-  ROKS_FLAG_AUTOTUNE = 8u
+  ROKS_FLAG_AUTOTUNE = 8u,
+  /* roks_solve (and so roks_batch_solve) runs its iterations in graph mode
+   * (roks_graph_steps, 8 at a time) while the context is within that mode's
+   * scope and at least 8 iterations remain, and a host step after a rejected
+   * one; the convergence test reads the records in order (iterations run
+   * past the point of convergence within a replay are counted). */
+  ROKS_FLAG_GRAPH = 16u
 };
 
 /* Separable Gaussian projector of one radial channel (Sec. II A, projector
@@ -335,8 +341,8 @@ roks_status roks_pcg_step(roks_ctx ctx, roks_step_info* info);
  * D) takes a Taylor polynomial of degree 18 and the squarings (at most 12,
  * else the trial fails) chosen on the device).  Scope (else
  * ROKS_ERR_STATE): the FP64 or FP32 tier, no exact exchange, overlap
- * coefficients, network, recording, periodic restart, canonicalisation or
- * autotuning; ROKS_ERR_ARG for k outside 1 .. 100000.  The call
+ * coefficients, network, recording, canonicalisation or autotuning
+ * (periodic restarts are taken on the device); ROKS_ERR_ARG for k outside 1 .. 100000.  The call
  * synchronizes the context's stream; the first call for a k also runs one
  * iteration that commits nothing (first-use set-up outside the capture). */
 roks_status roks_graph_steps(roks_ctx ctx, int32_t k, roks_step_info* info, int32_t* accepted);

@@ -380,9 +380,24 @@ roks_status roks_solve(roks_ctx ctx, double tol, int32_t maxiter, roks_step_info
   return guard(ctx, [&](roks::Ctx& c) {
     ROKS_CHECK(tol > 0 && maxiter > 0, ROKS_ERR_ARG, "tol and maxiter must be > 0");
     int hits = 0, it = 0;
-    bool retried = false, linesearch_failed = false;
+    bool retried = false, linesearch_failed = false, done = false;
     roks_step_info info{};
-    while (it < maxiter) {
+    constexpr int kChunk = 8;
+    roks_step_info recs[kChunk];
+    while (it < maxiter && !done) {
+      if ((c.flags & ROKS_FLAG_GRAPH) && it + kChunk <= maxiter && roks::graph_eligible(c)) {
+        // graph mode: the accepted iterations of one replay, in order; after
+        // a rejected one the host step below takes over
+        const int acc = roks::graph_steps(c, kChunk, recs);
+        for (int i = 0; i < acc; ++i) {
+          info = recs[i];
+          ++it;
+          retried = false;
+          hits = std::fabs(info.E1 - info.E0) < tol ? hits + 1 : 0;
+          if (hits >= 2) done = true;
+        }
+        if (done || acc == kChunk) continue;
+      }
       roks::pcg_step(c, &info);
       ++it;
       if (info.stalled) {

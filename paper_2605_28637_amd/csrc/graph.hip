@@ -27,7 +27,7 @@
 //
 // Scope (checked before capture): FP64 or FP32 tier, LDA or PBE without
 // exact exchange, no overlap coefficients, no network, no recording, no
-// canonicalisation, no periodic restart, no autotuning.
+// canonicalisation, no autotuning; periodic restarts are taken on the device.
 #include <cmath>
 #include <cstring>
 
@@ -40,7 +40,7 @@ namespace {
 // slots of the device state block
 enum : int {
   gE0 = 0, gEt, gEts, gT, gTs, gDt, gPg, gPgOld, gBeta, gDE0, gDelta, gE1, gHaveOld, gAccept,
-  gBest, gOkT, gOkTs, gHalt, gNormG, gRestart, gNormD, gSq, gNSlots
+  gBest, gOkT, gOkTs, gHalt, gNormG, gRestart, gNormD, gSq, gSince, gSinceNew, gPeriod, gNSlots
 };
 constexpr int kRecLen = 8;  // per iteration: E0, E1, delta, beta, dE0, accepted, |g_I|, restarted
 
@@ -111,11 +111,14 @@ __global__ void __launch_bounds__(256) k_g_directions(
     size_t n2, const double* __restrict__ A, const double* __restrict__ Dold, double* __restrict__ D) {
   __shared__ double sb;
   if (threadIdx.x == 0) {
+    // periodic restart (reading R23): every gPeriod steps the carried
+    // directions and the step length are dropped
+    const bool periodic = gs[gPeriod] > 0.0 && gs[gSince] >= gs[gPeriod];
     const double spg = band_sum(pgb, nb);
     const double swg = band_sum(wgb, nb);
     const double pg = add(spg, mul(0.5, asymA[0]));
     double beta = 0.0;
-    if (gs[gHaveOld] != 0.0 && gs[gPgOld] != 0.0) beta = dvd(pg, gs[gPgOld]);
+    if (!periodic && gs[gHaveOld] != 0.0 && gs[gPgOld] != 0.0) beta = dvd(pg, gs[gPgOld]);
     double dE0 = add(mul(2.0, add(spg, mul(beta, swg))), add(asymA[0], mul(beta, asymD[0])));
     const bool restart = beta != 0.0 && dE0 >= 0.0;
     if (restart) {
@@ -124,11 +127,12 @@ __global__ void __launch_bounds__(256) k_g_directions(
     }
     sb = beta;
     if (blockIdx.x == 0) {
-      gs[gRestart] = restart ? 1.0 : 0.0;
+      gs[gRestart] = (restart || periodic) ? 1.0 : 0.0;
       gs[gPg] = pg;
       gs[gBeta] = beta;
       gs[gDE0] = dE0;
-      gs[gT] = gs[gDt];
+      gs[gT] = periodic ? (double)kDtInit : gs[gDt];
+      gs[gSinceNew] = periodic ? 1.0 : gs[gSince] + 1.0;
       gs[gNormG] = sqrt(fmax(0.0, band_sum(gg, nb)));
     }
   }
@@ -293,6 +297,7 @@ __global__ void __launch_bounds__(256) k_g_finish(double* __restrict__ gs, Segs 
     gs[gPgOld] = gs[gPg];
     gs[gHaveOld] = 1.0;
     gs[gDt] = fmin(dt_max, fmax(dt_min, gs[gDelta]));
+    gs[gSince] = gs[gSinceNew];
   } else {
     gs[gHalt] = 1.0;
   }
@@ -506,7 +511,6 @@ void graph_check(const Ctx& c) {
              "graph mode runs in the FP64 or FP32 tier");
   ROKS_CHECK(c.exx == 0.0 && !c.has_q && !c.mlp && c.rec_max == 0, ROKS_ERR_STATE,
              "graph mode excludes exact exchange, overlap coefficients, a network and recording");
-  ROKS_CHECK(c.restart_period == 0, ROKS_ERR_STATE, "graph mode runs without periodic restarts");
   ROKS_CHECK(!(c.flags & (ROKS_FLAG_CANONICALIZE | ROKS_FLAG_AUTOTUNE)), ROKS_ERR_STATE,
              "graph mode excludes canonicalisation and autotuning");
 }
@@ -557,6 +561,8 @@ void graph_load_state(Ctx& c, bool halt) {
   s[gPgOld] = c.pg_old;
   s[gHaveOld] = c.have_old ? 1.0 : 0.0;
   s[gHalt] = halt ? 1.0 : 0.0;
+  s[gSince] = c.since_restart;
+  s[gPeriod] = c.restart_period;
   ROKS_HIP(hipMemcpyAsync(c.d_gstate, s, sizeof s, hipMemcpyHostToDevice, c.stream));
   if (!c.have_old) {
     // no carried direction: S_old and D_old enter with beta = 0, as zeros
@@ -649,6 +655,15 @@ void capture(Ctx& c, int k) {
 
 }  // namespace
 
+bool graph_eligible(const Ctx& c) {
+  try {
+    graph_check(c);
+  } catch (const Error&) {
+    return false;
+  }
+  return true;
+}
+
 void free_graph(Ctx& c) {
   if (c.graph_exec) (void)hipGraphExecDestroy(c.graph_exec);
   c.graph_exec = nullptr;
@@ -706,6 +721,7 @@ int graph_steps(Ctx& c, int k, roks_step_info* info) {
     c.dt = m[gDt];
     c.pg_old = m[gPgOld];
     c.have_old = true;
+    c.since_restart = (int)m[gSince];
     c.iteration += acc;
   }
   c.potentials_valid = false;

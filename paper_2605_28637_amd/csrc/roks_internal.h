@@ -632,6 +632,7 @@ void reset_cg(Ctx& c);
 // graph mode (graph.hip): k device-decided CG iterations replayed from one
 // captured graph; returns the leading accepted ones (info: k records)
 int graph_steps(Ctx& c, int k, roks_step_info* info);
+bool graph_eligible(const Ctx& c);  // within graph mode's scope
 void free_graph(Ctx& c);       // the captured graph
 void free_graph_mode(Ctx& c);  // and the pinned records
 

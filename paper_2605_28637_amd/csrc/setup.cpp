@@ -157,7 +157,7 @@ void build_problem(Ctx& c, const roks_system* s) {
   // the FFT tier; the projector products follow the BF16x3 flag
   c.prec = s->precision == ROKS_FP64 ? ROKS_FP64 : ROKS_FP32;
   c.bf3 = s->precision == ROKS_FP32_BF16X3;
-  ROKS_CHECK((s->flags & ~15u) == 0, ROKS_ERR_ARG, "unknown flag bits");
+  ROKS_CHECK((s->flags & ~31u) == 0, ROKS_ERR_ARG, "unknown flag bits");
   c.flags = s->flags;
 
   // shells: closed (all ones), open patterns by first appearance, virtual (all zeros)

@@ -22,6 +22,7 @@ FLAG_SUPPRESS_OPEN_COUPLING = 1
 FLAG_CANONICALIZE = 2
 FLAG_WEIGHT_PRECOND = 4
 FLAG_AUTOTUNE = 8
+FLAG_GRAPH = 16
 
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_SHAPE", 3: "ERR_HIP", 4: "ERR_OOM", 5: "ERR_NOT_PD",
           6: "ERR_LINESEARCH", 7: "ERR_NAN", 8: "ERR_STATE"}

@@ -96,6 +96,31 @@ def test_graph_steps_with_many_bands_match_the_oracle(nb):
     h.close()
 
 
+def test_graph_periodic_restart_matches_the_oracle():
+    """Reading R23 taken on the device: 12 graph iterations (three replays
+    of 4) with a restart every 5, against the oracle's 12 steps."""
+    rb = ensure_built()
+    s = inputs.tiny_cell()
+    g = _ctx(rb, s)
+    g.set_restart(5)
+    m = orc.Model(s)
+    st = orc.CGState(psi=orc.orthonormalize(
+        inputs.random_coefficients(m.miller, m.cell, m.nb, s["seed"])),
+        dt=orc.DT_INIT, restart_period=5)
+    recs = []
+    for _ in range(3):
+        acc, r = g.graph_steps(4)
+        assert acc == 4
+        recs += r
+    for i, gi in enumerate(recs):
+        oi = orc.pcg_step(m, st)
+        assert bool(gi["restarted"]) == bool(oi.restarted), i
+        assert (gi["beta"] == 0.0) == (oi.beta == 0.0), i
+        assert abs(gi["E1"] - oi.E1) < 1e-9 * max(1.0, abs(oi.E0)), i
+    assert recs[5]["restarted"] == 1 and recs[10]["restarted"] == 1
+    g.close()
+
+
 def test_replays_interleaved_with_host_steps():
     """graph(3), graph(3) (the same graph replayed), a host step (which
     trades the orbital and trial buffers), graph(3) (the graph's buffers
@@ -183,6 +208,32 @@ def test_batch_graph_steps_follow_the_batch_steps():
     b.close()
     for r in par + seq:
         r.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_with_the_graph_flag_reaches_the_host_minimum(precision):
+    """ROKS_FLAG_GRAPH: roks_solve runs replays of 8 device-decided
+    iterations, a host step after a rejected one, to the same converged
+    energy as the host-driven solve (FP64: 1e-9 Ha; FP32 tier: its
+    resolution), then the FP64 polish of the ladder."""
+    rb = ensure_built()
+    s = small_molecule()
+    out = []
+    for flags in (0, rb.FLAG_GRAPH):
+        r = rb.Roks(s, precision=precision, flags=flags)
+        r.set_coeffs(inputs.random_coefficients(r.miller(), s["cell"], r.nb, s["seed"]), True)
+        info, it = r.solve(tol=1e-10 if precision == 0 else 1e-6, maxiter=600)
+        if precision == 1:
+            r.set_precision(rb.FP64)
+            info, it2 = r.solve(tol=1e-10, maxiter=600)
+            it += it2
+        print("flags", flags, "E", info["E1"], "iterations", it, flush=True)
+        out.append((info["E1"], it, r.forces()))
+        r.close()
+    (e0, i0, f0), (e1, i1, f1) = out
+    assert abs(e1 - e0) < 1e-9
+    assert np.abs(f1 - f0).max() < 1e-5
+    assert i1 <= 2 * i0 + 16
 
 
 @pytest.mark.parametrize("what", ["exx", "overlap", "bf16x3", "k"])
