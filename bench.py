@@ -468,6 +468,35 @@ def cg_graph_report(steps=8, workers=8):
     return res
 
 
+def batch_solve_report(tol=1e-6, switch_tol=1e-5, workers=8):
+    """The 32-system batch solved to |dE| < tol (FP32 tier to switch_tol,
+    then FP64: the precision ladder), iterations driven from the host and
+    then in graph mode (ROKS_FLAG_GRAPH), from the same starts."""
+    systems = inputs.batch_systems()
+    res = {"systems": len(systems), "tol_Ha": tol, "switch_tol_Ha": switch_tol, "workers": workers}
+    energies = {}
+    for name, flags in (("host", 0), ("graph", rb.FLAG_GRAPH)):
+        ctxs = []
+        for s in systems:
+            r = rb.Roks(s, precision=rb.FP32, flags=flags)
+            r.set_coeffs(inputs.random_coefficients(r.miller(), s["cell"], r.nb, s["seed"]), True)
+            ctxs.append(r)
+        b = rb.Batch(ctxs, workers=workers)
+        t0 = time.perf_counter()
+        out = b.solve(tol=tol, maxiter=3000, switch_tol=switch_tol)
+        res[name + "_seconds"] = time.perf_counter() - t0
+        res[name + "_iterations"] = int(sum(o[1] for o in out))
+        res[name + "_all_ok"] = all(o[0] == 0 for o in out)
+        energies[name] = [o[2]["E1"] for o in out]
+        b.close()
+        for r in ctxs:
+            r.close()
+    res["speedup"] = res["host_seconds"] / res["graph_seconds"]
+    res["max_abs_dE_graph_vs_host_Ha"] = float(max(abs(a - b) for a, b in
+                                                   zip(energies["host"], energies["graph"])))
+    return res
+
+
 def oxide_graph_report(system, steps=4):
     """Graph mode on the oxide supercell (FP64): `steps` CG iterations
     replayed from one graph against the same iterations driven from the
@@ -737,6 +766,7 @@ def main():
             out["batch"] = batch_report()
             out["batch_apply_graph"] = graph_report_child()
             out["batch_cg_graph"] = cg_graph_report()
+            out["batch_solve_graph"] = batch_solve_report()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(system)
     print(json.dumps(out))
