@@ -342,9 +342,10 @@ roks_status roks_pcg_step(roks_ctx ctx, roks_step_info* info);
  * else the trial fails) chosen on the device).  Scope (else
  * ROKS_ERR_STATE): the FP64 or FP32 tier, no exact exchange, overlap
  * coefficients, network, recording, canonicalisation or autotuning
- * (periodic restarts are taken on the device); ROKS_ERR_ARG for k outside 1 .. 100000.  The call
- * synchronizes the context's stream; the first call for a k also runs one
- * iteration that commits nothing (first-use set-up outside the capture). */
+ * (periodic restarts are taken on the device); ROKS_ERR_ARG for k outside
+ * 1 .. 1024.  The call synchronizes the context's stream; the first call
+ * for a k (or after a change of tier or flags) also runs one iteration that
+ * commits nothing (first-use set-up outside the capture). */
 roks_status roks_graph_steps(roks_ctx ctx, int32_t k, roks_step_info* info, int32_t* accepted);
 
 /* Forget the carried search directions (next step is steepest descent). */

@@ -681,7 +681,7 @@ void free_graph_mode(Ctx& c) {
 }
 
 int graph_steps(Ctx& c, int k, roks_step_info* info) {
-  ROKS_CHECK(k >= 1 && k <= 100000, ROKS_ERR_ARG, "k must be 1 .. 100000");
+  ROKS_CHECK(k >= 1 && k <= 1024, ROKS_ERR_ARG, "k must be 1 .. 1024");
   graph_check(c);
   reset_diis(c);  // the kept DIIS iterates do not lead to these orbitals
   graph_buffers(c, k);
