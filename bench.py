@@ -335,14 +335,16 @@ def converge_report(system, tol=1e-6):
         v["max_force_diff_vs_reference"] = float(np.abs(F - ref["forces"]).max())
         v["to_reference"] = time_to_reference(system, ref, prec, nn, rs)
         out[k] = v
-    net.close()
-    # the plain variants again with their iterations in graph mode
-    for k, prec in (("plain_fp64_restart_graph", rb.FP64), ("mixed_plain_restart_graph", rb.FP32)):
-        v = time_to_converge(system, tol, prec, None, RESTART, flags=rb.FLAG_GRAPH)
+    # the variants with restarts again with their iterations in graph mode
+    for k, prec, nn in (("plain_fp64_restart_graph", rb.FP64, None),
+                        ("mixed_plain_restart_graph", rb.FP32, None),
+                        ("mixed_learned_graph", rb.FP32, net)):
+        v = time_to_converge(system, tol, prec, nn, RESTART, flags=rb.FLAG_GRAPH)
         F = v.pop("forces")
         v["dE_singlet_vs_reference_Ha"] = v["E_singlet"] - ref["E_singlet"]
         v["max_force_diff_vs_reference"] = float(np.abs(F - ref["forces"]).max())
         out[k] = v
+    net.close()
     out["training"] = tr
     sec = {k: out[k]["seconds"] for k in ("plain_fp64", "plain_fp64_restart", "mixed_plain_restart",
                                           "fp64_learned", "mixed_learned")}
@@ -354,7 +356,8 @@ def converge_report(system, tol=1e-6):
         "fp32_tier_with_learned_vs_fp64_learned": sec["fp64_learned"] / sec["mixed_learned"],
         "graph_vs_host_fp64_restart": sec["plain_fp64_restart"] / out["plain_fp64_restart_graph"]["seconds"],
         "graph_vs_host_fp32_tier_restart":
-            sec["mixed_plain_restart"] / out["mixed_plain_restart_graph"]["seconds"]}
+            sec["mixed_plain_restart"] / out["mixed_plain_restart_graph"]["seconds"],
+        "graph_vs_host_mixed_learned": sec["mixed_learned"] / out["mixed_learned_graph"]["seconds"]}
     out["speedup_mixed_learned_vs_plain_fp64_to_reference"] = (
         out["plain_fp64"]["to_reference"]["seconds"] / out["mixed_learned"]["to_reference"]["seconds"])
     return out

@@ -341,8 +341,10 @@ roks_status roks_pcg_step(roks_ctx ctx, roks_step_info* info);
  * D) takes a Taylor polynomial of degree 18 and the squarings (at most 12,
  * else the trial fails) chosen on the device).  Scope (else
  * ROKS_ERR_STATE): the FP64 or FP32 tier, no exact exchange, overlap
- * coefficients, network, recording, canonicalisation or autotuning
- * (periodic restarts are taken on the device); ROKS_ERR_ARG for k outside
+ * coefficients, recording, canonicalisation or autotuning (periodic
+ * restarts and an attached network's rescaling are taken on the device; a
+ * learned search that fails halts the replay, and the host step then
+ * retries with the plain preconditioner); ROKS_ERR_ARG for k outside
  * 1 .. 1024.  The call synchronizes the context's stream; the first call
  * for a k (or after a change of tier or flags) also runs one iteration that
  * commits nothing (first-use set-up outside the capture). */

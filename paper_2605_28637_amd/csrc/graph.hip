@@ -26,8 +26,10 @@
 // caller sees the first rejected iteration and continues with roks_pcg_step.
 //
 // Scope (checked before capture): FP64 or FP32 tier, LDA or PBE without
-// exact exchange, no overlap coefficients, no network, no recording, no
-// canonicalisation, no autotuning; periodic restarts are taken on the device.
+// exact exchange, no overlap coefficients, no recording, no
+// canonicalisation, no autotuning; periodic restarts and the learned
+// rescaling of the preconditioner are taken on the device (the plain
+// preconditioner's retry after a failed learned search is the host step's).
 #include <cmath>
 #include <cstring>
 
@@ -441,7 +443,14 @@ static void graph_step(Ctx& c, int step, bool carry) {
   // until a step has been accepted)
   band_dots2(c, c.d_gI, c.d_gI, nb, c.d_bandv + nb, c.d_bandv, nullptr, nullptr);
   const double* bandw = (c.flags & ROKS_FLAG_WEIGHT_PRECOND) ? c.d_kinw_shell : nullptr;
-  launch_teter(c, c.d_bandv, c.d_bandv + nb, c.d_gI, bandw, c.d_w1);
+  if (c.mlp) {
+    // the learned rescaling of K (its features from <g|T|g>, <g|g>, <n|T|n>)
+    band_dots(c, c.d_psi, c.d_psi, nb, 1, c.d_bandv + 4 * nb);
+    launch_features(c, c.d_bandv, c.d_bandv + nb, c.d_bandv + 4 * nb);
+    launch_teter_scaled(c, c.d_bandv, c.d_bandv + nb, c.d_gI, bandw, c.d_w1);
+  } else {
+    launch_teter(c, c.d_bandv, c.d_bandv + nb, c.d_gI, bandw, c.d_w1);
+  }
   gemm_wdot(c, nb, 2 * nb, K, dbl(c.d_psi), K, dbl(c.d_w1), K, c.d_m12, 2 * nb, 1.0, 0.0, true);
   gemm_expand_to(c, nb, K, nb, c.d_m12, 2 * nb, false, dbl(c.d_psi), K, dbl(c.d_w1), K, dbl(c.d_p), K,
                  -1.0, 1.0);
@@ -509,8 +518,8 @@ void graph_check(const Ctx& c) {
   ROKS_CHECK(c.have_orbitals, ROKS_ERR_STATE, "no orbitals set");
   ROKS_CHECK(!c.bf3 && (c.prec == ROKS_FP64 || c.prec == ROKS_FP32), ROKS_ERR_STATE,
              "graph mode runs in the FP64 or FP32 tier");
-  ROKS_CHECK(c.exx == 0.0 && !c.has_q && !c.mlp && c.rec_max == 0, ROKS_ERR_STATE,
-             "graph mode excludes exact exchange, overlap coefficients, a network and recording");
+  ROKS_CHECK(c.exx == 0.0 && !c.has_q && c.rec_max == 0, ROKS_ERR_STATE,
+             "graph mode excludes exact exchange, overlap coefficients and recording");
   ROKS_CHECK(!(c.flags & (ROKS_FLAG_CANONICALIZE | ROKS_FLAG_AUTOTUNE)), ROKS_ERR_STATE,
              "graph mode excludes canonicalisation and autotuning");
 }
@@ -650,6 +659,7 @@ void capture(Ctx& c, int k) {
   c.graph_k = k;
   c.graph_prec = c.prec;
   c.graph_flags = c.flags;
+  c.graph_mlp = c.mlp;
   current_bufs(c, c.graph_bufs);
 }
 
@@ -688,7 +698,8 @@ int graph_steps(Ctx& c, int k, roks_step_info* info) {
   void* cur[5];
   current_bufs(c, cur);
   const bool reuse = c.graph_exec && c.graph_k == k && c.graph_prec == c.prec &&
-                     c.graph_flags == c.flags && same_sets(cur, c.graph_bufs);
+                     c.graph_flags == c.flags && c.graph_mlp == c.mlp &&
+                     same_sets(cur, c.graph_bufs);
   if (reuse)
     restore_bufs(c);
   else
@@ -711,6 +722,7 @@ int graph_steps(Ctx& c, int k, roks_step_info* info) {
       s.stalled = r[5] != 0.0 ? 0 : 1;
       s.norm_gI = r[6];
       s.restarted = r[7] != 0.0 ? 1 : 0;
+      s.learned = c.mlp ? 1 : 0;
       s.evaluations = i <= acc ? 2 : 0;
       s.iteration = c.iteration + std::min(i + 1, acc);
       info[i] = s;

@@ -294,6 +294,7 @@ struct Ctx {
   int graph_k = 0;                 // how many (0: none captured)
   int graph_prec = 0;              // the tier and flags it was captured with
   uint32_t graph_flags = 0;
+  const Mlp* graph_mlp = nullptr;  // and the network attached
   // the buffers the capture baked in (orbitals, trials, projections, which
   // the host CG trades by pointer)
   void* graph_bufs[5] = {};

@@ -121,6 +121,34 @@ def test_graph_periodic_restart_matches_the_oracle():
     g.close()
 
 
+def test_learned_graph_steps_follow_the_host_learned_steps():
+    """With a network attached (seeded, untrained: a non-trivial rescaling)
+    the learned preconditioner runs inside the graph: graph iterations
+    against host iterations with the same network, while the learned
+    search succeeds on both (FP64 bar)."""
+    rb = ensure_built()
+    s = small_molecule()
+    net = rb.Mlp(seed=7)
+    a = _ctx(rb, s)
+    b = _ctx(rb, s)
+    a.set_mlp(net)
+    b.set_mlp(net)
+    acc, recs = a.graph_steps(4)
+    assert acc >= 2
+    for i in range(acc):
+        y = b.pcg_step()
+        x = recs[i]
+        print(i, x["E1"], y["E1"], y["fallback"], flush=True)
+        assert x["learned"] == 1 and y["learned"] == 1
+        if y["fallback"]:
+            break
+        assert abs(x["E1"] - y["E1"]) < TOL * max(1.0, abs(y["E0"])), i
+        assert abs(x["delta"] - y["delta"]) < 1e-8 * max(1.0, y["delta"]), i
+    a.close()
+    b.close()
+    net.close()
+
+
 def test_replays_interleaved_with_host_steps():
     """graph(3), graph(3) (the same graph replayed), a host step (which
     trades the orbital and trial buffers), graph(3) (the graph's buffers
@@ -236,7 +264,7 @@ def test_solve_with_the_graph_flag_reaches_the_host_minimum(precision):
     assert i1 <= 2 * i0 + 16
 
 
-@pytest.mark.parametrize("what", ["exx", "overlap", "bf16x3", "k"])
+@pytest.mark.parametrize("what", ["exx", "overlap", "bf16x3", "k", "recording"])
 def test_graph_mode_scope_is_checked(what):
     rb = ensure_built()
     s = small_molecule()
@@ -248,6 +276,8 @@ def test_graph_mode_scope_is_checked(what):
     elif what == "bf16x3":
         prec = rb.FP32_BF16X3
     g = _ctx(rb, s, prec)
+    if what == "recording":
+        g.record(4, 1)
     with pytest.raises(rb.RoksError) as ei:
         g.graph_steps(0 if what == "k" else 2)
     assert ei.value.status == (1 if what == "k" else 8)
