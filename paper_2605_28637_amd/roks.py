@@ -579,9 +579,10 @@ class Mlp:
 
 class Batch:
     """Independent contexts solved side by side (a roks_batch): a work queue,
-    longest system first, drained by `workers` host threads."""
+    longest system first, drained by `workers` host threads (four by
+    default, one per hardware queue of the device)."""
 
-    def __init__(self, systems, workers: int = 8):
+    def __init__(self, systems, workers: int = 4):
         self._L = lib()
         self.systems = list(systems)
         n = len(self.systems)
