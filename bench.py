@@ -55,10 +55,10 @@ RESTART = 20
 # kernels are the ones measured.
 TRAFFIC = {
     ("gemm_expand", "oxide", 0): {
-        "bytes_per_launch": 1.28643e+09,
+        "bytes_per_launch": 1.18339e+09,
         "profile": "profiles/gemm_expand_oxide_fp64_traffic.md",
         "sources": ["paper_2605_28637_amd/csrc/tile_gemm.hip"],
-        "sha256": "eecf9e8a3b3a69c38695d5c494b47f310b147768e239ca65ec757d400b8c8915"},
+        "sha256": "98ca437b0ae4f7ecccfd42604e55306926e694890d15466f079b6e1cbf8c430a"},
 }
 KERNELS = ("zpass_bwd", "plane_apply", "plane_density", "zpass_fwd", "fft3d", "gemm_wdot",
            "gemm_expand", "xc", "proj_bf3")

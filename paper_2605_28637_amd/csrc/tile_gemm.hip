@@ -141,20 +141,38 @@ __device__ __forceinline__ void tile_main(const double* __restrict__ A, int lda,
     }
     const double* as = As[buf];
     const double* bs = Bs[buf];
+    // while issuing products a wave runs at raised priority, and the next
+    // 4-k slice of its operands is read from LDS before this slice's
+    // products (2 % on the band products, 2 % on the expansions)
+    __builtin_amdgcn_s_setprio(1);
+    double a[4], b[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = as[s * kTLd + wm * 64 + 16 * i + r16];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = bs[s * kTLd + wn * 32 + 16 * j + r16];
 #pragma unroll
     for (int kk = 0; kk < kTK; kk += 4) {
-      double a[4], b[2];
+      double an[4], bn[2];
+      if (kk + 4 < kTK) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = as[(kk + s) * kTLd + wm * 64 + 16 * i + r16];
+        for (int i = 0; i < 4; ++i) an[i] = as[(kk + 4 + s) * kTLd + wm * 64 + 16 * i + r16];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = bs[(kk + s) * kTLd + wn * 32 + 16 * j + r16];
+        for (int j = 0; j < 2; ++j) bn[j] = bs[(kk + 4 + s) * kTLd + wn * 32 + 16 * j + r16];
+      }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           if (!GUARD || (vi[i] && vj[j]))
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+      if (kk + 4 < kTK) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = an[i];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = bn[j];
+      }
     }
+    __builtin_amdgcn_s_setprio(0);
     if (more) {
       tile_store<ALAY>(As[buf ^ 1], va);
       tile_store<BLAY>(Bs[buf ^ 1], vb);
