@@ -390,6 +390,13 @@ int tuned_splits(Ctx& c, int M, int N, int K, const double* A, int lda, const do
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  // the timing buffer goes (the stream is idle after the last event)
+  for (size_t i = 0; i < c.allocations.size(); ++i)
+    if (c.allocations[i].p == scratch) {
+      ROKS_HIP(hipFree(scratch));
+      c.allocations.erase(c.allocations.begin() + (long)i);
+      break;
+    }
   g_tuned[key] = best;
   write_tune_cache(c);
   return best;
