@@ -192,7 +192,8 @@ __global__ void __launch_bounds__(256) k_g_prep(int nb, const double* __restrict
 }
 
 // Past the single-workgroup exponential: exp(X) by scaling and squaring
-// around a Taylor polynomial of fixed degree kTaylor (the launches are fixed)
+// around a Taylor polynomial of fixed degree kTaylor (the launches are fixed;
+// the polynomial by the Paterson-Stockmeyer scheme)
 // with a squaring count s chosen on the device, the smallest with
 // ||X||_1 / 2^s <= 1 (so the truncation error stays below
 // 1 / (kTaylor + 1)! < 1e-17); kSqMax squaring launches, those past s undone.
@@ -372,15 +373,10 @@ static void graph_trial(Ctx& c, double2* out, double* M, double* U, bool alt, in
     hipLaunchKernelGGL(k_g_expm_prep, dim3((unsigned)grid_for(nn)), dim3(256), 0, c.stream, nb, c.d_D,
                        c.d_m1, c.d_gstate, alt ? 0 : 1, c.d_flag);
     ROKS_HIP(hipGetLastError());
-    // P_m = I + X / m, P_q = I + X P_{q+1} / q, ..., P_1
-    set_identity(c, c.d_m2, nb, 1.0);
-    axpby(c, nn, 1.0 / kTaylor, c.d_m1, 1.0, c.d_m2, c.d_m2);
-    double* cur = c.d_m2;
-    double* nxt = c.d_m4;
-    for (int q = kTaylor - 1; q >= 1; --q) {
-      gemm_small(c, nb, nb, nb, c.d_m1, nb, false, cur, nb, false, nxt, nb, 1.0 / q, 0.0, 1.0);
-      std::swap(cur, nxt);
-    }
+    // the series of degree kTaylor (Paterson-Stockmeyer: 8 products), then
+    // the squarings; d_gram is free once the factorisation ran
+    double* cur = taylor_ps(c, nb, kTaylor, c.d_m1, c.d_m2, c.d_m3, c.d_m4, c.d_gram);
+    double* nxt = cur == c.d_m4 ? c.d_gram : c.d_m4;
     for (int i = 0; i < kSqMax; ++i) {
       gemm_small(c, nb, nb, nb, cur, nb, false, cur, nb, false, nxt, nb, 1.0, 0.0);
       hipLaunchKernelGGL(k_g_keep, dim3((unsigned)grid_for(nn)), dim3(256), 0, c.stream, nn, nxt, cur,

@@ -221,6 +221,19 @@ __global__ void k_set_identity(double* A, int n, double d) {
   A[t] = (i == j) ? d : 0.0;
 }
 
+// out = c0 I + c1 X + c2 X2 (X2 may be null), n x n
+__global__ void k_poly_block(int n, double c0, double c1, const double* __restrict__ X, double c2,
+                             const double* __restrict__ X2, double* __restrict__ out) {
+  const size_t nn = (size_t)n * n;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < nn; t += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t / n), j = (int)(t - (size_t)i * n);
+    double v = c1 * X[t];
+    if (X2) v += c2 * X2[t];
+    if (i == j) v += c0;
+    out[t] = v;
+  }
+}
+
 __global__ void k_scale_shift(const double* __restrict__ in, int n, double a, double d,
                               double* __restrict__ out) {
   const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -899,6 +912,38 @@ void launch_zero_g0_imag(Ctx& c, double2* vecs, int nvec) {
 void axpby(Ctx& c, size_t n, double a, const double* x, double b, const double* y, double* out) {
   hipLaunchKernelGGL(k_axpby, dim3(blocks_for(n)), dim3(256), 0, c.stream, n, a, x, b, y, out);
   ROKS_HIP(hipGetLastError());
+}
+
+int taylor_products(int m) { return (m >= 2) + (m >= 3) + m / 3; }
+
+// T_m(X) = sum_{k <= m} X^k / k! by the Paterson-Stockmeyer scheme with
+// blocks of three: T = B_0 + Y (B_1 + Y (B_2 + ...)), Y = X^3, B_j = c_3j I +
+// c_3j+1 X + c_3j+2 X^2 (c_k = 1/k!, zero past m): taylor_products(m)
+// products instead of m in Horner form.  X2, X3, w0, w1 are n x n scratch;
+// returns the buffer (w0 or w1) holding the result.
+double* taylor_ps(Ctx& c, int n, int m, const double* X, double* X2, double* X3, double* w0, double* w1) {
+  const size_t nn = (size_t)n * n;
+  std::vector<double> cf(m + 3, 0.0);
+  cf[0] = 1.0;
+  for (int k = 1; k <= m; ++k) cf[k] = cf[k - 1] / k;
+  if (m >= 2) gemm_small(c, n, n, n, X, n, false, X, n, false, X2, n, 1.0, 0.0);
+  const int r = m / 3;
+  if (r >= 1) gemm_small(c, n, n, n, X2, n, false, X, n, false, X3, n, 1.0, 0.0);
+  const unsigned grid = (unsigned)std::min<size_t>(4096, (nn + 255) / 256);
+  auto block = [&](int j, double* out) {
+    hipLaunchKernelGGL(k_poly_block, dim3(grid), dim3(256), 0, c.stream, n, cf[3 * j], cf[3 * j + 1], X,
+                       cf[3 * j + 2], m >= 2 ? X2 : nullptr, out);
+    ROKS_HIP(hipGetLastError());
+  };
+  double* acc = w0;
+  double* nxt = w1;
+  block(r, acc);
+  for (int j = r - 1; j >= 0; --j) {
+    block(j, nxt);
+    gemm_small(c, n, n, n, X3, n, false, acc, n, false, nxt, n, 1.0, 1.0);
+    std::swap(acc, nxt);
+  }
+  return acc;
 }
 
 void set_identity(Ctx& c, double* A, int n, double diag) {

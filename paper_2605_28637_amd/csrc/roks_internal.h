@@ -537,6 +537,11 @@ void band_dots2(Ctx& c, const double2* X, const double2* Y, int nvec, double* ou
 void axpby(Ctx& c, size_t n, double a, const double* x, double b, const double* y, double* out);
 void cholesky_inverse(Ctx& c, const double* G, int n, double* Linv, int32_t* flag);
 void set_identity(Ctx& c, double* A, int n, double diag);
+// the truncated exponential series of X (n x n) to degree m by the
+// Paterson-Stockmeyer scheme (blocks of three) in taylor_products(m) matrix
+// products; X2, X3, w0, w1 scratch, the result in w0 or w1 (returned)
+int taylor_products(int m);
+double* taylor_ps(Ctx& c, int n, int m, const double* X, double* X2, double* X3, double* w0, double* w1);
 // out = a in + d I (n x n)
 void scale_shift(Ctx& c, const double* in, int n, double a, double d, double* out);
 void matrix_norm1(Ctx& c, const double* A, int n, double* out);

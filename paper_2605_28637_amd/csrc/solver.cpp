@@ -17,9 +17,9 @@ namespace {
 
 
 // U = exp(X) for X = delta * D (antisymmetric): scaling and squaring around a
-// Taylor polynomial in Horner form, the degree m and squarings s chosen as in
-// the single-workgroup kernel (fewest products with theta^(m+1)/(m+1)! <= 1e-17,
-// theta = ||X||_1 / 2^s <= 1)
+// Taylor polynomial evaluated by the Paterson-Stockmeyer scheme, the degree m
+// and squarings s with theta^(m+1)/(m+1)! <= 1e-17 (theta = ||X||_1 / 2^s <=
+// 1, the single-workgroup kernel's criterion) and the fewest products
 void expm(Ctx& c, double delta, const double* D, double* U) {
   if (expm_in_lds(c)) {
     launch_expm_lds(c, D, delta, U, c.stream);
@@ -47,23 +47,17 @@ void expm(Ctx& c, double delta, const double* D, double* U) {
       ++mm;
       term *= th / (mm + 1);
     }
-    if (mm + sq < best) {
-      best = mm + sq;
+    if (taylor_products(mm) + sq < best) {
+      best = taylor_products(mm) + sq;
       s = sq;
       m = mm;
     }
     if (mm <= 1) break;
   }
   if (s > 0) axpby(c, nn, std::ldexp(1.0, -s), c.d_m1, 0.0, nullptr, c.d_m1);
-  // P_m = I + X/m, P_q = I + X P_{q+1} / q, ..., P_1
-  set_identity(c, c.d_m2, n, 1.0);
-  if (m >= 1) axpby(c, nn, 1.0 / m, c.d_m1, 1.0, c.d_m2, c.d_m2);
-  double* cur = c.d_m2;
-  double* nxt = c.d_m4;
-  for (int q = m - 1; q >= 1; --q) {
-    gemm_small(c, n, n, n, c.d_m1, n, false, cur, n, false, nxt, n, 1.0 / q, 0.0, 1.0);
-    std::swap(cur, nxt);
-  }
+  // the series (X in d_m1; d_gram is free once the trial's factorisation ran)
+  double* cur = taylor_ps(c, n, m, c.d_m1, c.d_m2, c.d_m3, c.d_m4, c.d_gram);
+  double* nxt = cur == c.d_m4 ? c.d_gram : c.d_m4;
   for (int i = 0; i < s; ++i) {
     gemm_small(c, n, n, n, cur, n, false, cur, n, false, nxt, n, 1.0, 0.0);
     std::swap(cur, nxt);
