@@ -131,6 +131,7 @@ void init_device(Ctx& c, void* stream) {
                      &c.d_Linv, &c.d_U, &c.d_M, &c.d_m1, &c.d_m2, &c.d_m3, &c.d_Mkeep,
                      &c.d_Ukeep, &c.d_m4, &c.d_SS};
   for (double** m : mats) *m = dalloc<double>(c, nn);
+  if (!expm_in_lds(c)) c.d_ex = dalloc<double>(c, 5 * nn);
   c.d_flag = dalloc<int32_t>(c, 16);
   // the energy sums, step scalars and status flags are written by kernels
   // straight into pinned, coherent host memory (read by the host after a

@@ -222,6 +222,7 @@ struct Ctx {
          *d_M = nullptr, *d_m1 = nullptr, *d_m2 = nullptr, *d_m3 = nullptr, *d_Mkeep = nullptr,
          *d_Ukeep = nullptr;
   double* d_SS = nullptr;        // <S_m|S_n> of the current search direction
+  double* d_ex = nullptr;        // [5][nb][nb] scratch of the multi-kernel exponential (nb > 78)
   double* d_P0 = nullptr;        // [nproj][nb] <beta|psi> at the start of the line search
   double* d_PS = nullptr;        // [nproj][nb] <beta|S>
   int32_t* d_flag = nullptr;     // device status flags

@@ -27,7 +27,10 @@ void expm(Ctx& c, double delta, const double* D, double* U) {
   }
   const int n = c.nb;
   const size_t nn = (size_t)n * n;
-  axpby(c, nn, delta, D, 0.0, nullptr, c.d_m1);
+  // scratch of its own (it runs beside the trial's factorisation)
+  double* X = c.d_ex;
+  double* w[4] = {c.d_ex + nn, c.d_ex + 2 * nn, c.d_ex + 3 * nn, c.d_ex + 4 * nn};
+  axpby(c, nn, delta, D, 0.0, nullptr, X);
   // ||delta D||_1 = |delta| ||D||_1: the norm of the search's D was queued by
   // prepare_line_search into the pinned mirror and is read after the
   // synchronisation that follows it (one more only if D changed since)
@@ -54,10 +57,9 @@ void expm(Ctx& c, double delta, const double* D, double* U) {
     }
     if (mm <= 1) break;
   }
-  if (s > 0) axpby(c, nn, std::ldexp(1.0, -s), c.d_m1, 0.0, nullptr, c.d_m1);
-  // the series (X in d_m1; d_gram is free once the trial's factorisation ran)
-  double* cur = taylor_ps(c, n, m, c.d_m1, c.d_m2, c.d_m3, c.d_m4, c.d_gram);
-  double* nxt = cur == c.d_m4 ? c.d_gram : c.d_m4;
+  if (s > 0) axpby(c, nn, std::ldexp(1.0, -s), X, 0.0, nullptr, X);
+  double* cur = taylor_ps(c, n, m, X, w[0], w[1], w[2], w[3]);
+  double* nxt = cur == w[2] ? w[3] : w[2];
   for (int i = 0; i < s; ++i) {
     gemm_small(c, n, n, n, cur, n, false, cur, n, false, nxt, n, 1.0, 0.0);
     std::swap(cur, nxt);
@@ -123,9 +125,39 @@ void evaluate_trial(Ctx& c, double delta, Trial& t, bool energy_only) {
     // exponential side by side: one launch, two workgroups
     launch_chol_expm_lds(c, c.d_SS, delta * delta, 1.0, c.d_Linv, c.hd_flag, c.d_D, delta, t.U);
   } else {
+    // the rotation on the side stream beside the factorisation (the two are
+    // independent short-kernel chains; the exponential has its own scratch)
+    if (c.normD_pending) {
+      sync(c);
+      c.normD_pending = false;
+    }
+    ensure_side_stream(c);
+    ROKS_HIP(hipEventRecord(c.ev_fork, c.stream));
+    ROKS_HIP(hipStreamWaitEvent(c.side, c.ev_fork, 0));
+    // the split-K partials of the products on the two streams go to the two
+    // halves of their buffer (restored on every exit)
+    struct Halves {
+      Ctx& c;
+      double* part;
+      size_t cap;
+      hipStream_t main;
+      ~Halves() {
+        c.d_gemm_part = part;
+        c.gemm_part_capacity = cap;
+        c.stream = main;
+      }
+    } halves{c, c.d_gemm_part, c.gemm_part_capacity, c.stream};
+    const size_t half = c.gemm_part_capacity / 2;
+    c.gemm_part_capacity = half;
+    c.d_gemm_part = halves.part + half;
+    c.stream = c.side;
+    expm(c, delta, c.d_D, t.U);
+    c.stream = halves.main;
+    c.d_gemm_part = halves.part;
+    ROKS_HIP(hipEventRecord(c.ev_join, c.side));
     scale_shift(c, c.d_SS, nb, delta * delta, 1.0, c.d_gram);
     cholesky_inverse(c, c.d_gram, nb, c.d_Linv, c.hd_flag);
-    expm(c, delta, c.d_D, t.U);
+    ROKS_HIP(hipStreamWaitEvent(c.stream, c.ev_join, 0));
   }
   gemm_small(c, nb, nb, nb, t.U, nb, true, c.d_Linv, nb, false, t.M, nb, 1.0, 0.0);
   // trial orbitals M^T (psi + delta S), the sum formed while loading
