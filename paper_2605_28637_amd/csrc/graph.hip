@@ -84,7 +84,8 @@ __global__ void k_g_energy(const double* __restrict__ scal, int nb, int nconf,
     const double EL = add(add(add(add(k, nl), ext), har), xc);
     E = add(E, mul(L == 0 ? c0 : c1, EL));
   }
-  const bool ok = !flag || flag[0] == 0;
+  // flag[0]: the factorisation; flag[1]: the exponential past 78 bands
+  const bool ok = !flag || (flag[0] | flag[1]) == 0;
   if (!ok || !isfinite(E)) E = INFINITY;
   gs[slot] = E;
   if (okslot >= 0) gs[okslot] = ok ? 1.0 : 0.0;
@@ -218,7 +219,7 @@ __global__ void __launch_bounds__(256) k_g_expm_prep(int n, const double* __rest
     sc = ok ? ldexp(t, -sq) : 0.0;
     if (blockIdx.x == 0) {
       gs[gSq] = ok ? sq : 0;
-      if (!ok) flag[0] |= 2;
+      flag[1] = ok ? 0 : 2;
     }
   }
   __syncthreads();
@@ -368,15 +369,43 @@ static void graph_trial(Ctx& c, double2* out, double* M, double* U, bool alt, in
   if (lds) {
     launch_chol_expm_lds(c, c.d_gram, 1.0, 0.0, c.d_Linv, c.d_flag, c.d_m1, 1.0, U);
   } else {
-    // the factorisation first (its panels use d_m1 .. d_m4 as scratch)
-    cholesky_inverse(c, c.d_gram, nb, c.d_Linv, c.d_flag);
-    hipLaunchKernelGGL(k_g_expm_prep, dim3((unsigned)grid_for(nn)), dim3(256), 0, c.stream, nb, c.d_D,
-                       c.d_m1, c.d_gstate, alt ? 0 : 1, c.d_flag);
+    // past 128 bands (the panel factorisation) the exponential runs on the
+    // side stream, a branch of the graph, beside the factorisation, with
+    // scratch of its own and the upper half of the split-K partials buffer
+    // (restored on every exit); below, a branch costs more than it hides (the
+    // uneven batch replayed 0.84x as fast with branches at 79-120 bands)
+    const bool branch = nb > 128;
+    if (branch) {
+      ensure_side_stream(c);
+      ROKS_HIP(hipEventRecord(c.ev_fork, c.stream));
+      ROKS_HIP(hipStreamWaitEvent(c.side, c.ev_fork, 0));
+    }
+    struct Halves {
+      Ctx& c;
+      double* part;
+      size_t cap;
+      hipStream_t main;
+      ~Halves() {
+        c.d_gemm_part = part;
+        c.gemm_part_capacity = cap;
+        c.stream = main;
+      }
+    } halves{c, c.d_gemm_part, c.gemm_part_capacity, c.stream};
+    if (branch) {
+      const size_t half = c.gemm_part_capacity / 2;
+      c.gemm_part_capacity = half;
+      c.d_gemm_part = halves.part + half;
+      c.stream = c.side;
+    }
+    double* X = c.d_ex;
+    double* w[4] = {c.d_ex + nn, c.d_ex + 2 * nn, c.d_ex + 3 * nn, c.d_ex + 4 * nn};
+    hipLaunchKernelGGL(k_g_expm_prep, dim3((unsigned)grid_for(nn)), dim3(256), 0, c.stream, nb, c.d_D, X,
+                       c.d_gstate, alt ? 0 : 1, c.d_flag);
     ROKS_HIP(hipGetLastError());
     // the series of degree kTaylor (Paterson-Stockmeyer: 8 products), then
-    // the squarings; d_gram is free once the factorisation ran
-    double* cur = taylor_ps(c, nb, kTaylor, c.d_m1, c.d_m2, c.d_m3, c.d_m4, c.d_gram);
-    double* nxt = cur == c.d_m4 ? c.d_gram : c.d_m4;
+    // the squarings
+    double* cur = taylor_ps(c, nb, kTaylor, X, w[0], w[1], w[2], w[3]);
+    double* nxt = cur == w[2] ? w[3] : w[2];
     for (int i = 0; i < kSqMax; ++i) {
       gemm_small(c, nb, nb, nb, cur, nb, false, cur, nb, false, nxt, nb, 1.0, 0.0);
       hipLaunchKernelGGL(k_g_keep, dim3((unsigned)grid_for(nn)), dim3(256), 0, c.stream, nn, nxt, cur,
@@ -385,6 +414,11 @@ static void graph_trial(Ctx& c, double2* out, double* M, double* U, bool alt, in
       std::swap(cur, nxt);
     }
     copy_dev(c, U, cur, nn * sizeof(double));
+    if (branch) ROKS_HIP(hipEventRecord(c.ev_join, c.side));
+    c.stream = halves.main;
+    c.d_gemm_part = halves.part;
+    cholesky_inverse(c, c.d_gram, nb, c.d_Linv, c.d_flag);
+    if (branch) ROKS_HIP(hipStreamWaitEvent(c.stream, c.ev_join, 0));
   }
   gemm_small(c, nb, nb, nb, U, nb, true, c.d_Linv, nb, false, M, nb, 1.0, 0.0);
   gemm_expand_sum(c, nb, K, nb, M, nb, true, dbl(c.d_psi), dbl(c.d_Pt), 1.0, K, dbl(out), K, dbl(out),
