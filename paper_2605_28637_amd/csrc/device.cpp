@@ -129,7 +129,7 @@ void init_device(Ctx& c, void* stream) {
   c.d_m12 = dalloc<double>(c, 2 * (size_t)nb * nb);
   double** mats[] = {&c.d_theta, &c.d_R, &c.d_kappa, &c.d_A, &c.d_D, &c.d_Dold, &c.d_gram,
                      &c.d_Linv, &c.d_U, &c.d_M, &c.d_m1, &c.d_m2, &c.d_m3, &c.d_Mkeep,
-                     &c.d_Ukeep, &c.d_m4, &c.d_SS};
+                     &c.d_Ukeep, &c.d_m4, &c.d_SS, &c.d_PSold};
   for (double** m : mats) *m = dalloc<double>(c, nn);
   if (!expm_in_lds(c)) c.d_ex = dalloc<double>(c, 5 * nn);
   c.d_flag = dalloc<int32_t>(c, 16);

@@ -223,6 +223,8 @@ struct Ctx {
          *d_Ukeep = nullptr;
   double* d_SS = nullptr;        // <S_m|S_n> of the current search direction
   double* d_ex = nullptr;        // [5][nb][nb] scratch of the multi-kernel exponential (nb > 78)
+  double* d_PSold = nullptr;     // <psi|S_old> left by the last commit
+  int psold_iter = -1;           // the iteration it belongs to (-1: none)
   double* d_P0 = nullptr;        // [nproj][nb] <beta|psi> at the start of the line search
   double* d_PS = nullptr;        // [nproj][nb] <beta|S>
   int32_t* d_flag = nullptr;     // device status flags

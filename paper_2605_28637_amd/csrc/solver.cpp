@@ -460,6 +460,7 @@ void reset_cg(Ctx& c) {
   c.pg_old = 0.0;
   c.dt = kDtInit;
   c.since_restart = 0;
+  c.psold_iter = -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -528,13 +529,16 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   // with carried directions the Fletcher-Reeves ratio is formed on the device
   // and the directions follow without a round trip to the host
   const bool dev_beta = c.have_old && c.pg_old != 0.0;
-  precondition_async(learned, c.have_old);
+  // <psi|S_old> is known from the last step's commit when the orbitals and
+  // S_old are the ones it left (S = 1): the band product then skips S_old
+  const bool psold = c.have_old && !c.has_q && c.psold_iter == c.iteration;
+  precondition_async(learned, c.have_old && !psold);
   bool restarted = periodic;
 
   // Sold projected out of the current span (kept in d_w1)
   if (c.have_old)
-    gemm_expand_to(c, nb, K, nb, c.d_m12 + nb, 2 * nb, false, dbl(c.d_psi), K, dbl(c.d_Sold), K,
-                   dbl(c.d_w1), K, -1.0, 1.0);
+    gemm_expand_to(c, nb, K, nb, psold ? c.d_PSold : c.d_m12 + nb, psold ? nb : 2 * nb, false,
+                   dbl(c.d_psi), K, dbl(c.d_Sold), K, dbl(c.d_w1), K, -1.0, 1.0);
   // S = p + b S_old', D = A + b D_old (b = 0: plain copies); b_dev: the factor
   // d_cg[1] formed on the device
   auto directions_async = [&](double b, bool b_dev) {
@@ -678,6 +682,12 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   // D_old <- U^T D U
   std::swap(c.d_psi, c.d_trial[best]);
   gemm_expand(c, nb, K, nb, t.M, nb, true, dbl(c.d_S), K, dbl(c.d_Sold), K, 1.0, 0.0);
+  if (!c.has_q) {
+    // <psi_new|S_old> = delta M <S|S> M^T: psi_new = M (psi + delta S),
+    // S_old = M S and <psi|S> = 0 (S was projected out of the span of psi)
+    gemm_small(c, nb, nb, nb, c.d_SS, nb, false, t.M, nb, true, c.d_m3, nb, 1.0, 0.0);
+    gemm_small(c, nb, nb, nb, t.M, nb, false, c.d_m3, nb, false, c.d_PSold, nb, delta, 0.0);
+  }
   gemm_small(c, nb, nb, nb, c.d_D, nb, false, t.U, nb, false, c.d_m4, nb, 1.0, 0.0);
   gemm_small(c, nb, nb, nb, t.U, nb, true, c.d_m4, nb, false, c.d_Dold, nb, 1.0, 0.0);
   c.have_old = true;
@@ -685,6 +695,7 @@ void pcg_step(Ctx& c, roks_step_info* info) {
   c.dt = std::min(kDtMax, std::max(kDtMin, delta));
   c.iteration++;
   r.iteration = c.iteration;
+  c.psold_iter = c.has_q ? -1 : c.iteration;
   // the last trial evaluated is tr[1]: when it is the one taken, its
   // densities, potentials, projections and energies are those of the new
   // orbitals (the same kernels on the same values), so they are kept
