@@ -192,6 +192,14 @@ __global__ void __launch_bounds__(256) k_g_prep(int nb, const double* __restrict
   }
 }
 
+// x *= gs[slot]
+__global__ void __launch_bounds__(256) k_g_scale(size_t n, double* __restrict__ x,
+                                                 const double* __restrict__ gs, int slot) {
+  const double f = gs[slot];
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    x[i] *= f;
+}
+
 // Past the single-workgroup exponential: exp(X) by scaling and squaring
 // around a Taylor polynomial of fixed degree kTaylor (the launches are fixed;
 // the polynomial by the Paterson-Stockmeyer scheme)
@@ -481,12 +489,15 @@ static void graph_step(Ctx& c, int step, bool carry) {
   } else {
     launch_teter(c, c.d_bandv, c.d_bandv + nb, c.d_gI, bandw, c.d_w1);
   }
-  gemm_wdot(c, nb, 2 * nb, K, dbl(c.d_psi), K, dbl(c.d_w1), K, c.d_m12, 2 * nb, 1.0, 0.0, true);
-  gemm_expand_to(c, nb, K, nb, c.d_m12, 2 * nb, false, dbl(c.d_psi), K, dbl(c.d_w1), K, dbl(c.d_p), K,
+  // <psi|S_old>: after an accepted iteration of this replay (carry) from its
+  // commit (delta M <S|S> M^T), else a band product beside <psi|w>
+  const int nc = carry ? nb : 2 * nb;
+  gemm_wdot(c, nb, nc, K, dbl(c.d_psi), K, dbl(c.d_w1), K, c.d_m12, nc, 1.0, 0.0, true);
+  gemm_expand_to(c, nb, K, nb, c.d_m12, nc, false, dbl(c.d_psi), K, dbl(c.d_w1), K, dbl(c.d_p), K,
                  -1.0, 1.0);
   band_dots_asym(c, c.d_p, c.d_gI, nb, c.d_cg + 8, nullptr, c.d_A, c.d_theta, c.d_cg, nullptr);
-  gemm_expand_to(c, nb, K, nb, c.d_m12 + nb, 2 * nb, false, dbl(c.d_psi), K, dbl(c.d_Sold), K,
-                 dbl(c.d_w1), K, -1.0, 1.0);
+  gemm_expand_to(c, nb, K, nb, carry ? c.d_PSold : c.d_m12 + nb, carry ? nb : 2 * nb, false,
+                 dbl(c.d_psi), K, dbl(c.d_Sold), K, dbl(c.d_w1), K, -1.0, 1.0);
   double* wgb = gs + gNSlots;          // [nb] <w_n|g_n>
   double* asymD = gs + gNSlots + nb;   // [1] sum D_old (theta - theta^T)
   band_dots_asym(c, c.d_w1, c.d_gI, nb, wgb, nullptr, c.d_Dold, c.d_theta, asymD, nullptr);
@@ -530,9 +541,16 @@ static void graph_step(Ctx& c, int step, bool carry) {
   gemm_expand(c, nb, K, nb, c.d_m3, nb, true, dbl(c.d_S), K, dbl(c.d_trial[0]), K, 1.0, 0.0);
   gemm_small(c, nb, nb, nb, c.d_D, nb, false, c.d_m4, nb, false, c.d_m2, nb, 1.0, 0.0);
   gemm_small(c, nb, nb, nb, c.d_m4, nb, true, c.d_m2, nb, false, c.d_m1, nb, 1.0, 0.0);
+  // <psi_new|S_old> = delta M <S|S> M^T (<psi|S> = 0) for the next iteration
+  gemm_small(c, nb, nb, nb, c.d_SS, nb, false, c.d_m3, nb, true, c.d_gram, nb, 1.0, 0.0);
+  gemm_small(c, nb, nb, nb, c.d_m3, nb, false, c.d_gram, nb, false, c.d_Linv, nb, 1.0, 0.0);
+  hipLaunchKernelGGL(k_g_scale, dim3((unsigned)grid_for(nn)), dim3(256), 0, c.stream, nn, c.d_Linv, gs,
+                     (int)gDelta);
+  ROKS_HIP(hipGetLastError());
   SegList f;
   f.add(c.d_trial[0], c.d_trial[0], c.d_Sold, band * sizeof(double2), kAccepted);
   f.add(c.d_m1, c.d_m1, c.d_Dold, nn * sizeof(double), kAccepted);
+  f.add(c.d_Linv, c.d_Linv, c.d_PSold, nn * sizeof(double), kAccepted);
   hipLaunchKernelGGL(k_g_finish, dim3(f.grid()), dim3(256), 0, c.stream, gs, f.g,
                      c.hd_grec + (size_t)step * kRecLen, c.hd_gmirror, kDtMin, kDtMax);
   ROKS_HIP(hipGetLastError());
@@ -765,6 +783,7 @@ int graph_steps(Ctx& c, int k, roks_step_info* info) {
     c.have_old = true;
     c.since_restart = (int)m[gSince];
     c.iteration += acc;
+    c.psold_iter = c.iteration;  // the last accepted iteration left <psi|S_old>
   }
   c.potentials_valid = false;
   return acc;
