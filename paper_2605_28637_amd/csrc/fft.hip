@@ -1222,6 +1222,7 @@ static void run_zpass_bwd(Ctx& c, const double2* vecs, int nvec, void* T, int np
 }
 
 void launch_zpass_bwd(Ctx& c, const double2* vecs, int nvec, void* T, int npairs) {
+  c.T_src = nullptr;
   KernelTimer kt(c, "zpass_bwd", band_bytes(c, nvec) + colbuf_bytes(c, npairs),
                  (double)npairs * c.ncol * line_flops(c.N[2]));
   const int CH = zchunk(c);
@@ -1383,6 +1384,7 @@ void dispatch_lines(Ctx& c, void* T, int npairs, int nchunk, const void* pot,
 
 void launch_plane_apply(Ctx& c, void* T, int npairs, const void* pot, int npot,
                         const int32_t* potidx, int nvec, double* Qpart, int nQ) {
+  c.T_src = nullptr;  // the pass writes its result over the column buffer
   ROKS_CHECK(npot >= 1 && npot <= 3 && nQ <= npot, ROKS_ERR_ARG, "plane pass takes 1..3 potentials");
   KernelTimer kt(c, "plane_apply", 2.0 * colbuf_bytes(c, npairs) + npot * grid_bytes(c),
                  (double)npairs * c.N[2] * plane_lines_flops(c, 2));

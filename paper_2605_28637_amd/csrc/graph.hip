@@ -786,6 +786,7 @@ int graph_steps(Ctx& c, int k, roks_step_info* info) {
     c.psold_iter = c.iteration;  // the last accepted iteration left <psi|S_old>
   }
   c.potentials_valid = false;
+  c.T_src = nullptr;  // the replay wrote the column buffer
   return acc;
 }
 

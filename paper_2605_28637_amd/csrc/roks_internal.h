@@ -145,6 +145,10 @@ struct Ctx {
   bool have_orbitals = false;
   bool potentials_valid = false;
   bool in_graph = false;  // launches being made for graph mode (one stream)
+  // the vectors whose z pass (G -> r) d_T holds, in tier T_prec (nullptr:
+  // none); an energy evaluation sets it, every other writer of d_T clears it
+  const void* T_src = nullptr;
+  int T_prec = -1;
 
   // device arrays (FP64 tier; FP32 copies live in the *_f32 members)
   int32_t* d_miller = nullptr;

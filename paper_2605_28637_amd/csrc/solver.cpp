@@ -219,6 +219,8 @@ void compute_potentials_async(Ctx& c, const double2* orb, bool have_P, bool ener
     } scope{c, c.prec};
     if (scope.prec == ROKS_FP32 && !fp32_density_planes(c)) c.prec = ROKS_FP64;
     launch_zpass_bwd(c, orb, nb, c.d_T, c.npairs);
+    c.T_src = orb;
+    c.T_prec = c.prec;
     launch_plane_density(c, c.d_T, c.npairs, c.d_rho_part, c.nchunk);
   }
   launch_density_reduce(c, c.d_rho_part, c.nchunk, c.d_rho);
@@ -330,7 +332,11 @@ void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bo
   if (c.nproj > 0 && !have_P)
     proj_wdot(c, nb, dbl(vecs), K, c.d_dP, nb);
   if (mask == 0) {
-    launch_zpass_bwd(c, vecs, nb, c.d_T, c.npairs);
+    // the z pass of the orbitals is still in d_T when their energy
+    // evaluation was the last writer (an accepted second trial): skipped
+    const bool reuse_T = !c.in_graph && vecs == c.d_psi && c.potentials_valid && c.T_src == vecs &&
+                         c.T_prec == c.prec;
+    if (!reuse_T) launch_zpass_bwd(c, vecs, nb, c.d_T, c.npairs);
     const void* vsh = c.prec == ROKS_FP32 ? (const void*)c.d_vsh32 : (const void*)c.d_vsh;
     launch_plane_apply(c, c.d_T, c.npairs, vsh, c.nsocc, c.d_potidx, nb, c.d_Qpart,
                        want_Q ? c.nsocc : 0);
