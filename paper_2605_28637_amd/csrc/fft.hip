@@ -305,7 +305,10 @@ __global__ void __launch_bounds__(512) k_zpass_bwd(const double2* __restrict__ v
                                                     int npw, const ColDesc* __restrict__ cols,
                                                     int ndesc, int nH, FftPlan1D plan,
                                                     const C2<R>* __restrict__ twg,
-                                                    C2<R>* __restrict__ T, int ncol, int CH) {
+                                                    C2<R>* __restrict__ T, int ncol, int CH,
+                                                    const double* __restrict__ skip) {
+  // a set skip flag: the column buffer already holds this transform
+  if (skip && skip[0] != 0.0) return;
   extern __shared__ char smem_raw[];
   C2<R>* smem = reinterpret_cast<C2<R>*>(smem_raw);
   const int N3 = plan.n, LS = N3 + 1;  // LDS line stride: N3 + 1 spreads the banks
@@ -1211,26 +1214,27 @@ int radix_set(const FftPlan1D& a, const FftPlan1D& b) {
 }
 
 template <typename R, int MP, int RS>
-static void run_zpass_bwd(Ctx& c, const double2* vecs, int nvec, void* T, int npairs, int CH) {
+static void run_zpass_bwd(Ctx& c, const double2* vecs, int nvec, void* T, int npairs, int CH,
+                          const double* skip) {
   const size_t lds = (size_t)(c.N[2] + 2 * CH * (c.N[2] + 1)) * sizeof(C2<R>);
   allow_lds(k_zpass_bwd<R, MP, RS>, lds);
   dim3 grid(cdiv(c.nH + 1, CH), npairs);
   hipLaunchKernelGGL((k_zpass_bwd<R, MP, RS>), grid, dim3(kZThreads), lds, c.stream, vecs, nvec, c.npw,
                      c.d_cols, c.nH + 1, c.nH, c.plan[2], twiddles<R>(c, 2),
-                     reinterpret_cast<C2<R>*>(T), c.ncol, CH);
+                     reinterpret_cast<C2<R>*>(T), c.ncol, CH, skip);
   ROKS_HIP(hipGetLastError());
 }
 
-void launch_zpass_bwd(Ctx& c, const double2* vecs, int nvec, void* T, int npairs) {
+void launch_zpass_bwd(Ctx& c, const double2* vecs, int nvec, void* T, int npairs, const double* skip) {
   c.T_src = nullptr;
   KernelTimer kt(c, "zpass_bwd", band_bytes(c, nvec) + colbuf_bytes(c, npairs),
                  (double)npairs * c.ncol * line_flops(c.N[2]));
   const int CH = zchunk(c);
   const int mp = pick_maxp(needed_points(2 * CH * c.N[2], kZThreads));
   if (c.prec == ROKS_FP32) {
-    ROKS_DISPATCH_MAXP(float, mp, radix_set(c.plan[2]), run_zpass_bwd, c, vecs, nvec, T, npairs, CH);
+    ROKS_DISPATCH_MAXP(float, mp, radix_set(c.plan[2]), run_zpass_bwd, c, vecs, nvec, T, npairs, CH, skip);
   } else {
-    ROKS_DISPATCH_MAXP(double, mp, radix_set(c.plan[2]), run_zpass_bwd, c, vecs, nvec, T, npairs, CH);
+    ROKS_DISPATCH_MAXP(double, mp, radix_set(c.plan[2]), run_zpass_bwd, c, vecs, nvec, T, npairs, CH, skip);
   }
 }
 

@@ -42,7 +42,7 @@ namespace {
 // slots of the device state block
 enum : int {
   gE0 = 0, gEt, gEts, gT, gTs, gDt, gPg, gPgOld, gBeta, gDE0, gDelta, gE1, gHaveOld, gAccept,
-  gBest, gOkT, gOkTs, gHalt, gNormG, gRestart, gNormD, gSq, gSince, gSinceNew, gPeriod, gNSlots
+  gBest, gOkT, gOkTs, gHalt, gNormG, gRestart, gNormD, gSq, gSince, gSinceNew, gPeriod, gReuseT, gNSlots
 };
 constexpr int kRecLen = 8;  // per iteration: E0, E1, delta, beta, dE0, accepted, |g_I|, restarted
 
@@ -305,6 +305,8 @@ __global__ void __launch_bounds__(256) k_g_finish(double* __restrict__ gs, Segs 
   const bool best = gs[gBest] != 0.0;
   copy_segs(g, acc, best);
   if (threadIdx.x || blockIdx.x) return;
+  // the second trial, taken, leaves its z pass in the column buffer
+  gs[gReuseT] = (acc && gs[gBest] != 0.0) ? 1.0 : 0.0;
   if (acc) {
     gs[gPgOld] = gs[gPg];
     gs[gHaveOld] = 1.0;
@@ -472,7 +474,13 @@ static void graph_step(Ctx& c, int step, bool carry) {
     ROKS_HIP(hipGetLastError());
   }
   c.potentials_valid = true;  // the apply reads the projections in d_P
+  // after a taken second trial its z pass is still in the column buffer
+  // (both in the tier of the apply unless the FP32 tier's densities run in
+  // FP64)
+  const bool same_tier = !(c.prec == ROKS_FP32 && !fp32_density_planes(c));
+  c.zskip = carry && same_tier ? gs + gReuseT : nullptr;
   apply_operator(c, c.d_psi, 0, c.d_Y, true);
+  c.zskip = nullptr;
   gemm_wdot(c, nb, nb, K, dbl(c.d_psi), K, dbl(c.d_Y), K, c.d_theta, nb, 1.0, 0.0, true);
   gemm_expand_to(c, nb, K, nb, c.d_theta, nb, false, dbl(c.d_psi), K, dbl(c.d_Y), K, dbl(c.d_gI), K,
                  -1.0, 1.0);

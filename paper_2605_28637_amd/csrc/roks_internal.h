@@ -149,6 +149,7 @@ struct Ctx {
   // none); an energy evaluation sets it, every other writer of d_T clears it
   const void* T_src = nullptr;
   int T_prec = -1;
+  const double* zskip = nullptr;  // graph mode: the apply's z pass skip flag
 
   // device arrays (FP64 tier; FP32 copies live in the *_f32 members)
   int32_t* d_miller = nullptr;
@@ -422,7 +423,10 @@ void upload_positions(Ctx& c);
 // fft.hip
 // The column buffer T and the potential grids are in the context's tier
 // (double for ROKS_FP64, float for ROKS_FP32); band vectors are FP64.
-void launch_zpass_bwd(Ctx& c, const double2* vecs, int nvec, void* T, int npairs);
+// skip (device, nullable): when *skip != 0 the launch does nothing (graph
+// mode: the buffer already holds the transform)
+void launch_zpass_bwd(Ctx& c, const double2* vecs, int nvec, void* T, int npairs,
+                      const double* skip = nullptr);
 // pot holds npot (1..3) grids; potidx[n] selects band n's grid (-1: zero);
 // nQ > 0 also accumulates <n|V^X|n> for the first nQ grids into Qpart
 void launch_plane_apply(Ctx& c, void* T, int npairs, const void* pot, int npot,

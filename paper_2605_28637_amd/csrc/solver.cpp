@@ -336,7 +336,7 @@ void apply_operator(Ctx& c, const double2* vecs, uint32_t mask, double2* out, bo
     // evaluation was the last writer (an accepted second trial): skipped
     const bool reuse_T = !c.in_graph && vecs == c.d_psi && c.potentials_valid && c.T_src == vecs &&
                          c.T_prec == c.prec;
-    if (!reuse_T) launch_zpass_bwd(c, vecs, nb, c.d_T, c.npairs);
+    if (!reuse_T) launch_zpass_bwd(c, vecs, nb, c.d_T, c.npairs, c.in_graph ? c.zskip : nullptr);
     const void* vsh = c.prec == ROKS_FP32 ? (const void*)c.d_vsh32 : (const void*)c.d_vsh;
     launch_plane_apply(c, c.d_T, c.npairs, vsh, c.nsocc, c.d_potidx, nb, c.d_Qpart,
                        want_Q ? c.nsocc : 0);
