@@ -11,7 +11,7 @@ batch of uneven systems."""
 import numpy as np
 import pytest
 
-from helpers import SphereMap, band_rel, ensure_built, small_molecule
+from helpers import SphereMap, band_rel, ensure_built, orthorhombic_cell, small_molecule
 from oracle import roks as orc
 from paper_2605_28637_amd import inputs
 
@@ -24,6 +24,10 @@ CASES = {
     "ground_state": lambda: inputs.with_configuration(inputs.tiny_cell(), "gs"),
     "pbe_molecule": lambda: dict(small_molecule(), xc="pbe"),
     "triplet": lambda: inputs.with_configuration(small_molecule(), "triplet"),
+    # an odd grid (45^3: the LDS-plane kernels, no Nyquist plane) and a
+    # non-cubic cell and grid
+    "odd_grid": lambda: inputs.molecule_box(seed=2007, natoms=4, nb=9, N=45, L=14.0),
+    "orthorhombic": lambda: orthorhombic_cell(),
 }
 
 
