@@ -502,6 +502,31 @@ def batch_solve_report(tol=1e-6, switch_tol=1e-5, workers=4):
     return res
 
 
+def batch_cg_only(mode, steps=8, workers=4):
+    """The 32-system batch (FP32 tier): a warm-up call, then `steps` CG
+    iterations of every system driven from the host (roks_batch_steps) or in
+    graph mode (roks_batch_graph_steps); one JSON line with the timed call's
+    wall time."""
+    systems = inputs.batch_systems()
+    ctxs = []
+    for s in systems:
+        r = rb.Roks(s, precision=rb.FP32)
+        r.set_coeffs(inputs.random_coefficients(r.miller(), s["cell"], r.nb, s["seed"]), True)
+        ctxs.append(r)
+    b = rb.Batch(ctxs, workers=workers)
+    run = (lambda: b.steps(steps)) if mode == "host" else (lambda: b.graph_steps(steps))
+    run()
+    t0 = time.perf_counter()
+    run()
+    dt = time.perf_counter() - t0
+    b.close()
+    for r in ctxs:
+        r.close()
+    print(json.dumps({"batch_cg": mode, "systems": len(systems), "steps_each": steps,
+                      "workers": workers, "seconds": dt,
+                      "band_applies_per_s": sum(s["nbands"] for s in systems) * steps / dt}))
+
+
 def oxide_graph_report(system, steps=4):
     """Graph mode on the oxide supercell (FP64): `steps` CG iterations
     replayed from one graph against the same iterations driven from the
@@ -698,11 +723,18 @@ def main():
                     help="the headline line only (no FP32 tier, molecule, converge, batch, CPU legs)")
     ap.add_argument("--tier", choices=("fp64", "fp32", "bf16x3"), default="fp64",
                     help="arithmetic tier of the headline measurement (profiling runs)")
+    ap.add_argument("--batch-cg", choices=("host", "graph"), default=None,
+                    help="only the 32-system batch's CG iterations (8 each, after a "
+                         "warm-up call), driven from the host or in graph mode: the "
+                         "workload of the graph-mode kernel trace")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the copy kernel that scales the HBM byte counters")
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.batch_cg:
+        batch_cg_only(args.batch_cg)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",

@@ -32,6 +32,7 @@
 // preconditioner's retry after a failed learned search is the host step's).
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "roks_internal.h"
 
@@ -675,7 +676,13 @@ void restore_bufs(Ctx& c) {
   c.d_P0 = static_cast<double*>(g[4]);
 }
 
+// captures of different contexts (the batch's worker threads) one at a
+// time: a capture is made once per context and k, the replays stay
+// concurrent
+std::mutex g_capture_mu;
+
 void capture(Ctx& c, int k) {
+  std::lock_guard<std::mutex> lock(g_capture_mu);
   free_graph(c);
   // one iteration outside the capture that commits nothing: first-use work
   // of every launcher (tables, LDS limits) happens here
