@@ -727,6 +727,9 @@ def main():
                     help="only the 32-system batch's CG iterations (8 each, after a "
                          "warm-up call), driven from the host or in graph mode: the "
                          "workload of the graph-mode kernel trace")
+    ap.add_argument("--molecule-only", action="store_true",
+                    help="only the 64^3 molecule-in-box steps (FP64), one JSON line: the "
+                         "second workload of the plane-pass counters")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the copy kernel that scales the HBM byte counters")
     args = ap.parse_args()
@@ -735,6 +738,12 @@ def main():
         return
     if args.batch_cg:
         batch_cg_only(args.batch_cg)
+        return
+    if args.molecule_only:
+        m = measure(inputs.molecule_box(), rb.FP64, args.steps, args.warmup,
+                    table_steps=min(args.steps, 4))
+        print(json.dumps({"molecule_64": {k: m[k] for k in ("band_applies_per_s", "ms_per_step",
+                                                              "nb", "npw")}}))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
